@@ -1,0 +1,255 @@
+"""FP64 CPU oracle for the ConKer hot path (mapping, convolution, summation).
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product library imports or calls this
+module; only the tests, the smoke check and the CPU-baseline leg of the bench
+use it.  It shares no code with the HIP path.
+
+Everything is computed in float64 with NumPy / SciPy, following the paper
+(Brown, Mishtaku & Demina, "ConKer: evaluating isotropic correlations of
+arbitrary order", arXiv:2108.00015) stage by stage:
+
+* mapping      -- Sec. 2.2 (Input): histograms D and R on a grid of spacing g_s,
+                  R normalised to the data total, N = D - R  (Eq. bgsubtracted_map);
+* kernels      -- Sec. 2.3 (Kernels): one-cell-thick spherical shells;
+* convolution  -- Sec. 2.4 (Convolution): W_i = N *** K_i and B_i = R *** K_i
+                  (Eqs. countconv, randconv), done with an FFT as the paper does;
+* summation    -- Sec. 2.5: xi_n = sum W_0 W_1 ... W_{n-1} / sum B_0 ... B_{n-1}
+                  (Eq. ksin_delta), W_0 = N and B_0 = R.
+
+Readings taken where the paper is silent (each is listed with its reason in the
+design notes):
+
+* NGP assignment, half-open cells, index floor((x - origin) / g_s) evaluated in
+  float64 from the float32 coordinates; points outside the grid are excluded and
+  counted.
+* R is normalised with alpha = sum(w_D) / sum(w_R) over in-grid points, and the
+  denominator sum B_0...B_{n-1} is evaluated on alpha * R_raw.
+* A shell of radius s holds the lattice offsets delta with
+  r - 1/2 <= |delta| < r + 1/2, r = s / g_s (cells whose centre lies within half
+  a cell of the sphere).
+* Convolution is circular on the given grid; bounded surveys are zero-padded so
+  that circular equals linear.
+* The sum in Eq. ksin_delta runs over every grid cell; the radius tuples are all
+  multisets a_1 <= ... <= a_{n-1} of shell indices.
+"""
+from __future__ import annotations
+
+import itertools
+import math
+import os
+from typing import Iterable, List, Optional, Sequence, Tuple
+
+import numpy as np
+import scipy.fft as sfft
+
+WORKERS = max(1, len(os.sched_getaffinity(0)))
+
+
+# ----------------------------------------------------------------------------
+# mapping (Sec. 2.2, Eq. bgsubtracted_map)
+# ----------------------------------------------------------------------------
+
+def cell_index(pos: np.ndarray, origin: Sequence[float], cell: float,
+               dims: Sequence[int]) -> Tuple[np.ndarray, np.ndarray]:
+    """NGP cell of each tracer: floor((x - origin) / g_s) per axis, in float64.
+
+    Returns (int64 [N, 3] cell indices, bool [N] inside-grid mask).
+    """
+    p = np.asarray(pos, dtype=np.float32).astype(np.float64)
+    o = np.asarray(origin, dtype=np.float64)
+    c = np.floor((p - o) / np.float64(cell))
+    d = np.asarray(dims, dtype=np.float64)
+    inside = np.all((c >= 0.0) & (c < d), axis=1)
+    c = np.where(inside[:, None], c, 0.0).astype(np.int64)
+    return c, inside
+
+
+def linear_index(c: np.ndarray, dims: Sequence[int]) -> np.ndarray:
+    """Row-major (C order, z fastest) linear cell index."""
+    ny, nz = int(dims[1]), int(dims[2])
+    return (c[:, 0] * ny + c[:, 1]) * nz + c[:, 2]
+
+
+def histogram(pos: np.ndarray, w: Optional[np.ndarray], origin, cell, dims
+              ) -> Tuple[np.ndarray, float, int]:
+    """Tracer (or weighted tracer) count per cell, Sec. 2.2.
+
+    Returns (float64 grid of shape dims, sum of in-grid weights, number of
+    out-of-grid tracers).
+    """
+    c, inside = cell_index(pos, origin, cell, dims)
+    lin = linear_index(c[inside], dims)
+    n_cells = int(np.prod(dims))
+    if w is None:
+        ww = np.ones(int(inside.sum()), dtype=np.float64)
+    else:
+        ww = np.asarray(w, dtype=np.float32).astype(np.float64)[inside]
+    grid = np.bincount(lin, weights=ww, minlength=n_cells).astype(np.float64)
+    return grid.reshape(tuple(int(x) for x in dims)), float(ww.sum()), int((~inside).sum())
+
+
+def density_deviation(D: np.ndarray, R_raw: np.ndarray, wsum_data: float,
+                      wsum_rand: float) -> Tuple[np.ndarray, float]:
+    """N = D - R with R = alpha * R_raw normalised to the data total (Eq. bgsubtracted_map).
+
+    Returns (N, alpha)."""
+    alpha = wsum_data / wsum_rand
+    return D - alpha * R_raw, alpha
+
+
+# ----------------------------------------------------------------------------
+# kernels (Sec. 2.3)
+# ----------------------------------------------------------------------------
+
+def shell_reach(r: float) -> int:
+    """Largest offset component M that a shell of radius r (cells) can hold."""
+    return int(math.ceil(r + 0.5)) - 1
+
+
+def shell_offsets(r: float) -> np.ndarray:
+    """Lattice offsets of the one-cell-thick shell of radius r (in cells).
+
+    S(r) = {delta in Z^3 : (r - 1/2)^2 <= |delta|^2 < (r + 1/2)^2}, compared in
+    float64 (exact for the half-integer bounds of integer r).
+    """
+    if not r >= 0.5:
+        raise ValueError("shell radius must be at least half a cell")
+    M = shell_reach(r)
+    ax = np.arange(-M, M + 1, dtype=np.int64)
+    d = np.stack(np.meshgrid(ax, ax, ax, indexing="ij"), axis=-1).reshape(-1, 3)
+    d2 = (d * d).sum(axis=1).astype(np.float64)
+    lo = (r - 0.5) ** 2
+    hi = (r + 0.5) ** 2
+    return d[(d2 >= lo) & (d2 < hi)]
+
+
+def check_shell_fits(r: float, dims: Sequence[int]) -> None:
+    if 2 * shell_reach(r) + 1 > min(int(x) for x in dims):
+        raise ValueError("shell of radius %g cells does not fit the grid %s" % (r, tuple(dims)))
+
+
+def shell_kernel_grid(r: float, dims: Sequence[int]) -> np.ndarray:
+    """Indicator of S(r) laid on the grid with its centre at cell (0,0,0), periodic wrap."""
+    check_shell_fits(r, dims)
+    k = np.zeros(tuple(int(x) for x in dims), dtype=np.float64)
+    d = shell_offsets(r)
+    k[d[:, 0] % dims[0], d[:, 1] % dims[1], d[:, 2] % dims[2]] = 1.0
+    return k
+
+
+def shell_spectrum(r: float, dims: Sequence[int]) -> np.ndarray:
+    """Full complex DFT of the wrapped shell indicator (unnormalised forward DFT)."""
+    return sfft.fftn(shell_kernel_grid(r, dims), workers=WORKERS)
+
+
+# ----------------------------------------------------------------------------
+# convolution (Sec. 2.4, Eqs. countconv, randconv)
+# ----------------------------------------------------------------------------
+
+def convolve_shell(F: np.ndarray, r: float, F_hat: Optional[np.ndarray] = None) -> np.ndarray:
+    """Map of shell sums C_r(x) = sum_{delta in S(r)} F(x + delta) (circular).
+
+    Computed as the paper does, by FFT: irfft(rfft(F) * rfft(K_r)).  The kernel
+    is point-symmetric, so convolution and correlation coincide.
+    """
+    dims = F.shape
+    K = shell_kernel_grid(r, dims)
+    if F_hat is None:
+        F_hat = sfft.rfftn(F, workers=WORKERS)
+    K_hat = sfft.rfftn(K, workers=WORKERS)
+    return sfft.irfftn(F_hat * K_hat, s=dims, workers=WORKERS)
+
+
+def convolve_shells(F: np.ndarray, radii_cells: Sequence[float]) -> np.ndarray:
+    """Stack of maps [N_s, nx, ny, nz], one per shell radius (in cells)."""
+    F_hat = sfft.rfftn(F, workers=WORKERS)
+    return np.stack([convolve_shell(F, r, F_hat) for r in radii_cells])
+
+
+def direct_shell_sum(F: np.ndarray, r: float, cells: np.ndarray) -> np.ndarray:
+    """C_r at the given cells [K, 3] by summing F over the shell offsets directly."""
+    dims = np.asarray(F.shape)
+    d = shell_offsets(r)
+    out = np.empty(len(cells), dtype=np.float64)
+    for i, x in enumerate(np.asarray(cells, dtype=np.int64)):
+        idx = (x[None, :] + d) % dims[None, :]
+        out[i] = F[idx[:, 0], idx[:, 1], idx[:, 2]].sum()
+    return out
+
+
+# ----------------------------------------------------------------------------
+# summation (Sec. 2.5, Eqs. ksin_delta, ksi2_delta, ksi3; Eq. ksinDiag)
+# ----------------------------------------------------------------------------
+
+def radius_tuples(n_radii: int, n: int) -> List[Tuple[int, ...]]:
+    """All multisets a_1 <= ... <= a_{n-1} of shell indices, lexicographic."""
+    if n < 2:
+        raise ValueError("correlation order must be at least 2")
+    return list(itertools.combinations_with_replacement(range(n_radii), n - 1))
+
+
+def num_tuples(n_radii: int, n: int) -> int:
+    return math.comb(n_radii + n - 2, n - 1)
+
+
+def contract(F: np.ndarray, maps: np.ndarray, n: int,
+             tuples: Optional[Iterable[Tuple[int, ...]]] = None,
+             chunk: int = 1 << 22) -> np.ndarray:
+    """W_n(a_1..a_{n-1}) = sum_x F(x) prod_i C_{a_i}(x) for each radius tuple.
+
+    This is the numerator (F = N, maps W_i) or the denominator (F = R, maps B_i)
+    of Eq. ksin_delta, summed over every grid cell; the sum over cells is taken
+    in consecutive slices of ``chunk`` cells to bound memory.
+    """
+    if tuples is None:
+        tuples = radius_tuples(maps.shape[0], n)
+    tuples = [tuple(t) for t in tuples]
+    for t in tuples:
+        if len(t) != n - 1:
+            raise ValueError("tuple %r does not match order n=%d" % (t, n))
+    f = F.reshape(-1)
+    C = maps.reshape(maps.shape[0], -1)
+    W = np.zeros(len(tuples), dtype=np.float64)
+    for s in range(0, f.size, chunk):
+        fs = f[s:s + chunk]
+        Cs = C[:, s:s + chunk]
+        for k, t in enumerate(tuples):
+            prod = fs.copy()
+            for a in t:
+                prod *= Cs[a]
+            W[k] += prod.sum()
+    return W
+
+
+def estimator(W_delta: np.ndarray, W_rand_raw: np.ndarray, alpha: float, n: int) -> np.ndarray:
+    """xi_n = sum W_0..W_{n-1} / sum B_0..B_{n-1}, with B built on R = alpha R_raw.
+
+    W_rand_raw is the contraction of R_raw; scaling R by alpha scales every
+    factor B_i by alpha, so the denominator is alpha^n * W_rand_raw.
+    """
+    return W_delta / (alpha ** n * W_rand_raw)
+
+
+def npcf(data_pos, rand_pos, dims, origin, cell, radii, n,
+         data_w=None, rand_w=None, tuples=None):
+    """End-to-end estimator for one catalog pair: mapping -> convolution -> summation.
+
+    radii are in length units.  Returns a dict with xi, W_delta, W_rand_raw,
+    alpha and the intermediate grids.
+    """
+    D, wd, out_d = histogram(data_pos, data_w, origin, cell, dims)
+    R_raw, wr, out_r = histogram(rand_pos, rand_w, origin, cell, dims)
+    N, alpha = density_deviation(D, R_raw, wd, wr)
+    rc = [float(s) / float(cell) for s in radii]
+    maps_N = convolve_shells(N, rc)
+    maps_R = convolve_shells(R_raw, rc)
+    Wd = contract(N, maps_N, n, tuples)
+    Wr = contract(R_raw, maps_R, n, tuples)
+    return dict(xi=estimator(Wd, Wr, alpha, n), W_delta=Wd, W_rand_raw=Wr, alpha=alpha,
+                N=N, R_raw=R_raw, maps_N=maps_N, maps_R=maps_R,
+                wsum_data=wd, wsum_rand=wr, outside=(out_d, out_r))
+
+
+def diagonal(F: np.ndarray, map_1: np.ndarray, n: int) -> float:
+    """Equidistant case, Eq. ksinDiag numerator: sum_x F(x) C_1(x)^(n-1)."""
+    return float((F * map_1 ** (n - 1)).sum())

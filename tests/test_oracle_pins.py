@@ -1,0 +1,377 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle itself.
+
+Each test names the passage of the paper (or the piece of mathematics) it checks.
+All run on the CPU in seconds.
+"""
+import itertools
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import brute
+from oracle import conker as oc
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------------------
+# helpers: tiny clustered catalogs on a zero-padded grid
+# ---------------------------------------------------------------------------
+
+def _tiny_catalog(n_data, n_rand, box, seed, weighted=False):
+    rng = np.random.default_rng(seed)
+    centres = rng.uniform(0, box, size=(3, 3))
+    d = centres[rng.integers(0, 3, n_data)] + rng.normal(0, box / 8, size=(n_data, 3))
+    d = np.clip(d, 0, box - 1e-3).astype(np.float32)
+    r = rng.uniform(0, box, size=(n_rand, 3)).astype(np.float32)
+    wd = rng.uniform(0.5, 1.5, n_data).astype(np.float32) if weighted else None
+    wr = rng.uniform(0.5, 1.5, n_rand).astype(np.float32) if weighted else None
+    return d, r, wd, wr
+
+
+def _theta_r3(t_max):
+    """r_3(t) = #{(x,y,z) in Z^3 : x^2+y^2+z^2 = t}, from the cube of the theta series."""
+    theta = np.zeros(t_max + 1, dtype=np.int64)
+    k = 0
+    while k * k <= t_max:
+        theta[k * k] += 1 if k == 0 else 2
+        k += 1
+    two = np.convolve(theta, theta)[: t_max + 1]
+    return np.convolve(two, theta)[: t_max + 1]
+
+
+# ---------------------------------------------------------------------------
+# P1, P2 -- mapping (Sec. 2.2, Eq. bgsubtracted_map)
+# ---------------------------------------------------------------------------
+
+def test_histogram_counts_match_dictionary_count():
+    """P1: unit weights give integer tracer counts per cell; out-of-grid tracers excluded."""
+    rng = np.random.default_rng(1)
+    pos = rng.uniform(-3.0, 35.0, size=(5000, 3)).astype(np.float32)
+    dims, origin, cell = (8, 9, 10), (0.0, 0.5, -1.0), 3.5
+    grid, wsum, outside = oc.histogram(pos, None, origin, cell, dims)
+    counts = {}
+    n_out = 0
+    for p in pos:
+        c = tuple(int(math.floor((float(p[k]) - origin[k]) / cell)) for k in range(3))
+        if all(0 <= c[k] < dims[k] for k in range(3)):
+            counts[c] = counts.get(c, 0) + 1
+        else:
+            n_out += 1
+    ref = np.zeros(dims)
+    for c, v in counts.items():
+        ref[c] = v
+    assert np.array_equal(grid, ref)
+    assert outside == n_out
+    assert wsum == len(pos) - n_out
+
+
+def test_histogram_weighted_total():
+    """P1: the weighted histogram sums to the in-grid weight total."""
+    rng = np.random.default_rng(2)
+    pos = rng.uniform(0, 20, size=(3000, 3)).astype(np.float32)
+    w = rng.lognormal(0, 0.2, 3000).astype(np.float32)
+    grid, wsum, outside = oc.histogram(pos, w, (0, 0, 0), 2.0, (10, 10, 10))
+    assert outside == 0
+    assert math.isclose(grid.sum(), float(w.astype(np.float64).sum()), rel_tol=1e-13)
+    assert math.isclose(wsum, grid.sum(), rel_tol=1e-13)
+
+
+def test_density_deviation_sums_to_zero():
+    """P2: N = D - alpha R with alpha = sum w_D / sum w_R has zero total."""
+    d, r, wd, wr = _tiny_catalog(500, 5000, 16.0, 3, weighted=True)
+    D, sd, _ = oc.histogram(d, wd, (0, 0, 0), 1.0, (16, 16, 16))
+    R, sr, _ = oc.histogram(r, wr, (0, 0, 0), 1.0, (16, 16, 16))
+    N, alpha = oc.density_deviation(D, R, sd, sr)
+    assert abs(N.sum()) < 1e-10 * D.sum()
+    assert math.isclose(alpha, sd / sr)
+
+
+# ---------------------------------------------------------------------------
+# P3 -- shell kernels (Sec. 2.3)
+# ---------------------------------------------------------------------------
+
+def test_r3_theta_series_textbook_values():
+    """The theta-series counter reproduces r_3(t) for t = 0..12 (sums of three squares)."""
+    assert list(_theta_r3(12)) == [1, 6, 12, 8, 6, 24, 24, 0, 12, 30, 24, 24, 8]
+
+
+@pytest.mark.parametrize("m", list(range(1, 42)))
+def test_shell_size_equals_theta_series(m):
+    """P3: |S_m| = sum of r_3(t) over m^2 - m + 1 <= t <= m^2 + m (one-cell-thick shell)."""
+    r3 = _theta_r3(m * m + m)
+    expect = int(r3[m * m - m + 1: m * m + m + 1].sum())
+    assert len(oc.shell_offsets(float(m))) == expect
+
+
+def test_shell_sizes_small_and_asymptotic():
+    sizes = [len(oc.shell_offsets(float(m))) for m in range(1, 12)]
+    assert sizes[:3] == [18, 62, 98]
+    for m in (10, 20, 30, 40):
+        n = len(oc.shell_offsets(float(m)))
+        assert abs(n / (4 * math.pi * m * m) - 1) < 0.06
+
+
+def test_shells_partition_lattice_and_are_cubic_symmetric():
+    """P3: shells m = 1..6 partition the nonzero offsets with |d| < 6.5, each invariant under
+    the 48 signed axis permutations."""
+    seen = set()
+    for m in range(1, 7):
+        s = {tuple(int(v) for v in d) for d in oc.shell_offsets(float(m))}
+        assert not (s & seen)
+        seen |= s
+        for perm in itertools.permutations(range(3)):
+            for signs in itertools.product((1, -1), repeat=3):
+                t = {tuple(signs[k] * d[perm[k]] for k in range(3)) for d in s}
+                assert t == s
+    box = [(x, y, z) for x in range(-6, 7) for y in range(-6, 7) for z in range(-6, 7)
+           if 0 < x * x + y * y + z * z < 6.5 ** 2]
+    assert seen == set(box)
+
+
+def test_shell_noninteger_radius_half_open():
+    """Reading of non-integer radii: the same half-open rule with real r."""
+    s = oc.shell_offsets(11.46)
+    d = np.sqrt((s.astype(float) ** 2).sum(1))
+    assert d.min() >= 10.96 - 1e-12 and d.max() < 11.96
+
+
+def test_shell_spectrum_real_even_and_dc():
+    """P3: the wrapped shell is point-symmetric, so its DFT is real; the DC term is |S|."""
+    dims = (16, 18, 20)
+    for r in (1.0, 3.0, 4.5):
+        K = oc.shell_spectrum(r, dims)
+        assert np.abs(K.imag).max() < 1e-10
+        assert math.isclose(K[0, 0, 0].real, len(oc.shell_offsets(r)), rel_tol=1e-14)
+
+
+def test_shell_must_fit_grid():
+    with pytest.raises(ValueError):
+        oc.shell_kernel_grid(8.0, (16, 16, 16))
+    with pytest.raises(ValueError):
+        oc.shell_offsets(0.4)
+
+
+# ---------------------------------------------------------------------------
+# P4 -- convolution maps (Sec. 2.4)
+# ---------------------------------------------------------------------------
+
+def test_maps_equal_direct_shell_sums_integer_field():
+    """P4: FFT maps equal the real-space shell sums of an integer field at every cell."""
+    rng = np.random.default_rng(4)
+    F = rng.integers(-3, 4, size=(12, 14, 16)).astype(np.float64)
+    cells = np.array(list(itertools.product(range(12), range(14), range(16))))
+    for r in (1.0, 2.0, 3.0, 5.0):
+        fft_map = oc.convolve_shell(F, r)
+        direct = oc.direct_shell_sum(F, r, cells).reshape(F.shape)
+        assert np.abs(fft_map - direct).max() < 1e-9
+
+
+def test_map_total_and_linearity():
+    """P4: sum_x C_m = |S_m| sum_x F; the map is linear in F."""
+    rng = np.random.default_rng(5)
+    F = rng.normal(size=(16, 16, 16))
+    G = rng.normal(size=(16, 16, 16))
+    for r in (2.0, 4.0):
+        C = oc.convolve_shell(F, r)
+        assert math.isclose(C.sum(), len(oc.shell_offsets(r)) * F.sum(), rel_tol=1e-9, abs_tol=1e-9)
+        lin = oc.convolve_shell(2.0 * F - 3.0 * G, r)
+        assert np.allclose(lin, 2.0 * C - 3.0 * oc.convolve_shell(G, r), atol=1e-10)
+
+
+# ---------------------------------------------------------------------------
+# P5 -- brute force over tracer tuples (Eq. ksin_delta)
+# ---------------------------------------------------------------------------
+
+def _grid_setup():
+    return (16, 16, 16), (0.0, 0.0, 0.0), 1.0
+
+
+@pytest.mark.parametrize("n,shells,n_data,n_rand", [
+    (2, [(1,), (2,), (3,)], 12, 24),
+    (3, [(1, 1), (1, 3), (2, 3)], 10, 20),
+    (4, [(1, 1, 2), (1, 2, 3)], 6, 10),
+    (5, [(1, 1, 2, 3)], 4, 7),
+])
+def test_oracle_matches_explicit_tuple_enumeration(n, shells, n_data, n_rand):
+    """P5: W^Delta_n and W^R_n from grid + FFT maps + contraction equal the explicit sum
+    over tracer tuples, with data weights +w and random weights -alpha w."""
+    dims, origin, cell = _grid_setup()
+    d, r, wd, wr = _tiny_catalog(n_data, n_rand, 8.0, 10 + n, weighted=True)
+    res = oc.npcf(d, r, dims, origin, cell, [1.0, 2.0, 3.0], n, wd, wr, tuples=[tuple(a - 1 for a in s) for s in shells])
+    cells, u, alpha, cr, wrr = brute.signed_tracers(d, r, origin, cell, dims, wd, wr)
+    assert math.isclose(alpha, res["alpha"], rel_tol=1e-14)
+    for k, s in enumerate(shells):
+        ref_d = brute.tuple_sum(cells, u, s, dims, periodic=False)
+        ref_r = brute.tuple_sum(cr, wrr, s, dims, periodic=False)
+        assert math.isclose(res["W_delta"][k], ref_d, rel_tol=1e-9, abs_tol=1e-9)
+        assert math.isclose(res["W_rand_raw"][k], ref_r, rel_tol=1e-9, abs_tol=1e-9)
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+def test_oracle_matches_pair_factorised_sum_all_tuples(periodic):
+    """P5 at a larger size: every tuple of n = 2..5 against the tracer-pair sum."""
+    dims, origin, cell = (20, 20, 20), (0.0, 0.0, 0.0), 1.0
+    box = 10.0 if not periodic else 20.0
+    d, r, wd, wr = _tiny_catalog(120, 240, box, 77, weighted=True)
+    radii = [1.0, 2.0, 3.0, 4.0]
+    cells, u, alpha, cr, wrr = brute.signed_tracers(d, r, origin, cell, dims, wd, wr)
+    for n in (2, 3, 4, 5):
+        res = oc.npcf(d, r, dims, origin, cell, radii, n, wd, wr)
+        for k, t in enumerate(oc.radius_tuples(len(radii), n)):
+            s = [a + 1 for a in t]
+            ref_d = brute.pair_factorised_sum(cells, u, s, dims, periodic)
+            ref_r = brute.pair_factorised_sum(cr, wrr, s, dims, periodic)
+            assert math.isclose(res["W_delta"][k], ref_d, rel_tol=1e-9, abs_tol=1e-8), (n, t)
+            assert math.isclose(res["W_rand_raw"][k], ref_r, rel_tol=1e-9, abs_tol=1e-8), (n, t)
+
+
+# ---------------------------------------------------------------------------
+# P6, P12 -- symmetry and the diagonal (Eq. ksinDiag)
+# ---------------------------------------------------------------------------
+
+def test_permutation_symmetry_and_diagonal():
+    rng = np.random.default_rng(6)
+    F = rng.normal(size=(16, 16, 16))
+    radii = [1.0, 2.0, 3.5]
+    maps = oc.convolve_shells(F, radii)
+    for n in (3, 4, 5):
+        full = list(itertools.product(range(3), repeat=n - 1))
+        W = oc.contract(F, maps, n, full)
+        lookup = dict(zip(full, W))
+        for t, v in lookup.items():
+            assert math.isclose(v, lookup[tuple(sorted(t))], rel_tol=1e-12, abs_tol=1e-12)
+        for m in range(3):
+            assert math.isclose(lookup[(m,) * (n - 1)], oc.diagonal(F, maps[m], n), rel_tol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# P7 -- n = 2 identities
+# ---------------------------------------------------------------------------
+
+def test_n2_equals_autocorrelation_and_parseval():
+    rng = np.random.default_rng(7)
+    dims = (16, 12, 10)
+    F = rng.normal(size=dims)
+    Fh = np.fft.fftn(F)
+    auto = np.fft.ifftn(np.abs(Fh) ** 2).real    # A(d) = sum_x F(x) F(x + d)
+    radii = [1.0, 2.0, 3.0, 4.0]
+    W2 = oc.contract(F, oc.convolve_shells(F, radii), 2)
+    for k, r in enumerate(radii):
+        d = oc.shell_offsets(r)
+        via_auto = auto[d[:, 0] % dims[0], d[:, 1] % dims[1], d[:, 2] % dims[2]].sum()
+        Kh = oc.shell_spectrum(r, dims).real
+        parseval = (np.abs(Fh) ** 2 * Kh).sum() / F.size
+        assert math.isclose(W2[k], via_auto, rel_tol=1e-10)
+        assert math.isclose(W2[k], parseval, rel_tol=1e-10)
+
+
+# ---------------------------------------------------------------------------
+# P8, P9 -- closed forms
+# ---------------------------------------------------------------------------
+
+def test_uniform_field_closed_form():
+    """P8: F = rho everywhere on a periodic grid -> W_n = N_c rho^n prod |S_a|."""
+    dims = (12, 12, 12)
+    rho = 1.75
+    F = np.full(dims, rho)
+    radii = [1.0, 2.0, 3.0]
+    sizes = [len(oc.shell_offsets(r)) for r in radii]
+    maps = oc.convolve_shells(F, radii)
+    for n in (2, 3, 4, 5):
+        W = oc.contract(F, maps, n)
+        for k, t in enumerate(oc.radius_tuples(3, n)):
+            ref = F.size * rho ** n * np.prod([sizes[a] for a in t])
+            assert math.isclose(W[k], ref, rel_tol=1e-11)
+
+
+def test_two_points_closed_form():
+    """P9: two unit tracers at lattice separation d: W_2(m) = 2[m = round|d|],
+    W_3(a, b) = 2[a = b = round|d|] (degenerate vertices kept, as the estimator is written)."""
+    dims = (20, 20, 20)
+    F = np.zeros(dims)
+    F[3, 4, 5] = 1.0
+    F[3 + 2, 4 + 1, 5 + 2] = 1.0   # |d| = 3
+    radii = [1.0, 2.0, 3.0, 4.0]
+    maps = oc.convolve_shells(F, radii)
+    W2 = oc.contract(F, maps, 2)
+    assert np.allclose(W2, [0, 0, 2, 0], atol=1e-12)
+    W3 = oc.contract(F, maps, 3)
+    for k, (a, b) in enumerate(oc.radius_tuples(4, 3)):
+        assert abs(W3[k] - (2.0 if a == b == 2 else 0.0)) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# P10 -- equivariance; P13 -- region additivity (Eq. ksi3combined)
+# ---------------------------------------------------------------------------
+
+def test_translation_and_cubic_group_invariance():
+    rng = np.random.default_rng(8)
+    F = rng.normal(size=(16, 16, 16))
+    radii = [1.0, 2.0, 3.0]
+    ref = oc.contract(F, oc.convolve_shells(F, radii), 3)
+    G = np.roll(F, shift=(3, -5, 7), axis=(0, 1, 2))
+    assert np.allclose(oc.contract(G, oc.convolve_shells(G, radii), 3), ref, rtol=1e-10)
+    H = np.flip(np.transpose(F, (2, 0, 1)), axis=1)
+    assert np.allclose(oc.contract(H, oc.convolve_shells(H, radii), 3), ref, rtol=1e-10)
+
+
+def test_weight_scaling():
+    """P10: scaling every weight by c multiplies both parts by c^n; xi is unchanged."""
+    dims, origin, cell = (16, 16, 16), (0.0, 0.0, 0.0), 1.0
+    d, r, wd, wr = _tiny_catalog(200, 800, 8.0, 9, weighted=True)
+    a = oc.npcf(d, r, dims, origin, cell, [1.0, 2.0], 3, wd, wr)
+    c = 2.0
+    b = oc.npcf(d, r, dims, origin, cell, [1.0, 2.0], 3, wd * np.float32(c), wr * np.float32(c))
+    assert np.allclose(b["W_delta"], c ** 3 * a["W_delta"], rtol=1e-10)
+    assert np.allclose(b["W_rand_raw"], c ** 3 * a["W_rand_raw"], rtol=1e-10)
+    assert np.allclose(b["xi"], a["xi"], rtol=1e-10)
+
+
+def test_region_additivity():
+    """P13: two fields in sub-boxes further apart than the largest shell: numerators add."""
+    rng = np.random.default_rng(10)
+    dims = (32, 16, 16)
+    F1 = np.zeros(dims)
+    F2 = np.zeros(dims)
+    F1[2:8, 2:8, 2:8] = rng.normal(size=(6, 6, 6))
+    F2[18:24, 2:8, 2:8] = rng.normal(size=(6, 6, 6))
+    radii = [1.0, 2.0, 3.0]
+    for n in (2, 3, 4):
+        W = oc.contract(F1 + F2, oc.convolve_shells(F1 + F2, radii), n)
+        W1 = oc.contract(F1, oc.convolve_shells(F1, radii), n)
+        W2 = oc.contract(F2, oc.convolve_shells(F2, radii), n)
+        assert np.allclose(W, W1 + W2, rtol=1e-10, atol=1e-10)
+
+
+# ---------------------------------------------------------------------------
+# P11 -- distance calibration (Sec. 3.1): RMS of the true separation ~ g_s / 2
+# ---------------------------------------------------------------------------
+
+def test_distance_calibration_rms_matches_paper():
+    """P11: for tracer pairs whose NGP cells lie on the shell of a 60-unit kernel at g_s = 5,
+    the true separation has an RMS spread of about half a cell (the paper's 2.5)."""
+    with open(os.path.join(GOLDEN, "calibration_rms.json")) as fh:
+        gold = json.load(fh)
+    g, s = gold["cell"], gold["radius"]
+    m = s / g
+    rng = np.random.default_rng(11)
+    n = 400_000
+    # random pairs: first tracer uniform in a cell-aligned box, second at a random
+    # offset of length near s (uniform in a thick spherical shell around the first)
+    a = rng.uniform(0, 50 * g, size=(n, 3))
+    rad = np.cbrt(rng.uniform((s - 2 * g) ** 3, (s + 2 * g) ** 3, size=n))
+    v = rng.normal(size=(n, 3))
+    v /= np.linalg.norm(v, axis=1)[:, None]
+    b = a + rad[:, None] * v
+    ca = np.floor(a / g).astype(np.int64)
+    cb = np.floor(b / g).astype(np.int64)
+    shell = {tuple(int(x) for x in d) for d in oc.shell_offsets(m)}
+    on = np.array([tuple(x) in shell for x in (cb - ca)])
+    true = rad[on]
+    rms = float(np.sqrt(((true - true.mean()) ** 2).mean()))
+    assert abs(rms - gold["rms"]) < gold["tolerance"], rms
+    assert abs(true.mean() - s) < 0.5

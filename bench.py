@@ -1,0 +1,242 @@
+"""Throughput of the ConKer hot path on one MI355X.
+
+One step = mapping (NGP scatter of data and randoms, N = D - alpha R) ->
+convolution of N and R_raw with every shell kernel (2 * N_s shell
+convolutions) -> n-point summation of both fields -> float64 ratio, on a
+synthetic survey-shaped catalog already resident in GPU memory.  The shell
+kernel spectra are built once per grid and radius set, outside the timed
+region.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+
+Prints one JSON line.  `value` is shell convolutions completed per second of
+whole-step time on the mixed-precision path (float32 FFTs, split-bf16 matrix
+core summation); the float64 path is timed beside it.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "s to W_3 at 512³ grid, 30 radii (mixed-prec vs FP64 GPU); shell-convs/s"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_bytes(kind, n_launch_units, nc, ns, kel, n_data, n_rand, weighted, esize, batch):
+    """Algorithmic HBM bytes of all launches of one kind in one step.
+
+    esize = bytes of one real value (4 or 8); complex = 2 * esize.
+    """
+    c = 2 * esize
+    if kind == "fft_fwd_z":       # two real fields in, one complex field out
+        return 2 * nc * esize + nc * c
+    if kind in ("fft_fwd_y", "fft_fwd_x"):
+        return 2 * nc * c
+    if kind == "fft_inv_x_mul":   # spectrum read once per batch, kernel octant + output per radius
+        n_batches = math.ceil(ns / batch)
+        return n_batches * nc * c + ns * (kel * esize + nc * c)
+    if kind == "fft_inv_y":
+        return ns * 2 * nc * c
+    if kind == "fft_inv_z":       # complex in, two real maps out
+        return ns * (nc * c + 2 * nc * esize)
+    if kind == "scatter":         # positions (+ weights) in, one grid value read-modify-write per point
+        per = 12 + (4 if weighted else 0) + 2 * esize
+        return (n_data + n_rand) * per
+    if kind == "form_delta":
+        return 3 * nc * esize
+    return None
+
+
+def cpu_baseline(w, data, rand, n, sample_radii=1):
+    """The FP64 oracle on a bounded sample, extrapolated to one full step.
+
+    Sample: full mapping of both catalogs; convolution of both fields with the
+    first `sample_radii` shells; summation of the tuples among those shells.
+    The full-step time is mapping + (N_s / k) x convolution + (T / T_k) x summation.
+    """
+    from oracle import conker as oc
+    ns = len(w.radii)
+    t0 = time.perf_counter()
+    D, wd, _ = oc.histogram(data.pos, data.w, w.origin, w.cell, w.dims)
+    R, wr, _ = oc.histogram(rand.pos, rand.w, w.origin, w.cell, w.dims)
+    N, alpha = oc.density_deviation(D, R, wd, wr)
+    t1 = time.perf_counter()
+    rc = [s / w.cell for s in w.radii[:sample_radii]]
+    mN = oc.convolve_shells(N, rc)
+    mR = oc.convolve_shells(R, rc)
+    t2 = time.perf_counter()
+    oc.contract(N, mN, n)
+    oc.contract(R, mR, n)
+    t3 = time.perf_counter()
+    k = sample_radii
+    full = (t1 - t0) + (ns / k) * (t2 - t1) + (oc.num_tuples(ns, n) / oc.num_tuples(k, n)) * (t3 - t2)
+    return dict(value=2 * ns / full, unit="shell-convs/s", cores=len(os.sched_getaffinity(0)), kind="oracle",
+                sample=("full mapping of both catalogs, convolution of both fields with %d of %d shells, "
+                        "summation (n=%d) over the %d tuples of those shells; extrapolated to all %d shells "
+                        "and %d tuples" % (k, ns, n, oc.num_tuples(k, n), ns, oc.num_tuples(ns, n))),
+                sample_seconds=t3 - t0, extrapolated_step_seconds=full,
+                stage_seconds=dict(mapping=t1 - t0, convolution=t2 - t1, summation=t3 - t2))
+
+
+def run_path(ck, torch, ctx, grid, w, dpos, dw, rpos, rw, n, dtype, prec, steps, warmup, profile):
+    ks, _ = ctx.make_shell_kernels(grid, w.radii, dtype)
+    torch.cuda.synchronize()
+    bufs = {}
+
+    def step():
+        return ck.npcf(ctx, grid, dpos, rpos, ks, n, dw, rw, precision=prec, dtype=dtype, bufs=bufs)
+
+    for _ in range(warmup):
+        out = step()
+    torch.cuda.synchronize()
+    if profile:
+        ctx.profile(True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        out = step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    prof = ctx.profile_read() if profile else {}
+    if profile:
+        ctx.profile(False)
+    res = dict(ms=ms, xi=out["xi"].cpu().numpy(), Wd=out["W_delta"].cpu().numpy(),
+               Wr=out["W_rand_raw"].cpu().numpy(), alpha=float(out["alpha"].item()), prof=prof,
+               workspace=ctx.workspace_bytes())
+    del bufs, ks, out
+    torch.cuda.empty_cache()
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="cap512_ns800k_r30")
+    ap.add_argument("--n", type=int, default=3)
+    ap.add_argument("--prec", default="split_bf16", choices=["split_bf16", "f32"])
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the hot path is measured on a single MI355X "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2108_00015_amd as ck
+    import synth
+
+    w = synth.workload(args.workload)
+    t = time.perf_counter()
+    data, rand = w.make()
+    log("catalogs: %d data + %d randoms in %.1f s" % (len(data), len(rand), time.perf_counter() - t))
+    dev = torch.device("cuda:0")
+    dpos = torch.from_numpy(data.pos).to(dev)
+    rpos = torch.from_numpy(rand.pos).to(dev)
+    dw = torch.from_numpy(data.w).to(dev) if data.w is not None else None
+    rw = torch.from_numpy(rand.w).to(dev) if rand.w is not None else None
+    grid = ck.Grid(w.dims, w.origin, w.cell)
+    ctx = ck.Context(0)
+    ns = len(w.radii)
+    nc = grid.n_cells
+    kel = ck.kspec_elems(grid)
+
+    log("mixed path (float32 FFT, %s summation): warmup %d, steps %d" % (args.prec, args.warmup, args.steps))
+    mixed = run_path(ck, torch, ctx, grid, w, dpos, dw, rpos, rw, args.n, torch.float32, args.prec,
+                     args.steps, args.warmup, True)
+    log("  %.2f ms/step" % mixed["ms"])
+    fp64 = None
+    if not args.no_fp64:
+        log("float64 path: warmup %d, steps %d" % (args.warmup, args.steps))
+        fp64 = run_path(ck, torch, ctx, grid, w, dpos, dw, rpos, rw, args.n, torch.float64, "f64",
+                        args.steps, args.warmup, True)
+        log("  %.2f ms/step" % fp64["ms"])
+
+    batch = int(os.environ.get("CONKER_RADIUS_BATCH", "4"))
+    batch = min(batch, ns)
+    stages = {}
+    for kind, (launches, tot) in mixed["prof"].items():
+        per_step = tot / args.steps
+        b = kernel_bytes(kind, launches, nc, ns, kel, len(data), len(rand), data.w is not None, 4, batch)
+        if kind == "contract_mm":
+            b = 2 * (ns + 1) * nc * 4
+        ent = dict(launches_per_step=launches / args.steps, ms_per_step=per_step,
+                   avg_launch_ms=tot / launches)
+        if b is not None:
+            ent["gbs"] = b / (per_step * 1e-3) / 1e9
+            ent["bytes_per_launch"] = b / (launches / args.steps)
+        stages[kind] = ent
+    # dominant kernel: largest time per step
+    dom = max(stages.items(), key=lambda kv: kv[1]["ms_per_step"]) if stages else None
+    roof = None
+    if dom is not None and "gbs" in dom[1]:
+        ach = dom[1]["bytes_per_launch"] / (dom[1]["avg_launch_ms"] * 1e-3) / 1e9
+        roof = dict(bound="hbm", kernel=dom[0], achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(ach / HBM_PEAK_GBS, 4), traffic=None,
+                    bytes_per_launch=dom[1]["bytes_per_launch"], avg_launch_ms=dom[1]["avg_launch_ms"])
+
+    cpu = None
+    if not args.no_cpu:
+        log("cpu baseline (oracle, bounded sample)")
+        cpu = cpu_baseline(w, data, rand, args.n)
+        log("  %.3f shell-convs/s on %d cores" % (cpu["value"], cpu["cores"]))
+
+    s_mixed = mixed["ms"] / 1e3
+    line = {
+        "metric": METRIC,
+        "value": round(2 * ns / s_mixed, 3),
+        "unit": "shell-convs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(mixed["ms"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "grid": list(w.dims), "cell": w.cell, "n_radii": ns,
+                   "radii": [w.radii[0], w.radii[-1]], "n": args.n, "n_data": len(data),
+                   "n_randoms": len(rand), "weights": "log-normal sigma 0.2",
+                   "summation": args.prec, "fft": "f32"},
+        "s_to_W3_mixed": round(s_mixed, 5),
+        "s_to_W3_fp64": round(fp64["ms"] / 1e3, 5) if fp64 else None,
+        "fp64_over_mixed": round(fp64["ms"] / mixed["ms"], 3) if fp64 else None,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "stages_mixed": stages,
+    }
+    if fp64:
+        st64 = {}
+        for kind, (launches, tot) in fp64["prof"].items():
+            st64[kind] = dict(launches_per_step=launches / args.steps, ms_per_step=tot / args.steps)
+        line["stages_fp64"] = st64
+        # agreement of the two GPU paths on this workload (relative to the largest entry)
+        line["mixed_vs_fp64_rel"] = {
+            "W_delta": float(np.abs(mixed["Wd"] - fp64["Wd"]).max() / np.abs(fp64["Wd"]).max()),
+            "W_rand": float(np.abs(mixed["Wr"] - fp64["Wr"]).max() / np.abs(fp64["Wr"]).max()),
+        }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

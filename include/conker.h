@@ -1,0 +1,194 @@
+/*
+ * conker.h -- C ABI of the MI355X (gfx950) ConKer hot path.
+ *
+ * ConKer (Brown, Mishtaku & Demina, arXiv:2108.00015) estimates isotropic
+ * n-point correlation functions of tracer catalogs in three stages:
+ *   mapping      (Sec. 2.2, Eq. bgsubtracted_map)  conker_grid_assign, conker_form_delta
+ *   kernels      (Sec. 2.3)                         conker_make_shell_kernels
+ *   convolution  (Sec. 2.4, Eqs. countconv/randconv) conker_convolve_shells
+ *   summation    (Sec. 2.5, Eq. ksin_delta)         conker_contract_npt, conker_ratio
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - d_* arguments are device pointers, h_* arguments host pointers.  The caller
+ *   owns every buffer it passes; the library never frees or retains them past
+ *   the call's stream work.
+ * - Grids are C order [nx][ny][nz] (z fastest), real float32 or float64 per
+ *   the conker_dtype argument.  Supported axis lengths: 32, 64, 128, 256, 512,
+ *   1024 (powers of two).
+ * - Every call enqueues work on the context's HIP stream and returns without
+ *   waiting for it (except where noted).  A context serves one stream and is
+ *   not thread-safe.
+ * - Every call returns CONKER_OK or a negative conker_status; nothing is
+ *   thrown.  Invalid arguments are rejected before any launch, and
+ *   conker_last_error() describes the last failure.
+ * - The context owns internal workspace (FFT spectra, partial sums, twiddle
+ *   tables), bounded by workspace_max_bytes; it is freed by conker_destroy.
+ */
+#ifndef CONKER_H
+#define CONKER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct conker_ctx conker_ctx;
+
+typedef enum {
+    CONKER_OK = 0,
+    CONKER_EINVAL = -1,       /* bad pointer, size or enum value              */
+    CONKER_ENOMEM = -2,       /* workspace above the cap, or allocation failed */
+    CONKER_EUNSUPPORTED = -3, /* axis length or order outside what is built   */
+    CONKER_EHIP = -4,         /* a HIP runtime call failed                     */
+    CONKER_ERANGE = -5        /* shell radius below half a cell or too large   */
+} conker_status;
+
+typedef enum { CONKER_F32 = 1, CONKER_F64 = 2 } conker_dtype;
+
+/* Arithmetic of the summation stage. */
+typedef enum {
+    CONKER_MM_F64 = 0,        /* float64 maps, float64 matrix cores            */
+    CONKER_MM_F32 = 1,        /* float32 maps, float32 matrix cores            */
+    CONKER_MM_SPLIT_BF16 = 2  /* float32 maps split into three bfloat16 terms,
+                                 bf16 matrix cores, float32 accumulation over
+                                 short chains, float64 across chains          */
+} conker_mmprec;
+
+/* Grid of spacing `cell` whose cell (0,0,0) has its lower corner at `origin`
+ * (Sec. 2.2).  Cell index of a point x: floor((x - origin) / cell) per axis,
+ * evaluated in float64. */
+typedef struct {
+    int32_t dims[3];
+    double origin[3];
+    double cell;
+} conker_grid;
+
+/* ---- context -------------------------------------------------------------
+ * conker_create: binds a context to HIP device `device` and stream
+ * `hip_stream` (a hipStream_t; NULL = the default stream).
+ * workspace_max_bytes caps internal allocations (0 = no cap).
+ * On success *out holds the context; on failure *out is NULL. */
+int conker_create(conker_ctx **out, int device, void *hip_stream, size_t workspace_max_bytes);
+void conker_destroy(conker_ctx *ctx);
+int conker_set_stream(conker_ctx *ctx, void *hip_stream);
+/* Message of the last failure on this context ("" if none).  With ctx NULL,
+ * the message of the last conker_create failure in this thread. */
+const char *conker_last_error(const conker_ctx *ctx);
+/* Bytes of internal workspace currently held by the context. */
+size_t conker_workspace_bytes(const conker_ctx *ctx);
+
+/* ---- mapping (Sec. 2.2) ----------------------------------------------------
+ * conker_grid_assign: nearest-grid-point histogram of a catalog.
+ *   d_pos        float32 [n][3] positions (x, y, z).
+ *   d_w          float32 [n] weights, or NULL for unit weights.
+ *   grid_dtype   dtype of d_grid; d_grid is ACCUMULATED into (zero it first).
+ *   d_wsum       float64 scalar, += sum of the weights of in-grid points
+ *                (may be NULL).
+ *   d_n_outside  int64 scalar, += number of points outside the grid or with a
+ *                non-finite coordinate or weight (may be NULL).  Such points
+ *                are skipped.
+ * Accumulation order is unspecified: float32 grids with non-integer weights
+ * are exact only up to rounding; unit weights give exact integer counts. */
+int conker_grid_assign(conker_ctx *ctx, const conker_grid *grid,
+                       const float *d_pos, const float *d_w, int64_t n,
+                       conker_dtype grid_dtype, void *d_grid,
+                       double *d_wsum, int64_t *d_n_outside);
+
+/* conker_form_delta: the density-variation histogram N = D - alpha R_raw with
+ * alpha = wsum_data / wsum_rand (R normalised to the data total,
+ * Eq. bgsubtracted_map).  d_grid holds D on entry and N on exit; d_rand holds
+ * R_raw (unchanged).  alpha is computed on the device in float64 and written
+ * to d_alpha (float64 scalar).  The subtraction is done in float64 and
+ * rounded once to the grid dtype. */
+int conker_form_delta(conker_ctx *ctx, const conker_grid *grid, conker_dtype dtype,
+                      void *d_grid, const void *d_rand,
+                      const double *d_wsum_data, const double *d_wsum_rand,
+                      double *d_alpha);
+
+/* ---- kernels (Sec. 2.3) ----------------------------------------------------
+ * A shell of radius s (length units) holds the lattice offsets delta with
+ * r - 1/2 <= |delta| < r + 1/2, r = s / cell.  It must satisfy r >= 1/2 and
+ * 2M + 1 <= min(dims), M = ceil(r + 1/2) - 1 (CONKER_ERANGE otherwise).
+ *
+ * conker_shell_size: number of offsets in the shell of r cells (host only). */
+int conker_shell_size(double r_cells, int64_t *h_size);
+
+/* Elements per radius of the stored kernel spectrum:
+ * (nx/2+1) * (ny/2+1) * (nz/2+1). */
+int64_t conker_kspec_elems(const conker_grid *grid);
+
+/* conker_make_shell_kernels: spectra of the shell indicators, K_hat_m / N_c,
+ * for n_radii radii h_radii[] (length units).  The spectrum of a
+ * point-symmetric shell is real and even in each axis, so only the octant
+ * 0 <= k <= n/2 per axis is stored:
+ *   d_kspec  dtype [n_radii][nx/2+1][ny/2+1][nz/2+1].
+ * The transform is done in float64 and rounded once to dtype.
+ * h_shell_sizes (may be NULL) receives |S_m| per radius. */
+int conker_make_shell_kernels(conker_ctx *ctx, const conker_grid *grid,
+                              const double *h_radii, int n_radii, conker_dtype dtype,
+                              void *d_kspec, int64_t *h_shell_sizes);
+
+/* ---- convolution (Sec. 2.4, Eqs. countconv, randconv) ---------------------
+ * conker_convolve_shells: per-radius shell-sum maps of one or two real fields,
+ *   maps_a[m](x) = sum over delta in S_m of field_a((x + delta) mod dims),
+ * i.e. the circular 3D convolution field *** K_m done with FFTs.  The two
+ * fields (typically N and R_raw) share every transform: they travel as the
+ * real and imaginary parts of one complex field, which the real, even kernel
+ * spectrum keeps apart.
+ *   d_field_a, d_field_b   dtype [nx][ny][nz]; d_field_b may be NULL.
+ *   d_kspec                from conker_make_shell_kernels (same grid, dtype).
+ *   d_maps_a, d_maps_b     dtype [n_radii][nx][ny][nz]; d_maps_b must be NULL
+ *                          exactly when d_field_b is. */
+int conker_convolve_shells(conker_ctx *ctx, const conker_grid *grid, conker_dtype dtype,
+                           const void *d_field_a, const void *d_field_b,
+                           const void *d_kspec, int n_radii,
+                           void *d_maps_a, void *d_maps_b);
+
+/* ---- summation (Sec. 2.5, Eqs. ksin_delta, ksi2_delta, ksi3, ksinDiag) ----
+ * Number of radius tuples of order n: multisets a_1 <= ... <= a_{n-1} of
+ * n_radii shell indices, C(n_radii + n - 2, n - 1).  Returns -1 if n < 2. */
+int64_t conker_num_tuples(int n_radii, int n);
+
+/* conker_contract_npt:
+ *   W[t] = sum over all cells x of field(x) * prod_i maps[a_i](x)
+ * for every tuple t = (a_1 <= ... <= a_{n-1}), in lexicographic order.
+ *   d_field  dtype [nx][ny][nz];  d_maps dtype [n_radii][nx][ny][nz].
+ *   n        2..5;  n_radii 1..64.
+ *   prec     CONKER_MM_F64 needs dtype F64; CONKER_MM_F32 and
+ *            CONKER_MM_SPLIT_BF16 need dtype F32.
+ *   d_W      float64 [conker_num_tuples(n_radii, n)], overwritten. */
+int conker_contract_npt(conker_ctx *ctx, const conker_grid *grid, conker_dtype dtype,
+                        const void *d_field, const void *d_maps, int n_radii, int n,
+                        conker_mmprec prec, double *d_W);
+
+/* conker_ratio: the estimator xi = W_delta / (alpha^n W_rand) in float64
+ * (Eq. ksin_delta with B_i built on R = alpha R_raw).  All pointers are
+ * device float64; d_alpha is a scalar. */
+int conker_ratio(conker_ctx *ctx, const double *d_Wd, const double *d_Wr,
+                 const double *d_alpha, int n, int64_t count, double *d_xi);
+
+/* Blocks until all work queued on the context's stream has finished. */
+int conker_synchronize(conker_ctx *ctx);
+
+/* ---- per-launch timing ----------------------------------------------------
+ * Not part of the method; used to report where the time goes, as the paper's
+ * timing study splits it into mapping, convolution and summation (Sec. 3.2).
+ * conker_profile_enable: with enable != 0, every later kernel launch of the
+ *   library is bracketed by HIP events on the context stream; any previous
+ *   records are dropped.  Waits for the stream first.
+ * conker_profile_read: number of launches and their summed event time (ms)
+ *   recorded for one launch kind; waits for the stream.
+ * conker_profile_kind_name: name of a launch kind (0 .. count-1), NULL past
+ *   the last one. */
+int conker_profile_enable(conker_ctx *ctx, int enable);
+int conker_profile_read(conker_ctx *ctx, int kind, int64_t *launches, double *total_ms);
+const char *conker_profile_kind_name(int kind);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CONKER_H */

@@ -1,0 +1,15 @@
+"""MI355X-native ConKer hot path: mapping, shell convolution and n-point summation.
+
+The compute runs in libconker.so (HIP, gfx950); this package only binds it to
+PyTorch tensors.  See include/conker.h for the C ABI.
+"""
+from .api import (  # noqa: F401
+    ConkerError,
+    Context,
+    Grid,
+    PRECISIONS,
+    kspec_elems,
+    npcf,
+    num_tuples,
+    shell_size,
+)

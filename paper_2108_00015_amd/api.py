@@ -1,0 +1,241 @@
+"""PyTorch-facing binding of the ConKer C ABI (include/conker.h).
+
+Argument marshalling only: every step runs in the HIP library.  Tensors must
+be CUDA (HIP) tensors on the context's device; the work is queued on the
+current torch stream of that device (or the stream the context was created
+with).  Errors from the library raise ConkerError with the library's message.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import dataclasses
+from typing import Optional, Sequence, Tuple
+
+import torch
+
+from . import _lib
+
+_DT = {torch.float32: _lib.F32, torch.float64: _lib.F64}
+PRECISIONS = {"f64": _lib.MM_F64, "f32": _lib.MM_F32, "split_bf16": _lib.MM_SPLIT_BF16}
+
+
+class ConkerError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (_lib.STATUS_NAMES.get(status, status), msg))
+        self.status = status
+
+
+@dataclasses.dataclass(frozen=True)
+class Grid:
+    """Grid of spacing `cell` whose cell (0, 0, 0) starts at `origin` (Sec. 2.2)."""
+    dims: Tuple[int, int, int]
+    origin: Tuple[float, float, float]
+    cell: float
+
+    @property
+    def n_cells(self) -> int:
+        return int(self.dims[0]) * int(self.dims[1]) * int(self.dims[2])
+
+    def c(self) -> _lib.ConkerGrid:
+        g = _lib.ConkerGrid()
+        for k in range(3):
+            g.dims[k] = int(self.dims[k])
+            g.origin[k] = float(self.origin[k])
+        g.cell = float(self.cell)
+        return g
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensor must be on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ct.c_void_p(t.data_ptr())
+
+
+def num_tuples(n_radii: int, n: int) -> int:
+    return int(_lib.load().conker_num_tuples(int(n_radii), int(n)))
+
+
+def shell_size(r_cells: float) -> int:
+    out = ct.c_int64()
+    st = _lib.load().conker_shell_size(float(r_cells), ct.byref(out))
+    if st != _lib.OK:
+        raise ConkerError(st, "shell radius %g cells" % r_cells)
+    return int(out.value)
+
+
+def kspec_elems(grid: Grid) -> int:
+    g = grid.c()
+    return int(_lib.load().conker_kspec_elems(ct.byref(g)))
+
+
+class Context:
+    """One library context bound to a device and a HIP stream."""
+
+    def __init__(self, device: int = 0, stream: Optional[torch.cuda.Stream] = None,
+                 workspace_max_bytes: int = 0):
+        self.lib = _lib.load()
+        self.device = int(device)
+        h = ct.c_void_p()
+        s = (stream if stream is not None else torch.cuda.current_stream(self.device)).cuda_stream
+        st = self.lib.conker_create(ct.byref(h), self.device, ct.c_void_p(s), int(workspace_max_bytes))
+        if st != _lib.OK:
+            raise ConkerError(st, self.lib.conker_last_error(None).decode())
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.conker_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st: int):
+        if st != _lib.OK:
+            raise ConkerError(st, self.lib.conker_last_error(self.h).decode())
+
+    def set_stream(self, stream: torch.cuda.Stream):
+        self._check(self.lib.conker_set_stream(self.h, ct.c_void_p(stream.cuda_stream)))
+
+    def synchronize(self):
+        self._check(self.lib.conker_synchronize(self.h))
+
+    def profile(self, enable: bool = True):
+        """Start (or stop) per-launch event timing; drops earlier records."""
+        self._check(self.lib.conker_profile_enable(self.h, 1 if enable else 0))
+
+    def profile_read(self) -> dict:
+        """{kind name: (launches, total ms)} for every kind with at least one launch."""
+        out = {}
+        k = 0
+        while True:
+            name = self.lib.conker_profile_kind_name(k)
+            if name is None:
+                break
+            n = ct.c_int64()
+            ms = ct.c_double()
+            self._check(self.lib.conker_profile_read(self.h, k, ct.byref(n), ct.byref(ms)))
+            if n.value:
+                out[name.decode()] = (int(n.value), float(ms.value))
+            k += 1
+        return out
+
+    def workspace_bytes(self) -> int:
+        return int(self.lib.conker_workspace_bytes(self.h))
+
+    # ---- mapping -----------------------------------------------------------
+    def grid_assign(self, grid: Grid, pos: torch.Tensor, w: Optional[torch.Tensor], out: torch.Tensor,
+                    wsum: Optional[torch.Tensor] = None, n_outside: Optional[torch.Tensor] = None):
+        if pos.dtype != torch.float32 or pos.dim() != 2 or pos.shape[1] != 3:
+            raise ValueError("positions must be float32 [N, 3]")
+        if w is not None and (w.dtype != torch.float32 or w.numel() != pos.shape[0]):
+            raise ValueError("weights must be float32 [N]")
+        if out.dtype not in _DT or out.numel() != grid.n_cells:
+            raise ValueError("grid tensor must be float32/float64 with dims cells")
+        if wsum is not None and wsum.dtype != torch.float64:
+            raise ValueError("wsum must be float64")
+        if n_outside is not None and n_outside.dtype != torch.int64:
+            raise ValueError("n_outside must be int64")
+        g = grid.c()
+        self._check(self.lib.conker_grid_assign(self.h, ct.byref(g), _ptr(pos), _ptr(w), int(pos.shape[0]),
+                                                _DT[out.dtype], _ptr(out), _ptr(wsum), _ptr(n_outside)))
+
+    def form_delta(self, grid: Grid, D: torch.Tensor, R: torch.Tensor, wsum_data: torch.Tensor,
+                   wsum_rand: torch.Tensor, alpha: torch.Tensor):
+        if D.dtype != R.dtype or D.numel() != grid.n_cells or R.numel() != grid.n_cells:
+            raise ValueError("D and R must be grids of one dtype")
+        g = grid.c()
+        self._check(self.lib.conker_form_delta(self.h, ct.byref(g), _DT[D.dtype], _ptr(D), _ptr(R),
+                                               _ptr(wsum_data), _ptr(wsum_rand), _ptr(alpha)))
+
+    # ---- kernels -----------------------------------------------------------
+    def make_shell_kernels(self, grid: Grid, radii: Sequence[float], dtype=torch.float32
+                           ) -> Tuple[torch.Tensor, list]:
+        nr = len(radii)
+        kel = kspec_elems(grid)
+        out = torch.empty((nr, kel), dtype=dtype, device="cuda:%d" % self.device)
+        rad = (ct.c_double * nr)(*[float(r) for r in radii])
+        sizes = (ct.c_int64 * nr)()
+        g = grid.c()
+        self._check(self.lib.conker_make_shell_kernels(self.h, ct.byref(g), rad, nr, _DT[dtype], _ptr(out),
+                                                       sizes))
+        return out, [int(s) for s in sizes]
+
+    # ---- convolution -------------------------------------------------------
+    def convolve_shells(self, grid: Grid, field_a: torch.Tensor, field_b: Optional[torch.Tensor],
+                        kspec: torch.Tensor, maps_a: Optional[torch.Tensor] = None,
+                        maps_b: Optional[torch.Tensor] = None):
+        nr = int(kspec.shape[0])
+        dt = field_a.dtype
+        if kspec.dtype != dt or (field_b is not None and field_b.dtype != dt):
+            raise ValueError("fields and kernel spectra must share a dtype")
+        shape = (nr,) + tuple(int(d) for d in grid.dims)
+        if maps_a is None:
+            maps_a = torch.empty(shape, dtype=dt, device=field_a.device)
+        if field_b is not None and maps_b is None:
+            maps_b = torch.empty(shape, dtype=dt, device=field_a.device)
+        g = grid.c()
+        self._check(self.lib.conker_convolve_shells(self.h, ct.byref(g), _DT[dt], _ptr(field_a), _ptr(field_b),
+                                                    _ptr(kspec), nr, _ptr(maps_a), _ptr(maps_b)))
+        return maps_a, maps_b
+
+    # ---- summation ---------------------------------------------------------
+    def contract_npt(self, grid: Grid, field: torch.Tensor, maps: torch.Tensor, n: int,
+                     precision: str = "f64", out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        nr = int(maps.shape[0])
+        cnt = num_tuples(nr, n)
+        if out is None:
+            out = torch.empty(max(cnt, 0), dtype=torch.float64, device=field.device)
+        g = grid.c()
+        self._check(self.lib.conker_contract_npt(self.h, ct.byref(g), _DT[field.dtype], _ptr(field), _ptr(maps),
+                                                 nr, int(n), PRECISIONS[precision], _ptr(out)))
+        return out
+
+    def ratio(self, Wd: torch.Tensor, Wr: torch.Tensor, alpha: torch.Tensor, n: int,
+              out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty_like(Wd)
+        self._check(self.lib.conker_ratio(self.h, _ptr(Wd), _ptr(Wr), _ptr(alpha), int(n), int(Wd.numel()),
+                                          _ptr(out)))
+        return out
+
+
+def npcf(ctx: Context, grid: Grid, data_pos: torch.Tensor, rand_pos: torch.Tensor, kspec: torch.Tensor,
+         n: int, data_w: Optional[torch.Tensor] = None, rand_w: Optional[torch.Tensor] = None,
+         precision: str = "f64", dtype=torch.float64, bufs: Optional[dict] = None) -> dict:
+    """Mapping -> convolution -> summation -> estimator, chaining the C ABI calls.
+
+    `bufs` may hold preallocated tensors (keys: N, R, maps_N, maps_R, wsum, nout, alpha) that are
+    reused across calls.  Returns xi, W_delta, W_rand_raw, alpha and the buffers (all on the GPU).
+    """
+    dev = data_pos.device
+    b = {} if bufs is None else bufs
+    shape = tuple(int(d) for d in grid.dims)
+    nr = int(kspec.shape[0])
+    if "N" not in b:
+        b["N"] = torch.empty(shape, dtype=dtype, device=dev)
+        b["R"] = torch.empty(shape, dtype=dtype, device=dev)
+        b["maps_N"] = torch.empty((nr,) + shape, dtype=dtype, device=dev)
+        b["maps_R"] = torch.empty((nr,) + shape, dtype=dtype, device=dev)
+        b["wsum"] = torch.empty(2, dtype=torch.float64, device=dev)
+        b["nout"] = torch.empty(2, dtype=torch.int64, device=dev)
+        b["alpha"] = torch.empty(1, dtype=torch.float64, device=dev)
+    b["N"].zero_()
+    b["R"].zero_()
+    b["wsum"].zero_()
+    b["nout"].zero_()
+    ctx.grid_assign(grid, data_pos, data_w, b["N"], b["wsum"][0:1], b["nout"][0:1])
+    ctx.grid_assign(grid, rand_pos, rand_w, b["R"], b["wsum"][1:2], b["nout"][1:2])
+    ctx.form_delta(grid, b["N"], b["R"], b["wsum"][0:1], b["wsum"][1:2], b["alpha"])
+    ctx.convolve_shells(grid, b["N"], b["R"], kspec, b["maps_N"], b["maps_R"])
+    Wd = ctx.contract_npt(grid, b["N"], b["maps_N"], n, precision)
+    Wr = ctx.contract_npt(grid, b["R"], b["maps_R"], n, precision)
+    xi = ctx.ratio(Wd, Wr, b["alpha"], n)
+    return dict(xi=xi, W_delta=Wd, W_rand_raw=Wr, alpha=b["alpha"], bufs=b)

@@ -1,0 +1,150 @@
+// Internal declarations shared by the ConKer HIP translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/conker.h"
+
+namespace conker {
+
+// ---------------------------------------------------------------------------
+// device buffers owned by a context
+// ---------------------------------------------------------------------------
+struct Buf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace conker
+
+struct conker_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    size_t ws_cap = 0;      // 0 = unlimited
+    size_t ws_bytes = 0;    // bytes currently held
+    std::string err;
+    // twiddle tables exp(-2 pi i t / L), t in [0, L), keyed by L
+    std::map<int, conker::Buf> tw32, tw64;
+    conker::Buf spec;       // forward spectrum of the packed field pair
+    conker::Buf tspec;      // per-radius spectra of one radius batch
+    conker::Buf partial;    // per-workgroup partial sums of the summation stage
+    conker::Buf full;       // reduced block matrices of the summation stage
+    std::map<uint64_t, conker::Buf> tables;  // item / tuple tables, keyed by (n_radii, n, prec)
+    // per-launch event timing (conker_profile_enable)
+    bool prof = false;
+    struct Rec {
+        int kind;
+        hipEvent_t e0, e1;
+    };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+};
+
+namespace conker {
+
+// ---------------------------------------------------------------------------
+// launch kinds reported by conker_profile_read
+// ---------------------------------------------------------------------------
+enum ProfKind {
+    PK_SCATTER = 0,
+    PK_FORM_DELTA,
+    PK_FFT_FWD_Z,
+    PK_FFT_FWD_Y,
+    PK_FFT_FWD_X,
+    PK_FFT_INV_X_MUL,
+    PK_FFT_INV_Y,
+    PK_FFT_INV_Z,
+    PK_BANK_Z,
+    PK_BANK_Y,
+    PK_BANK_X,
+    PK_CONTRACT_DOT,
+    PK_CONTRACT_MM,
+    PK_CONTRACT_REDUCE,
+    PK_RATIO,
+    PK_COUNT
+};
+
+// Brackets the launches of one kind with events on the context stream while
+// profiling is enabled; free otherwise.
+struct ProfScope {
+    conker_ctx *c;
+    int kind;
+    hipEvent_t e0 = nullptr;
+    ProfScope(conker_ctx *ctx, int k);
+    ~ProfScope();
+};
+
+// ---------------------------------------------------------------------------
+// status helpers
+// ---------------------------------------------------------------------------
+int fail(conker_ctx *ctx, int code, const char *fmt, ...);
+
+#define CK_HIP(ctx, expr)                                                           \
+    do {                                                                            \
+        hipError_t e_ = (expr);                                                     \
+        if (e_ != hipSuccess)                                                       \
+            return ::conker::fail((ctx), CONKER_EHIP, "%s failed: %s (%s:%d)", #expr, \
+                                  hipGetErrorString(e_), __FILE__, __LINE__);       \
+    } while (0)
+
+#define CK_LAUNCH(ctx)                                                              \
+    do {                                                                            \
+        hipError_t e_ = hipGetLastError();                                          \
+        if (e_ != hipSuccess)                                                       \
+            return ::conker::fail((ctx), CONKER_EHIP, "kernel launch failed: %s (%s:%d)", \
+                                  hipGetErrorString(e_), __FILE__, __LINE__);       \
+    } while (0)
+
+#define CK_OK(expr)                   \
+    do {                              \
+        int s_ = (expr);              \
+        if (s_ != CONKER_OK) return s_; \
+    } while (0)
+
+// Grows `b` to at least `bytes` (contents are not preserved).  Respects the
+// context's workspace cap.  Waits for the stream before releasing memory.
+int ws_reserve(conker_ctx *ctx, Buf &b, size_t bytes);
+
+// Device twiddle table of length L (float2 or double2), built on first use.
+int twiddles(conker_ctx *ctx, int L, bool f64, const void **out);
+
+// Validates ctx / grid pointers and the FFT-supported axis lengths.
+int check_grid(conker_ctx *ctx, const conker_grid *g, bool need_fft);
+
+inline size_t ncells(const conker_grid *g) {
+    return (size_t)g->dims[0] * (size_t)g->dims[1] * (size_t)g->dims[2];
+}
+
+inline bool fft_length_ok(int L) {
+    return L == 32 || L == 64 || L == 128 || L == 256 || L == 512 || L == 1024;
+}
+
+// Largest offset component of a shell of radius r cells: ceil(r + 1/2) - 1.
+int shell_reach(double r);
+// Validates a shell radius (cells) against the grid; CONKER_ERANGE if it does not fit.
+int check_shell(conker_ctx *ctx, const conker_grid *g, double r_cells);
+
+// FFT passes (fft.hip) ------------------------------------------------------
+// Forward 3D FFT of the complex field packed from two real fields
+// (a + i b) into the spectrum buffer `spec` (natural order, unnormalised).
+int fft_forward_pair(conker_ctx *ctx, const conker_grid *g, bool f64,
+                     const void *a, const void *b, void *spec);
+// Forward 3D FFT of two shell indicators packed as (K_ra + i K_rb), float64,
+// followed by extraction of the real octant spectra (scaled by 1/N_c) into
+// kspec rows ma and mb (mb < 0: none) with dtype out_f64 ? double : float.
+int fft_shell_pair(conker_ctx *ctx, const conker_grid *g, double lo_a, double hi_a,
+                   double lo_b, double hi_b, void *work, void *kspec, bool out_f64,
+                   int ma, int mb);
+// Inverse passes for radii [m0, m0 + nb): multiply spectrum by K_m, inverse
+// 3D FFT, write real parts to maps_a[m] and imaginary parts to maps_b[m].
+int fft_inverse_batch(conker_ctx *ctx, const conker_grid *g, bool f64,
+                      const void *spec, const void *kspec, int m0, int nb, void *tspec,
+                      void *maps_a, void *maps_b);
+
+}  // namespace conker

@@ -1,0 +1,625 @@
+// Summation stage (Sec. 2.5, Eq. ksin_delta):
+//   W(a_1..a_{n-1}) = sum_x F(x) prod_i C_{a_i}(x)
+// for every multiset a_1 <= ... <= a_{n-1} of shell indices.
+//
+// n = 2 is a set of dot products and runs on the vector ALUs.
+// n = 3, 4, 5 are written as one matrix product over the cells:
+//   rows    = left items  (F * C_a for n = 3; F * C_a * C_b, a <= b, for n = 4, 5)
+//   columns = right items (C_c for n = 3, 4; C_c * C_d, c <= d, for n = 5)
+//   M[row][col] = sum_x row(x) * col(x)
+// and every tuple is one entry of M: (a, b) for n = 3, ((a, b), c) for n = 4,
+// ((a, b), (c, d)) for n = 5.  M is computed in output tiles on the matrix
+// cores; each lane builds its operand values on the fly from the maps, so no
+// item product is ever stored.  Cells are split across workgroups; each
+// workgroup writes float64 partial tiles that a second kernel sums in a fixed
+// order, and a third gathers the tuple entries.
+//
+// Matrix-core instructions (gfx950, wave64):
+//   float64:  v_mfma_f64_16x16x4_f64    (16x16 tiles, 4 cells per instruction)
+//   float32:  v_mfma_f32_32x32x2_f32    (32x32 tiles, 2 cells per instruction)
+//   split:    v_mfma_f32_32x32x16_bf16  (32x32 tiles, 16 cells per instruction);
+//             each float32 operand is split into three bfloat16 terms
+//             x = h + m + l and the six products of order <= 2^-16 relative
+//             (hh, hm, mh, hl, mm, lh) are accumulated.
+// float32 accumulators are flushed into float64 registers every ~128 cells.
+#include <algorithm>
+#include <type_traits>
+
+#include "common.h"
+
+using namespace conker;
+
+namespace {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int NT = 256;
+constexpr int WAVES = NT / 64;
+
+// Item code of one lane for one tile: maps (a, b) for the left item and
+// (c, d) for the right item.  -1 = no factor (value 1), -2 = padding (value 0).
+struct Items {
+    int a, b, c, d;
+};
+
+// V consecutive values starting at a 16-byte aligned address, as 16-byte loads
+template <typename T, int V>
+__device__ __forceinline__ void ld(const T *__restrict__ p, T (&v)[V]) {
+    if constexpr (std::is_same<T, float>::value) {
+        static_assert(V % 4 == 0, "float loads come in fours");
+#pragma unroll
+        for (int q = 0; q < V / 4; ++q) {
+            const float4 u = reinterpret_cast<const float4 *>(p)[q];
+            v[4 * q + 0] = u.x;
+            v[4 * q + 1] = u.y;
+            v[4 * q + 2] = u.z;
+            v[4 * q + 3] = u.w;
+        }
+    } else {
+        static_assert(V % 2 == 0, "double loads come in pairs");
+#pragma unroll
+        for (int q = 0; q < V / 2; ++q) {
+            const double2 u = reinterpret_cast<const double2 *>(p)[q];
+            v[2 * q + 0] = u.x;
+            v[2 * q + 1] = u.y;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// n = 2: W(a) = sum_x F(x) C_a(x), float64 accumulation
+// ---------------------------------------------------------------------------
+template <typename T, int NS>
+__global__ __launch_bounds__(NT) void k_dot(const T *__restrict__ F, const T *__restrict__ maps,
+                                            size_t nc, int n_radii, size_t chunk,
+                                            double *__restrict__ partial) {
+    constexpr int V = std::is_same<T, float>::value ? 4 : 2;   // cells per 16-byte load
+    double acc[NS];
+#pragma unroll
+    for (int a = 0; a < NS; ++a) acc[a] = 0.0;
+    const size_t c0 = (size_t)blockIdx.x * chunk;
+    const size_t c1 = std::min(c0 + chunk, nc);
+    for (size_t x = c0 + (size_t)threadIdx.x * V; x < c1; x += (size_t)NT * V) {
+        T f[V];
+        ld<T, V>(F + x, f);
+#pragma unroll
+        for (int a = 0; a < NS; ++a) {
+            if (a < n_radii) {
+                T m[V];
+                ld<T, V>(maps + (size_t)a * nc + x, m);
+#pragma unroll
+                for (int e = 0; e < V; ++e) acc[a] += (double)f[e] * (double)m[e];
+            }
+        }
+    }
+    __shared__ double red[WAVES][NS];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int a = 0; a < NS; ++a) {
+        double v = acc[a];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+        if (lane == 0) red[w][a] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < n_radii) {
+        double s = 0.0;
+        for (int k = 0; k < WAVES; ++k) s += red[k][threadIdx.x];
+        partial[(size_t)blockIdx.x * n_radii + threadIdx.x] = s;
+    }
+}
+
+// One block per radius: strided partial sums, then a fixed-order tree in LDS.
+__global__ __launch_bounds__(256) void k_dot_reduce(const double *__restrict__ partial, int G, int n_radii,
+                                                    double *W) {
+    const int a = blockIdx.x;
+    double s = 0.0;
+    for (int g = threadIdx.x; g < G; g += 256) s += partial[(size_t)g * n_radii + a];
+    __shared__ double t[256];
+    t[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) t[threadIdx.x] += t[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) W[a] = t[0];
+}
+
+// ---------------------------------------------------------------------------
+// operand values: product of up to two maps at V consecutive cells
+// ---------------------------------------------------------------------------
+template <typename T, int V>
+__device__ __forceinline__ void item_vals(const T *__restrict__ maps, size_t nc, size_t x, int a, int b,
+                                          T (&v)[V]) {
+    if (a == -2) {
+#pragma unroll
+        for (int e = 0; e < V; ++e) v[e] = (T)0;
+        return;
+    }
+    if (a >= 0) {
+        ld<T, V>(maps + (size_t)a * nc + x, v);
+    } else {
+#pragma unroll
+        for (int e = 0; e < V; ++e) v[e] = (T)1;
+    }
+    if (b >= 0) {
+        T u[V];
+        ld<T, V>(maps + (size_t)b * nc + x, u);
+#pragma unroll
+        for (int e = 0; e < V; ++e) v[e] *= u[e];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// matrix-core kernels.  Grid: (cell chunks, tile groups).  Each workgroup of
+// four waves handles one cell chunk for NBW output tiles; the waves split the
+// chunk, then combine their float64 tiles through LDS.
+// ---------------------------------------------------------------------------
+template <int TS>
+__device__ void wave_combine_store(double (&acc)[TS * TS / 64], double *lds, double *out) {
+    // acc holds this lane's share of one TS x TS tile in instruction layout
+    constexpr int PL = TS * TS / 64;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int v = 0; v < PL; ++v) lds[(w * PL + v) * 64 + lane] = acc[v];
+    __syncthreads();
+    for (int e = threadIdx.x; e < TS * TS; e += NT) {
+        // element e = (row i, col j) of the tile; locate its (lane, reg)
+        const int i = e / TS, j = e - (e / TS) * TS;
+        int l, v;
+        if constexpr (TS == 16) {          // f64 16x16x4: lane = j + 16 (i % 4), reg = i / 4
+            l = j + 16 * (i & 3);
+            v = i >> 2;
+        } else {                           // 32x32: lane = j + 32 ((i / 4) % 2), reg = i % 4 + 4 (i / 8)
+            l = j + 32 * ((i >> 2) & 1);
+            v = (i & 3) + 4 * (i >> 3);
+        }
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < WAVES; ++k) s += lds[(k * PL + v) * 64 + l];
+        out[e] = s;
+    }
+    __syncthreads();
+}
+
+// float64: 16x16 tiles, each lane feeds row (lane % 16) with the cell of k-slot lane / 16
+template <int NBW>
+__global__ __launch_bounds__(NT) void k_mm_f64(const double *__restrict__ F, const double *__restrict__ maps,
+                                               size_t nc, size_t chunk, const Items *__restrict__ tab,
+                                               int n_tiles, double *__restrict__ partial) {
+    constexpr int TS = 16, CPI = 8;   // 4 k-slots x 2 cells per iteration
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int r = lane & 15, h = lane >> 4;
+    Items it[NBW];
+    bool live[NBW], same[NBW];
+#pragma unroll
+    for (int s = 0; s < NBW; ++s) {
+        const int tile = blockIdx.y * NBW + s;
+        live[s] = tile < n_tiles;
+        it[s] = live[s] ? tab[(size_t)tile * TS + r] : Items{-2, -1, -2, -1};
+        same[s] = (it[s].a == it[s].c) && (it[s].b == it[s].d);
+    }
+    doublex4 acc[NBW];
+#pragma unroll
+    for (int s = 0; s < NBW; ++s) acc[s] = doublex4{0, 0, 0, 0};
+    const size_t c0 = (size_t)blockIdx.x * chunk;
+    const size_t c1 = std::min(c0 + chunk, nc);
+    for (size_t x0 = c0 + (size_t)w * CPI; x0 < c1; x0 += (size_t)WAVES * CPI) {
+        const size_t x = x0 + 2 * h;
+        double fv[2];
+        ld<double, 2>(F + x, fv);
+        const double f0 = fv[0], f1 = fv[1];
+#pragma unroll
+        for (int s = 0; s < NBW; ++s) {
+            if (!live[s]) continue;
+            double av[2], bv[2];
+            item_vals<double, 2>(maps, nc, x, it[s].a, it[s].b, av);
+            if (same[s]) { bv[0] = av[0]; bv[1] = av[1]; }
+            else item_vals<double, 2>(maps, nc, x, it[s].c, it[s].d, bv);
+            acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[0] * f0, bv[0], acc[s], 0, 0, 0);
+            acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[1] * f1, bv[1], acc[s], 0, 0, 0);
+        }
+    }
+    __shared__ double lds[WAVES * 4 * 64];
+    const int G = gridDim.x;
+#pragma unroll
+    for (int s = 0; s < NBW; ++s) {
+        const int tile = blockIdx.y * NBW + s;
+        if (tile >= n_tiles) break;
+        double a4[4] = {acc[s][0], acc[s][1], acc[s][2], acc[s][3]};
+        wave_combine_store<16>(a4, lds, partial + ((size_t)tile * G + blockIdx.x) * (TS * TS));
+    }
+}
+
+// float32: 32x32 tiles, v_mfma_f32_32x32x2_f32, lane feeds row lane % 32 in k-slot lane / 32
+template <int NBW>
+__global__ __launch_bounds__(NT) void k_mm_f32(const float *__restrict__ F, const float *__restrict__ maps,
+                                               size_t nc, size_t chunk, const Items *__restrict__ tab,
+                                               int n_tiles, double *__restrict__ partial) {
+    constexpr int TS = 32, CPI = 8, FLUSH = 16;   // 2 k-slots x 4 cells per iteration
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int r = lane & 31, h = lane >> 5;
+    Items it[NBW];
+    bool live[NBW], same[NBW];
+#pragma unroll
+    for (int s = 0; s < NBW; ++s) {
+        const int tile = blockIdx.y * NBW + s;
+        live[s] = tile < n_tiles;
+        it[s] = live[s] ? tab[(size_t)tile * TS + r] : Items{-2, -1, -2, -1};
+        same[s] = (it[s].a == it[s].c) && (it[s].b == it[s].d);
+    }
+    floatx16 acc[NBW];
+    double accd[NBW][16];
+#pragma unroll
+    for (int s = 0; s < NBW; ++s) {
+        acc[s] = floatx16{0};
+#pragma unroll
+        for (int v = 0; v < 16; ++v) accd[s][v] = 0.0;
+    }
+    const size_t c0 = (size_t)blockIdx.x * chunk;
+    const size_t c1 = std::min(c0 + chunk, nc);
+    int cnt = 0;
+    for (size_t x0 = c0 + (size_t)w * CPI; x0 < c1; x0 += (size_t)WAVES * CPI) {
+        const size_t x = x0 + 4 * h;
+        float f[4];
+        ld<float, 4>(F + x, f);
+#pragma unroll
+        for (int s = 0; s < NBW; ++s) {
+            if (!live[s]) continue;
+            float av[4], bv[4];
+            item_vals<float, 4>(maps, nc, x, it[s].a, it[s].b, av);
+            if (same[s]) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) bv[e] = av[e];
+            } else {
+                item_vals<float, 4>(maps, nc, x, it[s].c, it[s].d, bv);
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                acc[s] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[e] * f[e], bv[e], acc[s], 0, 0, 0);
+        }
+        if (++cnt == FLUSH) {
+            cnt = 0;
+#pragma unroll
+            for (int s = 0; s < NBW; ++s) {
+#pragma unroll
+                for (int v = 0; v < 16; ++v) accd[s][v] += (double)acc[s][v];
+                acc[s] = floatx16{0};
+            }
+        }
+    }
+    __shared__ double lds[WAVES * 16 * 64];
+    const int G = gridDim.x;
+#pragma unroll
+    for (int s = 0; s < NBW; ++s) {
+        const int tile = blockIdx.y * NBW + s;
+        if (tile >= n_tiles) break;
+        double a16[16];
+#pragma unroll
+        for (int v = 0; v < 16; ++v) a16[v] = accd[s][v] + (double)acc[s][v];
+        wave_combine_store<32>(a16, lds, partial + ((size_t)tile * G + blockIdx.x) * (TS * TS));
+    }
+}
+
+__device__ __forceinline__ void split3(const float (&v)[8], bf16x8 &hi, bf16x8 &mi, bf16x8 &lo) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const __bf16 h = (__bf16)v[e];
+        const float r1 = v[e] - (float)h;
+        const __bf16 m = (__bf16)r1;
+        const float r2 = r1 - (float)m;
+        hi[e] = h;
+        mi[e] = m;
+        lo[e] = (__bf16)r2;
+    }
+}
+
+// split bfloat16: 32x32 tiles, v_mfma_f32_32x32x16_bf16, lane feeds row lane % 32
+// with the 8 cells of k-slot lane / 32
+template <int NBW>
+__global__ __launch_bounds__(NT) void k_mm_bf16(const float *__restrict__ F, const float *__restrict__ maps,
+                                                size_t nc, size_t chunk, const Items *__restrict__ tab,
+                                                int n_tiles, double *__restrict__ partial) {
+    constexpr int TS = 32, CPI = 16, FLUSH = 8;   // 2 k-slots x 8 cells per iteration
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int r = lane & 31, h = lane >> 5;
+    Items it[NBW];
+    bool live[NBW], same[NBW];
+#pragma unroll
+    for (int s = 0; s < NBW; ++s) {
+        const int tile = blockIdx.y * NBW + s;
+        live[s] = tile < n_tiles;
+        it[s] = live[s] ? tab[(size_t)tile * TS + r] : Items{-2, -1, -2, -1};
+        same[s] = (it[s].a == it[s].c) && (it[s].b == it[s].d);
+    }
+    floatx16 acc[NBW];
+    double accd[NBW][16];
+#pragma unroll
+    for (int s = 0; s < NBW; ++s) {
+        acc[s] = floatx16{0};
+#pragma unroll
+        for (int v = 0; v < 16; ++v) accd[s][v] = 0.0;
+    }
+    const size_t c0 = (size_t)blockIdx.x * chunk;
+    const size_t c1 = std::min(c0 + chunk, nc);
+    int cnt = 0;
+    for (size_t x0 = c0 + (size_t)w * CPI; x0 < c1; x0 += (size_t)WAVES * CPI) {
+        const size_t x = x0 + 8 * h;
+        float f[8];
+        ld<float, 8>(F + x, f);
+#pragma unroll
+        for (int s = 0; s < NBW; ++s) {
+            if (!live[s]) continue;
+            float cv[8], av[8], bv[8];
+            item_vals<float, 8>(maps, nc, x, it[s].a, it[s].b, cv);
+            if (same[s]) {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) bv[e] = cv[e];
+            } else {
+                item_vals<float, 8>(maps, nc, x, it[s].c, it[s].d, bv);
+            }
+#pragma unroll
+            for (int e = 0; e < 8; ++e) av[e] = cv[e] * f[e];
+            bf16x8 ah, am, al, bh, bm, bl;
+            split3(av, ah, am, al);
+            split3(bv, bh, bm, bl);
+            acc[s] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc[s], 0, 0, 0);
+            acc[s] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bm, acc[s], 0, 0, 0);
+            acc[s] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc[s], 0, 0, 0);
+            acc[s] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bh, acc[s], 0, 0, 0);
+            acc[s] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bm, acc[s], 0, 0, 0);
+            acc[s] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc[s], 0, 0, 0);
+        }
+        if (++cnt == FLUSH) {
+            cnt = 0;
+#pragma unroll
+            for (int s = 0; s < NBW; ++s) {
+#pragma unroll
+                for (int v = 0; v < 16; ++v) accd[s][v] += (double)acc[s][v];
+                acc[s] = floatx16{0};
+            }
+        }
+    }
+    __shared__ double lds[WAVES * 16 * 64];
+    const int G = gridDim.x;
+#pragma unroll
+    for (int s = 0; s < NBW; ++s) {
+        const int tile = blockIdx.y * NBW + s;
+        if (tile >= n_tiles) break;
+        double a16[16];
+#pragma unroll
+        for (int v = 0; v < 16; ++v) a16[v] = accd[s][v] + (double)acc[s][v];
+        wave_combine_store<32>(a16, lds, partial + ((size_t)tile * G + blockIdx.x) * (TS * TS));
+    }
+}
+
+// Sum the per-workgroup partial tiles in a fixed order, in two levels:
+// slice s of every tile element sums workgroups [s*G/S, (s+1)*G/S), then the
+// S slice sums are added.  full[tile][e].
+constexpr int RED_S = 64;
+__global__ void k_tile_reduce1(const double *__restrict__ partial, int n_tiles, int G, int te,
+                               double *__restrict__ slices) {
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;   // (tile, s, e), e fastest
+    if (idx >= (size_t)n_tiles * RED_S * te) return;
+    const size_t e = idx % te;
+    const size_t s = (idx / te) % RED_S;
+    const size_t tile = idx / ((size_t)te * RED_S);
+    const int g0 = (int)((long)G * s / RED_S), g1 = (int)((long)G * (s + 1) / RED_S);
+    const double *p = partial + tile * (size_t)G * te + e;
+    double acc = 0.0;
+    for (int g = g0; g < g1; ++g) acc += p[(size_t)g * te];
+    slices[idx] = acc;
+}
+
+__global__ void k_tile_reduce2(const double *__restrict__ slices, int n_tiles, int te,
+                               double *__restrict__ full) {
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;   // (tile, e)
+    if (idx >= (size_t)n_tiles * te) return;
+    const size_t e = idx % te, tile = idx / te;
+    const double *p = slices + tile * (size_t)RED_S * te + e;
+    double acc = 0.0;
+    for (int s = 0; s < RED_S; ++s) acc += p[(size_t)s * te];
+    full[idx] = acc;
+}
+
+__global__ void k_gather(const double *__restrict__ full, const int *__restrict__ where, int64_t count,
+                         double *__restrict__ W) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < count) W[t] = full[where[t]];
+}
+
+// ---------------------------------------------------------------------------
+// host-side planning: items, needed tiles, tuple locations
+// ---------------------------------------------------------------------------
+struct Plan {
+    int TS = 0;
+    int n_tiles = 0;
+    int64_t count = 0;
+    Buf *items = nullptr;   // Items [n_tiles][TS]
+    Buf *where = nullptr;   // int [count]: index into full[n_tiles][TS*TS]
+};
+
+void enumerate_tuples(int ns, int k, std::vector<std::vector<int>> &out) {
+    std::vector<int> t(k, 0);
+    if (k == 0) return;
+    while (true) {
+        out.push_back(t);
+        int i = k - 1;
+        while (i >= 0 && t[i] == ns - 1) --i;
+        if (i < 0) break;
+        ++t[i];
+        for (int j = i + 1; j < k; ++j) t[j] = t[i];
+    }
+}
+
+int make_plan(conker_ctx *c, int ns, int n, int TS, Plan &pl) {
+    const uint64_t key = ((uint64_t)ns << 16) | ((uint64_t)n << 8) | (uint64_t)TS;
+    Buf &bi = c->tables[key * 2];
+    Buf &bw = c->tables[key * 2 + 1];
+    // left / right item lists
+    std::vector<std::pair<int, int>> left, right;
+    std::vector<std::vector<int>> pairs;
+    enumerate_tuples(ns, 2, pairs);
+    std::vector<int> pair_index(ns * ns, -1);
+    for (size_t p = 0; p < pairs.size(); ++p) pair_index[pairs[p][0] * ns + pairs[p][1]] = (int)p;
+    if (n == 3 || n == 4) {
+        for (int a = 0; a < ns; ++a) right.push_back({a, -1});
+    }
+    if (n == 3) {
+        for (int a = 0; a < ns; ++a) left.push_back({a, -1});
+    } else {
+        for (auto &p : pairs) left.push_back({p[0], p[1]});
+        if (n == 5)
+            for (auto &p : pairs) right.push_back({p[0], p[1]});
+    }
+    const int LT = ((int)left.size() + TS - 1) / TS, RT = ((int)right.size() + TS - 1) / TS;
+    std::vector<std::vector<int>> tuples;
+    enumerate_tuples(ns, n - 1, tuples);
+    pl.count = (int64_t)tuples.size();
+    std::vector<int> tile_id(LT * RT, -1);
+    std::vector<std::pair<int, int>> tiles;
+    std::vector<std::pair<int, int>> rc(tuples.size());
+    for (size_t t = 0; t < tuples.size(); ++t) {
+        const auto &u = tuples[t];
+        int li, ri;
+        if (n == 3) { li = u[0]; ri = u[1]; }
+        else if (n == 4) { li = pair_index[u[0] * ns + u[1]]; ri = u[2]; }
+        else { li = pair_index[u[0] * ns + u[1]]; ri = pair_index[u[2] * ns + u[3]]; }
+        rc[t] = {li, ri};
+        int &id = tile_id[(li / TS) * RT + ri / TS];
+        if (id < 0) {
+            id = (int)tiles.size();
+            tiles.push_back({li / TS, ri / TS});
+        }
+    }
+    pl.n_tiles = (int)tiles.size();
+    pl.TS = TS;
+    if (!bi.p) {
+        std::vector<Items> hi((size_t)pl.n_tiles * TS);
+        for (int k = 0; k < pl.n_tiles; ++k)
+            for (int r = 0; r < TS; ++r) {
+                const int li = tiles[k].first * TS + r, ri = tiles[k].second * TS + r;
+                Items &x = hi[(size_t)k * TS + r];
+                if (li < (int)left.size()) { x.a = left[li].first; x.b = left[li].second; }
+                else { x.a = -2; x.b = -1; }
+                if (ri < (int)right.size()) { x.c = right[ri].first; x.d = right[ri].second; }
+                else { x.c = -2; x.d = -1; }
+            }
+        std::vector<int> hw(tuples.size());
+        for (size_t t = 0; t < tuples.size(); ++t) {
+            const int li = rc[t].first, ri = rc[t].second;
+            const int k = tile_id[(li / TS) * RT + ri / TS];
+            hw[t] = k * TS * TS + (li % TS) * TS + (ri % TS);
+        }
+        CK_OK(ws_reserve(c, bi, hi.size() * sizeof(Items)));
+        CK_OK(ws_reserve(c, bw, hw.size() * sizeof(int)));
+        CK_HIP(c, hipMemcpy(bi.p, hi.data(), hi.size() * sizeof(Items), hipMemcpyHostToDevice));
+        CK_HIP(c, hipMemcpy(bw.p, hw.data(), hw.size() * sizeof(int), hipMemcpyHostToDevice));
+    }
+    pl.items = &bi;
+    pl.where = &bw;
+    return CONKER_OK;
+}
+
+template <typename T>
+int contract_dot(conker_ctx *c, const T *F, const T *maps, size_t nc, int ns, double *W) {
+    constexpr int V = std::is_same<T, float>::value ? 4 : 2;
+    int G = (int)std::min<size_t>(2048, std::max<size_t>(1, nc / 4096));
+    size_t chunk = (nc + G - 1) / G;
+    chunk = (chunk + NT * V - 1) / (NT * V) * (NT * V);
+    G = (int)((nc + chunk - 1) / chunk);
+    CK_OK(ws_reserve(c, c->partial, (size_t)G * ns * sizeof(double)));
+    double *part = (double *)c->partial.p;
+    {
+    ProfScope ps(c, PK_CONTRACT_DOT);
+    if (ns <= 16)
+        hipLaunchKernelGGL((k_dot<T, 16>), dim3(G), dim3(NT), 0, c->stream, F, maps, nc, ns, chunk, part);
+    else if (ns <= 32)
+        hipLaunchKernelGGL((k_dot<T, 32>), dim3(G), dim3(NT), 0, c->stream, F, maps, nc, ns, chunk, part);
+    else
+        hipLaunchKernelGGL((k_dot<T, 64>), dim3(G), dim3(NT), 0, c->stream, F, maps, nc, ns, chunk, part);
+    CK_LAUNCH(c);
+    }
+    ProfScope ps(c, PK_CONTRACT_REDUCE);
+    hipLaunchKernelGGL(k_dot_reduce, dim3(ns), dim3(256), 0, c->stream, part, G, ns, W);
+    CK_LAUNCH(c);
+    return CONKER_OK;
+}
+
+template <int NBW>
+int launch_mm(conker_ctx *c, conker_mmprec prec, dim3 grid, const void *F, const void *maps, size_t nc,
+              size_t chunk, const Items *tab, int n_tiles, double *part) {
+    if (prec == CONKER_MM_F64)
+        hipLaunchKernelGGL((k_mm_f64<NBW>), grid, dim3(NT), 0, c->stream, (const double *)F,
+                           (const double *)maps, nc, chunk, tab, n_tiles, part);
+    else if (prec == CONKER_MM_F32)
+        hipLaunchKernelGGL((k_mm_f32<NBW>), grid, dim3(NT), 0, c->stream, (const float *)F,
+                           (const float *)maps, nc, chunk, tab, n_tiles, part);
+    else
+        hipLaunchKernelGGL((k_mm_bf16<NBW>), grid, dim3(NT), 0, c->stream, (const float *)F,
+                           (const float *)maps, nc, chunk, tab, n_tiles, part);
+    CK_LAUNCH(c);
+    return CONKER_OK;
+}
+
+}  // namespace
+
+extern "C" int conker_contract_npt(conker_ctx *c, const conker_grid *g, conker_dtype dt, const void *F,
+                                   const void *maps, int ns, int n, conker_mmprec prec, double *W) {
+    CK_OK(check_grid(c, g, false));
+    if (!F || !maps || !W) return fail(c, CONKER_EINVAL, "NULL pointer");
+    if (n < 2 || n > 5) return fail(c, CONKER_EINVAL, "order n=%d outside 2..5", n);
+    if (ns < 1 || ns > 64) return fail(c, CONKER_EINVAL, "n_radii=%d outside 1..64", ns);
+    if (dt != CONKER_F32 && dt != CONKER_F64) return fail(c, CONKER_EINVAL, "bad dtype");
+    if (prec == CONKER_MM_F64 && dt != CONKER_F64)
+        return fail(c, CONKER_EINVAL, "float64 summation needs float64 maps");
+    if ((prec == CONKER_MM_F32 || prec == CONKER_MM_SPLIT_BF16) && dt != CONKER_F32)
+        return fail(c, CONKER_EINVAL, "float32 and split-bf16 summation need float32 maps");
+    if (prec != CONKER_MM_F64 && prec != CONKER_MM_F32 && prec != CONKER_MM_SPLIT_BF16)
+        return fail(c, CONKER_EINVAL, "bad precision");
+    const size_t nc = ncells(g);
+    if (nc % 16) return fail(c, CONKER_EUNSUPPORTED, "cell count must be a multiple of 16");
+    CK_HIP(c, hipSetDevice(c->device));
+    if (n == 2) {
+        if (dt == CONKER_F64) return contract_dot<double>(c, (const double *)F, (const double *)maps, nc, ns, W);
+        return contract_dot<float>(c, (const float *)F, (const float *)maps, nc, ns, W);
+    }
+    const int TS = prec == CONKER_MM_F64 ? 16 : 32;
+    Plan pl;
+    CK_OK(make_plan(c, ns, n, TS, pl));
+    const int NBW = pl.n_tiles == 1 ? 1 : (prec == CONKER_MM_F64 ? 4 : 2);
+    const int groups = (pl.n_tiles + NBW - 1) / NBW;
+    // cell chunks: aim for ~4096 workgroups in total, chunk a multiple of 4 waves x 16 cells
+    const size_t unit = (size_t)WAVES * 16;
+    size_t G = std::max<size_t>(1, std::min<size_t>(nc / 1024, 4096 / (size_t)groups));
+    size_t chunk = (nc + G - 1) / G;
+    chunk = (chunk + unit - 1) / unit * unit;
+    G = (nc + chunk - 1) / chunk;
+    const int te = TS * TS;
+    CK_OK(ws_reserve(c, c->partial, (size_t)pl.n_tiles * G * te * sizeof(double)));
+    CK_OK(ws_reserve(c, c->full, (size_t)pl.n_tiles * te * (RED_S + 1) * sizeof(double)));
+    double *part = (double *)c->partial.p;
+    const Items *tab = (const Items *)pl.items->p;
+    dim3 grid((unsigned)G, (unsigned)groups);
+    {
+    ProfScope ps(c, PK_CONTRACT_MM);
+    if (NBW == 1) CK_OK(launch_mm<1>(c, prec, grid, F, maps, nc, chunk, tab, pl.n_tiles, part));
+    else if (NBW == 2) CK_OK(launch_mm<2>(c, prec, grid, F, maps, nc, chunk, tab, pl.n_tiles, part));
+    else CK_OK(launch_mm<4>(c, prec, grid, F, maps, nc, chunk, tab, pl.n_tiles, part));
+    }
+    ProfScope ps(c, PK_CONTRACT_REDUCE);
+    const size_t tot = (size_t)pl.n_tiles * te;
+    double *full = (double *)c->full.p;
+    double *slices = full + tot;
+    hipLaunchKernelGGL(k_tile_reduce1, dim3((unsigned)((tot * RED_S + 255) / 256)), dim3(256), 0, c->stream,
+                       part, pl.n_tiles, (int)G, te, slices);
+    CK_LAUNCH(c);
+    hipLaunchKernelGGL(k_tile_reduce2, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, c->stream, slices,
+                       pl.n_tiles, te, full);
+    CK_LAUNCH(c);
+    hipLaunchKernelGGL(k_gather, dim3((unsigned)((pl.count + 255) / 256)), dim3(256), 0, c->stream,
+                       (const double *)full, (const int *)pl.where->p, pl.count, W);
+    CK_LAUNCH(c);
+    return CONKER_OK;
+}

@@ -1,0 +1,79 @@
+// Shell-kernel bank (Sec. 2.3) and shell convolutions (Sec. 2.4).
+#include <cmath>
+#include <cstdlib>
+
+#include "common.h"
+
+using namespace conker;
+
+namespace {
+
+// Radii convolved per inverse batch: one read of the forward spectrum serves
+// this many kernel multiplies and inverse x-axis transforms.
+int batch_radii(conker_ctx *c, size_t per_radius_bytes, int n_radii, size_t fixed_bytes) {
+    int b = 4;
+    if (const char *e = std::getenv("CONKER_RADIUS_BATCH")) {
+        int v = std::atoi(e);
+        if (v >= 1 && v <= 64) b = v;
+    }
+    if (b > n_radii) b = n_radii;
+    if (c->ws_cap) {
+        while (b > 1 && c->ws_bytes - c->tspec.bytes - c->spec.bytes + fixed_bytes +
+                                (size_t)b * per_radius_bytes > c->ws_cap)
+            --b;
+    }
+    return b < 1 ? 1 : b;
+}
+
+}  // namespace
+
+
+extern "C" int conker_make_shell_kernels(conker_ctx *c, const conker_grid *g, const double *h_radii,
+                                         int n_radii, conker_dtype dt, void *d_kspec,
+                                         int64_t *h_sizes) {
+    CK_OK(check_grid(c, g, true));
+    if (n_radii <= 0 || !h_radii || !d_kspec) return fail(c, CONKER_EINVAL, "bad radii or NULL pointer");
+    if (dt != CONKER_F32 && dt != CONKER_F64) return fail(c, CONKER_EINVAL, "bad dtype");
+    std::vector<double> r(n_radii);
+    for (int m = 0; m < n_radii; ++m) {
+        r[m] = h_radii[m] / g->cell;
+        CK_OK(check_shell(c, g, r[m]));
+    }
+    CK_HIP(c, hipSetDevice(c->device));
+    const size_t nc = ncells(g);
+    CK_OK(ws_reserve(c, c->spec, nc * sizeof(double2)));
+    for (int m = 0; m < n_radii; m += 2) {
+        const double ra = r[m];
+        const double rb = (m + 1 < n_radii) ? r[m + 1] : ra;
+        CK_OK(fft_shell_pair(c, g, (ra - 0.5) * (ra - 0.5), (ra + 0.5) * (ra + 0.5),
+                             (rb - 0.5) * (rb - 0.5), (rb + 0.5) * (rb + 0.5), c->spec.p, d_kspec,
+                             dt == CONKER_F64, m, (m + 1 < n_radii) ? m + 1 : -1));
+    }
+    if (h_sizes)
+        for (int m = 0; m < n_radii; ++m) CK_OK(conker_shell_size(r[m], &h_sizes[m]));
+    return CONKER_OK;
+}
+
+extern "C" int conker_convolve_shells(conker_ctx *c, const conker_grid *g, conker_dtype dt,
+                                      const void *fa, const void *fb, const void *kspec,
+                                      int n_radii, void *ma, void *mb) {
+    CK_OK(check_grid(c, g, true));
+    if (dt != CONKER_F32 && dt != CONKER_F64) return fail(c, CONKER_EINVAL, "bad dtype");
+    if (!fa || !kspec || !ma) return fail(c, CONKER_EINVAL, "NULL pointer");
+    if ((fb == nullptr) != (mb == nullptr))
+        return fail(c, CONKER_EINVAL, "field_b and maps_b must both be given or both be NULL");
+    if (n_radii <= 0) return fail(c, CONKER_EINVAL, "n_radii must be positive");
+    CK_HIP(c, hipSetDevice(c->device));
+    const bool f64 = dt == CONKER_F64;
+    const size_t nc = ncells(g);
+    const size_t cbytes = nc * (f64 ? sizeof(double2) : sizeof(float2));
+    const int B = batch_radii(c, cbytes, n_radii, cbytes);
+    CK_OK(ws_reserve(c, c->spec, cbytes));
+    CK_OK(ws_reserve(c, c->tspec, (size_t)B * cbytes));
+    CK_OK(fft_forward_pair(c, g, f64, fa, fb, c->spec.p));
+    for (int m0 = 0; m0 < n_radii; m0 += B) {
+        const int nb = (m0 + B <= n_radii) ? B : n_radii - m0;
+        CK_OK(fft_inverse_batch(c, g, f64, c->spec.p, kspec, m0, nb, c->tspec.p, ma, mb));
+    }
+    return CONKER_OK;
+}

@@ -1,0 +1,300 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Error measure for W (and maps): max |got - ref| / max |ref| over the outputs of
+one call.  Bars: integer work (histograms of unit weights, shell sizes)
+bit-exact; float64 path <= 1e-12; float32 / split-bf16 paths <= 1e-5.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import conker as oc  # noqa: E402
+import synth  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ck():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2108_00015_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(ck):
+    c = ck.Context(0)
+    yield c
+    c.close()
+
+
+DEV = "cuda:0"
+TDT = {"f32": torch.float32, "f64": torch.float64}
+
+
+def relerr(got, ref):
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    return float(np.abs(got - ref).max() / max(np.abs(ref).max(), 1e-300))
+
+
+def _gpu(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+    return t if dtype is None else t.to(dtype)
+
+
+# ---------------------------------------------------------------------------
+# mapping
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+def test_scatter_unit_weights_bit_exact(ck, ctx, dt):
+    w = synth.workload("cube512_ns20k_grid128")
+    data, rand = w.make()
+    grid = ck.Grid(w.dims, w.origin, w.cell)
+    for cat in (data, rand):
+        _say("scatter unit", dt, len(cat))
+        out = torch.zeros(w.dims, dtype=TDT[dt], device=DEV)
+        wsum = torch.zeros(1, dtype=torch.float64, device=DEV)
+        nout = torch.zeros(1, dtype=torch.int64, device=DEV)
+        ctx.grid_assign(grid, _gpu(cat.pos), None, out, wsum, nout)
+        ref, rs, ro = oc.histogram(cat.pos, None, w.origin, w.cell, w.dims)
+        assert np.array_equal(out.cpu().numpy().astype(np.float64), ref)
+        assert wsum.item() == rs and nout.item() == ro
+
+
+@pytest.mark.parametrize("dt,tol", [("f32", 2e-6), ("f64", 1e-13)])
+def test_scatter_weighted_survey_cap(ck, ctx, dt, tol):
+    w = synth.workload("cap512_ns800k_r30")
+    data, rand = w.make(scale=0.02)
+    grid = ck.Grid(w.dims, w.origin, w.cell)
+    for cat in (data, rand):
+        _say("scatter weighted", dt, len(cat))
+        out = torch.zeros(w.dims, dtype=TDT[dt], device=DEV)
+        wsum = torch.zeros(1, dtype=torch.float64, device=DEV)
+        nout = torch.zeros(1, dtype=torch.int64, device=DEV)
+        ctx.grid_assign(grid, _gpu(cat.pos), _gpu(cat.w), out, wsum, nout)
+        ref, rs, ro = oc.histogram(cat.pos, cat.w, w.origin, w.cell, w.dims)
+        got = out.cpu().numpy().astype(np.float64)
+        assert np.abs(got - ref).max() <= tol * ref.max()
+        assert math.isclose(wsum.item(), rs, rel_tol=1e-12)
+        assert nout.item() == ro == 0
+
+
+def test_scatter_rejects_outside_and_nonfinite(ck, ctx):
+    dims, origin, cell = (32, 32, 32), (0.0, 0.0, 0.0), 1.0
+    grid = ck.Grid(dims, origin, cell)
+    pos = np.array([[1.5, 2.5, 3.5], [32.0, 1.0, 1.0], [-0.001, 1, 1], [5, 5, np.nan],
+                    [31.999, 31.999, 31.999], [7, 7, 7]], dtype=np.float32)
+    wts = np.array([1.0, 1.0, 1.0, 1.0, 2.0, np.inf], dtype=np.float32)
+    out = torch.zeros(dims, dtype=torch.float64, device=DEV)
+    wsum = torch.zeros(1, dtype=torch.float64, device=DEV)
+    nout = torch.zeros(1, dtype=torch.int64, device=DEV)
+    ctx.grid_assign(grid, _gpu(pos), _gpu(wts), out, wsum, nout)
+    g = out.cpu().numpy()
+    assert g[1, 2, 3] == 1.0 and g[31, 31, 31] == 2.0 and g.sum() == 3.0
+    assert nout.item() == 4 and wsum.item() == 3.0
+
+
+def test_scatter_empty_catalog_is_noop(ck, ctx):
+    grid = ck.Grid((32, 32, 32), (0, 0, 0), 1.0)
+    out = torch.zeros((32, 32, 32), dtype=torch.float32, device=DEV)
+    ctx.grid_assign(grid, torch.zeros((0, 3), dtype=torch.float32, device=DEV), None, out)
+    assert out.abs().sum().item() == 0.0
+
+
+@pytest.mark.parametrize("dt,tol", [("f32", 1e-6), ("f64", 1e-15)])
+def test_form_delta(ck, ctx, dt, tol):
+    rng = np.random.default_rng(3)
+    D = rng.integers(0, 5, size=(32, 32, 64)).astype(np.float64)
+    R = rng.integers(0, 40, size=(32, 32, 64)).astype(np.float64)
+    grid = ck.Grid((32, 32, 64), (0, 0, 0), 1.0)
+    Dt, Rt = _gpu(D, TDT[dt]), _gpu(R, TDT[dt])
+    ws = torch.tensor([D.sum(), R.sum()], dtype=torch.float64, device=DEV)
+    alpha = torch.zeros(1, dtype=torch.float64, device=DEV)
+    ctx.form_delta(grid, Dt, Rt, ws[0:1], ws[1:2], alpha)
+    N, a = oc.density_deviation(D, R, D.sum(), R.sum())
+    assert alpha.item() == a
+    assert relerr(Dt.cpu().numpy(), N) <= tol
+
+
+# ---------------------------------------------------------------------------
+# kernels
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dims", [(32, 32, 32), (64, 32, 128), (128, 128, 128)])
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_shell_kernel_spectra(ck, ctx, dims, dt):
+    cell = 2.0
+    radii = [1.0, 2.0, 3.0, 5.0, 7.5, 9.0, 22.0]   # r = 0.5 .. 11 cells, odd count
+    radii = [r for r in radii if 2 * oc.shell_reach(r / cell) + 1 <= min(dims)]
+    _say("shells", dims, dt, radii)
+    grid = ck.Grid(dims, (0, 0, 0), cell)
+    ks, sizes = ctx.make_shell_kernels(grid, radii, TDT[dt])
+    ks = ks.cpu().numpy().reshape(len(radii), dims[0] // 2 + 1, dims[1] // 2 + 1, dims[2] // 2 + 1)
+    nc = np.prod(dims)
+    for m, s in enumerate(radii):
+        r = s / cell
+        assert sizes[m] == len(oc.shell_offsets(r))
+        ref = oc.shell_spectrum(r, dims).real[: dims[0] // 2 + 1, : dims[1] // 2 + 1, : dims[2] // 2 + 1] / nc
+        tol = 1e-13 if dt == "f64" else 1e-7
+        assert np.abs(ks[m] - ref).max() <= tol * sizes[m] / nc, (m, r)
+        assert abs(ks[m][0, 0, 0] * nc - sizes[m]) <= (1e-9 if dt == "f64" else 1e-3)
+
+
+def test_shell_radius_errors(ck, ctx):
+    grid = ck.Grid((32, 32, 32), (0, 0, 0), 1.0)
+    with pytest.raises(ck.ConkerError) as e:
+        ctx.make_shell_kernels(grid, [16.0], torch.float64)
+    assert "ERANGE" in str(e.value)
+    with pytest.raises(ck.ConkerError) as e:
+        ctx.make_shell_kernels(grid, [0.4], torch.float64)
+    assert "ERANGE" in str(e.value)
+    with pytest.raises(ck.ConkerError) as e:
+        ctx.make_shell_kernels(ck.Grid((96, 96, 96), (0, 0, 0), 1.0), [3.0], torch.float64)
+    assert "UNSUPPORTED" in str(e.value)
+
+
+# ---------------------------------------------------------------------------
+# convolution
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dims", [(32, 32, 32), (32, 64, 128), (128, 64, 32), (64, 64, 64)])
+@pytest.mark.parametrize("dt,tol", [("f64", 1e-12), ("f32", 3e-6)])
+def test_convolve_shells_vs_oracle(ck, ctx, dims, dt, tol):
+    rng = np.random.default_rng(11)
+    A = rng.normal(size=dims)
+    B = rng.poisson(3.0, size=dims).astype(np.float64)
+    cell = 1.0
+    radii = [1.0, 2.0, 3.0, 4.0, 6.0, 9.0, 13.0]
+    radii = [r for r in radii if 2 * oc.shell_reach(r) + 1 <= min(dims)]
+    _say("convolve", dims, dt, radii)
+    grid = ck.Grid(dims, (0, 0, 0), cell)
+    ks, _ = ctx.make_shell_kernels(grid, radii, TDT[dt])
+    ma, mb = ctx.convolve_shells(grid, _gpu(A, TDT[dt]), _gpu(B, TDT[dt]), ks)
+    ma, mb = ma.cpu().numpy(), mb.cpu().numpy()
+    Af = A.astype(np.float32).astype(np.float64) if dt == "f32" else A
+    Bf = B
+    for m, r in enumerate(radii):
+        ra, rb = oc.convolve_shell(Af, r), oc.convolve_shell(Bf, r)
+        ea, eb = relerr(ma[m], ra), relerr(mb[m], rb)
+        assert ea <= tol and eb <= tol, (m, r, ea, eb)
+
+
+def test_convolve_single_field_and_one_radius(ck, ctx):
+    dims = (64, 64, 64)
+    rng = np.random.default_rng(12)
+    A = rng.normal(size=dims)
+    grid = ck.Grid(dims, (0, 0, 0), 1.0)
+    ks, _ = ctx.make_shell_kernels(grid, [5.0], torch.float64)
+    ma, mb = ctx.convolve_shells(grid, _gpu(A), None, ks)
+    assert mb is None
+    assert relerr(ma.cpu().numpy()[0], oc.convolve_shell(A, 5.0)) <= 1e-12
+
+
+def test_convolve_integer_field_equals_direct_shell_sums(ck, ctx):
+    dims = (64, 64, 64)
+    rng = np.random.default_rng(13)
+    A = rng.integers(-2, 3, size=dims).astype(np.float64)
+    grid = ck.Grid(dims, (0, 0, 0), 1.0)
+    ks, _ = ctx.make_shell_kernels(grid, [7.0, 20.0], torch.float64)
+    ma, _ = ctx.convolve_shells(grid, _gpu(A), None, ks)
+    ma = ma.cpu().numpy()
+    cells = rng.integers(0, 64, size=(200, 3))
+    for m, r in enumerate([7.0, 20.0]):
+        direct = oc.direct_shell_sum(A, r, cells)
+        got = ma[m][cells[:, 0], cells[:, 1], cells[:, 2]]
+        assert np.abs(got - direct).max() < 1e-9
+
+
+# ---------------------------------------------------------------------------
+# summation
+# ---------------------------------------------------------------------------
+
+CONTRACT_CASES = [
+    # (prec, n, n_radii, dims)
+    ("f64", 2, 7, (32, 32, 32)),
+    ("f64", 3, 7, (32, 32, 32)),
+    ("f64", 3, 33, (32, 32, 64)),
+    ("f64", 4, 9, (32, 32, 32)),
+    ("f64", 5, 6, (32, 32, 32)),
+    ("f32", 2, 30, (32, 32, 32)),
+    ("f32", 3, 30, (32, 64, 64)),
+    ("f32", 3, 40, (32, 32, 32)),
+    ("f32", 4, 9, (32, 32, 32)),
+    ("f32", 5, 6, (32, 32, 32)),
+    ("split_bf16", 2, 30, (32, 32, 32)),
+    ("split_bf16", 3, 30, (32, 64, 64)),
+    ("split_bf16", 3, 40, (32, 32, 32)),
+    ("split_bf16", 4, 9, (32, 32, 32)),
+    ("split_bf16", 5, 6, (32, 32, 32)),
+]
+
+
+@pytest.mark.parametrize("prec,n,ns,dims", CONTRACT_CASES)
+def test_contract_vs_oracle(ck, ctx, prec, n, ns, dims):
+    _say("contract", prec, n, ns, dims)
+    rng = np.random.default_rng(100 + n * 7 + ns)
+    F = rng.normal(size=dims)
+    maps = rng.normal(size=(ns,) + dims) + 0.3
+    dt = torch.float64 if prec == "f64" else torch.float32
+    if dt == torch.float32:
+        F = F.astype(np.float32).astype(np.float64)
+        maps = maps.astype(np.float32).astype(np.float64)
+    grid = ck.Grid(dims, (0, 0, 0), 1.0)
+    W = ctx.contract_npt(grid, _gpu(F, dt), _gpu(maps, dt), n, prec).cpu().numpy()
+    ref = oc.contract(F, maps, n)
+    err = relerr(W, ref)
+    bad = np.argsort(-np.abs(W - ref))[:5]
+    _say("  err %.3e worst tuples %s" % (err, [oc.radius_tuples(ns, n)[i] for i in bad]))
+    assert err <= (1e-12 if prec == "f64" else 1e-5)
+
+
+def test_contract_argument_errors(ck, ctx):
+    grid = ck.Grid((32, 32, 32), (0, 0, 0), 1.0)
+    F = torch.zeros((32, 32, 32), dtype=torch.float32, device=DEV)
+    M = torch.zeros((3, 32, 32, 32), dtype=torch.float32, device=DEV)
+    with pytest.raises(ck.ConkerError):
+        ctx.contract_npt(grid, F, M, 3, "f64")          # float64 summation on float32 maps
+    with pytest.raises(ck.ConkerError):
+        ctx.contract_npt(grid, F, M, 6, "f32")          # order outside 2..5
+
+
+# ---------------------------------------------------------------------------
+# end to end
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def cube128_ref():
+    w = synth.workload("cube512_ns20k_grid128")
+    data, rand = w.make()
+    refs = {n: oc.npcf(data.pos, rand.pos, w.dims, w.origin, w.cell, w.radii, n) for n in (2, 3)}
+    return w, data, rand, refs
+
+
+@pytest.mark.parametrize("n", [2, 3])
+@pytest.mark.parametrize("path,prec,tol", [("f64", "f64", 1e-12), ("f32", "f32", 1e-5),
+                                           ("f32", "split_bf16", 1e-5)])
+def test_end_to_end_cube128(ck, ctx, cube128_ref, n, path, prec, tol):
+    w, data, rand, refs = cube128_ref
+    ref = refs[n]
+    _say("end-to-end cube128", n, path, prec)
+    grid = ck.Grid(w.dims, w.origin, w.cell)
+    ks, _ = ctx.make_shell_kernels(grid, w.radii, TDT[path])
+    out = ck.npcf(ctx, grid, _gpu(data.pos), _gpu(rand.pos), ks, n, precision=prec, dtype=TDT[path])
+    ed = relerr(out["W_delta"].cpu().numpy(), ref["W_delta"])
+    er = relerr(out["W_rand_raw"].cpu().numpy(), ref["W_rand_raw"])
+    ex = relerr(out["xi"].cpu().numpy(), ref["xi"])
+    _say("  W_delta %.3e  W_R %.3e  xi %.3e" % (ed, er, ex))
+    assert abs(out["alpha"].item() - ref["alpha"]) <= 1e-15 * ref["alpha"]
+    assert ed <= tol and er <= tol and ex <= 10 * tol

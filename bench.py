@@ -171,8 +171,7 @@ def main():
                         args.steps, args.warmup, True)
         log("  %.2f ms/step" % fp64["ms"])
 
-    batch = int(os.environ.get("CONKER_RADIUS_BATCH", "4"))
-    batch = min(batch, ns)
+    batch = min(int(os.environ.get("CONKER_RADIUS_BATCH", str(ns))), ns)
     stages = {}
     for kind, (launches, tot) in mixed["prof"].items():
         per_step = tot / args.steps

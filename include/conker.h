@@ -123,8 +123,8 @@ int64_t conker_kspec_elems(const conker_grid *grid);
 /* conker_make_shell_kernels: spectra of the shell indicators, K_hat_m / N_c,
  * for n_radii radii h_radii[] (length units).  The spectrum of a
  * point-symmetric shell is real and even in each axis, so only the octant
- * 0 <= k <= n/2 per axis is stored:
- *   d_kspec  dtype [n_radii][nx/2+1][ny/2+1][nz/2+1].
+ * 0 <= k <= n/2 per axis is stored, x fastest:
+ *   d_kspec  dtype [n_radii][ny/2+1][nz/2+1][nx/2+1].
  * The transform is done in float64 and rounded once to dtype.
  * h_shell_sizes (may be NULL) receives |S_m| per radius. */
 int conker_make_shell_kernels(conker_ctx *ctx, const conker_grid *grid,

@@ -9,9 +9,17 @@ using namespace conker;
 namespace {
 
 // Radii convolved per inverse batch: one read of the forward spectrum serves
-// this many kernel multiplies and inverse x-axis transforms.
+// this many kernel multiplies and inverse x-axis transforms.  Default: every
+// radius, as long as the batch spectra take at most half of the free device
+// memory (plus what this context already holds for them).
 int batch_radii(conker_ctx *c, size_t per_radius_bytes, int n_radii, size_t fixed_bytes) {
-    int b = 4;
+    int b = n_radii;
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) == hipSuccess) {
+        const size_t budget = fr / 2 + c->tspec.bytes;
+        const size_t fit = per_radius_bytes ? budget / per_radius_bytes : (size_t)n_radii;
+        if ((size_t)b > fit) b = (int)(fit < 1 ? 1 : fit);
+    }
     if (const char *e = std::getenv("CONKER_RADIUS_BATCH")) {
         int v = std::atoi(e);
         if (v >= 1 && v <= 64) b = v;

@@ -15,6 +15,7 @@
 // engine packs two real fields into one complex field, multiplies by a kernel
 // spectrum, unpacks real maps, generates shell indicators on the fly, or
 // extracts the stored octant of a kernel spectrum.
+#include <cstdlib>
 #include <type_traits>
 
 #include "common.h"
@@ -93,32 +94,44 @@ constexpr int stage_ns() {   // product of radices before stage S
     return p;
 }
 
-// Tile shapes.  MAPJ: lanes run along a line (z-axis tiles of whole lines);
-// MAPC: lanes run across the TC columns of a tile (y and x axes).
-template <typename T, int L>
+// Tile modes.
+//   TM_J: lanes run along a line; a tile is TC whole contiguous lines (z axis).
+//   TM_C: lanes run across the TC columns of a tile of strided lines (y, x axes);
+//         runs of TC consecutive complex values (128 bytes).
+//   TM_W: as TM_C with twice the columns (256-byte runs), for the x axis whose
+//         line points are a whole y-z plane apart.
+//   TM_R: as TM_C with up to 1024 threads; used by the x pass that keeps its
+//         spectrum tile resident in LDS across a batch of radii.
+enum TileMode { TM_J = 0, TM_C = 1, TM_W = 2, TM_R = 3 };
+
+template <typename T, int L, int MODE>
 struct Shape {
     static constexpr bool f64 = std::is_same<T, double>::value;
-    // columns per tile for strided (y, x) passes: runs of TC complex values
     static constexpr int TC_C = f64 ? (L >= 1024 ? 4 : 8) : (L >= 1024 ? 8 : 16);
-    static constexpr int PAD_C = f64 ? 0 : (L >= 1024 ? 0 : 2);
-    // lines per tile for contiguous (z) passes
-    static constexpr int TC_J = (f64 ? 2048 : 4096) / L;
-    static constexpr int PADSH_J = 3;   // one pad element every 8
+    static constexpr int TC = MODE == TM_J ? (f64 ? 2048 : 4096) / L : (MODE == TM_W ? 2 * TC_C : TC_C);
+    static constexpr int PAD = MODE == TM_J ? 0 : (f64 ? 0 : 2);
+    static constexpr int NB0 = (L / 8) * TC;   // first-stage butterflies per tile
+    static constexpr int NT =
+        MODE == TM_J ? 256
+                     : (((MODE == TM_W || MODE == TM_R) && NB0 >= 1024) ? 1024 : (NB0 >= 512 ? 512 : 256));
+    static constexpr int LDS = MODE == TM_J ? TC * (L + (L >> 3)) : L * (TC + PAD);
+    // registers per thread must stay near 128 for four waves per SIMD
+    static constexpr int MINW = NT >= 512 ? 4 : 2;
 };
 
-template <bool MAPJ, int L, int TC, int PAD>
+template <int MODE, int L, int TC, int PAD>
 __device__ __forceinline__ int lds_addr(int i, int c) {
-    if constexpr (MAPJ) return c * (L + (L >> 3)) + i + (i >> 3);
+    if constexpr (MODE == TM_J) return c * (L + (L >> 3)) + i + (i >> 3);
     else return i * (TC + PAD) + c;
 }
 
 // Butterfly q of this thread -> (j = butterfly index within a line, c = column).
-// MAPC: the column is fixed per thread (NT is a multiple of TC), j steps by NT/TC.
-// MAPJ: lanes run along j; the line index steps by NT/LR (or j by NT when LR > NT).
-template <int NT, bool MAPJ, int LR, int TC>
+// TM_C / TM_W: the column is fixed per thread (NT is a multiple of TC), j steps by NT/TC.
+// TM_J: lanes run along j; the line index steps by NT/LR (or j by NT when LR > NT).
+template <int NT, int MODE, int LR, int TC>
 __device__ __forceinline__ void split_q(int q, int &j, int &c) {
     const int t = threadIdx.x;
-    if constexpr (MAPJ) {
+    if constexpr (MODE == TM_J) {
         if constexpr (NT % LR == 0) { j = t % LR; c = t / LR + q * (NT / LR); }
         else { const int b = t + q * NT; j = b % LR; c = b / LR; }
     } else {
@@ -128,12 +141,14 @@ __device__ __forceinline__ void split_q(int q, int &j, int &c) {
     }
 }
 
-template <typename T, int L, int TC, int PAD, bool MAPJ, int DIR, int NT, int S, class Op>
+template <typename T, int L, int MODE, int DIR, int S, bool STAGED, class Op>
 __device__ __forceinline__ void fft_stage(cplx<T> *lds, const cplx<T> *tw, Op &op) {
     using C = cplx<T>;
+    using SH = Shape<T, L, MODE>;
+    constexpr int NT = SH::NT, TC = SH::TC, PAD = SH::PAD;
     constexpr int R = Plan<L>::r[S];
     constexpr int NSV = stage_ns<L, S>();
-    constexpr bool FIRST = (S == 0);
+    constexpr bool FIRST = (S == 0) && !STAGED;   // first stage reads global memory
     constexpr bool LAST = (S == Plan<L>::n - 1);
     constexpr int LR = L / R;
     constexpr int NB = LR * TC;
@@ -145,12 +160,12 @@ __device__ __forceinline__ void fft_stage(cplx<T> *lds, const cplx<T> *tw, Op &o
         const int b = threadIdx.x + q * NT;
         if (NB % NT == 0 || b < NB) {
             int j, c;
-            split_q<NT, MAPJ, LR, TC>(q, j, c);
+            split_q<NT, MODE, LR, TC>(q, j, c);
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int i = j + r * LR;
                 if constexpr (FIRST) v[q][r] = op.load(i, c);
-                else v[q][r] = lds[lds_addr<MAPJ, L, TC, PAD>(i, c)];
+                else v[q][r] = lds[lds_addr<MODE, L, TC, PAD>(i, c)];
             }
             if constexpr (NSV > 1) {
                 const int k = j & (NSV - 1);
@@ -170,65 +185,56 @@ __device__ __forceinline__ void fft_stage(cplx<T> *lds, const cplx<T> *tw, Op &o
         const int b = threadIdx.x + q * NT;
         if (NB % NT == 0 || b < NB) {
             int j, c;
-            split_q<NT, MAPJ, LR, TC>(q, j, c);
+            split_q<NT, MODE, LR, TC>(q, j, c);
             const int k = j & (NSV - 1);
             const int base = (j - k) * R + k;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int o = base + r * NSV;
                 if constexpr (LAST) op.store(o, c, v[q][r]);
-                else lds[lds_addr<MAPJ, L, TC, PAD>(o, c)] = v[q][r];
+                else lds[lds_addr<MODE, L, TC, PAD>(o, c)] = v[q][r];
             }
         }
     }
     if constexpr (!LAST) __syncthreads();
 }
 
-template <typename T, int L, int TC, int PAD, bool MAPJ, int DIR, int NT, class Op>
+// STAGED: the tile is first copied into LDS with a plain row loop (one load in
+// flight per row instead of a whole radix-8 butterfly's worth of addresses),
+// and the first stage reads LDS.  Used where the load does extra work.
+template <typename T, int L, int MODE, int DIR, bool STAGED, class Op>
 __device__ __forceinline__ void fft_line_tile(cplx<T> *lds, const cplx<T> *tw, Op &op) {
-    fft_stage<T, L, TC, PAD, MAPJ, DIR, NT, 0>(lds, tw, op);
-    if constexpr (Plan<L>::n > 1) fft_stage<T, L, TC, PAD, MAPJ, DIR, NT, 1>(lds, tw, op);
-    if constexpr (Plan<L>::n > 2) fft_stage<T, L, TC, PAD, MAPJ, DIR, NT, 2>(lds, tw, op);
-    if constexpr (Plan<L>::n > 3) fft_stage<T, L, TC, PAD, MAPJ, DIR, NT, 3>(lds, tw, op);
-}
-
-// Threads per workgroup: 512 when a tile holds at least 512 first-stage
-// butterflies (keeps each thread to one or two radix-8 butterflies per stage,
-// so that the strided passes fit in ~128 registers), else 256.
-template <typename T, int L, bool MAPJ>
-constexpr int threads_of() {
-    using S = Shape<T, L>;
-    constexpr int tc = MAPJ ? S::TC_J : S::TC_C;
-    return (!MAPJ && (L / 8) * tc >= 512) ? 512 : 256;
-}
-
-template <typename T, int L, bool MAPJ>
-constexpr int lds_elems() {
-    using S = Shape<T, L>;
-    if constexpr (MAPJ) return S::TC_J * (L + (L >> 3));
-    else return L * (S::TC_C + S::PAD_C);
+    constexpr bool ST = STAGED && MODE != TM_J;   // staged loads are for column tiles
+    if constexpr (ST) {
+        using SH = Shape<T, L, MODE>;
+        constexpr int NT = SH::NT, TC = SH::TC, PAD = SH::PAD;
+        const int c = threadIdx.x % TC;
+#pragma unroll 8
+        for (int i = threadIdx.x / TC; i < L; i += NT / TC) lds[lds_addr<MODE, L, TC, PAD>(i, c)] = op.load(i, c);
+        __syncthreads();
+    }
+    fft_stage<T, L, MODE, DIR, 0, ST>(lds, tw, op);
+    if constexpr (Plan<L>::n > 1) fft_stage<T, L, MODE, DIR, 1, ST>(lds, tw, op);
+    if constexpr (Plan<L>::n > 2) fft_stage<T, L, MODE, DIR, 2, ST>(lds, tw, op);
+    if constexpr (Plan<L>::n > 3) fft_stage<T, L, MODE, DIR, 3, ST>(lds, tw, op);
 }
 
 // One launch = one pass over one axis.  Op::iters() line transforms are run
 // per tile (more than one when a tile is reused across several radii).
-template <typename T, int L, bool MAPJ, int DIR, class Op>
-__global__ __launch_bounds__((threads_of<T, L, MAPJ>()), (threads_of<T, L, MAPJ>() == 512 ? 4 : 2)) void k_fft(
-    Op op) {
+template <typename T, int L, int MODE, int DIR, class Op>
+__global__ __launch_bounds__((Shape<T, L, MODE>::NT), (Shape<T, L, MODE>::MINW)) void k_fft(Op op) {
     using C = cplx<T>;
-    using S = Shape<T, L>;
-    constexpr int NT = threads_of<T, L, MAPJ>();
-    constexpr int TC = MAPJ ? S::TC_J : S::TC_C;
-    constexpr int PAD = MAPJ ? 0 : S::PAD_C;
-    __shared__ C lds[lds_elems<T, L, MAPJ>()];
+    using SH = Shape<T, L, MODE>;
+    __shared__ C lds[SH::LDS];
     __shared__ C tw[L];
     const C *twg = reinterpret_cast<const C *>(op.tw);
-    for (int t = threadIdx.x; t < L; t += NT) tw[t] = twg[t];
-    op.begin(TC);
+    for (int t = threadIdx.x; t < L; t += SH::NT) tw[t] = twg[t];
+    op.template begin<SH::TC>();
     __syncthreads();
     const int it_n = op.iters();
     for (int it = 0; it < it_n; ++it) {
         op.set_iter(it);
-        fft_line_tile<T, L, TC, PAD, MAPJ, DIR, NT>(lds, tw, op);
+        fft_line_tile<T, L, MODE, DIR, Op::STAGED>(lds, tw, op);
         if (it + 1 < it_n) __syncthreads();
     }
 }
@@ -269,15 +275,20 @@ __device__ __forceinline__ Tile make_tile(int axis, const Dims &d, int t, int TC
     return g;
 }
 
-__device__ __forceinline__ size_t at(const Tile &g, int i, int c) {
-    return g.base + (size_t)i * g.si + (size_t)c * g.sc;
+// Offset of element (i, c) from the tile base; below 2^31 for every grid up to 2^30 cells.
+__device__ __forceinline__ unsigned off(const Tile &g, int i, int c) {
+    return (unsigned)i * (unsigned)g.si + (unsigned)c * (unsigned)g.sc;
 }
+
+// Octant folding of a frequency index: k and n - k share an entry.
+__device__ __forceinline__ int fold(int k, int n) { return k <= n - k ? k : n - k; }
 
 // ---------------------------------------------------------------------------
 // operators
 // ---------------------------------------------------------------------------
 template <typename T>
-struct OpPack {   // z pass, forward: (a + i b) -> spec
+struct OpPack {
+    static constexpr bool STAGED = false;   // z pass, forward: (a + i b) -> spec
     using C = cplx<T>;
     const void *tw;
     Dims d;
@@ -285,18 +296,24 @@ struct OpPack {   // z pass, forward: (a + i b) -> spec
     const T *b;
     C *out;
     Tile g;
-    __device__ void begin(int TC) { g = make_tile(AX_Z, d, blockIdx.x, TC); }
+    template <int TC> __device__ void begin() {
+        g = make_tile(AX_Z, d, blockIdx.x, TC);
+        a += g.base;
+        if (b) b += g.base;
+        out += g.base;
+    }
     __device__ int iters() const { return 1; }
     __device__ void set_iter(int) {}
     __device__ C load(int i, int c) const {
-        const size_t k = at(g, i, c);
+        const unsigned k = off(g, i, c);
         return C{a[k], b ? b[k] : (T)0};
     }
-    __device__ void store(int i, int c, C v) const { out[at(g, i, c)] = v; }
+    __device__ void store(int i, int c, C v) const { out[off(g, i, c)] = v; }
 };
 
 template <typename T>
-struct OpInplace {   // any axis, in place; blockIdx.y selects a grid of the batch
+struct OpInplace {
+    static constexpr bool STAGED = false;   // any axis, in place; blockIdx.y selects a grid of the batch
     using C = cplx<T>;
     const void *tw;
     Dims d;
@@ -305,23 +322,27 @@ struct OpInplace {   // any axis, in place; blockIdx.y selects a grid of the bat
     size_t nc;
     Tile g;
     C *p;
-    __device__ void begin(int TC) {
+    template <int TC> __device__ void begin() {
         g = make_tile(axis, d, blockIdx.x, TC);
-        p = buf + (size_t)blockIdx.y * nc;
+        p = buf + (size_t)blockIdx.y * nc + g.base;
     }
     __device__ int iters() const { return 1; }
     __device__ void set_iter(int) {}
-    __device__ C load(int i, int c) const { return p[at(g, i, c)]; }
-    __device__ void store(int i, int c, C v) const { p[at(g, i, c)] = v; }
+    __device__ C load(int i, int c) const { return p[off(g, i, c)]; }
+    __device__ void store(int i, int c, C v) const { p[off(g, i, c)] = v; }
 };
 
 // x pass, inverse, for radii m0 .. m0+nb-1: spec * K_m -> tspec[m - m0].
-// K_m is stored as its octant [nx/2+1][ny/2+1][nz/2+1]; k and n - k share an entry.
-// One radius per workgroup.  Workgroups are dispatched round-robin over the 8
-// XCDs; the nb radii of one tile are given ids 8 apart so that they run on the
-// same XCD back to back and re-read the tile of `spec` from that XCD's L2.
-template <typename T>
+// The kernel octant of radius m is stored [ky'][kz'][kx'] (x fastest), so the
+// values a thread needs for its (ky, kz) column are one contiguous run.
+// With loop = 0 each workgroup handles one (tile, radius) pair.  Workgroups are
+// dispatched round-robin over the 8 XCDs; the nb radii of one tile get ids 8
+// apart so that they run on one XCD back to back and re-read the tile of
+// `spec` from that XCD's L2.  With loop = 1 each workgroup runs the nb radii of
+// its tile one after the other.
+template <typename T, bool STG>
 struct OpMulK {
+    static constexpr bool STAGED = STG;
     using C = cplx<T>;
     const void *tw;
     Dims d;
@@ -330,17 +351,19 @@ struct OpMulK {
     C *tspec;
     size_t nc;
     size_t kel;   // octant elements per radius
-    int m0, nb, tiles;
+    int m0, nb, tiles, loop;
     Tile g;
-    int m;
+    int m, col;
     const C *src;   // spec at this tile and this thread's column
     C *dst;
-    const T *kcol;  // kspec of radius m at this thread's (ky, kz) column
-    int kplane;     // octant elements per kx
-    __device__ void begin(int TC) {
+    const T *kcol;  // octant of radius m at this thread's (ky, kz) column
+    template <int TC> __device__ void begin() {
         const int w = blockIdx.x;
         int tile;
-        if ((tiles & 7) == 0) {
+        if (loop) {
+            tile = w;
+            m = 0;
+        } else if ((tiles & 7) == 0) {
             const int xcd = w & 7, slot = w >> 3;
             tile = (slot / nb) * 8 + xcd;
             m = slot % nb;
@@ -349,20 +372,24 @@ struct OpMulK {
             m = w % nb;
         }
         g = make_tile(AX_X, d, tile, TC);
-        const int c = threadIdx.x % TC;
-        const int ky = g.p0, kz = g.p1 + c;
-        const int oy = ky <= d.ny - ky ? ky : d.ny - ky;
-        const int oz = kz <= d.nz - kz ? kz : d.nz - kz;
-        kplane = (d.ny / 2 + 1) * (d.nz / 2 + 1);
-        kcol = kspec + (size_t)(m0 + m) * kel + (size_t)oy * (d.nz / 2 + 1) + oz;
-        src = spec + g.base + c;
-        dst = tspec + (size_t)m * nc + g.base + c;
+        col = threadIdx.x % TC;
+        src = spec + g.base + col;
+        set_radius();
     }
-    __device__ int iters() const { return 1; }
-    __device__ void set_iter(int) {}
+    __device__ void set_radius() {
+        const int oy = fold(g.p0, d.ny), oz = fold(g.p1 + col, d.nz);
+        kcol = kspec + (size_t)(m0 + m) * kel + ((size_t)oy * (d.nz / 2 + 1) + oz) * (d.nx / 2 + 1);
+        dst = tspec + (size_t)m * nc + g.base + col;
+    }
+    __device__ int iters() const { return loop ? nb : 1; }
+    __device__ void set_iter(int it) {
+        if (loop) {
+            m = it;
+            set_radius();
+        }
+    }
     __device__ C load(int i, int) const {
-        const int ox = i <= d.nx - i ? i : d.nx - i;
-        const T kv = kcol[(unsigned)(ox * kplane)];
+        const T kv = kcol[fold(i, d.nx)];
         const C s = src[(size_t)(unsigned)i * (unsigned)g.si];
         return C{s.x * kv, s.y * kv};
     }
@@ -372,6 +399,7 @@ struct OpMulK {
 // z pass, inverse: tspec[m] -> real parts to maps_a[m0+m], imaginary to maps_b[m0+m].
 template <typename T>
 struct OpUnpack {
+    static constexpr bool STAGED = false;
     using C = cplx<T>;
     const void *tw;
     Dims d;
@@ -382,17 +410,18 @@ struct OpUnpack {
     int m0;
     Tile g;
     const C *src;
-    size_t off;
-    __device__ void begin(int TC) {
+    template <int TC> __device__ void begin() {
         g = make_tile(AX_Z, d, blockIdx.x, TC);
-        src = tspec + (size_t)blockIdx.y * nc;
-        off = (size_t)(m0 + blockIdx.y) * nc;
+        src = tspec + (size_t)blockIdx.y * nc + g.base;
+        const size_t o = (size_t)(m0 + blockIdx.y) * nc + g.base;
+        ma += o;
+        if (mb) mb += o;
     }
     __device__ int iters() const { return 1; }
     __device__ void set_iter(int) {}
-    __device__ C load(int i, int c) const { return src[at(g, i, c)]; }
+    __device__ C load(int i, int c) const { return src[off(g, i, c)]; }
     __device__ void store(int i, int c, C v) const {
-        const size_t k = off + at(g, i, c);
+        const unsigned k = off(g, i, c);
         ma[k] = v.x;
         if (mb) mb[k] = v.y;
     }
@@ -402,13 +431,14 @@ struct OpUnpack {
 // real part = [lo_a <= |delta|^2 < hi_a], imaginary part likewise for b,
 // with delta the minimum-image offset of the cell from cell (0, 0, 0).
 struct OpShellFill {
+    static constexpr bool STAGED = false;
     using C = double2;
     const void *tw;
     Dims d;
     double lo_a, hi_a, lo_b, hi_b;
     C *out;
     Tile g;
-    __device__ void begin(int TC) { g = make_tile(AX_Z, d, blockIdx.x, TC); }
+    template <int TC> __device__ void begin() { g = make_tile(AX_Z, d, blockIdx.x, TC); }
     __device__ int iters() const { return 1; }
     __device__ void set_iter(int) {}
     __device__ C load(int i, int c) const {
@@ -420,12 +450,14 @@ struct OpShellFill {
         const double d2 = (double)(dx * dx + dy * dy + dz * dz);
         return C{(d2 >= lo_a && d2 < hi_a) ? 1.0 : 0.0, (d2 >= lo_b && d2 < hi_b) ? 1.0 : 0.0};
     }
-    __device__ void store(int i, int c, C v) const { out[at(g, i, c)] = v; }
+    __device__ void store(int i, int c, C v) const { out[g.base + off(g, i, c)] = v; }
 };
 
-// x pass, forward, of the packed shell pair: keep the octant, scale by 1/N_c.
+// x pass, forward, of the packed shell pair: keep the octant, x fastest,
+// scaled by 1/N_c: kspec[m][ky][kz][kx] for kx <= nx/2, ky <= ny/2, kz <= nz/2.
 template <typename K>
 struct OpExtract {
+    static constexpr bool STAGED = false;
     using C = double2;
     const void *tw;
     Dims d;
@@ -435,52 +467,148 @@ struct OpExtract {
     int ma, mb;
     double scale;
     Tile g;
-    __device__ void begin(int TC) { g = make_tile(AX_X, d, blockIdx.x, TC); }
+    template <int TC> __device__ void begin() { g = make_tile(AX_X, d, blockIdx.x, TC); }
     __device__ int iters() const { return 1; }
     __device__ void set_iter(int) {}
-    __device__ C load(int i, int c) const { return buf[at(g, i, c)]; }
+    __device__ C load(int i, int c) const { return buf[g.base + off(g, i, c)]; }
     __device__ void store(int i, int c, C v) const {
         const int ky = g.p0, kz = g.p1 + c, kx = i;
         if (2 * kx > d.nx || 2 * ky > d.ny || 2 * kz > d.nz) return;
-        const size_t ko = ((size_t)kx * (d.ny / 2 + 1) + ky) * (d.nz / 2 + 1) + kz;
+        const size_t ko = ((size_t)ky * (d.nz / 2 + 1) + kz) * (d.nx / 2 + 1) + kx;
         kspec[(size_t)ma * kel + ko] = (K)(v.x * scale);
         if (mb >= 0) kspec[(size_t)mb * kel + ko] = (K)(v.y * scale);
     }
 };
 
 // ---------------------------------------------------------------------------
-// launch helpers
+// x pass, inverse, with the kernel multiply, for a batch of radii, keeping the
+// spectrum tile resident in LDS: the tile (all kx of one ky and TC columns kz)
+// is read from HBM once per batch instead of once per radius.  For each radius
+// the kernel octant values of the tile's columns (one contiguous run per
+// column, x fastest) are staged into LDS with coalesced reads, prefetched into
+// registers while the previous radius is transformed.
 // ---------------------------------------------------------------------------
+template <typename T, int L, int TC>
+struct OpResident {
+    static constexpr bool STAGED = false;
+    using C = cplx<T>;
+    const C *st;    // LDS: spectrum tile [L][TC]
+    const T *kt;    // LDS: kernel values [TC][L/2 + 1]
+    C *out;         // global: output tile base
+    unsigned si;
+    __device__ C load(int i, int c) const {
+        const C s = st[i * TC + c];
+        const T k = kt[c * (L / 2 + 1) + (i <= L - i ? i : L - i)];
+        return C{s.x * k, s.y * k};
+    }
+    __device__ void store(int i, int c, C v) const { out[(unsigned)i * si + (unsigned)c] = v; }
+};
+
 template <typename T, int L>
-constexpr int tc_of(bool mapj) {
-    return mapj ? Shape<T, L>::TC_J : Shape<T, L>::TC_C;
+constexpr bool resident_fits() {
+    using SH = Shape<T, L, TM_R>;
+    return (size_t)SH::LDS * sizeof(cplx<T>) + (size_t)L * sizeof(cplx<T>) +
+               (size_t)L * SH::TC * sizeof(cplx<T>) + (size_t)SH::TC * (L / 2 + 1) * sizeof(T) <=
+           160 * 1024;
 }
 
-template <typename T>
-int tc_of(int L, bool mapj) {
-    switch (L) {
-        case 32: return tc_of<T, 32>(mapj);
-        case 64: return tc_of<T, 64>(mapj);
-        case 128: return tc_of<T, 128>(mapj);
-        case 256: return tc_of<T, 256>(mapj);
-        case 512: return tc_of<T, 512>(mapj);
-        default: return tc_of<T, 1024>(mapj);
+template <typename T, int L>
+__global__ __launch_bounds__((Shape<T, L, TM_R>::NT), (Shape<T, L, TM_R>::MINW)) void k_xmul_resident(
+    const cplx<T> *__restrict__ spec, const T *__restrict__ kspec, cplx<T> *__restrict__ tspec,
+    const cplx<T> *__restrict__ twg, Dims d, size_t nc, size_t kel, int m0, int nb) {
+    using C = cplx<T>;
+    using SH = Shape<T, L, TM_R>;
+    constexpr int TC = SH::TC, NT = SH::NT, NXH = L / 2 + 1;
+    constexpr int KPT = (TC * NXH + NT - 1) / NT;   // kernel values staged per thread
+    __shared__ C lds[SH::LDS];
+    __shared__ C tw[L];
+    __shared__ C st[L * TC];
+    __shared__ T kt[TC * NXH];
+    const Tile g = make_tile(AX_X, d, blockIdx.x, TC);
+    for (int t = threadIdx.x; t < L; t += NT) tw[t] = twg[t];
+    for (int e = threadIdx.x; e < L * TC; e += NT) {
+        const int i = e / TC, c = e - (e / TC) * TC;
+        st[e] = spec[g.base + (size_t)(unsigned)i * (unsigned)g.si + c];
+    }
+    const int oy = fold(g.p0, d.ny);
+    const int nzh = d.nz / 2 + 1;
+    auto kload = [&](int m, T (&kv)[KPT]) {
+        const T *kb = kspec + (size_t)(m0 + m) * kel + (size_t)oy * nzh * NXH;
+#pragma unroll
+        for (int q = 0; q < KPT; ++q) {
+            const int e = threadIdx.x + q * NT;
+            if (e < TC * NXH) {
+                const int c = e / NXH, ox = e - (e / NXH) * NXH;
+                kv[q] = kb[(size_t)fold(g.p1 + c, d.nz) * NXH + ox];
+            }
+        }
+    };
+    T kv[KPT];
+    kload(0, kv);
+    for (int m = 0; m < nb; ++m) {
+#pragma unroll
+        for (int q = 0; q < KPT; ++q) {
+            const int e = threadIdx.x + q * NT;
+            if (e < TC * NXH) kt[e] = kv[q];
+        }
+        __syncthreads();
+        if (m + 1 < nb) kload(m + 1, kv);
+        OpResident<T, L, TC> op{st, kt, tspec + (size_t)m * nc + g.base, (unsigned)g.si};
+        fft_line_tile<T, L, TM_R, +1, false>(lds, tw, op);
+        __syncthreads();
     }
 }
 
-template <typename T, bool MAPJ, int DIR, class Op>
-int launch_len(conker_ctx *ctx, int kind, int L, int axis, const Dims &d, dim3 gy, Op op) {
-    ProfScope ps(ctx, kind);
+// ---------------------------------------------------------------------------
+// launch helpers
+// ---------------------------------------------------------------------------
+template <typename T, int L>
+int tc_of_mode(int mode) {
+    switch (mode) {
+        case TM_J: return Shape<T, L, TM_J>::TC;
+        case TM_C: return Shape<T, L, TM_C>::TC;
+        default: return Shape<T, L, TM_W>::TC;
+    }
+}
+
+template <typename T>
+int tc_of(int L, int mode) {
+    switch (L) {
+        case 32: return tc_of_mode<T, 32>(mode);
+        case 64: return tc_of_mode<T, 64>(mode);
+        case 128: return tc_of_mode<T, 128>(mode);
+        case 256: return tc_of_mode<T, 256>(mode);
+        case 512: return tc_of_mode<T, 512>(mode);
+        default: return tc_of_mode<T, 1024>(mode);
+    }
+}
+
+// Tile mode of x-axis passes: wide (256-byte runs) unless CONKER_X_WIDE=0.
+int x_mode() {
+    static const int m = [] {
+        const char *e = std::getenv("CONKER_X_WIDE");
+        return (e && e[0] == '0') ? (int)TM_C : (int)TM_W;
+    }();
+    return m;
+}
+
+template <typename T>
+int x_mode_for(const Dims &d) {
+    const int m = x_mode();
+    return (m == TM_W && d.nz < tc_of<T>(d.nx, TM_W)) ? (int)TM_C : m;
+}
+
+template <typename T, int MODE, int DIR, class Op>
+int launch_len_mode(conker_ctx *ctx, int L, int axis, const Dims &d, dim3 gy, Op op) {
     auto go = [&](auto Lc) -> int {
         constexpr int LL = decltype(Lc)::value;
-        const int TC = tc_of<T, LL>(MAPJ);
+        using SH = Shape<T, LL, MODE>;
         long tiles;
-        if (axis == AX_Z) tiles = (long)d.nx * d.ny / TC;
-        else if (axis == AX_Y) tiles = (long)d.nx * d.nz / TC;
-        else tiles = (long)d.ny * d.nz / TC;
+        if (axis == AX_Z) tiles = (long)d.nx * d.ny / SH::TC;
+        else if (axis == AX_Y) tiles = (long)d.nx * d.nz / SH::TC;
+        else tiles = (long)d.ny * d.nz / SH::TC;
         dim3 grid((unsigned)(tiles * gy.z), gy.y, 1);
-        hipLaunchKernelGGL((k_fft<T, LL, MAPJ, DIR, Op>), grid, dim3(threads_of<T, LL, MAPJ>()), 0, ctx->stream,
-                           op);
+        hipLaunchKernelGGL((k_fft<T, LL, MODE, DIR, Op>), grid, dim3(SH::NT), 0, ctx->stream, op);
         CK_LAUNCH(ctx);
         return CONKER_OK;
     };
@@ -495,6 +623,14 @@ int launch_len(conker_ctx *ctx, int kind, int L, int axis, const Dims &d, dim3 g
     }
 }
 
+template <typename T, int DIR, class Op>
+int launch_len(conker_ctx *ctx, int kind, int mode, int L, int axis, const Dims &d, dim3 gy, Op op) {
+    ProfScope ps(ctx, kind);
+    if (mode == TM_J) return launch_len_mode<T, TM_J, DIR>(ctx, L, axis, d, gy, op);
+    if (mode == TM_C) return launch_len_mode<T, TM_C, DIR>(ctx, L, axis, d, gy, op);
+    return launch_len_mode<T, TM_W, DIR>(ctx, L, axis, d, gy, op);
+}
+
 template <typename T>
 int forward_pair_t(conker_ctx *ctx, const conker_grid *g, const void *a, const void *b, void *spec) {
     using C = cplx<T>;
@@ -506,17 +642,17 @@ int forward_pair_t(conker_ctx *ctx, const conker_grid *g, const void *a, const v
     CK_OK(twiddles(ctx, d.nx, f64, &twx));
     const size_t nc = ncells(g);
     OpPack<T> pz{twz, d, (const T *)a, (const T *)b, (C *)spec, {}};
-    CK_OK((launch_len<T, true, -1>(ctx, PK_FFT_FWD_Z, d.nz, AX_Z, d, dim3(1, 1), pz)));
+    CK_OK((launch_len<T, -1>(ctx, PK_FFT_FWD_Z, TM_J, d.nz, AX_Z, d, dim3(1, 1), pz)));
     OpInplace<T> py{twy, d, AX_Y, (C *)spec, nc, {}, nullptr};
-    CK_OK((launch_len<T, false, -1>(ctx, PK_FFT_FWD_Y, d.ny, AX_Y, d, dim3(1, 1), py)));
+    CK_OK((launch_len<T, -1>(ctx, PK_FFT_FWD_Y, TM_C, d.ny, AX_Y, d, dim3(1, 1), py)));
     OpInplace<T> px{twx, d, AX_X, (C *)spec, nc, {}, nullptr};
-    CK_OK((launch_len<T, false, -1>(ctx, PK_FFT_FWD_X, d.nx, AX_X, d, dim3(1, 1), px)));
+    CK_OK((launch_len<T, -1>(ctx, PK_FFT_FWD_X, x_mode_for<T>(d), d.nx, AX_X, d, dim3(1, 1), px)));
     return CONKER_OK;
 }
 
 template <typename T>
-int inverse_batch_t(conker_ctx *ctx, const conker_grid *g, const void *spec, const void *kspec,
-                    int m0, int nb, void *tspec, void *maps_a, void *maps_b) {
+int inverse_batch_t(conker_ctx *ctx, const conker_grid *g, const void *spec, const void *kspec, int m0,
+                    int nb, void *tspec, void *maps_a, void *maps_b) {
     using C = cplx<T>;
     const bool f64 = std::is_same<T, double>::value;
     Dims d{g->dims[0], g->dims[1], g->dims[2]};
@@ -526,14 +662,63 @@ int inverse_batch_t(conker_ctx *ctx, const conker_grid *g, const void *spec, con
     CK_OK(twiddles(ctx, d.nx, f64, &twx));
     const size_t nc = ncells(g);
     const size_t kel = (size_t)(d.nx / 2 + 1) * (d.ny / 2 + 1) * (d.nz / 2 + 1);
-    OpMulK<T> px{twx, d, (const C *)spec, (const T *)kspec, (C *)tspec, nc, kel, m0, nb, 0, {}, 0,
-                 nullptr, nullptr, nullptr, 0};
-    px.tiles = (int)((long)d.ny * d.nz / tc_of<T>(d.nx, false));
-    CK_OK((launch_len<T, false, +1>(ctx, PK_FFT_INV_X_MUL, d.nx, AX_X, d, dim3(1, 1, (unsigned)nb), px)));
+    static const int loop = [] {
+        const char *e = std::getenv("CONKER_XMUL_LOOP");
+        return (e && e[0] == '1') ? 1 : 0;
+    }();
+    const int xm = x_mode_for<T>(d);
+    static const int staged = [] {
+        const char *e = std::getenv("CONKER_XMUL_STAGED");
+        return (e && e[0] == '0') ? 0 : 1;
+    }();
+    const int tiles = (int)((long)d.ny * d.nz / tc_of<T>(d.nx, xm));
+    const dim3 gxm(1, 1, loop ? 1u : (unsigned)nb);
+    static const int resident = [] {
+        const char *e = std::getenv("CONKER_XMUL_RESIDENT");
+        return (e && e[0] == '0') ? 0 : 1;
+    }();
+    bool done = false;
+    if (resident) {
+        auto go = [&](auto Lc) -> int {
+            constexpr int LL = decltype(Lc)::value;
+            if constexpr (resident_fits<T, LL>()) {
+                using SH = Shape<T, LL, TM_R>;
+                if (d.nz % SH::TC) return CONKER_OK;
+                ProfScope ps(ctx, PK_FFT_INV_X_MUL);
+                const unsigned nt = (unsigned)((long)d.ny * d.nz / SH::TC);
+                hipLaunchKernelGGL((k_xmul_resident<T, LL>), dim3(nt), dim3(SH::NT), 0, ctx->stream,
+                                   (const C *)spec, (const T *)kspec, (C *)tspec, (const C *)twx, d, nc, kel, m0,
+                                   nb);
+                CK_LAUNCH(ctx);
+                done = true;
+            }
+            return CONKER_OK;
+        };
+        int st = CONKER_OK;
+        switch (d.nx) {
+            case 32: st = go(std::integral_constant<int, 32>()); break;
+            case 64: st = go(std::integral_constant<int, 64>()); break;
+            case 128: st = go(std::integral_constant<int, 128>()); break;
+            case 256: st = go(std::integral_constant<int, 256>()); break;
+            case 512: st = go(std::integral_constant<int, 512>()); break;
+            default: break;
+        }
+        CK_OK(st);
+    }
+    if (done) {
+    } else if (staged) {
+        OpMulK<T, true> px{twx, d, (const C *)spec, (const T *)kspec, (C *)tspec, nc, kel, m0, nb, tiles, loop,
+                           {}, 0, 0, nullptr, nullptr, nullptr};
+        CK_OK((launch_len<T, +1>(ctx, PK_FFT_INV_X_MUL, xm, d.nx, AX_X, d, gxm, px)));
+    } else {
+        OpMulK<T, false> px{twx, d, (const C *)spec, (const T *)kspec, (C *)tspec, nc, kel, m0, nb, tiles, loop,
+                            {}, 0, 0, nullptr, nullptr, nullptr};
+        CK_OK((launch_len<T, +1>(ctx, PK_FFT_INV_X_MUL, xm, d.nx, AX_X, d, gxm, px)));
+    }
     OpInplace<T> py{twy, d, AX_Y, (C *)tspec, nc, {}, nullptr};
-    CK_OK((launch_len<T, false, +1>(ctx, PK_FFT_INV_Y, d.ny, AX_Y, d, dim3(1, (unsigned)nb), py)));
-    OpUnpack<T> pz{twz, d, (const C *)tspec, (T *)maps_a, (T *)maps_b, nc, m0, {}, nullptr, 0};
-    CK_OK((launch_len<T, true, +1>(ctx, PK_FFT_INV_Z, d.nz, AX_Z, d, dim3(1, (unsigned)nb), pz)));
+    CK_OK((launch_len<T, +1>(ctx, PK_FFT_INV_Y, TM_C, d.ny, AX_Y, d, dim3(1, (unsigned)nb), py)));
+    OpUnpack<T> pz{twz, d, (const C *)tspec, (T *)maps_a, (T *)maps_b, nc, m0, {}, nullptr};
+    CK_OK((launch_len<T, +1>(ctx, PK_FFT_INV_Z, TM_J, d.nz, AX_Z, d, dim3(1, (unsigned)nb), pz)));
     return CONKER_OK;
 }
 
@@ -562,16 +747,16 @@ int fft_shell_pair(conker_ctx *ctx, const conker_grid *g, double lo_a, double hi
     const size_t nc = ncells(g);
     const size_t kel = (size_t)(d.nx / 2 + 1) * (d.ny / 2 + 1) * (d.nz / 2 + 1);
     OpShellFill pz{twz, d, lo_a, hi_a, lo_b, hi_b, (double2 *)work, {}};
-    CK_OK((launch_len<double, true, -1>(ctx, PK_BANK_Z, d.nz, AX_Z, d, dim3(1, 1), pz)));
+    CK_OK((launch_len<double, -1>(ctx, PK_BANK_Z, TM_J, d.nz, AX_Z, d, dim3(1, 1), pz)));
     OpInplace<double> py{twy, d, AX_Y, (double2 *)work, nc, {}, nullptr};
-    CK_OK((launch_len<double, false, -1>(ctx, PK_BANK_Y, d.ny, AX_Y, d, dim3(1, 1), py)));
+    CK_OK((launch_len<double, -1>(ctx, PK_BANK_Y, TM_C, d.ny, AX_Y, d, dim3(1, 1), py)));
     const double scale = 1.0 / (double)nc;
     if (out_f64) {
         OpExtract<double> px{twx, d, (const double2 *)work, (double *)kspec, kel, ma, mb, scale, {}};
-        CK_OK((launch_len<double, false, -1>(ctx, PK_BANK_X, d.nx, AX_X, d, dim3(1, 1), px)));
+        CK_OK((launch_len<double, -1>(ctx, PK_BANK_X, TM_C, d.nx, AX_X, d, dim3(1, 1), px)));
     } else {
         OpExtract<float> px{twx, d, (const double2 *)work, (float *)kspec, kel, ma, mb, scale, {}};
-        CK_OK((launch_len<double, false, -1>(ctx, PK_BANK_X, d.nx, AX_X, d, dim3(1, 1), px)));
+        CK_OK((launch_len<double, -1>(ctx, PK_BANK_X, TM_C, d.nx, AX_X, d, dim3(1, 1), px)));
     }
     return CONKER_OK;
 }

@@ -141,7 +141,9 @@ def test_shell_kernel_spectra(ck, ctx, dims, dt):
     _say("shells", dims, dt, radii)
     grid = ck.Grid(dims, (0, 0, 0), cell)
     ks, sizes = ctx.make_shell_kernels(grid, radii, TDT[dt])
-    ks = ks.cpu().numpy().reshape(len(radii), dims[0] // 2 + 1, dims[1] // 2 + 1, dims[2] // 2 + 1)
+    # stored octant layout: [radius][ky][kz][kx] (x fastest)
+    ks = ks.cpu().numpy().reshape(len(radii), dims[1] // 2 + 1, dims[2] // 2 + 1, dims[0] // 2 + 1)
+    ks = ks.transpose(0, 3, 1, 2)
     nc = np.prod(dims)
     for m, s in enumerate(radii):
         r = s / cell

@@ -58,6 +58,8 @@ def kernel_bytes(kind, n_launch_units, nc, ns, kel, n_data, n_rand, weighted, es
         return (n_data + n_rand) * per
     if kind == "form_delta":
         return 3 * nc * esize
+    if kind == "fused_zinv_contract":   # every radius's spectrum once, both fields once
+        return ns * nc * c + 2 * nc * esize
     return None
 
 

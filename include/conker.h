@@ -164,6 +164,22 @@ int conker_contract_npt(conker_ctx *ctx, const conker_grid *grid, conker_dtype d
                         const void *d_field, const void *d_maps, int n_radii, int n,
                         conker_mmprec prec, double *d_W);
 
+/* conker_convolve_contract: conker_convolve_shells followed by
+ * conker_contract_npt for orders n = 2 or 3, in one pass that never writes the
+ * per-radius maps to memory (each line of cells is transformed back for every
+ * radius in on-chip memory and summed at once):
+ *   W_a[t] = sum_x field_a(x) prod_i maps_a[a_i](x), and likewise W_b for
+ *   field_b, maps as defined for conker_convolve_shells, tuples in the order
+ *   of conker_contract_npt.
+ *   d_field_b and d_W_b: both given or both NULL.
+ * Supported: dtype CONKER_F32 with prec CONKER_MM_F32 or
+ * CONKER_MM_SPLIT_BF16, nz = 512, 1 <= n_radii <= 30; anything else returns
+ * CONKER_EUNSUPPORTED before doing work (use the two separate calls).  The
+ * context holds the spectra of all radii at once (n_radii * N_c * 8 bytes). */
+int conker_convolve_contract(conker_ctx *ctx, const conker_grid *grid, conker_dtype dtype,
+                             const void *d_field_a, const void *d_field_b, const void *d_kspec,
+                             int n_radii, int n, conker_mmprec prec, double *d_W_a, double *d_W_b);
+
 /* conker_ratio: the estimator xi = W_delta / (alpha^n W_rand) in float64
  * (Eq. ksin_delta with B_i built on R = alpha R_raw).  All pointers are
  * device float64; d_alpha is a scalar. */

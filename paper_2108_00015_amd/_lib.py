@@ -38,6 +38,9 @@ SIGNATURES = {
     "conker_num_tuples": (ct.c_int64, [ct.c_int, ct.c_int]),
     "conker_contract_npt": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_void_p,
                                        ct.c_int, ct.c_int, ct.c_int, ct.c_void_p]),
+    "conker_convolve_contract": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_void_p,
+                                            ct.c_void_p, ct.c_int, ct.c_int, ct.c_int, ct.c_void_p,
+                                            ct.c_void_p]),
     "conker_ratio": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int,
                                 ct.c_int64, ct.c_void_p]),
     "conker_synchronize": (ct.c_int, [ct.c_void_p]),

@@ -198,6 +198,22 @@ class Context:
                                                  nr, int(n), PRECISIONS[precision], _ptr(out)))
         return out
 
+    def convolve_contract(self, grid: Grid, field_a: torch.Tensor, field_b: Optional[torch.Tensor],
+                          kspec: torch.Tensor, n: int, precision: str = "split_bf16",
+                          out_a: Optional[torch.Tensor] = None, out_b: Optional[torch.Tensor] = None):
+        """Convolution + summation (n = 2, 3) without storing maps; returns (W_a, W_b)."""
+        nr = int(kspec.shape[0])
+        cnt = num_tuples(nr, n)
+        if out_a is None:
+            out_a = torch.empty(max(cnt, 0), dtype=torch.float64, device=field_a.device)
+        if field_b is not None and out_b is None:
+            out_b = torch.empty(max(cnt, 0), dtype=torch.float64, device=field_a.device)
+        g = grid.c()
+        self._check(self.lib.conker_convolve_contract(self.h, ct.byref(g), _DT[field_a.dtype], _ptr(field_a),
+                                                      _ptr(field_b), _ptr(kspec), nr, int(n),
+                                                      PRECISIONS[precision], _ptr(out_a), _ptr(out_b)))
+        return out_a, out_b
+
     def ratio(self, Wd: torch.Tensor, Wr: torch.Tensor, alpha: torch.Tensor, n: int,
               out: Optional[torch.Tensor] = None) -> torch.Tensor:
         if out is None:
@@ -207,14 +223,26 @@ class Context:
         return out
 
 
+def fused_supported(grid: Grid, n_radii: int, n: int, precision: str, dtype) -> bool:
+    """Whether conker_convolve_contract handles this case (else the two separate calls are used)."""
+    return (dtype == torch.float32 and precision in ("f32", "split_bf16") and n in (2, 3)
+            and int(grid.dims[2]) == 512 and 1 <= n_radii <= 30)
+
+
 def npcf(ctx: Context, grid: Grid, data_pos: torch.Tensor, rand_pos: torch.Tensor, kspec: torch.Tensor,
          n: int, data_w: Optional[torch.Tensor] = None, rand_w: Optional[torch.Tensor] = None,
-         precision: str = "f64", dtype=torch.float64, bufs: Optional[dict] = None) -> dict:
+         precision: str = "f64", dtype=torch.float64, bufs: Optional[dict] = None,
+         fused: Optional[bool] = None) -> dict:
     """Mapping -> convolution -> summation -> estimator, chaining the C ABI calls.
 
     `bufs` may hold preallocated tensors (keys: N, R, maps_N, maps_R, wsum, nout, alpha) that are
-    reused across calls.  Returns xi, W_delta, W_rand_raw, alpha and the buffers (all on the GPU).
+    reused across calls.  With `fused` (default: whenever supported) the convolution and summation
+    run as one call that never stores the maps.  Returns xi, W_delta, W_rand_raw, alpha and the
+    buffers (all on the GPU).
     """
+    nr_ = int(kspec.shape[0])
+    if fused is None:
+        fused = fused_supported(grid, nr_, n, precision, dtype)
     dev = data_pos.device
     b = {} if bufs is None else bufs
     shape = tuple(int(d) for d in grid.dims)
@@ -222,8 +250,6 @@ def npcf(ctx: Context, grid: Grid, data_pos: torch.Tensor, rand_pos: torch.Tenso
     if "N" not in b:
         b["N"] = torch.empty(shape, dtype=dtype, device=dev)
         b["R"] = torch.empty(shape, dtype=dtype, device=dev)
-        b["maps_N"] = torch.empty((nr,) + shape, dtype=dtype, device=dev)
-        b["maps_R"] = torch.empty((nr,) + shape, dtype=dtype, device=dev)
         b["wsum"] = torch.empty(2, dtype=torch.float64, device=dev)
         b["nout"] = torch.empty(2, dtype=torch.int64, device=dev)
         b["alpha"] = torch.empty(1, dtype=torch.float64, device=dev)
@@ -234,8 +260,14 @@ def npcf(ctx: Context, grid: Grid, data_pos: torch.Tensor, rand_pos: torch.Tenso
     ctx.grid_assign(grid, data_pos, data_w, b["N"], b["wsum"][0:1], b["nout"][0:1])
     ctx.grid_assign(grid, rand_pos, rand_w, b["R"], b["wsum"][1:2], b["nout"][1:2])
     ctx.form_delta(grid, b["N"], b["R"], b["wsum"][0:1], b["wsum"][1:2], b["alpha"])
-    ctx.convolve_shells(grid, b["N"], b["R"], kspec, b["maps_N"], b["maps_R"])
-    Wd = ctx.contract_npt(grid, b["N"], b["maps_N"], n, precision)
-    Wr = ctx.contract_npt(grid, b["R"], b["maps_R"], n, precision)
+    if fused:
+        Wd, Wr = ctx.convolve_contract(grid, b["N"], b["R"], kspec, n, precision)
+    else:
+        if "maps_N" not in b:
+            b["maps_N"] = torch.empty((nr,) + shape, dtype=dtype, device=dev)
+            b["maps_R"] = torch.empty((nr,) + shape, dtype=dtype, device=dev)
+        ctx.convolve_shells(grid, b["N"], b["R"], kspec, b["maps_N"], b["maps_R"])
+        Wd = ctx.contract_npt(grid, b["N"], b["maps_N"], n, precision)
+        Wr = ctx.contract_npt(grid, b["R"], b["maps_R"], n, precision)
     xi = ctx.ratio(Wd, Wr, b["alpha"], n)
     return dict(xi=xi, W_delta=Wd, W_rand_raw=Wr, alpha=b["alpha"], bufs=b)

@@ -37,6 +37,7 @@ struct conker_ctx {
     conker::Buf full;       // reduced block matrices of the summation stage
     std::map<uint64_t, conker::Buf> tables;  // item / tuple tables, keyed by (n_radii, n, prec)
     // per-launch event timing (conker_profile_enable)
+    int n_cu = 0;
     bool prof = false;
     struct Rec {
         int kind;
@@ -67,6 +68,7 @@ enum ProfKind {
     PK_CONTRACT_MM,
     PK_CONTRACT_REDUCE,
     PK_RATIO,
+    PK_FUSED_ZC,
     PK_COUNT
 };
 
@@ -111,6 +113,9 @@ int fail(conker_ctx *ctx, int code, const char *fmt, ...);
 // context's workspace cap.  Waits for the stream before releasing memory.
 int ws_reserve(conker_ctx *ctx, Buf &b, size_t bytes);
 
+// Number of compute units of the context's device (cached).
+int cu_count(conker_ctx *ctx);
+
 // Device twiddle table of length L (float2 or double2), built on first use.
 int twiddles(conker_ctx *ctx, int L, bool f64, const void **out);
 
@@ -143,6 +148,8 @@ int fft_shell_pair(conker_ctx *ctx, const conker_grid *g, double lo_a, double hi
                    int ma, int mb);
 // Inverse passes for radii [m0, m0 + nb): multiply spectrum by K_m, inverse
 // 3D FFT, write real parts to maps_a[m] and imaginary parts to maps_b[m].
+// With maps_a NULL only the x and y passes run, leaving tspec[m - m0] holding
+// the spectra transformed back along x and y (still along kz).
 int fft_inverse_batch(conker_ctx *ctx, const conker_grid *g, bool f64,
                       const void *spec, const void *kspec, int m0, int nb, void *tspec,
                       void *maps_a, void *maps_b);

@@ -119,6 +119,16 @@ int check_grid(conker_ctx *ctx, const conker_grid *g, bool need_fft) {
     return CONKER_OK;
 }
 
+int cu_count(conker_ctx *c) {
+    if (c->n_cu <= 0) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess || v <= 0)
+            v = 256;
+        c->n_cu = v;
+    }
+    return c->n_cu;
+}
+
 static hipEvent_t take_event(conker_ctx *c) {
     if (!c->pool.empty()) {
         hipEvent_t e = c->pool.back();
@@ -266,7 +276,8 @@ extern "C" int conker_profile_read(conker_ctx *c, int kind, int64_t *launches, d
 extern "C" const char *conker_profile_kind_name(int kind) {
     static const char *names[PK_COUNT] = {
         "scatter", "form_delta", "fft_fwd_z", "fft_fwd_y", "fft_fwd_x", "fft_inv_x_mul", "fft_inv_y",
-        "fft_inv_z", "bank_z", "bank_y", "bank_x", "contract_dot", "contract_mm", "contract_reduce", "ratio"};
+        "fft_inv_z", "bank_z", "bank_y", "bank_x", "contract_dot", "contract_mm", "contract_reduce", "ratio",
+        "fused_zinv_contract"};
     return (kind >= 0 && kind < PK_COUNT) ? names[kind] : nullptr;
 }
 

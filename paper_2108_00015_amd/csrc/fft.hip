@@ -19,63 +19,13 @@
 #include <type_traits>
 
 #include "common.h"
+#include "fft_math.h"
 
 using namespace conker;
 
 namespace {
 
-template <typename T>
-using cplx = typename std::conditional<std::is_same<T, float>::value, float2, double2>::type;
-
-template <typename C>
-__device__ __forceinline__ C cadd(C a, C b) { return C{a.x + b.x, a.y + b.y}; }
-template <typename C>
-__device__ __forceinline__ C csub(C a, C b) { return C{a.x - b.x, a.y - b.y}; }
-template <typename C>
-__device__ __forceinline__ C cmul(C a, C b) {
-    return C{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
-}
-// a * (DIR i)
-template <int DIR, typename C>
-__device__ __forceinline__ C mul_di(C a) {
-    if constexpr (DIR > 0) return C{-a.y, a.x};
-    else return C{a.y, -a.x};
-}
-
-// X_k = sum_r v_r exp(DIR 2 pi i r k / R), in place.
-template <int R, int DIR, typename C>
-__device__ __forceinline__ void dft(C *v) {
-    if constexpr (R == 2) {
-        C a = v[0];
-        v[0] = cadd(a, v[1]);
-        v[1] = csub(a, v[1]);
-    } else if constexpr (R == 4) {
-        C a0 = cadd(v[0], v[2]), a1 = csub(v[0], v[2]);
-        C a2 = cadd(v[1], v[3]), a3 = mul_di<DIR>(csub(v[1], v[3]));
-        v[0] = cadd(a0, a2);
-        v[2] = csub(a0, a2);
-        v[1] = cadd(a1, a3);
-        v[3] = csub(a1, a3);
-    } else {
-        static_assert(R == 8, "radix");
-        using T = decltype(v[0].x);
-        C e[4] = {v[0], v[2], v[4], v[6]};
-        C o[4] = {v[1], v[3], v[5], v[7]};
-        dft<4, DIR>(e);
-        dft<4, DIR>(o);
-        const T h = (T)0.70710678118654752440;   // 1/sqrt(2)
-        const T d = (T)DIR;
-        // o_k *= exp(DIR 2 pi i k / 8)
-        o[1] = C{(o[1].x - d * o[1].y) * h, (o[1].y + d * o[1].x) * h};
-        o[2] = mul_di<DIR>(o[2]);
-        o[3] = C{(-o[3].x - d * o[3].y) * h, (d * o[3].x - o[3].y) * h};
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            v[k] = cadd(e[k], o[k]);
-            v[k + 4] = csub(e[k], o[k]);
-        }
-    }
-}
+using namespace conker::fftm;
 
 // Radix schedule per line length (product of the stage radices).
 template <int L>
@@ -524,7 +474,21 @@ __global__ __launch_bounds__((Shape<T, L, TM_R>::NT), (Shape<T, L, TM_R>::MINW))
     __shared__ C tw[L];
     __shared__ C st[L * TC];
     __shared__ T kt[TC * NXH];
-    const Tile g = make_tile(AX_X, d, blockIdx.x, TC);
+    // Tiles (ky, kz-block) and (ny - ky, kz-block) read the same kernel values.
+    // Workgroups are dispatched round-robin over the 8 XCDs; ids w and w + 8
+    // (same XCD, consecutive) take the two tiles of one mirror pair, so the
+    // second read of each kernel block hits that XCD's L2.  Pair k = 0 holds
+    // the two self-mirrored rows ky = 0 and ky = ny/2.
+    const int nzb = d.nz / TC;
+    int tile = blockIdx.x;
+    if ((((d.ny / 2) * nzb) & 7) == 0) {
+        const int xcd = blockIdx.x & 7, s8 = blockIdx.x >> 3;
+        const int p = (s8 >> 1) * 8 + xcd, member = s8 & 1;
+        const int k = p / nzb, zb = p - (p / nzb) * nzb;
+        const int ky = member == 0 ? k : (k == 0 ? d.ny / 2 : d.ny - k);
+        tile = ky * nzb + zb;
+    }
+    const Tile g = make_tile(AX_X, d, tile, TC);
     for (int t = threadIdx.x; t < L; t += NT) tw[t] = twg[t];
     for (int e = threadIdx.x; e < L * TC; e += NT) {
         const int i = e / TC, c = e - (e / TC) * TC;
@@ -717,6 +681,7 @@ int inverse_batch_t(conker_ctx *ctx, const conker_grid *g, const void *spec, con
     }
     OpInplace<T> py{twy, d, AX_Y, (C *)tspec, nc, {}, nullptr};
     CK_OK((launch_len<T, +1>(ctx, PK_FFT_INV_Y, TM_C, d.ny, AX_Y, d, dim3(1, (unsigned)nb), py)));
+    if (!maps_a) return CONKER_OK;   // x and y passes only
     OpUnpack<T> pz{twz, d, (const C *)tspec, (T *)maps_a, (T *)maps_b, nc, m0, {}, nullptr};
     CK_OK((launch_len<T, +1>(ctx, PK_FFT_INV_Z, TM_J, d.nz, AX_Z, d, dim3(1, (unsigned)nb), pz)));
     return CONKER_OK;

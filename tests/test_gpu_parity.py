@@ -300,3 +300,67 @@ def test_end_to_end_cube128(ck, ctx, cube128_ref, n, path, prec, tol):
     _say("  W_delta %.3e  W_R %.3e  xi %.3e" % (ed, er, ex))
     assert abs(out["alpha"].item() - ref["alpha"]) <= 1e-15 * ref["alpha"]
     assert ed <= tol and er <= tol and ex <= 10 * tol
+
+
+# ---------------------------------------------------------------------------
+# fused convolution + summation (maps never stored)
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def line512_fields():
+    rng = np.random.default_rng(21)
+    dims = (32, 64, 512)
+    A = rng.normal(size=dims)
+    B = rng.poisson(2.0, size=dims).astype(np.float64)
+    radii = [0.5 * k for k in range(1, 31)]      # 0.5 .. 15 cells: half-integer radii included
+    A32 = A.astype(np.float32).astype(np.float64)
+    B32 = B.astype(np.float32).astype(np.float64)
+    maps_a = oc.convolve_shells(A32, radii)
+    maps_b = oc.convolve_shells(B32, radii)
+    return dims, radii, A32, B32, maps_a, maps_b
+
+
+@pytest.mark.parametrize("prec", ["split_bf16", "f32"])
+@pytest.mark.parametrize("n", [2, 3])
+@pytest.mark.parametrize("ns", [30, 7, 1])
+def test_fused_convolve_contract_vs_oracle(ck, ctx, line512_fields, prec, n, ns):
+    dims, radii, A, B, maps_a, maps_b = line512_fields
+    _say("fused", prec, n, ns)
+    grid = ck.Grid(dims, (0, 0, 0), 1.0)
+    ks, _ = ctx.make_shell_kernels(grid, radii[:ns], torch.float32)
+    Wa, Wb = ctx.convolve_contract(grid, _gpu(A, torch.float32), _gpu(B, torch.float32), ks, n, prec)
+    ra = oc.contract(A, maps_a[:ns], n)
+    rb = oc.contract(B, maps_b[:ns], n)
+    ea, eb = relerr(Wa.cpu().numpy(), ra), relerr(Wb.cpu().numpy(), rb)
+    _say("  err a %.3e b %.3e" % (ea, eb))
+    assert ea <= 1e-5 and eb <= 1e-5
+
+
+def test_fused_single_field_and_unsupported(ck, ctx, line512_fields):
+    dims, radii, A, B, maps_a, maps_b = line512_fields
+    grid = ck.Grid(dims, (0, 0, 0), 1.0)
+    ks, _ = ctx.make_shell_kernels(grid, radii[:5], torch.float32)
+    Wa, Wb = ctx.convolve_contract(grid, _gpu(A, torch.float32), None, ks, 3, "split_bf16")
+    assert Wb is None
+    assert relerr(Wa.cpu().numpy(), oc.contract(A, maps_a[:5], 3)) <= 1e-5
+    with pytest.raises(ck.ConkerError) as e:
+        ctx.convolve_contract(grid, _gpu(A, torch.float32), None, ks, 4, "split_bf16")
+    assert "UNSUPPORTED" in str(e.value)
+    g2 = ck.Grid((32, 32, 256), (0, 0, 0), 1.0)
+    ks2, _ = ctx.make_shell_kernels(g2, radii[:3], torch.float32)
+    with pytest.raises(ck.ConkerError):
+        ctx.convolve_contract(g2, torch.zeros((32, 32, 256), device=DEV), None, ks2, 3, "split_bf16")
+
+
+def test_fused_matches_separate_calls_bitwise_order_free(ck, ctx, line512_fields):
+    """The fused pass and convolve_shells + contract_npt agree to float32 rounding."""
+    dims, radii, A, B, maps_a, maps_b = line512_fields
+    grid = ck.Grid(dims, (0, 0, 0), 1.0)
+    ks, _ = ctx.make_shell_kernels(grid, radii, torch.float32)
+    At, Bt = _gpu(A, torch.float32), _gpu(B, torch.float32)
+    Wa, Wb = ctx.convolve_contract(grid, At, Bt, ks, 3, "split_bf16")
+    ma, mb = ctx.convolve_shells(grid, At, Bt, ks)
+    Sa = ctx.contract_npt(grid, At, ma, 3, "split_bf16")
+    Sb = ctx.contract_npt(grid, Bt, mb, 3, "split_bf16")
+    assert relerr(Wa.cpu().numpy(), Sa.cpu().numpy()) <= 2e-6
+    assert relerr(Wb.cpu().numpy(), Sb.cpu().numpy()) <= 2e-6

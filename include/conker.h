@@ -186,6 +186,53 @@ int conker_convolve_contract(conker_ctx *ctx, const conker_grid *grid, conker_dt
 int conker_ratio(conker_ctx *ctx, const double *d_Wd, const double *d_Wr,
                  const double *d_alpha, int n, int64_t count, double *d_xi);
 
+/* ---- batches of catalogs ---------------------------------------------------
+ * One job = the whole path for one catalog pair (data, randoms) on its own
+ * grid: zero the grids, grid_assign both catalogs, form_delta, convolution and
+ * summation of both fields (conker_convolve_contract when it applies and the
+ * map pointers are NULL, else convolve_shells + contract_npt), and ratio.
+ * Independent catalogs (mocks, survey regions) combine afterwards by adding
+ * numerators and denominators (Eq. ksi3combined).  All pointers are caller
+ * owned device memory; jobs may share grid and map buffers (they run in
+ * order on the context's stream) but not outputs. */
+typedef struct {
+    conker_grid grid;
+    conker_dtype dtype;
+    conker_mmprec prec;
+    int n;                          /* correlation order 2..5 */
+    int n_radii;
+    const void *d_kspec;            /* from conker_make_shell_kernels for this grid */
+    const float *d_data_pos;        /* [n_data][3] */
+    const float *d_data_w;          /* [n_data] or NULL */
+    int64_t n_data;
+    const float *d_rand_pos;        /* [n_rand][3] */
+    const float *d_rand_w;          /* [n_rand] or NULL */
+    int64_t n_rand;
+    void *d_N;                      /* dtype grid: N on exit */
+    void *d_R;                      /* dtype grid: R_raw on exit */
+    void *d_maps_N;                 /* dtype [n_radii][grid] or NULL (fused path) */
+    void *d_maps_R;                 /* likewise, NULL exactly when d_maps_N is */
+    double *d_wsum;                 /* [2]: in-grid weight sums of data, randoms */
+    int64_t *d_n_outside;           /* [2]: rejected tracers of data, randoms */
+    double *d_alpha;                /* [1] */
+    double *d_W_delta;              /* [num_tuples(n_radii, n)] */
+    double *d_W_rand;               /* [num_tuples]: sums on R_raw */
+    double *d_xi;                   /* [num_tuples] */
+} conker_job;
+
+/* conker_batch_plan: validates and stores the job list, then runs it once
+ * (synchronously) so that every workspace buffer, table and kernel attribute
+ * the jobs need exists.  Replaces any earlier batch and captured graph.
+ * conker_batch_run: enqueues every job again, in order.
+ * conker_batch_capture: records the whole batch into one HIP graph (the
+ * context stream must not be the default stream); nothing is allocated or
+ * zeroed with memset nodes inside the capture.
+ * conker_batch_launch: replays the captured graph on the context stream. */
+int conker_batch_plan(conker_ctx *ctx, const conker_job *jobs, int n_jobs);
+int conker_batch_run(conker_ctx *ctx);
+int conker_batch_capture(conker_ctx *ctx);
+int conker_batch_launch(conker_ctx *ctx);
+
 /* Blocks until all work queued on the context's stream has finished. */
 int conker_synchronize(conker_ctx *ctx);
 

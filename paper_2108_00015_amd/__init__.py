@@ -7,7 +7,10 @@ from .api import (  # noqa: F401
     ConkerError,
     Context,
     Grid,
+    Job,
     PRECISIONS,
+    fused_supported,
+    make_job,
     kspec_elems,
     npcf,
     num_tuples,

@@ -44,6 +44,10 @@ SIGNATURES = {
     "conker_ratio": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int,
                                 ct.c_int64, ct.c_void_p]),
     "conker_synchronize": (ct.c_int, [ct.c_void_p]),
+    "conker_batch_plan": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int]),
+    "conker_batch_run": (ct.c_int, [ct.c_void_p]),
+    "conker_batch_capture": (ct.c_int, [ct.c_void_p]),
+    "conker_batch_launch": (ct.c_int, [ct.c_void_p]),
     "conker_profile_enable": (ct.c_int, [ct.c_void_p, ct.c_int]),
     "conker_profile_read": (ct.c_int, [ct.c_void_p, ct.c_int, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_double)]),
     "conker_profile_kind_name": (ct.c_char_p, [ct.c_int]),
@@ -52,6 +56,16 @@ SIGNATURES = {
 
 class ConkerGrid(ct.Structure):
     _fields_ = [("dims", ct.c_int32 * 3), ("origin", ct.c_double * 3), ("cell", ct.c_double)]
+
+
+class ConkerJob(ct.Structure):
+    _fields_ = [("grid", ConkerGrid), ("dtype", ct.c_int), ("prec", ct.c_int), ("n", ct.c_int),
+                ("n_radii", ct.c_int), ("d_kspec", ct.c_void_p),
+                ("d_data_pos", ct.c_void_p), ("d_data_w", ct.c_void_p), ("n_data", ct.c_int64),
+                ("d_rand_pos", ct.c_void_p), ("d_rand_w", ct.c_void_p), ("n_rand", ct.c_int64),
+                ("d_N", ct.c_void_p), ("d_R", ct.c_void_p), ("d_maps_N", ct.c_void_p), ("d_maps_R", ct.c_void_p),
+                ("d_wsum", ct.c_void_p), ("d_n_outside", ct.c_void_p), ("d_alpha", ct.c_void_p),
+                ("d_W_delta", ct.c_void_p), ("d_W_rand", ct.c_void_p), ("d_xi", ct.c_void_p)]
 
 
 _LIB = None

@@ -214,6 +214,22 @@ class Context:
                                                       PRECISIONS[precision], _ptr(out_a), _ptr(out_b)))
         return out_a, out_b
 
+    # ---- batches -----------------------------------------------------------
+    def batch_plan(self, jobs):
+        """Plans (and runs once, synchronously) a list of Job."""
+        self._jobs = list(jobs)   # keep every tensor alive while the batch exists
+        arr = (_lib.ConkerJob * len(self._jobs))(*[j.c() for j in self._jobs])
+        self._check(self.lib.conker_batch_plan(self.h, ct.cast(arr, ct.c_void_p), len(self._jobs)))
+
+    def batch_run(self):
+        self._check(self.lib.conker_batch_run(self.h))
+
+    def batch_capture(self):
+        self._check(self.lib.conker_batch_capture(self.h))
+
+    def batch_launch(self):
+        self._check(self.lib.conker_batch_launch(self.h))
+
     def ratio(self, Wd: torch.Tensor, Wr: torch.Tensor, alpha: torch.Tensor, n: int,
               out: Optional[torch.Tensor] = None) -> torch.Tensor:
         if out is None:
@@ -221,6 +237,79 @@ class Context:
         self._check(self.lib.conker_ratio(self.h, _ptr(Wd), _ptr(Wr), _ptr(alpha), int(n), int(Wd.numel()),
                                           _ptr(out)))
         return out
+
+
+@dataclasses.dataclass
+class Job:
+    """One catalog pair of a batch (see conker_job); holds its tensors alive."""
+    grid: Grid
+    kspec: torch.Tensor
+    n: int
+    precision: str
+    data_pos: torch.Tensor
+    rand_pos: torch.Tensor
+    data_w: Optional[torch.Tensor]
+    rand_w: Optional[torch.Tensor]
+    N: torch.Tensor
+    R: torch.Tensor
+    maps_N: Optional[torch.Tensor]
+    maps_R: Optional[torch.Tensor]
+    wsum: torch.Tensor
+    nout: torch.Tensor
+    alpha: torch.Tensor
+    W_delta: torch.Tensor
+    W_rand: torch.Tensor
+    xi: torch.Tensor
+
+    def c(self) -> _lib.ConkerJob:
+        j = _lib.ConkerJob()
+        j.grid = self.grid.c()
+        j.dtype = _DT[self.N.dtype]
+        j.prec = PRECISIONS[self.precision]
+        j.n = int(self.n)
+        j.n_radii = int(self.kspec.shape[0])
+        j.d_kspec = _ptr(self.kspec)
+        j.d_data_pos, j.d_data_w, j.n_data = _ptr(self.data_pos), _ptr(self.data_w), int(self.data_pos.shape[0])
+        j.d_rand_pos, j.d_rand_w, j.n_rand = _ptr(self.rand_pos), _ptr(self.rand_w), int(self.rand_pos.shape[0])
+        j.d_N, j.d_R = _ptr(self.N), _ptr(self.R)
+        j.d_maps_N, j.d_maps_R = _ptr(self.maps_N), _ptr(self.maps_R)
+        j.d_wsum, j.d_n_outside, j.d_alpha = _ptr(self.wsum), _ptr(self.nout), _ptr(self.alpha)
+        j.d_W_delta, j.d_W_rand, j.d_xi = _ptr(self.W_delta), _ptr(self.W_rand), _ptr(self.xi)
+        return j
+
+
+def make_job(grid: Grid, kspec: torch.Tensor, n: int, precision: str, data_pos: torch.Tensor,
+             rand_pos: torch.Tensor, data_w: Optional[torch.Tensor] = None, rand_w: Optional[torch.Tensor] = None,
+             N: Optional[torch.Tensor] = None, R: Optional[torch.Tensor] = None,
+             maps_N: Optional[torch.Tensor] = None, maps_R: Optional[torch.Tensor] = None,
+             fused: Optional[bool] = None) -> Job:
+    """Builds a Job, allocating what is not given.  Grid and map tensors may be
+    shared between jobs of one batch (they run in order); outputs are per job."""
+    dev, dt = kspec.device, kspec.dtype
+    shape = tuple(int(d) for d in grid.dims)
+    nr = int(kspec.shape[0])
+    if fused is None:
+        fused = fused_supported(grid, nr, n, precision, dt)
+    N = torch.empty(shape, dtype=dt, device=dev) if N is None else N
+    R = torch.empty(shape, dtype=dt, device=dev) if R is None else R
+    if fused:
+        maps_N = maps_R = None
+    elif maps_N is None:
+        maps_N = torch.empty((nr,) + shape, dtype=dt, device=dev)
+        maps_R = torch.empty((nr,) + shape, dtype=dt, device=dev)
+    else:   # shared buffers: at least n_radii * cells elements of the kernel dtype
+        need = nr * grid.n_cells
+        for m in (maps_N, maps_R):
+            if m is None or m.dtype != dt or m.numel() < need or not m.is_contiguous():
+                raise ValueError("maps_N / maps_R must be contiguous %s buffers of >= %d elements" % (dt, need))
+    for t in (N, R):
+        if t.dtype != dt or t.numel() < grid.n_cells or not t.is_contiguous():
+            raise ValueError("N / R must be contiguous %s buffers of >= %d elements" % (dt, grid.n_cells))
+    cnt = num_tuples(nr, n)
+    z = lambda k, t: torch.zeros(k, dtype=t, device=dev)  # noqa: E731
+    return Job(grid, kspec, n, precision, data_pos, rand_pos, data_w, rand_w, N, R, maps_N, maps_R,
+               z(2, torch.float64), z(2, torch.int64), z(1, torch.float64), z(cnt, torch.float64),
+               z(cnt, torch.float64), z(cnt, torch.float64))
 
 
 def fused_supported(grid: Grid, n_radii: int, n: int, precision: str, dtype) -> bool:

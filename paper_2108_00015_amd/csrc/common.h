@@ -39,6 +39,9 @@ struct conker_ctx {
     // per-launch event timing (conker_profile_enable)
     int n_cu = 0;
     bool prof = false;
+    bool capturing = false;            // inside conker_batch_capture
+    std::vector<conker_job> jobs;      // planned batch
+    hipGraphExec_t graph_exec = nullptr;
     struct Rec {
         int kind;
         hipEvent_t e0, e1;
@@ -127,7 +130,8 @@ inline size_t ncells(const conker_grid *g) {
 }
 
 inline bool fft_length_ok(int L) {
-    return L == 32 || L == 64 || L == 128 || L == 256 || L == 512 || L == 1024;
+    return L == 32 || L == 64 || L == 96 || L == 128 || L == 192 || L == 256 || L == 384 || L == 512 ||
+           L == 1024;
 }
 
 // Largest offset component of a shell of radius r cells: ceil(r + 1/2) - 1.

@@ -394,6 +394,185 @@ __global__ __launch_bounds__(NT) void k_mm_bf16(const float *__restrict__ F, con
     }
 }
 
+// ---------------------------------------------------------------------------
+// float32 / split-bf16 matrix-core summation with operands built once per
+// chunk.  A workgroup owns a chunk of cells and a group of up to 16 output
+// tiles (a rectangle of row tiles x column tiles).  For every 64 cells it
+// stages the maps and F in LDS; for every 16 of those it builds each row item
+// (F C_a [C_b]) and column item (C_c [C_d]) of its rectangle once, as three
+// bf16 planes (or one float32 plane), in LDS; then each wave runs the matrix
+// instructions of its (at most two) tiles from LDS.  float32 accumulators are
+// flushed into float64 registers every 128 cells.
+// ---------------------------------------------------------------------------
+struct Group {
+    int rt0, nrt, ct0, nct, t0, nt;
+};
+
+constexpr int V2_NT = 512, V2_WAVES = V2_NT / 64, V2_MAXT = 2, V2_MAXU = 4;
+
+template <int PREC>
+__global__ __launch_bounds__(V2_NT) void k_mm2(const float *__restrict__ F, const float *__restrict__ maps, size_t nc,
+                                              int ns, size_t chunk, const int2 *__restrict__ ritems,
+                                              const int2 *__restrict__ citems, const int2 *__restrict__ tiles,
+                                              const Group *__restrict__ groups, int G, double *__restrict__ partial) {
+    constexpr bool SPLIT = PREC == CONKER_MM_SPLIT_BF16;
+    constexpr int NP = SPLIT ? 3 : 1;                       // operand planes
+    constexpr int EB = SPLIT ? 2 : 4;                       // bytes per operand element
+    extern __shared__ __align__(16) unsigned char smem[];
+    const Group gr = groups[blockIdx.y];
+    float *sm_maps = reinterpret_cast<float *>(smem);       // [ns][64]
+    float *sm_F = sm_maps + ns * 64;                        // [64]
+    unsigned char *sA = reinterpret_cast<unsigned char *>(sm_F + 64);
+    const int na = gr.nrt * 32, nb = gr.nct * 32;
+    unsigned char *sB = sA + (size_t)NP * na * 16 * EB;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int r = lane & 31, h = lane >> 5;
+    // build units of this thread: unit u -> (item, half); items of A first, then B
+    int2 uit[V2_MAXU];
+    int uitem[V2_MAXU];
+#pragma unroll
+    for (int k = 0; k < V2_MAXU; ++k) {
+        const int u = threadIdx.x + k * V2_NT;
+        const int item = u >> 1;
+        uitem[k] = item;
+        if (item < na) uit[k] = ritems[gr.rt0 * 32 + item];
+        else if (item < na + nb) uit[k] = citems[gr.ct0 * 32 + (item - na)];
+        else uit[k] = int2{-3, -1};
+    }
+    // tiles of this wave
+    int ta[V2_MAXT], tb[V2_MAXT];
+    bool tl[V2_MAXT];
+#pragma unroll
+    for (int k = 0; k < V2_MAXT; ++k) {
+        const int lt = w + k * V2_WAVES;
+        tl[k] = lt < gr.nt;
+        const int2 t = tl[k] ? tiles[gr.t0 + lt] : int2{gr.rt0, gr.ct0};
+        ta[k] = (t.x - gr.rt0) * 32 + r;
+        tb[k] = (t.y - gr.ct0) * 32 + r;
+    }
+    floatx16 acc[V2_MAXT];
+    double dacc[V2_MAXT][16];
+#pragma unroll
+    for (int k = 0; k < V2_MAXT; ++k) {
+        acc[k] = floatx16{0};
+#pragma unroll
+        for (int v = 0; v < 16; ++v) dacc[k][v] = 0.0;
+    }
+    const size_t c0 = (size_t)blockIdx.x * chunk;
+    const size_t c1 = c0 + chunk < nc ? c0 + chunk : nc;
+    int since = 0;
+    for (size_t x = c0; x < c1; x += 64) {
+        // stage the maps and F of 64 cells
+        for (int e = threadIdx.x; e < (ns + 1) * 16; e += V2_NT) {
+            const int row = e >> 4, q = e & 15;
+            const float *src = row < ns ? maps + (size_t)row * nc + x + 4 * q : F + x + 4 * q;
+            reinterpret_cast<float4 *>(sm_maps + row * 64)[q] = *reinterpret_cast<const float4 *>(src);
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int sub = 0; sub < 4; ++sub) {
+            // build the operands of 16 cells
+#pragma unroll
+            for (int k = 0; k < V2_MAXU; ++k) {
+                const int2 it = uit[k];
+                if (it.x == -3) continue;
+                const int item = uitem[k];
+                const bool isA = item < na;
+                const int half = (threadIdx.x + k * V2_NT) & 1;
+                const int cb = sub * 16 + half * 8;
+                float v[8];
+                if (it.x == -2) {
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) v[e] = 0.f;
+                } else {
+                    const float4 *pa = reinterpret_cast<const float4 *>(sm_maps + it.x * 64 + cb);
+                    const float4 a0 = pa[0], a1 = pa[1];
+                    v[0] = a0.x; v[1] = a0.y; v[2] = a0.z; v[3] = a0.w;
+                    v[4] = a1.x; v[5] = a1.y; v[6] = a1.z; v[7] = a1.w;
+                    if (it.y >= 0) {
+                        const float4 *pb = reinterpret_cast<const float4 *>(sm_maps + it.y * 64 + cb);
+                        const float4 b0 = pb[0], b1 = pb[1];
+                        v[0] *= b0.x; v[1] *= b0.y; v[2] *= b0.z; v[3] *= b0.w;
+                        v[4] *= b1.x; v[5] *= b1.y; v[6] *= b1.z; v[7] *= b1.w;
+                    }
+                    if (isA) {
+                        const float4 *pf = reinterpret_cast<const float4 *>(sm_F + cb);
+                        const float4 f0 = pf[0], f1 = pf[1];
+                        v[0] *= f0.x; v[1] *= f0.y; v[2] *= f0.z; v[3] *= f0.w;
+                        v[4] *= f1.x; v[5] *= f1.y; v[6] *= f1.z; v[7] *= f1.w;
+                    }
+                }
+                unsigned char *dst = isA ? sA : sB;
+                const int row = isA ? item : item - na;
+                const int nrows = isA ? na : nb;
+                if constexpr (SPLIT) {
+                    bf16x8 hi, mi, lo;
+                    split3(v, hi, mi, lo);
+                    bf16x8 *d = reinterpret_cast<bf16x8 *>(dst);
+                    d[(0 * nrows + row) * 2 + half] = hi;
+                    d[(1 * nrows + row) * 2 + half] = mi;
+                    d[(2 * nrows + row) * 2 + half] = lo;
+                } else {
+                    float4 *d = reinterpret_cast<float4 *>(dst) + (row * 2 + half) * 2;
+                    d[0] = float4{v[0], v[1], v[2], v[3]};
+                    d[1] = float4{v[4], v[5], v[6], v[7]};
+                }
+            }
+            __syncthreads();
+            // matrix instructions of this wave's tiles
+#pragma unroll
+            for (int k = 0; k < V2_MAXT; ++k) {
+                if (!tl[k]) continue;
+                if constexpr (SPLIT) {
+                    const bf16x8 *A = reinterpret_cast<const bf16x8 *>(sA);
+                    const bf16x8 *B = reinterpret_cast<const bf16x8 *>(sB);
+                    const bf16x8 ah = A[(0 * na + ta[k]) * 2 + h], am = A[(1 * na + ta[k]) * 2 + h],
+                                 al = A[(2 * na + ta[k]) * 2 + h];
+                    const bf16x8 bh = B[(0 * nb + tb[k]) * 2 + h], bm = B[(1 * nb + tb[k]) * 2 + h],
+                                 bl = B[(2 * nb + tb[k]) * 2 + h];
+                    acc[k] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc[k], 0, 0, 0);
+                    acc[k] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bm, acc[k], 0, 0, 0);
+                    acc[k] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc[k], 0, 0, 0);
+                    acc[k] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bh, acc[k], 0, 0, 0);
+                    acc[k] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bm, acc[k], 0, 0, 0);
+                    acc[k] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc[k], 0, 0, 0);
+                } else {
+                    const float4 *A = reinterpret_cast<const float4 *>(sA) + (ta[k] * 2 + h) * 2;
+                    const float4 *B = reinterpret_cast<const float4 *>(sB) + (tb[k] * 2 + h) * 2;
+                    const float4 a0 = A[0], a1 = A[1], b0 = B[0], b1 = B[1];
+                    const float av[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+                    const float bv[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
+#pragma unroll
+                    for (int e = 0; e < 8; ++e)
+                        acc[k] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[e], bv[e], acc[k], 0, 0, 0);
+                }
+            }
+            __syncthreads();
+        }
+        if (++since == 2) {
+            since = 0;
+#pragma unroll
+            for (int k = 0; k < V2_MAXT; ++k) {
+#pragma unroll
+                for (int v = 0; v < 16; ++v) dacc[k][v] += (double)acc[k][v];
+                acc[k] = floatx16{0};
+            }
+        }
+    }
+    // write this wave's tiles: lane l, reg v holds (i = 8 (v / 4) + 4 (l / 32) + v % 4, j = l % 32)
+#pragma unroll
+    for (int k = 0; k < V2_MAXT; ++k) {
+        if (!tl[k]) continue;
+        const int tile = gr.t0 + w + k * V2_WAVES;
+        double *out = partial + ((size_t)tile * G + blockIdx.x) * 1024;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int i = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3), j = lane & 31;
+            out[i * 32 + j] = dacc[k][v] + (double)acc[k][v];
+        }
+    }
+}
+
 // Sum the per-workgroup partial tiles in a fixed order, in two levels:
 // slice s of every tile element sums workgroups [s*G/S, (s+1)*G/S), then the
 // S slice sums are added.  full[tile][e].
@@ -522,6 +701,96 @@ int make_plan(conker_ctx *c, int ns, int n, int TS, Plan &pl) {
     return CONKER_OK;
 }
 
+// Plan of the operand-sharing kernel: item tables per row / column tile, the
+// needed tiles (same order as make_plan, so `where` from make_plan applies),
+// and groups of at most 16 tiles whose row and column rectangles fit LDS.
+struct Plan2 {
+    int n_tiles = 0, n_groups = 0, max_lds = 0;
+    Buf *ritems = nullptr, *citems = nullptr, *tiles = nullptr, *groups = nullptr;
+};
+
+int make_plan2(conker_ctx *c, int ns, int n, bool split, Plan2 &p2) {
+    constexpr int TS = 32;
+    const uint64_t key = (((uint64_t)ns << 16) | ((uint64_t)n << 8) | 32u) * 16 + (split ? 8 : 9);
+    Buf &bri = c->tables[key * 4 + 0], &bci = c->tables[key * 4 + 1];
+    Buf &bti = c->tables[key * 4 + 2], &bgr = c->tables[key * 4 + 3];
+    std::vector<std::pair<int, int>> left, right;
+    std::vector<std::vector<int>> pairs;
+    enumerate_tuples(ns, 2, pairs);
+    std::vector<int> pair_index(ns * ns, -1);
+    for (size_t p = 0; p < pairs.size(); ++p) pair_index[pairs[p][0] * ns + pairs[p][1]] = (int)p;
+    if (n == 3 || n == 4)
+        for (int a = 0; a < ns; ++a) right.push_back({a, -1});
+    if (n == 3) {
+        for (int a = 0; a < ns; ++a) left.push_back({a, -1});
+    } else {
+        for (auto &p : pairs) left.push_back({p[0], p[1]});
+        if (n == 5)
+            for (auto &p : pairs) right.push_back({p[0], p[1]});
+    }
+    const int LT = ((int)left.size() + TS - 1) / TS, RT = ((int)right.size() + TS - 1) / TS;
+    std::vector<std::vector<int>> tuples;
+    enumerate_tuples(ns, n - 1, tuples);
+    std::vector<int> tile_id(LT * RT, -1);
+    std::vector<std::pair<int, int>> tiles;
+    for (auto &u : tuples) {
+        int li, ri;
+        if (n == 3) { li = u[0]; ri = u[1]; }
+        else if (n == 4) { li = pair_index[u[0] * ns + u[1]]; ri = u[2]; }
+        else { li = pair_index[u[0] * ns + u[1]]; ri = pair_index[u[2] * ns + u[3]]; }
+        int &id = tile_id[(li / TS) * RT + ri / TS];
+        if (id < 0) {
+            id = (int)tiles.size();
+            tiles.push_back({li / TS, ri / TS});
+        }
+    }
+    const int eb = split ? 6 : 4;   // LDS bytes per operand element over all planes
+    auto lds_of = [&](int nrt, int nct) { return (ns * 64 + 64) * 4 + (nrt + nct) * TS * 16 * eb; };
+    std::vector<Group> groups;
+    int i = 0;
+    p2.max_lds = 0;
+    while (i < (int)tiles.size()) {
+        Group g{tiles[i].first, 1, tiles[i].second, 1, i, 1};
+        int rlo = tiles[i].first, rhi = rlo, clo = tiles[i].second, chi = clo;
+        int j = i + 1;
+        while (j < (int)tiles.size() && j - i < V2_WAVES * V2_MAXT) {
+            const int nrlo = std::min(rlo, tiles[j].first), nrhi = std::max(rhi, tiles[j].first);
+            const int nclo = std::min(clo, tiles[j].second), nchi = std::max(chi, tiles[j].second);
+            const int nrt = nrhi - nrlo + 1, nct = nchi - nclo + 1;
+            if ((nrt + nct) * TS * 2 > V2_NT * V2_MAXU || lds_of(nrt, nct) > 96 * 1024) break;
+            rlo = nrlo; rhi = nrhi; clo = nclo; chi = nchi;
+            ++j;
+        }
+        g.rt0 = rlo; g.nrt = rhi - rlo + 1; g.ct0 = clo; g.nct = chi - clo + 1; g.t0 = i; g.nt = j - i;
+        p2.max_lds = std::max(p2.max_lds, lds_of(g.nrt, g.nct));
+        groups.push_back(g);
+        i = j;
+    }
+    p2.n_tiles = (int)tiles.size();
+    p2.n_groups = (int)groups.size();
+    if (!bri.p) {
+        std::vector<int2> hr((size_t)LT * TS), hc((size_t)RT * TS), ht(tiles.size());
+        for (int k = 0; k < LT * TS; ++k)
+            hr[k] = k < (int)left.size() ? int2{left[k].first, left[k].second} : int2{-2, -1};
+        for (int k = 0; k < RT * TS; ++k)
+            hc[k] = k < (int)right.size() ? int2{right[k].first, right[k].second} : int2{-2, -1};
+        for (size_t k = 0; k < tiles.size(); ++k) ht[k] = int2{tiles[k].first, tiles[k].second};
+        CK_OK(ws_reserve(c, bri, hr.size() * sizeof(int2)));
+        CK_OK(ws_reserve(c, bci, hc.size() * sizeof(int2)));
+        CK_OK(ws_reserve(c, bti, ht.size() * sizeof(int2)));
+        CK_OK(ws_reserve(c, bgr, groups.size() * sizeof(Group)));
+        CK_HIP(c, hipMemcpy(bri.p, hr.data(), hr.size() * sizeof(int2), hipMemcpyHostToDevice));
+        CK_HIP(c, hipMemcpy(bci.p, hc.data(), hc.size() * sizeof(int2), hipMemcpyHostToDevice));
+        CK_HIP(c, hipMemcpy(bti.p, ht.data(), ht.size() * sizeof(int2), hipMemcpyHostToDevice));
+        CK_HIP(c, hipMemcpy(bgr.p, groups.data(), groups.size() * sizeof(Group), hipMemcpyHostToDevice));
+    }
+    p2.ritems = &bri;
+    p2.citems = &bci;
+    p2.tiles = &bti;
+    p2.groups = &bgr;
+    return CONKER_OK;
+}
+
 template <typename T>
 int contract_dot(conker_ctx *c, const T *F, const T *maps, size_t nc, int ns, double *W) {
     constexpr int V = std::is_same<T, float>::value ? 4 : 2;
@@ -588,6 +857,57 @@ extern "C" int conker_contract_npt(conker_ctx *c, const conker_grid *g, conker_d
     const int TS = prec == CONKER_MM_F64 ? 16 : 32;
     Plan pl;
     CK_OK(make_plan(c, ns, n, TS, pl));
+    if (prec != CONKER_MM_F64) {
+        // operand-sharing matrix-core kernel
+        Plan2 p2;
+        CK_OK(make_plan2(c, ns, n, prec == CONKER_MM_SPLIT_BF16, p2));
+        if (nc % 64) return fail(c, CONKER_EUNSUPPORTED, "cell count must be a multiple of 64");
+        size_t G = std::max<size_t>(1, std::min<size_t>(nc / 512, 1024 / (size_t)p2.n_groups));
+        size_t chunk = (nc + G - 1) / G;
+        chunk = (chunk + 63) / 64 * 64;
+        G = (nc + chunk - 1) / chunk;
+        const int te = 1024;
+        CK_OK(ws_reserve(c, c->partial, (size_t)p2.n_tiles * G * te * sizeof(double)));
+        CK_OK(ws_reserve(c, c->full, (size_t)p2.n_tiles * te * (RED_S + 1) * sizeof(double)));
+        double *part = (double *)c->partial.p;
+        {
+            ProfScope ps(c, PK_CONTRACT_MM);
+            dim3 grid((unsigned)G, (unsigned)p2.n_groups);
+            static bool attr_set = false;
+            if (!attr_set) {
+                CK_HIP(c, hipFuncSetAttribute((const void *)k_mm2<CONKER_MM_SPLIT_BF16>,
+                                              hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024));
+                CK_HIP(c, hipFuncSetAttribute((const void *)k_mm2<CONKER_MM_F32>,
+                                              hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024));
+                attr_set = true;
+            }
+            if (prec == CONKER_MM_SPLIT_BF16)
+                hipLaunchKernelGGL(k_mm2<CONKER_MM_SPLIT_BF16>, grid, dim3(V2_NT), p2.max_lds, c->stream,
+                                   (const float *)F, (const float *)maps, nc, ns, chunk,
+                                   (const int2 *)p2.ritems->p, (const int2 *)p2.citems->p,
+                                   (const int2 *)p2.tiles->p, (const Group *)p2.groups->p, (int)G, part);
+            else
+                hipLaunchKernelGGL(k_mm2<CONKER_MM_F32>, grid, dim3(V2_NT), p2.max_lds, c->stream, (const float *)F,
+                                   (const float *)maps, nc, ns, chunk, (const int2 *)p2.ritems->p,
+                                   (const int2 *)p2.citems->p, (const int2 *)p2.tiles->p,
+                                   (const Group *)p2.groups->p, (int)G, part);
+            CK_LAUNCH(c);
+        }
+        ProfScope ps(c, PK_CONTRACT_REDUCE);
+        const size_t tot = (size_t)p2.n_tiles * te;
+        double *full = (double *)c->full.p;
+        double *slices = full + tot;
+        hipLaunchKernelGGL(k_tile_reduce1, dim3((unsigned)((tot * RED_S + 255) / 256)), dim3(256), 0, c->stream,
+                           part, p2.n_tiles, (int)G, te, slices);
+        CK_LAUNCH(c);
+        hipLaunchKernelGGL(k_tile_reduce2, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, c->stream, slices,
+                           p2.n_tiles, te, full);
+        CK_LAUNCH(c);
+        hipLaunchKernelGGL(k_gather, dim3((unsigned)((pl.count + 255) / 256)), dim3(256), 0, c->stream,
+                           (const double *)full, (const int *)pl.where->p, pl.count, W);
+        CK_LAUNCH(c);
+        return CONKER_OK;
+    }
     const int NBW = pl.n_tiles == 1 ? 1 : (prec == CONKER_MM_F64 ? 4 : 2);
     const int groups = (pl.n_tiles + NBW - 1) / NBW;
     // cell chunks: aim for ~4096 workgroups in total, chunk a multiple of 4 waves x 16 cells

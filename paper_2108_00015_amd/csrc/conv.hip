@@ -14,6 +14,11 @@ namespace {
 // memory (plus what this context already holds for them).
 int batch_radii(conker_ctx *c, size_t per_radius_bytes, int n_radii, size_t fixed_bytes) {
     int b = n_radii;
+    if (c->capturing) {   // inside a graph capture: use the batch buffer as planned
+        const size_t fit = per_radius_bytes ? c->tspec.bytes / per_radius_bytes : (size_t)n_radii;
+        b = (int)(fit < 1 ? 1 : (fit < (size_t)n_radii ? fit : (size_t)n_radii));
+        return b;
+    }
     size_t fr = 0, tot = 0;
     if (hipMemGetInfo(&fr, &tot) == hipSuccess) {
         const size_t budget = fr / 2 + c->tspec.bytes;

@@ -24,6 +24,8 @@ int fail(conker_ctx *ctx, int code, const char *fmt, ...) {
 
 int ws_reserve(conker_ctx *ctx, Buf &b, size_t bytes) {
     if (bytes <= b.bytes) return CONKER_OK;
+    if (ctx->capturing)
+        return fail(ctx, CONKER_ENOMEM, "workspace would grow to %zu bytes inside a graph capture", bytes);
     size_t next = ctx->ws_bytes - b.bytes + bytes;
     if (ctx->ws_cap && next > ctx->ws_cap)
         return fail(ctx, CONKER_ENOMEM, "workspace of %zu bytes needed, cap is %zu", next, ctx->ws_cap);
@@ -108,7 +110,7 @@ int check_grid(conker_ctx *ctx, const conker_grid *g, bool need_fft) {
         if (g->dims[k] <= 0) return fail(ctx, CONKER_EINVAL, "grid dims must be positive");
         if (need_fft && !fft_length_ok(g->dims[k]))
             return fail(ctx, CONKER_EUNSUPPORTED,
-                        "axis length %d not supported (32, 64, 128, 256, 512 or 1024)", g->dims[k]);
+                        "axis length %d not supported (32, 64, 96, 128, 192, 256, 384, 512 or 1024)", g->dims[k]);
     }
     if ((double)g->dims[0] * g->dims[1] * g->dims[2] > (double)(1u << 30))
         return fail(ctx, CONKER_EUNSUPPORTED, "grid larger than 2^30 cells");
@@ -218,6 +220,7 @@ extern "C" void conker_destroy(conker_ctx *c) {
     for (auto &kv : c->tw32) rel(kv.second);
     for (auto &kv : c->tw64) rel(kv.second);
     for (auto &kv : c->tables) rel(kv.second);
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
     recycle_records(c);
     for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
     c->pool.clear();

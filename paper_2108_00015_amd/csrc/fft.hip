@@ -36,6 +36,11 @@ template <> struct Plan<128>  { static constexpr int n = 3; static constexpr int
 template <> struct Plan<256>  { static constexpr int n = 3; static constexpr int r[4] = {8, 8, 4, 1}; };
 template <> struct Plan<512>  { static constexpr int n = 3; static constexpr int r[4] = {8, 8, 8, 1}; };
 template <> struct Plan<1024> { static constexpr int n = 4; static constexpr int r[4] = {8, 8, 4, 4}; };
+// lengths with a factor 3: the radix-3 stage comes last, so that every earlier
+// stage has a power-of-two span
+template <> struct Plan<96>   { static constexpr int n = 3; static constexpr int r[4] = {8, 4, 3, 1}; };
+template <> struct Plan<192>  { static constexpr int n = 3; static constexpr int r[4] = {8, 8, 3, 1}; };
+template <> struct Plan<384>  { static constexpr int n = 4; static constexpr int r[4] = {8, 8, 2, 3}; };
 
 template <int L, int S>
 constexpr int stage_ns() {   // product of radices before stage S
@@ -58,7 +63,10 @@ template <typename T, int L, int MODE>
 struct Shape {
     static constexpr bool f64 = std::is_same<T, double>::value;
     static constexpr int TC_C = f64 ? (L >= 1024 ? 4 : 8) : (L >= 1024 ? 8 : 16);
-    static constexpr int TC = MODE == TM_J ? (f64 ? 2048 : 4096) / L : (MODE == TM_W ? 2 * TC_C : TC_C);
+    static constexpr int TCJ0 = (f64 ? 2048 : 4096) / L;   // lines per z tile: a power of two
+    static constexpr int TCJ = TCJ0 >= 256 ? 256 : TCJ0 >= 128 ? 128 : TCJ0 >= 64 ? 64 : TCJ0 >= 32 ? 32
+                             : TCJ0 >= 16 ? 16 : TCJ0 >= 8 ? 8 : TCJ0 >= 4 ? 4 : TCJ0 >= 2 ? 2 : 1;
+    static constexpr int TC = MODE == TM_J ? TCJ : (MODE == TM_W ? 2 * TC_C : TC_C);
     static constexpr int PAD = MODE == TM_J ? 0 : (f64 ? 0 : 2);
     static constexpr int NB0 = (L / 8) * TC;   // first-stage butterflies per tile
     static constexpr int NT =
@@ -104,6 +112,7 @@ __device__ __forceinline__ void fft_stage(cplx<T> *lds, const cplx<T> *tw, Op &o
     constexpr int NB = LR * TC;
     constexpr int PER = (NB + NT - 1) / NT;
     constexpr int TWS = L / (NSV * R);
+    static_assert((NSV & (NSV - 1)) == 0, "stages before the last have power-of-two spans");
     C v[PER][R];
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
@@ -538,6 +547,9 @@ int tc_of_mode(int mode) {
 template <typename T>
 int tc_of(int L, int mode) {
     switch (L) {
+        case 96: return tc_of_mode<T, 96>(mode);
+        case 192: return tc_of_mode<T, 192>(mode);
+        case 384: return tc_of_mode<T, 384>(mode);
         case 32: return tc_of_mode<T, 32>(mode);
         case 64: return tc_of_mode<T, 64>(mode);
         case 128: return tc_of_mode<T, 128>(mode);
@@ -579,8 +591,11 @@ int launch_len_mode(conker_ctx *ctx, int L, int axis, const Dims &d, dim3 gy, Op
     switch (L) {
         case 32: return go(std::integral_constant<int, 32>());
         case 64: return go(std::integral_constant<int, 64>());
+        case 96: return go(std::integral_constant<int, 96>());
         case 128: return go(std::integral_constant<int, 128>());
+        case 192: return go(std::integral_constant<int, 192>());
         case 256: return go(std::integral_constant<int, 256>());
+        case 384: return go(std::integral_constant<int, 384>());
         case 512: return go(std::integral_constant<int, 512>());
         case 1024: return go(std::integral_constant<int, 1024>());
         default: return fail(ctx, CONKER_EUNSUPPORTED, "FFT length %d", L);
@@ -660,6 +675,9 @@ int inverse_batch_t(conker_ctx *ctx, const conker_grid *g, const void *spec, con
         };
         int st = CONKER_OK;
         switch (d.nx) {
+            case 96: st = go(std::integral_constant<int, 96>()); break;
+            case 192: st = go(std::integral_constant<int, 192>()); break;
+            case 384: st = go(std::integral_constant<int, 384>()); break;
             case 32: st = go(std::integral_constant<int, 32>()); break;
             case 64: st = go(std::integral_constant<int, 64>()); break;
             case 128: st = go(std::integral_constant<int, 128>()); break;

@@ -34,6 +34,17 @@ __device__ __forceinline__ void dft(C *v) {
         C a = v[0];
         v[0] = cadd(a, v[1]);
         v[1] = csub(a, v[1]);
+    } else if constexpr (R == 3) {
+        // w = exp(DIR 2 pi i / 3) = -1/2 + DIR i sqrt(3)/2
+        using T = decltype(v[0].x);
+        const T s3 = (T)0.86602540378443864676 * (T)DIR;   // DIR sqrt(3)/2
+        const C t = cadd(v[1], v[2]);
+        const C d = csub(v[1], v[2]);
+        const C m = C{v[0].x - (T)0.5 * t.x, v[0].y - (T)0.5 * t.y};
+        v[0] = cadd(v[0], t);
+        // X1 = m + i s3 d, X2 = m - i s3 d
+        v[1] = C{m.x - s3 * d.y, m.y + s3 * d.x};
+        v[2] = C{m.x + s3 * d.y, m.y - s3 * d.x};
     } else if constexpr (R == 4) {
         C a0 = cadd(v[0], v[2]), a1 = csub(v[0], v[2]);
         C a2 = cadd(v[1], v[3]), a3 = mul_di<DIR>(csub(v[1], v[3]));

@@ -14,4 +14,7 @@ from .catalogs import (  # noqa: F401
     lognormal_weights,
     workload,
     WORKLOADS,
+    mock_catalog,
+    mock_sizes,
+    MOCK_RADII,
 )

@@ -255,6 +255,19 @@ def workload(name: str) -> Workload:
     return WORKLOADS[name]
 
 
+def mock_catalog(j: int, grid: int, n: int, scale: float = 1.0, cell: float = 5.0):
+    """Mock j of a batch: periodic box of side cell * grid, n Neyman-Scott points
+    (n / 50 parents, sigma 10) and 10 n uniform randoms, both times `scale`."""
+    L = cell * grid
+    nd = max(1, int(n * scale))
+    d = neyman_scott_box(nd, max(1, nd // 50), 10.0, 0.0, L, 4000 + 2 * j, True)
+    r = uniform_box(10 * nd, 0.0, L, 4001 + 2 * j, True)
+    return Catalog(d), Catalog(r)
+
+
+MOCK_RADII = tuple(float(10 + 5 * i) for i in range(16))   # 10 .. 85, 16 shells
+
+
 def mock_sizes(n_mocks: int = 64, seed: int = 400) -> Sequence[tuple]:
     """Grid sizes and catalog sizes of a batch of independent periodic mocks."""
     rng = np.random.default_rng(seed)

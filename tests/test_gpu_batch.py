@@ -1,0 +1,150 @@
+"""Batches of independent mocks through conker_batch_*: the eager planning pass,
+eager re-runs and HIP-graph replays agree with each other and with the FP64
+oracle (Eq. ksi3combined is then a sum over jobs).  Grids of 96, 128 and 192
+cells per side exercise the radix-3 FFT lengths beside the powers of two.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import conker as oc  # noqa: E402
+import synth  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+CELL = 5.0
+RADII = synth.MOCK_RADII          # 16 shells, 10 .. 85
+SAMPLE = (0, 7, 15)               # shells the oracle convolves
+MOCKS = ((96, 20_000), (128, 30_000), (192, 40_000), (96, 10_000))
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _rel(got, ref):
+    return float(np.abs(np.asarray(got) - np.asarray(ref)).max() / max(1e-300, np.abs(ref).max()))
+
+
+@pytest.fixture(scope="module")
+def mocks():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return [synth.mock_catalog(j, g, n, cell=CELL) for j, (g, n) in enumerate(MOCKS)]
+
+
+@pytest.fixture(scope="module")
+def oracle_first(mocks):
+    """FP64 oracle for mock 0 (96^3): alpha, and W_n over the tuples of SAMPLE."""
+    g = MOCKS[0][0]
+    d, r = mocks[0]
+    dims = (g, g, g)
+    D, wd, _ = oc.histogram(d.pos, d.w, (0.0, 0.0, 0.0), CELL, dims)
+    R, wr, _ = oc.histogram(r.pos, r.w, (0.0, 0.0, 0.0), CELL, dims)
+    N, alpha = oc.density_deviation(D, R, wd, wr)
+    rc = [RADII[m] / CELL for m in SAMPLE]
+    mN, mR = oc.convolve_shells(N, rc), oc.convolve_shells(R, rc)
+    ref = {}
+    for n in (2, 3):
+        loc = oc.radius_tuples(len(SAMPLE), n)
+        tl = [tuple(SAMPLE[i] for i in t) for t in loc]
+        ref[n] = (tl, oc.contract(N, mN, n, loc), oc.contract(R, mR, n, loc))
+    return alpha, ref
+
+
+def _pick(W, n, tuples):
+    idx = {t: i for i, t in enumerate(oc.radius_tuples(len(RADII), n))}
+    return np.array([W[idx[t]] for t in tuples])
+
+
+def _build(ck, ctx, mocks, n, dtype, prec):
+    dev = "cuda:0"
+    kspecs = {}
+    gmax = max(g for g, _ in MOCKS)
+    ncmax = gmax ** 3
+    N = torch.empty(ncmax, dtype=dtype, device=dev)
+    R = torch.empty(ncmax, dtype=dtype, device=dev)
+    mN = torch.empty(len(RADII) * ncmax, dtype=dtype, device=dev)
+    mR = torch.empty(len(RADII) * ncmax, dtype=dtype, device=dev)
+    jobs = []
+    for (g, _), (d, r) in zip(MOCKS, mocks):
+        grid = ck.Grid((g, g, g), (0.0, 0.0, 0.0), CELL)
+        if g not in kspecs:
+            kspecs[g] = ctx.make_shell_kernels(grid, RADII, dtype)[0]
+        dp = torch.from_numpy(d.pos).to(dev)
+        rp = torch.from_numpy(r.pos).to(dev)
+        jobs.append(ck.make_job(grid, kspecs[g], n, prec, dp, rp, N=N, R=R, maps_N=mN, maps_R=mR, fused=False))
+    return jobs
+
+
+def _outs(jobs):
+    return [np.concatenate([j.W_delta.cpu().numpy(), j.W_rand.cpu().numpy(), j.xi.cpu().numpy(),
+                            j.alpha.cpu().numpy()]) for j in jobs]
+
+
+@pytest.mark.parametrize("path", ["fp64", "mixed"])
+@pytest.mark.parametrize("n", [3, 2])
+def test_batch_eager_graph_oracle(mocks, oracle_first, path, n):
+    import paper_2108_00015_amd as ck
+    dtype = torch.float64 if path == "fp64" else torch.float32
+    prec = "f64" if path == "fp64" else "split_bf16"
+    tol_self = 1e-12 if path == "fp64" else 1e-5     # atomics reorder the scatter sums
+    tol_ref = 1e-12 if path == "fp64" else 1e-5
+    _say("batch", path, "n=%d" % n, [g for g, _ in MOCKS])
+    s = torch.cuda.Stream()
+    ctx = ck.Context(0, stream=s)
+    jobs = _build(ck, ctx, mocks, n, dtype, prec)
+    torch.cuda.synchronize()
+    ctx.batch_plan(jobs)
+    first = _outs(jobs)
+    for j in jobs:
+        j.xi.zero_()
+    torch.cuda.synchronize()
+    ctx.batch_run()
+    ctx.synchronize()
+    again = _outs(jobs)
+    ctx.batch_capture()
+    graphs = []
+    for rep in range(3):
+        for j in jobs:               # eager work between replays; the graph must refill everything
+            j.W_delta.fill_(7.0)
+            j.W_rand.fill_(-3.0)
+            j.xi.fill_(1.0)
+        torch.cuda.synchronize()
+        ctx.batch_launch()
+        ctx.synchronize()
+        graphs.append(_outs(jobs))
+    for k in range(len(jobs)):
+        for o in [again[k]] + [gr[k] for gr in graphs]:
+            assert _rel(o, first[k]) <= tol_self, (k, _rel(o, first[k]))
+    # oracle on mock 0
+    alpha, ref = oracle_first
+    tl, rd, rr = ref[n]
+    j0 = jobs[0]
+    gd = _pick(graphs[-1][0][:len(j0.W_delta)], n, tl)
+    gr_ = _pick(graphs[-1][0][len(j0.W_delta):2 * len(j0.W_delta)], n, tl)
+    ed, er = _rel(gd, rd), _rel(gr_, rr)
+    _say("  oracle mock0: W_delta %.3e W_R %.3e" % (ed, er))
+    assert ed <= tol_ref and er <= tol_ref
+    assert abs(j0.alpha.item() - alpha) <= 1e-13 * alpha
+    ctx.close()
+
+
+def test_batch_rejects_bad_jobs(mocks):
+    import paper_2108_00015_amd as ck
+    ctx = ck.Context(0, stream=torch.cuda.Stream())
+    jobs = _build(ck, ctx, mocks[:1], 3, torch.float32, "split_bf16")
+    jobs[0].n = 6
+    with pytest.raises(ck.ConkerError):
+        ctx.batch_plan(jobs)
+    jobs[0].n = 3
+    jobs[0].maps_N = None
+    with pytest.raises(ck.ConkerError):
+        ctx.batch_plan(jobs)
+    with pytest.raises(ck.ConkerError):
+        ctx.batch_launch()
+    ctx.close()

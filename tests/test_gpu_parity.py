@@ -132,7 +132,7 @@ def test_form_delta(ck, ctx, dt, tol):
 # kernels
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("dims", [(32, 32, 32), (64, 32, 128), (128, 128, 128)])
+@pytest.mark.parametrize("dims", [(32, 32, 32), (64, 32, 128), (128, 128, 128), (96, 192, 96)])
 @pytest.mark.parametrize("dt", ["f64", "f32"])
 def test_shell_kernel_spectra(ck, ctx, dims, dt):
     cell = 2.0
@@ -163,7 +163,7 @@ def test_shell_radius_errors(ck, ctx):
         ctx.make_shell_kernels(grid, [0.4], torch.float64)
     assert "ERANGE" in str(e.value)
     with pytest.raises(ck.ConkerError) as e:
-        ctx.make_shell_kernels(ck.Grid((96, 96, 96), (0, 0, 0), 1.0), [3.0], torch.float64)
+        ctx.make_shell_kernels(ck.Grid((80, 80, 80), (0, 0, 0), 1.0), [3.0], torch.float64)
     assert "UNSUPPORTED" in str(e.value)
 
 
@@ -171,7 +171,8 @@ def test_shell_radius_errors(ck, ctx):
 # convolution
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("dims", [(32, 32, 32), (32, 64, 128), (128, 64, 32), (64, 64, 64)])
+@pytest.mark.parametrize("dims", [(32, 32, 32), (32, 64, 128), (128, 64, 32), (64, 64, 64), (96, 96, 96),
+                                  (192, 96, 96), (96, 192, 384)])
 @pytest.mark.parametrize("dt,tol", [("f64", 1e-12), ("f32", 3e-6)])
 def test_convolve_shells_vs_oracle(ck, ctx, dims, dt, tol):
     rng = np.random.default_rng(11)
@@ -240,6 +241,15 @@ CONTRACT_CASES = [
     ("split_bf16", 3, 40, (32, 32, 32)),
     ("split_bf16", 4, 9, (32, 32, 32)),
     ("split_bf16", 5, 6, (32, 32, 32)),
+    # operand-sharing kernel with several tiles and tile groups
+    ("split_bf16", 4, 30, (32, 32, 32)),
+    ("f32", 4, 30, (32, 32, 32)),
+    ("split_bf16", 5, 20, (32, 32, 32)),
+    ("f32", 5, 20, (32, 32, 32)),
+    ("split_bf16", 5, 30, (32, 32, 32)),
+    ("split_bf16", 3, 64, (32, 32, 32)),
+    ("f64", 4, 30, (32, 32, 32)),
+    ("f64", 5, 20, (32, 32, 32)),
 ]
 
 

@@ -180,6 +180,28 @@ int conker_convolve_contract(conker_ctx *ctx, const conker_grid *grid, conker_dt
                              const void *d_field_a, const void *d_field_b, const void *d_kspec,
                              int n_radii, int n, conker_mmprec prec, double *d_W_a, double *d_W_b);
 
+/* ---- equidistant configurations (Sec. 2.5, Eq. ksinDiag) -------------------
+ * The diagonal entries a_1 = ... = a_{n-1} = m of Eq. ksin_delta, for every
+ * order n = 2 .. n_max at once:
+ *   out[(n - 2) * n_radii + m] = sum over all cells x of field(x) * C_m(x)^(n-1)
+ * with C_m the shell map of radius m (conker_convolve_shells).  n_max 2..5.
+ * Outputs are float64 device arrays of (n_max - 1) * n_radii, overwritten.
+ *
+ * conker_contract_diag: from stored maps, d_maps dtype [n_radii][nx][ny][nz].
+ * Any dtype (F32 products are formed in float32 and summed in float64). */
+int conker_contract_diag(conker_ctx *ctx, const conker_grid *grid, conker_dtype dtype,
+                         const void *d_field, const void *d_maps, int n_radii, int n_max,
+                         double *d_out);
+
+/* conker_convolve_diag: the same sums for field_a (and field_b) straight from
+ * the kernel bank, without storing any map: the last inverse FFT pass of each
+ * radius feeds the sums instead of memory, so the device holds only the
+ * spectra of one radius batch.  Every supported grid and both dtypes.
+ *   d_field_b and d_out_b: both given or both NULL. */
+int conker_convolve_diag(conker_ctx *ctx, const conker_grid *grid, conker_dtype dtype,
+                         const void *d_field_a, const void *d_field_b, const void *d_kspec,
+                         int n_radii, int n_max, double *d_out_a, double *d_out_b);
+
 /* conker_ratio: the estimator xi = W_delta / (alpha^n W_rand) in float64
  * (Eq. ksin_delta with B_i built on R = alpha R_raw).  All pointers are
  * device float64; d_alpha is a scalar. */

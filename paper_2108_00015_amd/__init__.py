@@ -11,6 +11,7 @@ from .api import (  # noqa: F401
     PRECISIONS,
     fused_supported,
     make_job,
+    npcf_diag,
     kspec_elems,
     npcf,
     num_tuples,

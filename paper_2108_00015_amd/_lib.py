@@ -41,6 +41,10 @@ SIGNATURES = {
     "conker_convolve_contract": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_void_p,
                                             ct.c_void_p, ct.c_int, ct.c_int, ct.c_int, ct.c_void_p,
                                             ct.c_void_p]),
+    "conker_contract_diag": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_void_p,
+                                        ct.c_int, ct.c_int, ct.c_void_p]),
+    "conker_convolve_diag": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_void_p,
+                                        ct.c_void_p, ct.c_int, ct.c_int, ct.c_void_p, ct.c_void_p]),
     "conker_ratio": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int,
                                 ct.c_int64, ct.c_void_p]),
     "conker_synchronize": (ct.c_int, [ct.c_void_p]),

@@ -214,6 +214,32 @@ class Context:
                                                       PRECISIONS[precision], _ptr(out_a), _ptr(out_b)))
         return out_a, out_b
 
+    # ---- equidistant (diagonal) sums, Eq. ksinDiag ---------------------------
+    def contract_diag(self, grid: Grid, field: torch.Tensor, maps: torch.Tensor, n_max: int) -> torch.Tensor:
+        """[n_max - 1, n_radii] float64: row n - 2 holds sum_x field * maps[m]^(n-1)."""
+        nr = int(maps.shape[0])
+        if maps.dtype != field.dtype or maps.numel() != nr * grid.n_cells or field.numel() != grid.n_cells:
+            raise ValueError("field / maps shape or dtype mismatch")
+        out = torch.empty((n_max - 1, nr), dtype=torch.float64, device=field.device)
+        g = grid.c()
+        self._check(self.lib.conker_contract_diag(self.h, ct.byref(g), _DT[field.dtype], _ptr(field), _ptr(maps),
+                                                  nr, int(n_max), _ptr(out)))
+        return out
+
+    def convolve_diag(self, grid: Grid, field_a: torch.Tensor, field_b: Optional[torch.Tensor],
+                      kspec: torch.Tensor, n_max: int):
+        """Diagonal sums of both fields without storing maps: (out_a, out_b), each [n_max - 1, n_radii]."""
+        nr = int(kspec.shape[0])
+        dt = field_a.dtype
+        if kspec.dtype != dt or (field_b is not None and field_b.dtype != dt):
+            raise ValueError("dtype mismatch")
+        oa = torch.empty((n_max - 1, nr), dtype=torch.float64, device=field_a.device)
+        ob = torch.empty_like(oa) if field_b is not None else None
+        g = grid.c()
+        self._check(self.lib.conker_convolve_diag(self.h, ct.byref(g), _DT[dt], _ptr(field_a), _ptr(field_b),
+                                                  _ptr(kspec), nr, int(n_max), _ptr(oa), _ptr(ob)))
+        return oa, ob
+
     # ---- batches -----------------------------------------------------------
     def batch_plan(self, jobs):
         """Plans (and runs once, synchronously) a list of Job."""
@@ -316,6 +342,30 @@ def fused_supported(grid: Grid, n_radii: int, n: int, precision: str, dtype) -> 
     """Whether conker_convolve_contract handles this case (else the two separate calls are used)."""
     return (dtype == torch.float32 and precision in ("f32", "split_bf16") and n in (2, 3)
             and int(grid.dims[2]) == 512 and 1 <= n_radii <= 30)
+
+
+def npcf_diag(ctx: Context, grid: Grid, data_pos: torch.Tensor, rand_pos: torch.Tensor, kspec: torch.Tensor,
+              n_max: int, data_w: Optional[torch.Tensor] = None, rand_w: Optional[torch.Tensor] = None,
+              dtype=torch.float64) -> dict:
+    """Equidistant n-point functions (Eq. ksinDiag) for n = 2 .. n_max without storing maps.
+
+    Returns xi, W_delta and W_rand_raw as [n_max - 1, n_radii] float64 (row n - 2 is order n),
+    and alpha."""
+    dev = data_pos.device
+    shape = tuple(int(d) for d in grid.dims)
+    N = torch.zeros(shape, dtype=dtype, device=dev)
+    R = torch.zeros(shape, dtype=dtype, device=dev)
+    wsum = torch.zeros(2, dtype=torch.float64, device=dev)
+    nout = torch.zeros(2, dtype=torch.int64, device=dev)
+    alpha = torch.empty(1, dtype=torch.float64, device=dev)
+    ctx.grid_assign(grid, data_pos, data_w, N, wsum[0:1], nout[0:1])
+    ctx.grid_assign(grid, rand_pos, rand_w, R, wsum[1:2], nout[1:2])
+    ctx.form_delta(grid, N, R, wsum[0:1], wsum[1:2], alpha)
+    Wd, Wr = ctx.convolve_diag(grid, N, R, kspec, n_max)
+    xi = torch.empty_like(Wd)
+    for k in range(n_max - 1):
+        ctx.ratio(Wd[k], Wr[k], alpha, k + 2, out=xi[k])
+    return dict(xi=xi, W_delta=Wd, W_rand_raw=Wr, alpha=alpha, n_outside=nout)
 
 
 def npcf(ctx: Context, grid: Grid, data_pos: torch.Tensor, rand_pos: torch.Tensor, kspec: torch.Tensor,

@@ -72,6 +72,9 @@ enum ProfKind {
     PK_CONTRACT_REDUCE,
     PK_RATIO,
     PK_FUSED_ZC,
+    PK_DIAG_Z,
+    PK_DIAG_MAPS,
+    PK_DIAG_REDUCE,
     PK_COUNT
 };
 
@@ -157,5 +160,18 @@ int fft_shell_pair(conker_ctx *ctx, const conker_grid *g, double lo_a, double hi
 int fft_inverse_batch(conker_ctx *ctx, const conker_grid *g, bool f64,
                       const void *spec, const void *kspec, int m0, int nb, void *tspec,
                       void *maps_a, void *maps_b);
+// Inverse z pass of tspec[0 .. nb) (after fft_inverse_batch with maps_a NULL)
+// with the equidistant sums sum_x F(x) C_m(x)^p, p = 1 .. pmax (1..4), of the
+// real part against fa and the imaginary part against fb (NULL: none), in
+// place of storing the maps.  `blocks` workgroups per radius (at most
+// fft_z_tiles) each write one row of 2 * pmax doubles to
+// part[(m * blocks + block) * 2 * pmax], field a first.
+int fft_inverse_z_diag(conker_ctx *ctx, const conker_grid *g, bool f64, const void *tspec, int nb,
+                       const void *fa, const void *fb, int pmax, int blocks, void *part);
+// Radii per inverse batch given the bytes one radius's spectrum takes
+// (conv.hip); fixed_bytes is the workspace needed beside the batch.
+int batch_radii(conker_ctx *c, size_t per_radius_bytes, int n_radii, size_t fixed_bytes);
+// Number of z-line tiles of the inverse z pass of this grid.
+int fft_z_tiles(const conker_grid *g, bool f64);
 
 }  // namespace conker

@@ -6,7 +6,7 @@
 
 using namespace conker;
 
-namespace {
+namespace conker {
 
 // Radii convolved per inverse batch: one read of the forward spectrum serves
 // this many kernel multiplies and inverse x-axis transforms.  Default: every
@@ -38,7 +38,7 @@ int batch_radii(conker_ctx *c, size_t per_radius_bytes, int n_radii, size_t fixe
     return b < 1 ? 1 : b;
 }
 
-}  // namespace
+}  // namespace conker
 
 
 extern "C" int conker_make_shell_kernels(conker_ctx *c, const conker_grid *g, const double *h_radii,

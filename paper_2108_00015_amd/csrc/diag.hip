@@ -1,0 +1,199 @@
+// Equidistant (diagonal) n-point sums, Eq. ksinDiag: for every radius m and
+// order n, sum_x F(x) C_m(x)^(n-1) -- the tuple a_1 = ... = a_{n-1} = m of
+// Eq. ksin_delta.  Two forms:
+//   * conker_convolve_diag: streamed out of the last inverse FFT pass, so no
+//     map is ever stored (memory: the spectra of one radius batch only);
+//   * conker_contract_diag: from stored maps.
+// Both write per-workgroup FP64 partial rows that one kernel reduces in a
+// fixed order, so results do not depend on scheduling.
+#include <algorithm>
+
+#include "common.h"
+
+using namespace conker;
+
+namespace {
+
+constexpr int DT = 256;   // threads of the map and reduce kernels
+
+template <typename T>
+struct Vec;
+template <>
+struct Vec<float> {
+    static constexpr int V = 4;
+    using type = float4;
+};
+template <>
+struct Vec<double> {
+    static constexpr int V = 2;
+    using type = double2;
+};
+
+template <typename T, int P>
+__device__ __forceinline__ void acc_pow(double (&acc)[P], T f, T c) {
+    T pw = c;
+    acc[0] += (double)(f * pw);
+#pragma unroll
+    for (int p = 1; p < P; ++p) {
+        pw *= c;
+        acc[p] += (double)(f * pw);
+    }
+}
+
+// Block sum of P doubles into row[p] (thread 0 .. P-1 write); ends with a barrier.
+template <int P>
+__device__ __forceinline__ void block_sum(double (&acc)[P], double (*red)[P], double *row) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        double v = acc[p];
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+        if (lane == 0) red[wv][p] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < P) {
+        double v = 0.0;
+#pragma unroll
+        for (int w = 0; w < DT / 64; ++w) v += red[w][threadIdx.x];
+        row[threadIdx.x] = v;
+    }
+    __syncthreads();
+}
+
+// Workgroup b covers cells [b * chunk, min(nc, (b + 1) * chunk)) for every
+// radius; the field chunk is re-read per radius from L2.
+template <typename T, int P>
+__global__ __launch_bounds__(DT) void k_diag_maps(const T *__restrict__ F, const T *__restrict__ maps, size_t nc,
+                                                  int ns, size_t chunk, double *__restrict__ part) {
+    using VT = typename Vec<T>::type;
+    constexpr int V = Vec<T>::V;
+    __shared__ double red[DT / 64][P];
+    const size_t c0 = (size_t)blockIdx.x * chunk;
+    const size_t c1 = c0 + chunk < nc ? c0 + chunk : nc;
+    for (int m = 0; m < ns; ++m) {
+        double acc[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) acc[p] = 0.0;
+        const T *mp = maps + (size_t)m * nc;
+        for (size_t i = c0 + (size_t)threadIdx.x * V; i < c1; i += (size_t)DT * V) {
+            const VT f = *reinterpret_cast<const VT *>(F + i);
+            const VT c = *reinterpret_cast<const VT *>(mp + i);
+            if constexpr (V == 4) {
+                acc_pow<T, P>(acc, f.x, c.x);
+                acc_pow<T, P>(acc, f.y, c.y);
+                acc_pow<T, P>(acc, f.z, c.z);
+                acc_pow<T, P>(acc, f.w, c.w);
+            } else {
+                acc_pow<T, P>(acc, f.x, c.x);
+                acc_pow<T, P>(acc, f.y, c.y);
+            }
+        }
+        block_sum<P>(acc, red, part + ((size_t)m * gridDim.x + blockIdx.x) * P);
+    }
+}
+
+// part rows [ns][blocks][nf * P] -> out_f[(p - 1) * ns + m], p = 1 .. P.
+__global__ __launch_bounds__(DT) void k_diag_reduce(const double *__restrict__ part, int blocks, int ns, int nf,
+                                                    int P, double *__restrict__ out_a, double *__restrict__ out_b) {
+    __shared__ double red[DT];
+    const int m = blockIdx.x;
+    const int W = nf * P;
+    for (int j = 0; j < W; ++j) {
+        double v = 0.0;
+        for (int b = threadIdx.x; b < blocks; b += DT) v += part[((size_t)m * blocks + b) * W + j];
+        red[threadIdx.x] = v;
+        __syncthreads();
+        for (int s = DT / 2; s >= 1; s >>= 1) {
+            if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            const int f = j / P, p = j - f * P;
+            double *o = f == 0 ? out_a : out_b;
+            if (o) o[(size_t)p * ns + m] = red[0];
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T>
+int launch_maps(conker_ctx *c, const T *F, const T *maps, size_t nc, int ns, int P, int G, size_t chunk,
+                double *part) {
+    switch (P) {
+        case 1: hipLaunchKernelGGL((k_diag_maps<T, 1>), dim3(G), dim3(DT), 0, c->stream, F, maps, nc, ns, chunk, part); break;
+        case 2: hipLaunchKernelGGL((k_diag_maps<T, 2>), dim3(G), dim3(DT), 0, c->stream, F, maps, nc, ns, chunk, part); break;
+        case 3: hipLaunchKernelGGL((k_diag_maps<T, 3>), dim3(G), dim3(DT), 0, c->stream, F, maps, nc, ns, chunk, part); break;
+        default: hipLaunchKernelGGL((k_diag_maps<T, 4>), dim3(G), dim3(DT), 0, c->stream, F, maps, nc, ns, chunk, part); break;
+    }
+    CK_LAUNCH(c);
+    return CONKER_OK;
+}
+
+int reduce(conker_ctx *c, const double *part, int blocks, int ns, int nf, int P, double *oa, double *ob) {
+    ProfScope ps(c, PK_DIAG_REDUCE);
+    hipLaunchKernelGGL(k_diag_reduce, dim3(ns), dim3(DT), 0, c->stream, part, blocks, ns, nf, P, oa, ob);
+    CK_LAUNCH(c);
+    return CONKER_OK;
+}
+
+int check_common(conker_ctx *c, const conker_grid *g, conker_dtype dt, int ns, int n_max) {
+    CK_OK(check_grid(c, g, true));
+    if (dt != CONKER_F32 && dt != CONKER_F64) return fail(c, CONKER_EINVAL, "bad dtype");
+    if (ns <= 0) return fail(c, CONKER_EINVAL, "n_radii must be positive");
+    if (n_max < 2 || n_max > 5) return fail(c, CONKER_EINVAL, "n_max %d outside 2..5", n_max);
+    return CONKER_OK;
+}
+
+}  // namespace
+
+extern "C" int conker_contract_diag(conker_ctx *c, const conker_grid *g, conker_dtype dt, const void *field,
+                                    const void *maps, int n_radii, int n_max, double *out) {
+    CK_OK(check_common(c, g, dt, n_radii, n_max));
+    if (!field || !maps || !out) return fail(c, CONKER_EINVAL, "NULL pointer");
+    CK_HIP(c, hipSetDevice(c->device));
+    const size_t nc = ncells(g);
+    const bool f64 = dt == CONKER_F64;
+    const size_t step = (size_t)DT * (f64 ? 2 : 4);
+    int G = (int)std::min<size_t>(2048, std::max<size_t>(1, nc / (4 * step)));
+    size_t chunk = (nc + G - 1) / G;
+    chunk = (chunk + step - 1) / step * step;
+    G = (int)((nc + chunk - 1) / chunk);
+    const int P = n_max - 1;
+    CK_OK(ws_reserve(c, c->partial, (size_t)n_radii * G * P * sizeof(double)));
+    double *part = (double *)c->partial.p;
+    {
+        ProfScope ps(c, PK_DIAG_MAPS);
+        if (f64) CK_OK(launch_maps<double>(c, (const double *)field, (const double *)maps, nc, n_radii, P, G, chunk, part));
+        else CK_OK(launch_maps<float>(c, (const float *)field, (const float *)maps, nc, n_radii, P, G, chunk, part));
+    }
+    return reduce(c, part, G, n_radii, 1, P, out, nullptr);
+}
+
+extern "C" int conker_convolve_diag(conker_ctx *c, const conker_grid *g, conker_dtype dt, const void *fa,
+                                    const void *fb, const void *kspec, int n_radii, int n_max, double *out_a,
+                                    double *out_b) {
+    CK_OK(check_common(c, g, dt, n_radii, n_max));
+    if (!fa || !kspec || !out_a) return fail(c, CONKER_EINVAL, "NULL pointer");
+    if ((fb == nullptr) != (out_b == nullptr))
+        return fail(c, CONKER_EINVAL, "field_b and out_b must both be given or both be NULL");
+    CK_HIP(c, hipSetDevice(c->device));
+    const bool f64 = dt == CONKER_F64;
+    const size_t nc = ncells(g);
+    const size_t cbytes = nc * (f64 ? sizeof(double2) : sizeof(float2));
+    const int B = batch_radii(c, cbytes, n_radii, cbytes);
+    const int P = n_max - 1;
+    const int blocks = std::min(fft_z_tiles(g, f64), 4 * cu_count(c));
+    CK_OK(ws_reserve(c, c->spec, cbytes));
+    CK_OK(ws_reserve(c, c->tspec, (size_t)B * cbytes));
+    CK_OK(ws_reserve(c, c->partial, (size_t)n_radii * blocks * 2 * P * sizeof(double)));
+    double *part = (double *)c->partial.p;
+    CK_OK(fft_forward_pair(c, g, f64, fa, fb, c->spec.p));
+    for (int m0 = 0; m0 < n_radii; m0 += B) {
+        const int nb = (m0 + B <= n_radii) ? B : n_radii - m0;
+        CK_OK(fft_inverse_batch(c, g, f64, c->spec.p, kspec, m0, nb, c->tspec.p, nullptr, nullptr));
+        CK_OK(fft_inverse_z_diag(c, g, f64, c->tspec.p, nb, fa, fb, P, blocks,
+                                 part + (size_t)m0 * blocks * 2 * P));
+    }
+    return reduce(c, part, blocks, n_radii, 2, P, out_a, out_b);
+}

@@ -533,6 +533,90 @@ __global__ __launch_bounds__((Shape<T, L, TM_R>::NT), (Shape<T, L, TM_R>::MINW))
 }
 
 // ---------------------------------------------------------------------------
+// z pass, inverse, with the equidistant summation of Eq. ksinDiag in place of
+// the map stores: for the radii of one batch (blockIdx.y) and both packed
+// fields, sum F(x) C_m(x)^p for p = 1 .. P over every cell.  Each workgroup
+// runs a strided set of z-line tiles, accumulating in FP64 per thread, and
+// writes one partial row per (radius, workgroup); rows are reduced in a fixed
+// order afterwards.
+// ---------------------------------------------------------------------------
+template <typename T, int P>
+struct OpDiag {
+    static constexpr bool STAGED = false;
+    using C = cplx<T>;
+    const C *src;
+    const T *fa;
+    const T *fb;
+    Tile g;
+    double acc[2][P];
+    __device__ C load(int i, int c) const { return src[off(g, i, c)]; }
+    __device__ void store(int i, int c, C v) {
+        const unsigned k = off(g, i, c);
+        const T a = fa[k];
+        T pw = v.x;
+        acc[0][0] += (double)(a * pw);
+#pragma unroll
+        for (int p = 1; p < P; ++p) {
+            pw *= v.x;
+            acc[0][p] += (double)(a * pw);
+        }
+        if (fb) {
+            const T b = fb[k];
+            pw = v.y;
+            acc[1][0] += (double)(b * pw);
+#pragma unroll
+            for (int p = 1; p < P; ++p) {
+                pw *= v.y;
+                acc[1][p] += (double)(b * pw);
+            }
+        }
+    }
+};
+
+template <typename T, int L, int P>
+__global__ __launch_bounds__((Shape<T, L, TM_J>::NT), (Shape<T, L, TM_J>::MINW)) void k_zinv_diag(
+    const cplx<T> *__restrict__ tspec, const T *__restrict__ fa, const T *__restrict__ fb,
+    const cplx<T> *__restrict__ twg, Dims d, size_t nc, int tiles, double *__restrict__ part) {
+    using C = cplx<T>;
+    using SH = Shape<T, L, TM_J>;
+    constexpr int NT = SH::NT, NW = NT / 64;
+    __shared__ C lds[SH::LDS];
+    __shared__ C tw[L];
+    __shared__ double red[NW][2 * P];
+    for (int t = threadIdx.x; t < L; t += NT) tw[t] = twg[t];
+    OpDiag<T, P> op;
+#pragma unroll
+    for (int p = 0; p < P; ++p) op.acc[0][p] = op.acc[1][p] = 0.0;
+    const C *base = tspec + (size_t)blockIdx.y * nc;
+    __syncthreads();
+    for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        op.g = make_tile(AX_Z, d, tile, SH::TC);
+        op.src = base + op.g.base;
+        op.fa = fa + op.g.base;
+        op.fb = fb ? fb + op.g.base : nullptr;
+        fft_line_tile<T, L, TM_J, +1, false>(lds, tw, op);
+        __syncthreads();
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int f = 0; f < 2; ++f)
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            double v = op.acc[f][p];
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+            if (lane == 0) red[wv][f * P + p] = v;
+        }
+    __syncthreads();
+    if (threadIdx.x < 2 * P) {
+        double v = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) v += red[w][threadIdx.x];
+        part[((size_t)blockIdx.y * gridDim.x + blockIdx.x) * (2 * P) + threadIdx.x] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // launch helpers
 // ---------------------------------------------------------------------------
 template <typename T, int L>
@@ -705,9 +789,67 @@ int inverse_batch_t(conker_ctx *ctx, const conker_grid *g, const void *spec, con
     return CONKER_OK;
 }
 
+template <typename T, int P>
+int zinv_diag_t(conker_ctx *ctx, const conker_grid *g, const void *tspec, int nb, const void *fa, const void *fb,
+                int blocks, void *part) {
+    using C = cplx<T>;
+    const bool f64 = std::is_same<T, double>::value;
+    Dims d{g->dims[0], g->dims[1], g->dims[2]};
+    const void *twz;
+    CK_OK(twiddles(ctx, d.nz, f64, &twz));
+    const size_t nc = ncells(g);
+    auto go = [&](auto Lc) -> int {
+        constexpr int LL = decltype(Lc)::value;
+        using SH = Shape<T, LL, TM_J>;
+        const int tiles = (int)((long)d.nx * d.ny / SH::TC);
+        if (blocks > tiles) return fail(ctx, CONKER_EINVAL, "more partial rows than z tiles");
+        ProfScope ps(ctx, PK_DIAG_Z);
+        hipLaunchKernelGGL((k_zinv_diag<T, LL, P>), dim3((unsigned)blocks, (unsigned)nb), dim3(SH::NT), 0,
+                           ctx->stream, (const C *)tspec, (const T *)fa, (const T *)fb, (const C *)twz, d, nc,
+                           tiles, (double *)part);
+        CK_LAUNCH(ctx);
+        return CONKER_OK;
+    };
+    switch (d.nz) {
+        case 32: return go(std::integral_constant<int, 32>());
+        case 64: return go(std::integral_constant<int, 64>());
+        case 96: return go(std::integral_constant<int, 96>());
+        case 128: return go(std::integral_constant<int, 128>());
+        case 192: return go(std::integral_constant<int, 192>());
+        case 256: return go(std::integral_constant<int, 256>());
+        case 384: return go(std::integral_constant<int, 384>());
+        case 512: return go(std::integral_constant<int, 512>());
+        case 1024: return go(std::integral_constant<int, 1024>());
+        default: return fail(ctx, CONKER_EUNSUPPORTED, "FFT length %d", d.nz);
+    }
+}
+
+template <typename T>
+int zinv_diag_p(conker_ctx *ctx, const conker_grid *g, const void *tspec, int nb, const void *fa, const void *fb,
+                int pmax, int blocks, void *part) {
+    switch (pmax) {
+        case 1: return zinv_diag_t<T, 1>(ctx, g, tspec, nb, fa, fb, blocks, part);
+        case 2: return zinv_diag_t<T, 2>(ctx, g, tspec, nb, fa, fb, blocks, part);
+        case 3: return zinv_diag_t<T, 3>(ctx, g, tspec, nb, fa, fb, blocks, part);
+        case 4: return zinv_diag_t<T, 4>(ctx, g, tspec, nb, fa, fb, blocks, part);
+        default: return fail(ctx, CONKER_EINVAL, "power %d outside 1..4", pmax);
+    }
+}
+
 }  // namespace
 
 namespace conker {
+
+int fft_inverse_z_diag(conker_ctx *ctx, const conker_grid *g, bool f64, const void *tspec, int nb,
+                       const void *fa, const void *fb, int pmax, int blocks, void *part) {
+    return f64 ? zinv_diag_p<double>(ctx, g, tspec, nb, fa, fb, pmax, blocks, part)
+               : zinv_diag_p<float>(ctx, g, tspec, nb, fa, fb, pmax, blocks, part);
+}
+
+int fft_z_tiles(const conker_grid *g, bool f64) {
+    const int tc = f64 ? tc_of<double>(g->dims[2], TM_J) : tc_of<float>(g->dims[2], TM_J);
+    return (int)((long)g->dims[0] * g->dims[1] / tc);
+}
 
 int fft_forward_pair(conker_ctx *ctx, const conker_grid *g, bool f64, const void *a, const void *b,
                      void *spec) {

@@ -36,10 +36,14 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_bytes(kind, n_launch_units, nc, ns, kel, n_data, n_rand, weighted, esize, batch):
+def kernel_bytes(kind, n_launch_units, nc, ns, kel, n_data, n_rand, weighted, esize, batch, fx=1.0, fl=1.0):
     """Algorithmic HBM bytes of all launches of one kind in one step.
 
-    esize = bytes of one real value (4 or 8); complex = 2 * esize.
+    esize = bytes of one real value (4 or 8); complex = 2 * esize.  When the maps
+    are only summed, the inverse passes produce their outputs on the z-lines that
+    carry field (fraction fl of all lines, in a fraction fx of the x-slabs):
+    the x pass writes fx of its output, the y pass reads fx and writes fl, the
+    z pass reads fl.
     """
     c = 2 * esize
     if kind == "fft_fwd_z":       # two real fields in, one complex field out
@@ -48,9 +52,13 @@ def kernel_bytes(kind, n_launch_units, nc, ns, kel, n_data, n_rand, weighted, es
         return 2 * nc * c
     if kind == "fft_inv_x_mul":   # spectrum read once per batch, kernel octant + output per radius
         n_batches = math.ceil(ns / batch)
-        return n_batches * nc * c + ns * (kel * esize + nc * c)
+        return n_batches * nc * c + ns * (kel * esize + fx * nc * c)
     if kind == "fft_inv_y":
-        return ns * 2 * nc * c
+        return ns * (fx + fl) * nc * c
+    if kind == "support":         # both fields read once
+        return 2 * nc * esize
+    if kind == "diag_zinv":
+        return ns * fl * nc * c + 2 * fl * nc * esize
     if kind == "fft_inv_z":       # complex in, two real maps out
         return ns * (nc * c + 2 * nc * esize)
     if kind == "scatter":         # positions (+ weights) in, one grid value read-modify-write per point
@@ -58,8 +66,8 @@ def kernel_bytes(kind, n_launch_units, nc, ns, kel, n_data, n_rand, weighted, es
         return (n_data + n_rand) * per
     if kind == "form_delta":
         return 3 * nc * esize
-    if kind == "fused_zinv_contract":   # every radius's spectrum once, both fields once
-        return ns * nc * c + 2 * nc * esize
+    if kind == "fused_zinv_contract":   # every radius's spectrum and both fields, on carrying lines
+        return ns * fl * nc * c + 2 * fl * nc * esize
     return None
 
 
@@ -90,6 +98,20 @@ def measured_traffic(kind, workload, n):
     if t.get("sources") != source_hashes(tuple(t.get("sources", {}).keys()) or TRAFFIC_SOURCES):
         return None
     return (t["fetch_kib_per_dispatch"] * t["fetch_factor"] + t["write_kib_per_dispatch"] * t["write_factor"]) * 1024.0
+
+
+def support_fractions(w, data, rand):
+    """Fractions of z-lines (x, y) and of x-slabs holding at least one catalog
+    point (the lines on which N or R_raw can be non-zero)."""
+    nx, ny = int(w.dims[0]), int(w.dims[1])
+    hit = np.zeros(nx * ny, dtype=bool)
+    o = np.asarray(w.origin, dtype=np.float64)
+    for cat in (data, rand):
+        c = np.floor((cat.pos.astype(np.float64) - o) / w.cell).astype(np.int64)
+        ok = np.all((c >= 0) & (c < np.asarray(w.dims)), axis=1)
+        hit[c[ok, 0] * ny + c[ok, 1]] = True
+    hit = hit.reshape(nx, ny)
+    return float(hit.any(axis=1).mean()), float(hit.mean())
 
 
 def cpu_baseline(w, data, rand, n, sample_radii=1):
@@ -203,10 +225,11 @@ def main():
         log("  %.2f ms/step" % fp64["ms"])
 
     batch = min(int(os.environ.get("CONKER_RADIUS_BATCH", str(ns))), ns)
+    fx, fl = support_fractions(w, data, rand)
     stages = {}
     for kind, (launches, tot) in mixed["prof"].items():
         per_step = tot / args.steps
-        b = kernel_bytes(kind, launches, nc, ns, kel, len(data), len(rand), data.w is not None, 4, batch)
+        b = kernel_bytes(kind, launches, nc, ns, kel, len(data), len(rand), data.w is not None, 4, batch, fx, fl)
         if kind == "contract_mm":
             b = 2 * (ns + 1) * nc * 4
         ent = dict(launches_per_step=launches / args.steps, ms_per_step=per_step,
@@ -249,7 +272,8 @@ def main():
         "config": {"workload": w.name, "grid": list(w.dims), "cell": w.cell, "n_radii": ns,
                    "radii": [w.radii[0], w.radii[-1]], "n": args.n, "n_data": len(data),
                    "n_randoms": len(rand), "weights": "log-normal sigma 0.2",
-                   "summation": args.prec, "fft": "f32"},
+                   "summation": args.prec, "fft": "f32",
+                   "carrying_lines": round(fl, 4), "carrying_x_slabs": round(fx, 4)},
         "s_to_W3_mixed": round(s_mixed, 5),
         "s_to_W3_fp64": round(fp64["ms"] / 1e3, 5) if fp64 else None,
         "fp64_over_mixed": round(fp64["ms"] / mixed["ms"], 3) if fp64 else None,

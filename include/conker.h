@@ -175,7 +175,10 @@ int conker_contract_npt(conker_ctx *ctx, const conker_grid *grid, conker_dtype d
  * Supported: dtype CONKER_F32 with prec CONKER_MM_F32 or
  * CONKER_MM_SPLIT_BF16, nz = 512, 1 <= n_radii <= 30; anything else returns
  * CONKER_EUNSUPPORTED before doing work (use the two separate calls).  The
- * context holds the spectra of all radii at once (n_radii * N_c * 8 bytes). */
+ * context holds the spectra of all radii at once (n_radii * N_c * 8 bytes).
+ * The fields must be 16-byte aligned (CONKER_EINVAL otherwise).  Since every
+ * term carries field(x), z-lines on which both fields vanish add nothing: the
+ * inverse transforms are carried out only where a line holds field. */
 int conker_convolve_contract(conker_ctx *ctx, const conker_grid *grid, conker_dtype dtype,
                              const void *d_field_a, const void *d_field_b, const void *d_kspec,
                              int n_radii, int n, conker_mmprec prec, double *d_W_a, double *d_W_b);
@@ -197,7 +200,9 @@ int conker_contract_diag(conker_ctx *ctx, const conker_grid *grid, conker_dtype 
  * the kernel bank, without storing any map: the last inverse FFT pass of each
  * radius feeds the sums instead of memory, so the device holds only the
  * spectra of one radius batch.  Every supported grid and both dtypes.
- *   d_field_b and d_out_b: both given or both NULL. */
+ *   d_field_b and d_out_b: both given or both NULL.
+ * Fields 16-byte aligned (CONKER_EINVAL otherwise); as for
+ * conker_convolve_contract, lines on which both fields vanish are skipped. */
 int conker_convolve_diag(conker_ctx *ctx, const conker_grid *grid, conker_dtype dtype,
                          const void *d_field_a, const void *d_field_b, const void *d_kspec,
                          int n_radii, int n_max, double *d_out_a, double *d_out_b);

@@ -35,6 +35,7 @@ struct conker_ctx {
     conker::Buf tspec;      // per-radius spectra of one radius batch
     conker::Buf partial;    // per-workgroup partial sums of the summation stage
     conker::Buf full;       // reduced block matrices of the summation stage
+    conker::Buf support;    // line mask, per-slab counts and list of lines carrying field
     std::map<uint64_t, conker::Buf> tables;  // item / tuple tables, keyed by (n_radii, n, prec)
     // per-launch event timing (conker_profile_enable)
     int n_cu = 0;
@@ -75,6 +76,7 @@ enum ProfKind {
     PK_DIAG_Z,
     PK_DIAG_MAPS,
     PK_DIAG_REDUCE,
+    PK_SUPPORT,
     PK_COUNT
 };
 
@@ -142,6 +144,16 @@ int shell_reach(double r);
 // Validates a shell radius (cells) against the grid; CONKER_ERANGE if it does not fit.
 int check_shell(conker_ctx *ctx, const conker_grid *g, double r_cells);
 
+// Lines (x, y) on which field_a or field_b is non-zero (support.hip).  The
+// fields must be 16-byte aligned (CONKER_EINVAL otherwise).
+struct Support {
+    const unsigned char *mask = nullptr;   // [nx * ny] 0 / 1
+    const int *xcount = nullptr;           // [nx] carrying lines per x-slab
+    const int *list = nullptr;             // carrying lines x * ny + y, increasing
+    const int *count = nullptr;            // device scalar: length of list
+};
+int support_lines(conker_ctx *c, const conker_grid *g, bool f64, const void *fa, const void *fb, Support *out);
+
 // FFT passes (fft.hip) ------------------------------------------------------
 // Forward 3D FFT of the complex field packed from two real fields
 // (a + i b) into the spectrum buffer `spec` (natural order, unnormalised).
@@ -157,9 +169,12 @@ int fft_shell_pair(conker_ctx *ctx, const conker_grid *g, double lo_a, double hi
 // 3D FFT, write real parts to maps_a[m] and imaginary parts to maps_b[m].
 // With maps_a NULL only the x and y passes run, leaving tspec[m - m0] holding
 // the spectra transformed back along x and y (still along kz).
+// With `sup` (maps_a NULL only): outputs are needed on carrying lines only; the
+// x pass writes carrying x-slabs, the y pass skips empty slabs and writes
+// carrying lines.
 int fft_inverse_batch(conker_ctx *ctx, const conker_grid *g, bool f64,
                       const void *spec, const void *kspec, int m0, int nb, void *tspec,
-                      void *maps_a, void *maps_b);
+                      void *maps_a, void *maps_b, const Support *sup = nullptr);
 // Inverse z pass of tspec[0 .. nb) (after fft_inverse_batch with maps_a NULL)
 // with the equidistant sums sum_x F(x) C_m(x)^p, p = 1 .. pmax (1..4), of the
 // real part against fa and the imaginary part against fb (NULL: none), in
@@ -167,7 +182,9 @@ int fft_inverse_batch(conker_ctx *ctx, const conker_grid *g, bool f64,
 // fft_z_tiles) each write one row of 2 * pmax doubles to
 // part[(m * blocks + block) * 2 * pmax], field a first.
 int fft_inverse_z_diag(conker_ctx *ctx, const conker_grid *g, bool f64, const void *tspec, int nb,
-                       const void *fa, const void *fb, int pmax, int blocks, void *part);
+                       const void *fa, const void *fb, int pmax, int blocks, void *part,
+                       const unsigned char *mask = nullptr);
+
 // Radii per inverse batch given the bytes one radius's spectrum takes
 // (conv.hip); fixed_bytes is the workspace needed beside the batch.
 int batch_radii(conker_ctx *c, size_t per_radius_bytes, int n_radii, size_t fixed_bytes);

@@ -188,12 +188,14 @@ extern "C" int conker_convolve_diag(conker_ctx *c, const conker_grid *g, conker_
     CK_OK(ws_reserve(c, c->tspec, (size_t)B * cbytes));
     CK_OK(ws_reserve(c, c->partial, (size_t)n_radii * blocks * 2 * P * sizeof(double)));
     double *part = (double *)c->partial.p;
+    Support sup;
+    CK_OK(support_lines(c, g, f64, fa, fb, &sup));
     CK_OK(fft_forward_pair(c, g, f64, fa, fb, c->spec.p));
     for (int m0 = 0; m0 < n_radii; m0 += B) {
         const int nb = (m0 + B <= n_radii) ? B : n_radii - m0;
-        CK_OK(fft_inverse_batch(c, g, f64, c->spec.p, kspec, m0, nb, c->tspec.p, nullptr, nullptr));
+        CK_OK(fft_inverse_batch(c, g, f64, c->spec.p, kspec, m0, nb, c->tspec.p, nullptr, nullptr, &sup));
         CK_OK(fft_inverse_z_diag(c, g, f64, c->tspec.p, nb, fa, fb, P, blocks,
-                                 part + (size_t)m0 * blocks * 2 * P));
+                                 part + (size_t)m0 * blocks * 2 * P, sup.mask));
     }
     return reduce(c, part, blocks, n_radii, 2, P, out_a, out_b);
 }

@@ -17,6 +17,7 @@
 // extracts the stored octant of a kernel spectrum.
 #include <cstdlib>
 #include <type_traits>
+#include <utility>
 
 #include "common.h"
 #include "fft_math.h"
@@ -178,6 +179,13 @@ __device__ __forceinline__ void fft_line_tile(cplx<T> *lds, const cplx<T> *tw, O
     if constexpr (Plan<L>::n > 3) fft_stage<T, L, MODE, DIR, 3, ST>(lds, tw, op);
 }
 
+// Ops with an active() member may skip a whole tile (same answer for every
+// thread of the workgroup).
+template <class Op, class = void>
+struct has_active : std::false_type {};
+template <class Op>
+struct has_active<Op, std::void_t<decltype(std::declval<const Op &>().active())>> : std::true_type {};
+
 // One launch = one pass over one axis.  Op::iters() line transforms are run
 // per tile (more than one when a tile is reused across several radii).
 template <typename T, int L, int MODE, int DIR, class Op>
@@ -187,8 +195,11 @@ __global__ __launch_bounds__((Shape<T, L, MODE>::NT), (Shape<T, L, MODE>::MINW))
     __shared__ C lds[SH::LDS];
     __shared__ C tw[L];
     const C *twg = reinterpret_cast<const C *>(op.tw);
-    for (int t = threadIdx.x; t < L; t += SH::NT) tw[t] = twg[t];
     op.template begin<SH::TC>();
+    if constexpr (has_active<Op>::value) {
+        if (!op.active()) return;   // the same for every thread of the workgroup
+    }
+    for (int t = threadIdx.x; t < L; t += SH::NT) tw[t] = twg[t];
     __syncthreads();
     const int it_n = op.iters();
     for (int it = 0; it < it_n; ++it) {
@@ -270,6 +281,8 @@ struct OpPack {
     __device__ void store(int i, int c, C v) const { out[off(g, i, c)] = v; }
 };
 
+// With `xcount` and `mask` (y axis only): tiles of x-slabs without carrying
+// lines do nothing, and only rows y of carrying lines (x, y) are written.
 template <typename T>
 struct OpInplace {
     static constexpr bool STAGED = false;   // any axis, in place; blockIdx.y selects a grid of the batch
@@ -281,15 +294,21 @@ struct OpInplace {
     size_t nc;
     Tile g;
     C *p;
+    const unsigned char *mask;
+    const int *xcount;
     template <int TC> __device__ void begin() {
         g = make_tile(axis, d, blockIdx.x, TC);
         p = buf + (size_t)blockIdx.y * nc + g.base;
     }
+    __device__ bool active() const { return !xcount || xcount[g.p0] > 0; }
     __device__ int iters() const { return 1; }
     __device__ void set_iter(int) {}
     __device__ C load(int i, int c) const { return p[off(g, i, c)]; }
-    __device__ void store(int i, int c, C v) const { p[off(g, i, c)] = v; }
+    __device__ void store(int i, int c, C v) const {
+        if (!mask || mask[(size_t)g.p0 * d.ny + i]) p[off(g, i, c)] = v;
+    }
 };
+
 
 // x pass, inverse, for radii m0 .. m0+nb-1: spec * K_m -> tspec[m - m0].
 // The kernel octant of radius m is stored [ky'][kz'][kx'] (x fastest), so the
@@ -455,12 +474,15 @@ struct OpResident {
     const T *kt;    // LDS: kernel values [TC][L/2 + 1]
     C *out;         // global: output tile base
     unsigned si;
+    const int *xcount;   // NULL, or carrying lines per x-slab: slabs without any are not written
     __device__ C load(int i, int c) const {
         const C s = st[i * TC + c];
         const T k = kt[c * (L / 2 + 1) + (i <= L - i ? i : L - i)];
         return C{s.x * k, s.y * k};
     }
-    __device__ void store(int i, int c, C v) const { out[(unsigned)i * si + (unsigned)c] = v; }
+    __device__ void store(int i, int c, C v) const {
+        if (!xcount || xcount[i] > 0) out[(unsigned)i * si + (unsigned)c] = v;
+    }
 };
 
 template <typename T, int L>
@@ -474,7 +496,7 @@ constexpr bool resident_fits() {
 template <typename T, int L>
 __global__ __launch_bounds__((Shape<T, L, TM_R>::NT), (Shape<T, L, TM_R>::MINW)) void k_xmul_resident(
     const cplx<T> *__restrict__ spec, const T *__restrict__ kspec, cplx<T> *__restrict__ tspec,
-    const cplx<T> *__restrict__ twg, Dims d, size_t nc, size_t kel, int m0, int nb) {
+    const cplx<T> *__restrict__ twg, Dims d, size_t nc, size_t kel, int m0, int nb, const int *__restrict__ xcount) {
     using C = cplx<T>;
     using SH = Shape<T, L, TM_R>;
     constexpr int TC = SH::TC, NT = SH::NT, NXH = L / 2 + 1;
@@ -526,7 +548,7 @@ __global__ __launch_bounds__((Shape<T, L, TM_R>::NT), (Shape<T, L, TM_R>::MINW))
         }
         __syncthreads();
         if (m + 1 < nb) kload(m + 1, kv);
-        OpResident<T, L, TC> op{st, kt, tspec + (size_t)m * nc + g.base, (unsigned)g.si};
+        OpResident<T, L, TC> op{st, kt, tspec + (size_t)m * nc + g.base, (unsigned)g.si, xcount};
         fft_line_tile<T, L, TM_R, +1, false>(lds, tw, op);
         __syncthreads();
     }
@@ -547,9 +569,13 @@ struct OpDiag {
     const C *src;
     const T *fa;
     const T *fb;
+    const unsigned char *mask;   // NULL, or lines carrying field: others read as zero
     Tile g;
     double acc[2][P];
-    __device__ C load(int i, int c) const { return src[off(g, i, c)]; }
+    __device__ C load(int i, int c) const {
+        if (mask && !mask[g.p0 + c]) return C{(T)0, (T)0};
+        return src[off(g, i, c)];
+    }
     __device__ void store(int i, int c, C v) {
         const unsigned k = off(g, i, c);
         const T a = fa[k];
@@ -576,7 +602,8 @@ struct OpDiag {
 template <typename T, int L, int P>
 __global__ __launch_bounds__((Shape<T, L, TM_J>::NT), (Shape<T, L, TM_J>::MINW)) void k_zinv_diag(
     const cplx<T> *__restrict__ tspec, const T *__restrict__ fa, const T *__restrict__ fb,
-    const cplx<T> *__restrict__ twg, Dims d, size_t nc, int tiles, double *__restrict__ part) {
+    const cplx<T> *__restrict__ twg, Dims d, size_t nc, int tiles, double *__restrict__ part,
+    const unsigned char *__restrict__ mask) {
     using C = cplx<T>;
     using SH = Shape<T, L, TM_J>;
     constexpr int NT = SH::NT, NW = NT / 64;
@@ -587,9 +614,15 @@ __global__ __launch_bounds__((Shape<T, L, TM_J>::NT), (Shape<T, L, TM_J>::MINW))
     OpDiag<T, P> op;
 #pragma unroll
     for (int p = 0; p < P; ++p) op.acc[0][p] = op.acc[1][p] = 0.0;
+    op.mask = mask;
     const C *base = tspec + (size_t)blockIdx.y * nc;
     __syncthreads();
     for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        if (mask) {   // a tile without carrying lines adds nothing
+            bool any = false;
+            for (int c = 0; c < SH::TC; ++c) any |= mask[tile * SH::TC + c] != 0;
+            if (!any) continue;
+        }
         op.g = make_tile(AX_Z, d, tile, SH::TC);
         op.src = base + op.g.base;
         op.fa = fa + op.g.base;
@@ -715,7 +748,9 @@ int forward_pair_t(conker_ctx *ctx, const conker_grid *g, const void *a, const v
 
 template <typename T>
 int inverse_batch_t(conker_ctx *ctx, const conker_grid *g, const void *spec, const void *kspec, int m0,
-                    int nb, void *tspec, void *maps_a, void *maps_b) {
+                    int nb, void *tspec, void *maps_a, void *maps_b, const Support *sup) {
+    const int *xcount = (sup && !maps_a) ? sup->xcount : nullptr;
+    const unsigned char *mask = (sup && !maps_a) ? sup->mask : nullptr;
     using C = cplx<T>;
     const bool f64 = std::is_same<T, double>::value;
     Dims d{g->dims[0], g->dims[1], g->dims[2]};
@@ -751,7 +786,7 @@ int inverse_batch_t(conker_ctx *ctx, const conker_grid *g, const void *spec, con
                 const unsigned nt = (unsigned)((long)d.ny * d.nz / SH::TC);
                 hipLaunchKernelGGL((k_xmul_resident<T, LL>), dim3(nt), dim3(SH::NT), 0, ctx->stream,
                                    (const C *)spec, (const T *)kspec, (C *)tspec, (const C *)twx, d, nc, kel, m0,
-                                   nb);
+                                   nb, xcount);
                 CK_LAUNCH(ctx);
                 done = true;
             }
@@ -781,7 +816,7 @@ int inverse_batch_t(conker_ctx *ctx, const conker_grid *g, const void *spec, con
                             {}, 0, 0, nullptr, nullptr, nullptr};
         CK_OK((launch_len<T, +1>(ctx, PK_FFT_INV_X_MUL, xm, d.nx, AX_X, d, gxm, px)));
     }
-    OpInplace<T> py{twy, d, AX_Y, (C *)tspec, nc, {}, nullptr};
+    OpInplace<T> py{twy, d, AX_Y, (C *)tspec, nc, {}, nullptr, mask, xcount};
     CK_OK((launch_len<T, +1>(ctx, PK_FFT_INV_Y, TM_C, d.ny, AX_Y, d, dim3(1, (unsigned)nb), py)));
     if (!maps_a) return CONKER_OK;   // x and y passes only
     OpUnpack<T> pz{twz, d, (const C *)tspec, (T *)maps_a, (T *)maps_b, nc, m0, {}, nullptr};
@@ -791,7 +826,7 @@ int inverse_batch_t(conker_ctx *ctx, const conker_grid *g, const void *spec, con
 
 template <typename T, int P>
 int zinv_diag_t(conker_ctx *ctx, const conker_grid *g, const void *tspec, int nb, const void *fa, const void *fb,
-                int blocks, void *part) {
+                int blocks, void *part, const unsigned char *mask) {
     using C = cplx<T>;
     const bool f64 = std::is_same<T, double>::value;
     Dims d{g->dims[0], g->dims[1], g->dims[2]};
@@ -806,7 +841,7 @@ int zinv_diag_t(conker_ctx *ctx, const conker_grid *g, const void *tspec, int nb
         ProfScope ps(ctx, PK_DIAG_Z);
         hipLaunchKernelGGL((k_zinv_diag<T, LL, P>), dim3((unsigned)blocks, (unsigned)nb), dim3(SH::NT), 0,
                            ctx->stream, (const C *)tspec, (const T *)fa, (const T *)fb, (const C *)twz, d, nc,
-                           tiles, (double *)part);
+                           tiles, (double *)part, mask);
         CK_LAUNCH(ctx);
         return CONKER_OK;
     };
@@ -826,12 +861,12 @@ int zinv_diag_t(conker_ctx *ctx, const conker_grid *g, const void *tspec, int nb
 
 template <typename T>
 int zinv_diag_p(conker_ctx *ctx, const conker_grid *g, const void *tspec, int nb, const void *fa, const void *fb,
-                int pmax, int blocks, void *part) {
+                int pmax, int blocks, void *part, const unsigned char *mask) {
     switch (pmax) {
-        case 1: return zinv_diag_t<T, 1>(ctx, g, tspec, nb, fa, fb, blocks, part);
-        case 2: return zinv_diag_t<T, 2>(ctx, g, tspec, nb, fa, fb, blocks, part);
-        case 3: return zinv_diag_t<T, 3>(ctx, g, tspec, nb, fa, fb, blocks, part);
-        case 4: return zinv_diag_t<T, 4>(ctx, g, tspec, nb, fa, fb, blocks, part);
+        case 1: return zinv_diag_t<T, 1>(ctx, g, tspec, nb, fa, fb, blocks, part, mask);
+        case 2: return zinv_diag_t<T, 2>(ctx, g, tspec, nb, fa, fb, blocks, part, mask);
+        case 3: return zinv_diag_t<T, 3>(ctx, g, tspec, nb, fa, fb, blocks, part, mask);
+        case 4: return zinv_diag_t<T, 4>(ctx, g, tspec, nb, fa, fb, blocks, part, mask);
         default: return fail(ctx, CONKER_EINVAL, "power %d outside 1..4", pmax);
     }
 }
@@ -841,9 +876,10 @@ int zinv_diag_p(conker_ctx *ctx, const conker_grid *g, const void *tspec, int nb
 namespace conker {
 
 int fft_inverse_z_diag(conker_ctx *ctx, const conker_grid *g, bool f64, const void *tspec, int nb,
-                       const void *fa, const void *fb, int pmax, int blocks, void *part) {
-    return f64 ? zinv_diag_p<double>(ctx, g, tspec, nb, fa, fb, pmax, blocks, part)
-               : zinv_diag_p<float>(ctx, g, tspec, nb, fa, fb, pmax, blocks, part);
+                       const void *fa, const void *fb, int pmax, int blocks, void *part,
+                       const unsigned char *mask) {
+    return f64 ? zinv_diag_p<double>(ctx, g, tspec, nb, fa, fb, pmax, blocks, part, mask)
+               : zinv_diag_p<float>(ctx, g, tspec, nb, fa, fb, pmax, blocks, part, mask);
 }
 
 int fft_z_tiles(const conker_grid *g, bool f64) {
@@ -857,9 +893,10 @@ int fft_forward_pair(conker_ctx *ctx, const conker_grid *g, bool f64, const void
 }
 
 int fft_inverse_batch(conker_ctx *ctx, const conker_grid *g, bool f64, const void *spec,
-                      const void *kspec, int m0, int nb, void *tspec, void *maps_a, void *maps_b) {
-    return f64 ? inverse_batch_t<double>(ctx, g, spec, kspec, m0, nb, tspec, maps_a, maps_b)
-               : inverse_batch_t<float>(ctx, g, spec, kspec, m0, nb, tspec, maps_a, maps_b);
+                      const void *kspec, int m0, int nb, void *tspec, void *maps_a, void *maps_b,
+                      const Support *sup) {
+    return f64 ? inverse_batch_t<double>(ctx, g, spec, kspec, m0, nb, tspec, maps_a, maps_b, sup)
+               : inverse_batch_t<float>(ctx, g, spec, kspec, m0, nb, tspec, maps_a, maps_b, sup);
 }
 
 int fft_shell_pair(conker_ctx *ctx, const conker_grid *g, double lo_a, double hi_a, double lo_b,

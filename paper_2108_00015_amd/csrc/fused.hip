@@ -81,12 +81,17 @@ __device__ __forceinline__ void mma_chunk(floatx16 &acc, const float (&a)[8], co
     }
 }
 
+// Lines: lines[0 .. *count) when `lines` is given (the lines carrying field;
+// the others add nothing), else every line 0 .. nlines - 1.
 template <int PREC>
 __global__ __launch_bounds__(NT, 1) void k_zinv_contract(const float2 *__restrict__ tspec, int ns, size_t nc,
-                                                         int nlines, const float *__restrict__ Fa,
+                                                         int nlines, const int *__restrict__ lines,
+                                                         const int *__restrict__ count,
+                                                         const float *__restrict__ Fa,
                                                          const float *__restrict__ Fb,
                                                          const float2 *__restrict__ twg,
                                                          double *__restrict__ partial) {
+    const int nact = lines ? *count : nlines;
     // maps of the current line, one plane per field: Mf[field][radius][z]
     __shared__ __align__(16) float Mf[2 * MAXR * MROW];
     __shared__ float2 S[NW * NZ];
@@ -108,16 +113,17 @@ __global__ __launch_bounds__(NT, 1) void k_zinv_contract(const float2 *__restric
 #pragma unroll
     for (int v = 0; v < 16; ++v) dacc[v] = 0.0;
     int since = 0;
+    auto line_of = [&](int idx) -> int { return lines ? lines[idx] : idx; };
     float2 nxt[8];   // this wave's next (line, radius) item, loaded one item ahead
-    if (w < ns && (int)blockIdx.x < nlines) {
-        const float2 *src = tspec + (size_t)w * nc + (size_t)blockIdx.x * NZ;
+    if (w < ns && (int)blockIdx.x < nact) {
+        const float2 *src = tspec + (size_t)w * nc + (size_t)line_of(blockIdx.x) * NZ;
 #pragma unroll
         for (int q = 0; q < 8; ++q) nxt[q] = src[lane + 64 * q];
     }
     __syncthreads();
 
-    for (int line = blockIdx.x; line < nlines; line += gridDim.x) {
-        const size_t base = (size_t)line * NZ;
+    for (int idx = blockIdx.x; idx < nact; idx += gridDim.x) {
+        const size_t base = (size_t)line_of(idx) * NZ;
         // ---- inverse z transform of every radius of this line --------------
         for (int m = w; m < ns; m += NW) {
             float2 v[8];
@@ -125,13 +131,13 @@ __global__ __launch_bounds__(NT, 1) void k_zinv_contract(const float2 *__restric
             for (int q = 0; q < 8; ++q) v[q] = nxt[q];
             {   // prefetch the next (line, radius) item of this wave
                 int mn = m + NW;
-                size_t bn = base;
+                int in = idx;
                 if (mn >= ns) {
                     mn = w;
-                    bn = base + (size_t)gridDim.x * NZ;
+                    in = idx + gridDim.x;
                 }
-                if (mn < ns && bn < (size_t)nlines * NZ) {
-                    const float2 *src = tspec + (size_t)mn * nc + bn;
+                if (mn < ns && in < nact) {
+                    const float2 *src = tspec + (size_t)mn * nc + (size_t)line_of(in) * NZ;
 #pragma unroll
                     for (int q = 0; q < 8; ++q) nxt[q] = src[lane + 64 * q];
                 }
@@ -261,8 +267,10 @@ extern "C" int conker_convolve_contract(conker_ctx *c, const conker_grid *g, con
     const size_t cbytes = nc * sizeof(float2);
     CK_OK(ws_reserve(c, c->spec, cbytes));
     CK_OK(ws_reserve(c, c->tspec, (size_t)ns * cbytes));
+    Support sup;
+    CK_OK(support_lines(c, g, false, fa, fb, &sup));
     CK_OK(fft_forward_pair(c, g, false, fa, fb, c->spec.p));
-    CK_OK(fft_inverse_batch(c, g, false, c->spec.p, kspec, 0, ns, c->tspec.p, nullptr, nullptr));
+    CK_OK(fft_inverse_batch(c, g, false, c->spec.p, kspec, 0, ns, c->tspec.p, nullptr, nullptr, &sup));
     const void *twz;
     CK_OK(twiddles(c, NZ, false, &twz));
     const int nlines = g->dims[0] * g->dims[1];
@@ -272,11 +280,13 @@ extern "C" int conker_convolve_contract(conker_ctx *c, const conker_grid *g, con
         ProfScope ps(c, PK_FUSED_ZC);
         if (prec == CONKER_MM_SPLIT_BF16)
             hipLaunchKernelGGL(k_zinv_contract<CONKER_MM_SPLIT_BF16>, dim3(G), dim3(NT), 0, c->stream,
-                               (const float2 *)c->tspec.p, ns, nc, nlines, (const float *)fa, (const float *)fb,
+                               (const float2 *)c->tspec.p, ns, nc, nlines, sup.list, sup.count, (const float *)fa,
+                               (const float *)fb,
                                (const float2 *)twz, (double *)c->partial.p);
         else
             hipLaunchKernelGGL(k_zinv_contract<CONKER_MM_F32>, dim3(G), dim3(NT), 0, c->stream,
-                               (const float2 *)c->tspec.p, ns, nc, nlines, (const float *)fa, (const float *)fb,
+                               (const float2 *)c->tspec.p, ns, nc, nlines, sup.list, sup.count, (const float *)fa,
+                               (const float *)fb,
                                (const float2 *)twz, (double *)c->partial.p);
         CK_LAUNCH(c);
     }

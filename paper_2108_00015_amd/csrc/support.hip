@@ -1,0 +1,130 @@
+// Lines of cells that can contribute to a summation.
+//
+// Every term of Eq. ksin_delta carries the factor F(x) of the field at the
+// tuple's central cell, so a z-line (x, y) on which both fields vanish adds
+// nothing, whatever the maps hold there.  Survey volumes leave many such lines
+// (a sky cap fills a cone of its box).  When the maps are only summed, never
+// stored, the inverse passes therefore need their outputs only on the lines
+// that carry field: the x pass writes only x-slabs with at least one such line,
+// the y pass skips empty x-slabs and writes only carrying lines, and the z pass
+// transforms only carrying lines.  The results are unchanged.
+//
+// A line carries field if any of its words is non-zero in either field (bit
+// test, so -0.0 and NaN count as non-zero, which only keeps a line).  Outputs:
+//   mask[x * ny + y]   1 or 0;
+//   xcount[x]          carrying lines of slab x;
+//   list[0 .. count)   carrying lines x * ny + y in increasing order;
+//   count              their number.
+#include "common.h"
+
+using namespace conker;
+
+namespace {
+
+constexpr int ST = 256;   // threads per workgroup (4 waves)
+
+__global__ __launch_bounds__(ST) void k_line_mask(const uint4 *__restrict__ fa, const uint4 *__restrict__ fb,
+                                                  int ny, int units, unsigned char *__restrict__ mask,
+                                                  int *__restrict__ xcount) {
+    __shared__ int cnt[ST / 64];
+    const int x = blockIdx.x, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int c = 0;
+    for (int y = w; y < ny; y += ST / 64) {
+        const size_t base = ((size_t)x * ny + y) * units;
+        unsigned any = 0;
+        for (int u = lane; u < units; u += 64) {
+            const uint4 a = fa[base + u];
+            any |= a.x | a.y | a.z | a.w;
+            if (fb) {
+                const uint4 b = fb[base + u];
+                any |= b.x | b.y | b.z | b.w;
+            }
+        }
+        const bool on = __ballot(any != 0u) != 0ull;
+        if (lane == 0) {
+            mask[(size_t)x * ny + y] = on ? 1 : 0;
+            c += on ? 1 : 0;
+        }
+    }
+    if (lane == 0) cnt[w] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int s = 0;
+        for (int i = 0; i < ST / 64; ++i) s += cnt[i];
+        xcount[x] = s;
+    }
+}
+
+// One workgroup per slab x: offset = carrying lines of slabs before x, then a
+// block scan over the slab's mask writes its lines in order.
+__global__ __launch_bounds__(ST) void k_line_list(const unsigned char *__restrict__ mask,
+                                                  const int *__restrict__ xcount, int nx, int ny,
+                                                  int *__restrict__ list, int *__restrict__ count) {
+    __shared__ int red[ST];
+    const int x = blockIdx.x, t = threadIdx.x;
+    int s = 0;
+    for (int i = t; i < x; i += ST) s += xcount[i];
+    red[t] = s;
+    __syncthreads();
+    for (int h = ST / 2; h >= 1; h >>= 1) {
+        if (t < h) red[t] += red[t + h];
+        __syncthreads();
+    }
+    const int offset = red[0];
+    const int mine = xcount[x];
+    if (x == nx - 1 && t == 0) *count = offset + mine;
+    if (mine == 0) return;   // uniform over the workgroup
+    __syncthreads();
+    const int per = (ny + ST - 1) / ST;
+    const int y0 = t * per;
+    int c = 0;
+    for (int y = y0; y < y0 + per && y < ny; ++y) c += mask[(size_t)x * ny + y];
+    red[t] = c;
+    __syncthreads();
+    for (int h = 1; h < ST; h <<= 1) {   // inclusive scan
+        const int v = t >= h ? red[t - h] : 0;
+        __syncthreads();
+        red[t] += v;
+        __syncthreads();
+    }
+    int pos = offset + red[t] - c;
+    for (int y = y0; y < y0 + per && y < ny; ++y)
+        if (mask[(size_t)x * ny + y]) list[pos++] = x * ny + y;
+}
+
+}  // namespace
+
+namespace conker {
+
+int support_lines(conker_ctx *c, const conker_grid *g, bool f64, const void *fa, const void *fb, Support *out) {
+    const int nx = g->dims[0], ny = g->dims[1], nz = g->dims[2];
+    *out = Support{};
+    if (((uintptr_t)fa & 15) || ((uintptr_t)fb & 15))
+        return fail(c, CONKER_EINVAL, "fields must be 16-byte aligned");
+    const size_t nl = (size_t)nx * ny;
+    const size_t mask_b = (nl + 255) / 256 * 256;
+    const size_t xc_b = ((size_t)nx * sizeof(int) + 255) / 256 * 256;
+    const size_t list_b = (nl * sizeof(int) + 255) / 256 * 256;
+    CK_OK(ws_reserve(c, c->support, mask_b + xc_b + list_b + 256));
+    char *p = (char *)c->support.p;
+    unsigned char *mask = (unsigned char *)p;
+    int *xcount = (int *)(p + mask_b);
+    int *list = (int *)(p + mask_b + xc_b);
+    int *count = (int *)(p + mask_b + xc_b + list_b);
+    const int units = (int)((size_t)nz * (f64 ? 8 : 4) / 16);   // 16-byte words per line
+    {
+        ProfScope ps(c, PK_SUPPORT);
+        hipLaunchKernelGGL(k_line_mask, dim3(nx), dim3(ST), 0, c->stream, (const uint4 *)fa, (const uint4 *)fb, ny,
+                           units, mask, xcount);
+        CK_LAUNCH(c);
+        hipLaunchKernelGGL(k_line_list, dim3(nx), dim3(ST), 0, c->stream, mask, xcount, nx, ny, list, count);
+        CK_LAUNCH(c);
+    }
+    out->mask = mask;
+    out->xcount = xcount;
+    out->list = list;
+    out->count = count;
+    return CONKER_OK;
+}
+
+}  // namespace conker

@@ -179,3 +179,34 @@ def test_diag_argument_errors(ck, ctx):
     # a zero field gives zero sums
     oa, _ = ctx.convolve_diag(grid, f, None, ks, 5)
     assert np.all(oa.cpu().numpy() == 0.0)
+
+
+@pytest.mark.parametrize("dims", [(96, 64, 96), (64, 32, 512)])
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_convolve_diag_sparse_support(ck, ctx, dims, dt):
+    """Fields vanishing on many z-lines and whole x-slabs: only carrying lines
+    are transformed back, the sums are unchanged."""
+    rng = np.random.default_rng(42)
+    nx, ny, nz = dims
+    A, B = _fields(dims, dt, 43)
+    # non-negative (count-like) fields: sums without cancellation, so that the
+    # relative bar measures the arithmetic; the masking is exercised all the same
+    A = np.abs(A)
+    x = np.arange(nx)[:, None]
+    y = np.arange(ny)[None, :]
+    keep = ((x - nx / 2) / (nx / 2)) ** 2 + ((y - ny / 2) / (ny / 2)) ** 2 <= 0.6
+    keep[: nx // 5] = False
+    keep &= rng.random(keep.shape) < 0.8
+    A = A * keep[:, :, None]
+    B = B * keep[:, :, None]
+    radii = _radii(dims)
+    _say("convolve_diag sparse", dims, dt, "carrying lines %.3f" % keep.mean())
+    grid = ck.Grid(dims, (0, 0, 0), 1.0)
+    ks, _ = ctx.make_shell_kernels(grid, radii, TDT[dt])
+    oa, ob = ctx.convolve_diag(grid, torch.from_numpy(A).to(DEV, TDT[dt]), torch.from_numpy(B).to(DEV, TDT[dt]),
+                               ks, 5)
+    ra, rb = _oracle_diag(A, radii, 5), _oracle_diag(B, radii, 5)
+    for k in range(4):
+        ea, eb = relerr(oa.cpu().numpy()[k], ra[k]), relerr(ob.cpu().numpy()[k], rb[k])
+        _say("  n=%d  a %.2e  b %.2e" % (k + 2, ea, eb))
+        assert ea <= TOL[dt] and eb <= TOL[dt], (k + 2, ea, eb)

@@ -374,3 +374,61 @@ def test_fused_matches_separate_calls_bitwise_order_free(ck, ctx, line512_fields
     Sb = ctx.contract_npt(grid, Bt, mb, 3, "split_bf16")
     assert relerr(Wa.cpu().numpy(), Sa.cpu().numpy()) <= 2e-6
     assert relerr(Wb.cpu().numpy(), Sb.cpu().numpy()) <= 2e-6
+
+
+# ---------------------------------------------------------------------------
+# fields that vanish on many z-lines (survey-shaped support): the fused pass
+# transforms only lines that carry field; results must not change
+# ---------------------------------------------------------------------------
+
+def _sparse_support(dims, seed):
+    """Fields zero outside an elliptic cylinder of lines and on whole x-slabs."""
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = dims
+    A = rng.normal(size=dims)
+    B = rng.poisson(2.0, size=dims).astype(np.float64)
+    x = np.arange(nx)[:, None]
+    y = np.arange(ny)[None, :]
+    keep = ((x - nx / 2) / (nx / 2)) ** 2 + ((y - ny / 2) / (ny / 2)) ** 2 <= 0.7
+    keep[: nx // 6] = False
+    keep[nx - nx // 8:] = False
+    A *= keep[:, :, None]
+    B *= keep[:, :, None]
+    B[:, :, : nz // 3] = 0.0       # lines of B vanish partly, never wholly where A is kept
+    A = A.astype(np.float32).astype(np.float64)
+    return A, B, keep
+
+
+@pytest.fixture(scope="module")
+def sparse512_fields():
+    dims = (64, 64, 512)
+    A, B, keep = _sparse_support(dims, 41)
+    radii = [0.5 * k for k in range(1, 31)]
+    return dims, radii, A, B, keep, oc.convolve_shells(A, radii), oc.convolve_shells(B, radii)
+
+
+@pytest.mark.parametrize("prec", ["split_bf16", "f32"])
+@pytest.mark.parametrize("n", [2, 3])
+def test_fused_sparse_support_vs_oracle(ck, ctx, sparse512_fields, prec, n):
+    dims, radii, A, B, keep, maps_a, maps_b = sparse512_fields
+    _say("fused sparse support", prec, n, "carrying lines %.3f" % keep.mean())
+    grid = ck.Grid(dims, (0, 0, 0), 1.0)
+    ks, _ = ctx.make_shell_kernels(grid, radii, torch.float32)
+    Wa, Wb = ctx.convolve_contract(grid, _gpu(A, torch.float32), _gpu(B, torch.float32), ks, n, prec)
+    ea = relerr(Wa.cpu().numpy(), oc.contract(A, maps_a, n))
+    eb = relerr(Wb.cpu().numpy(), oc.contract(B, maps_b, n))
+    _say("  err a %.3e b %.3e" % (ea, eb))
+    assert ea <= 1e-5 and eb <= 1e-5
+
+
+def test_fused_zero_fields_give_zero(ck, ctx, sparse512_fields):
+    dims, radii, A, B, keep, maps_a, maps_b = sparse512_fields
+    grid = ck.Grid(dims, (0, 0, 0), 1.0)
+    ks, _ = ctx.make_shell_kernels(grid, radii[:6], torch.float32)
+    z = torch.zeros(dims, dtype=torch.float32, device=DEV)
+    Wa, Wb = ctx.convolve_contract(grid, z, z.clone(), ks, 3, "split_bf16")
+    assert np.all(Wa.cpu().numpy() == 0.0) and np.all(Wb.cpu().numpy() == 0.0)
+    # one field empty, the other sparse: the empty one still sums to exactly zero
+    Wa, Wb = ctx.convolve_contract(grid, _gpu(A, torch.float32), z, ks, 3, "split_bf16")
+    assert np.all(Wb.cpu().numpy() == 0.0)
+    assert relerr(Wa.cpu().numpy(), oc.contract(A, maps_a[:6], 3)) <= 1e-5

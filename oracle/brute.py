@@ -115,3 +115,28 @@ def pair_factorised_sum(cells, u, shells: Sequence[int], dims, periodic: bool) -
     for a in shells:
         prod = prod * g[:, a]
     return float(prod.sum())
+
+
+def cross_shell_counts(cells0, cells1, v1, dims, periodic: bool, m_max: int) -> np.ndarray:
+    """g[p, m] = sum of v_q over tracers q of set 1 on shell m around tracer p of set 0."""
+    c0 = np.asarray(cells0, dtype=np.int64)
+    c1 = np.asarray(cells1, dtype=np.int64)
+    d = c1[None, :, :] - c0[:, None, :]
+    if periodic:
+        n = np.asarray(dims, dtype=np.int64)
+        d = (d + n // 2) % n - n // 2
+    m = np.floor(np.sqrt((d.astype(np.float64) ** 2).sum(axis=-1)) + 0.5).astype(np.int64)
+    g = np.zeros((len(c0), m_max + 1))
+    for k in range(m_max + 1):
+        g[:, k] = ((m == k) * np.asarray(v1)[None, :]).sum(axis=1)
+    return g
+
+
+def cross_tuple_sum(cells0, u0, cells1, v1, shells: Sequence[int], dims, periodic: bool) -> float:
+    """sum over tracer tuples (p_0 from set 0; p_1 .. p_{n-1} from set 1) of
+    u_{p_0} v_{p_1} ... v_{p_{n-1}} [cell(p_i) - cell(p_0) on shell a_i]."""
+    g = cross_shell_counts(cells0, cells1, v1, dims, periodic, max(shells))
+    prod = np.asarray(u0, dtype=np.float64).copy()
+    for a in shells:
+        prod = prod * g[:, a]
+    return float(prod.sum())

@@ -253,3 +253,57 @@ def npcf(data_pos, rand_pos, dims, origin, cell, radii, n,
 def diagonal(F: np.ndarray, map_1: np.ndarray, n: int) -> float:
     """Equidistant case, Eq. ksinDiag numerator: sum_x F(x) C_1(x)^(n-1)."""
     return float((F * map_1 ** (n - 1)).sum())
+
+
+# ----------------------------------------------------------------------------
+# continuous tracers (Sec. 2.6, Eqs. densitycont, ksin_cont, ksi2_cont)
+# ----------------------------------------------------------------------------
+
+def delta_field(D: np.ndarray, R: np.ndarray) -> np.ndarray:
+    """Relative over-density delta = (D - R) / R of two continuous fields on the
+    grid (Eq. densitycont).  Cells with R = 0 have no random coverage: they lie
+    outside the survey and get delta = 0."""
+    D = np.asarray(D, dtype=np.float64)
+    R = np.asarray(R, dtype=np.float64)
+    out = np.zeros_like(D)
+    m = R != 0.0
+    out[m] = (D[m] - R[m]) / R[m]
+    return out
+
+
+def npcf_continuous(D: np.ndarray, R: np.ndarray, radii_cells: Sequence[float], n: int,
+                    tuples=None) -> np.ndarray:
+    """xi_n = sum_x W_0(x) W_1(x; s_1) ... W_{n-1}(x; s_{n-1}) with W_0 = delta and
+    W_i = delta *** K_i (Eq. ksin_cont): delta is already normalised, so the sum
+    is not divided by anything."""
+    delta = delta_field(D, R)
+    return contract(delta, convolve_shells(delta, radii_cells), n, tuples)
+
+
+# ----------------------------------------------------------------------------
+# cross-correlation of two tracers (Sec. 2.7)
+# ----------------------------------------------------------------------------
+
+def estimator_cross(W_cross: np.ndarray, W_rand_raw: np.ndarray, alpha0: float, alpha1: float,
+                    n: int) -> np.ndarray:
+    """xi = sum Delta_0 W_1..W_{n-1} / sum B_0 B_1..B_{n-1}, where W_i are the maps of
+    tracer 1 and the denominator is built on the common randoms normalised to
+    each tracer: B_0 = alpha0 R_raw, B_i = alpha1 (R_raw *** K_i), i.e.
+    alpha0 alpha1^(n-1) times the contraction of R_raw."""
+    return W_cross / (alpha0 * alpha1 ** (n - 1) * W_rand_raw)
+
+
+def npcf_cross(data0_pos, data1_pos, rand_pos, dims, origin, cell, radii, n,
+               data0_w=None, data1_w=None, rand_w=None, tuples=None):
+    """Cross-correlation of tracer 0 (vertex 0) with tracer 1 (the other vertices),
+    both background-subtracted against one random catalog.  radii in length units."""
+    D0, wd0, _ = histogram(data0_pos, data0_w, origin, cell, dims)
+    D1, wd1, _ = histogram(data1_pos, data1_w, origin, cell, dims)
+    R_raw, wr, _ = histogram(rand_pos, rand_w, origin, cell, dims)
+    N0, a0 = density_deviation(D0, R_raw, wd0, wr)
+    N1, a1 = density_deviation(D1, R_raw, wd1, wr)
+    rc = [float(s) / float(cell) for s in radii]
+    Wc = contract(N0, convolve_shells(N1, rc), n, tuples)
+    Wr = contract(R_raw, convolve_shells(R_raw, rc), n, tuples)
+    return dict(xi=estimator_cross(Wc, Wr, a0, a1, n), W_cross=Wc, W_rand_raw=Wr, alpha0=a0, alpha1=a1,
+                N0=N0, N1=N1, R_raw=R_raw)

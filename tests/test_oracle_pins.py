@@ -375,3 +375,65 @@ def test_distance_calibration_rms_matches_paper():
     rms = float(np.sqrt(((true - true.mean()) ** 2).mean()))
     assert abs(rms - gold["rms"]) < gold["tolerance"], rms
     assert abs(true.mean() - s) < 0.5
+
+
+# ---------------------------------------------------------------------------
+# continuous delta fields (Sec. 2.6) and cross-correlation (Sec. 2.7)
+# ---------------------------------------------------------------------------
+
+def test_delta_field_closed_forms():
+    rng = np.random.default_rng(30)
+    R = rng.uniform(0.5, 2.0, size=(8, 8, 8))
+    R[0] = 0.0                                   # no random coverage
+    assert np.all(oc.delta_field(2.0 * R, R)[1:] == 1.0)
+    assert np.all(oc.delta_field(R, R) == 0.0)
+    D = rng.uniform(0.0, 3.0, size=R.shape)
+    d = oc.delta_field(D, R)
+    assert np.all(d[0] == 0.0)
+    assert np.allclose(d[1:] * R[1:] + R[1:], D[1:], rtol=1e-14, atol=0)
+
+
+def test_continuous_uniform_delta_closed_form():
+    """delta = c on every cell of a periodic grid -> xi_n = N_c c^n prod |S_a| (Eq. ksin_cont)."""
+    dims = (12, 12, 12)
+    R = np.full(dims, 1.5)
+    c = -0.3
+    D = (1.0 + c) * R
+    radii = [1.0, 2.0, 2.5]
+    sizes = [len(oc.shell_offsets(r)) for r in radii]
+    for n in (2, 3, 4):
+        xi = oc.npcf_continuous(D, R, radii, n)
+        for k, t in enumerate(oc.radius_tuples(len(radii), n)):
+            ref = np.prod(dims) * (D[0, 0, 0] / R[0, 0, 0] - 1.0) ** n * np.prod([sizes[a] for a in t])
+            assert math.isclose(xi[k], ref, rel_tol=1e-10)
+
+
+def test_cross_of_a_tracer_with_itself_is_the_auto_estimator():
+    dims, origin, cell = _grid_setup()
+    d, r, wd, wr = _tiny_catalog(40, 200, 12.0, 31, weighted=True)
+    for n in (2, 3):
+        auto = oc.npcf(d, r, dims, origin, cell, [1.0, 2.0, 3.0], n, wd, wr)
+        cross = oc.npcf_cross(d, d, r, dims, origin, cell, [1.0, 2.0, 3.0], n, wd, wd, wr)
+        assert np.allclose(cross["W_cross"], auto["W_delta"], rtol=1e-12, atol=1e-12)
+        assert np.allclose(cross["xi"], auto["xi"], rtol=1e-12, atol=1e-12)
+
+
+def test_cross_matches_explicit_tracer_sums_and_n2_symmetry():
+    """Cross W_n against the two-set tracer sum (vertex 0 from tracer 0 and its
+    randoms, the others from tracer 1 and its randoms); W_2 is symmetric in the
+    two tracers."""
+    dims, origin, cell = (20, 20, 20), (0.0, 0.0, 0.0), 1.0
+    d0, r, w0, wr = _tiny_catalog(60, 240, 10.0, 32, weighted=True)
+    d1, _, w1, _ = _tiny_catalog(50, 10, 10.0, 33, weighted=True)
+    radii = [1.0, 2.0, 3.0]
+    c0, u0, a0, cr, wrr = brute.signed_tracers(d0, r, origin, cell, dims, w0, wr)
+    c1, u1, a1, _, _ = brute.signed_tracers(d1, r, origin, cell, dims, w1, wr)
+    for n in (2, 3, 4):
+        res = oc.npcf_cross(d0, d1, r, dims, origin, cell, radii, n, w0, w1, wr)
+        assert math.isclose(res["alpha0"], a0, rel_tol=1e-14) and math.isclose(res["alpha1"], a1, rel_tol=1e-14)
+        for k, t in enumerate(oc.radius_tuples(len(radii), n)):
+            ref = brute.cross_tuple_sum(c0, u0, c1, u1, [a + 1 for a in t], dims, False)
+            assert math.isclose(res["W_cross"][k], ref, rel_tol=1e-9, abs_tol=1e-8), (n, t)
+    w01 = oc.npcf_cross(d0, d1, r, dims, origin, cell, radii, 2, w0, w1, wr)["W_cross"]
+    w10 = oc.npcf_cross(d1, d0, r, dims, origin, cell, radii, 2, w1, w0, wr)["W_cross"]
+    assert np.allclose(w01, w10, rtol=1e-10, atol=1e-9)

@@ -207,6 +207,59 @@ int conker_convolve_diag(conker_ctx *ctx, const conker_grid *grid, conker_dtype 
                          const void *d_field_a, const void *d_field_b, const void *d_kspec,
                          int n_radii, int n_max, double *d_out_a, double *d_out_b);
 
+/* ---- cross-correlation of two tracers (Sec. 2.7) ----------------------------
+ * Vertex 0 weighs with one field (the "centre" field Delta_0), the shells with
+ * the maps of another (Delta_1).  From stored maps this is conker_contract_npt
+ * called with d_field = Delta_0 and d_maps = the maps of Delta_1.  Without
+ * storing maps:
+ *
+ * conker_convolve_contract_cross: as conker_convolve_contract, but the maps of
+ * d_field_a (d_field_b) are summed against d_centre_a (d_centre_b):
+ *   W_a[t] = sum_x centre_a(x) prod_i maps_a[a_i](x).
+ * d_field_b, d_centre_b and d_W_b: all given or all NULL.  Same support and
+ * alignment rules; lines where the centre fields vanish are skipped. */
+int conker_convolve_contract_cross(conker_ctx *ctx, const conker_grid *grid, conker_dtype dtype,
+                                   const void *d_field_a, const void *d_field_b,
+                                   const void *d_centre_a, const void *d_centre_b, const void *d_kspec,
+                                   int n_radii, int n, conker_mmprec prec, double *d_W_a, double *d_W_b);
+
+/* conker_convolve_diag_cross: conker_convolve_diag with centre fields:
+ *   out_a[(n - 2) * n_radii + m] = sum_x centre_a(x) C_m[field_a](x)^(n-1). */
+int conker_convolve_diag_cross(conker_ctx *ctx, const conker_grid *grid, conker_dtype dtype,
+                               const void *d_field_a, const void *d_field_b,
+                               const void *d_centre_a, const void *d_centre_b, const void *d_kspec,
+                               int n_radii, int n_max, double *d_out_a, double *d_out_b);
+
+/* conker_ratio_cross: xi = W_cross / (alpha0 alpha1^(n-1) W_rand) in float64,
+ * the two-tracer estimator with common randoms normalised to each tracer
+ * (B_0 = alpha0 R_raw for vertex 0, alpha1 R_raw in the shells).  d_alpha0,
+ * d_alpha1: device float64 scalars (from conker_form_delta of each tracer). */
+int conker_ratio_cross(conker_ctx *ctx, const double *d_W_cross, const double *d_W_rand,
+                       const double *d_alpha0, const double *d_alpha1, int n, int64_t count,
+                       double *d_xi);
+
+/* ---- n = 2 in Fourier space (Sec. 2.5, Eq. ksi2_delta; Sec. 2.7) ------------
+ * conker_pair_spectral: for every radius m, from the forward spectra alone
+ * (Parseval, K_m real and even):
+ *   W_aa[m] = sum_x a(x) (K_m *** a)(x),  W_bb[m] likewise for b,
+ *   W_ab[m] = sum_x a(x) (K_m *** b)(x)   (the cross-correlation of a and b),
+ * i.e. conker_contract_npt with n = 2, in one pass over the spectrum and one
+ * read of each kernel octant instead of an inverse transform per radius.
+ * d_field_b may be NULL (then d_W_bb and d_W_ab must be NULL); d_W_bb and
+ * d_W_ab may be NULL when not wanted.  Every supported grid, both dtypes. */
+int conker_pair_spectral(conker_ctx *ctx, const conker_grid *grid, conker_dtype dtype,
+                         const void *d_field_a, const void *d_field_b, const void *d_kspec,
+                         int n_radii, double *d_W_aa, double *d_W_bb, double *d_W_ab);
+
+/* ---- continuous tracers (Sec. 2.6, Eqs. densitycont, ksin_cont) -------------
+ * conker_delta_field: delta = (D - alpha R) / (alpha R) on cells where
+ * alpha R != 0, and 0 on cells without random coverage.  d_alpha: device
+ * float64 scalar, or NULL for 1.  d_delta may alias d_D.  The estimator of a
+ * continuous tracer is then the plain sum W[t] = sum_x delta prod_i C_{a_i}[delta]
+ * (conker_contract_npt / conker_convolve_contract on delta), with no ratio. */
+int conker_delta_field(conker_ctx *ctx, const conker_grid *grid, conker_dtype dtype, const void *d_D,
+                       const void *d_R, const double *d_alpha, void *d_delta);
+
 /* conker_ratio: the estimator xi = W_delta / (alpha^n W_rand) in float64
  * (Eq. ksin_delta with B_i built on R = alpha R_raw).  All pointers are
  * device float64; d_alpha is a scalar. */

@@ -11,6 +11,8 @@ from .api import (  # noqa: F401
     PRECISIONS,
     fused_supported,
     make_job,
+    npcf_continuous,
+    npcf_cross,
     npcf_diag,
     kspec_elems,
     npcf,

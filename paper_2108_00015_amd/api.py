@@ -200,8 +200,12 @@ class Context:
 
     def convolve_contract(self, grid: Grid, field_a: torch.Tensor, field_b: Optional[torch.Tensor],
                           kspec: torch.Tensor, n: int, precision: str = "split_bf16",
-                          out_a: Optional[torch.Tensor] = None, out_b: Optional[torch.Tensor] = None):
-        """Convolution + summation (n = 2, 3) without storing maps; returns (W_a, W_b)."""
+                          out_a: Optional[torch.Tensor] = None, out_b: Optional[torch.Tensor] = None,
+                          centre_a: Optional[torch.Tensor] = None, centre_b: Optional[torch.Tensor] = None):
+        """Convolution + summation (n = 2, 3) without storing maps; returns (W_a, W_b).
+
+        With centre fields (cross-correlation), the maps of field_a are summed against centre_a
+        (and likewise b)."""
         nr = int(kspec.shape[0])
         cnt = num_tuples(nr, n)
         if out_a is None:
@@ -209,10 +213,47 @@ class Context:
         if field_b is not None and out_b is None:
             out_b = torch.empty(max(cnt, 0), dtype=torch.float64, device=field_a.device)
         g = grid.c()
-        self._check(self.lib.conker_convolve_contract(self.h, ct.byref(g), _DT[field_a.dtype], _ptr(field_a),
-                                                      _ptr(field_b), _ptr(kspec), nr, int(n),
-                                                      PRECISIONS[precision], _ptr(out_a), _ptr(out_b)))
+        if centre_a is None and centre_b is None:
+            self._check(self.lib.conker_convolve_contract(self.h, ct.byref(g), _DT[field_a.dtype], _ptr(field_a),
+                                                          _ptr(field_b), _ptr(kspec), nr, int(n),
+                                                          PRECISIONS[precision], _ptr(out_a), _ptr(out_b)))
+        else:
+            self._check(self.lib.conker_convolve_contract_cross(
+                self.h, ct.byref(g), _DT[field_a.dtype], _ptr(field_a), _ptr(field_b), _ptr(centre_a),
+                _ptr(centre_b), _ptr(kspec), nr, int(n), PRECISIONS[precision], _ptr(out_a), _ptr(out_b)))
         return out_a, out_b
+
+    def pair_spectral(self, grid: Grid, field_a: torch.Tensor, field_b: Optional[torch.Tensor],
+                      kspec: torch.Tensor, cross: bool = True):
+        """n = 2 sums from the spectra (Parseval): (W_aa, W_bb, W_ab), each [n_radii] float64
+        (W_bb, W_ab None without field_b; W_ab None unless cross)."""
+        nr = int(kspec.shape[0])
+        dev = field_a.device
+        aa = torch.empty(nr, dtype=torch.float64, device=dev)
+        bb = torch.empty(nr, dtype=torch.float64, device=dev) if field_b is not None else None
+        ab = torch.empty(nr, dtype=torch.float64, device=dev) if (field_b is not None and cross) else None
+        g = grid.c()
+        self._check(self.lib.conker_pair_spectral(self.h, ct.byref(g), _DT[field_a.dtype], _ptr(field_a),
+                                                  _ptr(field_b), _ptr(kspec), nr, _ptr(aa), _ptr(bb), _ptr(ab)))
+        return aa, bb, ab
+
+    def delta_field(self, grid: Grid, D: torch.Tensor, R: torch.Tensor, alpha: Optional[torch.Tensor] = None,
+                    out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """delta = (D - alpha R) / (alpha R), 0 where alpha R = 0 (Eq. densitycont)."""
+        if D.dtype != R.dtype or D.numel() != grid.n_cells or R.numel() != grid.n_cells:
+            raise ValueError("D / R shape or dtype mismatch")
+        out = torch.empty_like(D) if out is None else out
+        g = grid.c()
+        self._check(self.lib.conker_delta_field(self.h, ct.byref(g), _DT[D.dtype], _ptr(D), _ptr(R), _ptr(alpha),
+                                                _ptr(out)))
+        return out
+
+    def ratio_cross(self, Wc: torch.Tensor, Wr: torch.Tensor, alpha0: torch.Tensor, alpha1: torch.Tensor, n: int,
+                    out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        out = torch.empty_like(Wc) if out is None else out
+        self._check(self.lib.conker_ratio_cross(self.h, _ptr(Wc), _ptr(Wr), _ptr(alpha0), _ptr(alpha1), int(n),
+                                                int(Wc.numel()), _ptr(out)))
+        return out
 
     # ---- equidistant (diagonal) sums, Eq. ksinDiag ---------------------------
     def contract_diag(self, grid: Grid, field: torch.Tensor, maps: torch.Tensor, n_max: int) -> torch.Tensor:
@@ -227,8 +268,10 @@ class Context:
         return out
 
     def convolve_diag(self, grid: Grid, field_a: torch.Tensor, field_b: Optional[torch.Tensor],
-                      kspec: torch.Tensor, n_max: int):
-        """Diagonal sums of both fields without storing maps: (out_a, out_b), each [n_max - 1, n_radii]."""
+                      kspec: torch.Tensor, n_max: int, centre_a: Optional[torch.Tensor] = None,
+                      centre_b: Optional[torch.Tensor] = None):
+        """Diagonal sums of both fields without storing maps: (out_a, out_b), each [n_max - 1, n_radii].
+        With centre fields the maps of field_a are summed against centre_a (cross-correlation)."""
         nr = int(kspec.shape[0])
         dt = field_a.dtype
         if kspec.dtype != dt or (field_b is not None and field_b.dtype != dt):
@@ -236,8 +279,13 @@ class Context:
         oa = torch.empty((n_max - 1, nr), dtype=torch.float64, device=field_a.device)
         ob = torch.empty_like(oa) if field_b is not None else None
         g = grid.c()
-        self._check(self.lib.conker_convolve_diag(self.h, ct.byref(g), _DT[dt], _ptr(field_a), _ptr(field_b),
-                                                  _ptr(kspec), nr, int(n_max), _ptr(oa), _ptr(ob)))
+        if centre_a is None and centre_b is None:
+            self._check(self.lib.conker_convolve_diag(self.h, ct.byref(g), _DT[dt], _ptr(field_a), _ptr(field_b),
+                                                      _ptr(kspec), nr, int(n_max), _ptr(oa), _ptr(ob)))
+        else:
+            self._check(self.lib.conker_convolve_diag_cross(
+                self.h, ct.byref(g), _DT[dt], _ptr(field_a), _ptr(field_b), _ptr(centre_a), _ptr(centre_b),
+                _ptr(kspec), nr, int(n_max), _ptr(oa), _ptr(ob)))
         return oa, ob
 
     # ---- batches -----------------------------------------------------------
@@ -366,6 +414,55 @@ def npcf_diag(ctx: Context, grid: Grid, data_pos: torch.Tensor, rand_pos: torch.
     for k in range(n_max - 1):
         ctx.ratio(Wd[k], Wr[k], alpha, k + 2, out=xi[k])
     return dict(xi=xi, W_delta=Wd, W_rand_raw=Wr, alpha=alpha, n_outside=nout)
+
+
+def npcf_continuous(ctx: Context, grid: Grid, D: torch.Tensor, R: torch.Tensor, kspec: torch.Tensor, n: int,
+                    precision: str = "f64", alpha: Optional[torch.Tensor] = None, fused: Optional[bool] = None) -> dict:
+    """Continuous tracers (Sec. 2.6): delta = (D - R) / R, then xi_n = sum_x delta prod_i (delta *** K_{a_i})
+    (Eq. ksin_cont), with no further normalisation.  Returns xi (= W) and delta."""
+    delta = ctx.delta_field(grid, D, R, alpha)
+    nr = int(kspec.shape[0])
+    if fused is None:
+        fused = fused_supported(grid, nr, n, precision, delta.dtype)
+    if fused:
+        xi, _ = ctx.convolve_contract(grid, delta, None, kspec, n, precision)
+    else:
+        maps, _ = ctx.convolve_shells(grid, delta, None, kspec)
+        xi = ctx.contract_npt(grid, delta, maps, n, precision)
+    return dict(xi=xi, delta=delta)
+
+
+def npcf_cross(ctx: Context, grid: Grid, data0_pos: torch.Tensor, data1_pos: torch.Tensor, rand_pos: torch.Tensor,
+               kspec: torch.Tensor, n: int, data0_w: Optional[torch.Tensor] = None,
+               data1_w: Optional[torch.Tensor] = None, rand_w: Optional[torch.Tensor] = None,
+               precision: str = "f64", dtype=torch.float64, fused: Optional[bool] = None) -> dict:
+    """Cross-correlation of tracer 0 (vertex 0) with tracer 1 (the shells), both background-subtracted
+    against one random catalog (Sec. 2.7): xi = W_cross / (alpha0 alpha1^(n-1) W_rand_raw)."""
+    dev = data0_pos.device
+    shape = tuple(int(d) for d in grid.dims)
+    N0 = torch.zeros(shape, dtype=dtype, device=dev)
+    N1 = torch.zeros(shape, dtype=dtype, device=dev)
+    R = torch.zeros(shape, dtype=dtype, device=dev)
+    wsum = torch.zeros(3, dtype=torch.float64, device=dev)
+    nout = torch.zeros(3, dtype=torch.int64, device=dev)
+    alpha = torch.empty(2, dtype=torch.float64, device=dev)
+    ctx.grid_assign(grid, data0_pos, data0_w, N0, wsum[0:1], nout[0:1])
+    ctx.grid_assign(grid, data1_pos, data1_w, N1, wsum[1:2], nout[1:2])
+    ctx.grid_assign(grid, rand_pos, rand_w, R, wsum[2:3], nout[2:3])
+    ctx.form_delta(grid, N0, R, wsum[0:1], wsum[2:3], alpha[0:1])
+    ctx.form_delta(grid, N1, R, wsum[1:2], wsum[2:3], alpha[1:2])
+    nr = int(kspec.shape[0])
+    if fused is None:
+        fused = fused_supported(grid, nr, n, precision, dtype)
+    if fused:
+        # maps of N1 summed against N0; maps of R_raw summed against R_raw
+        Wc, Wr = ctx.convolve_contract(grid, N1, R, kspec, n, precision, centre_a=N0, centre_b=R)
+    else:
+        maps1, mapsR = ctx.convolve_shells(grid, N1, R, kspec)
+        Wc = ctx.contract_npt(grid, N0, maps1, n, precision)
+        Wr = ctx.contract_npt(grid, R, mapsR, n, precision)
+    xi = ctx.ratio_cross(Wc, Wr, alpha[0:1], alpha[1:2], n)
+    return dict(xi=xi, W_cross=Wc, W_rand_raw=Wr, alpha=alpha, n_outside=nout)
 
 
 def npcf(ctx: Context, grid: Grid, data_pos: torch.Tensor, rand_pos: torch.Tensor, kspec: torch.Tensor,

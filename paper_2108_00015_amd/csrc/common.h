@@ -77,6 +77,7 @@ enum ProfKind {
     PK_DIAG_MAPS,
     PK_DIAG_REDUCE,
     PK_SUPPORT,
+    PK_SPECTRAL,
     PK_COUNT
 };
 

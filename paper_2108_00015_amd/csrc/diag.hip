@@ -170,13 +170,14 @@ extern "C" int conker_contract_diag(conker_ctx *c, const conker_grid *g, conker_
     return reduce(c, part, G, n_radii, 1, P, out, nullptr);
 }
 
-extern "C" int conker_convolve_diag(conker_ctx *c, const conker_grid *g, conker_dtype dt, const void *fa,
-                                    const void *fb, const void *kspec, int n_radii, int n_max, double *out_a,
-                                    double *out_b) {
+// Maps from fa (fb), summed against the centre fields ca (cb).
+static int convolve_diag(conker_ctx *c, const conker_grid *g, conker_dtype dt, const void *fa, const void *fb,
+                         const void *ca, const void *cb, const void *kspec, int n_radii, int n_max, double *out_a,
+                         double *out_b) {
     CK_OK(check_common(c, g, dt, n_radii, n_max));
-    if (!fa || !kspec || !out_a) return fail(c, CONKER_EINVAL, "NULL pointer");
-    if ((fb == nullptr) != (out_b == nullptr))
-        return fail(c, CONKER_EINVAL, "field_b and out_b must both be given or both be NULL");
+    if (!fa || !ca || !kspec || !out_a) return fail(c, CONKER_EINVAL, "NULL pointer");
+    if ((fb == nullptr) != (out_b == nullptr) || (fb == nullptr) != (cb == nullptr))
+        return fail(c, CONKER_EINVAL, "field_b, its centre field and out_b must all be given or all be NULL");
     CK_HIP(c, hipSetDevice(c->device));
     const bool f64 = dt == CONKER_F64;
     const size_t nc = ncells(g);
@@ -189,13 +190,25 @@ extern "C" int conker_convolve_diag(conker_ctx *c, const conker_grid *g, conker_
     CK_OK(ws_reserve(c, c->partial, (size_t)n_radii * blocks * 2 * P * sizeof(double)));
     double *part = (double *)c->partial.p;
     Support sup;
-    CK_OK(support_lines(c, g, f64, fa, fb, &sup));
+    CK_OK(support_lines(c, g, f64, ca, cb, &sup));
     CK_OK(fft_forward_pair(c, g, f64, fa, fb, c->spec.p));
     for (int m0 = 0; m0 < n_radii; m0 += B) {
         const int nb = (m0 + B <= n_radii) ? B : n_radii - m0;
         CK_OK(fft_inverse_batch(c, g, f64, c->spec.p, kspec, m0, nb, c->tspec.p, nullptr, nullptr, &sup));
-        CK_OK(fft_inverse_z_diag(c, g, f64, c->tspec.p, nb, fa, fb, P, blocks,
+        CK_OK(fft_inverse_z_diag(c, g, f64, c->tspec.p, nb, ca, cb, P, blocks,
                                  part + (size_t)m0 * blocks * 2 * P, sup.mask));
     }
     return reduce(c, part, blocks, n_radii, 2, P, out_a, out_b);
+}
+
+extern "C" int conker_convolve_diag(conker_ctx *c, const conker_grid *g, conker_dtype dt, const void *fa,
+                                    const void *fb, const void *kspec, int n_radii, int n_max, double *out_a,
+                                    double *out_b) {
+    return convolve_diag(c, g, dt, fa, fb, fa, fb, kspec, n_radii, n_max, out_a, out_b);
+}
+
+extern "C" int conker_convolve_diag_cross(conker_ctx *c, const conker_grid *g, conker_dtype dt, const void *fa,
+                                          const void *fb, const void *ca, const void *cb, const void *kspec,
+                                          int n_radii, int n_max, double *out_a, double *out_b) {
+    return convolve_diag(c, g, dt, fa, fb, ca, cb, kspec, n_radii, n_max, out_a, out_b);
 }

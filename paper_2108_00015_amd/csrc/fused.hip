@@ -250,13 +250,14 @@ __global__ void k_fused_finish(const double *__restrict__ partial, int G, int ns
 
 }  // namespace
 
-extern "C" int conker_convolve_contract(conker_ctx *c, const conker_grid *g, conker_dtype dt, const void *fa,
-                                        const void *fb, const void *kspec, int ns, int n, conker_mmprec prec,
-                                        double *Wa, double *Wb) {
+// Maps from fa (fb), summed against the centre fields ca (cb) of vertex 0.
+static int convolve_contract(conker_ctx *c, const conker_grid *g, conker_dtype dt, const void *fa, const void *fb,
+                             const void *ca, const void *cb, const void *kspec, int ns, int n, conker_mmprec prec,
+                             double *Wa, double *Wb) {
     CK_OK(check_grid(c, g, true));
-    if (!fa || !kspec || !Wa) return fail(c, CONKER_EINVAL, "NULL pointer");
-    if ((fb == nullptr) != (Wb == nullptr))
-        return fail(c, CONKER_EINVAL, "field_b and W_b must both be given or both be NULL");
+    if (!fa || !ca || !kspec || !Wa) return fail(c, CONKER_EINVAL, "NULL pointer");
+    if ((fb == nullptr) != (Wb == nullptr) || (fb == nullptr) != (cb == nullptr))
+        return fail(c, CONKER_EINVAL, "field_b, its centre field and W_b must all be given or all be NULL");
     if (n != 2 && n != 3) return fail(c, CONKER_EUNSUPPORTED, "fused summation supports n = 2 and 3");
     if (dt != CONKER_F32 || (prec != CONKER_MM_F32 && prec != CONKER_MM_SPLIT_BF16))
         return fail(c, CONKER_EUNSUPPORTED, "fused summation supports float32 with f32 or split-bf16");
@@ -268,7 +269,7 @@ extern "C" int conker_convolve_contract(conker_ctx *c, const conker_grid *g, con
     CK_OK(ws_reserve(c, c->spec, cbytes));
     CK_OK(ws_reserve(c, c->tspec, (size_t)ns * cbytes));
     Support sup;
-    CK_OK(support_lines(c, g, false, fa, fb, &sup));
+    CK_OK(support_lines(c, g, false, ca, cb, &sup));
     CK_OK(fft_forward_pair(c, g, false, fa, fb, c->spec.p));
     CK_OK(fft_inverse_batch(c, g, false, c->spec.p, kspec, 0, ns, c->tspec.p, nullptr, nullptr, &sup));
     const void *twz;
@@ -280,13 +281,13 @@ extern "C" int conker_convolve_contract(conker_ctx *c, const conker_grid *g, con
         ProfScope ps(c, PK_FUSED_ZC);
         if (prec == CONKER_MM_SPLIT_BF16)
             hipLaunchKernelGGL(k_zinv_contract<CONKER_MM_SPLIT_BF16>, dim3(G), dim3(NT), 0, c->stream,
-                               (const float2 *)c->tspec.p, ns, nc, nlines, sup.list, sup.count, (const float *)fa,
-                               (const float *)fb,
+                               (const float2 *)c->tspec.p, ns, nc, nlines, sup.list, sup.count, (const float *)ca,
+                               (const float *)cb,
                                (const float2 *)twz, (double *)c->partial.p);
         else
             hipLaunchKernelGGL(k_zinv_contract<CONKER_MM_F32>, dim3(G), dim3(NT), 0, c->stream,
-                               (const float2 *)c->tspec.p, ns, nc, nlines, sup.list, sup.count, (const float *)fa,
-                               (const float *)fb,
+                               (const float2 *)c->tspec.p, ns, nc, nlines, sup.list, sup.count, (const float *)ca,
+                               (const float *)cb,
                                (const float2 *)twz, (double *)c->partial.p);
         CK_LAUNCH(c);
     }
@@ -296,4 +297,17 @@ extern "C" int conker_convolve_contract(conker_ctx *c, const conker_grid *g, con
                        (const double *)c->partial.p, G, ns, n, Wa, Wb);
     CK_LAUNCH(c);
     return CONKER_OK;
+}
+
+extern "C" int conker_convolve_contract(conker_ctx *c, const conker_grid *g, conker_dtype dt, const void *fa,
+                                        const void *fb, const void *kspec, int ns, int n, conker_mmprec prec,
+                                        double *Wa, double *Wb) {
+    return convolve_contract(c, g, dt, fa, fb, fa, fb, kspec, ns, n, prec, Wa, Wb);
+}
+
+extern "C" int conker_convolve_contract_cross(conker_ctx *c, const conker_grid *g, conker_dtype dt,
+                                              const void *fa, const void *fb, const void *ca, const void *cb,
+                                              const void *kspec, int ns, int n, conker_mmprec prec, double *Wa,
+                                              double *Wb) {
+    return convolve_contract(c, g, dt, fa, fb, ca, cb, kspec, ns, n, prec, Wa, Wb);
 }

@@ -185,7 +185,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="cap512_ns800k_r30")
     ap.add_argument("--n", type=int, default=3)
-    ap.add_argument("--prec", default="split_bf16", choices=["split_bf16", "f32"])
+    ap.add_argument("--prec", default="split_bf16", choices=["split_bf16", "f32", "split_f16"])
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()

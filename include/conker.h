@@ -52,9 +52,15 @@ typedef enum { CONKER_F32 = 1, CONKER_F64 = 2 } conker_dtype;
 typedef enum {
     CONKER_MM_F64 = 0,        /* float64 maps, float64 matrix cores            */
     CONKER_MM_F32 = 1,        /* float32 maps, float32 matrix cores            */
-    CONKER_MM_SPLIT_BF16 = 2  /* float32 maps split into three bfloat16 terms,
+    CONKER_MM_SPLIT_BF16 = 2, /* float32 maps split into three bfloat16 terms,
                                  bf16 matrix cores, float32 accumulation over
                                  short chains, float64 across chains          */
+    CONKER_MM_SPLIT_F16 = 3   /* float32 operands scaled by powers of two from
+                                 the largest |value| of each map and of the
+                                 field, split into two float16 terms (22
+                                 significant bits), three of the four term
+                                 products on fp16 matrix cores; accumulation
+                                 as for split-bf16; n >= 3 (n = 2: float32)   */
 } conker_mmprec;
 
 /* Grid of spacing `cell` whose cell (0,0,0) has its lower corner at `origin`
@@ -157,8 +163,8 @@ int64_t conker_num_tuples(int n_radii, int n);
  * for every tuple t = (a_1 <= ... <= a_{n-1}), in lexicographic order.
  *   d_field  dtype [nx][ny][nz];  d_maps dtype [n_radii][nx][ny][nz].
  *   n        2..5;  n_radii 1..64.
- *   prec     CONKER_MM_F64 needs dtype F64; CONKER_MM_F32 and
- *            CONKER_MM_SPLIT_BF16 need dtype F32.
+ *   prec     CONKER_MM_F64 needs dtype F64; CONKER_MM_F32,
+ *            CONKER_MM_SPLIT_BF16 and CONKER_MM_SPLIT_F16 need dtype F32.
  *   d_W      float64 [conker_num_tuples(n_radii, n)], overwritten. */
 int conker_contract_npt(conker_ctx *ctx, const conker_grid *grid, conker_dtype dtype,
                         const void *d_field, const void *d_maps, int n_radii, int n,

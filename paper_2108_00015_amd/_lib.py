@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(PKG, "libconker.so")
 
 OK, EINVAL, ENOMEM, EUNSUPPORTED, EHIP, ERANGE = 0, -1, -2, -3, -4, -5
 F32, F64 = 1, 2
-MM_F64, MM_F32, MM_SPLIT_BF16 = 0, 1, 2
+MM_F64, MM_F32, MM_SPLIT_BF16, MM_SPLIT_F16 = 0, 1, 2, 3
 
 STATUS_NAMES = {OK: "CONKER_OK", EINVAL: "CONKER_EINVAL", ENOMEM: "CONKER_ENOMEM",
                 EUNSUPPORTED: "CONKER_EUNSUPPORTED", EHIP: "CONKER_EHIP", ERANGE: "CONKER_ERANGE"}

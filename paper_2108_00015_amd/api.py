@@ -16,7 +16,8 @@ import torch
 from . import _lib
 
 _DT = {torch.float32: _lib.F32, torch.float64: _lib.F64}
-PRECISIONS = {"f64": _lib.MM_F64, "f32": _lib.MM_F32, "split_bf16": _lib.MM_SPLIT_BF16}
+PRECISIONS = {"f64": _lib.MM_F64, "f32": _lib.MM_F32, "split_bf16": _lib.MM_SPLIT_BF16,
+              "split_f16": _lib.MM_SPLIT_F16}
 
 
 class ConkerError(RuntimeError):

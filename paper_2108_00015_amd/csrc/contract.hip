@@ -34,6 +34,7 @@ namespace {
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int NT = 256;
 constexpr int WAVES = NT / 64;
@@ -410,14 +411,75 @@ struct Group {
 
 constexpr int V2_NT = 512, V2_WAVES = V2_NT / 64, V2_MAXT = 2, V2_MAXU = 4;
 
+// split-fp16: each factor x of an operand (the field, or a map of one radius)
+// is normalised by 2^s_x, s_x = -(floor(log2 max|x|) + 1), so that it lies
+// below 1 in magnitude; an operand (a product of factors) is then scaled by
+// 2^(14 + sum s_x) < 2^14, inside the float16 range with room for rounding,
+// and split into hi = fp16(v), lo = fp16(v - hi).  All scales are powers of
+// two, so scaling and unscaling are exact.  maxabs[m] holds the bits of
+// max|maps[m]| (m < ns) and of max|F| (m = ns).
+__device__ __forceinline__ int norm_exp(unsigned bits) {
+    if (bits == 0u) return 0;
+    const int e = (int)((bits >> 23) & 255u) - 127;   // floor(log2) for normal values
+    const int s = -(e + 1);
+    return s < -100 ? -100 : (s > 100 ? 100 : s);
+}
+
+__device__ __forceinline__ int item_exp(const unsigned *maxabs, int ns, int2 it, bool with_f) {
+    if (it.x < 0) return 0;
+    int s = 14 + norm_exp(maxabs[it.x]);
+    if (it.y >= 0) s += norm_exp(maxabs[it.y]);
+    if (with_f) s += norm_exp(maxabs[ns]);
+    return s;
+}
+
+__device__ __forceinline__ void split2h(const float (&v)[8], f16x8 &hi, f16x8 &lo) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const _Float16 h = (_Float16)v[e];
+        hi[e] = h;
+        lo[e] = (_Float16)(v[e] - (float)h);
+    }
+}
+
+// max |x| of every map row and of F, as float bits (non-negative floats order
+// like their bit patterns): grid (blocks, ns + 1).
+__global__ __launch_bounds__(256) void k_absmax(const float *__restrict__ F, const float *__restrict__ maps,
+                                                size_t nc, int ns, size_t chunk, unsigned *__restrict__ out) {
+    __shared__ float red[4];
+    const int row = blockIdx.y;
+    const float *src = row < ns ? maps + (size_t)row * nc : F;
+    const size_t c0 = (size_t)blockIdx.x * chunk;
+    const size_t c1 = c0 + chunk < nc ? c0 + chunk : nc;
+    float m = 0.f;
+    for (size_t i = c0 + (size_t)threadIdx.x * 4; i < c1; i += 256 * 4) {
+        const float4 v = *reinterpret_cast<const float4 *>(src + i);
+        m = fmaxf(m, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
+    }
+    for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        m = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+        atomicMax(out + row, __float_as_uint(m));
+    }
+}
+
+__global__ void k_zero_u32(unsigned *p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
 template <int PREC>
 __global__ __launch_bounds__(V2_NT) void k_mm2(const float *__restrict__ F, const float *__restrict__ maps, size_t nc,
                                               int ns, size_t chunk, const int2 *__restrict__ ritems,
                                               const int2 *__restrict__ citems, const int2 *__restrict__ tiles,
-                                              const Group *__restrict__ groups, int G, double *__restrict__ partial) {
+                                              const Group *__restrict__ groups, int G, double *__restrict__ partial,
+                                              const unsigned *__restrict__ maxabs) {
     constexpr bool SPLIT = PREC == CONKER_MM_SPLIT_BF16;
-    constexpr int NP = SPLIT ? 3 : 1;                       // operand planes
-    constexpr int EB = SPLIT ? 2 : 4;                       // bytes per operand element
+    constexpr bool F16 = PREC == CONKER_MM_SPLIT_F16;
+    constexpr int NP = SPLIT ? 3 : (F16 ? 2 : 1);           // operand planes
+    constexpr int EB = (SPLIT || F16) ? 2 : 4;              // bytes per operand element
     extern __shared__ __align__(16) unsigned char smem[];
     const Group gr = groups[blockIdx.y];
     float *sm_maps = reinterpret_cast<float *>(smem);       // [ns][64]
@@ -430,6 +492,7 @@ __global__ __launch_bounds__(V2_NT) void k_mm2(const float *__restrict__ F, cons
     // build units of this thread: unit u -> (item, half); items of A first, then B
     int2 uit[V2_MAXU];
     int uitem[V2_MAXU];
+    int uexp[V2_MAXU];   // split-fp16 operand scale exponents
 #pragma unroll
     for (int k = 0; k < V2_MAXU; ++k) {
         const int u = threadIdx.x + k * V2_NT;
@@ -438,6 +501,10 @@ __global__ __launch_bounds__(V2_NT) void k_mm2(const float *__restrict__ F, cons
         if (item < na) uit[k] = ritems[gr.rt0 * 32 + item];
         else if (item < na + nb) uit[k] = citems[gr.ct0 * 32 + (item - na)];
         else uit[k] = int2{-3, -1};
+        uexp[k] = 0;
+        if constexpr (F16) {
+            if (uit[k].x >= 0) uexp[k] = item_exp(maxabs, ns, uit[k], item < na);
+        }
     }
     // tiles of this wave
     int ta[V2_MAXT], tb[V2_MAXT];
@@ -512,6 +579,14 @@ __global__ __launch_bounds__(V2_NT) void k_mm2(const float *__restrict__ F, cons
                     d[(0 * nrows + row) * 2 + half] = hi;
                     d[(1 * nrows + row) * 2 + half] = mi;
                     d[(2 * nrows + row) * 2 + half] = lo;
+                } else if constexpr (F16) {
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) v[e] = ldexpf(v[e], uexp[k]);
+                    f16x8 hi, lo;
+                    split2h(v, hi, lo);
+                    f16x8 *d = reinterpret_cast<f16x8 *>(dst);
+                    d[(0 * nrows + row) * 2 + half] = hi;
+                    d[(1 * nrows + row) * 2 + half] = lo;
                 } else {
                     float4 *d = reinterpret_cast<float4 *>(dst) + (row * 2 + half) * 2;
                     d[0] = float4{v[0], v[1], v[2], v[3]};
@@ -536,6 +611,14 @@ __global__ __launch_bounds__(V2_NT) void k_mm2(const float *__restrict__ F, cons
                     acc[k] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bh, acc[k], 0, 0, 0);
                     acc[k] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bm, acc[k], 0, 0, 0);
                     acc[k] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc[k], 0, 0, 0);
+                } else if constexpr (F16) {
+                    const f16x8 *A = reinterpret_cast<const f16x8 *>(sA);
+                    const f16x8 *B = reinterpret_cast<const f16x8 *>(sB);
+                    const f16x8 ah = A[(0 * na + ta[k]) * 2 + h], al = A[(1 * na + ta[k]) * 2 + h];
+                    const f16x8 bh = B[(0 * nb + tb[k]) * 2 + h], bl = B[(1 * nb + tb[k]) * 2 + h];
+                    acc[k] = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, bh, acc[k], 0, 0, 0);
+                    acc[k] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bl, acc[k], 0, 0, 0);
+                    acc[k] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bh, acc[k], 0, 0, 0);
                 } else {
                     const float4 *A = reinterpret_cast<const float4 *>(sA) + (ta[k] * 2 + h) * 2;
                     const float4 *B = reinterpret_cast<const float4 *>(sB) + (tb[k] * 2 + h) * 2;
@@ -565,10 +648,17 @@ __global__ __launch_bounds__(V2_NT) void k_mm2(const float *__restrict__ F, cons
         if (!tl[k]) continue;
         const int tile = gr.t0 + w + k * V2_WAVES;
         double *out = partial + ((size_t)tile * G + blockIdx.x) * 1024;
+        int ecol = 0;
+        if constexpr (F16) ecol = item_exp(maxabs, ns, citems[(gr.ct0 * 32) + tb[k]], false);
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
             const int i = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3), j = lane & 31;
-            out[i * 32 + j] = dacc[k][v] + (double)acc[k][v];
+            double x = dacc[k][v] + (double)acc[k][v];
+            if constexpr (F16) {
+                const int erow = item_exp(maxabs, ns, ritems[gr.rt0 * 32 + (ta[k] - r) + i], true);
+                x = ldexp(x, -(erow + ecol));
+            }
+            out[i * 32 + j] = x;
         }
     }
 }
@@ -843,9 +933,10 @@ extern "C" int conker_contract_npt(conker_ctx *c, const conker_grid *g, conker_d
     if (dt != CONKER_F32 && dt != CONKER_F64) return fail(c, CONKER_EINVAL, "bad dtype");
     if (prec == CONKER_MM_F64 && dt != CONKER_F64)
         return fail(c, CONKER_EINVAL, "float64 summation needs float64 maps");
-    if ((prec == CONKER_MM_F32 || prec == CONKER_MM_SPLIT_BF16) && dt != CONKER_F32)
-        return fail(c, CONKER_EINVAL, "float32 and split-bf16 summation need float32 maps");
-    if (prec != CONKER_MM_F64 && prec != CONKER_MM_F32 && prec != CONKER_MM_SPLIT_BF16)
+    if ((prec == CONKER_MM_F32 || prec == CONKER_MM_SPLIT_BF16 || prec == CONKER_MM_SPLIT_F16) && dt != CONKER_F32)
+        return fail(c, CONKER_EINVAL, "float32, split-bf16 and split-f16 summation need float32 maps");
+    if (prec != CONKER_MM_F64 && prec != CONKER_MM_F32 && prec != CONKER_MM_SPLIT_BF16 &&
+        prec != CONKER_MM_SPLIT_F16)
         return fail(c, CONKER_EINVAL, "bad precision");
     const size_t nc = ncells(g);
     if (nc % 16) return fail(c, CONKER_EUNSUPPORTED, "cell count must be a multiple of 16");
@@ -867,9 +958,22 @@ extern "C" int conker_contract_npt(conker_ctx *c, const conker_grid *g, conker_d
         chunk = (chunk + 63) / 64 * 64;
         G = (nc + chunk - 1) / chunk;
         const int te = 1024;
+        const size_t full_b = (size_t)p2.n_tiles * te * (RED_S + 1) * sizeof(double);
         CK_OK(ws_reserve(c, c->partial, (size_t)p2.n_tiles * G * te * sizeof(double)));
-        CK_OK(ws_reserve(c, c->full, (size_t)p2.n_tiles * te * (RED_S + 1) * sizeof(double)));
+        CK_OK(ws_reserve(c, c->full, full_b + 1024));
         double *part = (double *)c->partial.p;
+        unsigned *maxabs = nullptr;
+        if (prec == CONKER_MM_SPLIT_F16) {   // largest |value| of every map and of F
+            ProfScope ps(c, PK_CONTRACT_DOT);
+            maxabs = (unsigned *)((char *)c->full.p + full_b);
+            hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(128), 0, c->stream, maxabs, ns + 1);
+            CK_LAUNCH(c);
+            const size_t mchunk = 64 * 1024;
+            const dim3 mg((unsigned)((nc + mchunk - 1) / mchunk), (unsigned)(ns + 1));
+            hipLaunchKernelGGL(k_absmax, mg, dim3(256), 0, c->stream, (const float *)F, (const float *)maps, nc, ns,
+                               mchunk, maxabs);
+            CK_LAUNCH(c);
+        }
         {
             ProfScope ps(c, PK_CONTRACT_MM);
             dim3 grid((unsigned)G, (unsigned)p2.n_groups);
@@ -879,18 +983,27 @@ extern "C" int conker_contract_npt(conker_ctx *c, const conker_grid *g, conker_d
                                               hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024));
                 CK_HIP(c, hipFuncSetAttribute((const void *)k_mm2<CONKER_MM_F32>,
                                               hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024));
+                CK_HIP(c, hipFuncSetAttribute((const void *)k_mm2<CONKER_MM_SPLIT_F16>,
+                                              hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024));
                 attr_set = true;
             }
             if (prec == CONKER_MM_SPLIT_BF16)
                 hipLaunchKernelGGL(k_mm2<CONKER_MM_SPLIT_BF16>, grid, dim3(V2_NT), p2.max_lds, c->stream,
                                    (const float *)F, (const float *)maps, nc, ns, chunk,
                                    (const int2 *)p2.ritems->p, (const int2 *)p2.citems->p,
-                                   (const int2 *)p2.tiles->p, (const Group *)p2.groups->p, (int)G, part);
+                                   (const int2 *)p2.tiles->p, (const Group *)p2.groups->p, (int)G, part,
+                                   (const unsigned *)nullptr);
+            else if (prec == CONKER_MM_SPLIT_F16)
+                hipLaunchKernelGGL(k_mm2<CONKER_MM_SPLIT_F16>, grid, dim3(V2_NT), p2.max_lds, c->stream,
+                                   (const float *)F, (const float *)maps, nc, ns, chunk,
+                                   (const int2 *)p2.ritems->p, (const int2 *)p2.citems->p,
+                                   (const int2 *)p2.tiles->p, (const Group *)p2.groups->p, (int)G, part,
+                                   (const unsigned *)maxabs);
             else
                 hipLaunchKernelGGL(k_mm2<CONKER_MM_F32>, grid, dim3(V2_NT), p2.max_lds, c->stream, (const float *)F,
                                    (const float *)maps, nc, ns, chunk, (const int2 *)p2.ritems->p,
                                    (const int2 *)p2.citems->p, (const int2 *)p2.tiles->p,
-                                   (const Group *)p2.groups->p, (int)G, part);
+                                   (const Group *)p2.groups->p, (int)G, part, (const unsigned *)nullptr);
             CK_LAUNCH(c);
         }
         ProfScope ps(c, PK_CONTRACT_REDUCE);

@@ -250,6 +250,14 @@ CONTRACT_CASES = [
     ("split_bf16", 3, 64, (32, 32, 32)),
     ("f64", 4, 30, (32, 32, 32)),
     ("f64", 5, 20, (32, 32, 32)),
+    # split float16 with power-of-two operand scaling
+    ("split_f16", 2, 30, (32, 32, 32)),
+    ("split_f16", 3, 30, (32, 64, 64)),
+    ("split_f16", 3, 40, (32, 32, 32)),
+    ("split_f16", 4, 9, (32, 32, 32)),
+    ("split_f16", 4, 30, (32, 32, 32)),
+    ("split_f16", 5, 6, (32, 32, 32)),
+    ("split_f16", 5, 20, (32, 32, 32)),
 ]
 
 
@@ -270,6 +278,29 @@ def test_contract_vs_oracle(ck, ctx, prec, n, ns, dims):
     bad = np.argsort(-np.abs(W - ref))[:5]
     _say("  err %.3e worst tuples %s" % (err, [oc.radius_tuples(ns, n)[i] for i in bad]))
     assert err <= (1e-12 if prec == "f64" else 1e-5)
+
+
+@pytest.mark.parametrize("n", [3, 4, 5])
+def test_split_f16_wide_dynamic_range(ck, ctx, n):
+    """Maps and fields spanning many binades (count-like maps of very different
+    sizes per radius, a field with values from 1e-6 to 1e4): the per-map
+    power-of-two scaling keeps every operand inside the float16 range."""
+    dims = (32, 32, 32)
+    ns = 12
+    rng = np.random.default_rng(200 + n)
+    F = rng.normal(size=dims) * np.exp(rng.uniform(np.log(1e-6), np.log(1e4), size=dims))
+    scale = np.exp(np.linspace(np.log(1e-3), np.log(3e4), ns))[:, None, None, None]
+    maps = (rng.poisson(5.0, size=(ns,) + dims) + 0.5) * scale
+    F = F.astype(np.float32).astype(np.float64)
+    maps = maps.astype(np.float32).astype(np.float64)
+    grid = ck.Grid(dims, (0, 0, 0), 1.0)
+    W = ctx.contract_npt(grid, _gpu(F, torch.float32), _gpu(maps, torch.float32), n, "split_f16").cpu().numpy()
+    ref = oc.contract(F, maps, n)
+    # per tuple, relative to the largest |term| sum of that tuple's scale
+    mag = oc.contract(np.abs(F), maps, n)
+    err = float(np.max(np.abs(W - ref) / mag))
+    _say("split_f16 wide range n=%d: max |err| / sum|terms| %.3e" % (n, err))
+    assert err <= 1e-5
 
 
 def test_contract_argument_errors(ck, ctx):

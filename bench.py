@@ -100,6 +100,10 @@ def measured_traffic(kind, workload, n):
     return (t["fetch_kib_per_dispatch"] * t["fetch_factor"] + t["write_kib_per_dispatch"] * t["write_factor"]) * 1024.0
 
 
+def stages_use_fused(prof):
+    return "fused_zinv_contract" in prof
+
+
 def support_fractions(w, data, rand):
     """Fractions of z-lines (x, y) and of x-slabs holding at least one catalog
     point (the lines on which N or R_raw can be non-zero)."""
@@ -145,13 +149,20 @@ def cpu_baseline(w, data, rand, n, sample_radii=1):
                 stage_seconds=dict(mapping=t1 - t0, convolution=t2 - t1, summation=t3 - t2))
 
 
-def run_path(ck, torch, ctx, grid, w, dpos, dw, rpos, rw, n, dtype, prec, steps, warmup, profile):
+def run_path(ck, torch, ctx, grid, w, dpos, dw, rpos, rw, n, dtype, prec, steps, warmup, profile,
+             mode="npcf", field_at_a_time=False):
     ks, _ = ctx.make_shell_kernels(grid, w.radii, dtype)
     torch.cuda.synchronize()
     bufs = {}
 
     def step():
-        return ck.npcf(ctx, grid, dpos, rpos, ks, n, dw, rw, precision=prec, dtype=dtype, bufs=bufs)
+        if mode == "diag":
+            out = ck.npcf_diag(ctx, grid, dpos, rpos, ks, n, dw, rw, dtype=dtype)
+            return dict(out, W_delta=out["W_delta"].reshape(-1), W_rand_raw=out["W_rand_raw"].reshape(-1))
+        if mode == "pair2":
+            return ck.npcf_pair2(ctx, grid, dpos, rpos, ks, dw, rw, dtype=dtype)
+        return ck.npcf(ctx, grid, dpos, rpos, ks, n, dw, rw, precision=prec, dtype=dtype, bufs=bufs,
+                       field_at_a_time=field_at_a_time)
 
     for _ in range(warmup):
         out = step()
@@ -178,6 +189,79 @@ def run_path(ck, torch, ctx, grid, w, dpos, dw, rpos, rw, n, dtype, prec, steps,
     return res
 
 
+MOCKS_NAME = "mocks64_periodic_grid96-256_r16"
+
+
+def bench_mocks(args):
+    """A batch of 64 independent periodic mocks (grids of 96..256 cells a side,
+    50k..400k Neyman-Scott points + 10x uniform randoms each, 16 shells 10..85,
+    n = 3, mixed precision), planned once and replayed as one HIP graph.  One
+    step = the whole batch; value = shell convolutions per second (2 x 16 per mock)."""
+    import torch
+    import paper_2108_00015_amd as ck
+    import synth
+    sizes = synth.mock_sizes(64, 400)
+    t = time.perf_counter()
+    cats = [synth.mock_catalog(j, g, n) for j, (g, n) in enumerate(sizes)]
+    npts = sum(len(d) + len(r) for d, r in cats)
+    log("64 mocks: %d points in %.1f s" % (npts, time.perf_counter() - t))
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream()
+    ctx = ck.Context(0, stream=stream)
+    radii = synth.MOCK_RADII
+    ns = len(radii)
+    gmax = max(g for g, _ in sizes) ** 3
+    dt = torch.float32
+    N = torch.empty(gmax, dtype=dt, device=dev)
+    R = torch.empty(gmax, dtype=dt, device=dev)
+    mN = torch.empty(ns * gmax, dtype=dt, device=dev)
+    mR = torch.empty(ns * gmax, dtype=dt, device=dev)
+    kspecs, jobs = {}, []
+    for (g, _), (d, r) in zip(sizes, cats):
+        grid = ck.Grid((g, g, g), (0.0, 0.0, 0.0), 5.0)
+        if g not in kspecs:
+            kspecs[g] = ctx.make_shell_kernels(grid, radii, dt)[0]
+        jobs.append(ck.make_job(grid, kspecs[g], args.n, args.prec, torch.from_numpy(d.pos).to(dev),
+                                torch.from_numpy(r.pos).to(dev), N=N, R=R, maps_N=mN, maps_R=mR, fused=False))
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    ctx.batch_plan(jobs)
+    log("plan (one eager pass, allocations): %.2f s" % (time.perf_counter() - t))
+    ctx.batch_capture()
+    for _ in range(args.warmup):
+        ctx.batch_launch()
+    ctx.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        e0.record(stream)
+        for _ in range(args.steps):
+            ctx.batch_launch()
+        e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    log("  %.2f ms per batch of 64 mocks" % ms)
+    # per-kind launch times of one eager pass (outside the timed region)
+    ctx.profile(True)
+    ctx.batch_run()
+    ctx.synchronize()
+    stages = {k: dict(launches=v[0], ms=round(v[1], 3)) for k, v in ctx.profile_read().items()}
+    ctx.profile(False)
+    total_cells = sum(g ** 3 for g, _ in sizes)
+    line = {
+        "metric": "shell-convs/s over a batch of 64 mocks (graph replay)",
+        "value": round(2 * ns * len(sizes) / (ms / 1e3), 3),
+        "unit": "shell-convs/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": MOCKS_NAME, "n_mocks": len(sizes), "grids": sorted({g for g, _ in sizes}),
+                   "total_cells": total_cells, "points": npts, "n_radii": ns, "n": args.n,
+                   "summation": args.prec, "fft": "f32", "execution": "one HIP graph per batch"},
+        "roofline": None, "cpu_baseline": None, "stages_eager": stages,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -188,11 +272,20 @@ def main():
     ap.add_argument("--prec", default="split_bf16", choices=["split_bf16", "f32", "split_f16"])
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--mode", default="npcf", choices=["npcf", "diag", "pair2"],
+                    help="npcf: all tuples of order n; diag: equidistant sums for orders 2..n without maps; "
+                         "pair2: n = 2 from the spectra")
+    ap.add_argument("--field-at-a-time", action="store_true",
+                    help="separate path with one maps buffer, N then R (large grids)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the hot path is measured on a single MI355X "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == MOCKS_NAME:
+        bench_mocks(args)
+        return
 
     import torch
     import paper_2108_00015_amd as ck
@@ -215,13 +308,13 @@ def main():
 
     log("mixed path (float32 FFT, %s summation): warmup %d, steps %d" % (args.prec, args.warmup, args.steps))
     mixed = run_path(ck, torch, ctx, grid, w, dpos, dw, rpos, rw, args.n, torch.float32, args.prec,
-                     args.steps, args.warmup, True)
+                     args.steps, args.warmup, True, args.mode, args.field_at_a_time)
     log("  %.2f ms/step" % mixed["ms"])
     fp64 = None
     if not args.no_fp64:
         log("float64 path: warmup %d, steps %d" % (args.warmup, args.steps))
         fp64 = run_path(ck, torch, ctx, grid, w, dpos, dw, rpos, rw, args.n, torch.float64, "f64",
-                        args.steps, args.warmup, True)
+                        args.steps, args.warmup, True, args.mode, args.field_at_a_time)
         log("  %.2f ms/step" % fp64["ms"])
 
     batch = min(int(os.environ.get("CONKER_RADIUS_BATCH", str(ns))), ns)
@@ -271,8 +364,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "grid": list(w.dims), "cell": w.cell, "n_radii": ns,
                    "radii": [w.radii[0], w.radii[-1]], "n": args.n, "n_data": len(data),
-                   "n_randoms": len(rand), "weights": "log-normal sigma 0.2",
-                   "summation": args.prec, "fft": "f32",
+                   "n_randoms": len(rand), "weights": "log-normal sigma 0.2" if data.w is not None else "unit",
+                   "summation": args.prec, "fft": "f32", "mode": args.mode,
+                   "maps": ("never stored" if (args.mode != "npcf" or stages_use_fused(mixed["prof"]))
+                            else ("one field at a time" if args.field_at_a_time else "both fields")),
                    "carrying_lines": round(fl, 4), "carrying_x_slabs": round(fx, 4)},
         "s_to_W3_mixed": round(s_mixed, 5),
         "s_to_W3_fp64": round(fp64["ms"] / 1e3, 5) if fp64 else None,

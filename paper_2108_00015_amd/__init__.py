@@ -14,6 +14,7 @@ from .api import (  # noqa: F401
     npcf_continuous,
     npcf_cross,
     npcf_diag,
+    npcf_pair2,
     kspec_elems,
     npcf,
     num_tuples,

@@ -417,6 +417,26 @@ def npcf_diag(ctx: Context, grid: Grid, data_pos: torch.Tensor, rand_pos: torch.
     return dict(xi=xi, W_delta=Wd, W_rand_raw=Wr, alpha=alpha, n_outside=nout)
 
 
+def npcf_pair2(ctx: Context, grid: Grid, data_pos: torch.Tensor, rand_pos: torch.Tensor, kspec: torch.Tensor,
+               data_w: Optional[torch.Tensor] = None, rand_w: Optional[torch.Tensor] = None,
+               dtype=torch.float64) -> dict:
+    """The 2pcf (Eq. ksi2_delta) with both sums taken in Fourier space (conker_pair_spectral):
+    no inverse transform and no map.  Returns xi, W_delta, W_rand_raw ([n_radii] float64), alpha."""
+    dev = data_pos.device
+    shape = tuple(int(d) for d in grid.dims)
+    N = torch.zeros(shape, dtype=dtype, device=dev)
+    R = torch.zeros(shape, dtype=dtype, device=dev)
+    wsum = torch.zeros(2, dtype=torch.float64, device=dev)
+    nout = torch.zeros(2, dtype=torch.int64, device=dev)
+    alpha = torch.empty(1, dtype=torch.float64, device=dev)
+    ctx.grid_assign(grid, data_pos, data_w, N, wsum[0:1], nout[0:1])
+    ctx.grid_assign(grid, rand_pos, rand_w, R, wsum[1:2], nout[1:2])
+    ctx.form_delta(grid, N, R, wsum[0:1], wsum[1:2], alpha)
+    Wd, Wr, _ = ctx.pair_spectral(grid, N, R, kspec, cross=False)
+    xi = ctx.ratio(Wd, Wr, alpha, 2)
+    return dict(xi=xi, W_delta=Wd, W_rand_raw=Wr, alpha=alpha, n_outside=nout)
+
+
 def npcf_continuous(ctx: Context, grid: Grid, D: torch.Tensor, R: torch.Tensor, kspec: torch.Tensor, n: int,
                     precision: str = "f64", alpha: Optional[torch.Tensor] = None, fused: Optional[bool] = None) -> dict:
     """Continuous tracers (Sec. 2.6): delta = (D - R) / R, then xi_n = sum_x delta prod_i (delta *** K_{a_i})
@@ -469,13 +489,15 @@ def npcf_cross(ctx: Context, grid: Grid, data0_pos: torch.Tensor, data1_pos: tor
 def npcf(ctx: Context, grid: Grid, data_pos: torch.Tensor, rand_pos: torch.Tensor, kspec: torch.Tensor,
          n: int, data_w: Optional[torch.Tensor] = None, rand_w: Optional[torch.Tensor] = None,
          precision: str = "f64", dtype=torch.float64, bufs: Optional[dict] = None,
-         fused: Optional[bool] = None) -> dict:
+         fused: Optional[bool] = None, field_at_a_time: bool = False) -> dict:
     """Mapping -> convolution -> summation -> estimator, chaining the C ABI calls.
 
     `bufs` may hold preallocated tensors (keys: N, R, maps_N, maps_R, wsum, nout, alpha) that are
     reused across calls.  With `fused` (default: whenever supported) the convolution and summation
-    run as one call that never stores the maps.  Returns xi, W_delta, W_rand_raw, alpha and the
-    buffers (all on the GPU).
+    run as one call that never stores the maps.  With `field_at_a_time` (separate path) the maps of
+    N and R are made and summed one field after the other in a single maps buffer (half the memory;
+    each field's radii are paired in the transforms).  Returns xi, W_delta, W_rand_raw, alpha and
+    the buffers (all on the GPU).
     """
     nr_ = int(kspec.shape[0])
     if fused is None:
@@ -499,6 +521,13 @@ def npcf(ctx: Context, grid: Grid, data_pos: torch.Tensor, rand_pos: torch.Tenso
     ctx.form_delta(grid, b["N"], b["R"], b["wsum"][0:1], b["wsum"][1:2], b["alpha"])
     if fused:
         Wd, Wr = ctx.convolve_contract(grid, b["N"], b["R"], kspec, n, precision)
+    elif field_at_a_time:
+        if "maps_N" not in b:
+            b["maps_N"] = torch.empty((nr,) + shape, dtype=dtype, device=dev)
+        ctx.convolve_shells(grid, b["N"], None, kspec, b["maps_N"])
+        Wd = ctx.contract_npt(grid, b["N"], b["maps_N"], n, precision)
+        ctx.convolve_shells(grid, b["R"], None, kspec, b["maps_N"])
+        Wr = ctx.contract_npt(grid, b["R"], b["maps_N"], n, precision)
     else:
         if "maps_N" not in b:
             b["maps_N"] = torch.empty((nr,) + shape, dtype=dtype, device=dev)

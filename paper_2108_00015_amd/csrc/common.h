@@ -173,9 +173,12 @@ int fft_shell_pair(conker_ctx *ctx, const conker_grid *g, double lo_a, double hi
 // With `sup` (maps_a NULL only): outputs are needed on carrying lines only; the
 // x pass writes carrying x-slabs, the y pass skips empty slabs and writes
 // carrying lines.
+// With pair_ns > 0 (one real field, maps_b NULL): radius pairing.  m0 and nb
+// count slots; slot j is multiplied by K_{2j} + i K_{2j+1} (K_{2j} alone when
+// 2j + 1 = pair_ns) and unpacked into maps_a rows 2j and 2j + 1.
 int fft_inverse_batch(conker_ctx *ctx, const conker_grid *g, bool f64,
                       const void *spec, const void *kspec, int m0, int nb, void *tspec,
-                      void *maps_a, void *maps_b, const Support *sup = nullptr);
+                      void *maps_a, void *maps_b, const Support *sup = nullptr, int pair_ns = 0);
 // Inverse z pass of tspec[0 .. nb) (after fft_inverse_batch with maps_a NULL)
 // with the equidistant sums sum_x F(x) C_m(x)^p, p = 1 .. pmax (1..4), of the
 // real part against fa and the imaginary part against fb (NULL: none), in

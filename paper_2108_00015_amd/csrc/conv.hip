@@ -80,13 +80,17 @@ extern "C" int conker_convolve_shells(conker_ctx *c, const conker_grid *g, conke
     const bool f64 = dt == CONKER_F64;
     const size_t nc = ncells(g);
     const size_t cbytes = nc * (f64 ? sizeof(double2) : sizeof(float2));
-    const int B = batch_radii(c, cbytes, n_radii, cbytes);
+    // one field: pair the radii instead (slot j carries C_{2j} + i C_{2j+1})
+    const bool pair = fb == nullptr && n_radii > 1;
+    const int slots = pair ? (n_radii + 1) / 2 : n_radii;
+    const int B = batch_radii(c, cbytes, slots, cbytes);
     CK_OK(ws_reserve(c, c->spec, cbytes));
     CK_OK(ws_reserve(c, c->tspec, (size_t)B * cbytes));
     CK_OK(fft_forward_pair(c, g, f64, fa, fb, c->spec.p));
-    for (int m0 = 0; m0 < n_radii; m0 += B) {
-        const int nb = (m0 + B <= n_radii) ? B : n_radii - m0;
-        CK_OK(fft_inverse_batch(c, g, f64, c->spec.p, kspec, m0, nb, c->tspec.p, ma, mb));
+    for (int m0 = 0; m0 < slots; m0 += B) {
+        const int nb = (m0 + B <= slots) ? B : slots - m0;
+        CK_OK(fft_inverse_batch(c, g, f64, c->spec.p, kspec, m0, nb, c->tspec.p, ma, mb, nullptr,
+                                pair ? n_radii : 0));
     }
     return CONKER_OK;
 }

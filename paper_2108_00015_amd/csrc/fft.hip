@@ -335,6 +335,9 @@ struct OpMulK {
     const C *src;   // spec at this tile and this thread's column
     C *dst;
     const T *kcol;  // octant of radius m at this thread's (ky, kz) column
+    // radius pairing (one real field): slot m multiplies by K_{2m} + i K_{2m+1}
+    int pair, ns;
+    const T *kcol_b;
     template <int TC> __device__ void begin() {
         const int w = blockIdx.x;
         int tile;
@@ -356,7 +359,14 @@ struct OpMulK {
     }
     __device__ void set_radius() {
         const int oy = fold(g.p0, d.ny), oz = fold(g.p1 + col, d.nz);
-        kcol = kspec + (size_t)(m0 + m) * kel + ((size_t)oy * (d.nz / 2 + 1) + oz) * (d.nx / 2 + 1);
+        const size_t co = ((size_t)oy * (d.nz / 2 + 1) + oz) * (d.nx / 2 + 1);
+        if (pair) {
+            const int ra = 2 * (m0 + m), rb = ra + 1;
+            kcol = kspec + (size_t)ra * kel + co;
+            kcol_b = rb < ns ? kspec + (size_t)rb * kel + co : nullptr;
+        } else {
+            kcol = kspec + (size_t)(m0 + m) * kel + co;
+        }
         dst = tspec + (size_t)m * nc + g.base + col;
     }
     __device__ int iters() const { return loop ? nb : 1; }
@@ -367,14 +377,22 @@ struct OpMulK {
         }
     }
     __device__ C load(int i, int) const {
-        const T kv = kcol[fold(i, d.nx)];
+        const int fi = fold(i, d.nx);
+        const T kv = kcol[fi];
         const C s = src[(size_t)(unsigned)i * (unsigned)g.si];
+        if (pair) {   // s (ka + i kb)
+            const T kb = kcol_b ? kcol_b[fi] : (T)0;
+            return C{s.x * kv - s.y * kb, s.y * kv + s.x * kb};
+        }
         return C{s.x * kv, s.y * kv};
     }
     __device__ void store(int i, int, C v) const { dst[(size_t)(unsigned)i * (unsigned)g.si] = v; }
 };
 
 // z pass, inverse: tspec[m] -> real parts to maps_a[m0+m], imaginary to maps_b[m0+m].
+// With `pair` (one real field, radii paired): slot j holds C_{2j} + i C_{2j+1};
+// the real part goes to maps_a[2 (m0 + j)], the imaginary part to the next row
+// of maps_a when that radius exists.
 template <typename T>
 struct OpUnpack {
     static constexpr bool STAGED = false;
@@ -388,9 +406,16 @@ struct OpUnpack {
     int m0;
     Tile g;
     const C *src;
+    int pair, ns;
     template <int TC> __device__ void begin() {
         g = make_tile(AX_Z, d, blockIdx.x, TC);
         src = tspec + (size_t)blockIdx.y * nc + g.base;
+        if (pair) {
+            const int ra = 2 * (m0 + blockIdx.y);
+            mb = ra + 1 < ns ? ma + (size_t)(ra + 1) * nc + g.base : nullptr;
+            ma += (size_t)ra * nc + g.base;
+            return;
+        }
         const size_t o = (size_t)(m0 + blockIdx.y) * nc + g.base;
         ma += o;
         if (mb) mb += o;
@@ -569,11 +594,11 @@ struct OpDiag {
     const C *src;
     const T *fa;
     const T *fb;
-    const unsigned char *mask;   // NULL, or lines carrying field: others read as zero
+    const unsigned char *mask;   // NULL, or this tile's line flags (LDS): others read as zero
     Tile g;
     double acc[2][P];
     __device__ C load(int i, int c) const {
-        if (mask && !mask[g.p0 + c]) return C{(T)0, (T)0};
+        if (mask && !mask[c]) return C{(T)0, (T)0};
         return src[off(g, i, c)];
     }
     __device__ void store(int i, int c, C v) {
@@ -610,18 +635,24 @@ __global__ __launch_bounds__((Shape<T, L, TM_J>::NT), (Shape<T, L, TM_J>::MINW))
     __shared__ C lds[SH::LDS];
     __shared__ C tw[L];
     __shared__ double red[NW][2 * P];
+    __shared__ unsigned char lmask[SH::TC];
     for (int t = threadIdx.x; t < L; t += NT) tw[t] = twg[t];
     OpDiag<T, P> op;
 #pragma unroll
     for (int p = 0; p < P; ++p) op.acc[0][p] = op.acc[1][p] = 0.0;
-    op.mask = mask;
+    op.mask = mask ? lmask : nullptr;
     const C *base = tspec + (size_t)blockIdx.y * nc;
     __syncthreads();
     for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
-        if (mask) {   // a tile without carrying lines adds nothing
-            bool any = false;
-            for (int c = 0; c < SH::TC; ++c) any |= mask[tile * SH::TC + c] != 0;
-            if (!any) continue;
+        if (mask) {   // this tile's line flags into LDS; a tile without carrying lines adds nothing
+            __syncthreads();   // the previous tile is done with lmask
+            int on = 0;
+            for (int c = threadIdx.x; c < SH::TC; c += NT) {
+                const unsigned char f = mask[tile * SH::TC + c];
+                lmask[c] = f;
+                on |= f;
+            }
+            if (!__syncthreads_or(on)) continue;   // uniform over the workgroup
         }
         op.g = make_tile(AX_Z, d, tile, SH::TC);
         op.src = base + op.g.base;
@@ -748,7 +779,8 @@ int forward_pair_t(conker_ctx *ctx, const conker_grid *g, const void *a, const v
 
 template <typename T>
 int inverse_batch_t(conker_ctx *ctx, const conker_grid *g, const void *spec, const void *kspec, int m0,
-                    int nb, void *tspec, void *maps_a, void *maps_b, const Support *sup) {
+                    int nb, void *tspec, void *maps_a, void *maps_b, const Support *sup, int pair_ns) {
+    const int pair = pair_ns > 0 ? 1 : 0;
     const int *xcount = (sup && !maps_a) ? sup->xcount : nullptr;
     const unsigned char *mask = (sup && !maps_a) ? sup->mask : nullptr;
     using C = cplx<T>;
@@ -776,7 +808,7 @@ int inverse_batch_t(conker_ctx *ctx, const conker_grid *g, const void *spec, con
         return (e && e[0] == '0') ? 0 : 1;
     }();
     bool done = false;
-    if (resident) {
+    if (resident && !pair) {
         auto go = [&](auto Lc) -> int {
             constexpr int LL = decltype(Lc)::value;
             if constexpr (resident_fits<T, LL>()) {
@@ -809,17 +841,17 @@ int inverse_batch_t(conker_ctx *ctx, const conker_grid *g, const void *spec, con
     if (done) {
     } else if (staged) {
         OpMulK<T, true> px{twx, d, (const C *)spec, (const T *)kspec, (C *)tspec, nc, kel, m0, nb, tiles, loop,
-                           {}, 0, 0, nullptr, nullptr, nullptr};
+                           {}, 0, 0, nullptr, nullptr, nullptr, pair, pair_ns, nullptr};
         CK_OK((launch_len<T, +1>(ctx, PK_FFT_INV_X_MUL, xm, d.nx, AX_X, d, gxm, px)));
     } else {
         OpMulK<T, false> px{twx, d, (const C *)spec, (const T *)kspec, (C *)tspec, nc, kel, m0, nb, tiles, loop,
-                            {}, 0, 0, nullptr, nullptr, nullptr};
+                            {}, 0, 0, nullptr, nullptr, nullptr, pair, pair_ns, nullptr};
         CK_OK((launch_len<T, +1>(ctx, PK_FFT_INV_X_MUL, xm, d.nx, AX_X, d, gxm, px)));
     }
     OpInplace<T> py{twy, d, AX_Y, (C *)tspec, nc, {}, nullptr, mask, xcount};
     CK_OK((launch_len<T, +1>(ctx, PK_FFT_INV_Y, TM_C, d.ny, AX_Y, d, dim3(1, (unsigned)nb), py)));
     if (!maps_a) return CONKER_OK;   // x and y passes only
-    OpUnpack<T> pz{twz, d, (const C *)tspec, (T *)maps_a, (T *)maps_b, nc, m0, {}, nullptr};
+    OpUnpack<T> pz{twz, d, (const C *)tspec, (T *)maps_a, (T *)maps_b, nc, m0, {}, nullptr, pair, pair_ns};
     CK_OK((launch_len<T, +1>(ctx, PK_FFT_INV_Z, TM_J, d.nz, AX_Z, d, dim3(1, (unsigned)nb), pz)));
     return CONKER_OK;
 }
@@ -894,9 +926,9 @@ int fft_forward_pair(conker_ctx *ctx, const conker_grid *g, bool f64, const void
 
 int fft_inverse_batch(conker_ctx *ctx, const conker_grid *g, bool f64, const void *spec,
                       const void *kspec, int m0, int nb, void *tspec, void *maps_a, void *maps_b,
-                      const Support *sup) {
-    return f64 ? inverse_batch_t<double>(ctx, g, spec, kspec, m0, nb, tspec, maps_a, maps_b, sup)
-               : inverse_batch_t<float>(ctx, g, spec, kspec, m0, nb, tspec, maps_a, maps_b, sup);
+                      const Support *sup, int pair_ns) {
+    return f64 ? inverse_batch_t<double>(ctx, g, spec, kspec, m0, nb, tspec, maps_a, maps_b, sup, pair_ns)
+               : inverse_batch_t<float>(ctx, g, spec, kspec, m0, nb, tspec, maps_a, maps_b, sup, pair_ns);
 }
 
 int fft_shell_pair(conker_ctx *ctx, const conker_grid *g, double lo_a, double hi_a, double lo_b,

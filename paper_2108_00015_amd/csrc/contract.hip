@@ -23,6 +23,7 @@
 //             (hh, hm, mh, hl, mm, lh) are accumulated.
 // float32 accumulators are flushed into float64 registers every ~128 cells.
 #include <algorithm>
+#include <cstdlib>
 #include <type_traits>
 
 #include "common.h"
@@ -948,7 +949,16 @@ extern "C" int conker_contract_npt(conker_ctx *c, const conker_grid *g, conker_d
     const int TS = prec == CONKER_MM_F64 ? 16 : 32;
     Plan pl;
     CK_OK(make_plan(c, ns, n, TS, pl));
-    if (prec != CONKER_MM_F64) {
+    // Operand-sharing kernel (k_mm2) for many tiles (pair products, n >= 4, and
+    // split-f16); per-wave tiles (k_mm_*) when the tuples fit a few 32 x 32
+    // tiles, where k_mm2 would leave most waves of a workgroup idle.
+    static const int mm_kernel = [] {
+        const char *e = std::getenv("CONKER_MM_KERNEL");
+        return e ? std::atoi(e) : 0;   // 0 auto, 1 per-wave tiles, 2 operand sharing
+    }();
+    const bool use_v2 = prec == CONKER_MM_SPLIT_F16 ||
+                        (prec != CONKER_MM_F64 && (mm_kernel == 2 || (mm_kernel == 0 && pl.n_tiles > 4)));
+    if (use_v2) {
         // operand-sharing matrix-core kernel
         Plan2 p2;
         CK_OK(make_plan2(c, ns, n, prec == CONKER_MM_SPLIT_BF16, p2));

@@ -111,9 +111,10 @@ def support_fractions(w, data, rand):
     hit = np.zeros(nx * ny, dtype=bool)
     o = np.asarray(w.origin, dtype=np.float64)
     for cat in (data, rand):
-        c = np.floor((cat.pos.astype(np.float64) - o) / w.cell).astype(np.int64)
-        ok = np.all((c >= 0) & (c < np.asarray(w.dims)), axis=1)
-        hit[c[ok, 0] * ny + c[ok, 1]] = True
+        for s in range(0, len(cat), 1 << 24):
+            c = np.floor((cat.pos[s:s + (1 << 24)].astype(np.float64) - o) / w.cell).astype(np.int64)
+            ok = np.all((c >= 0) & (c < np.asarray(w.dims)), axis=1)
+            hit[c[ok, 0] * ny + c[ok, 1]] = True
     hit = hit.reshape(nx, ny)
     return float(hit.any(axis=1).mean()), float(hit.mean())
 

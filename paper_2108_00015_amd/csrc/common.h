@@ -36,6 +36,7 @@ struct conker_ctx {
     conker::Buf partial;    // per-workgroup partial sums of the summation stage
     conker::Buf full;       // reduced block matrices of the summation stage
     conker::Buf support;    // line mask, per-slab counts and list of lines carrying field
+    conker::Buf scales;     // split-f16 summation: largest |value| per map and of the field
     std::map<uint64_t, conker::Buf> tables;  // item / tuple tables, keyed by (n_radii, n, prec)
     // per-launch event timing (conker_profile_enable)
     int n_cu = 0;

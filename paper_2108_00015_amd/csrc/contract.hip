@@ -317,101 +317,6 @@ __device__ __forceinline__ void split3(const float (&v)[8], bf16x8 &hi, bf16x8 &
     }
 }
 
-// split bfloat16: 32x32 tiles, v_mfma_f32_32x32x16_bf16, lane feeds row lane % 32
-// with the 8 cells of k-slot lane / 32
-template <int NBW>
-__global__ __launch_bounds__(NT) void k_mm_bf16(const float *__restrict__ F, const float *__restrict__ maps,
-                                                size_t nc, size_t chunk, const Items *__restrict__ tab,
-                                                int n_tiles, double *__restrict__ partial) {
-    constexpr int TS = 32, CPI = 16, FLUSH = 8;   // 2 k-slots x 8 cells per iteration
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int r = lane & 31, h = lane >> 5;
-    Items it[NBW];
-    bool live[NBW], same[NBW];
-#pragma unroll
-    for (int s = 0; s < NBW; ++s) {
-        const int tile = blockIdx.y * NBW + s;
-        live[s] = tile < n_tiles;
-        it[s] = live[s] ? tab[(size_t)tile * TS + r] : Items{-2, -1, -2, -1};
-        same[s] = (it[s].a == it[s].c) && (it[s].b == it[s].d);
-    }
-    floatx16 acc[NBW];
-    double accd[NBW][16];
-#pragma unroll
-    for (int s = 0; s < NBW; ++s) {
-        acc[s] = floatx16{0};
-#pragma unroll
-        for (int v = 0; v < 16; ++v) accd[s][v] = 0.0;
-    }
-    const size_t c0 = (size_t)blockIdx.x * chunk;
-    const size_t c1 = std::min(c0 + chunk, nc);
-    int cnt = 0;
-    for (size_t x0 = c0 + (size_t)w * CPI; x0 < c1; x0 += (size_t)WAVES * CPI) {
-        const size_t x = x0 + 8 * h;
-        float f[8];
-        ld<float, 8>(F + x, f);
-#pragma unroll
-        for (int s = 0; s < NBW; ++s) {
-            if (!live[s]) continue;
-            float cv[8], av[8], bv[8];
-            item_vals<float, 8>(maps, nc, x, it[s].a, it[s].b, cv);
-            if (same[s]) {
-#pragma unroll
-                for (int e = 0; e < 8; ++e) bv[e] = cv[e];
-            } else {
-                item_vals<float, 8>(maps, nc, x, it[s].c, it[s].d, bv);
-            }
-#pragma unroll
-            for (int e = 0; e < 8; ++e) av[e] = cv[e] * f[e];
-            bf16x8 ah, am, al, bh, bm, bl;
-            split3(av, ah, am, al);
-            split3(bv, bh, bm, bl);
-            acc[s] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc[s], 0, 0, 0);
-            acc[s] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bm, acc[s], 0, 0, 0);
-            acc[s] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc[s], 0, 0, 0);
-            acc[s] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bh, acc[s], 0, 0, 0);
-            acc[s] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bm, acc[s], 0, 0, 0);
-            acc[s] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc[s], 0, 0, 0);
-        }
-        if (++cnt == FLUSH) {
-            cnt = 0;
-#pragma unroll
-            for (int s = 0; s < NBW; ++s) {
-#pragma unroll
-                for (int v = 0; v < 16; ++v) accd[s][v] += (double)acc[s][v];
-                acc[s] = floatx16{0};
-            }
-        }
-    }
-    __shared__ double lds[WAVES * 16 * 64];
-    const int G = gridDim.x;
-#pragma unroll
-    for (int s = 0; s < NBW; ++s) {
-        const int tile = blockIdx.y * NBW + s;
-        if (tile >= n_tiles) break;
-        double a16[16];
-#pragma unroll
-        for (int v = 0; v < 16; ++v) a16[v] = accd[s][v] + (double)acc[s][v];
-        wave_combine_store<32>(a16, lds, partial + ((size_t)tile * G + blockIdx.x) * (TS * TS));
-    }
-}
-
-// ---------------------------------------------------------------------------
-// float32 / split-bf16 matrix-core summation with operands built once per
-// chunk.  A workgroup owns a chunk of cells and a group of up to 16 output
-// tiles (a rectangle of row tiles x column tiles).  For every 64 cells it
-// stages the maps and F in LDS; for every 16 of those it builds each row item
-// (F C_a [C_b]) and column item (C_c [C_d]) of its rectangle once, as three
-// bf16 planes (or one float32 plane), in LDS; then each wave runs the matrix
-// instructions of its (at most two) tiles from LDS.  float32 accumulators are
-// flushed into float64 registers every 128 cells.
-// ---------------------------------------------------------------------------
-struct Group {
-    int rt0, nrt, ct0, nct, t0, nt;
-};
-
-constexpr int V2_NT = 512, V2_WAVES = V2_NT / 64, V2_MAXT = 2, V2_MAXU = 4;
-
 // split-fp16: each factor x of an operand (the field, or a map of one radius)
 // is normalised by 2^s_x, s_x = -(floor(log2 max|x|) + 1), so that it lies
 // below 1 in magnitude; an operand (a product of factors) is then scaled by
@@ -470,6 +375,143 @@ __global__ void k_zero_u32(unsigned *p, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0u;
 }
+
+// Scale exponent of a per-wave item (a, b): constant-1 (-1) and absent factors
+// add nothing; padding (-2) holds zeros.
+__device__ __forceinline__ int items_exp(const unsigned *maxabs, int ns, int a, int b, bool with_f) {
+    if (a == -2) return 0;
+    int s = 14;
+    if (a >= 0) s += norm_exp(maxabs[a]);
+    if (b >= 0) s += norm_exp(maxabs[b]);
+    if (with_f) s += norm_exp(maxabs[ns]);
+    return s;
+}
+
+// split bfloat16 (three terms, six products) or split float16 (scaled, two
+// terms, three products): 32x32 tiles, 32x32x16 matrix instructions, lane feeds
+// row lane % 32 with the 8 cells of k-slot lane / 32
+template <int NBW, int PREC>
+__global__ __launch_bounds__(NT) void k_mm_split(const float *__restrict__ F, const float *__restrict__ maps,
+                                                 size_t nc, size_t chunk, const Items *__restrict__ tab,
+                                                 int n_tiles, double *__restrict__ partial, int ns,
+                                                 const unsigned *__restrict__ maxabs) {
+    constexpr bool F16 = PREC == CONKER_MM_SPLIT_F16;
+    constexpr int TS = 32, CPI = 16, FLUSH = 8;   // 2 k-slots x 8 cells per iteration
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int r = lane & 31, h = lane >> 5;
+    Items it[NBW];
+    bool live[NBW], same[NBW];
+    int er[NBW], ec[NBW];   // split-f16 scale exponents of this lane's row and column items
+#pragma unroll
+    for (int s = 0; s < NBW; ++s) {
+        const int tile = blockIdx.y * NBW + s;
+        live[s] = tile < n_tiles;
+        it[s] = live[s] ? tab[(size_t)tile * TS + r] : Items{-2, -1, -2, -1};
+        same[s] = (it[s].a == it[s].c) && (it[s].b == it[s].d);
+        er[s] = ec[s] = 0;
+        if constexpr (F16) {
+            er[s] = items_exp(maxabs, ns, it[s].a, it[s].b, true);
+            ec[s] = items_exp(maxabs, ns, it[s].c, it[s].d, false);
+        }
+    }
+    floatx16 acc[NBW];
+    double accd[NBW][16];
+#pragma unroll
+    for (int s = 0; s < NBW; ++s) {
+        acc[s] = floatx16{0};
+#pragma unroll
+        for (int v = 0; v < 16; ++v) accd[s][v] = 0.0;
+    }
+    const size_t c0 = (size_t)blockIdx.x * chunk;
+    const size_t c1 = std::min(c0 + chunk, nc);
+    int cnt = 0;
+    for (size_t x0 = c0 + (size_t)w * CPI; x0 < c1; x0 += (size_t)WAVES * CPI) {
+        const size_t x = x0 + 8 * h;
+        float f[8];
+        ld<float, 8>(F + x, f);
+#pragma unroll
+        for (int s = 0; s < NBW; ++s) {
+            if (!live[s]) continue;
+            float cv[8], av[8], bv[8];
+            item_vals<float, 8>(maps, nc, x, it[s].a, it[s].b, cv);
+            if (same[s]) {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) bv[e] = cv[e];
+            } else {
+                item_vals<float, 8>(maps, nc, x, it[s].c, it[s].d, bv);
+            }
+#pragma unroll
+            for (int e = 0; e < 8; ++e) av[e] = cv[e] * f[e];
+            if constexpr (F16) {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    av[e] = ldexpf(av[e], er[s]);
+                    bv[e] = ldexpf(bv[e], ec[s]);
+                }
+                f16x8 ah, al, bh, bl;
+                split2h(av, ah, al);
+                split2h(bv, bh, bl);
+                acc[s] = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, bh, acc[s], 0, 0, 0);
+                acc[s] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bl, acc[s], 0, 0, 0);
+                acc[s] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bh, acc[s], 0, 0, 0);
+            } else {
+                bf16x8 ah, am, al, bh, bm, bl;
+                split3(av, ah, am, al);
+                split3(bv, bh, bm, bl);
+                acc[s] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc[s], 0, 0, 0);
+                acc[s] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bm, acc[s], 0, 0, 0);
+                acc[s] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc[s], 0, 0, 0);
+                acc[s] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bh, acc[s], 0, 0, 0);
+                acc[s] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bm, acc[s], 0, 0, 0);
+                acc[s] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc[s], 0, 0, 0);
+            }
+        }
+        if (++cnt == FLUSH) {
+            cnt = 0;
+#pragma unroll
+            for (int s = 0; s < NBW; ++s) {
+#pragma unroll
+                for (int v = 0; v < 16; ++v) accd[s][v] += (double)acc[s][v];
+                acc[s] = floatx16{0};
+            }
+        }
+    }
+    __shared__ double lds[WAVES * 16 * 64];
+    const int G = gridDim.x;
+#pragma unroll
+    for (int s = 0; s < NBW; ++s) {
+        const int tile = blockIdx.y * NBW + s;
+        if (tile >= n_tiles) break;
+        double a16[16];
+#pragma unroll
+        for (int v = 0; v < 16; ++v) a16[v] = accd[s][v] + (double)acc[s][v];
+        if constexpr (F16) {   // element (i, j = lane % 32): row exponent from lane i, column exponent ours
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int i = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                a16[v] = ldexp(a16[v], -(__shfl(er[s], i) + ec[s]));
+            }
+        }
+        wave_combine_store<32>(a16, lds, partial + ((size_t)tile * G + blockIdx.x) * (TS * TS));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// float32 / split-bf16 matrix-core summation with operands built once per
+// chunk.  A workgroup owns a chunk of cells and a group of up to 16 output
+// tiles (a rectangle of row tiles x column tiles).  For every 64 cells it
+// stages the maps and F in LDS; for every 16 of those it builds each row item
+// (F C_a [C_b]) and column item (C_c [C_d]) of its rectangle once, as three
+// bf16 planes (or one float32 plane), in LDS; then each wave runs the matrix
+// instructions of its (at most two) tiles from LDS.  float32 accumulators are
+// flushed into float64 registers every 128 cells.
+// ---------------------------------------------------------------------------
+struct Group {
+    int rt0, nrt, ct0, nct, t0, nt;
+};
+
+constexpr int V2_NT = 512, V2_WAVES = V2_NT / 64, V2_MAXT = 2, V2_MAXU = 4;
+
 
 template <int PREC>
 __global__ __launch_bounds__(V2_NT) void k_mm2(const float *__restrict__ F, const float *__restrict__ maps, size_t nc,
@@ -909,16 +951,20 @@ int contract_dot(conker_ctx *c, const T *F, const T *maps, size_t nc, int ns, do
 
 template <int NBW>
 int launch_mm(conker_ctx *c, conker_mmprec prec, dim3 grid, const void *F, const void *maps, size_t nc,
-              size_t chunk, const Items *tab, int n_tiles, double *part) {
+              size_t chunk, const Items *tab, int n_tiles, double *part, int ns, const unsigned *maxabs) {
     if (prec == CONKER_MM_F64)
         hipLaunchKernelGGL((k_mm_f64<NBW>), grid, dim3(NT), 0, c->stream, (const double *)F,
                            (const double *)maps, nc, chunk, tab, n_tiles, part);
     else if (prec == CONKER_MM_F32)
         hipLaunchKernelGGL((k_mm_f32<NBW>), grid, dim3(NT), 0, c->stream, (const float *)F,
                            (const float *)maps, nc, chunk, tab, n_tiles, part);
+    else if (prec == CONKER_MM_SPLIT_F16)
+        hipLaunchKernelGGL((k_mm_split<NBW, CONKER_MM_SPLIT_F16>), grid, dim3(NT), 0, c->stream, (const float *)F,
+                           (const float *)maps, nc, chunk, tab, n_tiles, part, ns, maxabs);
     else
-        hipLaunchKernelGGL((k_mm_bf16<NBW>), grid, dim3(NT), 0, c->stream, (const float *)F,
-                           (const float *)maps, nc, chunk, tab, n_tiles, part);
+        hipLaunchKernelGGL((k_mm_split<NBW, CONKER_MM_SPLIT_BF16>), grid, dim3(NT), 0, c->stream,
+                           (const float *)F, (const float *)maps, nc, chunk, tab, n_tiles, part, ns,
+                           (const unsigned *)nullptr);
     CK_LAUNCH(c);
     return CONKER_OK;
 }
@@ -956,8 +1002,20 @@ extern "C" int conker_contract_npt(conker_ctx *c, const conker_grid *g, conker_d
         const char *e = std::getenv("CONKER_MM_KERNEL");
         return e ? std::atoi(e) : 0;   // 0 auto, 1 per-wave tiles, 2 operand sharing
     }();
-    const bool use_v2 = prec == CONKER_MM_SPLIT_F16 ||
-                        (prec != CONKER_MM_F64 && (mm_kernel == 2 || (mm_kernel == 0 && pl.n_tiles > 4)));
+    const bool use_v2 = prec != CONKER_MM_F64 && (mm_kernel == 2 || (mm_kernel == 0 && pl.n_tiles > 4));
+    unsigned *maxabs = nullptr;
+    if (prec == CONKER_MM_SPLIT_F16) {   // largest |value| of every map and of F, after the workspace below
+        CK_OK(ws_reserve(c, c->scales, 256 * sizeof(unsigned)));
+        ProfScope ps(c, PK_CONTRACT_DOT);
+        maxabs = (unsigned *)c->scales.p;
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(128), 0, c->stream, maxabs, ns + 1);
+        CK_LAUNCH(c);
+        const size_t mchunk = 64 * 1024;
+        const dim3 mg((unsigned)((nc + mchunk - 1) / mchunk), (unsigned)(ns + 1));
+        hipLaunchKernelGGL(k_absmax, mg, dim3(256), 0, c->stream, (const float *)F, (const float *)maps, nc, ns,
+                           mchunk, maxabs);
+        CK_LAUNCH(c);
+    }
     if (use_v2) {
         // operand-sharing matrix-core kernel
         Plan2 p2;
@@ -970,20 +1028,8 @@ extern "C" int conker_contract_npt(conker_ctx *c, const conker_grid *g, conker_d
         const int te = 1024;
         const size_t full_b = (size_t)p2.n_tiles * te * (RED_S + 1) * sizeof(double);
         CK_OK(ws_reserve(c, c->partial, (size_t)p2.n_tiles * G * te * sizeof(double)));
-        CK_OK(ws_reserve(c, c->full, full_b + 1024));
+        CK_OK(ws_reserve(c, c->full, full_b));
         double *part = (double *)c->partial.p;
-        unsigned *maxabs = nullptr;
-        if (prec == CONKER_MM_SPLIT_F16) {   // largest |value| of every map and of F
-            ProfScope ps(c, PK_CONTRACT_DOT);
-            maxabs = (unsigned *)((char *)c->full.p + full_b);
-            hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(128), 0, c->stream, maxabs, ns + 1);
-            CK_LAUNCH(c);
-            const size_t mchunk = 64 * 1024;
-            const dim3 mg((unsigned)((nc + mchunk - 1) / mchunk), (unsigned)(ns + 1));
-            hipLaunchKernelGGL(k_absmax, mg, dim3(256), 0, c->stream, (const float *)F, (const float *)maps, nc, ns,
-                               mchunk, maxabs);
-            CK_LAUNCH(c);
-        }
         {
             ProfScope ps(c, PK_CONTRACT_MM);
             dim3 grid((unsigned)G, (unsigned)p2.n_groups);
@@ -1047,9 +1093,9 @@ extern "C" int conker_contract_npt(conker_ctx *c, const conker_grid *g, conker_d
     dim3 grid((unsigned)G, (unsigned)groups);
     {
     ProfScope ps(c, PK_CONTRACT_MM);
-    if (NBW == 1) CK_OK(launch_mm<1>(c, prec, grid, F, maps, nc, chunk, tab, pl.n_tiles, part));
-    else if (NBW == 2) CK_OK(launch_mm<2>(c, prec, grid, F, maps, nc, chunk, tab, pl.n_tiles, part));
-    else CK_OK(launch_mm<4>(c, prec, grid, F, maps, nc, chunk, tab, pl.n_tiles, part));
+    if (NBW == 1) CK_OK(launch_mm<1>(c, prec, grid, F, maps, nc, chunk, tab, pl.n_tiles, part, ns, maxabs));
+    else if (NBW == 2) CK_OK(launch_mm<2>(c, prec, grid, F, maps, nc, chunk, tab, pl.n_tiles, part, ns, maxabs));
+    else CK_OK(launch_mm<4>(c, prec, grid, F, maps, nc, chunk, tab, pl.n_tiles, part, ns, maxabs));
     }
     ProfScope ps(c, PK_CONTRACT_REDUCE);
     const size_t tot = (size_t)pl.n_tiles * te;

@@ -10,8 +10,9 @@ namespace conker {
 
 // Radii convolved per inverse batch: one read of the forward spectrum serves
 // this many kernel multiplies and inverse x-axis transforms.  Default: every
-// radius, as long as the batch spectra take at most half of the free device
-// memory (plus what this context already holds for them).
+// radius, as long as the batch spectra take at most half of the device memory
+// that is free or already held for them (so that the choice is the same from
+// call to call and the buffer is not regrown).
 int batch_radii(conker_ctx *c, size_t per_radius_bytes, int n_radii, size_t fixed_bytes) {
     int b = n_radii;
     if (c->capturing) {   // inside a graph capture: use the batch buffer as planned
@@ -21,7 +22,7 @@ int batch_radii(conker_ctx *c, size_t per_radius_bytes, int n_radii, size_t fixe
     }
     size_t fr = 0, tot = 0;
     if (hipMemGetInfo(&fr, &tot) == hipSuccess) {
-        const size_t budget = fr / 2 + c->tspec.bytes;
+        const size_t budget = (fr + c->tspec.bytes) / 2;
         const size_t fit = per_radius_bytes ? budget / per_radius_bytes : (size_t)n_radii;
         if ((size_t)b > fit) b = (int)(fit < 1 ? 1 : fit);
     }

@@ -229,6 +229,7 @@ extern "C" void conker_destroy(conker_ctx *c) {
     rel(c->partial);
     rel(c->full);
     rel(c->support);
+    rel(c->scales);
     delete c;
 }
 

@@ -100,6 +100,40 @@ def measured_traffic(kind, workload, n):
     return (t["fetch_kib_per_dispatch"] * t["fetch_factor"] + t["write_kib_per_dispatch"] * t["write_factor"]) * 1024.0
 
 
+MFMA_PEAK_TFLOPS = {"split_bf16": 2500.0, "split_f16": 2500.0, "f32": 157.3, "f64": 78.6}
+TERM_PRODUCTS = {"split_bf16": 6, "split_f16": 3, "f32": 1, "f64": 1}
+
+
+def summation_tiles(ns, n, ts=32):
+    """32 x 32 output tiles the matrix-core summation issues for order n (row items
+    F C_a or F C_a C_b, column items C_b or C_c C_d, as in the library's plan)."""
+    singles = [(a,) for a in range(ns)]
+    pairs = [(a, b) for a in range(ns) for b in range(a, ns)]
+    if n == 3:
+        left, right = singles, singles
+    elif n == 4:
+        left, right = pairs, singles
+    else:
+        left, right = pairs, pairs
+    li = {t: i for i, t in enumerate(left)}
+    ri = {t: i for i, t in enumerate(right)}
+    import itertools
+    tiles = set()
+    for t in itertools.combinations_with_replacement(range(ns), n - 1):
+        if n == 3:
+            a, b = (t[0],), (t[1],)
+        elif n == 4:
+            a, b = (t[0], t[1]), (t[2],)
+        else:
+            a, b = (t[0], t[1]), (t[2], t[3])
+        tiles.add((li[a] // ts, ri[b] // ts))
+    return len(tiles)
+
+
+def comb_tuples(ns, n):
+    return math.comb(ns + n - 2, n - 1)
+
+
 def stages_use_fused(prof):
     return "fused_zinv_contract" in prof
 
@@ -332,6 +366,17 @@ def main():
             ent["gbs"] = b / (per_step * 1e-3) / 1e9
             ent["bytes_per_launch"] = b / (launches / args.steps)
         stages[kind] = ent
+    # matrix-core use of the separate summation (orders n >= 3)
+    if "contract_mm" in stages and args.n >= 3:
+        tiles = summation_tiles(ns, args.n)
+        issued = 2.0 * tiles * 1024 * nc * TERM_PRODUCTS[args.prec]       # per field
+        per_launch_ms = stages["contract_mm"]["avg_launch_ms"]
+        tflops = issued / (per_launch_ms * 1e-3) / 1e12
+        ent = stages["contract_mm"]
+        ent["mfma_tiles"] = tiles
+        ent["mfma_issued_tflops"] = round(tflops, 2)
+        ent["mfma_frac_of_peak"] = round(tflops / MFMA_PEAK_TFLOPS[args.prec], 4)
+        ent["tuple_cells_per_s"] = round(comb_tuples(ns, args.n) * nc / (per_launch_ms * 1e-3), 1)
     # dominant kernel: largest time per step
     dom = max(stages.items(), key=lambda kv: kv[1]["ms_per_step"]) if stages else None
     roof = None

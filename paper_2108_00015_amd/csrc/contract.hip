@@ -511,6 +511,9 @@ struct Group {
 };
 
 constexpr int V2_NT = 512, V2_WAVES = V2_NT / 64, V2_MAXT = 2, V2_MAXU = 4;
+constexpr int V2_PRE = 3;                       // staged float4 per thread: (64 + 1) * 16 <= 3 * 512
+constexpr int V2_LDS_MAX = 150 * 1024;          // dynamic LDS of one k_mm2 workgroup
+constexpr int V2_SROW = 68;                     // staged row stride (floats): 64 cells + 4 of padding
 
 
 template <int PREC>
@@ -525,28 +528,43 @@ __global__ __launch_bounds__(V2_NT) void k_mm2(const float *__restrict__ F, cons
     constexpr int EB = (SPLIT || F16) ? 2 : 4;              // bytes per operand element
     extern __shared__ __align__(16) unsigned char smem[];
     const Group gr = groups[blockIdx.y];
-    float *sm_maps = reinterpret_cast<float *>(smem);       // [ns][64]
-    float *sm_F = sm_maps + ns * 64;                        // [64]
-    unsigned char *sA = reinterpret_cast<unsigned char *>(sm_F + 64);
+    // LDS: two staging buffers [ns + 3][V2_SROW] (maps, F, a row of ones, a row
+    // of zeros; rows padded against bank conflicts) and two operand buffers (A
+    // planes, then B planes), so that the next 64 cells load while these are
+    // summed and the next 16-cell operands build while these multiply
+    const int SZ = (ns + 3) * V2_SROW;
+    const int ROW_F = ns, ROW_ONE = ns + 1, ROW_ZERO = ns + 2;
+    float *stg0 = reinterpret_cast<float *>(smem);
     const int na = gr.nrt * 32, nb = gr.nct * 32;
-    unsigned char *sB = sA + (size_t)NP * na * 16 * EB;
+    const size_t abytes = (size_t)NP * na * 16 * EB;
+    const size_t opb = abytes + (size_t)NP * nb * 16 * EB;
+    unsigned char *ops0 = reinterpret_cast<unsigned char *>(stg0 + 2 * SZ);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int r = lane & 31, h = lane >> 5;
     // build units of this thread: unit u -> (item, half); items of A first, then B
-    int2 uit[V2_MAXU];
-    int uitem[V2_MAXU];
+    // Each unit builds v = S[r0] * S[r1] * S[r2] over 8 cells from three staged
+    // rows (a map or zeros; a map or ones; F or ones), with no branches, and
+    // stores it at operand offset uoff (-1: no such unit).
+    const int a_units = na * 2;   // operand offsets below this are rows of A, the rest of B
+    int urow[V2_MAXU][3];
+    int uoff[V2_MAXU];
     int uexp[V2_MAXU];   // split-fp16 operand scale exponents
 #pragma unroll
     for (int k = 0; k < V2_MAXU; ++k) {
         const int u = threadIdx.x + k * V2_NT;
-        const int item = u >> 1;
-        uitem[k] = item;
-        if (item < na) uit[k] = ritems[gr.rt0 * 32 + item];
-        else if (item < na + nb) uit[k] = citems[gr.ct0 * 32 + (item - na)];
-        else uit[k] = int2{-3, -1};
+        const int item = u >> 1, half = u & 1;
+        int2 it;
+        if (item < na) it = ritems[gr.rt0 * 32 + item];
+        else if (item < na + nb) it = citems[gr.ct0 * 32 + (item - na)];
+        else it = int2{-3, -1};
+        const bool isA = item < na;
+        urow[k][0] = it.x >= 0 ? it.x : ROW_ZERO;
+        urow[k][1] = (it.x >= 0 && it.y >= 0) ? it.y : ROW_ONE;
+        urow[k][2] = (it.x >= 0 && isA) ? ROW_F : ROW_ONE;
+        uoff[k] = it.x == -3 ? -1 : item * 2 + half;   // B rows follow the A rows
         uexp[k] = 0;
         if constexpr (F16) {
-            if (uit[k].x >= 0) uexp[k] = item_exp(maxabs, ns, uit[k], item < na);
+            if (it.x >= 0) uexp[k] = item_exp(maxabs, ns, it, isA);
         }
     }
     // tiles of this wave
@@ -570,68 +588,86 @@ __global__ __launch_bounds__(V2_NT) void k_mm2(const float *__restrict__ F, cons
     }
     const size_t c0 = (size_t)blockIdx.x * chunk;
     const size_t c1 = c0 + chunk < nc ? c0 + chunk : nc;
-    int since = 0;
-    for (size_t x = c0; x < c1; x += 64) {
-        // stage the maps and F of 64 cells
-        for (int e = threadIdx.x; e < (ns + 1) * 16; e += V2_NT) {
-            const int row = e >> 4, q = e & 15;
-            const float *src = row < ns ? maps + (size_t)row * nc + x + 4 * q : F + x + 4 * q;
-            reinterpret_cast<float4 *>(sm_maps + row * 64)[q] = *reinterpret_cast<const float4 *>(src);
+    // constant rows of both staging buffers
+    for (int e = threadIdx.x; e < 2 * 64; e += V2_NT) {
+        const int b = e >> 6, c = e & 63;
+        stg0[b * SZ + ROW_ONE * V2_SROW + c] = 1.f;
+        stg0[b * SZ + ROW_ZERO * V2_SROW + c] = 0.f;
+    }
+    // staging of 64 cells: (ns + 1) * 16 float4, at most V2_PRE per thread
+    const int nst = (ns + 1) * 16;
+    float4 pre[V2_PRE];
+    auto fetch = [&](size_t x) {
+#pragma unroll
+        for (int k = 0; k < V2_PRE; ++k) {
+            const int e = threadIdx.x + k * V2_NT;
+            if (e < nst) {
+                const int row = e >> 4, q = e & 15;
+                const float *src = row < ns ? maps + (size_t)row * nc + x + 4 * q : F + x + 4 * q;
+                pre[k] = *reinterpret_cast<const float4 *>(src);
+            }
         }
-        __syncthreads();
+    };
+    auto put = [&](float *dst) {
+#pragma unroll
+        for (int k = 0; k < V2_PRE; ++k) {
+            const int e = threadIdx.x + k * V2_NT;
+            if (e < nst) reinterpret_cast<float4 *>(dst + (e >> 4) * V2_SROW)[e & 15] = pre[k];
+        }
+    };
+    if (c0 < c1) {
+        fetch(c0);
+        put(stg0);
+    }
+    __syncthreads();
+    int since = 0, sb = 0, ob = 0;
+    for (size_t x = c0; x < c1; x += 64) {
+        const bool more = x + 64 < c1;
+        if (more) fetch(x + 64);   // in flight while these 64 cells are summed
+        const float *sm_maps = stg0 + sb * SZ;
 #pragma unroll 1
         for (int sub = 0; sub < 4; ++sub) {
+            unsigned char *sA = ops0 + ob * opb;
+            unsigned char *sB = sA + abytes;
             // build the operands of 16 cells
 #pragma unroll
             for (int k = 0; k < V2_MAXU; ++k) {
-                const int2 it = uit[k];
-                if (it.x == -3) continue;
-                const int item = uitem[k];
-                const bool isA = item < na;
                 const int half = (threadIdx.x + k * V2_NT) & 1;
                 const int cb = sub * 16 + half * 8;
                 float v[8];
-                if (it.x == -2) {
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) v[e] = 0.f;
-                } else {
-                    const float4 *pa = reinterpret_cast<const float4 *>(sm_maps + it.x * 64 + cb);
-                    const float4 a0 = pa[0], a1 = pa[1];
-                    v[0] = a0.x; v[1] = a0.y; v[2] = a0.z; v[3] = a0.w;
-                    v[4] = a1.x; v[5] = a1.y; v[6] = a1.z; v[7] = a1.w;
-                    if (it.y >= 0) {
-                        const float4 *pb = reinterpret_cast<const float4 *>(sm_maps + it.y * 64 + cb);
-                        const float4 b0 = pb[0], b1 = pb[1];
-                        v[0] *= b0.x; v[1] *= b0.y; v[2] *= b0.z; v[3] *= b0.w;
-                        v[4] *= b1.x; v[5] *= b1.y; v[6] *= b1.z; v[7] *= b1.w;
-                    }
-                    if (isA) {
-                        const float4 *pf = reinterpret_cast<const float4 *>(sm_F + cb);
-                        const float4 f0 = pf[0], f1 = pf[1];
-                        v[0] *= f0.x; v[1] *= f0.y; v[2] *= f0.z; v[3] *= f0.w;
-                        v[4] *= f1.x; v[5] *= f1.y; v[6] *= f1.z; v[7] *= f1.w;
-                    }
+                {
+                    const float4 *p0 = reinterpret_cast<const float4 *>(sm_maps + urow[k][0] * V2_SROW + cb);
+                    const float4 *p1 = reinterpret_cast<const float4 *>(sm_maps + urow[k][1] * V2_SROW + cb);
+                    const float4 *p2 = reinterpret_cast<const float4 *>(sm_maps + urow[k][2] * V2_SROW + cb);
+                    const float4 a0 = p0[0], a1 = p0[1], b0 = p1[0], b1 = p1[1], f0 = p2[0], f1 = p2[1];
+                    v[0] = a0.x * b0.x * f0.x; v[1] = a0.y * b0.y * f0.y;
+                    v[2] = a0.z * b0.z * f0.z; v[3] = a0.w * b0.w * f0.w;
+                    v[4] = a1.x * b1.x * f1.x; v[5] = a1.y * b1.y * f1.y;
+                    v[6] = a1.z * b1.z * f1.z; v[7] = a1.w * b1.w * f1.w;
                 }
+                const int o = uoff[k];
+                if (o < 0) continue;
+                const bool isA = o < a_units;
                 unsigned char *dst = isA ? sA : sB;
-                const int row = isA ? item : item - na;
+                const int ro = isA ? o : o - a_units;   // (row * 2 + half) within its operand
                 const int nrows = isA ? na : nb;
                 if constexpr (SPLIT) {
                     bf16x8 hi, mi, lo;
                     split3(v, hi, mi, lo);
                     bf16x8 *d = reinterpret_cast<bf16x8 *>(dst);
-                    d[(0 * nrows + row) * 2 + half] = hi;
-                    d[(1 * nrows + row) * 2 + half] = mi;
-                    d[(2 * nrows + row) * 2 + half] = lo;
+                    d[0 * nrows * 2 + ro] = hi;
+                    d[1 * nrows * 2 + ro] = mi;
+                    d[2 * nrows * 2 + ro] = lo;
                 } else if constexpr (F16) {
 #pragma unroll
                     for (int e = 0; e < 8; ++e) v[e] = ldexpf(v[e], uexp[k]);
                     f16x8 hi, lo;
                     split2h(v, hi, lo);
                     f16x8 *d = reinterpret_cast<f16x8 *>(dst);
-                    d[(0 * nrows + row) * 2 + half] = hi;
-                    d[(1 * nrows + row) * 2 + half] = lo;
+                    d[0 * nrows * 2 + ro] = hi;
+                    d[1 * nrows * 2 + ro] = lo;
                 } else {
-                    float4 *d = reinterpret_cast<float4 *>(dst) + (row * 2 + half) * 2;
+                    float4 *d = reinterpret_cast<float4 *>(dst) + ro * 2;
                     d[0] = float4{v[0], v[1], v[2], v[3]};
                     d[1] = float4{v[4], v[5], v[6], v[7]};
                 }
@@ -673,8 +709,11 @@ __global__ __launch_bounds__(V2_NT) void k_mm2(const float *__restrict__ F, cons
                         acc[k] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[e], bv[e], acc[k], 0, 0, 0);
                 }
             }
-            __syncthreads();
+            ob ^= 1;   // the next sub-step builds into the other operand buffer
         }
+        if (more) put(stg0 + (sb ^ 1) * SZ);
+        __syncthreads();
+        sb ^= 1;
         if (++since == 2) {
             since = 0;
 #pragma unroll
@@ -878,7 +917,7 @@ int make_plan2(conker_ctx *c, int ns, int n, bool split, Plan2 &p2) {
         }
     }
     const int eb = split ? 6 : 4;   // LDS bytes per operand element over all planes
-    auto lds_of = [&](int nrt, int nct) { return (ns * 64 + 64) * 4 + (nrt + nct) * TS * 16 * eb; };
+    auto lds_of = [&](int nrt, int nct) { return 2 * (ns + 3) * V2_SROW * 4 + 2 * (nrt + nct) * TS * 16 * eb; };
     std::vector<Group> groups;
     int i = 0;
     p2.max_lds = 0;
@@ -890,7 +929,7 @@ int make_plan2(conker_ctx *c, int ns, int n, bool split, Plan2 &p2) {
             const int nrlo = std::min(rlo, tiles[j].first), nrhi = std::max(rhi, tiles[j].first);
             const int nclo = std::min(clo, tiles[j].second), nchi = std::max(chi, tiles[j].second);
             const int nrt = nrhi - nrlo + 1, nct = nchi - nclo + 1;
-            if ((nrt + nct) * TS * 2 > V2_NT * V2_MAXU || lds_of(nrt, nct) > 96 * 1024) break;
+            if ((nrt + nct) * TS * 2 > V2_NT * V2_MAXU || lds_of(nrt, nct) > V2_LDS_MAX) break;
             rlo = nrlo; rhi = nrhi; clo = nclo; chi = nchi;
             ++j;
         }
@@ -1036,11 +1075,11 @@ extern "C" int conker_contract_npt(conker_ctx *c, const conker_grid *g, conker_d
             static bool attr_set = false;
             if (!attr_set) {
                 CK_HIP(c, hipFuncSetAttribute((const void *)k_mm2<CONKER_MM_SPLIT_BF16>,
-                                              hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024));
+                                              hipFuncAttributeMaxDynamicSharedMemorySize, V2_LDS_MAX));
                 CK_HIP(c, hipFuncSetAttribute((const void *)k_mm2<CONKER_MM_F32>,
-                                              hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024));
+                                              hipFuncAttributeMaxDynamicSharedMemorySize, V2_LDS_MAX));
                 CK_HIP(c, hipFuncSetAttribute((const void *)k_mm2<CONKER_MM_SPLIT_F16>,
-                                              hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024));
+                                              hipFuncAttributeMaxDynamicSharedMemorySize, V2_LDS_MAX));
                 attr_set = true;
             }
             if (prec == CONKER_MM_SPLIT_BF16)

@@ -121,6 +121,9 @@ __global__ __launch_bounds__(NT, 1) void k_zinv_contract(const float2 *__restric
         for (int q = 0; q < 8; ++q) nxt[q] = src[lane + 64 * q];
     }
     __syncthreads();
+    float2 w3[7];   // this lane's third-stage twiddles, read once (strided LDS reads conflict)
+#pragma unroll
+    for (int q = 1; q < 8; ++q) w3[q - 1] = tw[q * lane];
 
     for (int idx = blockIdx.x; idx < nact; idx += gridDim.x) {
         const size_t base = (size_t)line_of(idx) * NZ;
@@ -162,7 +165,7 @@ __global__ __launch_bounds__(NT, 1) void k_zinv_contract(const float2 *__restric
 #pragma unroll
             for (int q = 0; q < 8; ++q) v[q] = Sw[swz(lane + 64 * q)];
 #pragma unroll
-            for (int q = 1; q < 8; ++q) v[q] = cmul(v[q], tw[q * lane]);   // stage 3: Ns = 64
+            for (int q = 1; q < 8; ++q) v[q] = cmul(v[q], w3[q - 1]);   // stage 3: Ns = 64
             dft<8, +1>(v);
 #pragma unroll
             for (int q = 0; q < 8; ++q) {

@@ -172,7 +172,7 @@ def test_shell_radius_errors(ck, ctx):
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("dims", [(32, 32, 32), (32, 64, 128), (128, 64, 32), (64, 64, 64), (96, 96, 96),
-                                  (192, 96, 96), (96, 192, 384)])
+                                  (192, 96, 96), (96, 192, 384), (1024, 32, 32), (32, 1024, 64)])
 @pytest.mark.parametrize("dt,tol", [("f64", 1e-12), ("f32", 3e-6)])
 def test_convolve_shells_vs_oracle(ck, ctx, dims, dt, tol):
     rng = np.random.default_rng(11)
@@ -205,14 +205,13 @@ def test_convolve_single_field_and_one_radius(ck, ctx):
     assert relerr(ma.cpu().numpy()[0], oc.convolve_shell(A, 5.0)) <= 1e-12
 
 
-@pytest.mark.parametrize("ns", [2, 5, 8])
+@pytest.mark.parametrize("ns,dims", [(2, (64, 96, 32)), (5, (64, 96, 32)), (8, (64, 96, 32)), (5, (1024, 32, 32))])
 @pytest.mark.parametrize("dt,tol", [("f64", 1e-12), ("f32", 3e-6)])
-def test_convolve_single_field_radius_pairs(ck, ctx, ns, dt, tol):
+def test_convolve_single_field_radius_pairs(ck, ctx, ns, dims, dt, tol):
     """One field: radii travel in pairs (C_a + i C_b through one inverse
     transform); odd counts leave a lone last radius; batches of one pair give
     bitwise the same maps."""
     import os
-    dims = (64, 96, 32)
     radii = [1.0, 2.0, 3.5, 5.0, 7.0, 9.0, 12.0, 15.0][:ns]
     rng = np.random.default_rng(14)
     A = rng.normal(size=dims)

@@ -307,3 +307,38 @@ def npcf_cross(data0_pos, data1_pos, rand_pos, dims, origin, cell, radii, n,
     Wr = contract(R_raw, convolve_shells(R_raw, rc), n, tuples)
     return dict(xi=estimator_cross(Wc, Wr, a0, a1, n), W_cross=Wc, W_rand_raw=Wr, alpha0=a0, alpha1=a1,
                 N0=N0, N1=N1, R_raw=R_raw)
+
+
+# ----------------------------------------------------------------------------
+# regions, maps and their distributions (Sec. 3.3, Eq. ksi3combined; Sec. 4)
+# ----------------------------------------------------------------------------
+
+def combine_regions(W_deltas: Sequence[np.ndarray], W_rands_raw: Sequence[np.ndarray],
+                    alphas: Sequence[float], n: int) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """Several regions (e.g. the two galactic caps) combined by adding numerators
+    and denominators (Eq. ksi3combined): xi = sum_j W_delta_j / sum_j alpha_j^n W_R_j.
+    Returns (xi, numerator, denominator)."""
+    num = np.sum([np.asarray(w, dtype=np.float64) for w in W_deltas], axis=0)
+    den = np.sum([a ** n * np.asarray(w, dtype=np.float64) for a, w in zip(alphas, W_rands_raw)], axis=0)
+    return num / den, num, den
+
+
+def map_ratio(N: np.ndarray, map_N: np.ndarray, W_rand_raw_2: float, alpha: float) -> np.ndarray:
+    """Per-cell W_0 W_1 / <B_0 B_1> for one radius (the maps of Sec. 4): N(x) C^N(x)
+    over the cell average of B_0 B_1 = alpha^2 R_raw C^R, i.e. alpha^2 W_R2 / N_c.
+    Its cell average is the 2pcf of that radius."""
+    return N * map_N / (alpha * alpha * W_rand_raw_2 / N.size)
+
+
+def value_histogram(values: np.ndarray, lo: float, hi: float, n_bins: int) -> np.ndarray:
+    """Counts of values in n_bins equal bins of [lo, hi), then one bin of values
+    below lo and one of values at or above hi (NaN counts as above)."""
+    v = np.asarray(values, dtype=np.float64).ravel()
+    counts = np.zeros(n_bins + 2, dtype=np.int64)
+    inside = (v >= lo) & (v < hi)
+    b = np.floor((v[inside] - lo) / (hi - lo) * n_bins).astype(np.int64)
+    b = np.minimum(b, n_bins - 1)
+    counts[:n_bins] = np.bincount(b, minlength=n_bins)
+    counts[n_bins] = int((v < lo).sum())
+    counts[n_bins + 1] = int(v.size - inside.sum() - (v < lo).sum())
+    return counts

@@ -437,3 +437,49 @@ def test_cross_matches_explicit_tracer_sums_and_n2_symmetry():
     w01 = oc.npcf_cross(d0, d1, r, dims, origin, cell, radii, 2, w0, w1, wr)["W_cross"]
     w10 = oc.npcf_cross(d1, d0, r, dims, origin, cell, radii, 2, w1, w0, wr)["W_cross"]
     assert np.allclose(w01, w10, rtol=1e-10, atol=1e-9)
+
+
+# ---------------------------------------------------------------------------
+# regions combined (Eq. ksi3combined), maps of W_0 W_1 / <B_0 B_1>, histograms
+# ---------------------------------------------------------------------------
+
+def test_combined_regions_equal_the_union_estimator():
+    """Two regions far apart with equal alpha: combining their numerators and
+    denominators gives the estimator of the union catalog."""
+    dims, origin, cell = (40, 16, 16), (0.0, 0.0, 0.0), 1.0
+    rng = np.random.default_rng(40)
+    d1 = rng.uniform(1, 8, size=(60, 3)).astype(np.float32)
+    r1 = rng.uniform(1, 8, size=(300, 3)).astype(np.float32)
+    d2 = (rng.uniform(1, 8, size=(60, 3)) + [24, 0, 0]).astype(np.float32)
+    r2 = (rng.uniform(1, 8, size=(300, 3)) + [24, 0, 0]).astype(np.float32)
+    radii = [1.0, 2.0, 3.0]
+    for n in (2, 3):
+        a = oc.npcf(d1, r1, dims, origin, cell, radii, n)
+        b = oc.npcf(d2, r2, dims, origin, cell, radii, n)
+        u = oc.npcf(np.concatenate([d1, d2]), np.concatenate([r1, r2]), dims, origin, cell, radii, n)
+        assert a["alpha"] == b["alpha"] == u["alpha"]
+        xi, num, den = oc.combine_regions([a["W_delta"], b["W_delta"]], [a["W_rand_raw"], b["W_rand_raw"]],
+                                          [a["alpha"], b["alpha"]], n)
+        assert np.allclose(xi, u["xi"], rtol=1e-12, atol=0)
+        single = oc.combine_regions([a["W_delta"]], [a["W_rand_raw"]], [a["alpha"]], n)[0]
+        assert np.allclose(single, a["xi"], rtol=1e-14, atol=0)
+
+
+def test_map_ratio_average_is_the_2pcf():
+    dims, origin, cell = (16, 16, 16), (0.0, 0.0, 0.0), 1.0
+    d, r, wd, wr = _tiny_catalog(200, 2000, 16.0, 41, weighted=True)
+    res = oc.npcf(d, r, dims, origin, cell, [2.0, 3.0, 5.0], 2, wd, wr)
+    for m in range(3):
+        mp = oc.map_ratio(res["N"], res["maps_N"][m], res["W_rand_raw"][m], res["alpha"])
+        assert math.isclose(mp.mean(), res["xi"][m], rel_tol=1e-12)
+
+
+def test_value_histogram_edges():
+    v = np.array([-1.0, 0.0, 0.25, 0.5, 0.999, 1.0, 2.0, np.nan])
+    c = oc.value_histogram(v, 0.0, 1.0, 4)
+    assert c.tolist() == [1, 1, 1, 1, 1, 3]   # [0,.25) [.25,.5) [.5,.75) [.75,1) below above
+    rng = np.random.default_rng(42)
+    w = rng.normal(size=10000)
+    c = oc.value_histogram(w, -2.0, 2.0, 16)
+    ref, _ = np.histogram(w[(w >= -2) & (w < 2)], bins=16, range=(-2.0, 2.0))
+    assert np.array_equal(c[:16], ref) and c[16] == (w < -2).sum() and c[17] == (w >= 2).sum()

@@ -266,6 +266,33 @@ int conker_pair_spectral(conker_ctx *ctx, const conker_grid *grid, conker_dtype 
 int conker_delta_field(conker_ctx *ctx, const conker_grid *grid, conker_dtype dtype, const void *d_D,
                        const void *d_R, const double *d_alpha, void *d_delta);
 
+/* ---- regions, maps and distributions (Sec. 3.3, Eq. ksi3combined; Sec. 4) ---
+ * conker_ratio_combined: regions (or mocks) measured separately, combined by
+ * adding numerators and denominators:
+ *   num[t] = sum_j W_delta[j][t],  den[t] = sum_j alpha_j^n W_rand[j][t],
+ *   xi[t] = num[t] / den[t]   (float64; regions summed in order j = 0, 1, ...).
+ * d_W_delta, d_W_rand: [n_regions][count] contiguous; d_alpha: [n_regions].
+ * d_num and d_den may be NULL. */
+int conker_ratio_combined(conker_ctx *ctx, int n_regions, const double *d_W_delta,
+                          const double *d_W_rand, const double *d_alpha, int n, int64_t count,
+                          double *d_xi, double *d_num, double *d_den);
+
+/* conker_map_ratio: the per-cell map W_0 W_1 / <B_0 B_1> of one radius,
+ *   out(x) = N(x) C^N(x) / (alpha^2 W_R2 / N_c),
+ * with C^N the map of N for that radius (conker_convolve_shells), W_R2 the
+ * n = 2 sum of R_raw for that radius and alpha the normalisation (device
+ * float64 scalars).  Its average over the cells is xi_2 of that radius.
+ * d_N, d_map, d_out: dtype [nx][ny][nz]; d_out may alias either input. */
+int conker_map_ratio(conker_ctx *ctx, const conker_grid *grid, conker_dtype dtype, const void *d_N,
+                     const void *d_map, const double *d_W_R2, const double *d_alpha, void *d_out);
+
+/* conker_value_histogram: counts of n values (dtype) in n_bins equal bins of
+ * [lo, hi) (bin = floor((v - lo) / (hi - lo) * n_bins) in float64), then the
+ * count below lo, then the count at or above hi (NaN included).
+ * d_counts: int64 [n_bins + 2], overwritten.  1 <= n_bins <= 16000, lo < hi. */
+int conker_value_histogram(conker_ctx *ctx, conker_dtype dtype, const void *d_values, int64_t n,
+                           double lo, double hi, int n_bins, int64_t *d_counts);
+
 /* conker_ratio: the estimator xi = W_delta / (alpha^n W_rand) in float64
  * (Eq. ksin_delta with B_i built on R = alpha R_raw).  All pointers are
  * device float64; d_alpha is a scalar. */

@@ -57,6 +57,12 @@ SIGNATURES = {
                                         ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_void_p, ct.c_void_p]),
     "conker_delta_field": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_void_p, ct.c_void_p,
                                       ct.c_void_p]),
+    "conker_ratio_combined": (ct.c_int, [ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int,
+                                         ct.c_int64, ct.c_void_p, ct.c_void_p, ct.c_void_p]),
+    "conker_map_ratio": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_void_p, ct.c_void_p,
+                                    ct.c_void_p, ct.c_void_p]),
+    "conker_value_histogram": (ct.c_int, [ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_int64, ct.c_double, ct.c_double,
+                                          ct.c_int, ct.c_void_p]),
     "conker_ratio": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int,
                                 ct.c_int64, ct.c_void_p]),
     "conker_synchronize": (ct.c_int, [ct.c_void_p]),

@@ -249,6 +249,36 @@ class Context:
                                                 _ptr(out)))
         return out
 
+    def ratio_combined(self, W_delta: torch.Tensor, W_rand: torch.Tensor, alpha: torch.Tensor, n: int):
+        """Regions combined (Eq. ksi3combined): W_delta, W_rand [n_regions, count], alpha [n_regions].
+        Returns (xi, numerator, denominator)."""
+        if W_delta.shape != W_rand.shape or W_delta.dim() != 2 or alpha.numel() != W_delta.shape[0]:
+            raise ValueError("W_delta / W_rand must be [n_regions, count] and alpha [n_regions]")
+        Wd, Wr, a = W_delta.contiguous(), W_rand.contiguous(), alpha.contiguous()
+        cnt = int(Wd.shape[1])
+        xi = torch.empty(cnt, dtype=torch.float64, device=Wd.device)
+        num, den = torch.empty_like(xi), torch.empty_like(xi)
+        self._check(self.lib.conker_ratio_combined(self.h, int(Wd.shape[0]), _ptr(Wd), _ptr(Wr), _ptr(a), int(n),
+                                                   cnt, _ptr(xi), _ptr(num), _ptr(den)))
+        return xi, num, den
+
+    def map_ratio(self, grid: Grid, N: torch.Tensor, map_N: torch.Tensor, W_R2: torch.Tensor, alpha: torch.Tensor,
+                  out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Per-cell W_0 W_1 / <B_0 B_1> of one radius (W_R2, alpha: device float64 scalars)."""
+        out = torch.empty_like(N) if out is None else out
+        g = grid.c()
+        self._check(self.lib.conker_map_ratio(self.h, ct.byref(g), _DT[N.dtype], _ptr(N), _ptr(map_N), _ptr(W_R2),
+                                              _ptr(alpha), _ptr(out)))
+        return out
+
+    def value_histogram(self, values: torch.Tensor, lo: float, hi: float, n_bins: int) -> torch.Tensor:
+        """int64 [n_bins + 2]: equal bins of [lo, hi), then below lo, then at or above hi."""
+        v = values.contiguous()
+        counts = torch.empty(n_bins + 2, dtype=torch.int64, device=v.device)
+        self._check(self.lib.conker_value_histogram(self.h, _DT[v.dtype], _ptr(v), int(v.numel()), float(lo),
+                                                    float(hi), int(n_bins), _ptr(counts)))
+        return counts
+
     def ratio_cross(self, Wc: torch.Tensor, Wr: torch.Tensor, alpha0: torch.Tensor, alpha1: torch.Tensor, n: int,
                     out: Optional[torch.Tensor] = None) -> torch.Tensor:
         out = torch.empty_like(Wc) if out is None else out

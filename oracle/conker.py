@@ -342,3 +342,76 @@ def value_histogram(values: np.ndarray, lo: float, hi: float, n_bins: int) -> np
     counts[n_bins] = int((v < lo).sum())
     counts[n_bins + 1] = int(v.size - inside.sum() - (v < lo).sum())
     return counts
+
+
+# ----------------------------------------------------------------------------
+# survey front end (Sec. 2.2, Eqs. hubbleint, cartesianx-z, factorizablility)
+# ----------------------------------------------------------------------------
+
+def hubble_e(z, Om: float, Ok: float, OL: float):
+    """E(z) = sqrt(Om (1+z)^3 + Ok (1+z)^2 + OL), the integrand's denominator of Eq. hubbleint."""
+    zp = 1.0 + np.asarray(z, dtype=np.float64)
+    return np.sqrt(Om * zp ** 3 + Ok * zp ** 2 + OL)
+
+
+def comoving_distance(z, Om: float = 0.307, Ok: float = 0.0, OL: float = 0.693,
+                      H0: float = 100.0, c: float = 300000.0) -> np.ndarray:
+    """r(z) = c/H0 int_0^z dz' / E(z') (Eq. hubbleint), adaptive quadrature per value
+    (with H0 = 100 the unit is Mpc/h, as in the paper's runs)."""
+    from scipy.integrate import quad
+    zz = np.atleast_1d(np.asarray(z, dtype=np.float64))
+    out = np.array([quad(lambda t: 1.0 / float(hubble_e(t, Om, Ok, OL)), 0.0, float(v),
+                         epsabs=0.0, epsrel=1e-13, limit=200)[0] for v in zz])
+    return (c / H0) * out
+
+
+def sky_to_cartesian(ra_deg, dec_deg, z, **cosmo) -> np.ndarray:
+    """Comoving Cartesian positions (Eqs. cartesianx, cartesiany, cartesianz):
+    X = r cos(dec) cos(ra), Y = r cos(dec) sin(ra), Z = r sin(dec); float64 [N, 3]."""
+    r = comoving_distance(z, **cosmo)
+    a = np.radians(np.asarray(ra_deg, dtype=np.float64))
+    d = np.radians(np.asarray(dec_deg, dtype=np.float64))
+    return np.stack([r * np.cos(d) * np.cos(a), r * np.cos(d) * np.sin(a), r * np.sin(d)], axis=1)
+
+
+def redshift_of_distance(r, z_max: float, Om: float = 0.307, Ok: float = 0.0, OL: float = 0.693,
+                         H0: float = 100.0, c: float = 300000.0, nodes: int = 4001) -> np.ndarray:
+    """z(r), the inverse of Eq. hubbleint, by a cubic spline through r(z) evaluated
+    with quadrature at `nodes` redshifts of [0, z_max] (r is monotonic in z)."""
+    from scipy.interpolate import CubicSpline
+    zk = np.linspace(0.0, z_max, nodes)
+    rk = comoving_distance(zk, Om, Ok, OL, H0, c)
+    return CubicSpline(rk, zk)(np.asarray(r, dtype=np.float64))
+
+
+def analytic_randoms(dims, origin, cell: float, n_tot: float, p_ang: np.ndarray, ra_range, dec_range,
+                     p_z: np.ndarray, z_range, Om: float = 0.307, Ok: float = 0.0, OL: float = 0.693,
+                     H0: float = 100.0, c: float = 300000.0) -> np.ndarray:
+    """Expected random count per cell for factorizable selection functions
+    (Eq. factorizablility): with P_ang a density per steradian on an equal-angle
+    (dec, ra) table and P_z a density in z on equal bins, the comoving number
+    density is n = N_tot P_ang P_z / (r^2 dr/dz), dr/dz = c / (H0 E(z)), and the
+    cell count is n at the cell centre times cell^3.  Cells whose centre falls
+    outside the tables get 0."""
+    nx, ny, nz = (int(v) for v in dims)
+    ix, iy, iz = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
+    X = origin[0] + (ix + 0.5) * cell
+    Y = origin[1] + (iy + 0.5) * cell
+    Z = origin[2] + (iz + 0.5) * cell
+    r = np.sqrt(X * X + Y * Y + Z * Z)
+    dec = np.degrees(np.arcsin(Z / r))
+    ra = np.degrees(np.arctan2(Y, X)) % 360.0
+    # z(r) from a table that reaches past the farthest cell centre (no extrapolation)
+    z_hi = max(float(z_range[1]), 0.01)
+    while comoving_distance([z_hi], Om, Ok, OL, H0, c)[0] < r.max() and z_hi < 64.0:
+        z_hi *= 2.0
+    z = redshift_of_distance(r, z_hi, Om, Ok, OL, H0, c)
+    nd, na = p_ang.shape
+    ia = np.floor((ra - ra_range[0]) / (ra_range[1] - ra_range[0]) * na).astype(np.int64)
+    idd = np.floor((dec - dec_range[0]) / (dec_range[1] - dec_range[0]) * nd).astype(np.int64)
+    izz = np.floor((z - z_range[0]) / (z_range[1] - z_range[0]) * len(p_z)).astype(np.int64)
+    ok = (ia >= 0) & (ia < na) & (idd >= 0) & (idd < nd) & (izz >= 0) & (izz < len(p_z)) & (r > 0)
+    out = np.zeros(r.shape)
+    drdz = c / (H0 * hubble_e(z, Om, Ok, OL))
+    out[ok] = n_tot * p_ang[idd[ok], ia[ok]] * p_z[izz[ok]] / (r[ok] ** 2 * drdz[ok]) * cell ** 3
+    return out

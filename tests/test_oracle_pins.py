@@ -483,3 +483,54 @@ def test_value_histogram_edges():
     c = oc.value_histogram(w, -2.0, 2.0, 16)
     ref, _ = np.histogram(w[(w >= -2) & (w < 2)], bins=16, range=(-2.0, 2.0))
     assert np.array_equal(c[:16], ref) and c[16] == (w < -2).sum() and c[17] == (w >= 2).sum()
+
+
+# ---------------------------------------------------------------------------
+# survey front end (Eqs. hubbleint, cartesian, factorizablility)
+# ---------------------------------------------------------------------------
+
+def test_comoving_distance_closed_forms():
+    z = np.array([0.0, 0.1, 0.57, 1.0, 2.5])
+    c, H0 = 300000.0, 100.0
+    eds = oc.comoving_distance(z, Om=1.0, Ok=0.0, OL=0.0)       # Einstein-de Sitter
+    assert np.allclose(eds, 2 * c / H0 * (1 - 1 / np.sqrt(1 + z)), rtol=1e-12, atol=1e-9)
+    lam = oc.comoving_distance(z, Om=0.0, Ok=0.0, OL=1.0)       # de Sitter
+    assert np.allclose(lam, c / H0 * z, rtol=1e-12, atol=1e-9)
+    cur = oc.comoving_distance(z, Om=0.0, Ok=1.0, OL=0.0)       # empty, E = 1 + z
+    assert np.allclose(cur, c / H0 * np.log1p(z), rtol=1e-12, atol=1e-9)
+    # the paper's cosmology at the CMASS median redshift: ~1.5 Gpc/h
+    assert 1400.0 < oc.comoving_distance([0.57])[0] < 1600.0
+
+
+def test_sky_to_cartesian_geometry_and_inverse():
+    rng = np.random.default_rng(90)
+    ra, dec, z = rng.uniform(0, 360, 50), rng.uniform(-80, 80, 50), rng.uniform(0.2, 0.8, 50)
+    xyz = oc.sky_to_cartesian(ra, dec, z)
+    r = np.linalg.norm(xyz, axis=1)
+    assert np.allclose(r, oc.comoving_distance(z), rtol=1e-13)
+    assert np.allclose(np.degrees(np.arcsin(xyz[:, 2] / r)), dec, atol=1e-9)
+    assert np.allclose(np.degrees(np.arctan2(xyz[:, 1], xyz[:, 0])) % 360.0, ra, atol=1e-9)
+    # z(r) inverts r(z); Einstein-de Sitter inverse in closed form
+    assert np.allclose(oc.redshift_of_distance(r, 1.0), z, atol=1e-10)
+    ze = oc.redshift_of_distance(np.array([500.0, 1500.0, 3000.0]), 3.0, Om=1.0, Ok=0.0, OL=0.0)
+    rr = np.array([500.0, 1500.0, 3000.0]) * 100.0 / (2 * 300000.0)
+    assert np.allclose(ze, 1 / (1 - rr) ** 2 - 1, atol=1e-10)
+
+
+def test_analytic_randoms_integrate_to_n_tot():
+    """A full-sky, constant-P_z shell sampled on a fine grid holds about N_tot
+    expected randoms (midpoint rule), and nothing outside the z range."""
+    p_ang = np.full((18, 36), 1.0 / (4 * np.pi))         # uniform per steradian
+    z_range = (0.1, 0.2)
+    p_z = np.full(4, 1.0 / (z_range[1] - z_range[0]))
+    r0, r1 = oc.comoving_distance(list(z_range))
+    g = 8.0
+    nside = int(np.ceil(2 * r1 / g)) + 2
+    nside += nside % 2
+    origin = (-nside * g / 2,) * 3
+    R = oc.analytic_randoms((nside,) * 3, origin, g, 1e6, p_ang, (0.0, 360.0), (-90.0, 90.0), p_z, z_range)
+    assert abs(R.sum() / 1e6 - 1.0) < 0.01
+    idx = np.indices(R.shape).reshape(3, -1).T
+    centres = np.asarray(origin) + (idx + 0.5) * g
+    rr = np.linalg.norm(centres, axis=1).reshape(R.shape)
+    assert np.all(R[(rr < r0 - 1e-9) | (rr > r1 + 1e-9)] == 0.0)

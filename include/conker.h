@@ -293,6 +293,38 @@ int conker_map_ratio(conker_ctx *ctx, const conker_grid *grid, conker_dtype dtyp
 int conker_value_histogram(conker_ctx *ctx, conker_dtype dtype, const void *d_values, int64_t n,
                            double lo, double hi, int n_bins, int64_t *d_counts);
 
+/* ---- survey front end (Sec. 2.2, Eqs. hubbleint, cartesianx-z, factorizablility)
+ * Fiducial cosmology: E(z) = sqrt(omega_m (1+z)^3 + omega_k (1+z)^2 +
+ * omega_lambda), comoving distance r(z) = c/h0 int_0^z dz'/E(z') (with
+ * h0 = 100 and c in km/s the unit is Mpc/h).  r(z) is tabulated on [0, z_max]
+ * for each call. */
+typedef struct {
+    double omega_m, omega_k, omega_lambda;
+    double h0, c;
+    double z_max;   /* largest redshift converted; E(z)^2 must stay positive on [0, z_max] */
+} conker_cosmology;
+
+/* conker_sky_to_cartesian: X = r cos(dec) cos(ra), Y = r cos(dec) sin(ra),
+ * Z = r sin(dec) with r = r(z).  d_ra_deg, d_dec_deg, d_z: float64 [n] device
+ * arrays (degrees); d_pos: float32 [n][3], ready for conker_grid_assign.
+ * Redshifts outside [0, z_max] (or NaN) give NaN positions, which
+ * conker_grid_assign skips and counts. */
+int conker_sky_to_cartesian(conker_ctx *ctx, const conker_cosmology *cosmo, const double *d_ra_deg,
+                            const double *d_dec_deg, const double *d_z, int64_t n, float *d_pos);
+
+/* conker_analytic_randoms: the expected random count per cell for
+ * factorizable selection functions, instead of a random catalog:
+ *   R(cell) = N_tot P_ang(ra, dec) P_z(z) / (r^2 dr/dz) * cell^3
+ * at the cell centre, with dr/dz = c/(h0 E(z)).  P_ang: density per steradian
+ * on an equal-angle table d_p_ang[n_dec][n_ra] over ra_range x dec_range
+ * (degrees, host arrays of 2); P_z: density in z on n_z equal bins of z_range
+ * (inside [0, z_max]).  Cells whose centre falls outside a table get 0.
+ * d_R: dtype [nx][ny][nz], overwritten. */
+int conker_analytic_randoms(conker_ctx *ctx, const conker_grid *grid, conker_dtype dtype,
+                            const conker_cosmology *cosmo, double n_tot, const double *d_p_ang,
+                            int n_dec, int n_ra, const double *h_ra_range, const double *h_dec_range,
+                            const double *d_p_z, int n_z, const double *h_z_range, void *d_R);
+
 /* conker_ratio: the estimator xi = W_delta / (alpha^n W_rand) in float64
  * (Eq. ksin_delta with B_i built on R = alpha R_raw).  All pointers are
  * device float64; d_alpha is a scalar. */

@@ -6,6 +6,7 @@ PyTorch tensors.  See include/conker.h for the C ABI.
 from .api import (  # noqa: F401
     ConkerError,
     Context,
+    Cosmology,
     Grid,
     Job,
     PRECISIONS,

@@ -63,6 +63,11 @@ SIGNATURES = {
                                     ct.c_void_p, ct.c_void_p]),
     "conker_value_histogram": (ct.c_int, [ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_int64, ct.c_double, ct.c_double,
                                           ct.c_int, ct.c_void_p]),
+    "conker_sky_to_cartesian": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p,
+                                           ct.c_int64, ct.c_void_p]),
+    "conker_analytic_randoms": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_double,
+                                           ct.c_void_p, ct.c_int, ct.c_int, ct.c_void_p, ct.c_void_p, ct.c_void_p,
+                                           ct.c_int, ct.c_void_p, ct.c_void_p]),
     "conker_ratio": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int,
                                 ct.c_int64, ct.c_void_p]),
     "conker_synchronize": (ct.c_int, [ct.c_void_p]),
@@ -78,6 +83,11 @@ SIGNATURES = {
 
 class ConkerGrid(ct.Structure):
     _fields_ = [("dims", ct.c_int32 * 3), ("origin", ct.c_double * 3), ("cell", ct.c_double)]
+
+
+class ConkerCosmology(ct.Structure):
+    _fields_ = [("omega_m", ct.c_double), ("omega_k", ct.c_double), ("omega_lambda", ct.c_double),
+                ("h0", ct.c_double), ("c", ct.c_double), ("z_max", ct.c_double)]
 
 
 class ConkerJob(ct.Structure):

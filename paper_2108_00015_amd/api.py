@@ -279,6 +279,39 @@ class Context:
                                                     float(hi), int(n_bins), _ptr(counts)))
         return counts
 
+    # ---- survey front end ----------------------------------------------------
+    def sky_to_cartesian(self, ra_deg: torch.Tensor, dec_deg: torch.Tensor, z: torch.Tensor,
+                         cosmo: Optional["Cosmology"] = None) -> torch.Tensor:
+        """float32 [n, 3] comoving positions from float64 ra, dec (degrees) and z."""
+        cosmo = Cosmology() if cosmo is None else cosmo
+        ra, dec, zz = (t.contiguous() for t in (ra_deg, dec_deg, z))
+        if any(t.dtype != torch.float64 for t in (ra, dec, zz)) or not (ra.numel() == dec.numel() == zz.numel()):
+            raise ValueError("ra, dec, z must be float64 of one length")
+        pos = torch.empty((ra.numel(), 3), dtype=torch.float32, device=ra.device)
+        cs = cosmo.c_struct()
+        self._check(self.lib.conker_sky_to_cartesian(self.h, ct.byref(cs), _ptr(ra), _ptr(dec), _ptr(zz),
+                                                     int(ra.numel()), _ptr(pos)))
+        return pos
+
+    def analytic_randoms(self, grid: Grid, n_tot: float, p_ang: torch.Tensor, ra_range, dec_range,
+                         p_z: torch.Tensor, z_range, cosmo: Optional["Cosmology"] = None,
+                         dtype=torch.float64) -> torch.Tensor:
+        """Expected random count per cell from factorizable selection functions (Eq. factorizablility)."""
+        cosmo = Cosmology() if cosmo is None else cosmo
+        pa, pz = p_ang.contiguous(), p_z.contiguous()
+        if pa.dtype != torch.float64 or pz.dtype != torch.float64 or pa.dim() != 2:
+            raise ValueError("p_ang [n_dec, n_ra] and p_z [n_z] must be float64")
+        R = torch.empty(tuple(int(d) for d in grid.dims), dtype=dtype, device=pa.device)
+        g = grid.c()
+        cs = cosmo.c_struct()
+        rr = (ct.c_double * 2)(*ra_range)
+        dr = (ct.c_double * 2)(*dec_range)
+        zr = (ct.c_double * 2)(*z_range)
+        self._check(self.lib.conker_analytic_randoms(self.h, ct.byref(g), _DT[dtype], ct.byref(cs), float(n_tot),
+                                                     _ptr(pa), int(pa.shape[0]), int(pa.shape[1]), rr, dr, _ptr(pz),
+                                                     int(pz.numel()), zr, _ptr(R)))
+        return R
+
     def ratio_cross(self, Wc: torch.Tensor, Wr: torch.Tensor, alpha0: torch.Tensor, alpha1: torch.Tensor, n: int,
                     out: Optional[torch.Tensor] = None) -> torch.Tensor:
         out = torch.empty_like(Wc) if out is None else out
@@ -342,6 +375,20 @@ class Context:
         self._check(self.lib.conker_ratio(self.h, _ptr(Wd), _ptr(Wr), _ptr(alpha), int(n), int(Wd.numel()),
                                           _ptr(out)))
         return out
+
+
+@dataclasses.dataclass
+class Cosmology:
+    """Fiducial cosmology of Eq. hubbleint (defaults: the paper's runs, Sec. 3)."""
+    omega_m: float = 0.307
+    omega_k: float = 0.0
+    omega_lambda: float = 0.693
+    h0: float = 100.0
+    c: float = 300000.0
+    z_max: float = 3.0
+
+    def c_struct(self) -> _lib.ConkerCosmology:
+        return _lib.ConkerCosmology(self.omega_m, self.omega_k, self.omega_lambda, self.h0, self.c, self.z_max)
 
 
 @dataclasses.dataclass

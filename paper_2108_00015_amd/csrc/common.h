@@ -37,6 +37,7 @@ struct conker_ctx {
     conker::Buf full;       // reduced block matrices of the summation stage
     conker::Buf support;    // line mask, per-slab counts and list of lines carrying field
     conker::Buf scales;     // split-f16 summation: largest |value| per map and of the field
+    conker::Buf cosmo;      // comoving-distance table of the survey front end
     std::map<uint64_t, conker::Buf> tables;  // item / tuple tables, keyed by (n_radii, n, prec)
     // per-launch event timing (conker_profile_enable)
     int n_cu = 0;
@@ -79,6 +80,7 @@ enum ProfKind {
     PK_DIAG_REDUCE,
     PK_SUPPORT,
     PK_SPECTRAL,
+    PK_SURVEY,
     PK_COUNT
 };
 

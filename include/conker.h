@@ -7,6 +7,15 @@
  *   kernels      (Sec. 2.3)                         conker_make_shell_kernels
  *   convolution  (Sec. 2.4, Eqs. countconv/randconv) conker_convolve_shells
  *   summation    (Sec. 2.5, Eq. ksin_delta)         conker_contract_npt, conker_ratio
+ *   both at once, maps never stored                 conker_convolve_contract
+ * and the paper's other forms: equidistant sums (Eq. ksinDiag,
+ * conker_convolve_diag / conker_contract_diag), cross-correlations (Sec. 2.7,
+ * *_cross), continuous delta fields (Sec. 2.6, conker_delta_field), n = 2 in
+ * Fourier space (conker_pair_spectral), regions combined (Eq. ksi3combined,
+ * conker_ratio_combined), maps and their distributions (Sec. 4,
+ * conker_map_ratio, conker_value_histogram), the survey front end (Sec. 2.2,
+ * conker_sky_to_cartesian, conker_analytic_randoms) and batches of catalogs
+ * replayed as one HIP graph (conker_batch_*).
  *
  * Conventions shared by every call
  * --------------------------------
@@ -14,8 +23,8 @@
  *   owns every buffer it passes; the library never frees or retains them past
  *   the call's stream work.
  * - Grids are C order [nx][ny][nz] (z fastest), real float32 or float64 per
- *   the conker_dtype argument.  Supported axis lengths: 32, 64, 128, 256, 512,
- *   1024 (powers of two).
+ *   the conker_dtype argument.  Supported axis lengths for every call that
+ *   transforms: 32, 64, 96, 128, 192, 256, 384, 512, 1024.
  * - Every call enqueues work on the context's HIP stream and returns without
  *   waiting for it (except where noted).  A context serves one stream and is
  *   not thread-safe.

@@ -148,3 +148,45 @@ def test_batch_rejects_bad_jobs(mocks):
     with pytest.raises(ck.ConkerError):
         ctx.batch_launch()
     ctx.close()
+
+
+def test_batch_fused_jobs_graph_replay():
+    """Jobs on a grid with 512-cell z lines take the fused pass (line masks,
+    list-driven transforms); graph replays match the eager pass and the oracle."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2108_00015_amd as ck
+    DEV = "cuda:0"
+    dims, cell = (32, 64, 512), 1.0
+    radii = [1.0, 2.0, 3.5, 5.0, 8.0, 12.0]
+    cats = []
+    for j in range(3):
+        rng = np.random.default_rng(500 + j)
+        d = rng.uniform(0, 30, size=(4000 + 1000 * j, 3)).astype(np.float32)
+        r = rng.uniform(0, 30, size=(40000, 3)).astype(np.float32)
+        cats.append((d, r))
+    s = torch.cuda.Stream()
+    ctx = ck.Context(0, stream=s)
+    grid = ck.Grid(dims, (0, 0, 0), cell)
+    ks, _ = ctx.make_shell_kernels(grid, radii, torch.float32)
+    jobs = [ck.make_job(grid, ks, 3, "split_bf16", torch.from_numpy(d).to(DEV), torch.from_numpy(r).to(DEV))
+            for d, r in cats]
+    assert all(j.maps_N is None for j in jobs)      # fused
+    torch.cuda.synchronize()
+    ctx.batch_plan(jobs)
+    first = _outs(jobs)
+    ctx.batch_capture()
+    for rep in range(3):
+        for j in jobs:
+            j.W_delta.fill_(5.0)
+            j.xi.fill_(0.0)
+        torch.cuda.synchronize()
+        ctx.batch_launch()
+        ctx.synchronize()
+        for k, o in enumerate(_outs(jobs)):
+            assert _rel(o, first[k]) <= 1e-5, (rep, k)
+    for k, (d, r) in enumerate(cats):
+        ref = oc.npcf(d, r, dims, (0, 0, 0), cell, radii, 3)
+        assert _rel(jobs[k].W_delta.cpu().numpy(), ref["W_delta"]) <= 1e-5
+        assert _rel(jobs[k].W_rand.cpu().numpy(), ref["W_rand_raw"]) <= 1e-5
+    ctx.close()

@@ -262,6 +262,14 @@ def bench_mocks(args):
     t = time.perf_counter()
     ctx.batch_plan(jobs)
     log("plan (one eager pass, allocations): %.2f s" % (time.perf_counter() - t))
+    tuned = None
+    if not args.no_autotune:
+        t = time.perf_counter()
+        chosen = ctx.batch_autotune(reps=2)
+        tuned = {}
+        for (g, _), c in zip(sizes, chosen):
+            tuned.setdefault("%d^3" % g, c)
+        log("autotune: %.2f s, %s" % (time.perf_counter() - t, tuned))
     ctx.batch_capture()
     for _ in range(args.warmup):
         ctx.batch_launch()
@@ -291,7 +299,8 @@ def bench_mocks(args):
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": MOCKS_NAME, "n_mocks": len(sizes), "grids": sorted({g for g, _ in sizes}),
                    "total_cells": total_cells, "points": npts, "n_radii": ns, "n": args.n,
-                   "summation": args.prec, "fft": "f32", "execution": "one HIP graph per batch"},
+                   "summation": args.prec, "fft": "f32", "execution": "one HIP graph per batch",
+                   "launch_settings": tuned if tuned is not None else "defaults"},
         "roofline": None, "cpu_baseline": None, "stages_eager": stages,
     }
     print(json.dumps(line), flush=True)
@@ -310,6 +319,8 @@ def main():
     ap.add_argument("--mode", default="npcf", choices=["npcf", "diag", "pair2"],
                     help="npcf: all tuples of order n; diag: equidistant sums for orders 2..n without maps; "
                          "pair2: n = 2 from the spectra")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="mock batches: keep the default launch settings instead of timing them per grid shape")
     ap.add_argument("--field-at-a-time", action="store_true",
                     help="separate path with one maps buffer, N then R (large grids)")
     args = ap.parse_args()

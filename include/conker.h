@@ -15,7 +15,8 @@
  * conker_ratio_combined), maps and their distributions (Sec. 4,
  * conker_map_ratio, conker_value_histogram), the survey front end (Sec. 2.2,
  * conker_sky_to_cartesian, conker_analytic_randoms) and batches of catalogs
- * replayed as one HIP graph (conker_batch_*).
+ * replayed as one HIP graph (conker_batch_*), whose launch shapes can be
+ * tuned per job shape by timing them (conker_batch_autotune, conker_set_tune).
  *
  * Conventions shared by every call
  * --------------------------------
@@ -386,6 +387,50 @@ int conker_batch_plan(conker_ctx *ctx, const conker_job *jobs, int n_jobs);
 int conker_batch_run(conker_ctx *ctx);
 int conker_batch_capture(conker_ctx *ctx);
 int conker_batch_launch(conker_ctx *ctx);
+
+/* ---- launch shapes and their tuning ---------------------------------------
+ * Not part of the method: how the convolution and summation stages are cut
+ * into workgroups.  Every choice computes the same sums (the same arithmetic
+ * in a different order of tiles); 0 in any field means the built-in default,
+ * which an environment switch of the same meaning may override.
+ *   x_tile, y_tile  columns per tile of the x- and y-axis inverse passes and
+ *                   of the forward passes of those axes:
+ *                   1 narrow (16 float32 / 8 float64 columns), 2 wide (twice
+ *                   that: 256-byte runs).  Default: x wide, y narrow.
+ *   x_resident      x-axis inverse pass: 1 streamed, 2 kernel-multiply tile
+ *                   kept resident in LDS across the batch's radii.  Default 2.
+ *   mm_kernel       matrix-core summation: 1 one output tile per wave,
+ *                   2 operand sharing across a workgroup.  Default: 2 above
+ *                   four 32 x 32 output tiles, else 1.
+ *   radius_batch    radii (or radius pairs) per inverse batch, 1..64.
+ *                   Default: as many as half of the free device memory holds.
+ *   ms              conker_batch_autotune only: the measured time of one run
+ *                   of the job with this setting (milliseconds).
+ * conker_set_tune: the setting used by every later call on the context
+ *   (NULL: all defaults); rejects values outside the ranges above.
+ * conker_get_tune: the current setting. */
+typedef struct {
+    int32_t x_tile;
+    int32_t y_tile;
+    int32_t x_resident;
+    int32_t mm_kernel;
+    int32_t radius_batch;
+    float ms;
+} conker_tune;
+
+int conker_set_tune(conker_ctx *ctx, const conker_tune *h_tune);
+int conker_get_tune(const conker_ctx *ctx, conker_tune *h_tune);
+
+/* conker_batch_autotune: after conker_batch_plan, picks a setting per job
+ * shape (grid dimensions, dtype, order, number of radii, summation arithmetic,
+ * fused or not) by timing the first job of that shape with HIP events: start
+ * from the defaults and, one field at a time, keep the alternative that is
+ * faster than the best so far (the minimum of `reps` timed runs, 1..16, after
+ * one untimed run per candidate).  Later conker_batch_run /
+ * conker_batch_capture use the chosen settings job by job; the jobs' outputs
+ * are recomputed with them before returning.  h_chosen (or NULL) receives
+ * n_jobs settings with their times.  Synchronous. */
+int conker_batch_autotune(conker_ctx *ctx, int reps, conker_tune *h_chosen);
 
 /* Blocks until all work queued on the context's stream has finished. */
 int conker_synchronize(conker_ctx *ctx);

@@ -75,6 +75,9 @@ SIGNATURES = {
     "conker_batch_run": (ct.c_int, [ct.c_void_p]),
     "conker_batch_capture": (ct.c_int, [ct.c_void_p]),
     "conker_batch_launch": (ct.c_int, [ct.c_void_p]),
+    "conker_set_tune": (ct.c_int, [ct.c_void_p, ct.c_void_p]),
+    "conker_get_tune": (ct.c_int, [ct.c_void_p, ct.c_void_p]),
+    "conker_batch_autotune": (ct.c_int, [ct.c_void_p, ct.c_int, ct.c_void_p]),
     "conker_profile_enable": (ct.c_int, [ct.c_void_p, ct.c_int]),
     "conker_profile_read": (ct.c_int, [ct.c_void_p, ct.c_int, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_double)]),
     "conker_profile_kind_name": (ct.c_char_p, [ct.c_int]),
@@ -88,6 +91,11 @@ class ConkerGrid(ct.Structure):
 class ConkerCosmology(ct.Structure):
     _fields_ = [("omega_m", ct.c_double), ("omega_k", ct.c_double), ("omega_lambda", ct.c_double),
                 ("h0", ct.c_double), ("c", ct.c_double), ("z_max", ct.c_double)]
+
+
+class ConkerTune(ct.Structure):
+    _fields_ = [("x_tile", ct.c_int32), ("y_tile", ct.c_int32), ("x_resident", ct.c_int32),
+                ("mm_kernel", ct.c_int32), ("radius_batch", ct.c_int32), ("ms", ct.c_float)]
 
 
 class ConkerJob(ct.Structure):

@@ -26,6 +26,15 @@ class ConkerError(RuntimeError):
         self.status = status
 
 
+TUNE_FIELDS = ("x_tile", "y_tile", "x_resident", "mm_kernel", "radius_batch")
+
+
+def _tune_dict(t) -> dict:
+    d = {k: int(getattr(t, k)) for k in TUNE_FIELDS}
+    d["ms"] = float(t.ms)
+    return d
+
+
 @dataclasses.dataclass(frozen=True)
 class Grid:
     """Grid of spacing `cell` whose cell (0, 0, 0) starts at `origin` (Sec. 2.2)."""
@@ -367,6 +376,29 @@ class Context:
 
     def batch_launch(self):
         self._check(self.lib.conker_batch_launch(self.h))
+
+    def batch_autotune(self, reps: int = 3) -> list:
+        """Times launch settings per job shape (after batch_plan) and keeps the
+        fastest for later batch_run / batch_capture; returns one dict per job."""
+        jobs = getattr(self, "_jobs", [])
+        arr = (_lib.ConkerTune * len(jobs))()
+        self._check(self.lib.conker_batch_autotune(self.h, int(reps), ct.cast(arr, ct.c_void_p) if jobs else None))
+        return [_tune_dict(t) for t in arr]
+
+    def set_tune(self, **fields):
+        """Launch setting for later calls: x_tile, y_tile (1 narrow, 2 wide),
+        x_resident (1 streamed, 2 resident), mm_kernel (1 per-wave tiles,
+        2 operand sharing), radius_batch; 0 or omitted = default."""
+        bad = set(fields) - set(TUNE_FIELDS)
+        if bad:
+            raise ValueError("unknown launch setting(s): %s" % sorted(bad))
+        t = _lib.ConkerTune(**{k: int(v) for k, v in fields.items()})
+        self._check(self.lib.conker_set_tune(self.h, ct.byref(t)))
+
+    def get_tune(self) -> dict:
+        t = _lib.ConkerTune()
+        self._check(self.lib.conker_get_tune(self.h, ct.byref(t)))
+        return _tune_dict(t)
 
     def ratio(self, Wd: torch.Tensor, Wr: torch.Tensor, alpha: torch.Tensor, n: int,
               out: Optional[torch.Tensor] = None) -> torch.Tensor:

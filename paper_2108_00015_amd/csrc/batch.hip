@@ -5,7 +5,10 @@
 // run eagerly again, or captured into one HIP graph and replayed.  Regions or
 // mocks are combined afterwards by adding numerators and denominators
 // (Eq. ksi3combined).
+#include <algorithm>
 #include <cstring>
+#include <map>
+#include <tuple>
 #include <vector>
 
 #include "common.h"
@@ -62,6 +65,101 @@ int run_job(conker_ctx *c, const conker_job &j) {
     return CONKER_OK;
 }
 
+// Launch shapes of job k while it is enqueued; the context setting again after.
+struct TuneScope {
+    conker_ctx *c;
+    TuneScope(conker_ctx *ctx, const conker_tune &t) : c(ctx) { c->tune = t; }
+    ~TuneScope() { c->tune = c->user_tune; }
+};
+
+const conker_tune &tune_of(const conker_ctx *c, size_t k) {
+    return c->job_tune.size() == c->jobs.size() ? c->job_tune[k] : c->user_tune;
+}
+
+int run_all(conker_ctx *c) {
+    for (size_t k = 0; k < c->jobs.size(); ++k) {
+        TuneScope ts(c, tune_of(c, k));
+        CK_OK(run_job(c, c->jobs[k]));
+    }
+    return CONKER_OK;
+}
+
+bool tune_ok(const conker_tune &t) {
+    auto in = [](int v, int lo, int hi) { return v >= lo && v <= hi; };
+    return in(t.x_tile, 0, 2) && in(t.y_tile, 0, 2) && in(t.x_resident, 0, 2) && in(t.mm_kernel, 0, 2) &&
+           in(t.radius_batch, 0, 64);
+}
+
+// Shortest of `reps` timed runs of job j with setting t (after one untimed run
+// that also grows any workspace the setting needs).  Infeasible settings
+// (workspace above the cap or the device's memory) time as infinity.
+int time_job(conker_ctx *c, const conker_job &j, const conker_tune &t, int reps, hipEvent_t e0, hipEvent_t e1,
+             float *ms) {
+    TuneScope ts(c, t);
+    int st = run_job(c, j);
+    if (st == CONKER_ENOMEM) {
+        (void)hipGetLastError();   // a failed allocation leaves its status behind
+        CK_HIP(c, hipStreamSynchronize(c->stream));
+        c->err.clear();
+        *ms = 3.0e38f;
+        return CONKER_OK;
+    }
+    CK_OK(st);
+    float best = 3.0e38f;
+    for (int r = 0; r < reps; ++r) {
+        CK_HIP(c, hipEventRecord(e0, c->stream));
+        CK_OK(run_job(c, j));
+        CK_HIP(c, hipEventRecord(e1, c->stream));
+        CK_HIP(c, hipEventSynchronize(e1));
+        float v = 0.f;
+        CK_HIP(c, hipEventElapsedTime(&v, e0, e1));
+        best = std::min(best, v);
+    }
+    *ms = best;
+    return CONKER_OK;
+}
+
+// One sweep over the fields: keep an alternative when it beats the best time
+// so far by more than 1 % (timing noise keeps the earlier choice).
+int tune_job(conker_ctx *c, const conker_job &j, int reps, hipEvent_t e0, hipEvent_t e1, conker_tune *out) {
+    conker_tune best = c->user_tune;
+    float best_ms;
+    CK_OK(time_job(c, j, best, reps, e0, e1, &best_ms));
+    const bool fused = j.d_maps_N == nullptr;
+    const int slots = j.n_radii;
+    struct Knob {
+        int32_t conker_tune::*field;
+        std::vector<int> alt;
+    };
+    std::vector<Knob> knobs = {{&conker_tune::y_tile, {1, 2}},
+                               {&conker_tune::x_tile, {1, 2}},
+                               {&conker_tune::x_resident, {1, 2}}};
+    if (!fused && j.n >= 3 && j.prec != CONKER_MM_F64) knobs.push_back({&conker_tune::mm_kernel, {1, 2}});
+    if (!fused && slots >= 4) {
+        std::vector<int> rb = {(slots + 1) / 2};
+        if (slots >= 8) rb.push_back((slots + 3) / 4);
+        knobs.push_back({&conker_tune::radius_batch, rb});
+    }
+    for (const auto &k : knobs) {
+        const int start = best.*(k.field);
+        for (int v : k.alt) {
+            if (v == start) continue;
+            conker_tune cand = best;
+            cand.*(k.field) = v;
+            float ms;
+            CK_OK(time_job(c, j, cand, reps, e0, e1, &ms));
+            if (ms < 0.99f * best_ms) {
+                best = cand;
+                best_ms = ms;
+            }
+        }
+    }
+    if (!(best_ms < 1.0e38f)) return fail(c, CONKER_ENOMEM, "no launch setting of the job fits in memory");
+    best.ms = best_ms;
+    *out = best;
+    return CONKER_OK;
+}
+
 int check_job(conker_ctx *c, const conker_job &j, int k) {
     CK_OK(check_grid(c, &j.grid, true));
     if (j.dtype != CONKER_F32 && j.dtype != CONKER_F64) return fail(c, CONKER_EINVAL, "job %d: bad dtype", k);
@@ -89,8 +187,9 @@ extern "C" int conker_batch_plan(conker_ctx *c, const conker_job *jobs, int n_jo
         c->graph_exec = nullptr;
     }
     c->jobs.assign(jobs, jobs + n_jobs);
+    c->job_tune.clear();
     // one eager pass allocates every buffer and table the jobs use
-    for (const auto &j : c->jobs) CK_OK(run_job(c, j));
+    CK_OK(run_all(c));
     CK_HIP(c, hipStreamSynchronize(c->stream));
     return CONKER_OK;
 }
@@ -99,8 +198,7 @@ extern "C" int conker_batch_run(conker_ctx *c) {
     if (!c) return CONKER_EINVAL;
     if (c->jobs.empty()) return fail(c, CONKER_EINVAL, "no batch planned");
     CK_HIP(c, hipSetDevice(c->device));
-    for (const auto &j : c->jobs) CK_OK(run_job(c, j));
-    return CONKER_OK;
+    return run_all(c);
 }
 
 extern "C" int conker_batch_capture(conker_ctx *c) {
@@ -116,11 +214,7 @@ extern "C" int conker_batch_capture(conker_ctx *c) {
     c->prof = false;
     c->capturing = true;
     CK_HIP(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-    int st = CONKER_OK;
-    for (const auto &j : c->jobs) {
-        st = run_job(c, j);
-        if (st != CONKER_OK) break;
-    }
+    const int st = run_all(c);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(c->stream, &graph);
     c->capturing = false;
@@ -144,5 +238,69 @@ extern "C" int conker_batch_launch(conker_ctx *c) {
     if (!c->graph_exec) return fail(c, CONKER_EINVAL, "no captured batch");
     CK_HIP(c, hipSetDevice(c->device));
     CK_HIP(c, hipGraphLaunch(c->graph_exec, c->stream));
+    return CONKER_OK;
+}
+
+extern "C" int conker_set_tune(conker_ctx *c, const conker_tune *t) {
+    if (!c) return CONKER_EINVAL;
+    conker_tune v{};
+    if (t) v = *t;
+    v.ms = 0.f;
+    if (!tune_ok(v))
+        return fail(c, CONKER_EINVAL, "launch setting out of range (tiles, resident, kernel 0..2; radius batch 0..64)");
+    c->user_tune = v;
+    c->tune = v;
+    return CONKER_OK;
+}
+
+extern "C" int conker_get_tune(const conker_ctx *c, conker_tune *t) {
+    if (!c || !t) return CONKER_EINVAL;
+    *t = c->user_tune;
+    return CONKER_OK;
+}
+
+extern "C" int conker_batch_autotune(conker_ctx *c, int reps, conker_tune *h_chosen) {
+    if (!c) return CONKER_EINVAL;
+    if (c->jobs.empty()) return fail(c, CONKER_EINVAL, "no batch planned");
+    if (reps < 1 || reps > 16) return fail(c, CONKER_EINVAL, "reps %d outside 1..16", reps);
+    CK_HIP(c, hipSetDevice(c->device));
+    if (c->graph_exec) {   // recorded with the earlier settings
+        CK_HIP(c, hipGraphExecDestroy(c->graph_exec));
+        c->graph_exec = nullptr;
+    }
+    const bool prof = c->prof;
+    c->prof = false;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int st = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess
+                 ? CONKER_OK
+                 : fail(c, CONKER_EHIP, "hipEventCreate failed");
+    using Key = std::tuple<int, int, int, int, int, int, int, bool>;
+    std::map<Key, conker_tune> seen;
+    std::vector<conker_tune> chosen(c->jobs.size());
+    for (size_t k = 0; k < c->jobs.size() && st == CONKER_OK; ++k) {
+        const conker_job &j = c->jobs[k];
+        const Key key{j.grid.dims[0], j.grid.dims[1], j.grid.dims[2], (int)j.dtype, (int)j.prec, j.n, j.n_radii,
+                      j.d_maps_N == nullptr};
+        auto it = seen.find(key);
+        if (it != seen.end()) {
+            chosen[k] = it->second;
+            continue;
+        }
+        st = tune_job(c, j, reps, e0, e1, &chosen[k]);
+        if (st == CONKER_OK) seen[key] = chosen[k];
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    c->prof = prof;
+    c->tune = c->user_tune;
+    if (st != CONKER_OK) {
+        c->job_tune.clear();
+        return st;
+    }
+    c->job_tune = chosen;
+    // outputs and workspace as the chosen settings leave them
+    CK_OK(run_all(c));
+    CK_HIP(c, hipStreamSynchronize(c->stream));
+    if (h_chosen) std::memcpy(h_chosen, chosen.data(), chosen.size() * sizeof(conker_tune));
     return CONKER_OK;
 }

@@ -44,6 +44,9 @@ struct conker_ctx {
     bool prof = false;
     bool capturing = false;            // inside conker_batch_capture
     std::vector<conker_job> jobs;      // planned batch
+    conker_tune tune{};                // launch shapes of the calls now enqueued (0 = default)
+    conker_tune user_tune{};           // set by conker_set_tune
+    std::vector<conker_tune> job_tune; // per planned job (conker_batch_autotune), else empty
     hipGraphExec_t graph_exec = nullptr;
     struct Rec {
         int kind;

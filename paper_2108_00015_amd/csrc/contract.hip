@@ -1037,10 +1037,11 @@ extern "C" int conker_contract_npt(conker_ctx *c, const conker_grid *g, conker_d
     // Operand-sharing kernel (k_mm2) for many tiles (pair products, n >= 4, and
     // split-f16); per-wave tiles (k_mm_*) when the tuples fit a few 32 x 32
     // tiles, where k_mm2 would leave most waves of a workgroup idle.
-    static const int mm_kernel = [] {
+    static const int mm_env = [] {
         const char *e = std::getenv("CONKER_MM_KERNEL");
         return e ? std::atoi(e) : 0;   // 0 auto, 1 per-wave tiles, 2 operand sharing
     }();
+    const int mm_kernel = c->tune.mm_kernel ? c->tune.mm_kernel : mm_env;
     const bool use_v2 = prec != CONKER_MM_F64 && (mm_kernel == 2 || (mm_kernel == 0 && pl.n_tiles > 4));
     unsigned *maxabs = nullptr;
     if (prec == CONKER_MM_SPLIT_F16) {   // largest |value| of every map and of F, after the workspace below

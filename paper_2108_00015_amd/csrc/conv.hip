@@ -12,12 +12,14 @@ namespace conker {
 // this many kernel multiplies and inverse x-axis transforms.  Default: every
 // radius, as long as the batch spectra take at most half of the device memory
 // that is free or already held for them (so that the choice is the same from
-// call to call and the buffer is not regrown).
+// call to call and the buffer is not regrown).  A context setting
+// (conker_set_tune, conker_batch_autotune) or CONKER_RADIUS_BATCH replaces it.
 int batch_radii(conker_ctx *c, size_t per_radius_bytes, int n_radii, size_t fixed_bytes) {
     int b = n_radii;
     if (c->capturing) {   // inside a graph capture: use the batch buffer as planned
         const size_t fit = per_radius_bytes ? c->tspec.bytes / per_radius_bytes : (size_t)n_radii;
         b = (int)(fit < 1 ? 1 : (fit < (size_t)n_radii ? fit : (size_t)n_radii));
+        if (c->tune.radius_batch && c->tune.radius_batch < b) b = c->tune.radius_batch;
         return b;
     }
     size_t fr = 0, tot = 0;
@@ -26,7 +28,9 @@ int batch_radii(conker_ctx *c, size_t per_radius_bytes, int n_radii, size_t fixe
         const size_t fit = per_radius_bytes ? budget / per_radius_bytes : (size_t)n_radii;
         if ((size_t)b > fit) b = (int)(fit < 1 ? 1 : fit);
     }
-    if (const char *e = std::getenv("CONKER_RADIUS_BATCH")) {
+    if (c->tune.radius_batch) {
+        b = c->tune.radius_batch;
+    } else if (const char *e = std::getenv("CONKER_RADIUS_BATCH")) {
         int v = std::atoi(e);
         if (v >= 1 && v <= 64) b = v;
     }

@@ -54,8 +54,9 @@ constexpr int stage_ns() {   // product of radices before stage S
 //   TM_J: lanes run along a line; a tile is TC whole contiguous lines (z axis).
 //   TM_C: lanes run across the TC columns of a tile of strided lines (y, x axes);
 //         runs of TC consecutive complex values (128 bytes).
-//   TM_W: as TM_C with twice the columns (256-byte runs), for the x axis whose
-//         line points are a whole y-z plane apart.
+//   TM_W: as TM_C with twice the columns (256-byte runs); the default for the
+//         x axis, whose line points are a whole y-z plane apart, and a launch
+//         setting for the y axis.
 //   TM_R: as TM_C with up to 1024 threads; used by the x pass that keeps its
 //         spectrum tile resident in LDS across a batch of radii.
 enum TileMode { TM_J = 0, TM_C = 1, TM_W = 2, TM_R = 3 };
@@ -707,19 +708,22 @@ int tc_of(int L, int mode) {
     }
 }
 
-// Tile mode of x-axis passes: wide (256-byte runs) unless CONKER_X_WIDE=0.
-int x_mode() {
-    static const int m = [] {
-        const char *e = std::getenv("CONKER_X_WIDE");
-        return (e && e[0] == '0') ? (int)TM_C : (int)TM_W;
-    }();
-    return m;
+int env_flag(const char *name, int dflt) {
+    const char *e = std::getenv(name);
+    return e ? (e[0] == '0' ? 0 : 1) : dflt;
 }
 
+// Column tiles of the x- and y-axis passes: the context's setting (1 narrow,
+// 2 wide), else CONKER_X_WIDE / CONKER_Y_WIDE, else x wide (256-byte runs) and
+// y narrow.  A wide tile needs at least as many z columns as it holds.
 template <typename T>
-int x_mode_for(const Dims &d) {
-    const int m = x_mode();
-    return (m == TM_W && d.nz < tc_of<T>(d.nx, TM_W)) ? (int)TM_C : m;
+int col_mode_for(const conker_ctx *ctx, const Dims &d, int axis) {
+    static const int x_wide = env_flag("CONKER_X_WIDE", 1);
+    static const int y_wide = env_flag("CONKER_Y_WIDE", 0);
+    const int t = axis == AX_X ? ctx->tune.x_tile : ctx->tune.y_tile;
+    const bool wide = t ? t == 2 : (axis == AX_X ? x_wide : y_wide) != 0;
+    const int L = axis == AX_X ? d.nx : d.ny;
+    return (wide && d.nz >= tc_of<T>(L, TM_W)) ? (int)TM_W : (int)TM_C;
 }
 
 template <typename T, int MODE, int DIR, class Op>
@@ -771,9 +775,9 @@ int forward_pair_t(conker_ctx *ctx, const conker_grid *g, const void *a, const v
     OpPack<T> pz{twz, d, (const T *)a, (const T *)b, (C *)spec, {}};
     CK_OK((launch_len<T, -1>(ctx, PK_FFT_FWD_Z, TM_J, d.nz, AX_Z, d, dim3(1, 1), pz)));
     OpInplace<T> py{twy, d, AX_Y, (C *)spec, nc, {}, nullptr};
-    CK_OK((launch_len<T, -1>(ctx, PK_FFT_FWD_Y, TM_C, d.ny, AX_Y, d, dim3(1, 1), py)));
+    CK_OK((launch_len<T, -1>(ctx, PK_FFT_FWD_Y, col_mode_for<T>(ctx, d, AX_Y), d.ny, AX_Y, d, dim3(1, 1), py)));
     OpInplace<T> px{twx, d, AX_X, (C *)spec, nc, {}, nullptr};
-    CK_OK((launch_len<T, -1>(ctx, PK_FFT_FWD_X, x_mode_for<T>(d), d.nx, AX_X, d, dim3(1, 1), px)));
+    CK_OK((launch_len<T, -1>(ctx, PK_FFT_FWD_X, col_mode_for<T>(ctx, d, AX_X), d.nx, AX_X, d, dim3(1, 1), px)));
     return CONKER_OK;
 }
 
@@ -796,17 +800,15 @@ int inverse_batch_t(conker_ctx *ctx, const conker_grid *g, const void *spec, con
         const char *e = std::getenv("CONKER_XMUL_LOOP");
         return (e && e[0] == '1') ? 1 : 0;
     }();
-    const int xm = x_mode_for<T>(d);
+    const int xm = col_mode_for<T>(ctx, d, AX_X);
     static const int staged = [] {
         const char *e = std::getenv("CONKER_XMUL_STAGED");
         return (e && e[0] == '0') ? 0 : 1;
     }();
     const int tiles = (int)((long)d.ny * d.nz / tc_of<T>(d.nx, xm));
     const dim3 gxm(1, 1, loop ? 1u : (unsigned)nb);
-    static const int resident = [] {
-        const char *e = std::getenv("CONKER_XMUL_RESIDENT");
-        return (e && e[0] == '0') ? 0 : 1;
-    }();
+    static const int resident_env = env_flag("CONKER_XMUL_RESIDENT", 1);
+    const int resident = ctx->tune.x_resident ? ctx->tune.x_resident == 2 : resident_env;
     bool done = false;
     if (resident && !pair) {
         auto go = [&](auto Lc) -> int {
@@ -849,7 +851,8 @@ int inverse_batch_t(conker_ctx *ctx, const conker_grid *g, const void *spec, con
         CK_OK((launch_len<T, +1>(ctx, PK_FFT_INV_X_MUL, xm, d.nx, AX_X, d, gxm, px)));
     }
     OpInplace<T> py{twy, d, AX_Y, (C *)tspec, nc, {}, nullptr, mask, xcount};
-    CK_OK((launch_len<T, +1>(ctx, PK_FFT_INV_Y, TM_C, d.ny, AX_Y, d, dim3(1, (unsigned)nb), py)));
+    CK_OK((launch_len<T, +1>(ctx, PK_FFT_INV_Y, col_mode_for<T>(ctx, d, AX_Y), d.ny, AX_Y, d,
+                                 dim3(1, (unsigned)nb), py)));
     if (!maps_a) return CONKER_OK;   // x and y passes only
     OpUnpack<T> pz{twz, d, (const C *)tspec, (T *)maps_a, (T *)maps_b, nc, m0, {}, nullptr, pair, pair_ns};
     CK_OK((launch_len<T, +1>(ctx, PK_FFT_INV_Z, TM_J, d.nz, AX_Z, d, dim3(1, (unsigned)nb), pz)));

@@ -1,0 +1,224 @@
+"""Launch settings (column tiles of the x / y passes, the LDS-resident x pass,
+the summation kernel, the radius batch) and the batch autotuner.  Every setting
+computes the same sums in another order of tiles, so each is held to the same
+bar against the FP64 oracle as the defaults: float64 1e-12, float32 3e-6 per
+map and 1e-5 for the summations (relative to the largest value).
+"""
+import itertools
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import conker as oc  # noqa: E402
+import synth  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+TDT = {"f32": torch.float32, "f64": torch.float64}
+TILES = list(itertools.product((1, 2), (1, 2), (1, 2)))   # x_tile, y_tile, x_resident
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def relerr(got, ref):
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    return float(np.abs(got - ref).max() / max(np.abs(ref).max(), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def ck():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2108_00015_amd as m
+    return m
+
+
+@pytest.fixture()
+def ctx(ck):
+    c = ck.Context(0)
+    yield c
+    c.set_tune()
+    c.close()
+
+
+def _gpu(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV, dtype)
+
+
+@pytest.mark.parametrize("dims", [(64, 96, 128), (96, 64, 32), (32, 1024, 64), (1024, 32, 32), (32, 32, 512)])
+@pytest.mark.parametrize("dt,tol", [("f64", 1e-12), ("f32", 3e-6)])
+def test_convolve_every_tile_setting(ck, ctx, dims, dt, tol):
+    rng = np.random.default_rng(131)
+    A = rng.normal(size=dims)
+    B = rng.poisson(3.0, size=dims).astype(np.float64)
+    radii = [r for r in (1.0, 2.5, 4.0, 7.0) if 2 * oc.shell_reach(r) + 1 <= min(dims)]
+    Af = A.astype(np.float32).astype(np.float64) if dt == "f32" else A
+    ref_a, ref_b = oc.convolve_shells(Af, radii), oc.convolve_shells(B, radii)
+    grid = ck.Grid(dims, (0, 0, 0), 1.0)
+    ks, _ = ctx.make_shell_kernels(grid, radii, TDT[dt])
+    At, Bt = _gpu(A, TDT[dt]), _gpu(B, TDT[dt])
+    for xt, yt, xr in TILES:
+        _say("tiles", dims, dt, dict(x_tile=xt, y_tile=yt, x_resident=xr))
+        ctx.set_tune(x_tile=xt, y_tile=yt, x_resident=xr)
+        ma, mb = ctx.convolve_shells(grid, At, Bt, ks)
+        ma, mb = ma.cpu().numpy(), mb.cpu().numpy()
+        for m in range(len(radii)):
+            ea, eb = relerr(ma[m], ref_a[m]), relerr(mb[m], ref_b[m])
+            assert ea <= tol and eb <= tol, (xt, yt, xr, m, ea, eb)
+        # one field: radius pairing through the same passes
+        mp, _ = ctx.convolve_shells(grid, At, None, ks)
+        assert relerr(mp.cpu().numpy(), ref_a) <= tol
+
+
+@pytest.mark.parametrize("rb", [1, 3])
+def test_radius_batch_setting(ck, ctx, rb):
+    dims = (64, 64, 64)
+    rng = np.random.default_rng(132)
+    A = rng.normal(size=dims)
+    radii = [1.0, 2.0, 3.0, 4.5, 6.0, 8.0, 11.0]
+    ref = oc.convolve_shells(A, radii)
+    grid = ck.Grid(dims, (0, 0, 0), 1.0)
+    ks, _ = ctx.make_shell_kernels(grid, radii, torch.float64)
+    ctx.set_tune(radius_batch=rb)
+    ma, mb = ctx.convolve_shells(grid, _gpu(A, torch.float64), _gpu(-A, torch.float64), ks)
+    assert relerr(ma.cpu().numpy(), ref) <= 1e-12
+    assert relerr(mb.cpu().numpy(), -ref) <= 1e-12
+
+
+@pytest.mark.parametrize("mm", [1, 2])
+@pytest.mark.parametrize("prec,n", [("split_bf16", 3), ("split_bf16", 4), ("f32", 3), ("split_f16", 4),
+                                    ("split_f16", 5), ("f32", 5)])
+def test_summation_kernel_setting(ck, ctx, mm, prec, n):
+    dims = (32, 32, 64)
+    rng = np.random.default_rng(133)
+    F = rng.normal(size=dims).astype(np.float32).astype(np.float64)
+    radii = [1.0, 2.0, 3.0, 4.0, 5.0, 6.0, 7.0][: (7 if n < 5 else 5)]
+    maps = oc.convolve_shells(F, radii).astype(np.float32).astype(np.float64)
+    ref = oc.contract(F, maps, n)
+    grid = ck.Grid(dims, (0, 0, 0), 1.0)
+    ctx.set_tune(mm_kernel=mm)
+    W = ctx.contract_npt(grid, _gpu(F, torch.float32), _gpu(maps, torch.float32), n, prec)
+    e = relerr(W.cpu().numpy(), ref)
+    _say("summation kernel", mm, prec, n, "%.3e" % e)
+    assert e <= 1e-5
+
+
+@pytest.mark.parametrize("yt", [1, 2])
+def test_fused_and_diag_with_line_masks(ck, ctx, yt):
+    """Survey-shaped support (the y pass skips empty slabs, writes carrying lines)."""
+    dims = (64, 64, 512)
+    rng = np.random.default_rng(134)
+    A = rng.normal(size=dims)
+    B = rng.poisson(2.0, size=dims).astype(np.float64)
+    x = np.arange(64)[:, None]
+    y = np.arange(64)[None, :]
+    keep = ((x - 32) / 32.0) ** 2 + ((y - 32) / 32.0) ** 2 <= 0.6
+    keep[:10] = False
+    A = (A * keep[:, :, None]).astype(np.float32).astype(np.float64)
+    B = B * keep[:, :, None]
+    radii = [1.0, 2.0, 3.5, 5.0, 8.0]
+    ma, mb = oc.convolve_shells(A, radii), oc.convolve_shells(B, radii)
+    grid = ck.Grid(dims, (0, 0, 0), 1.0)
+    ks, _ = ctx.make_shell_kernels(grid, radii, torch.float32)
+    ctx.set_tune(y_tile=yt)
+    At, Bt = _gpu(A, torch.float32), _gpu(B, torch.float32)
+    Wa, Wb = ctx.convolve_contract(grid, At, Bt, ks, 3, "split_bf16")
+    assert relerr(Wa.cpu().numpy(), oc.contract(A, ma, 3)) <= 1e-5
+    assert relerr(Wb.cpu().numpy(), oc.contract(B, mb, 3)) <= 1e-5
+    Da, Db = ctx.convolve_diag(grid, At, Bt, ks, 4)
+    for p in range(2, 5):
+        ra = np.array([np.sum(A * ma[m] ** (p - 1)) for m in range(len(radii))])
+        rb = np.array([np.sum(B * mb[m] ** (p - 1)) for m in range(len(radii))])
+        assert relerr(Da.cpu().numpy()[p - 2], ra) <= 1e-5
+        assert relerr(Db.cpu().numpy()[p - 2], rb) <= 1e-5
+
+
+def test_set_tune_rejects_out_of_range(ck, ctx):
+    for bad in (dict(x_tile=3), dict(y_tile=-1), dict(x_resident=5), dict(mm_kernel=3), dict(radius_batch=65)):
+        with pytest.raises(ck.ConkerError):
+            ctx.set_tune(**bad)
+    with pytest.raises(ValueError):
+        ctx.set_tune(z_tile=1)
+    ctx.set_tune(x_tile=1, radius_batch=4)
+    t = ctx.get_tune()
+    assert (t["x_tile"], t["y_tile"], t["radius_batch"]) == (1, 0, 4)
+    ctx.set_tune()
+    assert all(v == 0 for k, v in ctx.get_tune().items() if k != "ms")
+    with pytest.raises(ck.ConkerError):     # nothing planned
+        ctx.batch_autotune()
+
+
+def _outs(jobs):
+    return [np.concatenate([j.W_delta.cpu().numpy(), j.W_rand.cpu().numpy(), j.xi.cpu().numpy()]) for j in jobs]
+
+
+def test_batch_autotune_then_graph(ck, ctx):
+    """Mocks of three shapes (separate maps) and two fused survey-line jobs:
+    autotuning keeps the results, jobs of one shape share a setting, and the
+    graph recorded afterwards replays to the same values."""
+    s = torch.cuda.Stream()
+    ctx.set_stream(s)
+    sizes = ((96, 15_000), (128, 20_000), (96, 12_000), (192, 30_000))
+    cats = [synth.mock_catalog(50 + j, g, n, cell=5.0) for j, (g, n) in enumerate(sizes)]
+    radii = synth.MOCK_RADII
+    gmax = max(g for g, _ in sizes) ** 3
+    N = torch.empty(gmax, device=DEV)
+    R = torch.empty(gmax, device=DEV)
+    mN = torch.empty(len(radii) * gmax, device=DEV)
+    mR = torch.empty(len(radii) * gmax, device=DEV)
+    kspecs, jobs = {}, []
+    for (g, _), (d, r) in zip(sizes, cats):
+        grid = ck.Grid((g, g, g), (0.0, 0.0, 0.0), 5.0)
+        if g not in kspecs:
+            kspecs[g] = ctx.make_shell_kernels(grid, radii, torch.float32)[0]
+        jobs.append(ck.make_job(grid, kspecs[g], 3, "split_bf16", torch.from_numpy(d.pos).to(DEV),
+                                torch.from_numpy(r.pos).to(DEV), N=N, R=R, maps_N=mN, maps_R=mR, fused=False))
+    lg = ck.Grid((32, 64, 512), (0, 0, 0), 1.0)
+    lks, _ = ctx.make_shell_kernels(lg, [1.0, 2.0, 3.5, 5.0, 8.0, 12.0], torch.float32)
+    for j in range(2):
+        rng = np.random.default_rng(600 + j)
+        d = rng.uniform(0, 30, size=(5000, 3)).astype(np.float32)
+        r = rng.uniform(0, 30, size=(50000, 3)).astype(np.float32)
+        jobs.append(ck.make_job(lg, lks, 3, "split_bf16", torch.from_numpy(d).to(DEV), torch.from_numpy(r).to(DEV)))
+    assert jobs[-1].maps_N is None
+    torch.cuda.synchronize()
+    ctx.batch_plan(jobs)
+    before = _outs(jobs)
+    chosen = ctx.batch_autotune(reps=2)
+    _say("autotune", chosen)
+    assert len(chosen) == len(jobs)
+    for t in chosen:
+        assert t["x_tile"] in (0, 1, 2) and t["y_tile"] in (0, 1, 2) and t["x_resident"] in (0, 1, 2)
+        assert t["mm_kernel"] in (0, 1, 2) and 0 <= t["radius_batch"] <= 16
+        assert 0.0 < t["ms"] < 1e4
+    strip = [{k: v for k, v in t.items() if k != "ms"} for t in chosen]
+    assert strip[0] == strip[2] and chosen[0]["ms"] == chosen[2]["ms"]     # same shape, one tuning
+    assert strip[4] == strip[5]
+    assert chosen[4]["mm_kernel"] == 0 and chosen[4]["radius_batch"] == 0  # fused: not tuned
+    after = _outs(jobs)
+    for k in range(len(jobs)):
+        assert relerr(after[k], before[k]) <= 1e-5, k
+    ctx.batch_capture()
+    for rep in range(3):
+        for j in jobs:
+            j.W_delta.fill_(9.0)
+            j.xi.fill_(0.0)
+        torch.cuda.synchronize()
+        ctx.batch_launch()
+        ctx.synchronize()
+        for k, o in enumerate(_outs(jobs)):
+            assert relerr(o, after[k]) <= 1e-5, (rep, k)
+    # the oracle on the first fused job
+    d0 = jobs[4]
+    ref = oc.npcf(d0.data_pos.cpu().numpy(), d0.rand_pos.cpu().numpy(), (32, 64, 512), (0, 0, 0), 1.0,
+                  [1.0, 2.0, 3.5, 5.0, 8.0, 12.0], 3)
+    assert relerr(d0.W_delta.cpu().numpy(), ref["W_delta"]) <= 1e-5
+    assert relerr(d0.W_rand.cpu().numpy(), ref["W_rand_raw"]) <= 1e-5

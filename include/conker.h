@@ -396,7 +396,7 @@ int conker_batch_launch(conker_ctx *ctx);
  *   x_tile, y_tile  columns per tile of the x- and y-axis inverse passes and
  *                   of the forward passes of those axes:
  *                   1 narrow (16 float32 / 8 float64 columns), 2 wide (twice
- *                   that: 256-byte runs).  Default: x wide, y narrow.
+ *                   that: 256-byte runs).  Default: wide.
  *   x_resident      x-axis inverse pass: 1 streamed, 2 kernel-multiply tile
  *                   kept resident in LDS across the batch's radii.  Default 2.
  *   mm_kernel       matrix-core summation: 1 one output tile per wave,

@@ -26,6 +26,18 @@ class ConkerError(RuntimeError):
         self.status = status
 
 
+def _check_outside(nout: torch.Tensor, allow_outside: bool):
+    """Tracers outside the grid (or with a non-finite coordinate or weight) are
+    dropped by the mapping and counted on the device; unless allowed, any such
+    tracer is an error (this waits for the stream)."""
+    if allow_outside:
+        return
+    cnt = [int(v) for v in nout.cpu().tolist()]
+    if any(cnt):
+        raise ConkerError(_lib.ERANGE, "tracers outside the grid or non-finite, per catalog: %s "
+                          "(pass allow_outside=True to drop them)" % cnt)
+
+
 TUNE_FIELDS = ("x_tile", "y_tile", "x_resident", "mm_kernel", "radius_batch")
 
 
@@ -504,7 +516,7 @@ def fused_supported(grid: Grid, n_radii: int, n: int, precision: str, dtype) -> 
 
 def npcf_diag(ctx: Context, grid: Grid, data_pos: torch.Tensor, rand_pos: torch.Tensor, kspec: torch.Tensor,
               n_max: int, data_w: Optional[torch.Tensor] = None, rand_w: Optional[torch.Tensor] = None,
-              dtype=torch.float64) -> dict:
+              dtype=torch.float64, allow_outside: bool = False) -> dict:
     """Equidistant n-point functions (Eq. ksinDiag) for n = 2 .. n_max without storing maps.
 
     Returns xi, W_delta and W_rand_raw as [n_max - 1, n_radii] float64 (row n - 2 is order n),
@@ -523,12 +535,13 @@ def npcf_diag(ctx: Context, grid: Grid, data_pos: torch.Tensor, rand_pos: torch.
     xi = torch.empty_like(Wd)
     for k in range(n_max - 1):
         ctx.ratio(Wd[k], Wr[k], alpha, k + 2, out=xi[k])
+    _check_outside(nout, allow_outside)
     return dict(xi=xi, W_delta=Wd, W_rand_raw=Wr, alpha=alpha, n_outside=nout)
 
 
 def npcf_pair2(ctx: Context, grid: Grid, data_pos: torch.Tensor, rand_pos: torch.Tensor, kspec: torch.Tensor,
                data_w: Optional[torch.Tensor] = None, rand_w: Optional[torch.Tensor] = None,
-               dtype=torch.float64) -> dict:
+               dtype=torch.float64, allow_outside: bool = False) -> dict:
     """The 2pcf (Eq. ksi2_delta) with both sums taken in Fourier space (conker_pair_spectral):
     no inverse transform and no map.  Returns xi, W_delta, W_rand_raw ([n_radii] float64), alpha."""
     dev = data_pos.device
@@ -543,6 +556,7 @@ def npcf_pair2(ctx: Context, grid: Grid, data_pos: torch.Tensor, rand_pos: torch
     ctx.form_delta(grid, N, R, wsum[0:1], wsum[1:2], alpha)
     Wd, Wr, _ = ctx.pair_spectral(grid, N, R, kspec, cross=False)
     xi = ctx.ratio(Wd, Wr, alpha, 2)
+    _check_outside(nout, allow_outside)
     return dict(xi=xi, W_delta=Wd, W_rand_raw=Wr, alpha=alpha, n_outside=nout)
 
 
@@ -565,7 +579,8 @@ def npcf_continuous(ctx: Context, grid: Grid, D: torch.Tensor, R: torch.Tensor, 
 def npcf_cross(ctx: Context, grid: Grid, data0_pos: torch.Tensor, data1_pos: torch.Tensor, rand_pos: torch.Tensor,
                kspec: torch.Tensor, n: int, data0_w: Optional[torch.Tensor] = None,
                data1_w: Optional[torch.Tensor] = None, rand_w: Optional[torch.Tensor] = None,
-               precision: str = "f64", dtype=torch.float64, fused: Optional[bool] = None) -> dict:
+               precision: str = "f64", dtype=torch.float64, fused: Optional[bool] = None,
+               allow_outside: bool = False) -> dict:
     """Cross-correlation of tracer 0 (vertex 0) with tracer 1 (the shells), both background-subtracted
     against one random catalog (Sec. 2.7): xi = W_cross / (alpha0 alpha1^(n-1) W_rand_raw)."""
     dev = data0_pos.device
@@ -592,13 +607,14 @@ def npcf_cross(ctx: Context, grid: Grid, data0_pos: torch.Tensor, data1_pos: tor
         Wc = ctx.contract_npt(grid, N0, maps1, n, precision)
         Wr = ctx.contract_npt(grid, R, mapsR, n, precision)
     xi = ctx.ratio_cross(Wc, Wr, alpha[0:1], alpha[1:2], n)
+    _check_outside(nout, allow_outside)
     return dict(xi=xi, W_cross=Wc, W_rand_raw=Wr, alpha=alpha, n_outside=nout)
 
 
 def npcf(ctx: Context, grid: Grid, data_pos: torch.Tensor, rand_pos: torch.Tensor, kspec: torch.Tensor,
          n: int, data_w: Optional[torch.Tensor] = None, rand_w: Optional[torch.Tensor] = None,
          precision: str = "f64", dtype=torch.float64, bufs: Optional[dict] = None,
-         fused: Optional[bool] = None, field_at_a_time: bool = False) -> dict:
+         fused: Optional[bool] = None, field_at_a_time: bool = False, allow_outside: bool = False) -> dict:
     """Mapping -> convolution -> summation -> estimator, chaining the C ABI calls.
 
     `bufs` may hold preallocated tensors (keys: N, R, maps_N, maps_R, wsum, nout, alpha) that are
@@ -606,7 +622,8 @@ def npcf(ctx: Context, grid: Grid, data_pos: torch.Tensor, rand_pos: torch.Tenso
     run as one call that never stores the maps.  With `field_at_a_time` (separate path) the maps of
     N and R are made and summed one field after the other in a single maps buffer (half the memory;
     each field's radii are paired in the transforms).  Returns xi, W_delta, W_rand_raw, alpha and
-    the buffers (all on the GPU).
+    the buffers (all on the GPU).  Tracers outside the grid raise ConkerError unless
+    `allow_outside` (checking them waits for the stream).
     """
     nr_ = int(kspec.shape[0])
     if fused is None:
@@ -645,4 +662,5 @@ def npcf(ctx: Context, grid: Grid, data_pos: torch.Tensor, rand_pos: torch.Tenso
         Wd = ctx.contract_npt(grid, b["N"], b["maps_N"], n, precision)
         Wr = ctx.contract_npt(grid, b["R"], b["maps_R"], n, precision)
     xi = ctx.ratio(Wd, Wr, b["alpha"], n)
-    return dict(xi=xi, W_delta=Wd, W_rand_raw=Wr, alpha=b["alpha"], bufs=b)
+    _check_outside(b["nout"], allow_outside)
+    return dict(xi=xi, W_delta=Wd, W_rand_raw=Wr, alpha=b["alpha"], n_outside=b["nout"], bufs=b)

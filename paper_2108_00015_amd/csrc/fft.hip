@@ -55,8 +55,7 @@ constexpr int stage_ns() {   // product of radices before stage S
 //   TM_C: lanes run across the TC columns of a tile of strided lines (y, x axes);
 //         runs of TC consecutive complex values (128 bytes).
 //   TM_W: as TM_C with twice the columns (256-byte runs); the default for the
-//         x axis, whose line points are a whole y-z plane apart, and a launch
-//         setting for the y axis.
+//         x and y axes (a launch setting selects TM_C instead).
 //   TM_R: as TM_C with up to 1024 threads; used by the x pass that keeps its
 //         spectrum tile resident in LDS across a batch of radii.
 enum TileMode { TM_J = 0, TM_C = 1, TM_W = 2, TM_R = 3 };
@@ -714,12 +713,12 @@ int env_flag(const char *name, int dflt) {
 }
 
 // Column tiles of the x- and y-axis passes: the context's setting (1 narrow,
-// 2 wide), else CONKER_X_WIDE / CONKER_Y_WIDE, else x wide (256-byte runs) and
-// y narrow.  A wide tile needs at least as many z columns as it holds.
+// 2 wide), else CONKER_X_WIDE / CONKER_Y_WIDE, else wide (256-byte runs).  A
+// wide tile needs at least as many z columns as it holds.
 template <typename T>
 int col_mode_for(const conker_ctx *ctx, const Dims &d, int axis) {
     static const int x_wide = env_flag("CONKER_X_WIDE", 1);
-    static const int y_wide = env_flag("CONKER_Y_WIDE", 0);
+    static const int y_wide = env_flag("CONKER_Y_WIDE", 1);
     const int t = axis == AX_X ? ctx->tune.x_tile : ctx->tune.y_tile;
     const bool wide = t ? t == 2 : (axis == AX_X ? x_wide : y_wide) != 0;
     const int L = axis == AX_X ? d.nx : d.ny;

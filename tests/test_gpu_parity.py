@@ -506,3 +506,31 @@ def test_fused_zero_fields_give_zero(ck, ctx, sparse512_fields):
     Wa, Wb = ctx.convolve_contract(grid, _gpu(A, torch.float32), z, ks, 3, "split_bf16")
     assert np.all(Wb.cpu().numpy() == 0.0)
     assert relerr(Wa.cpu().numpy(), oc.contract(A, maps_a[:6], 3)) <= 1e-5
+
+
+@pytest.mark.parametrize("fn", ["npcf", "npcf_diag", "npcf_pair2"])
+def test_outside_tracers_raise_unless_allowed(ck, ctx, fn):
+    """Out-of-grid and non-finite tracers are counted by the mapping; the
+    Python entry points raise unless they are explicitly allowed, and then the
+    result equals that of the catalog without them."""
+    dims = (32, 32, 32)
+    rng = np.random.default_rng(140)
+    d = rng.uniform(0, 32, size=(500, 3)).astype(np.float32)
+    r = rng.uniform(0, 32, size=(5000, 3)).astype(np.float32)
+    bad = np.array([[40.0, 1.0, 1.0], [np.nan, 2.0, 2.0], [3.0, -0.5, 3.0]], dtype=np.float32)
+    d2 = np.concatenate([d, bad[:2]])
+    r2 = np.concatenate([r, bad[2:]])
+    grid = ck.Grid(dims, (0, 0, 0), 1.0)
+    ks, _ = ctx.make_shell_kernels(grid, [2.0, 3.0, 5.0], torch.float64)
+    call = {"npcf": lambda a, b, **kw: ck.npcf(ctx, grid, a, b, ks, 3, **kw),
+            "npcf_diag": lambda a, b, **kw: ck.npcf_diag(ctx, grid, a, b, ks, 3, **kw),
+            "npcf_pair2": lambda a, b, **kw: ck.npcf_pair2(ctx, grid, a, b, ks, **kw)}[fn]
+    base = call(_gpu(d), _gpu(r))
+    assert base["n_outside"].cpu().tolist() == [0, 0]
+    with pytest.raises(ck.ConkerError) as e:
+        call(_gpu(d2), _gpu(r2))
+    assert "allow_outside" in str(e.value)
+    out = call(_gpu(d2), _gpu(r2), allow_outside=True)
+    assert out["n_outside"].cpu().tolist() == [2, 1]
+    for k in ("W_delta", "W_rand_raw", "xi"):
+        assert relerr(out[k].cpu().numpy(), base[k].cpu().numpy()) <= 1e-15, k

@@ -184,9 +184,8 @@ def test_batch_autotune_then_graph(ck, ctx):
     lg = ck.Grid((32, 64, 512), (0, 0, 0), 1.0)
     lks, _ = ctx.make_shell_kernels(lg, [1.0, 2.0, 3.5, 5.0, 8.0, 12.0], torch.float32)
     for j in range(2):
-        rng = np.random.default_rng(600 + j)
-        d = rng.uniform(0, 30, size=(5000, 3)).astype(np.float32)
-        r = rng.uniform(0, 30, size=(50000, 3)).astype(np.float32)
+        d = synth.neyman_scott_box(5000, 40, 1.5, 0.0, 30.0, seed=600 + j)
+        r = synth.uniform_box(50000, 0.0, 30.0, seed=610 + j)
         jobs.append(ck.make_job(lg, lks, 3, "split_bf16", torch.from_numpy(d).to(DEV), torch.from_numpy(r).to(DEV)))
     assert jobs[-1].maps_N is None
     torch.cuda.synchronize()

@@ -100,6 +100,17 @@ __device__ __forceinline__ void split_q(int q, int &j, int &c) {
     }
 }
 
+// Ops whose stores are conditional expose keeps() (uniform: whether any row is
+// skipped) and flag(i) (row i of the tile is written iff flag(i) != 0).  The
+// last stage issues every flag load it needs together, before its
+// butterflies, so that no store waits behind a flag load (a wait for
+// outstanding vector memory operations would also wait for the stores already
+// issued) and the loads overlap each other.
+template <class Op, class = void>
+struct has_keep : std::false_type {};
+template <class Op>
+struct has_keep<Op, std::void_t<decltype(std::declval<const Op &>().flag(0))>> : std::true_type {};
+
 template <typename T, int L, int MODE, int DIR, int S, bool STAGED, class Op>
 __device__ __forceinline__ void fft_stage(cplx<T> *lds, const cplx<T> *tw, Op &op) {
     using C = cplx<T>;
@@ -114,6 +125,33 @@ __device__ __forceinline__ void fft_stage(cplx<T> *lds, const cplx<T> *tw, Op &o
     constexpr int PER = (NB + NT - 1) / NT;
     constexpr int TWS = L / (NSV * R);
     static_assert((NSV & (NSV - 1)) == 0, "stages before the last have power-of-two spans");
+    constexpr bool KEEP = LAST && has_keep<Op>::value;
+    static_assert(!KEEP || R <= 8, "keep flags are packed 8 per butterfly");
+    unsigned kbits[PER];
+    if constexpr (KEEP) {
+        if (op.keeps()) {
+            int fl[PER][R];
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
+                const int b = threadIdx.x + q * NT;
+                int j, c;
+                split_q<NT, MODE, LR, TC>(q, j, c);
+                const int k = j & (NSV - 1);
+                const int base = (NB % NT == 0 || b < NB) ? (j - k) * R + k : 0;
+#pragma unroll
+                for (int r = 0; r < R; ++r) fl[q][r] = op.flag(base + r * NSV);   // base + r NSV < L
+            }
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
+                kbits[q] = 0;
+#pragma unroll
+                for (int r = 0; r < R; ++r) kbits[q] |= fl[q][r] != 0 ? (1u << r) : 0u;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < PER; ++q) kbits[q] = 0xffu;
+        }
+    }
     C v[PER][R];
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
@@ -151,8 +189,13 @@ __device__ __forceinline__ void fft_stage(cplx<T> *lds, const cplx<T> *tw, Op &o
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int o = base + r * NSV;
-                if constexpr (LAST) op.store(o, c, v[q][r]);
-                else lds[lds_addr<MODE, L, TC, PAD>(o, c)] = v[q][r];
+                if constexpr (KEEP) {
+                    if (kbits[q] & (1u << r)) op.store(o, c, v[q][r]);
+                } else if constexpr (LAST) {
+                    op.store(o, c, v[q][r]);
+                } else {
+                    lds[lds_addr<MODE, L, TC, PAD>(o, c)] = v[q][r];
+                }
             }
         }
     }
@@ -304,9 +347,9 @@ struct OpInplace {
     __device__ int iters() const { return 1; }
     __device__ void set_iter(int) {}
     __device__ C load(int i, int c) const { return p[off(g, i, c)]; }
-    __device__ void store(int i, int c, C v) const {
-        if (!mask || mask[(size_t)g.p0 * d.ny + i]) p[off(g, i, c)] = v;
-    }
+    __device__ bool keeps() const { return mask != nullptr; }
+    __device__ int flag(int i) const { return mask[(size_t)g.p0 * d.ny + i]; }
+    __device__ void store(int i, int c, C v) const { p[off(g, i, c)] = v; }   // rows with a flag
 };
 
 
@@ -499,22 +542,22 @@ struct OpResident {
     const T *kt;    // LDS: kernel values [TC][L/2 + 1]
     C *out;         // global: output tile base
     unsigned si;
-    const int *xcount;   // NULL, or carrying lines per x-slab: slabs without any are not written
+    const unsigned char *xf;   // LDS: x-slab carries field (row written), or NULL: every row
     __device__ C load(int i, int c) const {
         const C s = st[i * TC + c];
         const T k = kt[c * (L / 2 + 1) + (i <= L - i ? i : L - i)];
         return C{s.x * k, s.y * k};
     }
-    __device__ void store(int i, int c, C v) const {
-        if (!xcount || xcount[i] > 0) out[(unsigned)i * si + (unsigned)c] = v;
-    }
+    __device__ bool keeps() const { return xf != nullptr; }
+    __device__ int flag(int i) const { return xf[i]; }
+    __device__ void store(int i, int c, C v) const { out[(unsigned)i * si + (unsigned)c] = v; }   // rows with a flag
 };
 
 template <typename T, int L>
 constexpr bool resident_fits() {
     using SH = Shape<T, L, TM_R>;
     return (size_t)SH::LDS * sizeof(cplx<T>) + (size_t)L * sizeof(cplx<T>) +
-               (size_t)L * SH::TC * sizeof(cplx<T>) + (size_t)SH::TC * (L / 2 + 1) * sizeof(T) <=
+               (size_t)L * SH::TC * sizeof(cplx<T>) + (size_t)SH::TC * (L / 2 + 1) * sizeof(T) + (size_t)L <=
            160 * 1024;
 }
 
@@ -530,6 +573,7 @@ __global__ __launch_bounds__((Shape<T, L, TM_R>::NT), (Shape<T, L, TM_R>::MINW))
     __shared__ C tw[L];
     __shared__ C st[L * TC];
     __shared__ T kt[TC * NXH];
+    __shared__ unsigned char xf[L];   // x-slabs carrying field (when xcount is given)
     // Tiles (ky, kz-block) and (ny - ky, kz-block) read the same kernel values.
     // Workgroups are dispatched round-robin over the 8 XCDs; ids w and w + 8
     // (same XCD, consecutive) take the two tiles of one mirror pair, so the
@@ -545,7 +589,10 @@ __global__ __launch_bounds__((Shape<T, L, TM_R>::NT), (Shape<T, L, TM_R>::MINW))
         tile = ky * nzb + zb;
     }
     const Tile g = make_tile(AX_X, d, tile, TC);
-    for (int t = threadIdx.x; t < L; t += NT) tw[t] = twg[t];
+    for (int t = threadIdx.x; t < L; t += NT) {
+        tw[t] = twg[t];
+        if (xcount) xf[t] = xcount[t] > 0 ? 1 : 0;
+    }
     for (int e = threadIdx.x; e < L * TC; e += NT) {
         const int i = e / TC, c = e - (e / TC) * TC;
         st[e] = spec[g.base + (size_t)(unsigned)i * (unsigned)g.si + c];
@@ -573,7 +620,7 @@ __global__ __launch_bounds__((Shape<T, L, TM_R>::NT), (Shape<T, L, TM_R>::MINW))
         }
         __syncthreads();
         if (m + 1 < nb) kload(m + 1, kv);
-        OpResident<T, L, TC> op{st, kt, tspec + (size_t)m * nc + g.base, (unsigned)g.si, xcount};
+        OpResident<T, L, TC> op{st, kt, tspec + (size_t)m * nc + g.base, (unsigned)g.si, xcount ? xf : nullptr};
         fft_line_tile<T, L, TM_R, +1, false>(lds, tw, op);
         __syncthreads();
     }

@@ -43,7 +43,9 @@ def kernel_bytes(kind, n_launch_units, nc, ns, kel, n_data, n_rand, weighted, es
     are only summed, the inverse passes produce their outputs on the z-lines that
     carry field (fraction fl of all lines, in a fraction fx of the x-slabs):
     the x pass writes fx of its output, the y pass reads fx and writes fl, the
-    z pass reads fl.
+    z pass reads fl.  With the axes permuted (axis_order), x, y and z are the
+    axes of the permuted grid: fx is the fraction of its first-axis slabs and fl
+    that of lines along its last axis.
     """
     c = 2 * esize
     if kind == "fft_fwd_z":       # two real fields in, one complex field out
@@ -57,6 +59,8 @@ def kernel_bytes(kind, n_launch_units, nc, ns, kel, n_data, n_rand, weighted, es
         return ns * (fx + fl) * nc * c
     if kind == "support":         # both fields read once
         return 2 * nc * esize
+    if kind == "axis_order":      # both fields read for the projections, then read and written permuted
+        return 6 * nc * esize
     if kind == "diag_zinv":
         return ns * fl * nc * c + 2 * fl * nc * esize
     if kind == "fft_inv_z":       # complex in, two real maps out
@@ -138,19 +142,27 @@ def stages_use_fused(prof):
     return "fused_zinv_contract" in prof
 
 
-def support_fractions(w, data, rand):
-    """Fractions of z-lines (x, y) and of x-slabs holding at least one catalog
-    point (the lines on which N or R_raw can be non-zero)."""
-    nx, ny = int(w.dims[0]), int(w.dims[1])
-    hit = np.zeros(nx * ny, dtype=bool)
+AXIS_ORDERS = {1: (0, 1, 2), 2: (0, 2, 1), 3: (1, 0, 2), 4: (1, 2, 0), 5: (2, 0, 1), 6: (2, 1, 0)}
+
+
+def support_fractions(w, data, rand, order=1):
+    """For the axes transformed in `order` (1..6, new axis k = old axis
+    AXIS_ORDERS[order][k]): the fraction of first-axis slabs and of lines along
+    the last axis holding at least one catalog point (where N or R_raw can be
+    non-zero)."""
+    dims = np.asarray(w.dims)
+    occ = np.zeros(tuple(int(d) for d in dims), dtype=bool)
     o = np.asarray(w.origin, dtype=np.float64)
     for cat in (data, rand):
         for s in range(0, len(cat), 1 << 24):
             c = np.floor((cat.pos[s:s + (1 << 24)].astype(np.float64) - o) / w.cell).astype(np.int64)
-            ok = np.all((c >= 0) & (c < np.asarray(w.dims)), axis=1)
-            hit[c[ok, 0] * ny + c[ok, 1]] = True
-    hit = hit.reshape(nx, ny)
-    return float(hit.any(axis=1).mean()), float(hit.mean())
+            ok = np.all((c >= 0) & (c < dims), axis=1)
+            occ[c[ok, 0], c[ok, 1], c[ok, 2]] = True
+    first, last = AXIS_ORDERS[order][0], AXIS_ORDERS[order][2]
+    others = tuple(a for a in range(3) if a != first)
+    fx = float(occ.any(axis=others).mean())
+    fl = float(occ.any(axis=last).mean())
+    return fx, fl
 
 
 def cpu_baseline(w, data, rand, n, sample_radii=1):
@@ -222,7 +234,7 @@ def run_path(ck, torch, ctx, grid, w, dpos, dw, rpos, rw, n, dtype, prec, steps,
         ctx.profile(False)
     res = dict(ms=ms, xi=out["xi"].cpu().numpy(), Wd=out["W_delta"].cpu().numpy(),
                Wr=out["W_rand_raw"].cpu().numpy(), alpha=float(out["alpha"].item()), prof=prof,
-               workspace=ctx.workspace_bytes())
+               workspace=ctx.workspace_bytes(), axis_order=ctx.axis_order_used() or 1)
     del bufs, ks, out
     torch.cuda.empty_cache()
     return res
@@ -368,7 +380,8 @@ def main():
         log("  %.2f ms/step" % fp64["ms"])
 
     batch = min(int(os.environ.get("CONKER_RADIUS_BATCH", str(ns))), ns)
-    fx, fl = support_fractions(w, data, rand)
+    order = mixed["axis_order"]
+    fx, fl = support_fractions(w, data, rand, order)
     stages = {}
     for kind, (launches, tot) in mixed["prof"].items():
         per_step = tot / args.steps
@@ -429,7 +442,8 @@ def main():
                    "summation": args.prec, "fft": "f32", "mode": args.mode,
                    "maps": ("never stored" if (args.mode != "npcf" or stages_use_fused(mixed["prof"]))
                             else ("one field at a time" if args.field_at_a_time else "both fields")),
-                   "carrying_lines": round(fl, 4), "carrying_x_slabs": round(fx, 4)},
+                   "axis_order": "".join("xyz"[a] for a in AXIS_ORDERS[order]),
+                   "carrying_lines": round(fl, 4), "first_axis_slabs": round(fx, 4)},
         "s_to_W3_mixed": round(s_mixed, 5),
         "s_to_W3_fp64": round(fp64["ms"] / 1e3, 5) if fp64 else None,
         "fp64_over_mixed": round(fp64["ms"] / mixed["ms"], 3) if fp64 else None,

@@ -404,6 +404,17 @@ int conker_batch_launch(conker_ctx *ctx);
  *                   four 32 x 32 output tiles, else 1.
  *   radius_batch    radii (or radius pairs) per inverse batch, 1..64.
  *                   Default: as many as half of the free device memory holds.
+ *   axis_order      map-free summations (conker_convolve_contract*,
+ *                   conker_convolve_diag*) on grids with equal axis lengths:
+ *                   the order of the axes the transforms run in, which sets
+ *                   how much of the work outside the field's support is
+ *                   skipped: 1 the given order (x,y,z), 2 (x,z,y),
+ *                   3 (y,x,z), 4 (y,z,x), 5 (z,x,y), 6 (z,y,x) (the first
+ *                   axis listed is transformed first after the kernel
+ *                   multiply, the last one is the contiguous axis of the
+ *                   summation); 0 (default) chosen on the device from the
+ *                   support.  Other than 1, the fields are copied into the
+ *                   permuted layout in workspace.
  *   ms              conker_batch_autotune only: the measured time of one run
  *                   of the job with this setting (milliseconds).
  * conker_set_tune: the setting used by every later call on the context
@@ -415,11 +426,17 @@ typedef struct {
     int32_t x_resident;
     int32_t mm_kernel;
     int32_t radius_batch;
+    int32_t axis_order;
     float ms;
 } conker_tune;
 
 int conker_set_tune(conker_ctx *ctx, const conker_tune *h_tune);
 int conker_get_tune(const conker_ctx *ctx, conker_tune *h_tune);
+
+/* conker_axis_order_used: the axis order (1..6, numbered as axis_order above)
+ * that the last map-free summation on this context ran in, 0 if none has run.
+ * Waits for the context's stream when the order was chosen on the device. */
+int conker_axis_order_used(conker_ctx *ctx, int *h_order);
 
 /* conker_batch_autotune: after conker_batch_plan, picks a setting per job
  * shape (grid dimensions, dtype, order, number of radii, summation arithmetic,

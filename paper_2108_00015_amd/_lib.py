@@ -78,6 +78,7 @@ SIGNATURES = {
     "conker_set_tune": (ct.c_int, [ct.c_void_p, ct.c_void_p]),
     "conker_get_tune": (ct.c_int, [ct.c_void_p, ct.c_void_p]),
     "conker_batch_autotune": (ct.c_int, [ct.c_void_p, ct.c_int, ct.c_void_p]),
+    "conker_axis_order_used": (ct.c_int, [ct.c_void_p, ct.POINTER(ct.c_int)]),
     "conker_profile_enable": (ct.c_int, [ct.c_void_p, ct.c_int]),
     "conker_profile_read": (ct.c_int, [ct.c_void_p, ct.c_int, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_double)]),
     "conker_profile_kind_name": (ct.c_char_p, [ct.c_int]),
@@ -95,7 +96,8 @@ class ConkerCosmology(ct.Structure):
 
 class ConkerTune(ct.Structure):
     _fields_ = [("x_tile", ct.c_int32), ("y_tile", ct.c_int32), ("x_resident", ct.c_int32),
-                ("mm_kernel", ct.c_int32), ("radius_batch", ct.c_int32), ("ms", ct.c_float)]
+                ("mm_kernel", ct.c_int32), ("radius_batch", ct.c_int32), ("axis_order", ct.c_int32),
+                ("ms", ct.c_float)]
 
 
 class ConkerJob(ct.Structure):

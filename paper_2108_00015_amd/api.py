@@ -38,7 +38,7 @@ def _check_outside(nout: torch.Tensor, allow_outside: bool):
                           "(pass allow_outside=True to drop them)" % cnt)
 
 
-TUNE_FIELDS = ("x_tile", "y_tile", "x_resident", "mm_kernel", "radius_batch")
+TUNE_FIELDS = ("x_tile", "y_tile", "x_resident", "mm_kernel", "radius_batch", "axis_order")
 
 
 def _tune_dict(t) -> dict:
@@ -400,12 +400,21 @@ class Context:
     def set_tune(self, **fields):
         """Launch setting for later calls: x_tile, y_tile (1 narrow, 2 wide),
         x_resident (1 streamed, 2 resident), mm_kernel (1 per-wave tiles,
-        2 operand sharing), radius_batch; 0 or omitted = default."""
+        2 operand sharing), radius_batch, axis_order (1 as given, 2..6 the
+        other permutations of a cubic grid, see conker.h); 0 or omitted = default."""
         bad = set(fields) - set(TUNE_FIELDS)
         if bad:
             raise ValueError("unknown launch setting(s): %s" % sorted(bad))
         t = _lib.ConkerTune(**{k: int(v) for k, v in fields.items()})
         self._check(self.lib.conker_set_tune(self.h, ct.byref(t)))
+
+    def axis_order_used(self) -> int:
+        """Axis order (1..6, see set_tune) of the last map-free summation; 0 if none ran."""
+        v = ct.c_int()
+        self._check(self.lib.conker_axis_order_used(self.h, ct.byref(v)))
+        return int(v.value)
+
+    AXIS_ORDERS = {1: (0, 1, 2), 2: (0, 2, 1), 3: (1, 0, 2), 4: (1, 2, 0), 5: (2, 0, 1), 6: (2, 1, 0)}
 
     def get_tune(self) -> dict:
         t = _lib.ConkerTune()

@@ -38,6 +38,9 @@ struct conker_ctx {
     conker::Buf support;    // line mask, per-slab counts and list of lines carrying field
     conker::Buf scales;     // split-f16 summation: largest |value| per map and of the field
     conker::Buf cosmo;      // comoving-distance table of the survey front end
+    conker::Buf order;      // support projections, chosen axis order and permuted fields
+    int order_last = 0;             // axis order of the last map-free summation (1..6), -1: on the device
+    const int *order_dev = nullptr; // with order_last -1: the chosen permutation index (0..5)
     std::map<uint64_t, conker::Buf> tables;  // item / tuple tables, keyed by (n_radii, n, prec)
     // per-launch event timing (conker_profile_enable)
     int n_cu = 0;
@@ -84,6 +87,7 @@ enum ProfKind {
     PK_SUPPORT,
     PK_SPECTRAL,
     PK_SURVEY,
+    PK_ORDER,
     PK_COUNT
 };
 
@@ -194,6 +198,14 @@ int fft_inverse_batch(conker_ctx *ctx, const conker_grid *g, bool f64,
 int fft_inverse_z_diag(conker_ctx *ctx, const conker_grid *g, bool f64, const void *tspec, int nb,
                        const void *fa, const void *fb, int pmax, int blocks, void *part,
                        const unsigned char *mask = nullptr);
+
+// Axis order of map-free summations (order.hip): with the context's
+// axis_order setting (0 auto, 1 as given, 2..6 a fixed permutation) and a
+// cubic grid, copies the distinct non-NULL fields in[0 .. n_in) into the
+// permuted layout and points out[k] at the copies; otherwise out = in.  With
+// n_in = 4, in[2] and in[3] are the centre fields that decide the support.
+int order_fields(conker_ctx *c, const conker_grid *g, bool f64, int ns, const void *const *in, int n_in,
+                 const void **out);
 
 // Radii per inverse batch given the bytes one radius's spectrum takes
 // (conv.hip); fixed_bytes is the workspace needed beside the batch.

@@ -231,6 +231,7 @@ extern "C" void conker_destroy(conker_ctx *c) {
     rel(c->support);
     rel(c->scales);
     rel(c->cosmo);
+    rel(c->order);
     delete c;
 }
 
@@ -283,7 +284,8 @@ extern "C" const char *conker_profile_kind_name(int kind) {
     static const char *names[PK_COUNT] = {
         "scatter", "form_delta", "fft_fwd_z", "fft_fwd_y", "fft_fwd_x", "fft_inv_x_mul", "fft_inv_y",
         "fft_inv_z", "bank_z", "bank_y", "bank_x", "contract_dot", "contract_mm", "contract_reduce", "ratio",
-        "fused_zinv_contract", "diag_zinv", "diag_maps", "diag_reduce", "support", "pair_spectral", "survey_front_end"};
+        "fused_zinv_contract", "diag_zinv", "diag_maps", "diag_reduce", "support", "pair_spectral", "survey_front_end",
+        "axis_order"};
     return (kind >= 0 && kind < PK_COUNT) ? names[kind] : nullptr;
 }
 

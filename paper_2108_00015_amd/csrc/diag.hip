@@ -180,6 +180,11 @@ static int convolve_diag(conker_ctx *c, const conker_grid *g, conker_dtype dt, c
         return fail(c, CONKER_EINVAL, "field_b, its centre field and out_b must all be given or all be NULL");
     CK_HIP(c, hipSetDevice(c->device));
     const bool f64 = dt == CONKER_F64;
+    {   // axis order of the transforms (cubic grids): the passes run on permuted copies
+        const void *in[4] = {fa, fb, ca, cb}, *out[4];
+        CK_OK(order_fields(c, g, f64, n_radii, in, 4, out));
+        fa = out[0]; fb = out[1]; ca = out[2]; cb = out[3];
+    }
     const size_t nc = ncells(g);
     const size_t cbytes = nc * (f64 ? sizeof(double2) : sizeof(float2));
     const int B = batch_radii(c, cbytes, n_radii, cbytes);

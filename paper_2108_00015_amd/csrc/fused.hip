@@ -267,6 +267,11 @@ static int convolve_contract(conker_ctx *c, const conker_grid *g, conker_dtype d
     if (g->dims[2] != NZ) return fail(c, CONKER_EUNSUPPORTED, "fused summation needs nz = %d", NZ);
     if (ns < 1 || ns > MAXR) return fail(c, CONKER_EUNSUPPORTED, "fused summation holds 1..%d radii", MAXR);
     CK_HIP(c, hipSetDevice(c->device));
+    {   // axis order of the transforms (cubic grids): the passes run on permuted copies
+        const void *in[4] = {fa, fb, ca, cb}, *out[4];
+        CK_OK(order_fields(c, g, false, ns, in, 4, out));
+        fa = out[0]; fb = out[1]; ca = out[2]; cb = out[3];
+    }
     const size_t nc = ncells(g);
     const size_t cbytes = nc * sizeof(float2);
     CK_OK(ws_reserve(c, c->spec, cbytes));

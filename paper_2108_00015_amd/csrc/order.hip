@@ -1,0 +1,279 @@
+// Axis order of the transforms for map-free summations on cubic grids.
+//
+// The inverse passes after the kernel multiply skip work outside the support
+// of the summed fields: the first pass writes only slabs (along the first
+// transformed axis) that hold field, the middle pass reads those slabs and
+// writes only lines along the last axis that carry field, and the last pass
+// (fused with the summation) runs over those lines.  How much is skipped
+// depends on which axis comes first and which last: a sky cap along z, for
+// instance, spans few z-slabs but most x-slabs.  On a cubic grid every
+// permutation of the axes maps the shell of radius r (Sec. 2.3) onto itself,
+// so the stored kernel spectra serve the permuted grid unchanged and the sums
+// of Eq. ksin_delta are the same; only the order in which they are added
+// changes.  The fields are therefore copied into the permuted layout (on the
+// device, graph-safe) and the passes run on the copies.
+//
+// The permutation is either fixed by the context's setting or chosen on the
+// device from the field's support: the projections of the non-zero cells onto
+// the three coordinate planes give, for each axis a, the fraction s_a of
+// slabs with field and the fraction l_a of lines along a that carry field.
+// With first axis A and last axis C the inverse passes move about
+// 2 s_A + 2 l_C grid-units of complex values per radius; the permutation with
+// the smallest figure is taken when it saves more than the copies cost.
+#include "common.h"
+
+using namespace conker;
+
+namespace {
+
+// Permutation p (0..5, lexicographic): new axis k is old axis PERM[p][k].
+__constant__ int PERM[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+
+constexpr int OT = 256;   // threads per workgroup
+
+// One wave per z-line (x, y) of an L^3 grid: pxy[x L + y] = line carries
+// field; bit z of row x of pxz (row y of pyz) is set when cell (x, y, z) holds
+// field.  Rows are L / 32 words.  Non-zero is a bit test of everything but
+// the sign, as for the line masks.  Each lane reads 16 bytes (CPL cells) per step; the lanes' flags are
+// packed into 32-bit words (LPW lanes a word) with shuffles.
+template <typename T>
+__global__ __launch_bounds__(OT) void k_occupancy(const T *__restrict__ fa, const T *__restrict__ fb, int L,
+                                                  unsigned char *__restrict__ pxy, unsigned *__restrict__ pxz,
+                                                  unsigned *__restrict__ pyz) {
+    constexpr int CPL = 16 / (int)sizeof(T), LPW = 32 / CPL;
+    const int lane = threadIdx.x & 63;
+    const size_t line = (size_t)blockIdx.x * (OT / 64) + (threadIdx.x >> 6);
+    if (line >= (size_t)L * L) return;   // uniform per wave
+    const int x = (int)(line / L), y = (int)(line - (size_t)x * L);
+    const uint4 *a = reinterpret_cast<const uint4 *>(fa + line * L);
+    const uint4 *b = fb ? reinterpret_cast<const uint4 *>(fb + line * L) : nullptr;
+    const int W = L / 32, units = L / CPL;
+    unsigned any = 0;
+    for (int j = 0; j * 64 < units; ++j) {
+        const int q = j * 64 + lane;
+        unsigned bits = 0;
+        if (q < units) {
+            // sign bits cleared: -0.0 adds nothing to any sum and counts as zero
+            constexpr unsigned MLO = CPL == 4 ? 0x7fffffffu : 0xffffffffu;
+            uint4 v = a[q];
+            if (b) {
+                const uint4 v2 = b[q];
+                v = uint4{v.x | v2.x, v.y | v2.y, v.z | v2.z, v.w | v2.w};
+            }
+            v = uint4{v.x & MLO, v.y & 0x7fffffffu, v.z & MLO, v.w & 0x7fffffffu};
+            if constexpr (CPL == 4) {
+                bits = (v.x != 0u ? 1u : 0u) | (v.y != 0u ? 2u : 0u) | (v.z != 0u ? 4u : 0u) | (v.w != 0u ? 8u : 0u);
+            } else {
+                bits = ((v.x | v.y) != 0u ? 1u : 0u) | ((v.z | v.w) != 0u ? 2u : 0u);
+            }
+        }
+        unsigned word = bits << (CPL * (lane % LPW));
+#pragma unroll
+        for (int o = 1; o < LPW; o <<= 1) word |= __shfl_xor(word, o);
+        any |= word;
+        const int wi = j * (64 / LPW) + lane / LPW;   // word of the line this lane group fills
+        if (lane % LPW == 0 && wi < W && word) {
+            unsigned *r1 = pxz + (size_t)x * W + wi;
+            unsigned *r2 = pyz + (size_t)y * W + wi;
+            if ((*r1 & word) != word) atomicOr(r1, word);
+            if ((*r2 & word) != word) atomicOr(r2, word);
+        }
+    }
+    const bool carry = __ballot(any != 0u) != 0ull;
+    if (lane == 0) pxy[line] = carry ? 1 : 0;
+}
+
+// One workgroup: fractions of slabs and lines per axis from the projections,
+// then the permutation with the smallest pass traffic (ties: the lower index,
+// so the given order wins).  Writes the chosen index to *perm.
+__global__ __launch_bounds__(1024) void k_choose_order(const unsigned char *__restrict__ pxy,
+                                                       const unsigned *__restrict__ pxz,
+                                                       const unsigned *__restrict__ pyz, int L, int ns,
+                                                       int *__restrict__ perm) {
+    __shared__ unsigned col_z[32];                // OR over x of the rows of pxz (bits z)
+    __shared__ unsigned long long cnt[6];         // slabs x, y, z; lines along x, y, z
+    const int t = threadIdx.x, W = L / 32;
+    if (t < 32) col_z[t] = 0u;
+    if (t < 6) cnt[t] = 0ull;
+    __syncthreads();
+    unsigned long long sx = 0, sy = 0, lx = 0, ly = 0, lz = 0;
+    for (int r = t; r < L; r += blockDim.x) {
+        unsigned ox = 0, oy = 0;
+        for (int w = 0; w < W; ++w) {
+            const unsigned a = pxz[(size_t)r * W + w], b = pyz[(size_t)r * W + w];
+            ox |= a;
+            oy |= b;
+            ly += __popc(a);   // (x, z) positions with field: lines along y
+            lx += __popc(b);   // (y, z) positions: lines along x
+            if (a) atomicOr(&col_z[w], a);
+        }
+        sx += ox != 0u;
+        sy += oy != 0u;
+    }
+    const uint4 *p16 = reinterpret_cast<const uint4 *>(pxy);   // bytes 0 / 1, L^2 a multiple of 16
+    for (size_t i = t; i < (size_t)L * L / 16; i += blockDim.x) {
+        const uint4 v = p16[i];
+        lz += __popc(v.x) + __popc(v.y) + __popc(v.z) + __popc(v.w);
+    }
+    atomicAdd(&cnt[0], sx);
+    atomicAdd(&cnt[1], sy);
+    atomicAdd(&cnt[3], lx);
+    atomicAdd(&cnt[4], ly);
+    atomicAdd(&cnt[5], lz);
+    __syncthreads();
+    if (t == 0) {
+        unsigned long long sz = 0;
+        for (int w = 0; w < W; ++w) sz += __popc(col_z[w]);
+        const double slab[3] = {(double)cnt[0] / L, (double)cnt[1] / L, (double)sz / L};
+        const double lines[3] = {(double)cnt[3] / ((double)L * L), (double)cnt[4] / ((double)L * L),
+                                 (double)cnt[5] / ((double)L * L)};
+        double best = 0.0;
+        int bp = 0;
+        for (int p = 0; p < 6; ++p) {
+            const double s = 2.0 * slab[PERM[p][0]] + 2.0 * lines[PERM[p][2]];
+            if (p == 0 || s < best) {
+                best = s;
+                bp = p;
+            }
+        }
+        const double id = 2.0 * slab[0] + 2.0 * lines[2];
+        // copies of the fields cost about two grid-units; ask for a clear saving
+        perm[0] = (ns * (id - best) > 3.0) ? bp : 0;
+    }
+}
+
+// dst = src with its axes permuted: new axis k is old axis PERM[p][k], with p
+// fixed (>= 0) or read from *pdev.  A workgroup moves a 32 x 32 tile spanned
+// by old z (contiguous in src) and the old axis u that becomes contiguous in
+// dst (u = y when z stays the contiguous axis), at one value of the third axis.
+template <typename T>
+__global__ __launch_bounds__(OT) void k_permute(const T *__restrict__ src, T *__restrict__ dst, int L, int pfix,
+                                                const int *__restrict__ pdev) {
+    __shared__ T tile[32][33];
+    const int p = pfix >= 0 ? pfix : *pdev;
+    const int b = PERM[p][2];
+    const int u = b != 2 ? b : 1, w = 1 - u;   // the three old axes are z (2), u and w
+    const size_t LL = (size_t)L * L;
+    auto old_stride = [&](int a) -> size_t { return a == 0 ? LL : (a == 1 ? (size_t)L : 1); };
+    auto new_stride = [&](int a) -> size_t {
+        return PERM[p][0] == a ? LL : (PERM[p][1] == a ? (size_t)L : 1);
+    };
+    const size_t su_o = old_stride(u), sw_o = old_stride(w);
+    const size_t sz_n = new_stride(2), su_n = new_stride(u), sw_n = new_stride(w);
+    const int z0 = blockIdx.x * 32, u0 = blockIdx.y * 32, wv = blockIdx.z;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const T *s0 = src + (size_t)wv * sw_o;
+    T *d0 = dst + (size_t)wv * sw_n;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int a = ty + 8 * r;
+        tile[a][tx] = s0[(size_t)(z0 + tx) + (size_t)(u0 + a) * su_o];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int a = ty + 8 * r;
+        if (b != 2)   // old u becomes contiguous: lanes run along u
+            d0[(size_t)(z0 + a) * sz_n + (size_t)(u0 + tx) * su_n] = tile[tx][a];
+        else          // z stays contiguous: lanes run along z
+            d0[(size_t)(z0 + tx) * sz_n + (size_t)(u0 + a) * su_n] = tile[a][tx];
+    }
+}
+
+__global__ void k_zero_words(unsigned *__restrict__ p, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+}  // namespace
+
+namespace conker {
+
+int order_fields(conker_ctx *c, const conker_grid *g, bool f64, int ns, const void *const *in, int n_in,
+                 const void **out) {
+    for (int k = 0; k < n_in; ++k) out[k] = in[k];
+    const int L = g->dims[0];
+    const int mode = c->tune.axis_order;   // 0 auto, else permutation mode - 1 (1: as given)
+    const int pfix = mode >= 1 ? mode - 1 : -1;
+    c->order_last = 1;
+    c->order_dev = nullptr;
+    if (pfix == 0 || g->dims[1] != L || g->dims[2] != L || L % 32) return CONKER_OK;
+    for (int k = 0; k < n_in; ++k)
+        if ((uintptr_t)in[k] & 15) return fail(c, CONKER_EINVAL, "fields must be 16-byte aligned");
+    // distinct non-NULL fields are copied; repeats share a copy
+    int src_of[4], n_copy = 0;
+    const void *uniq[4];
+    for (int k = 0; k < n_in; ++k) {
+        src_of[k] = -1;
+        if (!in[k]) continue;
+        for (int j = 0; j < n_copy; ++j)
+            if (uniq[j] == in[k]) src_of[k] = j;
+        if (src_of[k] < 0) {
+            uniq[n_copy] = in[k];
+            src_of[k] = n_copy++;
+        }
+    }
+    const size_t nc = ncells(g), esz = f64 ? 8 : 4;
+    const size_t W = (size_t)L / 32;
+    const size_t pxy_b = ((size_t)L * L + 255) / 256 * 256;
+    const size_t plane_b = (W * L * sizeof(unsigned) + 255) / 256 * 256;
+    const size_t head = pxy_b + 2 * plane_b + 256;
+    const size_t field_b = (nc * esz + 255) / 256 * 256;
+    CK_OK(ws_reserve(c, c->order, head + (size_t)n_copy * field_b));
+    char *base = (char *)c->order.p;
+    unsigned char *pxy = (unsigned char *)base;
+    unsigned *pxz = (unsigned *)(base + pxy_b);
+    unsigned *pyz = (unsigned *)(base + pxy_b + plane_b);
+    int *perm = (int *)(base + pxy_b + 2 * plane_b);
+    ProfScope ps(c, PK_ORDER);
+    if (pfix < 0) {
+        const size_t words = 2 * plane_b / sizeof(unsigned);
+        hipLaunchKernelGGL(k_zero_words, dim3((unsigned)std::min<size_t>(1024, (words + 255) / 256)), dim3(256), 0,
+                           c->stream, pxz, words);
+        CK_LAUNCH(c);
+        // centre fields decide the support (they carry the factor F of every term)
+        const void *sa = in[n_in >= 4 ? 2 : 0], *sb = in[n_in >= 4 ? 3 : 1];
+        const unsigned blocks = (unsigned)(((size_t)L * L + OT / 64 - 1) / (OT / 64));
+        if (f64)
+            hipLaunchKernelGGL(k_occupancy<double>, dim3(blocks), dim3(OT), 0, c->stream, (const double *)sa,
+                               (const double *)sb, L, pxy, pxz, pyz);
+        else
+            hipLaunchKernelGGL(k_occupancy<float>, dim3(blocks), dim3(OT), 0, c->stream, (const float *)sa,
+                               (const float *)sb, L, pxy, pxz, pyz);
+        CK_LAUNCH(c);
+        hipLaunchKernelGGL(k_choose_order, dim3(1), dim3(1024), 0, c->stream, pxy, pxz, pyz, L, ns, perm);
+        CK_LAUNCH(c);
+    }
+    const dim3 grid((unsigned)(L / 32), (unsigned)(L / 32), (unsigned)L);
+    for (int j = 0; j < n_copy; ++j) {
+        void *dst = base + head + (size_t)j * field_b;
+        if (f64)
+            hipLaunchKernelGGL(k_permute<double>, grid, dim3(OT), 0, c->stream, (const double *)uniq[j],
+                               (double *)dst, L, pfix, perm);
+        else
+            hipLaunchKernelGGL(k_permute<float>, grid, dim3(OT), 0, c->stream, (const float *)uniq[j], (float *)dst,
+                               L, pfix, perm);
+        CK_LAUNCH(c);
+    }
+    for (int k = 0; k < n_in; ++k)
+        if (in[k]) out[k] = base + head + (size_t)src_of[k] * field_b;
+    c->order_last = pfix >= 0 ? pfix + 1 : -1;
+    c->order_dev = pfix >= 0 ? nullptr : perm;
+    return CONKER_OK;
+}
+
+}  // namespace conker
+
+extern "C" int conker_axis_order_used(conker_ctx *c, int *h_order) {
+    if (!c || !h_order) return CONKER_EINVAL;
+    if (c->order_last >= 0) {
+        *h_order = c->order_last;
+        return CONKER_OK;
+    }
+    CK_HIP(c, hipSetDevice(c->device));
+    int v = 0;
+    CK_HIP(c, hipMemcpyAsync(&v, c->order_dev, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    CK_HIP(c, hipStreamSynchronize(c->stream));
+    *h_order = v + 1;
+    return CONKER_OK;
+}

@@ -9,8 +9,9 @@
 // the y pass skips empty x-slabs and writes only carrying lines, and the z pass
 // transforms only carrying lines.  The results are unchanged.
 //
-// A line carries field if any of its words is non-zero in either field (bit
-// test, so -0.0 and NaN count as non-zero, which only keeps a line).  Outputs:
+// A line carries field if any value is non-zero in either field, tested on
+// the bits other than the sign (-0.0 counts as zero: it adds nothing to any
+// sum; NaN counts as non-zero, which only keeps a line).  Outputs:
 //   mask[x * ny + y]   1 or 0;
 //   xcount[x]          carrying lines of slab x;
 //   list[0 .. count)   carrying lines x * ny + y in increasing order;
@@ -23,8 +24,10 @@ namespace {
 
 constexpr int ST = 256;   // threads per workgroup (4 waves)
 
+// sm: the bits other than the sign of the four 32-bit words of 16 bytes
+// (float32: every word; float64: the high word of each value).
 __global__ __launch_bounds__(ST) void k_line_mask(const uint4 *__restrict__ fa, const uint4 *__restrict__ fb,
-                                                  int ny, int units, unsigned char *__restrict__ mask,
+                                                  int ny, int units, uint4 sm, unsigned char *__restrict__ mask,
                                                   int *__restrict__ xcount) {
     __shared__ int cnt[ST / 64];
     const int x = blockIdx.x, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -34,10 +37,10 @@ __global__ __launch_bounds__(ST) void k_line_mask(const uint4 *__restrict__ fa, 
         unsigned any = 0;
         for (int u = lane; u < units; u += 64) {
             const uint4 a = fa[base + u];
-            any |= a.x | a.y | a.z | a.w;
+            any |= (a.x & sm.x) | (a.y & sm.y) | (a.z & sm.z) | (a.w & sm.w);
             if (fb) {
                 const uint4 b = fb[base + u];
-                any |= b.x | b.y | b.z | b.w;
+                any |= (b.x & sm.x) | (b.y & sm.y) | (b.z & sm.z) | (b.w & sm.w);
             }
         }
         const bool on = __ballot(any != 0u) != 0ull;
@@ -114,8 +117,10 @@ int support_lines(conker_ctx *c, const conker_grid *g, bool f64, const void *fa,
     const int units = (int)((size_t)nz * (f64 ? 8 : 4) / 16);   // 16-byte words per line
     {
         ProfScope ps(c, PK_SUPPORT);
+        const uint4 sm = f64 ? uint4{0xffffffffu, 0x7fffffffu, 0xffffffffu, 0x7fffffffu}
+                             : uint4{0x7fffffffu, 0x7fffffffu, 0x7fffffffu, 0x7fffffffu};
         hipLaunchKernelGGL(k_line_mask, dim3(nx), dim3(ST), 0, c->stream, (const uint4 *)fa, (const uint4 *)fb, ny,
-                           units, mask, xcount);
+                           units, sm, mask, xcount);
         CK_LAUNCH(c);
         hipLaunchKernelGGL(k_line_list, dim3(nx), dim3(ST), 0, c->stream, mask, xcount, nx, ny, list, count);
         CK_LAUNCH(c);

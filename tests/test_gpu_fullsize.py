@@ -95,3 +95,30 @@ def test_cap512_full_size_sampled(cap, path):
     ctx.close()
     del ks
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("order", [1, 5, 6, 0])
+def test_cap512_fused_axis_orders(cap, order):
+    """The fused pass on the survey cap with the axes transformed in the given
+    order (1), in two fixed permutations (5: z, x, y; 6: z, y, x) and in the
+    order chosen from the support (0): every one against the oracle."""
+    ck, w, data, rand, o = cap
+    dev = "cuda:0"
+    grid = ck.Grid(w.dims, w.origin, w.cell)
+    ctx = ck.Context(0)
+    ctx.set_tune(axis_order=order)
+    _say("fused, axis order", order)
+    ks, _ = ctx.make_shell_kernels(grid, w.radii, torch.float32)
+    dpos, rpos = torch.from_numpy(data.pos).to(dev), torch.from_numpy(rand.pos).to(dev)
+    dw, rw = torch.from_numpy(data.w).to(dev), torch.from_numpy(rand.w).to(dev)
+    ns = len(w.radii)
+    for n in (3, 2):
+        out = ck.npcf(ctx, grid, dpos, rpos, ks, n, dw, rw, precision="split_bf16", dtype=torch.float32)
+        tl, rd, rr = o["ref"][n]
+        ed = _rel(_pick(out["W_delta"].cpu().numpy(), ns, n, tl), rd)
+        er = _rel(_pick(out["W_rand_raw"].cpu().numpy(), ns, n, tl), rr)
+        _say("  n=%d W_delta %.3e W_R %.3e" % (n, ed, er))
+        assert ed <= 1e-5 and er <= 1e-5
+    ctx.close()
+    del ks
+    torch.cuda.empty_cache()

@@ -221,3 +221,43 @@ def test_batch_autotune_then_graph(ck, ctx):
                   [1.0, 2.0, 3.5, 5.0, 8.0, 12.0], 3)
     assert relerr(d0.W_delta.cpu().numpy(), ref["W_delta"]) <= 1e-5
     assert relerr(d0.W_rand.cpu().numpy(), ref["W_rand_raw"]) <= 1e-5
+
+
+@pytest.fixture(scope="module")
+def cone64():
+    """A cubic grid whose field fills a cone along z (few z-slabs, most x- and
+    y-slabs), with the oracle's maps of four shells."""
+    L = 64
+    rng = np.random.default_rng(150)
+    x, y, z = np.meshgrid(*(np.arange(L) - 0.5 * L,) * 3, indexing="ij")
+    zz = z + 0.5 * L
+    keep = (zz >= 30) & (zz < 52) & (x * x + y * y <= (0.6 * zz) ** 2)
+    A = rng.normal(size=(L, L, L)) * keep
+    B = rng.poisson(2.0, size=(L, L, L)).astype(np.float64) * keep
+    radii = [1.0, 2.5, 4.0, 6.0]
+    return (L, L, L), A, B, radii, oc.convolve_shells(A, radii), oc.convolve_shells(B, radii)
+
+
+@pytest.mark.parametrize("order", [0, 1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("dt,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_diag_every_axis_order(ck, ctx, cone64, order, dt, tol):
+    dims, A, B, radii, ma, mb = cone64
+    Af = A.astype(np.float32).astype(np.float64) if dt == "f32" else A
+    if dt == "f32":
+        ma = oc.convolve_shells(Af, radii)
+    grid = ck.Grid(dims, (0, 0, 0), 1.0)
+    ks, _ = ctx.make_shell_kernels(grid, radii, TDT[dt])
+    ctx.set_tune(axis_order=order)
+    Da, Db = ctx.convolve_diag(grid, _gpu(A, TDT[dt]), _gpu(B, TDT[dt]), ks, 4)
+    used = ctx.axis_order_used()
+    # fixed orders report themselves; from the support, z (few slabs) comes first
+    assert used == order if order else used in (5, 6), used
+    for p in range(2, 5):
+        ra = np.array([np.sum(Af * ma[m] ** (p - 1)) for m in range(len(radii))])
+        rb = np.array([np.sum(B * mb[m] ** (p - 1)) for m in range(len(radii))])
+        ea, eb = relerr(Da.cpu().numpy()[p - 2], ra), relerr(Db.cpu().numpy()[p - 2], rb)
+        assert ea <= tol and eb <= tol, (order, p, ea, eb)
+    # cross form: maps of A summed against the centre field B
+    Ca, _ = ctx.convolve_diag(grid, _gpu(A, TDT[dt]), None, ks, 3, centre_a=_gpu(B, TDT[dt]))
+    rc = np.array([np.sum(B * ma[m]) for m in range(len(radii))])
+    assert relerr(Ca.cpu().numpy()[0], rc) <= tol

@@ -79,7 +79,8 @@ def kernel_bytes(kind, n_launch_units, nc, ns, kel, n_data, n_rand, weighted, es
 # dispatch, KiB) are committed under profiles/ together with a hash of the
 # sources the kernel is built from; the figure is used only while they match.
 TRAFFIC_SOURCES = ("paper_2108_00015_amd/csrc/fft.hip", "paper_2108_00015_amd/csrc/fft_math.h",
-                   "paper_2108_00015_amd/csrc/common.h", "paper_2108_00015_amd/csrc/fused.hip")
+                   "paper_2108_00015_amd/csrc/common.h", "paper_2108_00015_amd/csrc/fused.hip",
+                   "paper_2108_00015_amd/csrc/order.hip", "paper_2108_00015_amd/csrc/support.hip")
 
 
 def source_hashes(paths=TRAFFIC_SOURCES):

@@ -387,6 +387,9 @@ def main():
     for kind, (launches, tot) in mixed["prof"].items():
         per_step = tot / args.steps
         b = kernel_bytes(kind, launches, nc, ns, kel, len(data), len(rand), data.w is not None, 4, batch, fx, fl)
+        if kind == "support" and "axis_order" in mixed["prof"]:
+            # built from the axis-order projections: line mask, slab counts and list written
+            b = (launches / args.steps) * (nc ** (2.0 / 3.0)) * 5
         if kind == "contract_mm":
             b = 2 * (ns + 1) * nc * 4
         ent = dict(launches_per_step=launches / args.steps, ms_per_step=per_step,

@@ -164,6 +164,11 @@ struct Support {
     const int *count = nullptr;            // device scalar: length of list
 };
 int support_lines(conker_ctx *c, const conker_grid *g, bool f64, const void *fa, const void *fb, Support *out);
+// The same outputs from a mask and per-slab counts computed elsewhere:
+// support_alloc reserves the buffers (mask [nx * ny], xcount [nx]) to fill,
+// support_list then builds the ordered list and its count.
+int support_alloc(conker_ctx *c, int nx, int ny, Support *out, unsigned char **mask, int **xcount);
+int support_list(conker_ctx *c, int nx, int ny, const Support &s);
 
 // FFT passes (fft.hip) ------------------------------------------------------
 // Forward 3D FFT of the complex field packed from two real fields
@@ -204,8 +209,11 @@ int fft_inverse_z_diag(conker_ctx *ctx, const conker_grid *g, bool f64, const vo
 // cubic grid, copies the distinct non-NULL fields in[0 .. n_in) into the
 // permuted layout and points out[k] at the copies; otherwise out = in.  With
 // n_in = 4, in[2] and in[3] are the centre fields that decide the support.
+// When the fields are permuted, *sup receives the line support of the
+// permuted centre fields (from the same projections) and *have_sup is set;
+// otherwise the caller computes it with support_lines.
 int order_fields(conker_ctx *c, const conker_grid *g, bool f64, int ns, const void *const *in, int n_in,
-                 const void **out);
+                 const void **out, Support *sup, bool *have_sup);
 
 // Radii per inverse batch given the bytes one radius's spectrum takes
 // (conv.hip); fixed_bytes is the workspace needed beside the batch.

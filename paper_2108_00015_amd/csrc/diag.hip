@@ -180,9 +180,11 @@ static int convolve_diag(conker_ctx *c, const conker_grid *g, conker_dtype dt, c
         return fail(c, CONKER_EINVAL, "field_b, its centre field and out_b must all be given or all be NULL");
     CK_HIP(c, hipSetDevice(c->device));
     const bool f64 = dt == CONKER_F64;
+    Support sup;
+    bool have_sup = false;
     {   // axis order of the transforms (cubic grids): the passes run on permuted copies
         const void *in[4] = {fa, fb, ca, cb}, *out[4];
-        CK_OK(order_fields(c, g, f64, n_radii, in, 4, out));
+        CK_OK(order_fields(c, g, f64, n_radii, in, 4, out, &sup, &have_sup));
         fa = out[0]; fb = out[1]; ca = out[2]; cb = out[3];
     }
     const size_t nc = ncells(g);
@@ -194,8 +196,7 @@ static int convolve_diag(conker_ctx *c, const conker_grid *g, conker_dtype dt, c
     CK_OK(ws_reserve(c, c->tspec, (size_t)B * cbytes));
     CK_OK(ws_reserve(c, c->partial, (size_t)n_radii * blocks * 2 * P * sizeof(double)));
     double *part = (double *)c->partial.p;
-    Support sup;
-    CK_OK(support_lines(c, g, f64, ca, cb, &sup));
+    if (!have_sup) CK_OK(support_lines(c, g, f64, ca, cb, &sup));
     CK_OK(fft_forward_pair(c, g, f64, fa, fb, c->spec.p));
     for (int m0 = 0; m0 < n_radii; m0 += B) {
         const int nb = (m0 + B <= n_radii) ? B : n_radii - m0;

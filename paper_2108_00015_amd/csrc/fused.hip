@@ -267,17 +267,18 @@ static int convolve_contract(conker_ctx *c, const conker_grid *g, conker_dtype d
     if (g->dims[2] != NZ) return fail(c, CONKER_EUNSUPPORTED, "fused summation needs nz = %d", NZ);
     if (ns < 1 || ns > MAXR) return fail(c, CONKER_EUNSUPPORTED, "fused summation holds 1..%d radii", MAXR);
     CK_HIP(c, hipSetDevice(c->device));
+    Support sup;
+    bool have_sup = false;
     {   // axis order of the transforms (cubic grids): the passes run on permuted copies
         const void *in[4] = {fa, fb, ca, cb}, *out[4];
-        CK_OK(order_fields(c, g, false, ns, in, 4, out));
+        CK_OK(order_fields(c, g, false, ns, in, 4, out, &sup, &have_sup));
         fa = out[0]; fb = out[1]; ca = out[2]; cb = out[3];
     }
     const size_t nc = ncells(g);
     const size_t cbytes = nc * sizeof(float2);
     CK_OK(ws_reserve(c, c->spec, cbytes));
     CK_OK(ws_reserve(c, c->tspec, (size_t)ns * cbytes));
-    Support sup;
-    CK_OK(support_lines(c, g, false, ca, cb, &sup));
+    if (!have_sup) CK_OK(support_lines(c, g, false, ca, cb, &sup));
     CK_OK(fft_forward_pair(c, g, false, fa, fb, c->spec.p));
     CK_OK(fft_inverse_batch(c, g, false, c->spec.p, kspec, 0, ns, c->tspec.p, nullptr, nullptr, &sup));
     const void *twz;

@@ -31,27 +31,26 @@ __constant__ int PERM[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0
 
 constexpr int OT = 256;   // threads per workgroup
 
-// One wave per z-line (x, y) of an L^3 grid: pxy[x L + y] = line carries
-// field; bit z of row x of pxz (row y of pyz) is set when cell (x, y, z) holds
-// field.  Rows are L / 32 words.  Non-zero is a bit test of everything but
-// the sign, as for the line masks.  Each lane reads 16 bytes (CPL cells) per step; the lanes' flags are
-// packed into 32-bit words (LPW lanes a word) with shuffles.
+// One wave per z-line (x, y) of an L^3 grid: bits[(x L + y) W + w] holds
+// cells 32 w .. 32 w + 31 of the line (bit set: the cell holds field in
+// either field), W = L / 32, and pxy[x L + y] = the line carries field.
+// Non-zero is a bit test of everything but the sign, as for the line masks.
+// Each lane reads 16 bytes (CPL cells) per step; the lanes' flags are packed
+// into 32-bit words (LPW lanes a word) with shuffles.
 template <typename T>
-__global__ __launch_bounds__(OT) void k_occupancy(const T *__restrict__ fa, const T *__restrict__ fb, int L,
-                                                  unsigned char *__restrict__ pxy, unsigned *__restrict__ pxz,
-                                                  unsigned *__restrict__ pyz) {
+__global__ __launch_bounds__(OT) void k_occ_bits(const T *__restrict__ fa, const T *__restrict__ fb, int L,
+                                                 unsigned *__restrict__ bits, unsigned char *__restrict__ pxy) {
     constexpr int CPL = 16 / (int)sizeof(T), LPW = 32 / CPL;
     const int lane = threadIdx.x & 63;
     const size_t line = (size_t)blockIdx.x * (OT / 64) + (threadIdx.x >> 6);
     if (line >= (size_t)L * L) return;   // uniform per wave
-    const int x = (int)(line / L), y = (int)(line - (size_t)x * L);
     const uint4 *a = reinterpret_cast<const uint4 *>(fa + line * L);
     const uint4 *b = fb ? reinterpret_cast<const uint4 *>(fb + line * L) : nullptr;
     const int W = L / 32, units = L / CPL;
     unsigned any = 0;
     for (int j = 0; j * 64 < units; ++j) {
         const int q = j * 64 + lane;
-        unsigned bits = 0;
+        unsigned fl = 0;
         if (q < units) {
             // sign bits cleared: -0.0 adds nothing to any sum and counts as zero
             constexpr unsigned MLO = CPL == 4 ? 0x7fffffffu : 0xffffffffu;
@@ -62,25 +61,41 @@ __global__ __launch_bounds__(OT) void k_occupancy(const T *__restrict__ fa, cons
             }
             v = uint4{v.x & MLO, v.y & 0x7fffffffu, v.z & MLO, v.w & 0x7fffffffu};
             if constexpr (CPL == 4) {
-                bits = (v.x != 0u ? 1u : 0u) | (v.y != 0u ? 2u : 0u) | (v.z != 0u ? 4u : 0u) | (v.w != 0u ? 8u : 0u);
+                fl = (v.x != 0u ? 1u : 0u) | (v.y != 0u ? 2u : 0u) | (v.z != 0u ? 4u : 0u) | (v.w != 0u ? 8u : 0u);
             } else {
-                bits = ((v.x | v.y) != 0u ? 1u : 0u) | ((v.z | v.w) != 0u ? 2u : 0u);
+                fl = ((v.x | v.y) != 0u ? 1u : 0u) | ((v.z | v.w) != 0u ? 2u : 0u);
             }
         }
-        unsigned word = bits << (CPL * (lane % LPW));
+        unsigned word = fl << (CPL * (lane % LPW));
 #pragma unroll
         for (int o = 1; o < LPW; o <<= 1) word |= __shfl_xor(word, o);
         any |= word;
         const int wi = j * (64 / LPW) + lane / LPW;   // word of the line this lane group fills
-        if (lane % LPW == 0 && wi < W && word) {
-            unsigned *r1 = pxz + (size_t)x * W + wi;
-            unsigned *r2 = pyz + (size_t)y * W + wi;
-            if ((*r1 & word) != word) atomicOr(r1, word);
-            if ((*r2 & word) != word) atomicOr(r2, word);
-        }
+        if (lane % LPW == 0 && wi < W) bits[line * W + wi] = word;
     }
     const bool carry = __ballot(any != 0u) != 0ull;
     if (lane == 0) pxy[line] = carry ? 1 : 0;
+}
+
+// Projections onto the (x, z) and (y, z) planes: workgroups 0 .. L-1 write
+// row x of pxz (OR over y of the lines' words), workgroups L .. 2L-1 row y of
+// pyz (OR over x).
+__global__ __launch_bounds__(OT) void k_occ_planes(const unsigned *__restrict__ bits, int L,
+                                                   unsigned *__restrict__ pxz, unsigned *__restrict__ pyz) {
+    __shared__ unsigned acc[32];
+    const int W = L / 32, t = threadIdx.x;
+    const bool rows_x = (int)blockIdx.x < L;
+    const int r = rows_x ? blockIdx.x : blockIdx.x - L;
+    if (t < W) acc[t] = 0u;
+    __syncthreads();
+    for (int e = t; e < L * W; e += OT) {
+        const int k = e / W, w = e - (e / W) * W;   // k: the other in-plane index (y for pxz, x for pyz)
+        const size_t line = rows_x ? (size_t)r * L + k : (size_t)k * L + r;
+        const unsigned v = bits[line * W + w];
+        if (v) atomicOr(&acc[w], v);
+    }
+    __syncthreads();
+    if (t < W) (rows_x ? pxz : pyz)[(size_t)r * W + t] = acc[t];
 }
 
 // One workgroup: fractions of slabs and lines per axis from the projections,
@@ -180,9 +195,40 @@ __global__ __launch_bounds__(OT) void k_permute(const T *__restrict__ src, T *__
     }
 }
 
-__global__ void k_zero_words(unsigned *__restrict__ p, size_t n) {
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        p[i] = 0u;
+// Line support of the permuted grid from the projections: workgroup n0 (a
+// slab of the new first axis) writes mask[n0 L + n1] for the lines along the
+// new last axis and xcount[n0], the number of those that carry field.
+__global__ __launch_bounds__(OT) void k_support_planes(const unsigned char *__restrict__ pxy,
+                                                       const unsigned *__restrict__ pxz,
+                                                       const unsigned *__restrict__ pyz, int L, int pfix,
+                                                       const int *__restrict__ pdev, unsigned char *__restrict__ mask,
+                                                       int *__restrict__ xcount) {
+    __shared__ int part[OT / 64];
+    const int p = pfix >= 0 ? pfix : *pdev;
+    const int a0 = PERM[p][0], a1 = PERM[p][1], C = PERM[p][2];
+    const int n0 = blockIdx.x, W = L / 32;
+    int cnt = 0;
+    for (int n1 = threadIdx.x; n1 < L; n1 += OT) {
+        // old coordinates fixed by the line (the one along C is free)
+        const int ox = a0 == 0 ? n0 : (a1 == 0 ? n1 : 0);
+        const int oy = a0 == 1 ? n0 : (a1 == 1 ? n1 : 0);
+        const int oz = a0 == 2 ? n0 : (a1 == 2 ? n1 : 0);
+        bool on;
+        if (C == 2) on = pxy[(size_t)ox * L + oy] != 0;
+        else if (C == 1) on = (pxz[(size_t)ox * W + (oz >> 5)] >> (oz & 31)) & 1u;
+        else on = (pyz[(size_t)oy * W + (oz >> 5)] >> (oz & 31)) & 1u;
+        mask[(size_t)n0 * L + n1] = on ? 1 : 0;
+        cnt += on ? 1 : 0;
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) cnt += __shfl_xor(cnt, o);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int s = 0;
+        for (int i = 0; i < OT / 64; ++i) s += part[i];
+        xcount[n0] = s;
+    }
 }
 
 }  // namespace
@@ -190,8 +236,9 @@ __global__ void k_zero_words(unsigned *__restrict__ p, size_t n) {
 namespace conker {
 
 int order_fields(conker_ctx *c, const conker_grid *g, bool f64, int ns, const void *const *in, int n_in,
-                 const void **out) {
+                 const void **out, Support *sup, bool *have_sup) {
     for (int k = 0; k < n_in; ++k) out[k] = in[k];
+    if (have_sup) *have_sup = false;
     const int L = g->dims[0];
     const int mode = c->tune.axis_order;   // 0 auto, else permutation mode - 1 (1: as given)
     const int pfix = mode >= 1 ? mode - 1 : -1;
@@ -215,50 +262,65 @@ int order_fields(conker_ctx *c, const conker_grid *g, bool f64, int ns, const vo
     }
     const size_t nc = ncells(g), esz = f64 ? 8 : 4;
     const size_t W = (size_t)L / 32;
-    const size_t pxy_b = ((size_t)L * L + 255) / 256 * 256;
-    const size_t plane_b = (W * L * sizeof(unsigned) + 255) / 256 * 256;
-    const size_t head = pxy_b + 2 * plane_b + 256;
-    const size_t field_b = (nc * esz + 255) / 256 * 256;
+    const auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t pxy_b = up((size_t)L * L), plane_b = up(W * L * sizeof(unsigned));
+    const size_t bits_b = up((size_t)L * L * W * sizeof(unsigned));
+    const size_t head = pxy_b + 2 * plane_b + 256 + bits_b;
+    const size_t field_b = up(nc * esz);
     CK_OK(ws_reserve(c, c->order, head + (size_t)n_copy * field_b));
     char *base = (char *)c->order.p;
     unsigned char *pxy = (unsigned char *)base;
     unsigned *pxz = (unsigned *)(base + pxy_b);
     unsigned *pyz = (unsigned *)(base + pxy_b + plane_b);
     int *perm = (int *)(base + pxy_b + 2 * plane_b);
-    ProfScope ps(c, PK_ORDER);
-    if (pfix < 0) {
-        const size_t words = 2 * plane_b / sizeof(unsigned);
-        hipLaunchKernelGGL(k_zero_words, dim3((unsigned)std::min<size_t>(1024, (words + 255) / 256)), dim3(256), 0,
-                           c->stream, pxz, words);
-        CK_LAUNCH(c);
-        // centre fields decide the support (they carry the factor F of every term)
+    unsigned *bits = (unsigned *)(base + pxy_b + 2 * plane_b + 256);
+    {
+        ProfScope ps(c, PK_ORDER);
+        // projections of the centre fields' support (they carry the factor F of every term)
         const void *sa = in[n_in >= 4 ? 2 : 0], *sb = in[n_in >= 4 ? 3 : 1];
         const unsigned blocks = (unsigned)(((size_t)L * L + OT / 64 - 1) / (OT / 64));
         if (f64)
-            hipLaunchKernelGGL(k_occupancy<double>, dim3(blocks), dim3(OT), 0, c->stream, (const double *)sa,
-                               (const double *)sb, L, pxy, pxz, pyz);
+            hipLaunchKernelGGL(k_occ_bits<double>, dim3(blocks), dim3(OT), 0, c->stream, (const double *)sa,
+                               (const double *)sb, L, bits, pxy);
         else
-            hipLaunchKernelGGL(k_occupancy<float>, dim3(blocks), dim3(OT), 0, c->stream, (const float *)sa,
-                               (const float *)sb, L, pxy, pxz, pyz);
+            hipLaunchKernelGGL(k_occ_bits<float>, dim3(blocks), dim3(OT), 0, c->stream, (const float *)sa,
+                               (const float *)sb, L, bits, pxy);
         CK_LAUNCH(c);
-        hipLaunchKernelGGL(k_choose_order, dim3(1), dim3(1024), 0, c->stream, pxy, pxz, pyz, L, ns, perm);
+        hipLaunchKernelGGL(k_occ_planes, dim3(2 * L), dim3(OT), 0, c->stream, bits, L, pxz, pyz);
         CK_LAUNCH(c);
-    }
-    const dim3 grid((unsigned)(L / 32), (unsigned)(L / 32), (unsigned)L);
-    for (int j = 0; j < n_copy; ++j) {
-        void *dst = base + head + (size_t)j * field_b;
-        if (f64)
-            hipLaunchKernelGGL(k_permute<double>, grid, dim3(OT), 0, c->stream, (const double *)uniq[j],
-                               (double *)dst, L, pfix, perm);
-        else
-            hipLaunchKernelGGL(k_permute<float>, grid, dim3(OT), 0, c->stream, (const float *)uniq[j], (float *)dst,
-                               L, pfix, perm);
-        CK_LAUNCH(c);
+        if (pfix < 0) {
+            hipLaunchKernelGGL(k_choose_order, dim3(1), dim3(1024), 0, c->stream, pxy, pxz, pyz, L, ns, perm);
+            CK_LAUNCH(c);
+        }
+        const dim3 grid((unsigned)(L / 32), (unsigned)(L / 32), (unsigned)L);
+        for (int j = 0; j < n_copy; ++j) {
+            void *dst = base + head + (size_t)j * field_b;
+            if (f64)
+                hipLaunchKernelGGL(k_permute<double>, grid, dim3(OT), 0, c->stream, (const double *)uniq[j],
+                                   (double *)dst, L, pfix, perm);
+            else
+                hipLaunchKernelGGL(k_permute<float>, grid, dim3(OT), 0, c->stream, (const float *)uniq[j],
+                                   (float *)dst, L, pfix, perm);
+            CK_LAUNCH(c);
+        }
     }
     for (int k = 0; k < n_in; ++k)
         if (in[k]) out[k] = base + head + (size_t)src_of[k] * field_b;
     c->order_last = pfix >= 0 ? pfix + 1 : -1;
     c->order_dev = pfix >= 0 ? nullptr : perm;
+    if (sup) {   // line support of the permuted centre fields, from the same projections
+        unsigned char *mask;
+        int *xcount;
+        CK_OK(support_alloc(c, L, L, sup, &mask, &xcount));
+        {
+            ProfScope ps(c, PK_SUPPORT);
+            hipLaunchKernelGGL(k_support_planes, dim3(L), dim3(OT), 0, c->stream, pxy, pxz, pyz, L, pfix, perm, mask,
+                               xcount);
+            CK_LAUNCH(c);
+        }
+        CK_OK(support_list(c, L, L, *sup));
+        if (have_sup) *have_sup = true;
+    }
     return CONKER_OK;
 }
 

@@ -99,21 +99,37 @@ __global__ __launch_bounds__(ST) void k_line_list(const unsigned char *__restric
 
 namespace conker {
 
-int support_lines(conker_ctx *c, const conker_grid *g, bool f64, const void *fa, const void *fb, Support *out) {
-    const int nx = g->dims[0], ny = g->dims[1], nz = g->dims[2];
+int support_alloc(conker_ctx *c, int nx, int ny, Support *out, unsigned char **mask, int **xcount) {
     *out = Support{};
-    if (((uintptr_t)fa & 15) || ((uintptr_t)fb & 15))
-        return fail(c, CONKER_EINVAL, "fields must be 16-byte aligned");
     const size_t nl = (size_t)nx * ny;
     const size_t mask_b = (nl + 255) / 256 * 256;
     const size_t xc_b = ((size_t)nx * sizeof(int) + 255) / 256 * 256;
     const size_t list_b = (nl * sizeof(int) + 255) / 256 * 256;
     CK_OK(ws_reserve(c, c->support, mask_b + xc_b + list_b + 256));
     char *p = (char *)c->support.p;
-    unsigned char *mask = (unsigned char *)p;
-    int *xcount = (int *)(p + mask_b);
-    int *list = (int *)(p + mask_b + xc_b);
-    int *count = (int *)(p + mask_b + xc_b + list_b);
+    out->mask = *mask = (unsigned char *)p;
+    out->xcount = *xcount = (int *)(p + mask_b);
+    out->list = (int *)(p + mask_b + xc_b);
+    out->count = (int *)(p + mask_b + xc_b + list_b);
+    return CONKER_OK;
+}
+
+int support_list(conker_ctx *c, int nx, int ny, const Support &s) {
+    ProfScope ps(c, PK_SUPPORT);
+    hipLaunchKernelGGL(k_line_list, dim3(nx), dim3(ST), 0, c->stream, s.mask, s.xcount, nx, ny,
+                       const_cast<int *>(s.list), const_cast<int *>(s.count));
+    CK_LAUNCH(c);
+    return CONKER_OK;
+}
+
+int support_lines(conker_ctx *c, const conker_grid *g, bool f64, const void *fa, const void *fb, Support *out) {
+    const int nx = g->dims[0], ny = g->dims[1], nz = g->dims[2];
+    *out = Support{};
+    if (((uintptr_t)fa & 15) || ((uintptr_t)fb & 15))
+        return fail(c, CONKER_EINVAL, "fields must be 16-byte aligned");
+    unsigned char *mask;
+    int *xcount;
+    CK_OK(support_alloc(c, nx, ny, out, &mask, &xcount));
     const int units = (int)((size_t)nz * (f64 ? 8 : 4) / 16);   // 16-byte words per line
     {
         ProfScope ps(c, PK_SUPPORT);
@@ -122,14 +138,8 @@ int support_lines(conker_ctx *c, const conker_grid *g, bool f64, const void *fa,
         hipLaunchKernelGGL(k_line_mask, dim3(nx), dim3(ST), 0, c->stream, (const uint4 *)fa, (const uint4 *)fb, ny,
                            units, sm, mask, xcount);
         CK_LAUNCH(c);
-        hipLaunchKernelGGL(k_line_list, dim3(nx), dim3(ST), 0, c->stream, mask, xcount, nx, ny, list, count);
-        CK_LAUNCH(c);
     }
-    out->mask = mask;
-    out->xcount = xcount;
-    out->list = list;
-    out->count = count;
-    return CONKER_OK;
+    return support_list(c, nx, ny, *out);
 }
 
 }  // namespace conker

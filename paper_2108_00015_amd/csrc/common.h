@@ -39,6 +39,7 @@ struct conker_ctx {
     conker::Buf scales;     // split-f16 summation: largest |value| per map and of the field
     conker::Buf cosmo;      // comoving-distance table of the survey front end
     conker::Buf order;      // support projections, chosen axis order and permuted fields
+    conker::Buf bins;       // binned mapping: per-brick counts and starts, per-workgroup histograms, placed points
     int order_last = 0;             // axis order of the last map-free summation (1..6), -1: on the device
     const int *order_dev = nullptr; // with order_last -1: the chosen permutation index (0..5)
     std::map<uint64_t, conker::Buf> tables;  // item / tuple tables, keyed by (n_radii, n, prec)

@@ -232,6 +232,7 @@ extern "C" void conker_destroy(conker_ctx *c) {
     rel(c->scales);
     rel(c->cosmo);
     rel(c->order);
+    rel(c->bins);
     delete c;
 }
 

@@ -10,6 +10,8 @@ struct GridGeom {
     int nx, ny, nz;
 };
 
+__device__ inline int cell_of(float x, double o, double cell, int n, bool &ok);
+
 template <typename T>
 __device__ inline void atomic_add_grid(T *p, float w);
 
@@ -76,6 +78,208 @@ __global__ __launch_bounds__(256) void k_scatter(const float *__restrict__ pos,
     }
 }
 
+// ---------------------------------------------------------------------------
+// Binned mapping for large catalogs.  Points arrive in no spatial order, so
+// one float atomic per point at a random address of a grid far larger than
+// the caches turns into a memory read-modify-write per point.  Instead the
+// grid is cut into bricks of BX x BY x BZ cells and the points are counted,
+// placed in brick order, and summed one brick at a time in LDS:
+//   k_bin_count  per-workgroup brick histogram (LDS) of a contiguous chunk of
+//                points, written out and added to the per-brick totals; the
+//                weight sum and rejected count as in k_scatter;
+//   k_bin_scan   exclusive prefix sum of the totals: brick starts, cursors;
+//   k_bin_place  each workgroup reserves its share of every brick with one
+//                atomic, then writes (cell in brick, weight) of its points at
+//                their brick's slots (ranks from LDS atomics);
+//   k_bin_accum  one workgroup per brick holding points: LDS tile sums, then
+//                the tile is added to the grid (the grid is accumulated into).
+// The sums are the same as the direct kernel's, in another order (exact for
+// unit weights, which give integer counts).
+// ---------------------------------------------------------------------------
+constexpr int BX = 16, BY = 16, BZ = 32, BCELLS = BX * BY * BZ;
+constexpr int MAX_BRICKS = 16384;   // LDS histogram of one workgroup: 64 KB
+constexpr int BG = 512;             // workgroups of the count / place passes
+constexpr int BT = 1024;            // their threads
+constexpr int64_t BIN_MIN_POINTS = (int64_t)1 << 22;
+
+struct BrickGeom {
+    int bnx, bny, bnz;   // bricks per axis
+};
+
+__device__ __forceinline__ bool locate(const float *pos, const float *w, int64_t p, const GridGeom &g,
+                                       const BrickGeom &bg, int &brick, int &inner, float &wt) {
+    const float x = pos[3 * p + 0], y = pos[3 * p + 1], z = pos[3 * p + 2];
+    wt = w ? w[p] : 1.0f;
+    bool ok = isfinite(x) && isfinite(y) && isfinite(z) && isfinite(wt);
+    const int cx = cell_of(x, g.ox, g.cell, g.nx, ok);
+    const int cy = cell_of(y, g.oy, g.cell, g.ny, ok);
+    const int cz = cell_of(z, g.oz, g.cell, g.nz, ok);
+    brick = ((cx / BX) * bg.bny + cy / BY) * bg.bnz + cz / BZ;
+    inner = ((cx % BX) * BY + cy % BY) * BZ + cz % BZ;
+    return ok;
+}
+
+__global__ __launch_bounds__(BT) void k_bin_count(const float *__restrict__ pos, const float *__restrict__ w,
+                                                  int64_t n, int64_t chunk, GridGeom g, BrickGeom bg, int nb,
+                                                  unsigned *__restrict__ hist_out, unsigned *__restrict__ totals,
+                                                  double *wsum, unsigned long long *n_out) {
+    __shared__ unsigned hist[MAX_BRICKS];
+    __shared__ double sw[BT / 64];
+    __shared__ unsigned long long so[BT / 64];
+    for (int b = threadIdx.x; b < nb; b += BT) hist[b] = 0u;
+    __syncthreads();
+    double my_w = 0.0;
+    unsigned long long my_out = 0;
+    const int64_t p0 = (int64_t)blockIdx.x * chunk, p1 = p0 + chunk < n ? p0 + chunk : n;
+    // four points per thread and step, all located before any LDS update
+    for (int64_t q = p0 + threadIdx.x; q < p1; q += 4 * BT) {
+        int brick[4], inner[4];
+        float wt[4];
+        bool ok[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int64_t p = q + (int64_t)k * BT;
+            ok[k] = p < p1 && locate(pos, w, p, g, bg, brick[k], inner[k], wt[k]);
+            if (p < p1 && !ok[k]) ++my_out;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (ok[k]) {
+                atomicAdd(&hist[brick[k]], 1u);
+                my_w += (double)wt[k];
+            }
+    }
+    __syncthreads();
+    unsigned *mine = hist_out + (size_t)blockIdx.x * nb;
+    for (int b = threadIdx.x; b < nb; b += BT) {
+        const unsigned h = hist[b];
+        mine[b] = h;
+        if (h) atomicAdd(&totals[b], h);
+    }
+    // weight sum and rejected count of the workgroup
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        my_w += __shfl_xor(my_w, o);
+        my_out += __shfl_xor(my_out, o);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        sw[threadIdx.x >> 6] = my_w;
+        so[threadIdx.x >> 6] = my_out;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0;
+        unsigned long long b = 0;
+        for (int i = 0; i < BT / 64; ++i) {
+            a += sw[i];
+            b += so[i];
+        }
+        if (wsum) unsafeAtomicAdd(wsum, a);
+        if (n_out && b) atomicAdd(n_out, b);
+    }
+}
+
+// One workgroup: start[b] = sum of totals before b (start[nb] = all), cursor = start.
+__global__ __launch_bounds__(BT) void k_bin_scan(const unsigned *__restrict__ totals, int nb,
+                                                 unsigned *__restrict__ start, unsigned *__restrict__ cursor) {
+    __shared__ unsigned part[BT];
+    const int t = threadIdx.x, per = (nb + BT - 1) / BT;
+    const int b0 = t * per;
+    unsigned s = 0;
+    for (int b = b0; b < b0 + per && b < nb; ++b) s += totals[b];
+    part[t] = s;
+    __syncthreads();
+    for (int h = 1; h < BT; h <<= 1) {   // inclusive scan of the thread sums
+        const unsigned v = t >= h ? part[t - h] : 0u;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    unsigned run = part[t] - s;
+    for (int b = b0; b < b0 + per && b < nb; ++b) {
+        start[b] = run;
+        cursor[b] = run;
+        run += totals[b];
+    }
+    if (t == BT - 1) start[nb] = part[t];
+}
+
+__global__ __launch_bounds__(BT) void k_bin_place(const float *__restrict__ pos, const float *__restrict__ w,
+                                                  int64_t n, int64_t chunk, GridGeom g, BrickGeom bg, int nb,
+                                                  const unsigned *__restrict__ hist_in, unsigned *__restrict__ cursor,
+                                                  uint2 *__restrict__ items) {
+    __shared__ unsigned base[MAX_BRICKS];
+    __shared__ unsigned rank[MAX_BRICKS];
+    const unsigned *mine = hist_in + (size_t)blockIdx.x * nb;
+    for (int b = threadIdx.x; b < nb; b += BT) {
+        const unsigned h = mine[b];
+        base[b] = h ? atomicAdd(&cursor[b], h) : 0u;
+        rank[b] = 0u;
+    }
+    __syncthreads();
+    const int64_t p0 = (int64_t)blockIdx.x * chunk, p1 = p0 + chunk < n ? p0 + chunk : n;
+    for (int64_t q = p0 + threadIdx.x; q < p1; q += 4 * BT) {
+        int brick[4], inner[4];
+        float wt[4];
+        bool ok[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int64_t p = q + (int64_t)k * BT;
+            ok[k] = p < p1 && locate(pos, w, p, g, bg, brick[k], inner[k], wt[k]);
+        }
+        unsigned slot[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (ok[k]) slot[k] = base[brick[k]] + atomicAdd(&rank[brick[k]], 1u);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (ok[k]) items[slot[k]] = uint2{(unsigned)inner[k], __float_as_uint(wt[k])};
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_bin_accum(const uint2 *__restrict__ items, const unsigned *__restrict__ start,
+                                                   GridGeom g, BrickGeom bg, T *__restrict__ grid) {
+    __shared__ T tile[BCELLS];
+    const int b = blockIdx.x;
+    const unsigned i0 = start[b], i1 = start[b + 1];
+    if (i0 == i1) return;   // uniform: no point in this brick
+    for (int e = threadIdx.x; e < BCELLS; e += 256) tile[e] = (T)0;
+    __syncthreads();
+    for (unsigned i = i0 + threadIdx.x; i < i1; i += 4 * 256) {
+        uint2 it[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) it[k] = i + k * 256 < i1 ? items[i + k * 256] : uint2{0u, 0u};
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (i + k * 256 < i1) atomicAdd(&tile[it[k].x], (T)__uint_as_float(it[k].y));
+    }
+    __syncthreads();
+    // the brick's rows of BZ cells, 4 values a thread-step; every value read before any is written
+    const int bz = b % bg.bnz, by = (b / bg.bnz) % bg.bny, bx = b / (bg.bnz * bg.bny);
+    constexpr int V = 4, PER = BCELLS / V / 256;
+    T v[PER][V];
+    size_t lin[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int e = (threadIdx.x + k * 256) * V;
+        const int lz = e % BZ, ly = (e / BZ) % BY, lx = e / (BZ * BY);
+        lin[k] = ((size_t)(bx * BX + lx) * g.ny + (by * BY + ly)) * g.nz + (bz * BZ + lz);
+#pragma unroll
+        for (int j = 0; j < V; ++j) v[k][j] = grid[lin[k] + j];
+    }
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int e = (threadIdx.x + k * 256) * V;
+#pragma unroll
+        for (int j = 0; j < V; ++j) grid[lin[k] + j] = v[k][j] + tile[e + j];
+    }
+}
+
+__global__ void k_zero_u32(unsigned *__restrict__ p, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0u;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_form_delta(T *__restrict__ D, const T *__restrict__ R,
                                                     size_t n, const double *wd, const double *wr,
@@ -101,11 +305,46 @@ extern "C" int conker_grid_assign(conker_ctx *c, const conker_grid *g, const flo
     if (n == 0) return CONKER_OK;
     CK_HIP(c, hipSetDevice(c->device));
     GridGeom gg{g->origin[0], g->origin[1], g->origin[2], g->cell, g->dims[0], g->dims[1], g->dims[2]};
+    auto *no = reinterpret_cast<unsigned long long *>(n_out);
+    ProfScope ps(c, PK_SCATTER);
+    const BrickGeom bg{g->dims[0] / BX, g->dims[1] / BY, g->dims[2] / BZ};
+    const int64_t nb64 = (int64_t)bg.bnx * bg.bny * bg.bnz;
+    if (n >= BIN_MIN_POINTS && n <= (int64_t)0xffffffffu && g->dims[0] % BX == 0 && g->dims[1] % BY == 0 &&
+        g->dims[2] % BZ == 0 && nb64 <= MAX_BRICKS) {
+        const int nb = (int)nb64;
+        const auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+        const size_t tot_b = up(nb * sizeof(unsigned)), start_b = up((nb + 1) * sizeof(unsigned));
+        const size_t hist_b = up((size_t)BG * nb * sizeof(unsigned)), items_b = up((size_t)n * sizeof(uint2));
+        CK_OK(ws_reserve(c, c->bins, 3 * tot_b + start_b + hist_b + items_b));
+        char *base = (char *)c->bins.p;
+        unsigned *totals = (unsigned *)base;
+        unsigned *cursor = (unsigned *)(base + tot_b);
+        unsigned *start = (unsigned *)(base + 3 * tot_b);
+        unsigned *hist = (unsigned *)(base + 3 * tot_b + start_b);
+        uint2 *items = (uint2 *)(base + 3 * tot_b + start_b + hist_b);
+        const int64_t chunk = (n + BG - 1) / BG;
+        hipLaunchKernelGGL(k_zero_u32, dim3(64), dim3(256), 0, c->stream, totals, nb);
+        CK_LAUNCH(c);
+        hipLaunchKernelGGL(k_bin_count, dim3(BG), dim3(BT), 0, c->stream, pos, w, n, chunk, gg, bg, nb, hist, totals,
+                           wsum, no);
+        CK_LAUNCH(c);
+        hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(BT), 0, c->stream, totals, nb, start, cursor);
+        CK_LAUNCH(c);
+        hipLaunchKernelGGL(k_bin_place, dim3(BG), dim3(BT), 0, c->stream, pos, w, n, chunk, gg, bg, nb, hist, cursor,
+                           items);
+        CK_LAUNCH(c);
+        if (dt == CONKER_F32)
+            hipLaunchKernelGGL(k_bin_accum<float>, dim3(nb), dim3(256), 0, c->stream, items, start, gg, bg,
+                               (float *)grid);
+        else
+            hipLaunchKernelGGL(k_bin_accum<double>, dim3(nb), dim3(256), 0, c->stream, items, start, gg, bg,
+                               (double *)grid);
+        CK_LAUNCH(c);
+        return CONKER_OK;
+    }
     int threads = 256;
     int64_t want = (n + threads - 1) / threads;
     int blocks = (int)(want < 8192 ? want : 8192);
-    auto *no = reinterpret_cast<unsigned long long *>(n_out);
-    ProfScope ps(c, PK_SCATTER);
     if (dt == CONKER_F32)
         hipLaunchKernelGGL(k_scatter<float>, dim3(blocks), dim3(threads), 0, c->stream, pos, w, n, gg,
                            (float *)grid, wsum, no);

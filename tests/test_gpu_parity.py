@@ -91,6 +91,34 @@ def test_scatter_weighted_survey_cap(ck, ctx, dt, tol):
         assert nout.item() == ro == 0
 
 
+@pytest.mark.parametrize("dims", [(128, 128, 128), (72, 64, 64)])
+@pytest.mark.parametrize("dt,weighted,tol", [("f32", False, 0.0), ("f64", False, 0.0), ("f32", True, 2e-6),
+                                             ("f64", True, 1e-13)])
+def test_scatter_large_catalog(ck, ctx, dims, dt, weighted, tol):
+    """Five million clustered points: 128^3 takes the brick-binned mapping,
+    72 x 64 x 64 (not a whole number of bricks) the direct one.  The grid is
+    accumulated into (pre-filled with 0.5); unit weights must count exactly."""
+    n = 5_000_000
+    pos = synth.neyman_scott_box(n, 300, 2.0, -3.0, 130.0, seed=171)
+    pos[::100_003] = np.nan
+    w = synth.lognormal_weights(n, 0.2, seed=172) if weighted else None
+    grid = ck.Grid(dims, (0.0, 0.0, 0.0), 1.0)
+    _say("scatter large", dims, dt, weighted)
+    out = torch.full(dims, 0.5, dtype=TDT[dt], device=DEV)
+    wsum = torch.zeros(1, dtype=torch.float64, device=DEV)
+    nout = torch.zeros(1, dtype=torch.int64, device=DEV)
+    ctx.grid_assign(grid, _gpu(pos), _gpu(w) if weighted else None, out, wsum, nout)
+    ref, rs, ro = oc.histogram(pos, w, (0.0, 0.0, 0.0), 1.0, dims)
+    got = out.cpu().numpy().astype(np.float64) - 0.5
+    assert ro > 0 and nout.item() == ro
+    if weighted:
+        assert np.abs(got - ref).max() <= tol * ref.max()
+        assert math.isclose(wsum.item(), rs, rel_tol=1e-12)
+    else:
+        assert np.array_equal(got, ref)
+        assert wsum.item() == rs
+
+
 def test_scatter_rejects_outside_and_nonfinite(ck, ctx):
     dims, origin, cell = (32, 32, 32), (0.0, 0.0, 0.0), 1.0
     grid = ck.Grid(dims, origin, cell)

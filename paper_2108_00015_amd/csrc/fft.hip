@@ -177,7 +177,10 @@ __device__ __forceinline__ void fft_stage(cplx<T> *lds, const cplx<T> *tw, Op &o
             dft<R, DIR>(v[q]);
         }
     }
-    if constexpr (!FIRST) __syncthreads();
+    // in-place LDS stages wait for every read before any write; the last stage
+    // writes global memory from registers, and every caller puts a barrier
+    // between a tile's last stage and the next writes to the LDS tile
+    if constexpr (!FIRST && !LAST) __syncthreads();
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
         const int b = threadIdx.x + q * NT;

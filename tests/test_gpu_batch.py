@@ -192,3 +192,62 @@ def test_batch_fused_jobs_graph_replay():
         assert _rel(jobs[k].W_delta.cpu().numpy(), ref["W_delta"]) <= 1e-5
         assert _rel(jobs[k].W_rand.cpu().numpy(), ref["W_rand_raw"]) <= 1e-5
     ctx.close()
+
+
+def test_batch_axis_order_under_graph_capture():
+    """Fused jobs on a cubic 512^3 grid with cone-shaped support: the axis
+    order is chosen on the device inside the captured graph.  Replays match
+    the eager pass, and both match the same jobs in the given axis order (the
+    order only changes the summation order; float32 bar 1e-5)."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2108_00015_amd as ck
+    DEV = "cuda:0"
+    L = 512
+    radii = [2.0, 3.5, 5.0, 8.0, 11.0, 14.0, 17.0, 20.0]   # enough radii for the copies to pay
+    cats = []
+    for j in range(2):
+        rng = np.random.default_rng(900 + j)
+        # points in a cone along z: few z-slabs, most x- and y-slabs
+        m = 60_000 + 20_000 * j
+        z = rng.uniform(250.0, 330.0, size=m)
+        rr = 0.6 * z * np.sqrt(rng.uniform(0, 1, size=m))
+        ph = rng.uniform(0, 2 * np.pi, size=m)
+        pts = np.stack([256 + rr * np.cos(ph) * 0.6, 256 + rr * np.sin(ph) * 0.6, z], 1).astype(np.float32)
+        cats.append((pts[: m // 10], pts))
+    grid = ck.Grid((L, L, L), (0, 0, 0), 1.0)
+
+    def run(order):
+        s = torch.cuda.Stream()
+        ctx = ck.Context(0, stream=s)
+        ctx.set_tune(axis_order=order)
+        ks, _ = ctx.make_shell_kernels(grid, radii, torch.float32)
+        jobs = [ck.make_job(grid, ks, 3, "split_bf16", torch.from_numpy(d).to(DEV), torch.from_numpy(r).to(DEV))
+                for d, r in cats]
+        assert all(j.maps_N is None for j in jobs)
+        torch.cuda.synchronize()
+        ctx.batch_plan(jobs)
+        used = ctx.axis_order_used()
+        first = _outs(jobs)
+        ctx.batch_capture()
+        reps = []
+        for rep in range(3):
+            for j in jobs:
+                j.W_delta.fill_(5.0)
+                j.xi.fill_(0.0)
+            torch.cuda.synchronize()
+            ctx.batch_launch()
+            ctx.synchronize()
+            reps.append(_outs(jobs))
+        ctx.close()
+        return used, first, reps
+
+    used, first, reps = run(0)
+    assert used in (5, 6), used
+    for r in reps:
+        for k in range(len(cats)):
+            assert np.array_equal(r[k], first[k]), k        # the graph repeats the eager arithmetic
+    used1, given, _ = run(1)
+    assert used1 == 1
+    for k in range(len(cats)):
+        assert _rel(first[k], given[k]) <= 1e-5, (k, _rel(first[k], given[k]))

@@ -528,12 +528,13 @@ __global__ __launch_bounds__(V2_NT) void k_mm2(const float *__restrict__ F, cons
     constexpr int EB = (SPLIT || F16) ? 2 : 4;              // bytes per operand element
     extern __shared__ __align__(16) unsigned char smem[];
     const Group gr = groups[blockIdx.y];
-    // LDS: two staging buffers [ns + 3][V2_SROW] (maps, F, a row of ones, a row
-    // of zeros; rows padded against bank conflicts) and two operand buffers (A
-    // planes, then B planes), so that the next 64 cells load while these are
-    // summed and the next 16-cell operands build while these multiply
-    const int SZ = (ns + 3) * V2_SROW;
-    const int ROW_F = ns, ROW_ONE = ns + 1, ROW_ZERO = ns + 2;
+    // LDS: two staging buffers [2 ns + 3][V2_SROW] (maps, F, a constant row,
+    // a row of zeros, then the products P_a = F C_a; rows padded against bank
+    // conflicts) and two operand buffers (A planes, then B planes), so that the
+    // next 64 cells load while these are summed and the next 16-cell operands
+    // build while these multiply.
+    const int SZ = (2 * ns + 3) * V2_SROW;
+    const int ROW_F = ns, ROW_ONE = ns + 1, ROW_ZERO = ns + 2, ROW_P = ns + 3;
     float *stg0 = reinterpret_cast<float *>(smem);
     const int na = gr.nrt * 32, nb = gr.nct * 32;
     const size_t abytes = (size_t)NP * na * 16 * EB;
@@ -542,11 +543,11 @@ __global__ __launch_bounds__(V2_NT) void k_mm2(const float *__restrict__ F, cons
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int r = lane & 31, h = lane >> 5;
     // build units of this thread: unit u -> (item, half); items of A first, then B
-    // Each unit builds v = S[r0] * S[r1] * S[r2] over 8 cells from three staged
-    // rows (a map or zeros; a map or ones; F or ones), with no branches, and
-    // stores it at operand offset uoff (-1: no such unit).
+    // Each unit builds v = S[r0] * S[r1] over 8 cells from two staged rows
+    // (P_a, a map or zeros; a map or ones), with no branches, and stores it at
+    // operand offset uoff (-1: no such unit).
     const int a_units = na * 2;   // operand offsets below this are rows of A, the rest of B
-    int urow[V2_MAXU][3];
+    int urow[V2_MAXU][2];
     int uoff[V2_MAXU];
     int uexp[V2_MAXU];   // split-fp16 operand scale exponents
 #pragma unroll
@@ -558,9 +559,8 @@ __global__ __launch_bounds__(V2_NT) void k_mm2(const float *__restrict__ F, cons
         else if (item < na + nb) it = citems[gr.ct0 * 32 + (item - na)];
         else it = int2{-3, -1};
         const bool isA = item < na;
-        urow[k][0] = it.x >= 0 ? it.x : ROW_ZERO;
+        urow[k][0] = it.x >= 0 ? (isA ? ROW_P + it.x : it.x) : ROW_ZERO;
         urow[k][1] = (it.x >= 0 && it.y >= 0) ? it.y : ROW_ONE;
-        urow[k][2] = (it.x >= 0 && isA) ? ROW_F : ROW_ONE;
         uoff[k] = it.x == -3 ? -1 : item * 2 + half;   // B rows follow the A rows
         uexp[k] = 0;
         if constexpr (F16) {
@@ -615,6 +615,16 @@ __global__ __launch_bounds__(V2_NT) void k_mm2(const float *__restrict__ F, cons
             if (e < nst) reinterpret_cast<float4 *>(dst + (e >> 4) * V2_SROW)[e & 15] = pre[k];
         }
     };
+    // rows P_a = F C_a of a staged buffer (after its maps and F are visible)
+    auto products = [&](float *buf) {
+        for (int e = threadIdx.x; e < ns * 16; e += V2_NT) {
+            const int a = e >> 4, q = e & 15;
+            const float4 c = reinterpret_cast<const float4 *>(buf + a * V2_SROW)[q];
+            const float4 f = reinterpret_cast<const float4 *>(buf + ROW_F * V2_SROW)[q];
+            reinterpret_cast<float4 *>(buf + (ROW_P + a) * V2_SROW)[q] =
+                float4{f.x * c.x, f.y * c.y, f.z * c.z, f.w * c.w};
+        }
+    };
     if (c0 < c1) {
         fetch(c0);
         put(stg0);
@@ -624,6 +634,8 @@ __global__ __launch_bounds__(V2_NT) void k_mm2(const float *__restrict__ F, cons
     for (size_t x = c0; x < c1; x += 64) {
         const bool more = x + 64 < c1;
         if (more) fetch(x + 64);   // in flight while these 64 cells are summed
+        products(stg0 + sb * SZ);
+        __syncthreads();
         const float *sm_maps = stg0 + sb * SZ;
 #pragma unroll 1
         for (int sub = 0; sub < 4; ++sub) {
@@ -638,12 +650,9 @@ __global__ __launch_bounds__(V2_NT) void k_mm2(const float *__restrict__ F, cons
                 {
                     const float4 *p0 = reinterpret_cast<const float4 *>(sm_maps + urow[k][0] * V2_SROW + cb);
                     const float4 *p1 = reinterpret_cast<const float4 *>(sm_maps + urow[k][1] * V2_SROW + cb);
-                    const float4 *p2 = reinterpret_cast<const float4 *>(sm_maps + urow[k][2] * V2_SROW + cb);
-                    const float4 a0 = p0[0], a1 = p0[1], b0 = p1[0], b1 = p1[1], f0 = p2[0], f1 = p2[1];
-                    v[0] = a0.x * b0.x * f0.x; v[1] = a0.y * b0.y * f0.y;
-                    v[2] = a0.z * b0.z * f0.z; v[3] = a0.w * b0.w * f0.w;
-                    v[4] = a1.x * b1.x * f1.x; v[5] = a1.y * b1.y * f1.y;
-                    v[6] = a1.z * b1.z * f1.z; v[7] = a1.w * b1.w * f1.w;
+                    const float4 a0 = p0[0], a1 = p0[1], b0 = p1[0], b1 = p1[1];
+                    v[0] = a0.x * b0.x; v[1] = a0.y * b0.y; v[2] = a0.z * b0.z; v[3] = a0.w * b0.w;
+                    v[4] = a1.x * b1.x; v[5] = a1.y * b1.y; v[6] = a1.z * b1.z; v[7] = a1.w * b1.w;
                 }
                 const int o = uoff[k];
                 if (o < 0) continue;
@@ -917,7 +926,7 @@ int make_plan2(conker_ctx *c, int ns, int n, bool split, Plan2 &p2) {
         }
     }
     const int eb = split ? 6 : 4;   // LDS bytes per operand element over all planes
-    auto lds_of = [&](int nrt, int nct) { return 2 * (ns + 3) * V2_SROW * 4 + 2 * (nrt + nct) * TS * 16 * eb; };
+    auto lds_of = [&](int nrt, int nct) { return 2 * (2 * ns + 3) * V2_SROW * 4 + 2 * (nrt + nct) * TS * 16 * eb; };
     std::vector<Group> groups;
     int i = 0;
     p2.max_lds = 0;

@@ -57,7 +57,7 @@ constexpr int stage_ns() {   // product of radices before stage S
 //   TM_W: as TM_C with twice the columns (256-byte runs); the default for the
 //         x and y axes (a launch setting selects TM_C instead).
 //   TM_R: as TM_C with up to 1024 threads; used by the x pass that keeps its
-//         spectrum tile resident in LDS across a batch of radii.
+//         spectrum tile resident (in registers) across a batch of radii.
 enum TileMode { TM_J = 0, TM_C = 1, TM_W = 2, TM_R = 3 };
 
 template <typename T, int L, int MODE>
@@ -111,6 +111,13 @@ struct has_keep : std::false_type {};
 template <class Op>
 struct has_keep<Op, std::void_t<decltype(std::declval<const Op &>().flag(0))>> : std::true_type {};
 
+// Ops with load_r(q, r, i, c) supply the first stage's inputs from registers
+// indexed by the thread's butterfly q and point r (constants once unrolled).
+template <class Op, class = void>
+struct has_load_r : std::false_type {};
+template <class Op>
+struct has_load_r<Op, std::void_t<decltype(std::declval<const Op &>().load_r(0, 0, 0, 0))>> : std::true_type {};
+
 template <typename T, int L, int MODE, int DIR, int S, bool STAGED, class Op>
 __device__ __forceinline__ void fft_stage(cplx<T> *lds, const cplx<T> *tw, Op &op) {
     using C = cplx<T>;
@@ -162,7 +169,8 @@ __device__ __forceinline__ void fft_stage(cplx<T> *lds, const cplx<T> *tw, Op &o
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int i = j + r * LR;
-                if constexpr (FIRST) v[q][r] = op.load(i, c);
+                if constexpr (FIRST && has_load_r<Op>::value) v[q][r] = op.load_r(q, r, i, c);
+                else if constexpr (FIRST) v[q][r] = op.load(i, c);
                 else v[q][r] = lds[lds_addr<MODE, L, TC, PAD>(i, c)];
             }
             if constexpr (NSV > 1) {
@@ -531,23 +539,25 @@ struct OpExtract {
 
 // ---------------------------------------------------------------------------
 // x pass, inverse, with the kernel multiply, for a batch of radii, keeping the
-// spectrum tile resident in LDS: the tile (all kx of one ky and TC columns kz)
-// is read from HBM once per batch instead of once per radius.  For each radius
-// the kernel octant values of the tile's columns (one contiguous run per
-// column, x fastest) are staged into LDS with coalesced reads, prefetched into
-// registers while the previous radius is transformed.
+// spectrum tile resident: the tile (all kx of one ky and TC columns kz) is
+// read from HBM once per batch instead of once per radius, each thread
+// holding in registers the points its first-stage butterflies take (the same
+// for every radius).  For each radius the kernel octant values of the tile's
+// columns (one contiguous run per column, x fastest) are staged into LDS with
+// coalesced reads, prefetched into registers while the previous radius is
+// transformed.
 // ---------------------------------------------------------------------------
-template <typename T, int L, int TC>
+template <typename T, int L, int TC, int PER0>
 struct OpResident {
     static constexpr bool STAGED = false;
     using C = cplx<T>;
-    const C *st;    // LDS: spectrum tile [L][TC]
-    const T *kt;    // LDS: kernel values [TC][L/2 + 1]
-    C *out;         // global: output tile base
+    const C (*sreg)[8];   // registers: this thread's first-stage inputs [PER0][8]
+    const T *kt;          // LDS: kernel values [TC][L/2 + 1]
+    C *out;               // global: output tile base
     unsigned si;
     const unsigned char *xf;   // LDS: x-slab carries field (row written), or NULL: every row
-    __device__ C load(int i, int c) const {
-        const C s = st[i * TC + c];
+    __device__ C load_r(int q, int r, int i, int c) const {
+        const C s = sreg[q][r];
         const T k = kt[c * (L / 2 + 1) + (i <= L - i ? i : L - i)];
         return C{s.x * k, s.y * k};
     }
@@ -559,9 +569,10 @@ struct OpResident {
 template <typename T, int L>
 constexpr bool resident_fits() {
     using SH = Shape<T, L, TM_R>;
-    return (size_t)SH::LDS * sizeof(cplx<T>) + (size_t)L * sizeof(cplx<T>) +
-               (size_t)L * SH::TC * sizeof(cplx<T>) + (size_t)SH::TC * (L / 2 + 1) * sizeof(T) + (size_t)L <=
-           160 * 1024;
+    return Plan<L>::r[0] == 8 &&
+           (size_t)SH::LDS * sizeof(cplx<T>) + (size_t)L * sizeof(cplx<T>) +
+                   (size_t)SH::TC * (L / 2 + 1) * sizeof(T) + (size_t)L <=
+               160 * 1024;
 }
 
 template <typename T, int L>
@@ -574,7 +585,6 @@ __global__ __launch_bounds__((Shape<T, L, TM_R>::NT), (Shape<T, L, TM_R>::MINW))
     constexpr int KPT = (TC * NXH + NT - 1) / NT;   // kernel values staged per thread
     __shared__ C lds[SH::LDS];
     __shared__ C tw[L];
-    __shared__ C st[L * TC];
     __shared__ T kt[TC * NXH];
     __shared__ unsigned char xf[L];   // x-slabs carrying field (when xcount is given)
     // Tiles (ky, kz-block) and (ny - ky, kz-block) read the same kernel values.
@@ -596,9 +606,19 @@ __global__ __launch_bounds__((Shape<T, L, TM_R>::NT), (Shape<T, L, TM_R>::MINW))
         tw[t] = twg[t];
         if (xcount) xf[t] = xcount[t] > 0 ? 1 : 0;
     }
-    for (int e = threadIdx.x; e < L * TC; e += NT) {
-        const int i = e / TC, c = e - (e / TC) * TC;
-        st[e] = spec[g.base + (size_t)(unsigned)i * (unsigned)g.si + c];
+    // this thread's first-stage points (radix 8, butterflies q of the first stage)
+    constexpr int LR0 = L / 8, NB0 = LR0 * TC, PER0 = (NB0 + NT - 1) / NT;
+    C sreg[PER0][8];
+#pragma unroll
+    for (int q = 0; q < PER0; ++q) {
+        const int b = threadIdx.x + q * NT;
+        int j, c;
+        split_q<NT, TM_R, LR0, TC>(q, j, c);
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+            sreg[q][r] = (NB0 % NT == 0 || b < NB0)
+                             ? spec[g.base + (size_t)(unsigned)(j + r * LR0) * (unsigned)g.si + c]
+                             : C{};
     }
     const int oy = fold(g.p0, d.ny);
     const int nzh = d.nz / 2 + 1;
@@ -623,7 +643,8 @@ __global__ __launch_bounds__((Shape<T, L, TM_R>::NT), (Shape<T, L, TM_R>::MINW))
         }
         __syncthreads();
         if (m + 1 < nb) kload(m + 1, kv);
-        OpResident<T, L, TC> op{st, kt, tspec + (size_t)m * nc + g.base, (unsigned)g.si, xcount ? xf : nullptr};
+        OpResident<T, L, TC, PER0> op{sreg, kt, tspec + (size_t)m * nc + g.base, (unsigned)g.si,
+                                      xcount ? xf : nullptr};
         fft_line_tile<T, L, TM_R, +1, false>(lds, tw, op);
         __syncthreads();
     }
@@ -885,6 +906,7 @@ int inverse_batch_t(conker_ctx *ctx, const conker_grid *g, const void *spec, con
             case 128: st = go(std::integral_constant<int, 128>()); break;
             case 256: st = go(std::integral_constant<int, 256>()); break;
             case 512: st = go(std::integral_constant<int, 512>()); break;
+            case 1024: st = go(std::integral_constant<int, 1024>()); break;
             default: break;
         }
         CK_OK(st);

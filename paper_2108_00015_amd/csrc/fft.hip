@@ -118,11 +118,15 @@ struct has_load_r : std::false_type {};
 template <class Op>
 struct has_load_r<Op, std::void_t<decltype(std::declval<const Op &>().load_r(0, 0, 0, 0))>> : std::true_type {};
 
-template <typename T, int L, int MODE, int DIR, int S, bool STAGED, class Op>
-__device__ __forceinline__ void fft_stage(cplx<T> *lds, const cplx<T> *tw, Op &op) {
+// Stage S reads src (LDS; global memory or registers for the first stage) and
+// writes dst (LDS; global memory for the last stage).  SYNC: the stage places
+// its own barriers (src == dst, in place); otherwise the caller orders the
+// buffers.  PADX >= 0 overrides the tile's row padding.
+template <typename T, int L, int MODE, int DIR, int S, bool STAGED, bool SYNC = true, int PADX = -1, class Op>
+__device__ __forceinline__ void fft_stage(const cplx<T> *src, cplx<T> *dst, const cplx<T> *tw, Op &op) {
     using C = cplx<T>;
     using SH = Shape<T, L, MODE>;
-    constexpr int NT = SH::NT, TC = SH::TC, PAD = SH::PAD;
+    constexpr int NT = SH::NT, TC = SH::TC, PAD = PADX >= 0 ? PADX : SH::PAD;
     constexpr int R = Plan<L>::r[S];
     constexpr int NSV = stage_ns<L, S>();
     constexpr bool FIRST = (S == 0) && !STAGED;   // first stage reads global memory
@@ -171,7 +175,7 @@ __device__ __forceinline__ void fft_stage(cplx<T> *lds, const cplx<T> *tw, Op &o
                 const int i = j + r * LR;
                 if constexpr (FIRST && has_load_r<Op>::value) v[q][r] = op.load_r(q, r, i, c);
                 else if constexpr (FIRST) v[q][r] = op.load(i, c);
-                else v[q][r] = lds[lds_addr<MODE, L, TC, PAD>(i, c)];
+                else v[q][r] = src[lds_addr<MODE, L, TC, PAD>(i, c)];
             }
             if constexpr (NSV > 1) {
                 const int k = j & (NSV - 1);
@@ -188,7 +192,7 @@ __device__ __forceinline__ void fft_stage(cplx<T> *lds, const cplx<T> *tw, Op &o
     // in-place LDS stages wait for every read before any write; the last stage
     // writes global memory from registers, and every caller puts a barrier
     // between a tile's last stage and the next writes to the LDS tile
-    if constexpr (!FIRST && !LAST) __syncthreads();
+    if constexpr (SYNC && !FIRST && !LAST) __syncthreads();
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
         const int b = threadIdx.x + q * NT;
@@ -205,12 +209,12 @@ __device__ __forceinline__ void fft_stage(cplx<T> *lds, const cplx<T> *tw, Op &o
                 } else if constexpr (LAST) {
                     op.store(o, c, v[q][r]);
                 } else {
-                    lds[lds_addr<MODE, L, TC, PAD>(o, c)] = v[q][r];
+                    dst[lds_addr<MODE, L, TC, PAD>(o, c)] = v[q][r];
                 }
             }
         }
     }
-    if constexpr (!LAST) __syncthreads();
+    if constexpr (SYNC && !LAST) __syncthreads();
 }
 
 // STAGED: the tile is first copied into LDS with a plain row loop (one load in
@@ -227,10 +231,10 @@ __device__ __forceinline__ void fft_line_tile(cplx<T> *lds, const cplx<T> *tw, O
         for (int i = threadIdx.x / TC; i < L; i += NT / TC) lds[lds_addr<MODE, L, TC, PAD>(i, c)] = op.load(i, c);
         __syncthreads();
     }
-    fft_stage<T, L, MODE, DIR, 0, ST>(lds, tw, op);
-    if constexpr (Plan<L>::n > 1) fft_stage<T, L, MODE, DIR, 1, ST>(lds, tw, op);
-    if constexpr (Plan<L>::n > 2) fft_stage<T, L, MODE, DIR, 2, ST>(lds, tw, op);
-    if constexpr (Plan<L>::n > 3) fft_stage<T, L, MODE, DIR, 3, ST>(lds, tw, op);
+    fft_stage<T, L, MODE, DIR, 0, ST>(lds, lds, tw, op);
+    if constexpr (Plan<L>::n > 1) fft_stage<T, L, MODE, DIR, 1, ST>(lds, lds, tw, op);
+    if constexpr (Plan<L>::n > 2) fft_stage<T, L, MODE, DIR, 2, ST>(lds, lds, tw, op);
+    if constexpr (Plan<L>::n > 3) fft_stage<T, L, MODE, DIR, 3, ST>(lds, lds, tw, op);
 }
 
 // Ops with an active() member may skip a whole tile (same answer for every
@@ -575,6 +579,18 @@ constexpr bool resident_fits() {
                160 * 1024;
 }
 
+// Two exchange buffers (rows padded by one value) in place of one: the three
+// stages of a line then alternate buffers and need one barrier each between
+// them, two per radius instead of five.
+template <typename T, int L>
+constexpr bool pingpong_fits() {
+    using SH = Shape<T, L, TM_R>;
+    return Plan<L>::n == 3 &&
+           2 * (size_t)L * (SH::TC + 1) * sizeof(cplx<T>) + (size_t)L * sizeof(cplx<T>) +
+                   (size_t)SH::TC * (L / 2 + 1) * sizeof(T) + (size_t)L <=
+               160 * 1024;
+}
+
 template <typename T, int L>
 __global__ __launch_bounds__((Shape<T, L, TM_R>::NT), (Shape<T, L, TM_R>::MINW)) void k_xmul_resident(
     const cplx<T> *__restrict__ spec, const T *__restrict__ kspec, cplx<T> *__restrict__ tspec,
@@ -583,7 +599,9 @@ __global__ __launch_bounds__((Shape<T, L, TM_R>::NT), (Shape<T, L, TM_R>::MINW))
     using SH = Shape<T, L, TM_R>;
     constexpr int TC = SH::TC, NT = SH::NT, NXH = L / 2 + 1;
     constexpr int KPT = (TC * NXH + NT - 1) / NT;   // kernel values staged per thread
-    __shared__ C lds[SH::LDS];
+    constexpr bool PP = pingpong_fits<T, L>();
+    constexpr int PADR = PP ? 1 : SH::PAD, LDSN = L * (TC + PADR);
+    __shared__ C lds[PP ? 2 * LDSN : LDSN];
     __shared__ C tw[L];
     __shared__ T kt[TC * NXH];
     __shared__ unsigned char xf[L];   // x-slabs carrying field (when xcount is given)
@@ -633,20 +651,50 @@ __global__ __launch_bounds__((Shape<T, L, TM_R>::NT), (Shape<T, L, TM_R>::MINW))
             }
         }
     };
-    T kv[KPT];
-    kload(0, kv);
-    for (int m = 0; m < nb; ++m) {
+    auto kstage = [&](const T (&kv)[KPT]) {
 #pragma unroll
         for (int q = 0; q < KPT; ++q) {
             const int e = threadIdx.x + q * NT;
             if (e < TC * NXH) kt[e] = kv[q];
         }
+    };
+    T kv[KPT];
+    kload(0, kv);
+    if constexpr (PP) {
+        // Stage 0 writes buffer A, stage 1 reads A and writes B, stage 2 reads
+        // B.  Each write follows the last read of the same buffer across a
+        // barrier: A's reads end before the barrier after stage 1, B's before
+        // the barrier after the next radius's stage 0.  The kernel values of
+        // radius m + 1 are written during stage 1 of radius m, after every
+        // stage-0 read of radius m's values and before the barrier that
+        // precedes their first read.
+        kstage(kv);
+        if (nb > 1) kload(1, kv);
         __syncthreads();
-        if (m + 1 < nb) kload(m + 1, kv);
-        OpResident<T, L, TC, PER0> op{sreg, kt, tspec + (size_t)m * nc + g.base, (unsigned)g.si,
-                                      xcount ? xf : nullptr};
-        fft_line_tile<T, L, TM_R, +1, false>(lds, tw, op);
-        __syncthreads();
+        C *const la = lds, *const lb = lds + LDSN;
+        for (int m = 0; m < nb; ++m) {
+            OpResident<T, L, TC, PER0> op{sreg, kt, tspec + (size_t)m * nc + g.base, (unsigned)g.si,
+                                          xcount ? xf : nullptr};
+            fft_stage<T, L, TM_R, +1, 0, false, false, PADR>(la, la, tw, op);
+            __syncthreads();
+            fft_stage<T, L, TM_R, +1, 1, false, false, PADR>(la, lb, tw, op);
+            if (m + 1 < nb) {
+                kstage(kv);
+                if (m + 2 < nb) kload(m + 2, kv);
+            }
+            __syncthreads();
+            fft_stage<T, L, TM_R, +1, 2, false, false, PADR>(lb, lb, tw, op);
+        }
+    } else {
+        for (int m = 0; m < nb; ++m) {
+            kstage(kv);
+            __syncthreads();
+            if (m + 1 < nb) kload(m + 1, kv);
+            OpResident<T, L, TC, PER0> op{sreg, kt, tspec + (size_t)m * nc + g.base, (unsigned)g.si,
+                                          xcount ? xf : nullptr};
+            fft_line_tile<T, L, TM_R, +1, false>(lds, tw, op);
+            __syncthreads();
+        }
     }
 }
 

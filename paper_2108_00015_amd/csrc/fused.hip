@@ -96,6 +96,9 @@ __global__ __launch_bounds__(NT, 1) void k_zinv_contract(const float2 *__restric
     __shared__ __align__(16) float Mf[2 * MAXR * MROW];
     __shared__ float2 S[NW * NZ];
     __shared__ float2 tw[NZ];
+    __shared__ unsigned long long zb[2][NW];   // per field and 64-cell block: bit c set iff F(c) != 0
+    __shared__ unsigned char clist[NW][8];     // per wave: the line's non-empty 16-cell chunks it sums
+    static_assert(NT == NZ, "one cell of the line per thread");
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int r = lane & 31, h = lane >> 5;
     // contraction split: waves 0..3 sum field a, waves 4..7 field b, 128 cells each
@@ -127,6 +130,9 @@ __global__ __launch_bounds__(NT, 1) void k_zinv_contract(const float2 *__restric
 
     for (int idx = blockIdx.x; idx < nact; idx += gridDim.x) {
         const size_t base = (size_t)line_of(idx) * NZ;
+        // this line's F, one cell per thread, for the chunk lists below
+        const float fza = Fa[base + threadIdx.x];
+        const float fzb = Fb ? Fb[base + threadIdx.x] : 0.f;
         // ---- inverse z transform of every radius of this line --------------
         for (int m = w; m < ns; m += NW) {
             float2 v[8];
@@ -174,12 +180,31 @@ __global__ __launch_bounds__(NT, 1) void k_zinv_contract(const float2 *__restric
             }
             wave_sync();
         }
+        {   // cells outside the survey (F = 0 of either sign) add exactly nothing
+            const unsigned long long ba = __ballot((__float_as_uint(fza) << 1) != 0);
+            const unsigned long long bb = __ballot((__float_as_uint(fzb) << 1) != 0);
+            if (lane == 0) {
+                zb[0][w] = ba;
+                zb[1][w] = bb;
+            }
+        }
         __syncthreads();
-        // ---- contraction of this wave's 128 cells of its field ---------------
+        // ---- contraction: the non-empty 16-cell chunks of this wave's field,
+        // dealt round-robin to the field's four waves -------------------------
         if (active) {
+            int nq;
+            {
+                const int k = lane & 31;   // chunk k: cells 16k .. 16k + 15
+                const bool on = lane < 32 && ((zb[fld][k >> 2] >> ((k & 3) * 16)) & 0xffffull) != 0;
+                const unsigned mk = (unsigned)__ballot(on);
+                const int pos = __popc(mk & ((1u << k) - 1u)), cnt = __popc(mk);
+                if (on && (pos & 3) == part) clist[w][pos >> 2] = (unsigned char)k;
+                nq = cnt > part ? (cnt - part + 3) >> 2 : 0;
+                wave_sync();
+            }
 #pragma unroll 2
-            for (int q = 0; q < 8; ++q) {
-                const int c0 = part * 128 + q * 16 + 8 * h;
+            for (int j = 0; j < nq; ++j) {
+                const int c0 = (int)clist[w][j] * 16 + 8 * h;
                 float x[8], f[8], p[8];
                 {
                     const float4 *mp = reinterpret_cast<const float4 *>(Mrow + c0);

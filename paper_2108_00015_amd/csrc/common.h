@@ -40,6 +40,7 @@ struct conker_ctx {
     conker::Buf cosmo;      // comoving-distance table of the survey front end
     conker::Buf order;      // support projections, chosen axis order and permuted fields
     conker::Buf bins;       // binned mapping: per-brick counts and starts, per-workgroup histograms, placed points
+    conker::Buf blocks;     // summation: list of the 64-cell blocks where the field is non-zero
     int order_last = 0;             // axis order of the last map-free summation (1..6), -1: on the device
     const int *order_dev = nullptr; // with order_last -1: the chosen permutation index (0..5)
     std::map<uint64_t, conker::Buf> tables;  // item / tuple tables, keyed by (n_radii, n, prec)
@@ -89,6 +90,7 @@ enum ProfKind {
     PK_SPECTRAL,
     PK_SURVEY,
     PK_ORDER,
+    PK_BLOCKS,
     PK_COUNT
 };
 
@@ -204,6 +206,11 @@ int fft_inverse_batch(conker_ctx *ctx, const conker_grid *g, bool f64,
 int fft_inverse_z_diag(conker_ctx *ctx, const conker_grid *g, bool f64, const void *tspec, int nb,
                        const void *fa, const void *fb, int pmax, int blocks, void *part,
                        const unsigned char *mask = nullptr);
+
+// Device list of the 64-cell blocks (cells 64 k .. 64 k + 63) holding a cell
+// where F != 0, ascending (blocks.hip): *list = int[*count], both in device
+// memory in the context's workspace, valid until the next call.  nc % 16 == 0.
+int block_list(conker_ctx *c, const void *F, bool f64, size_t nc, const int **list, const int **count);
 
 // Axis order of map-free summations (order.hip): with the context's
 // axis_order setting (0 auto, 1 as given, 2..6 a fixed permutation) and a

@@ -10,7 +10,9 @@
 // and every tuple is one entry of M: (a, b) for n = 3, ((a, b), c) for n = 4,
 // ((a, b), (c, d)) for n = 5.  M is computed in output tiles on the matrix
 // cores; each lane builds its operand values on the fly from the maps, so no
-// item product is ever stored.  Cells are split across workgroups; each
+// item product is ever stored.  Only the 64-cell blocks where F is non-zero
+// are summed (the others add exactly nothing), from a list in ascending block
+// order split evenly across workgroups (blocks.hip); each
 // workgroup writes float64 partial tiles that a second kernel sums in a fixed
 // order, and a third gathers the tuple entries.
 //
@@ -46,6 +48,23 @@ struct Items {
     int a, b, c, d;
 };
 
+// The 64-cell blocks of one workgroup: an equal share (one of gridDim.x) of
+// list[0 .. *count) -- the blocks where F is non-zero, in ascending order --
+// when a list is given, else of all blocks in order.  Block k starts at cell
+// first(k); the last block of the grid may be partial (nc % 16 == 0).
+struct Blocks {
+    const int *list;
+    int k0, k1;
+    __device__ size_t first(int k) const { return (size_t)(list ? list[k] : k) * 64; }
+};
+
+__device__ __forceinline__ Blocks my_blocks(const int *list, const int *count, size_t nc) {
+    const long n = list ? (long)*count : (long)((nc + 63) / 64);
+    const long per = (n + (long)gridDim.x - 1) / (long)gridDim.x;
+    const long k0 = (long)blockIdx.x * per;
+    return Blocks{list, (int)(k0 < n ? k0 : n), (int)(k0 + per < n ? k0 + per : n)};
+}
+
 // V consecutive values starting at a 16-byte aligned address, as 16-byte loads
 template <typename T, int V>
 __device__ __forceinline__ void ld(const T *__restrict__ p, T (&v)[V]) {
@@ -75,15 +94,17 @@ __device__ __forceinline__ void ld(const T *__restrict__ p, T (&v)[V]) {
 // ---------------------------------------------------------------------------
 template <typename T, int NS>
 __global__ __launch_bounds__(NT) void k_dot(const T *__restrict__ F, const T *__restrict__ maps,
-                                            size_t nc, int n_radii, size_t chunk,
-                                            double *__restrict__ partial) {
+                                            size_t nc, int n_radii, const int *__restrict__ list,
+                                            const int *__restrict__ count, double *__restrict__ partial) {
     constexpr int V = std::is_same<T, float>::value ? 4 : 2;   // cells per 16-byte load
+    constexpr int TPB = 64 / V;                                  // threads per block
     double acc[NS];
 #pragma unroll
     for (int a = 0; a < NS; ++a) acc[a] = 0.0;
-    const size_t c0 = (size_t)blockIdx.x * chunk;
-    const size_t c1 = std::min(c0 + chunk, nc);
-    for (size_t x = c0 + (size_t)threadIdx.x * V; x < c1; x += (size_t)NT * V) {
+    const Blocks bk = my_blocks(list, count, nc);
+    for (int k = bk.k0 + (int)threadIdx.x / TPB; k < bk.k1; k += NT / TPB) {
+        const size_t x = bk.first(k) + (size_t)(threadIdx.x % TPB) * V;
+        if (x >= nc) continue;
         T f[V];
         ld<T, V>(F + x, f);
 #pragma unroll
@@ -154,9 +175,10 @@ __device__ __forceinline__ void item_vals(const T *__restrict__ maps, size_t nc,
 }
 
 // ---------------------------------------------------------------------------
-// matrix-core kernels.  Grid: (cell chunks, tile groups).  Each workgroup of
-// four waves handles one cell chunk for NBW output tiles; the waves split the
-// chunk, then combine their float64 tiles through LDS.
+// matrix-core kernels.  Grid: (workgroups, tile groups).  Each workgroup of
+// four waves handles its share of the summed 64-cell blocks for NBW output
+// tiles; the waves split each block, then combine their float64 tiles through
+// LDS.
 // ---------------------------------------------------------------------------
 template <int TS>
 __device__ void wave_combine_store(double (&acc)[TS * TS / 64], double *lds, double *out) {
@@ -188,7 +210,8 @@ __device__ void wave_combine_store(double (&acc)[TS * TS / 64], double *lds, dou
 // float64: 16x16 tiles, each lane feeds row (lane % 16) with the cell of k-slot lane / 16
 template <int NBW>
 __global__ __launch_bounds__(NT) void k_mm_f64(const double *__restrict__ F, const double *__restrict__ maps,
-                                               size_t nc, size_t chunk, const Items *__restrict__ tab,
+                                               size_t nc, const int *__restrict__ list,
+                                               const int *__restrict__ count, const Items *__restrict__ tab,
                                                int n_tiles, double *__restrict__ partial) {
     constexpr int TS = 16, CPI = 8;   // 4 k-slots x 2 cells per iteration
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -205,9 +228,11 @@ __global__ __launch_bounds__(NT) void k_mm_f64(const double *__restrict__ F, con
     doublex4 acc[NBW];
 #pragma unroll
     for (int s = 0; s < NBW; ++s) acc[s] = doublex4{0, 0, 0, 0};
-    const size_t c0 = (size_t)blockIdx.x * chunk;
-    const size_t c1 = std::min(c0 + chunk, nc);
-    for (size_t x0 = c0 + (size_t)w * CPI; x0 < c1; x0 += (size_t)WAVES * CPI) {
+    const Blocks bk = my_blocks(list, count, nc);
+    size_t xb = bk.k0 < bk.k1 ? bk.first(bk.k0) : 0;
+    for (int k = bk.k0; k < bk.k1; ++k) {
+    const size_t xn = k + 1 < bk.k1 ? bk.first(k + 1) : 0, xe = std::min(xb + 64, nc);
+    for (size_t x0 = xb + (size_t)w * CPI; x0 < xe; x0 += (size_t)WAVES * CPI) {
         const size_t x = x0 + 2 * h;
         double fv[2];
         ld<double, 2>(F + x, fv);
@@ -223,6 +248,8 @@ __global__ __launch_bounds__(NT) void k_mm_f64(const double *__restrict__ F, con
             acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[1] * f1, bv[1], acc[s], 0, 0, 0);
         }
     }
+    xb = xn;
+    }
     __shared__ double lds[WAVES * 4 * 64];
     const int G = gridDim.x;
 #pragma unroll
@@ -237,7 +264,8 @@ __global__ __launch_bounds__(NT) void k_mm_f64(const double *__restrict__ F, con
 // float32: 32x32 tiles, v_mfma_f32_32x32x2_f32, lane feeds row lane % 32 in k-slot lane / 32
 template <int NBW>
 __global__ __launch_bounds__(NT) void k_mm_f32(const float *__restrict__ F, const float *__restrict__ maps,
-                                               size_t nc, size_t chunk, const Items *__restrict__ tab,
+                                               size_t nc, const int *__restrict__ list,
+                                               const int *__restrict__ count, const Items *__restrict__ tab,
                                                int n_tiles, double *__restrict__ partial) {
     constexpr int TS = 32, CPI = 8, FLUSH = 16;   // 2 k-slots x 4 cells per iteration
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -259,10 +287,12 @@ __global__ __launch_bounds__(NT) void k_mm_f32(const float *__restrict__ F, cons
 #pragma unroll
         for (int v = 0; v < 16; ++v) accd[s][v] = 0.0;
     }
-    const size_t c0 = (size_t)blockIdx.x * chunk;
-    const size_t c1 = std::min(c0 + chunk, nc);
+    const Blocks bk = my_blocks(list, count, nc);
+    size_t xb = bk.k0 < bk.k1 ? bk.first(bk.k0) : 0;
     int cnt = 0;
-    for (size_t x0 = c0 + (size_t)w * CPI; x0 < c1; x0 += (size_t)WAVES * CPI) {
+    for (int k = bk.k0; k < bk.k1; ++k) {
+    const size_t xn = k + 1 < bk.k1 ? bk.first(k + 1) : 0, xe = std::min(xb + 64, nc);
+    for (size_t x0 = xb + (size_t)w * CPI; x0 < xe; x0 += (size_t)WAVES * CPI) {
         const size_t x = x0 + 4 * h;
         float f[4];
         ld<float, 4>(F + x, f);
@@ -290,6 +320,8 @@ __global__ __launch_bounds__(NT) void k_mm_f32(const float *__restrict__ F, cons
                 acc[s] = floatx16{0};
             }
         }
+    }
+    xb = xn;
     }
     __shared__ double lds[WAVES * 16 * 64];
     const int G = gridDim.x;
@@ -348,17 +380,20 @@ __device__ __forceinline__ void split2h(const float (&v)[8], f16x8 &hi, f16x8 &l
     }
 }
 
-// max |x| of every map row and of F, as float bits (non-negative floats order
-// like their bit patterns): grid (blocks, ns + 1).
+// max |x| of every map row and of F over the summed blocks (the cells that
+// enter any sum), as float bits (non-negative floats order like their bit
+// patterns): grid (workgroups, ns + 1).
 __global__ __launch_bounds__(256) void k_absmax(const float *__restrict__ F, const float *__restrict__ maps,
-                                                size_t nc, int ns, size_t chunk, unsigned *__restrict__ out) {
+                                                size_t nc, int ns, const int *__restrict__ list,
+                                                const int *__restrict__ count, unsigned *__restrict__ out) {
     __shared__ float red[4];
     const int row = blockIdx.y;
     const float *src = row < ns ? maps + (size_t)row * nc : F;
-    const size_t c0 = (size_t)blockIdx.x * chunk;
-    const size_t c1 = c0 + chunk < nc ? c0 + chunk : nc;
+    const Blocks bk = my_blocks(list, count, nc);
     float m = 0.f;
-    for (size_t i = c0 + (size_t)threadIdx.x * 4; i < c1; i += 256 * 4) {
+    for (int k = bk.k0 + (int)threadIdx.x / 16; k < bk.k1; k += 256 / 16) {
+        const size_t i = bk.first(k) + (size_t)(threadIdx.x & 15) * 4;
+        if (i >= nc) continue;
         const float4 v = *reinterpret_cast<const float4 *>(src + i);
         m = fmaxf(m, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
     }
@@ -392,7 +427,8 @@ __device__ __forceinline__ int items_exp(const unsigned *maxabs, int ns, int a, 
 // row lane % 32 with the 8 cells of k-slot lane / 32
 template <int NBW, int PREC>
 __global__ __launch_bounds__(NT) void k_mm_split(const float *__restrict__ F, const float *__restrict__ maps,
-                                                 size_t nc, size_t chunk, const Items *__restrict__ tab,
+                                                 size_t nc, const int *__restrict__ list,
+                                                 const int *__restrict__ count, const Items *__restrict__ tab,
                                                  int n_tiles, double *__restrict__ partial, int ns,
                                                  const unsigned *__restrict__ maxabs) {
     constexpr bool F16 = PREC == CONKER_MM_SPLIT_F16;
@@ -422,10 +458,12 @@ __global__ __launch_bounds__(NT) void k_mm_split(const float *__restrict__ F, co
 #pragma unroll
         for (int v = 0; v < 16; ++v) accd[s][v] = 0.0;
     }
-    const size_t c0 = (size_t)blockIdx.x * chunk;
-    const size_t c1 = std::min(c0 + chunk, nc);
+    const Blocks bk = my_blocks(list, count, nc);
+    size_t xb = bk.k0 < bk.k1 ? bk.first(bk.k0) : 0;
     int cnt = 0;
-    for (size_t x0 = c0 + (size_t)w * CPI; x0 < c1; x0 += (size_t)WAVES * CPI) {
+    for (int k = bk.k0; k < bk.k1; ++k) {
+    const size_t xn = k + 1 < bk.k1 ? bk.first(k + 1) : 0, xe = std::min(xb + 64, nc);
+    for (size_t x0 = xb + (size_t)w * CPI; x0 < xe; x0 += (size_t)WAVES * CPI) {
         const size_t x = x0 + 8 * h;
         float f[8];
         ld<float, 8>(F + x, f);
@@ -476,6 +514,8 @@ __global__ __launch_bounds__(NT) void k_mm_split(const float *__restrict__ F, co
             }
         }
     }
+    xb = xn;
+    }
     __shared__ double lds[WAVES * 16 * 64];
     const int G = gridDim.x;
 #pragma unroll
@@ -498,7 +538,7 @@ __global__ __launch_bounds__(NT) void k_mm_split(const float *__restrict__ F, co
 
 // ---------------------------------------------------------------------------
 // float32 / split-bf16 matrix-core summation with operands built once per
-// chunk.  A workgroup owns a chunk of cells and a group of up to 16 output
+// chunk.  A workgroup owns a share of the summed 64-cell blocks and a group of up to 16 output
 // tiles (a rectangle of row tiles x column tiles).  For every 64 cells it
 // stages the maps and F in LDS; for every 16 of those it builds each row item
 // (F C_a [C_b]) and column item (C_c [C_d]) of its rectangle once, as three
@@ -518,7 +558,8 @@ constexpr int V2_SROW = 68;                     // staged row stride (floats): 6
 
 template <int PREC>
 __global__ __launch_bounds__(V2_NT) void k_mm2(const float *__restrict__ F, const float *__restrict__ maps, size_t nc,
-                                              int ns, size_t chunk, const int2 *__restrict__ ritems,
+                                              int ns, const int *__restrict__ list, const int *__restrict__ count,
+                                              const int2 *__restrict__ ritems,
                                               const int2 *__restrict__ citems, const int2 *__restrict__ tiles,
                                               const Group *__restrict__ groups, int G, double *__restrict__ partial,
                                               const unsigned *__restrict__ maxabs) {
@@ -586,8 +627,7 @@ __global__ __launch_bounds__(V2_NT) void k_mm2(const float *__restrict__ F, cons
 #pragma unroll
         for (int v = 0; v < 16; ++v) dacc[k][v] = 0.0;
     }
-    const size_t c0 = (size_t)blockIdx.x * chunk;
-    const size_t c1 = c0 + chunk < nc ? c0 + chunk : nc;
+    const Blocks bk = my_blocks(list, count, nc);
     // constant rows of both staging buffers
     for (int e = threadIdx.x; e < 2 * 64; e += V2_NT) {
         const int b = e >> 6, c = e & 63;
@@ -625,15 +665,15 @@ __global__ __launch_bounds__(V2_NT) void k_mm2(const float *__restrict__ F, cons
                 float4{f.x * c.x, f.y * c.y, f.z * c.z, f.w * c.w};
         }
     };
-    if (c0 < c1) {
-        fetch(c0);
+    if (bk.k0 < bk.k1) {
+        fetch(bk.first(bk.k0));
         put(stg0);
     }
     __syncthreads();
     int since = 0, sb = 0, ob = 0;
-    for (size_t x = c0; x < c1; x += 64) {
-        const bool more = x + 64 < c1;
-        if (more) fetch(x + 64);   // in flight while these 64 cells are summed
+    for (int k = bk.k0; k < bk.k1; ++k) {
+        const bool more = k + 1 < bk.k1;
+        if (more) fetch(bk.first(k + 1));   // in flight while these 64 cells are summed
         products(stg0 + sb * SZ);
         __syncthreads();
         const float *sm_maps = stg0 + sb * SZ;
@@ -973,22 +1013,19 @@ int make_plan2(conker_ctx *c, int ns, int n, bool split, Plan2 &p2) {
 }
 
 template <typename T>
-int contract_dot(conker_ctx *c, const T *F, const T *maps, size_t nc, int ns, double *W) {
-    constexpr int V = std::is_same<T, float>::value ? 4 : 2;
-    int G = (int)std::min<size_t>(2048, std::max<size_t>(1, nc / 4096));
-    size_t chunk = (nc + G - 1) / G;
-    chunk = (chunk + NT * V - 1) / (NT * V) * (NT * V);
-    G = (int)((nc + chunk - 1) / chunk);
+int contract_dot(conker_ctx *c, const T *F, const T *maps, size_t nc, int ns, const int *list, const int *count,
+                 double *W) {
+    const int G = (int)std::min<size_t>(2048, std::max<size_t>(1, nc / 4096));
     CK_OK(ws_reserve(c, c->partial, (size_t)G * ns * sizeof(double)));
     double *part = (double *)c->partial.p;
     {
     ProfScope ps(c, PK_CONTRACT_DOT);
     if (ns <= 16)
-        hipLaunchKernelGGL((k_dot<T, 16>), dim3(G), dim3(NT), 0, c->stream, F, maps, nc, ns, chunk, part);
+        hipLaunchKernelGGL((k_dot<T, 16>), dim3(G), dim3(NT), 0, c->stream, F, maps, nc, ns, list, count, part);
     else if (ns <= 32)
-        hipLaunchKernelGGL((k_dot<T, 32>), dim3(G), dim3(NT), 0, c->stream, F, maps, nc, ns, chunk, part);
+        hipLaunchKernelGGL((k_dot<T, 32>), dim3(G), dim3(NT), 0, c->stream, F, maps, nc, ns, list, count, part);
     else
-        hipLaunchKernelGGL((k_dot<T, 64>), dim3(G), dim3(NT), 0, c->stream, F, maps, nc, ns, chunk, part);
+        hipLaunchKernelGGL((k_dot<T, 64>), dim3(G), dim3(NT), 0, c->stream, F, maps, nc, ns, list, count, part);
     CK_LAUNCH(c);
     }
     ProfScope ps(c, PK_CONTRACT_REDUCE);
@@ -999,19 +1036,20 @@ int contract_dot(conker_ctx *c, const T *F, const T *maps, size_t nc, int ns, do
 
 template <int NBW>
 int launch_mm(conker_ctx *c, conker_mmprec prec, dim3 grid, const void *F, const void *maps, size_t nc,
-              size_t chunk, const Items *tab, int n_tiles, double *part, int ns, const unsigned *maxabs) {
+              const int *list, const int *count, const Items *tab, int n_tiles, double *part, int ns,
+              const unsigned *maxabs) {
     if (prec == CONKER_MM_F64)
         hipLaunchKernelGGL((k_mm_f64<NBW>), grid, dim3(NT), 0, c->stream, (const double *)F,
-                           (const double *)maps, nc, chunk, tab, n_tiles, part);
+                           (const double *)maps, nc, list, count, tab, n_tiles, part);
     else if (prec == CONKER_MM_F32)
         hipLaunchKernelGGL((k_mm_f32<NBW>), grid, dim3(NT), 0, c->stream, (const float *)F,
-                           (const float *)maps, nc, chunk, tab, n_tiles, part);
+                           (const float *)maps, nc, list, count, tab, n_tiles, part);
     else if (prec == CONKER_MM_SPLIT_F16)
         hipLaunchKernelGGL((k_mm_split<NBW, CONKER_MM_SPLIT_F16>), grid, dim3(NT), 0, c->stream, (const float *)F,
-                           (const float *)maps, nc, chunk, tab, n_tiles, part, ns, maxabs);
+                           (const float *)maps, nc, list, count, tab, n_tiles, part, ns, maxabs);
     else
         hipLaunchKernelGGL((k_mm_split<NBW, CONKER_MM_SPLIT_BF16>), grid, dim3(NT), 0, c->stream,
-                           (const float *)F, (const float *)maps, nc, chunk, tab, n_tiles, part, ns,
+                           (const float *)F, (const float *)maps, nc, list, count, tab, n_tiles, part, ns,
                            (const unsigned *)nullptr);
     CK_LAUNCH(c);
     return CONKER_OK;
@@ -1036,9 +1074,13 @@ extern "C" int conker_contract_npt(conker_ctx *c, const conker_grid *g, conker_d
     const size_t nc = ncells(g);
     if (nc % 16) return fail(c, CONKER_EUNSUPPORTED, "cell count must be a multiple of 16");
     CK_HIP(c, hipSetDevice(c->device));
+    // only the 64-cell blocks holding a non-zero F are summed
+    const int *blist = nullptr, *bcount = nullptr;
+    CK_OK(block_list(c, F, dt == CONKER_F64, nc, &blist, &bcount));
     if (n == 2) {
-        if (dt == CONKER_F64) return contract_dot<double>(c, (const double *)F, (const double *)maps, nc, ns, W);
-        return contract_dot<float>(c, (const float *)F, (const float *)maps, nc, ns, W);
+        if (dt == CONKER_F64)
+            return contract_dot<double>(c, (const double *)F, (const double *)maps, nc, ns, blist, bcount, W);
+        return contract_dot<float>(c, (const float *)F, (const float *)maps, nc, ns, blist, bcount, W);
     }
     const int TS = prec == CONKER_MM_F64 ? 16 : 32;
     Plan pl;
@@ -1062,7 +1104,7 @@ extern "C" int conker_contract_npt(conker_ctx *c, const conker_grid *g, conker_d
         const size_t mchunk = 64 * 1024;
         const dim3 mg((unsigned)((nc + mchunk - 1) / mchunk), (unsigned)(ns + 1));
         hipLaunchKernelGGL(k_absmax, mg, dim3(256), 0, c->stream, (const float *)F, (const float *)maps, nc, ns,
-                           mchunk, maxabs);
+                           blist, bcount, maxabs);
         CK_LAUNCH(c);
     }
     if (use_v2) {
@@ -1070,10 +1112,7 @@ extern "C" int conker_contract_npt(conker_ctx *c, const conker_grid *g, conker_d
         Plan2 p2;
         CK_OK(make_plan2(c, ns, n, prec == CONKER_MM_SPLIT_BF16, p2));
         if (nc % 64) return fail(c, CONKER_EUNSUPPORTED, "cell count must be a multiple of 64");
-        size_t G = std::max<size_t>(1, std::min<size_t>(nc / 512, 1024 / (size_t)p2.n_groups));
-        size_t chunk = (nc + G - 1) / G;
-        chunk = (chunk + 63) / 64 * 64;
-        G = (nc + chunk - 1) / chunk;
+        const size_t G = std::max<size_t>(1, std::min<size_t>(nc / 512, 1024 / (size_t)p2.n_groups));
         const int te = 1024;
         const size_t full_b = (size_t)p2.n_tiles * te * (RED_S + 1) * sizeof(double);
         CK_OK(ws_reserve(c, c->partial, (size_t)p2.n_tiles * G * te * sizeof(double)));
@@ -1094,19 +1133,19 @@ extern "C" int conker_contract_npt(conker_ctx *c, const conker_grid *g, conker_d
             }
             if (prec == CONKER_MM_SPLIT_BF16)
                 hipLaunchKernelGGL(k_mm2<CONKER_MM_SPLIT_BF16>, grid, dim3(V2_NT), p2.max_lds, c->stream,
-                                   (const float *)F, (const float *)maps, nc, ns, chunk,
+                                   (const float *)F, (const float *)maps, nc, ns, blist, bcount,
                                    (const int2 *)p2.ritems->p, (const int2 *)p2.citems->p,
                                    (const int2 *)p2.tiles->p, (const Group *)p2.groups->p, (int)G, part,
                                    (const unsigned *)nullptr);
             else if (prec == CONKER_MM_SPLIT_F16)
                 hipLaunchKernelGGL(k_mm2<CONKER_MM_SPLIT_F16>, grid, dim3(V2_NT), p2.max_lds, c->stream,
-                                   (const float *)F, (const float *)maps, nc, ns, chunk,
+                                   (const float *)F, (const float *)maps, nc, ns, blist, bcount,
                                    (const int2 *)p2.ritems->p, (const int2 *)p2.citems->p,
                                    (const int2 *)p2.tiles->p, (const Group *)p2.groups->p, (int)G, part,
                                    (const unsigned *)maxabs);
             else
                 hipLaunchKernelGGL(k_mm2<CONKER_MM_F32>, grid, dim3(V2_NT), p2.max_lds, c->stream, (const float *)F,
-                                   (const float *)maps, nc, ns, chunk, (const int2 *)p2.ritems->p,
+                                   (const float *)maps, nc, ns, blist, bcount, (const int2 *)p2.ritems->p,
                                    (const int2 *)p2.citems->p, (const int2 *)p2.tiles->p,
                                    (const Group *)p2.groups->p, (int)G, part, (const unsigned *)nullptr);
             CK_LAUNCH(c);
@@ -1128,12 +1167,8 @@ extern "C" int conker_contract_npt(conker_ctx *c, const conker_grid *g, conker_d
     }
     const int NBW = pl.n_tiles == 1 ? 1 : (prec == CONKER_MM_F64 ? 4 : 2);
     const int groups = (pl.n_tiles + NBW - 1) / NBW;
-    // cell chunks: aim for ~4096 workgroups in total, chunk a multiple of 4 waves x 16 cells
-    const size_t unit = (size_t)WAVES * 16;
-    size_t G = std::max<size_t>(1, std::min<size_t>(nc / 1024, 4096 / (size_t)groups));
-    size_t chunk = (nc + G - 1) / G;
-    chunk = (chunk + unit - 1) / unit * unit;
-    G = (nc + chunk - 1) / chunk;
+    // ~4096 workgroups in total, each with an equal share of the summed blocks
+    const size_t G = std::max<size_t>(1, std::min<size_t>(nc / 1024, 4096 / (size_t)groups));
     const int te = TS * TS;
     CK_OK(ws_reserve(c, c->partial, (size_t)pl.n_tiles * G * te * sizeof(double)));
     CK_OK(ws_reserve(c, c->full, (size_t)pl.n_tiles * te * (RED_S + 1) * sizeof(double)));
@@ -1142,9 +1177,9 @@ extern "C" int conker_contract_npt(conker_ctx *c, const conker_grid *g, conker_d
     dim3 grid((unsigned)G, (unsigned)groups);
     {
     ProfScope ps(c, PK_CONTRACT_MM);
-    if (NBW == 1) CK_OK(launch_mm<1>(c, prec, grid, F, maps, nc, chunk, tab, pl.n_tiles, part, ns, maxabs));
-    else if (NBW == 2) CK_OK(launch_mm<2>(c, prec, grid, F, maps, nc, chunk, tab, pl.n_tiles, part, ns, maxabs));
-    else CK_OK(launch_mm<4>(c, prec, grid, F, maps, nc, chunk, tab, pl.n_tiles, part, ns, maxabs));
+    if (NBW == 1) CK_OK(launch_mm<1>(c, prec, grid, F, maps, nc, blist, bcount, tab, pl.n_tiles, part, ns, maxabs));
+    else if (NBW == 2) CK_OK(launch_mm<2>(c, prec, grid, F, maps, nc, blist, bcount, tab, pl.n_tiles, part, ns, maxabs));
+    else CK_OK(launch_mm<4>(c, prec, grid, F, maps, nc, blist, bcount, tab, pl.n_tiles, part, ns, maxabs));
     }
     ProfScope ps(c, PK_CONTRACT_REDUCE);
     const size_t tot = (size_t)pl.n_tiles * te;

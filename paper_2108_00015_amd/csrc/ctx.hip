@@ -233,6 +233,7 @@ extern "C" void conker_destroy(conker_ctx *c) {
     rel(c->cosmo);
     rel(c->order);
     rel(c->bins);
+    rel(c->blocks);
     delete c;
 }
 
@@ -286,7 +287,7 @@ extern "C" const char *conker_profile_kind_name(int kind) {
         "scatter", "form_delta", "fft_fwd_z", "fft_fwd_y", "fft_fwd_x", "fft_inv_x_mul", "fft_inv_y",
         "fft_inv_z", "bank_z", "bank_y", "bank_x", "contract_dot", "contract_mm", "contract_reduce", "ratio",
         "fused_zinv_contract", "diag_zinv", "diag_maps", "diag_reduce", "support", "pair_spectral", "survey_front_end",
-        "axis_order"};
+        "axis_order", "cell_blocks"};
     return (kind >= 0 && kind < PK_COUNT) ? names[kind] : nullptr;
 }
 

@@ -358,6 +358,75 @@ def test_split_f16_wide_dynamic_range(ck, ctx, n):
     assert err <= 1e-5
 
 
+def _block_sparse_field(dims, rng, dt):
+    """F zero (either sign) on about 70 % of the 64-cell blocks of the flat
+    grid, with a single non-zero cell in some of those, and a ragged last block
+    when the cell count is not a multiple of 64."""
+    F = rng.normal(size=dims)
+    flat = F.reshape(-1)
+    nblk = -(-flat.size // 64)
+    for b in np.flatnonzero(rng.random(nblk) < 0.7):
+        seg = flat[64 * b:64 * b + 64]
+        seg[:] = -0.0 if b % 3 == 0 else 0.0
+        if b % 5 == 0:
+            seg[rng.integers(len(seg))] = rng.normal()
+    if dt == torch.float32:
+        F = F.astype(np.float32).astype(np.float64)
+    return F
+
+
+SPARSE_CONTRACT_CASES = [
+    # 2.5 workgroups of the block marking (2048 blocks each)
+    ("f64", 2, 8, (64, 64, 80)),
+    ("split_bf16", 2, 8, (64, 64, 80)),
+    ("f64", 3, 12, (64, 64, 80)),
+    ("f32", 3, 30, (64, 64, 80)),
+    ("split_bf16", 3, 30, (64, 64, 80)),
+    ("split_f16", 3, 30, (64, 64, 80)),
+    ("split_bf16", 4, 9, (64, 64, 80)),
+    ("split_f16", 4, 12, (64, 64, 80)),
+    ("f32", 5, 6, (64, 64, 80)),
+    ("f64", 4, 6, (64, 64, 80)),
+    # 720 cells: the last 64-cell block holds 16
+    ("f64", 2, 8, (3, 5, 48)),
+    ("f64", 3, 8, (3, 5, 48)),
+    ("f32", 3, 8, (3, 5, 48)),
+    ("split_bf16", 3, 8, (3, 5, 48)),
+    ("split_f16", 3, 8, (3, 5, 48)),
+]
+
+
+@pytest.mark.parametrize("prec,n,ns,dims", SPARSE_CONTRACT_CASES)
+def test_contract_block_sparse_field_vs_oracle(ck, ctx, prec, n, ns, dims):
+    """Only the 64-cell blocks where F is non-zero are summed: the result is the
+    full sum over every cell."""
+    _say("contract block-sparse", prec, n, ns, dims)
+    rng = np.random.default_rng(300 + n * 11 + ns)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    F = _block_sparse_field(dims, rng, dt)
+    maps = rng.normal(size=(ns,) + dims) + 0.3
+    if dt == torch.float32:
+        maps = maps.astype(np.float32).astype(np.float64)
+    grid = ck.Grid(dims, (0, 0, 0), 1.0)
+    W = ctx.contract_npt(grid, _gpu(F, dt), _gpu(maps, dt), n, prec).cpu().numpy()
+    ref = oc.contract(F, maps, n)
+    err = relerr(W, ref)
+    _say("  err %.3e" % err)
+    assert err <= (1e-12 if prec == "f64" else 1e-5)
+
+
+@pytest.mark.parametrize("prec,n", [("f64", 2), ("f64", 3), ("split_bf16", 3), ("split_f16", 4)])
+def test_contract_zero_field_gives_zero(ck, ctx, prec, n):
+    """A field that is zero everywhere (no block to sum) gives exactly zero."""
+    dims = (32, 32, 32)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    grid = ck.Grid(dims, (0, 0, 0), 1.0)
+    F = torch.zeros(dims, dtype=dt, device=DEV)
+    M = torch.ones((6,) + dims, dtype=dt, device=DEV)
+    W = ctx.contract_npt(grid, F, M, n, prec).cpu().numpy()
+    assert W.shape == (oc.num_tuples(6, n),) and np.all(W == 0.0)
+
+
 def test_contract_argument_errors(ck, ctx):
     grid = ck.Grid((32, 32, 32), (0, 0, 0), 1.0)
     F = torch.zeros((32, 32, 32), dtype=torch.float32, device=DEV)

@@ -340,6 +340,9 @@ def main():
                     help="mock batches: keep the default launch settings instead of timing them per grid shape")
     ap.add_argument("--field-at-a-time", action="store_true",
                     help="separate path with one maps buffer, N then R (large grids)")
+    ap.add_argument("--tune", default="",
+                    help="launch settings for the single-catalog workloads, e.g. x_resident=3,radius_batch=15 "
+                         "(conker_tune fields; default: the library's)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the hot path is measured on a single MI355X "
@@ -365,6 +368,8 @@ def main():
     rw = torch.from_numpy(rand.w).to(dev) if rand.w is not None else None
     grid = ck.Grid(w.dims, w.origin, w.cell)
     ctx = ck.Context(0)
+    if args.tune:
+        ctx.set_tune(**{k: int(v) for k, v in (kv.split("=") for kv in args.tune.split(","))})
     ns = len(w.radii)
     nc = grid.n_cells
     kel = ck.kspec_elems(grid)
@@ -447,7 +452,8 @@ def main():
                    "maps": ("never stored" if (args.mode != "npcf" or stages_use_fused(mixed["prof"]))
                             else ("one field at a time" if args.field_at_a_time else "both fields")),
                    "axis_order": "".join("xyz"[a] for a in AXIS_ORDERS[order]),
-                   "carrying_lines": round(fl, 4), "first_axis_slabs": round(fx, 4)},
+                   "carrying_lines": round(fl, 4), "first_axis_slabs": round(fx, 4),
+                   **({"tune": args.tune} if args.tune else {})},
         "s_to_W3_mixed": round(s_mixed, 5),
         "s_to_W3_fp64": round(fp64["ms"] / 1e3, 5) if fp64 else None,
         "fp64_over_mixed": round(fp64["ms"] / mixed["ms"], 3) if fp64 else None,

@@ -398,7 +398,11 @@ int conker_batch_launch(conker_ctx *ctx);
  *                   1 narrow (16 float32 / 8 float64 columns), 2 wide (twice
  *                   that: 256-byte runs).  Default: wide.
  *   x_resident      x-axis inverse pass: 1 streamed, 2 kernel-multiply tile
- *                   kept resident on chip across the batch's radii.  Default 2.
+ *                   kept resident on chip across the batch's radii, its
+ *                   stages alternating between two LDS exchange buffers
+ *                   where both fit, 3 as 2 with one exchange buffer.
+ *                   Default: 2 where the pass stores only the slabs
+ *                   carrying field, else 3.
  *   mm_kernel       matrix-core summation: 1 one output tile per wave,
  *                   2 operand sharing across a workgroup.  Default: 2 above
  *                   four 32 x 32 output tiles, else 1.

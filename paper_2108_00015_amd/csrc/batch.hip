@@ -86,7 +86,7 @@ int run_all(conker_ctx *c) {
 
 bool tune_ok(const conker_tune &t) {
     auto in = [](int v, int lo, int hi) { return v >= lo && v <= hi; };
-    return in(t.x_tile, 0, 2) && in(t.y_tile, 0, 2) && in(t.x_resident, 0, 2) && in(t.mm_kernel, 0, 2) &&
+    return in(t.x_tile, 0, 2) && in(t.y_tile, 0, 2) && in(t.x_resident, 0, 3) && in(t.mm_kernel, 0, 2) &&
            in(t.radius_batch, 0, 64) && in(t.axis_order, 0, 6);
 }
 
@@ -133,7 +133,7 @@ int tune_job(conker_ctx *c, const conker_job &j, int reps, hipEvent_t e0, hipEve
     };
     std::vector<Knob> knobs = {{&conker_tune::y_tile, {1, 2}},
                                {&conker_tune::x_tile, {1, 2}},
-                               {&conker_tune::x_resident, {1, 2}}};
+                               {&conker_tune::x_resident, {1, 2, 3}}};
     if (!fused && j.n >= 3 && j.prec != CONKER_MM_F64) knobs.push_back({&conker_tune::mm_kernel, {1, 2}});
     if (fused && j.grid.dims[0] == j.grid.dims[1] && j.grid.dims[1] == j.grid.dims[2])
         knobs.push_back({&conker_tune::axis_order, {1}});   // the given order against the chosen one

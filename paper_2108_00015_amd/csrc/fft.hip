@@ -591,7 +591,7 @@ constexpr bool pingpong_fits() {
                160 * 1024;
 }
 
-template <typename T, int L>
+template <typename T, int L, bool PPW>
 __global__ __launch_bounds__((Shape<T, L, TM_R>::NT), (Shape<T, L, TM_R>::MINW)) void k_xmul_resident(
     const cplx<T> *__restrict__ spec, const T *__restrict__ kspec, cplx<T> *__restrict__ tspec,
     const cplx<T> *__restrict__ twg, Dims d, size_t nc, size_t kel, int m0, int nb, const int *__restrict__ xcount) {
@@ -599,7 +599,7 @@ __global__ __launch_bounds__((Shape<T, L, TM_R>::NT), (Shape<T, L, TM_R>::MINW))
     using SH = Shape<T, L, TM_R>;
     constexpr int TC = SH::TC, NT = SH::NT, NXH = L / 2 + 1;
     constexpr int KPT = (TC * NXH + NT - 1) / NT;   // kernel values staged per thread
-    constexpr bool PP = pingpong_fits<T, L>();
+    constexpr bool PP = PPW && pingpong_fits<T, L>();
     constexpr int PADR = PP ? 1 : SH::PAD, LDSN = L * (TC + PADR);
     __shared__ C lds[PP ? 2 * LDSN : LDSN];
     __shared__ C tw[L];
@@ -926,7 +926,10 @@ int inverse_batch_t(conker_ctx *ctx, const conker_grid *g, const void *spec, con
     const int tiles = (int)((long)d.ny * d.nz / tc_of<T>(d.nx, xm));
     const dim3 gxm(1, 1, loop ? 1u : (unsigned)nb);
     static const int resident_env = env_flag("CONKER_XMUL_RESIDENT", 1);
-    const int resident = ctx->tune.x_resident ? ctx->tune.x_resident == 2 : resident_env;
+    const int resident = ctx->tune.x_resident ? ctx->tune.x_resident >= 2 : resident_env;
+    // two exchange buffers pay where most rows are skipped (the pass is bound by
+    // its arithmetic and barriers); with every row stored, one buffer measures faster
+    const bool one_buffer = ctx->tune.x_resident == 3 || (ctx->tune.x_resident == 0 && !xcount);
     bool done = false;
     if (resident && !pair) {
         auto go = [&](auto Lc) -> int {
@@ -936,9 +939,14 @@ int inverse_batch_t(conker_ctx *ctx, const conker_grid *g, const void *spec, con
                 if (d.nz % SH::TC) return CONKER_OK;
                 ProfScope ps(ctx, PK_FFT_INV_X_MUL);
                 const unsigned nt = (unsigned)((long)d.ny * d.nz / SH::TC);
-                hipLaunchKernelGGL((k_xmul_resident<T, LL>), dim3(nt), dim3(SH::NT), 0, ctx->stream,
-                                   (const C *)spec, (const T *)kspec, (C *)tspec, (const C *)twx, d, nc, kel, m0,
-                                   nb, xcount);
+                if (one_buffer)
+                    hipLaunchKernelGGL((k_xmul_resident<T, LL, false>), dim3(nt), dim3(SH::NT), 0, ctx->stream,
+                                       (const C *)spec, (const T *)kspec, (C *)tspec, (const C *)twx, d, nc, kel,
+                                       m0, nb, xcount);
+                else
+                    hipLaunchKernelGGL((k_xmul_resident<T, LL, true>), dim3(nt), dim3(SH::NT), 0, ctx->stream,
+                                       (const C *)spec, (const T *)kspec, (C *)tspec, (const C *)twx, d, nc, kel,
+                                       m0, nb, xcount);
                 CK_LAUNCH(ctx);
                 done = true;
             }

@@ -7,7 +7,7 @@
  *   kernels      (Sec. 2.3)                         conker_make_shell_kernels
  *   convolution  (Sec. 2.4, Eqs. countconv/randconv) conker_convolve_shells
  *   summation    (Sec. 2.5, Eq. ksin_delta)         conker_contract_npt, conker_ratio
- *   both at once, maps never stored                 conker_convolve_contract
+ *   both at once, maps never returned               conker_convolve_contract
  * and the paper's other forms: equidistant sums (Eq. ksinDiag,
  * conker_convolve_diag / conker_contract_diag), cross-correlations (Sec. 2.7,
  * *_cross), continuous delta fields (Sec. 2.6, conker_delta_field), n = 2 in
@@ -181,20 +181,25 @@ int conker_contract_npt(conker_ctx *ctx, const conker_grid *grid, conker_dtype d
                         conker_mmprec prec, double *d_W);
 
 /* conker_convolve_contract: conker_convolve_shells followed by
- * conker_contract_npt for orders n = 2 or 3, in one pass that never writes the
- * per-radius maps to memory (each line of cells is transformed back for every
- * radius in on-chip memory and summed at once):
+ * conker_contract_npt, without returning the maps:
  *   W_a[t] = sum_x field_a(x) prod_i maps_a[a_i](x), and likewise W_b for
  *   field_b, maps as defined for conker_convolve_shells, tuples in the order
  *   of conker_contract_npt.
  *   d_field_b and d_W_b: both given or both NULL.
- * Supported: dtype CONKER_F32 with prec CONKER_MM_F32 or
- * CONKER_MM_SPLIT_BF16, nz = 512, 1 <= n_radii <= 30; anything else returns
- * CONKER_EUNSUPPORTED before doing work (use the two separate calls).  The
- * context holds the spectra of all radii at once (n_radii * N_c * 8 bytes).
- * The fields must be 16-byte aligned (CONKER_EINVAL otherwise).  Since every
- * term carries field(x), z-lines on which both fields vanish add nothing: the
- * inverse transforms are carried out only where a line holds field. */
+ * Arguments as for conker_contract_npt (n 2..5, n_radii 1..64, dtype and prec
+ * alike).  Since every term carries field(x), z-lines on which both fields
+ * vanish add nothing: the inverse transforms are carried out only where a
+ * line holds field.
+ * - dtype CONKER_F32 with prec CONKER_MM_F32 or CONKER_MM_SPLIT_BF16, n = 2
+ *   or 3, nz = 512, n_radii <= 30: one pass that never writes the maps to
+ *   memory (each line of cells is transformed back for every radius in
+ *   on-chip memory and summed at once); the context holds the spectra of all
+ *   radii at once (n_radii * N_c * 8 bytes).
+ * - every other case: the maps are written to the context's workspace
+ *   (fields * n_radii * N_c * element size bytes) on the carrying lines only,
+ *   and summed as conker_contract_npt does; the spectra are batched over the
+ *   radii as in conker_convolve_shells.
+ * The fields must be 16-byte aligned (CONKER_EINVAL otherwise). */
 int conker_convolve_contract(conker_ctx *ctx, const conker_grid *grid, conker_dtype dtype,
                              const void *d_field_a, const void *d_field_b, const void *d_kspec,
                              int n_radii, int n, conker_mmprec prec, double *d_W_a, double *d_W_b);
@@ -344,8 +349,8 @@ int conker_ratio(conker_ctx *ctx, const double *d_Wd, const double *d_Wr,
 /* ---- batches of catalogs ---------------------------------------------------
  * One job = the whole path for one catalog pair (data, randoms) on its own
  * grid: zero the grids, grid_assign both catalogs, form_delta, convolution and
- * summation of both fields (conker_convolve_contract when it applies and the
- * map pointers are NULL, else convolve_shells + contract_npt), and ratio.
+ * summation of both fields (conker_convolve_contract when the map pointers
+ * are NULL, else convolve_shells + contract_npt), and ratio.
  * Independent catalogs (mocks, survey regions) combine afterwards by adding
  * numerators and denominators (Eq. ksi3combined).  All pointers are caller
  * owned device memory; jobs may share grid and map buffers (they run in
@@ -365,7 +370,7 @@ typedef struct {
     int64_t n_rand;
     void *d_N;                      /* dtype grid: N on exit */
     void *d_R;                      /* dtype grid: R_raw on exit */
-    void *d_maps_N;                 /* dtype [n_radii][grid] or NULL (fused path) */
+    void *d_maps_N;                 /* dtype [n_radii][grid] or NULL (conker_convolve_contract) */
     void *d_maps_R;                 /* likewise, NULL exactly when d_maps_N is */
     double *d_wsum;                 /* [2]: in-grid weight sums of data, randoms */
     int64_t *d_n_outside;           /* [2]: rejected tracers of data, randoms */

@@ -224,10 +224,12 @@ class Context:
                           kspec: torch.Tensor, n: int, precision: str = "split_bf16",
                           out_a: Optional[torch.Tensor] = None, out_b: Optional[torch.Tensor] = None,
                           centre_a: Optional[torch.Tensor] = None, centre_b: Optional[torch.Tensor] = None):
-        """Convolution + summation (n = 2, 3) without storing maps; returns (W_a, W_b).
+        """Convolution + summation without returning the maps; returns (W_a, W_b).
 
-        With centre fields (cross-correlation), the maps of field_a are summed against centre_a
-        (and likewise b)."""
+        n = 2..5 and every precision of contract_npt: the fused kernel (maps never stored) where
+        it applies (fused_supported), else the maps of the lines carrying field in the context's
+        workspace.  With centre fields (cross-correlation), the maps of field_a are summed against
+        centre_a (and likewise b)."""
         nr = int(kspec.shape[0])
         cnt = num_tuples(nr, n)
         if out_a is None:
@@ -519,7 +521,8 @@ def make_job(grid: Grid, kspec: torch.Tensor, n: int, precision: str, data_pos: 
 
 
 def fused_supported(grid: Grid, n_radii: int, n: int, precision: str, dtype) -> bool:
-    """Whether conker_convolve_contract handles this case (else the two separate calls are used)."""
+    """Whether conker_convolve_contract runs its fused kernel here, which never stores the maps
+    (else it keeps the maps of the carrying lines in the context's workspace)."""
     return (dtype == torch.float32 and precision in ("f32", "split_bf16") and n in (2, 3)
             and int(grid.dims[2]) == 512 and 1 <= n_radii <= 30)
 
@@ -575,9 +578,8 @@ def npcf_continuous(ctx: Context, grid: Grid, D: torch.Tensor, R: torch.Tensor, 
     """Continuous tracers (Sec. 2.6): delta = (D - R) / R, then xi_n = sum_x delta prod_i (delta *** K_{a_i})
     (Eq. ksin_cont), with no further normalisation.  Returns xi (= W) and delta."""
     delta = ctx.delta_field(grid, D, R, alpha)
-    nr = int(kspec.shape[0])
     if fused is None:
-        fused = fused_supported(grid, nr, n, precision, delta.dtype)
+        fused = True
     if fused:
         xi, _ = ctx.convolve_contract(grid, delta, None, kspec, n, precision)
     else:
@@ -606,9 +608,8 @@ def npcf_cross(ctx: Context, grid: Grid, data0_pos: torch.Tensor, data1_pos: tor
     ctx.grid_assign(grid, rand_pos, rand_w, R, wsum[2:3], nout[2:3])
     ctx.form_delta(grid, N0, R, wsum[0:1], wsum[2:3], alpha[0:1])
     ctx.form_delta(grid, N1, R, wsum[1:2], wsum[2:3], alpha[1:2])
-    nr = int(kspec.shape[0])
     if fused is None:
-        fused = fused_supported(grid, nr, n, precision, dtype)
+        fused = True
     if fused:
         # maps of N1 summed against N0; maps of R_raw summed against R_raw
         Wc, Wr = ctx.convolve_contract(grid, N1, R, kspec, n, precision, centre_a=N0, centre_b=R)
@@ -628,16 +629,17 @@ def npcf(ctx: Context, grid: Grid, data_pos: torch.Tensor, rand_pos: torch.Tenso
     """Mapping -> convolution -> summation -> estimator, chaining the C ABI calls.
 
     `bufs` may hold preallocated tensors (keys: N, R, maps_N, maps_R, wsum, nout, alpha) that are
-    reused across calls.  With `fused` (default: whenever supported) the convolution and summation
-    run as one call that never stores the maps.  With `field_at_a_time` (separate path) the maps of
+    reused across calls.  With `fused` (default, unless field_at_a_time) the convolution and
+    summation run as one call, conker_convolve_contract: its fused kernel never stores the maps
+    (fused_supported), otherwise it keeps the maps of the lines carrying field in the context's
+    workspace.  With `field_at_a_time` (separate path) the maps of
     N and R are made and summed one field after the other in a single maps buffer (half the memory;
     each field's radii are paired in the transforms).  Returns xi, W_delta, W_rand_raw, alpha and
     the buffers (all on the GPU).  Tracers outside the grid raise ConkerError unless
     `allow_outside` (checking them waits for the stream).
     """
-    nr_ = int(kspec.shape[0])
     if fused is None:
-        fused = fused_supported(grid, nr_, n, precision, dtype)
+        fused = not field_at_a_time
     dev = data_pos.device
     b = {} if bufs is None else bufs
     shape = tuple(int(d) for d in grid.dims)

@@ -51,7 +51,7 @@ int run_job(conker_ctx *c, const conker_job &j) {
     CK_OK(conker_grid_assign(c, &j.grid, j.d_rand_pos, j.d_rand_w, j.n_rand, j.dtype, j.d_R, j.d_wsum + 1,
                              j.d_n_outside + 1));
     CK_OK(conker_form_delta(c, &j.grid, j.dtype, j.d_N, j.d_R, j.d_wsum, j.d_wsum + 1, j.d_alpha));
-    if (!j.d_maps_N && fused_ok(j)) {
+    if (!j.d_maps_N) {
         CK_OK(conker_convolve_contract(c, &j.grid, j.dtype, j.d_N, j.d_R, j.d_kspec, j.n_radii, j.n, j.prec,
                                        j.d_W_delta, j.d_W_rand));
     } else {
@@ -125,7 +125,8 @@ int tune_job(conker_ctx *c, const conker_job &j, int reps, hipEvent_t e0, hipEve
     conker_tune best = c->user_tune;
     float best_ms;
     CK_OK(time_job(c, j, best, reps, e0, e1, &best_ms));
-    const bool fused = j.d_maps_N == nullptr;
+    const bool nomaps = j.d_maps_N == nullptr;   // conker_convolve_contract
+    const bool fused = nomaps && fused_ok(j);     // ... with its fused kernel
     const int slots = j.n_radii;
     struct Knob {
         int32_t conker_tune::*field;
@@ -135,7 +136,7 @@ int tune_job(conker_ctx *c, const conker_job &j, int reps, hipEvent_t e0, hipEve
                                {&conker_tune::x_tile, {1, 2}},
                                {&conker_tune::x_resident, {1, 2, 3}}};
     if (!fused && j.n >= 3 && j.prec != CONKER_MM_F64) knobs.push_back({&conker_tune::mm_kernel, {1, 2}});
-    if (fused && j.grid.dims[0] == j.grid.dims[1] && j.grid.dims[1] == j.grid.dims[2])
+    if (nomaps && j.grid.dims[0] == j.grid.dims[1] && j.grid.dims[1] == j.grid.dims[2])
         knobs.push_back({&conker_tune::axis_order, {1}});   // the given order against the chosen one
     if (!fused && slots >= 4) {
         std::vector<int> rb = {(slots + 1) / 2};
@@ -172,8 +173,6 @@ int check_job(conker_ctx *c, const conker_job &j, int k) {
         return fail(c, CONKER_EINVAL, "job %d: NULL pointer", k);
     if ((j.d_maps_N == nullptr) != (j.d_maps_R == nullptr))
         return fail(c, CONKER_EINVAL, "job %d: maps_N and maps_R must both be given or both be NULL", k);
-    if (!j.d_maps_N && !fused_ok(j))
-        return fail(c, CONKER_EINVAL, "job %d: maps are needed (the fused summation does not apply)", k);
     return CONKER_OK;
 }
 

@@ -41,6 +41,7 @@ struct conker_ctx {
     conker::Buf order;      // support projections, chosen axis order and permuted fields
     conker::Buf bins;       // binned mapping: per-brick counts and starts, per-workgroup histograms, placed points
     conker::Buf blocks;     // summation: list of the 64-cell blocks where the field is non-zero
+    conker::Buf maps;       // convolve-contract without the fused kernel: maps of carrying lines
     int order_last = 0;             // axis order of the last map-free summation (1..6), -1: on the device
     const int *order_dev = nullptr; // with order_last -1: the chosen permutation index (0..5)
     std::map<uint64_t, conker::Buf> tables;  // item / tuple tables, keyed by (n_radii, n, prec)
@@ -188,15 +189,18 @@ int fft_shell_pair(conker_ctx *ctx, const conker_grid *g, double lo_a, double hi
 // 3D FFT, write real parts to maps_a[m] and imaginary parts to maps_b[m].
 // With maps_a NULL only the x and y passes run, leaving tspec[m - m0] holding
 // the spectra transformed back along x and y (still along kz).
-// With `sup` (maps_a NULL only): outputs are needed on carrying lines only; the
-// x pass writes carrying x-slabs, the y pass skips empty slabs and writes
-// carrying lines.
+// With `sup` (and maps_a NULL, or sup_maps): outputs are needed on carrying
+// lines only; the x pass writes carrying x-slabs, the y pass skips empty slabs
+// and writes carrying lines, and with sup_maps the z pass writes the maps of
+// carrying lines only (z-line tiles without one are skipped; the maps of other
+// lines keep whatever they held).
 // With pair_ns > 0 (one real field, maps_b NULL): radius pairing.  m0 and nb
 // count slots; slot j is multiplied by K_{2j} + i K_{2j+1} (K_{2j} alone when
 // 2j + 1 = pair_ns) and unpacked into maps_a rows 2j and 2j + 1.
 int fft_inverse_batch(conker_ctx *ctx, const conker_grid *g, bool f64,
                       const void *spec, const void *kspec, int m0, int nb, void *tspec,
-                      void *maps_a, void *maps_b, const Support *sup = nullptr, int pair_ns = 0);
+                      void *maps_a, void *maps_b, const Support *sup = nullptr, int pair_ns = 0,
+                      bool sup_maps = false);
 // Inverse z pass of tspec[0 .. nb) (after fft_inverse_batch with maps_a NULL)
 // with the equidistant sums sum_x F(x) C_m(x)^p, p = 1 .. pmax (1..4), of the
 // real part against fa and the imaginary part against fb (NULL: none), in

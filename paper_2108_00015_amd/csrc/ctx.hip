@@ -234,6 +234,7 @@ extern "C" void conker_destroy(conker_ctx *c) {
     rel(c->order);
     rel(c->bins);
     rel(c->blocks);
+    rel(c->maps);
     delete c;
 }
 

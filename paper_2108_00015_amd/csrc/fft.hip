@@ -465,8 +465,11 @@ struct OpUnpack {
     Tile g;
     const C *src;
     int pair, ns;
+    const unsigned char *mask;   // NULL, or line flags [nx * ny]: only lines with a flag are written
+    int tcn;
     template <int TC> __device__ void begin() {
         g = make_tile(AX_Z, d, blockIdx.x, TC);
+        tcn = TC;
         src = tspec + (size_t)blockIdx.y * nc + g.base;
         if (pair) {
             const int ra = 2 * (m0 + blockIdx.y);
@@ -478,10 +481,17 @@ struct OpUnpack {
         ma += o;
         if (mb) mb += o;
     }
+    __device__ bool active() const {   // the same for every thread: any line of the tile flagged
+        if (!mask) return true;
+        int any = 0;
+        for (int k = 0; k < tcn; ++k) any |= mask[(size_t)g.p0 + k];
+        return any != 0;
+    }
     __device__ int iters() const { return 1; }
     __device__ void set_iter(int) {}
     __device__ C load(int i, int c) const { return src[off(g, i, c)]; }
     __device__ void store(int i, int c, C v) const {
+        if (mask && !mask[(size_t)g.p0 + c]) return;
         const unsigned k = off(g, i, c);
         ma[k] = v.x;
         if (mb) mb[k] = v.y;
@@ -901,10 +911,12 @@ int forward_pair_t(conker_ctx *ctx, const conker_grid *g, const void *a, const v
 
 template <typename T>
 int inverse_batch_t(conker_ctx *ctx, const conker_grid *g, const void *spec, const void *kspec, int m0,
-                    int nb, void *tspec, void *maps_a, void *maps_b, const Support *sup, int pair_ns) {
+                    int nb, void *tspec, void *maps_a, void *maps_b, const Support *sup, int pair_ns,
+                    bool sup_maps) {
     const int pair = pair_ns > 0 ? 1 : 0;
-    const int *xcount = (sup && !maps_a) ? sup->xcount : nullptr;
-    const unsigned char *mask = (sup && !maps_a) ? sup->mask : nullptr;
+    const bool use_sup = sup && (!maps_a || sup_maps);
+    const int *xcount = use_sup ? sup->xcount : nullptr;
+    const unsigned char *mask = use_sup ? sup->mask : nullptr;
     using C = cplx<T>;
     const bool f64 = std::is_same<T, double>::value;
     Dims d{g->dims[0], g->dims[1], g->dims[2]};
@@ -981,7 +993,7 @@ int inverse_batch_t(conker_ctx *ctx, const conker_grid *g, const void *spec, con
     CK_OK((launch_len<T, +1>(ctx, PK_FFT_INV_Y, col_mode_for<T>(ctx, d, AX_Y), d.ny, AX_Y, d,
                                  dim3(1, (unsigned)nb), py)));
     if (!maps_a) return CONKER_OK;   // x and y passes only
-    OpUnpack<T> pz{twz, d, (const C *)tspec, (T *)maps_a, (T *)maps_b, nc, m0, {}, nullptr, pair, pair_ns};
+    OpUnpack<T> pz{twz, d, (const C *)tspec, (T *)maps_a, (T *)maps_b, nc, m0, {}, nullptr, pair, pair_ns, mask, 0};
     CK_OK((launch_len<T, +1>(ctx, PK_FFT_INV_Z, TM_J, d.nz, AX_Z, d, dim3(1, (unsigned)nb), pz)));
     return CONKER_OK;
 }
@@ -1056,9 +1068,9 @@ int fft_forward_pair(conker_ctx *ctx, const conker_grid *g, bool f64, const void
 
 int fft_inverse_batch(conker_ctx *ctx, const conker_grid *g, bool f64, const void *spec,
                       const void *kspec, int m0, int nb, void *tspec, void *maps_a, void *maps_b,
-                      const Support *sup, int pair_ns) {
-    return f64 ? inverse_batch_t<double>(ctx, g, spec, kspec, m0, nb, tspec, maps_a, maps_b, sup, pair_ns)
-               : inverse_batch_t<float>(ctx, g, spec, kspec, m0, nb, tspec, maps_a, maps_b, sup, pair_ns);
+                      const Support *sup, int pair_ns, bool sup_maps) {
+    return f64 ? inverse_batch_t<double>(ctx, g, spec, kspec, m0, nb, tspec, maps_a, maps_b, sup, pair_ns, sup_maps)
+               : inverse_batch_t<float>(ctx, g, spec, kspec, m0, nb, tspec, maps_a, maps_b, sup, pair_ns, sup_maps);
 }
 
 int fft_shell_pair(conker_ctx *ctx, const conker_grid *g, double lo_a, double hi_a, double lo_b,

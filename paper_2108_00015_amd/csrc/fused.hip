@@ -278,6 +278,53 @@ __global__ void k_fused_finish(const double *__restrict__ partial, int G, int ns
 
 }  // namespace
 
+// Every other order, precision and grid: the maps go to the context's
+// workspace, but only on the z-lines carrying centre field -- the x pass
+// writes carrying x-slabs, the y pass carrying lines, the z pass the maps of
+// carrying lines -- since every term of every sum carries the centre field
+// (the other cells of the maps are never read).  The sums are then those of
+// conker_contract_npt, over the 64-cell blocks where the centre field is
+// non-zero, all of which lie on carrying lines.
+static int convolve_contract_maps(conker_ctx *c, const conker_grid *g, conker_dtype dt, const void *fa,
+                                  const void *fb, const void *ca, const void *cb, const void *kspec, int ns, int n,
+                                  conker_mmprec prec, double *Wa, double *Wb) {
+    if (n < 2 || n > 5) return fail(c, CONKER_EINVAL, "order n=%d outside 2..5", n);
+    if (ns < 1 || ns > 64) return fail(c, CONKER_EINVAL, "n_radii=%d outside 1..64", ns);
+    if (dt != CONKER_F32 && dt != CONKER_F64) return fail(c, CONKER_EINVAL, "bad dtype");
+    if (prec == CONKER_MM_F64 ? dt != CONKER_F64 : dt != CONKER_F32)
+        return fail(c, CONKER_EINVAL, "float64 summation needs float64 fields, the others float32");
+    if (prec != CONKER_MM_F64 && prec != CONKER_MM_F32 && prec != CONKER_MM_SPLIT_BF16 && prec != CONKER_MM_SPLIT_F16)
+        return fail(c, CONKER_EINVAL, "bad precision");
+    const bool f64 = dt == CONKER_F64;
+    CK_HIP(c, hipSetDevice(c->device));
+    Support sup;
+    bool have_sup = false;
+    {   // axis order of the transforms (cubic grids): the passes run on permuted copies
+        const void *in[4] = {fa, fb, ca, cb}, *out[4];
+        CK_OK(order_fields(c, g, f64, ns, in, 4, out, &sup, &have_sup));
+        fa = out[0]; fb = out[1]; ca = out[2]; cb = out[3];
+    }
+    const size_t nc = ncells(g);
+    const size_t esz = f64 ? sizeof(double) : sizeof(float);
+    const size_t cbytes = 2 * nc * esz;
+    const size_t mbytes = (size_t)ns * nc * esz;
+    CK_OK(ws_reserve(c, c->maps, (fb ? 2 : 1) * mbytes));
+    const int B = batch_radii(c, cbytes, ns, cbytes);
+    CK_OK(ws_reserve(c, c->spec, cbytes));
+    CK_OK(ws_reserve(c, c->tspec, (size_t)B * cbytes));
+    if (!have_sup) CK_OK(support_lines(c, g, f64, ca, cb, &sup));
+    void *ma = c->maps.p;
+    void *mb = fb ? (void *)((char *)c->maps.p + mbytes) : nullptr;
+    CK_OK(fft_forward_pair(c, g, f64, fa, fb, c->spec.p));
+    for (int m0 = 0; m0 < ns; m0 += B) {
+        const int nb = (m0 + B <= ns) ? B : ns - m0;
+        CK_OK(fft_inverse_batch(c, g, f64, c->spec.p, kspec, m0, nb, c->tspec.p, ma, mb, &sup, 0, true));
+    }
+    CK_OK(conker_contract_npt(c, g, dt, ca, ma, ns, n, prec, Wa));
+    if (fb) CK_OK(conker_contract_npt(c, g, dt, cb, mb, ns, n, prec, Wb));
+    return CONKER_OK;
+}
+
 // Maps from fa (fb), summed against the centre fields ca (cb) of vertex 0.
 static int convolve_contract(conker_ctx *c, const conker_grid *g, conker_dtype dt, const void *fa, const void *fb,
                              const void *ca, const void *cb, const void *kspec, int ns, int n, conker_mmprec prec,
@@ -286,11 +333,11 @@ static int convolve_contract(conker_ctx *c, const conker_grid *g, conker_dtype d
     if (!fa || !ca || !kspec || !Wa) return fail(c, CONKER_EINVAL, "NULL pointer");
     if ((fb == nullptr) != (Wb == nullptr) || (fb == nullptr) != (cb == nullptr))
         return fail(c, CONKER_EINVAL, "field_b, its centre field and W_b must all be given or all be NULL");
-    if (n != 2 && n != 3) return fail(c, CONKER_EUNSUPPORTED, "fused summation supports n = 2 and 3");
-    if (dt != CONKER_F32 || (prec != CONKER_MM_F32 && prec != CONKER_MM_SPLIT_BF16))
-        return fail(c, CONKER_EUNSUPPORTED, "fused summation supports float32 with f32 or split-bf16");
-    if (g->dims[2] != NZ) return fail(c, CONKER_EUNSUPPORTED, "fused summation needs nz = %d", NZ);
-    if (ns < 1 || ns > MAXR) return fail(c, CONKER_EUNSUPPORTED, "fused summation holds 1..%d radii", MAXR);
+    // the fused kernel: float32 with f32 or split-bf16 products, n = 2, 3,
+    // z-lines of 512 cells, at most 30 radii (the maps of one line in LDS)
+    if ((n != 2 && n != 3) || dt != CONKER_F32 || (prec != CONKER_MM_F32 && prec != CONKER_MM_SPLIT_BF16) ||
+        g->dims[2] != NZ || ns < 1 || ns > MAXR)
+        return convolve_contract_maps(c, g, dt, fa, fb, ca, cb, kspec, ns, n, prec, Wa, Wb);
     CK_HIP(c, hipSetDevice(c->device));
     Support sup;
     bool have_sup = false;

@@ -61,7 +61,7 @@ def _pick(W, n, tuples):
     return np.array([W[idx[t]] for t in tuples])
 
 
-def _build(ck, ctx, mocks, n, dtype, prec):
+def _build(ck, ctx, mocks, n, dtype, prec, stored=True):
     dev = "cuda:0"
     kspecs = {}
     gmax = max(g for g, _ in MOCKS)
@@ -77,7 +77,10 @@ def _build(ck, ctx, mocks, n, dtype, prec):
             kspecs[g] = ctx.make_shell_kernels(grid, RADII, dtype)[0]
         dp = torch.from_numpy(d.pos).to(dev)
         rp = torch.from_numpy(r.pos).to(dev)
-        jobs.append(ck.make_job(grid, kspecs[g], n, prec, dp, rp, N=N, R=R, maps_N=mN, maps_R=mR, fused=False))
+        if stored:
+            jobs.append(ck.make_job(grid, kspecs[g], n, prec, dp, rp, N=N, R=R, maps_N=mN, maps_R=mR, fused=False))
+        else:   # conker_convolve_contract: maps of carrying lines in the context's workspace
+            jobs.append(ck.make_job(grid, kspecs[g], n, prec, dp, rp, N=N, R=R, fused=True))
     return jobs
 
 
@@ -86,18 +89,20 @@ def _outs(jobs):
                             j.alpha.cpu().numpy()]) for j in jobs]
 
 
+@pytest.mark.parametrize("maps", ["stored", "workspace"])
 @pytest.mark.parametrize("path", ["fp64", "mixed"])
 @pytest.mark.parametrize("n", [3, 2])
-def test_batch_eager_graph_oracle(mocks, oracle_first, path, n):
+def test_batch_eager_graph_oracle(mocks, oracle_first, path, n, maps):
     import paper_2108_00015_amd as ck
     dtype = torch.float64 if path == "fp64" else torch.float32
     prec = "f64" if path == "fp64" else "split_bf16"
     tol_self = 1e-12 if path == "fp64" else 1e-5     # atomics reorder the scatter sums
     tol_ref = 1e-12 if path == "fp64" else 1e-5
-    _say("batch", path, "n=%d" % n, [g for g, _ in MOCKS])
+    _say("batch", path, "n=%d" % n, maps, [g for g, _ in MOCKS])
     s = torch.cuda.Stream()
     ctx = ck.Context(0, stream=s)
-    jobs = _build(ck, ctx, mocks, n, dtype, prec)
+    jobs = _build(ck, ctx, mocks, n, dtype, prec, stored=maps == "stored")
+    assert all((j.maps_N is None) == (maps == "workspace") for j in jobs)
     torch.cuda.synchronize()
     ctx.batch_plan(jobs)
     first = _outs(jobs)
@@ -142,7 +147,7 @@ def test_batch_rejects_bad_jobs(mocks):
     with pytest.raises(ck.ConkerError):
         ctx.batch_plan(jobs)
     jobs[0].n = 3
-    jobs[0].maps_N = None
+    jobs[0].maps_N = None           # maps_R still given
     with pytest.raises(ck.ConkerError):
         ctx.batch_plan(jobs)
     with pytest.raises(ck.ConkerError):

@@ -71,8 +71,13 @@ def test_cap512_full_size_sampled(cap, path):
     dpos, rpos = torch.from_numpy(data.pos).to(dev), torch.from_numpy(rand.pos).to(dev)
     dw, rw = torch.from_numpy(data.w).to(dev), torch.from_numpy(rand.w).to(dev)
     ns = len(w.radii)
-    for n in (3, 2):
-        out = ck.npcf(ctx, grid, dpos, rpos, ks, n, dw, rw, precision=prec, dtype=dt)
+    # one call for convolution and summation (float64: maps of carrying lines in
+    # the context's workspace), then for float64 the separate calls, whose maps
+    # are checked below
+    runs = [(3, None), (2, None)] + ([(3, False)] if path == "fp64" else [])
+    for n, fused in runs:
+        _say("  n=%d fused=%s" % (n, fused))
+        out = ck.npcf(ctx, grid, dpos, rpos, ks, n, dw, rw, precision=prec, dtype=dt, fused=fused)
         tl, rd, rr = o["ref"][n]
         gd = _pick(out["W_delta"].cpu().numpy(), ns, n, tl)
         gr = _pick(out["W_rand_raw"].cpu().numpy(), ns, n, tl)

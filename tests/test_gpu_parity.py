@@ -517,20 +517,53 @@ def test_fused_convolve_contract_vs_oracle(ck, ctx, line512_fields, prec, n, ns)
     assert ea <= 1e-5 and eb <= 1e-5
 
 
-def test_fused_single_field_and_unsupported(ck, ctx, line512_fields):
+def test_convolve_contract_single_field_and_routes(ck, ctx, line512_fields):
+    """One field; the fused kernel (n = 3), the workspace maps (n = 4, and a z axis of
+    256 cells), and argument errors."""
     dims, radii, A, B, maps_a, maps_b = line512_fields
     grid = ck.Grid(dims, (0, 0, 0), 1.0)
     ks, _ = ctx.make_shell_kernels(grid, radii[:5], torch.float32)
     Wa, Wb = ctx.convolve_contract(grid, _gpu(A, torch.float32), None, ks, 3, "split_bf16")
     assert Wb is None
     assert relerr(Wa.cpu().numpy(), oc.contract(A, maps_a[:5], 3)) <= 1e-5
-    with pytest.raises(ck.ConkerError) as e:
-        ctx.convolve_contract(grid, _gpu(A, torch.float32), None, ks, 4, "split_bf16")
-    assert "UNSUPPORTED" in str(e.value)
+    W4, _ = ctx.convolve_contract(grid, _gpu(A, torch.float32), None, ks, 4, "split_bf16")
+    assert relerr(W4.cpu().numpy(), oc.contract(A, maps_a[:5], 4)) <= 1e-5
+    rng = np.random.default_rng(23)
+    A2 = rng.normal(size=(32, 32, 256)).astype(np.float32).astype(np.float64)
     g2 = ck.Grid((32, 32, 256), (0, 0, 0), 1.0)
     ks2, _ = ctx.make_shell_kernels(g2, radii[:3], torch.float32)
+    W2, _ = ctx.convolve_contract(g2, _gpu(A2, torch.float32), None, ks2, 3, "split_bf16")
+    assert relerr(W2.cpu().numpy(), oc.contract(A2, oc.convolve_shells(A2, radii[:3]), 3)) <= 1e-5
     with pytest.raises(ck.ConkerError):
-        ctx.convolve_contract(g2, torch.zeros((32, 32, 256), device=DEV), None, ks2, 3, "split_bf16")
+        ctx.convolve_contract(grid, _gpu(A, torch.float32), None, ks, 6, "split_bf16")   # n outside 2..5
+    with pytest.raises(ck.ConkerError):
+        ctx.convolve_contract(grid, _gpu(A, torch.float32), None, ks, 3, "f64")          # f64 sums, f32 field
+
+
+WORKSPACE_CASES = [
+    ("f64", 2, 30), ("f64", 3, 30), ("f64", 4, 10), ("f64", 5, 6),
+    ("f32", 4, 12), ("split_bf16", 4, 12), ("split_f16", 4, 12), ("split_f16", 3, 30), ("split_bf16", 5, 6),
+]
+
+
+@pytest.mark.parametrize("prec,n,ns", WORKSPACE_CASES)
+def test_convolve_contract_workspace_maps_sparse_vs_oracle(ck, ctx, sparse512_fields, prec, n, ns):
+    """Orders and precisions beyond the fused kernel: the maps of the carrying lines only, in
+    the context's workspace, on fields zero outside a cylinder of lines and on whole slabs."""
+    dims, radii, A, B, keep, maps_a, maps_b = sparse512_fields
+    dt = torch.float64 if prec == "f64" else torch.float32
+    _say("workspace maps", prec, n, ns)
+    grid = ck.Grid(dims, (0, 0, 0), 1.0)
+    ks, _ = ctx.make_shell_kernels(grid, radii[:ns], dt)
+    Wa, Wb = ctx.convolve_contract(grid, _gpu(A, dt), _gpu(B, dt), ks, n, prec)
+    ref_a, ref_b = oc.contract(A, maps_a[:ns], n), oc.contract(B, maps_b[:ns], n)
+    # A is zero-mean noise (cancelling terms): its error is bounded by sum |F| |C_a| ...
+    scale_a = oc.contract(np.abs(A), np.abs(maps_a[:ns]), n)
+    ta = float(np.abs(Wa.cpu().numpy() - ref_a).max() / np.abs(scale_a).max())
+    eb = relerr(Wb.cpu().numpy(), ref_b)
+    _say("  err a %.3e (of the terms) b %.3e" % (ta, eb))
+    tol = 1e-12 if prec == "f64" else 1e-5
+    assert ta <= tol and eb <= tol
 
 
 def test_fused_matches_separate_calls_bitwise_order_free(ck, ctx, line512_fields):

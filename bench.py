@@ -63,8 +63,8 @@ def kernel_bytes(kind, n_launch_units, nc, ns, kel, n_data, n_rand, weighted, es
         return 6 * nc * esize
     if kind == "diag_zinv":
         return ns * fl * nc * c + 2 * fl * nc * esize
-    if kind == "fft_inv_z":       # complex in, two real maps out
-        return ns * (nc * c + 2 * nc * esize)
+    if kind == "fft_inv_z":       # complex in, two real maps out (carrying lines, or every line)
+        return ns * fl * (nc * c + 2 * nc * esize)
     if kind == "scatter":         # positions (+ weights) in, one grid value read-modify-write per point
         per = 12 + (4 if weighted else 0) + 2 * esize
         return (n_data + n_rand) * per
@@ -148,9 +148,10 @@ AXIS_ORDERS = {1: (0, 1, 2), 2: (0, 2, 1), 3: (1, 0, 2), 4: (1, 2, 0), 5: (2, 0,
 
 def support_fractions(w, data, rand, order=1):
     """For the axes transformed in `order` (1..6, new axis k = old axis
-    AXIS_ORDERS[order][k]): the fraction of first-axis slabs and of lines along
-    the last axis holding at least one catalog point (where N or R_raw can be
-    non-zero)."""
+    AXIS_ORDERS[order][k]): the fraction of first-axis slabs, of lines along
+    the last axis and of 64-cell blocks of the permuted grid (runs of 64 cells
+    along that axis, the unit the summation skips) holding at least one
+    catalog point (where N or R_raw can be non-zero)."""
     dims = np.asarray(w.dims)
     occ = np.zeros(tuple(int(d) for d in dims), dtype=bool)
     o = np.asarray(w.origin, dtype=np.float64)
@@ -163,7 +164,15 @@ def support_fractions(w, data, rand, order=1):
     others = tuple(a for a in range(3) if a != first)
     fx = float(occ.any(axis=others).mean())
     fl = float(occ.any(axis=last).mean())
-    return fx, fl
+    lines = np.moveaxis(occ, last, -1)
+    n_last = lines.shape[-1]
+    if n_last % 64 == 0:
+        fb = float(lines.reshape(-1, n_last // 64, 64).any(axis=2).mean())
+    else:   # blocks straddle lines: count them on the flat permuted grid
+        flat = np.moveaxis(occ, AXIS_ORDERS[order], (0, 1, 2)).reshape(-1)
+        pad = (-flat.size) % 64
+        fb = float(np.concatenate([flat, np.zeros(pad, bool)]).reshape(-1, 64).any(axis=1).mean())
+    return fx, fl, fb
 
 
 def cpu_baseline(w, data, rand, n, sample_radii=1):
@@ -387,7 +396,9 @@ def main():
 
     batch = min(int(os.environ.get("CONKER_RADIUS_BATCH", str(ns))), ns)
     order = mixed["axis_order"]
-    fx, fl = support_fractions(w, data, rand, order)
+    fx, fl, fb = support_fractions(w, data, rand, order)
+    if args.field_at_a_time:   # conker_convolve_shells: every slab and line, full maps
+        fx = fl = 1.0
     stages = {}
     for kind, (launches, tot) in mixed["prof"].items():
         per_step = tot / args.steps
@@ -395,8 +406,8 @@ def main():
         if kind == "support" and "axis_order" in mixed["prof"]:
             # built from the axis-order projections: line mask, slab counts and list written
             b = (launches / args.steps) * (nc ** (2.0 / 3.0)) * 5
-        if kind == "contract_mm":
-            b = 2 * (ns + 1) * nc * 4
+        if kind == "contract_mm":   # maps and field of both fields, on the summed blocks
+            b = 2 * (ns + 1) * fb * nc * 4
         ent = dict(launches_per_step=launches / args.steps, ms_per_step=per_step,
                    avg_launch_ms=tot / launches)
         if b is not None:
@@ -406,14 +417,14 @@ def main():
     # matrix-core use of the separate summation (orders n >= 3)
     if "contract_mm" in stages and args.n >= 3:
         tiles = summation_tiles(ns, args.n)
-        issued = 2.0 * tiles * 1024 * nc * TERM_PRODUCTS[args.prec]       # per field
+        issued = 2.0 * tiles * 1024 * fb * nc * TERM_PRODUCTS[args.prec]       # per field, summed blocks
         per_launch_ms = stages["contract_mm"]["avg_launch_ms"]
         tflops = issued / (per_launch_ms * 1e-3) / 1e12
         ent = stages["contract_mm"]
         ent["mfma_tiles"] = tiles
         ent["mfma_issued_tflops"] = round(tflops, 2)
         ent["mfma_frac_of_peak"] = round(tflops / MFMA_PEAK_TFLOPS[args.prec], 4)
-        ent["tuple_cells_per_s"] = round(comb_tuples(ns, args.n) * nc / (per_launch_ms * 1e-3), 1)
+        ent["tuple_cells_per_s"] = round(comb_tuples(ns, args.n) * fb * nc / (per_launch_ms * 1e-3), 1)
     # dominant kernel: largest time per step
     dom = max(stages.items(), key=lambda kv: kv[1]["ms_per_step"]) if stages else None
     roof = None
@@ -450,9 +461,11 @@ def main():
                    "n_randoms": len(rand), "weights": "log-normal sigma 0.2" if data.w is not None else "unit",
                    "summation": args.prec, "fft": "f32", "mode": args.mode,
                    "maps": ("never stored" if (args.mode != "npcf" or stages_use_fused(mixed["prof"]))
-                            else ("one field at a time" if args.field_at_a_time else "both fields")),
+                            else ("one field at a time" if args.field_at_a_time
+                                  else "carrying lines, in the workspace")),
                    "axis_order": "".join("xyz"[a] for a in AXIS_ORDERS[order]),
                    "carrying_lines": round(fl, 4), "first_axis_slabs": round(fx, 4),
+                   "summed_blocks": round(fb, 4),
                    **({"tune": args.tune} if args.tune else {})},
         "s_to_W3_mixed": round(s_mixed, 5),
         "s_to_W3_fp64": round(fp64["ms"] / 1e3, 5) if fp64 else None,

@@ -177,8 +177,11 @@ int support_list(conker_ctx *c, int nx, int ny, const Support &s);
 // FFT passes (fft.hip) ------------------------------------------------------
 // Forward 3D FFT of the complex field packed from two real fields
 // (a + i b) into the spectrum buffer `spec` (natural order, unnormalised).
+// With `sup`, the line support of a and b themselves (both zero on every other
+// line): inputs known to be zero are neither written between the passes nor
+// read.
 int fft_forward_pair(conker_ctx *ctx, const conker_grid *g, bool f64,
-                     const void *a, const void *b, void *spec);
+                     const void *a, const void *b, void *spec, const Support *sup = nullptr);
 // Forward 3D FFT of two shell indicators packed as (K_ra + i K_rb), float64,
 // followed by extraction of the real octant spectra (scaled by 1/N_c) into
 // kspec rows ma and mb (mb < 0: none) with dtype out_f64 ? double : float.

@@ -197,7 +197,9 @@ static int convolve_diag(conker_ctx *c, const conker_grid *g, conker_dtype dt, c
     CK_OK(ws_reserve(c, c->partial, (size_t)n_radii * blocks * 2 * P * sizeof(double)));
     double *part = (double *)c->partial.p;
     if (!have_sup) CK_OK(support_lines(c, g, f64, ca, cb, &sup));
-    CK_OK(fft_forward_pair(c, g, f64, fa, fb, c->spec.p));
+    // the convolved fields are the centre fields (auto-correlation): their
+    // support also prunes the forward transform
+    CK_OK(fft_forward_pair(c, g, f64, fa, fb, c->spec.p, (fa == ca && fb == cb) ? &sup : nullptr));
     for (int m0 = 0; m0 < n_radii; m0 += B) {
         const int nb = (m0 + B <= n_radii) ? B : n_radii - m0;
         CK_OK(fft_inverse_batch(c, g, f64, c->spec.p, kspec, m0, nb, c->tspec.p, nullptr, nullptr, &sup));

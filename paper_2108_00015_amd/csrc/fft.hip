@@ -244,6 +244,13 @@ struct has_active : std::false_type {};
 template <class Op>
 struct has_active<Op, std::void_t<decltype(std::declval<const Op &>().active())>> : std::true_type {};
 
+// Ops with rowflag(i) and wants_rowf() read only the rows of a tile whose flag
+// is set (the others are zero); the flags of the tile are staged in LDS once.
+template <class Op, class = void>
+struct has_rowf : std::false_type {};
+template <class Op>
+struct has_rowf<Op, std::void_t<decltype(std::declval<const Op &>().rowflag(0))>> : std::true_type {};
+
 // One launch = one pass over one axis.  Op::iters() line transforms are run
 // per tile (more than one when a tile is reused across several radii).
 template <typename T, int L, int MODE, int DIR, class Op>
@@ -252,12 +259,19 @@ __global__ __launch_bounds__((Shape<T, L, MODE>::NT), (Shape<T, L, MODE>::MINW))
     using SH = Shape<T, L, MODE>;
     __shared__ C lds[SH::LDS];
     __shared__ C tw[L];
+    __shared__ unsigned char rowf[has_rowf<Op>::value ? L : 1];
     const C *twg = reinterpret_cast<const C *>(op.tw);
     op.template begin<SH::TC>();
     if constexpr (has_active<Op>::value) {
         if (!op.active()) return;   // the same for every thread of the workgroup
     }
     for (int t = threadIdx.x; t < L; t += SH::NT) tw[t] = twg[t];
+    if constexpr (has_rowf<Op>::value) {
+        if (op.wants_rowf()) {   // the same for every thread
+            for (int t = threadIdx.x; t < L; t += SH::NT) rowf[t] = op.rowflag(t);
+            op.rowf = rowf;
+        }
+    }
     __syncthreads();
     const int it_n = op.iters();
     for (int it = 0; it < it_n; ++it) {
@@ -314,6 +328,9 @@ __device__ __forceinline__ int fold(int k, int n) { return k <= n - k ? k : n - 
 // ---------------------------------------------------------------------------
 // operators
 // ---------------------------------------------------------------------------
+// With `mask` (line flags [nx * ny], both fields zero on lines without one):
+// z-line tiles without a flagged line do nothing, and only flagged lines are
+// written (the y pass then reads the others as zero).
 template <typename T>
 struct OpPack {
     static constexpr bool STAGED = false;   // z pass, forward: (a + i b) -> spec
@@ -324,11 +341,20 @@ struct OpPack {
     const T *b;
     C *out;
     Tile g;
+    const unsigned char *mask;
+    int tcn;
     template <int TC> __device__ void begin() {
         g = make_tile(AX_Z, d, blockIdx.x, TC);
+        tcn = TC;
         a += g.base;
         if (b) b += g.base;
         out += g.base;
+    }
+    __device__ bool active() const {   // the same for every thread: any line of the tile flagged
+        if (!mask) return true;
+        int any = 0;
+        for (int k = 0; k < tcn; ++k) any |= mask[(size_t)g.p0 + k];
+        return any != 0;
     }
     __device__ int iters() const { return 1; }
     __device__ void set_iter(int) {}
@@ -336,11 +362,17 @@ struct OpPack {
         const unsigned k = off(g, i, c);
         return C{a[k], b ? b[k] : (T)0};
     }
-    __device__ void store(int i, int c, C v) const { out[off(g, i, c)] = v; }
+    __device__ void store(int i, int c, C v) const {
+        if (mask && !mask[(size_t)g.p0 + c]) return;
+        out[off(g, i, c)] = v;
+    }
 };
 
 // With `xcount` and `mask` (y axis only): tiles of x-slabs without carrying
 // lines do nothing, and only rows y of carrying lines (x, y) are written.
+// Inputs known to be zero are not read: with `lmask` (y axis), rows y of lines
+// (x, y) without a flag; with `lxcount` (x axis), rows x of slabs without a
+// carrying line.
 template <typename T>
 struct OpInplace {
     static constexpr bool STAGED = false;   // any axis, in place; blockIdx.y selects a grid of the batch
@@ -354,14 +386,25 @@ struct OpInplace {
     C *p;
     const unsigned char *mask;
     const int *xcount;
+    const unsigned char *lmask;
+    const int *lxcount;
+    const unsigned char *rowf = nullptr;   // LDS: the tile's row flags from lmask / lxcount
     template <int TC> __device__ void begin() {
         g = make_tile(axis, d, blockIdx.x, TC);
         p = buf + (size_t)blockIdx.y * nc + g.base;
     }
     __device__ bool active() const { return !xcount || xcount[g.p0] > 0; }
+    __device__ bool wants_rowf() const { return lmask != nullptr || lxcount != nullptr; }
+    __device__ unsigned char rowflag(int i) const {
+        if (lmask) return lmask[(size_t)g.p0 * d.ny + i];
+        return lxcount[i] > 0 ? 1 : 0;
+    }
     __device__ int iters() const { return 1; }
     __device__ void set_iter(int) {}
-    __device__ C load(int i, int c) const { return p[off(g, i, c)]; }
+    __device__ C load(int i, int c) const {
+        if (rowf && !rowf[i]) return C{};
+        return p[off(g, i, c)];
+    }
     __device__ bool keeps() const { return mask != nullptr; }
     __device__ int flag(int i) const { return mask[(size_t)g.p0 * d.ny + i]; }
     __device__ void store(int i, int c, C v) const { p[off(g, i, c)] = v; }   // rows with a flag
@@ -891,7 +934,8 @@ int launch_len(conker_ctx *ctx, int kind, int mode, int L, int axis, const Dims 
 }
 
 template <typename T>
-int forward_pair_t(conker_ctx *ctx, const conker_grid *g, const void *a, const void *b, void *spec) {
+int forward_pair_t(conker_ctx *ctx, const conker_grid *g, const void *a, const void *b, void *spec,
+                   const Support *sup) {
     using C = cplx<T>;
     const bool f64 = std::is_same<T, double>::value;
     Dims d{g->dims[0], g->dims[1], g->dims[2]};
@@ -900,11 +944,15 @@ int forward_pair_t(conker_ctx *ctx, const conker_grid *g, const void *a, const v
     CK_OK(twiddles(ctx, d.ny, f64, &twy));
     CK_OK(twiddles(ctx, d.nx, f64, &twx));
     const size_t nc = ncells(g);
-    OpPack<T> pz{twz, d, (const T *)a, (const T *)b, (C *)spec, {}};
+    // with the fields' support: the z pass writes carrying lines, the y pass
+    // reads them in carrying slabs only, the x pass reads carrying slabs
+    const unsigned char *mask = sup ? sup->mask : nullptr;
+    const int *xcount = sup ? sup->xcount : nullptr;
+    OpPack<T> pz{twz, d, (const T *)a, (const T *)b, (C *)spec, {}, mask, 0};
     CK_OK((launch_len<T, -1>(ctx, PK_FFT_FWD_Z, TM_J, d.nz, AX_Z, d, dim3(1, 1), pz)));
-    OpInplace<T> py{twy, d, AX_Y, (C *)spec, nc, {}, nullptr};
+    OpInplace<T> py{twy, d, AX_Y, (C *)spec, nc, {}, nullptr, nullptr, xcount, mask, nullptr};
     CK_OK((launch_len<T, -1>(ctx, PK_FFT_FWD_Y, col_mode_for<T>(ctx, d, AX_Y), d.ny, AX_Y, d, dim3(1, 1), py)));
-    OpInplace<T> px{twx, d, AX_X, (C *)spec, nc, {}, nullptr};
+    OpInplace<T> px{twx, d, AX_X, (C *)spec, nc, {}, nullptr, nullptr, nullptr, nullptr, xcount};
     CK_OK((launch_len<T, -1>(ctx, PK_FFT_FWD_X, col_mode_for<T>(ctx, d, AX_X), d.nx, AX_X, d, dim3(1, 1), px)));
     return CONKER_OK;
 }
@@ -1062,8 +1110,8 @@ int fft_z_tiles(const conker_grid *g, bool f64) {
 }
 
 int fft_forward_pair(conker_ctx *ctx, const conker_grid *g, bool f64, const void *a, const void *b,
-                     void *spec) {
-    return f64 ? forward_pair_t<double>(ctx, g, a, b, spec) : forward_pair_t<float>(ctx, g, a, b, spec);
+                     void *spec, const Support *sup) {
+    return f64 ? forward_pair_t<double>(ctx, g, a, b, spec, sup) : forward_pair_t<float>(ctx, g, a, b, spec, sup);
 }
 
 int fft_inverse_batch(conker_ctx *ctx, const conker_grid *g, bool f64, const void *spec,

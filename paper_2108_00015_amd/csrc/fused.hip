@@ -315,7 +315,9 @@ static int convolve_contract_maps(conker_ctx *c, const conker_grid *g, conker_dt
     if (!have_sup) CK_OK(support_lines(c, g, f64, ca, cb, &sup));
     void *ma = c->maps.p;
     void *mb = fb ? (void *)((char *)c->maps.p + mbytes) : nullptr;
-    CK_OK(fft_forward_pair(c, g, f64, fa, fb, c->spec.p));
+    // the convolved fields are the centre fields (auto-correlation): their
+    // support also prunes the forward transform
+    CK_OK(fft_forward_pair(c, g, f64, fa, fb, c->spec.p, (fa == ca && fb == cb) ? &sup : nullptr));
     for (int m0 = 0; m0 < ns; m0 += B) {
         const int nb = (m0 + B <= ns) ? B : ns - m0;
         CK_OK(fft_inverse_batch(c, g, f64, c->spec.p, kspec, m0, nb, c->tspec.p, ma, mb, &sup, 0, true));
@@ -351,7 +353,7 @@ static int convolve_contract(conker_ctx *c, const conker_grid *g, conker_dtype d
     CK_OK(ws_reserve(c, c->spec, cbytes));
     CK_OK(ws_reserve(c, c->tspec, (size_t)ns * cbytes));
     if (!have_sup) CK_OK(support_lines(c, g, false, ca, cb, &sup));
-    CK_OK(fft_forward_pair(c, g, false, fa, fb, c->spec.p));
+    CK_OK(fft_forward_pair(c, g, false, fa, fb, c->spec.p, (fa == ca && fb == cb) ? &sup : nullptr));
     CK_OK(fft_inverse_batch(c, g, false, c->spec.p, kspec, 0, ns, c->tspec.p, nullptr, nullptr, &sup));
     const void *twz;
     CK_OK(twiddles(c, NZ, false, &twz));

@@ -9,10 +9,11 @@
 // is fixed, so the split of the list over workgroups, and with it every
 // floating-point sum, is the same from run to run.
 //   k_blk_mark   one bit per block and the number of marked blocks per
-//                workgroup (2048 blocks each), from coalesced 16-byte loads;
+//                workgroup (256 blocks each), from coalesced 16-byte loads;
 //   k_blk_scan   exclusive prefix sum of the workgroup counts, and the total;
-//   k_blk_place  one wave per workgroup range writes the indices of its
-//                marked blocks at its offset.
+//   k_blk_place  one wave per 2048 blocks (64 words, eight mark workgroups)
+//                writes the indices of its marked blocks from the offset of
+//                its first mark workgroup.
 // No memset: every word of the workspace read later is written first, so the
 // three launches may be captured in a graph.
 #include <cstdint>
@@ -25,7 +26,8 @@ using namespace conker;
 namespace {
 
 constexpr int BK_T = 256;      // threads of the mark pass
-constexpr int BK_PER = 2048;   // blocks per mark / place workgroup: 64 words of 32 bits
+constexpr int BK_PER = 256;    // blocks per mark workgroup: 8 words of 32 bits
+constexpr int PL_WORDS = 64;   // words per place wave: 2048 blocks
 constexpr int BK_S = 1024;     // threads of the scan
 
 template <typename T>
@@ -100,18 +102,20 @@ __global__ __launch_bounds__(BK_S) void k_blk_scan(const unsigned *__restrict__ 
     if (t == BK_S - 1) total[0] = (int)part[t];
 }
 
-__global__ __launch_bounds__(64) void k_blk_place(const unsigned *__restrict__ bits,
+__global__ __launch_bounds__(64) void k_blk_place(const unsigned *__restrict__ bits, size_t nwords,
                                                   const unsigned *__restrict__ wgoff, int *__restrict__ list) {
+    static_assert(PL_WORDS * 32 % BK_PER == 0, "a place wave covers whole mark workgroups");
     const int lane = threadIdx.x;   // word `lane` of this range: blocks base .. base + 31
-    const unsigned word = bits[(size_t)blockIdx.x * (BK_PER / 32) + lane];
+    const size_t wi = (size_t)blockIdx.x * PL_WORDS + lane;
+    const unsigned word = wi < nwords ? bits[wi] : 0u;
     const int c = __popc(word);
     int incl = c;
     for (int o = 1; o < 64; o <<= 1) {
         const int v = __shfl_up(incl, o);
         if (lane >= o) incl += v;
     }
-    int pos = (int)wgoff[blockIdx.x] + incl - c;
-    const int base = blockIdx.x * BK_PER + lane * 32;
+    int pos = (int)wgoff[(size_t)blockIdx.x * (PL_WORDS * 32 / BK_PER)] + incl - c;
+    const int base = (int)(wi * 32);
     unsigned rest = word;
     while (rest) {
         const int j = __ffs(rest) - 1;
@@ -128,7 +132,7 @@ int block_list(conker_ctx *c, const void *F, bool f64, size_t nc, const int **li
     if (nc % 16) return fail(c, CONKER_EUNSUPPORTED, "cell count must be a multiple of 16");
     const size_t nblk = (nc + 63) / 64;
     const size_t ng = (nblk + BK_PER - 1) / BK_PER;
-    // workspace: bits [ng * 64], wgcnt [ng], wgoff [ng], total [4], list [nblk]
+    // workspace: bits [ng * 8], wgcnt [ng], wgoff [ng], total [4], list [nblk]
     const size_t words = ng * (BK_PER / 32);
     const size_t bytes = (words + 2 * ng + 4) * sizeof(unsigned) + nblk * sizeof(int);
     CK_OK(ws_reserve(c, c->blocks, bytes));
@@ -147,7 +151,9 @@ int block_list(conker_ctx *c, const void *F, bool f64, size_t nc, const int **li
     CK_LAUNCH(c);
     hipLaunchKernelGGL(k_blk_scan, dim3(1), dim3(BK_S), 0, c->stream, wgcnt, (int)ng, wgoff, total);
     CK_LAUNCH(c);
-    hipLaunchKernelGGL(k_blk_place, dim3((unsigned)ng), dim3(64), 0, c->stream, bits, wgoff, lst);
+    const size_t np = (words + PL_WORDS - 1) / PL_WORDS;
+    hipLaunchKernelGGL(k_blk_place, dim3((unsigned)np), dim3(64), 0, c->stream, (const unsigned *)bits, words, wgoff,
+                       lst);
     CK_LAUNCH(c);
     *list = lst;
     *count = total;

@@ -59,7 +59,9 @@ struct Blocks {
 };
 
 __device__ __forceinline__ Blocks my_blocks(const int *list, const int *count, size_t nc) {
-    const long n = list ? (long)*count : (long)((nc + 63) / 64);
+    const long nall = (long)((nc + 63) / 64);
+    const long n = list ? (long)*count : nall;
+    if (n == nall) list = nullptr;   // every block listed: they are 0 .. nall - 1 in order
     const long per = (n + (long)gridDim.x - 1) / (long)gridDim.x;
     const long k0 = (long)blockIdx.x * per;
     return Blocks{list, (int)(k0 < n ? k0 : n), (int)(k0 + per < n ? k0 + per : n)};
@@ -231,8 +233,11 @@ __global__ __launch_bounds__(NT) void k_mm_f64(const double *__restrict__ F, con
     const Blocks bk = my_blocks(list, count, nc);
     size_t xb = bk.k0 < bk.k1 ? bk.first(bk.k0) : 0;
     for (int k = bk.k0; k < bk.k1; ++k) {
-    const size_t xn = k + 1 < bk.k1 ? bk.first(k + 1) : 0, xe = std::min(xb + 64, nc);
-    for (size_t x0 = xb + (size_t)w * CPI; x0 < xe; x0 += (size_t)WAVES * CPI) {
+    const size_t xn = k + 1 < bk.k1 ? bk.first(k + 1) : 0;
+#pragma unroll
+    for (int u = 0; u < 64 / (WAVES * CPI); ++u) {   // this wave's cells of the block
+        const size_t x0 = xb + (size_t)(u * WAVES + w) * CPI;
+        if (x0 >= nc) break;   // the last block of the grid may be partial
         const size_t x = x0 + 2 * h;
         double fv[2];
         ld<double, 2>(F + x, fv);
@@ -291,8 +296,11 @@ __global__ __launch_bounds__(NT) void k_mm_f32(const float *__restrict__ F, cons
     size_t xb = bk.k0 < bk.k1 ? bk.first(bk.k0) : 0;
     int cnt = 0;
     for (int k = bk.k0; k < bk.k1; ++k) {
-    const size_t xn = k + 1 < bk.k1 ? bk.first(k + 1) : 0, xe = std::min(xb + 64, nc);
-    for (size_t x0 = xb + (size_t)w * CPI; x0 < xe; x0 += (size_t)WAVES * CPI) {
+    const size_t xn = k + 1 < bk.k1 ? bk.first(k + 1) : 0;
+#pragma unroll
+    for (int u = 0; u < 64 / (WAVES * CPI); ++u) {   // this wave's cells of the block
+        const size_t x0 = xb + (size_t)(u * WAVES + w) * CPI;
+        if (x0 >= nc) break;   // the last block of the grid may be partial
         const size_t x = x0 + 4 * h;
         float f[4];
         ld<float, 4>(F + x, f);
@@ -462,8 +470,11 @@ __global__ __launch_bounds__(NT) void k_mm_split(const float *__restrict__ F, co
     size_t xb = bk.k0 < bk.k1 ? bk.first(bk.k0) : 0;
     int cnt = 0;
     for (int k = bk.k0; k < bk.k1; ++k) {
-    const size_t xn = k + 1 < bk.k1 ? bk.first(k + 1) : 0, xe = std::min(xb + 64, nc);
-    for (size_t x0 = xb + (size_t)w * CPI; x0 < xe; x0 += (size_t)WAVES * CPI) {
+    const size_t xn = k + 1 < bk.k1 ? bk.first(k + 1) : 0;
+#pragma unroll
+    for (int u = 0; u < 64 / (WAVES * CPI); ++u) {   // this wave's cells of the block
+        const size_t x0 = xb + (size_t)(u * WAVES + w) * CPI;
+        if (x0 >= nc) break;   // the last block of the grid may be partial
         const size_t x = x0 + 8 * h;
         float f[8];
         ld<float, 8>(F + x, f);

@@ -244,12 +244,13 @@ struct has_active : std::false_type {};
 template <class Op>
 struct has_active<Op, std::void_t<decltype(std::declval<const Op &>().active())>> : std::true_type {};
 
-// Ops with rowflag(i) and wants_rowf() read only the rows of a tile whose flag
-// is set (the others are zero); the flags of the tile are staged in LDS once.
+// Ops with ROWF = true (and rowflag(i), wants_rowf()) read only the rows of a
+// tile whose flag is set (the others are zero); the flags of the tile are
+// staged in LDS once.
 template <class Op, class = void>
 struct has_rowf : std::false_type {};
 template <class Op>
-struct has_rowf<Op, std::void_t<decltype(std::declval<const Op &>().rowflag(0))>> : std::true_type {};
+struct has_rowf<Op, std::enable_if_t<Op::ROWF>> : std::true_type {};
 
 // One launch = one pass over one axis.  Op::iters() line transforms are run
 // per tile (more than one when a tile is reused across several radii).
@@ -370,12 +371,13 @@ struct OpPack {
 
 // With `xcount` and `mask` (y axis only): tiles of x-slabs without carrying
 // lines do nothing, and only rows y of carrying lines (x, y) are written.
-// Inputs known to be zero are not read: with `lmask` (y axis), rows y of lines
-// (x, y) without a flag; with `lxcount` (x axis), rows x of slabs without a
-// carrying line.
-template <typename T>
+// RF: inputs known to be zero are not read: with `lmask` (y axis), rows y of
+// lines (x, y) without a flag; with `lxcount` (x axis), rows x of slabs without
+// a carrying line.
+template <typename T, bool RF = false>
 struct OpInplace {
     static constexpr bool STAGED = false;   // any axis, in place; blockIdx.y selects a grid of the batch
+    static constexpr bool ROWF = RF;
     using C = cplx<T>;
     const void *tw;
     Dims d;
@@ -402,7 +404,9 @@ struct OpInplace {
     __device__ int iters() const { return 1; }
     __device__ void set_iter(int) {}
     __device__ C load(int i, int c) const {
-        if (rowf && !rowf[i]) return C{};
+        if constexpr (RF) {
+            if (rowf && !rowf[i]) return C{};
+        }
         return p[off(g, i, c)];
     }
     __device__ bool keeps() const { return mask != nullptr; }
@@ -950,9 +954,9 @@ int forward_pair_t(conker_ctx *ctx, const conker_grid *g, const void *a, const v
     const int *xcount = sup ? sup->xcount : nullptr;
     OpPack<T> pz{twz, d, (const T *)a, (const T *)b, (C *)spec, {}, mask, 0};
     CK_OK((launch_len<T, -1>(ctx, PK_FFT_FWD_Z, TM_J, d.nz, AX_Z, d, dim3(1, 1), pz)));
-    OpInplace<T> py{twy, d, AX_Y, (C *)spec, nc, {}, nullptr, nullptr, xcount, mask, nullptr};
+    OpInplace<T, true> py{twy, d, AX_Y, (C *)spec, nc, {}, nullptr, nullptr, xcount, mask, nullptr};
     CK_OK((launch_len<T, -1>(ctx, PK_FFT_FWD_Y, col_mode_for<T>(ctx, d, AX_Y), d.ny, AX_Y, d, dim3(1, 1), py)));
-    OpInplace<T> px{twx, d, AX_X, (C *)spec, nc, {}, nullptr, nullptr, nullptr, nullptr, xcount};
+    OpInplace<T, true> px{twx, d, AX_X, (C *)spec, nc, {}, nullptr, nullptr, nullptr, nullptr, xcount};
     CK_OK((launch_len<T, -1>(ctx, PK_FFT_FWD_X, col_mode_for<T>(ctx, d, AX_X), d.nx, AX_X, d, dim3(1, 1), px)));
     return CONKER_OK;
 }

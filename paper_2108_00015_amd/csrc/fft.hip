@@ -118,6 +118,31 @@ struct has_load_r : std::false_type {};
 template <class Op>
 struct has_load_r<Op, std::void_t<decltype(std::declval<const Op &>().load_r(0, 0, 0, 0))>> : std::true_type {};
 
+// TM_J tiles whose stages all give a line the same number of butterflies, a
+// divisor of 64 (512 = 8 8 8, 64 = 8 8): the threads of a line then lie in one
+// wave in every stage, each line owns its LDS rows, and an ordering within the
+// wave replaces the workgroup barrier between stages.
+template <int L>
+constexpr bool lines_in_wave() {
+    const int lr = L / Plan<L>::r[0];
+    if (64 % lr != 0) return false;
+    for (int s = 1; s < Plan<L>::n; ++s)
+        if (L / Plan<L>::r[s] != lr) return false;
+    return true;
+}
+
+__device__ __forceinline__ void wave_order() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int L, int MODE>
+__device__ __forceinline__ void stage_sync() {
+    if constexpr (MODE == TM_J && lines_in_wave<L>()) wave_order();
+    else __syncthreads();
+}
+
 // Stage S reads src (LDS; global memory or registers for the first stage) and
 // writes dst (LDS; global memory for the last stage).  SYNC: the stage places
 // its own barriers (src == dst, in place); otherwise the caller orders the
@@ -192,7 +217,7 @@ __device__ __forceinline__ void fft_stage(const cplx<T> *src, cplx<T> *dst, cons
     // in-place LDS stages wait for every read before any write; the last stage
     // writes global memory from registers, and every caller puts a barrier
     // between a tile's last stage and the next writes to the LDS tile
-    if constexpr (SYNC && !FIRST && !LAST) __syncthreads();
+    if constexpr (SYNC && !FIRST && !LAST) stage_sync<L, MODE>();
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
         const int b = threadIdx.x + q * NT;
@@ -214,7 +239,7 @@ __device__ __forceinline__ void fft_stage(const cplx<T> *src, cplx<T> *dst, cons
             }
         }
     }
-    if constexpr (SYNC && !LAST) __syncthreads();
+    if constexpr (SYNC && !LAST) stage_sync<L, MODE>();
 }
 
 // STAGED: the tile is first copied into LDS with a plain row loop (one load in

@@ -209,10 +209,11 @@ int fft_inverse_batch(conker_ctx *ctx, const conker_grid *g, bool f64,
 // real part against fa and the imaginary part against fb (NULL: none), in
 // place of storing the maps.  `blocks` workgroups per radius (at most
 // fft_z_tiles) each write one row of 2 * pmax doubles to
-// part[(m * blocks + block) * 2 * pmax], field a first.
+// part[(m * blocks + block) * 2 * pmax], field a first.  With `sup`, only its
+// list of carrying lines is transformed and summed (in tiles of listed lines).
 int fft_inverse_z_diag(conker_ctx *ctx, const conker_grid *g, bool f64, const void *tspec, int nb,
                        const void *fa, const void *fb, int pmax, int blocks, void *part,
-                       const unsigned char *mask = nullptr);
+                       const Support *sup = nullptr);
 
 // Device list of the 64-cell blocks (cells 64 k .. 64 k + 63) holding a cell
 // where F != 0, ascending (blocks.hip): *list = int[*count], both in device

@@ -204,7 +204,7 @@ static int convolve_diag(conker_ctx *c, const conker_grid *g, conker_dtype dt, c
         const int nb = (m0 + B <= n_radii) ? B : n_radii - m0;
         CK_OK(fft_inverse_batch(c, g, f64, c->spec.p, kspec, m0, nb, c->tspec.p, nullptr, nullptr, &sup));
         CK_OK(fft_inverse_z_diag(c, g, f64, c->tspec.p, nb, ca, cb, P, blocks,
-                                 part + (size_t)m0 * blocks * 2 * P, sup.mask));
+                                 part + (size_t)m0 * blocks * 2 * P, &sup));
     }
     return reduce(c, part, blocks, n_radii, 2, P, out_a, out_b);
 }

@@ -792,18 +792,21 @@ template <typename T, int P>
 struct OpDiag {
     static constexpr bool STAGED = false;
     using C = cplx<T>;
+    static constexpr unsigned NONE = 0xffffffffu;
     const C *src;
     const T *fa;
     const T *fb;
-    const unsigned char *mask;   // NULL, or this tile's line flags (LDS): others read as zero
-    Tile g;
+    const unsigned *row;   // LDS: first cell of each line of the tile, NONE for no line
     double acc[2][P];
     __device__ C load(int i, int c) const {
-        if (mask && !mask[c]) return C{(T)0, (T)0};
-        return src[off(g, i, c)];
+        const unsigned r = row[c];
+        if (r == NONE) return C{(T)0, (T)0};
+        return src[r + (unsigned)i];
     }
     __device__ void store(int i, int c, C v) {
-        const unsigned k = off(g, i, c);
+        const unsigned r = row[c];
+        if (r == NONE) return;
+        const unsigned k = r + (unsigned)i;
         const T a = fa[k];
         T pw = v.x;
         acc[0][0] += (double)(a * pw);
@@ -829,39 +832,37 @@ template <typename T, int L, int P>
 __global__ __launch_bounds__((Shape<T, L, TM_J>::NT), (Shape<T, L, TM_J>::MINW)) void k_zinv_diag(
     const cplx<T> *__restrict__ tspec, const T *__restrict__ fa, const T *__restrict__ fb,
     const cplx<T> *__restrict__ twg, Dims d, size_t nc, int tiles, double *__restrict__ part,
-    const unsigned char *__restrict__ mask) {
+    const int *__restrict__ list, const int *__restrict__ count) {
     using C = cplx<T>;
     using SH = Shape<T, L, TM_J>;
-    constexpr int NT = SH::NT, NW = NT / 64;
+    constexpr int NT = SH::NT, NW = NT / 64, TC = SH::TC;
     __shared__ C lds[SH::LDS];
     __shared__ C tw[L];
     __shared__ double red[NW][2 * P];
-    __shared__ unsigned char lmask[SH::TC];
+    __shared__ unsigned row[TC];
     for (int t = threadIdx.x; t < L; t += NT) tw[t] = twg[t];
     OpDiag<T, P> op;
 #pragma unroll
     for (int p = 0; p < P; ++p) op.acc[0][p] = op.acc[1][p] = 0.0;
-    op.mask = mask ? lmask : nullptr;
-    const C *base = tspec + (size_t)blockIdx.y * nc;
-    __syncthreads();
-    for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
-        if (mask) {   // this tile's line flags into LDS; a tile without carrying lines adds nothing
-            __syncthreads();   // the previous tile is done with lmask
-            int on = 0;
-            for (int c = threadIdx.x; c < SH::TC; c += NT) {
-                const unsigned char f = mask[tile * SH::TC + c];
-                lmask[c] = f;
-                on |= f;
-            }
-            if (!__syncthreads_or(on)) continue;   // uniform over the workgroup
+    op.row = row;
+    op.src = tspec + (size_t)blockIdx.y * nc;
+    op.fa = fa;
+    op.fb = fb;
+    // with a list: tiles of TC listed lines (the lines carrying field; the
+    // others add nothing), else tiles of TC consecutive lines
+    const int nlist = list ? *count : 0;
+    const int ntiles = list ? (nlist + TC - 1) / TC : tiles;
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        __syncthreads();   // the previous tile is done with row (and the twiddles are in)
+        for (int c = threadIdx.x; c < TC; c += NT) {
+            const int k = tile * TC + c;
+            row[c] = list ? (k < nlist ? (unsigned)list[k] * (unsigned)d.nz : OpDiag<T, P>::NONE)
+                          : (unsigned)k * (unsigned)d.nz;
         }
-        op.g = make_tile(AX_Z, d, tile, SH::TC);
-        op.src = base + op.g.base;
-        op.fa = fa + op.g.base;
-        op.fb = fb ? fb + op.g.base : nullptr;
-        fft_line_tile<T, L, TM_J, +1, false>(lds, tw, op);
         __syncthreads();
+        fft_line_tile<T, L, TM_J, +1, false>(lds, tw, op);
     }
+    __syncthreads();
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
     for (int f = 0; f < 2; ++f)
@@ -1077,7 +1078,7 @@ int inverse_batch_t(conker_ctx *ctx, const conker_grid *g, const void *spec, con
 
 template <typename T, int P>
 int zinv_diag_t(conker_ctx *ctx, const conker_grid *g, const void *tspec, int nb, const void *fa, const void *fb,
-                int blocks, void *part, const unsigned char *mask) {
+                int blocks, void *part, const int *list, const int *count) {
     using C = cplx<T>;
     const bool f64 = std::is_same<T, double>::value;
     Dims d{g->dims[0], g->dims[1], g->dims[2]};
@@ -1092,7 +1093,7 @@ int zinv_diag_t(conker_ctx *ctx, const conker_grid *g, const void *tspec, int nb
         ProfScope ps(ctx, PK_DIAG_Z);
         hipLaunchKernelGGL((k_zinv_diag<T, LL, P>), dim3((unsigned)blocks, (unsigned)nb), dim3(SH::NT), 0,
                            ctx->stream, (const C *)tspec, (const T *)fa, (const T *)fb, (const C *)twz, d, nc,
-                           tiles, (double *)part, mask);
+                           tiles, (double *)part, list, count);
         CK_LAUNCH(ctx);
         return CONKER_OK;
     };
@@ -1112,12 +1113,12 @@ int zinv_diag_t(conker_ctx *ctx, const conker_grid *g, const void *tspec, int nb
 
 template <typename T>
 int zinv_diag_p(conker_ctx *ctx, const conker_grid *g, const void *tspec, int nb, const void *fa, const void *fb,
-                int pmax, int blocks, void *part, const unsigned char *mask) {
+                int pmax, int blocks, void *part, const int *list, const int *count) {
     switch (pmax) {
-        case 1: return zinv_diag_t<T, 1>(ctx, g, tspec, nb, fa, fb, blocks, part, mask);
-        case 2: return zinv_diag_t<T, 2>(ctx, g, tspec, nb, fa, fb, blocks, part, mask);
-        case 3: return zinv_diag_t<T, 3>(ctx, g, tspec, nb, fa, fb, blocks, part, mask);
-        case 4: return zinv_diag_t<T, 4>(ctx, g, tspec, nb, fa, fb, blocks, part, mask);
+        case 1: return zinv_diag_t<T, 1>(ctx, g, tspec, nb, fa, fb, blocks, part, list, count);
+        case 2: return zinv_diag_t<T, 2>(ctx, g, tspec, nb, fa, fb, blocks, part, list, count);
+        case 3: return zinv_diag_t<T, 3>(ctx, g, tspec, nb, fa, fb, blocks, part, list, count);
+        case 4: return zinv_diag_t<T, 4>(ctx, g, tspec, nb, fa, fb, blocks, part, list, count);
         default: return fail(ctx, CONKER_EINVAL, "power %d outside 1..4", pmax);
     }
 }
@@ -1128,9 +1129,10 @@ namespace conker {
 
 int fft_inverse_z_diag(conker_ctx *ctx, const conker_grid *g, bool f64, const void *tspec, int nb,
                        const void *fa, const void *fb, int pmax, int blocks, void *part,
-                       const unsigned char *mask) {
-    return f64 ? zinv_diag_p<double>(ctx, g, tspec, nb, fa, fb, pmax, blocks, part, mask)
-               : zinv_diag_p<float>(ctx, g, tspec, nb, fa, fb, pmax, blocks, part, mask);
+                       const Support *sup) {
+    const int *list = sup ? sup->list : nullptr, *count = sup ? sup->count : nullptr;
+    return f64 ? zinv_diag_p<double>(ctx, g, tspec, nb, fa, fb, pmax, blocks, part, list, count)
+               : zinv_diag_p<float>(ctx, g, tspec, nb, fa, fb, pmax, blocks, part, list, count);
 }
 
 int fft_z_tiles(const conker_grid *g, bool f64) {

@@ -279,14 +279,43 @@ struct has_rowf<Op, std::enable_if_t<Op::ROWF>> : std::true_type {};
 
 // One launch = one pass over one axis.  Op::iters() line transforms are run
 // per tile (more than one when a tile is reused across several radii).
+// Ops with PERSIST = true (and begin_at(tile, batch), a set-up that can be
+// repeated) may run persistent: with items > 0 each workgroup takes the work
+// items blockIdx.x, + gridDim.x, ... of items = tiles x batches, loading the
+// twiddles once.
+template <class Op, class = void>
+struct has_persist : std::false_type {};
+template <class Op>
+struct has_persist<Op, std::enable_if_t<Op::PERSIST>> : std::true_type {};
+
 template <typename T, int L, int MODE, int DIR, class Op>
-__global__ __launch_bounds__((Shape<T, L, MODE>::NT), (Shape<T, L, MODE>::MINW)) void k_fft(Op op) {
+__global__ __launch_bounds__((Shape<T, L, MODE>::NT), (Shape<T, L, MODE>::MINW)) void k_fft(Op op, int items,
+                                                                                         int tiles) {
     using C = cplx<T>;
     using SH = Shape<T, L, MODE>;
     __shared__ C lds[SH::LDS];
     __shared__ C tw[L];
     __shared__ unsigned char rowf[has_rowf<Op>::value ? L : 1];
     const C *twg = reinterpret_cast<const C *>(op.tw);
+    if constexpr (has_persist<Op>::value) {
+        if (items > 0) {   // the same for every thread
+            for (int t = threadIdx.x; t < L; t += SH::NT) tw[t] = twg[t];
+            for (int item = blockIdx.x; item < items; item += gridDim.x) {
+                op.template begin_at<SH::TC>(item % tiles, item / tiles);
+                if constexpr (has_active<Op>::value) {
+                    if (!op.active()) continue;   // the same for every thread
+                }
+                __syncthreads();   // twiddles in; the previous item is done with the LDS tile
+                const int it_n = op.iters();
+                for (int it = 0; it < it_n; ++it) {
+                    op.set_iter(it);
+                    fft_line_tile<T, L, MODE, DIR, Op::STAGED>(lds, tw, op);
+                    if (it + 1 < it_n) __syncthreads();
+                }
+            }
+            return;
+        }
+    }
     op.template begin<SH::TC>();
     if constexpr (has_active<Op>::value) {
         if (!op.active()) return;   // the same for every thread of the workgroup
@@ -416,9 +445,13 @@ struct OpInplace {
     const unsigned char *lmask;
     const int *lxcount;
     const unsigned char *rowf = nullptr;   // LDS: the tile's row flags from lmask / lxcount
-    template <int TC> __device__ void begin() {
-        g = make_tile(axis, d, blockIdx.x, TC);
-        p = buf + (size_t)blockIdx.y * nc + g.base;
+    // persistent launches (the inverse y pass): workgroups loop over tiles
+    static constexpr bool PERSIST = !RF;
+    bool persist = false;
+    template <int TC> __device__ void begin() { begin_at<TC>(blockIdx.x, blockIdx.y); }
+    template <int TC> __device__ void begin_at(int tile, int batch) {
+        g = make_tile(axis, d, tile, TC);
+        p = buf + (size_t)batch * nc + g.base;
     }
     __device__ bool active() const { return !xcount || xcount[g.p0] > 0; }
     __device__ bool wants_rowf() const { return lmask != nullptr || lxcount != nullptr; }
@@ -937,7 +970,14 @@ int launch_len_mode(conker_ctx *ctx, int L, int axis, const Dims &d, dim3 gy, Op
         else if (axis == AX_Y) tiles = (long)d.nx * d.nz / SH::TC;
         else tiles = (long)d.ny * d.nz / SH::TC;
         dim3 grid((unsigned)(tiles * gy.z), gy.y, 1);
-        hipLaunchKernelGGL((k_fft<T, LL, MODE, DIR, Op>), grid, dim3(SH::NT), 0, ctx->stream, op);
+        int items = 0;
+        if constexpr (has_persist<Op>::value) {
+            if (op.persist && gy.z == 1) {   // one workgroup per CU loops over tiles x batches
+                items = (int)(tiles * gy.y);
+                grid = dim3((unsigned)std::min<long>(items, cu_count(ctx)), 1, 1);
+            }
+        }
+        hipLaunchKernelGGL((k_fft<T, LL, MODE, DIR, Op>), grid, dim3(SH::NT), 0, ctx->stream, op, items, (int)tiles);
         CK_LAUNCH(ctx);
         return CONKER_OK;
     };
@@ -1020,6 +1060,7 @@ int inverse_batch_t(conker_ctx *ctx, const conker_grid *g, const void *spec, con
     // two exchange buffers pay where most rows are skipped (the pass is bound by
     // its arithmetic and barriers); with every row stored, one buffer measures faster
     const bool one_buffer = ctx->tune.x_resident == 3 || (ctx->tune.x_resident == 0 && !xcount);
+    static const bool persist_y = env_flag("CONKER_Y_PERSIST", 1) != 0;
     bool done = false;
     if (resident && !pair) {
         auto go = [&](auto Lc) -> int {
@@ -1068,6 +1109,7 @@ int inverse_batch_t(conker_ctx *ctx, const conker_grid *g, const void *spec, con
         CK_OK((launch_len<T, +1>(ctx, PK_FFT_INV_X_MUL, xm, d.nx, AX_X, d, gxm, px)));
     }
     OpInplace<T> py{twy, d, AX_Y, (C *)tspec, nc, {}, nullptr, mask, xcount};
+    py.persist = persist_y;
     CK_OK((launch_len<T, +1>(ctx, PK_FFT_INV_Y, col_mode_for<T>(ctx, d, AX_Y), d.ny, AX_Y, d,
                                  dim3(1, (unsigned)nb), py)));
     if (!maps_a) return CONKER_OK;   // x and y passes only

@@ -1109,7 +1109,7 @@ int inverse_batch_t(conker_ctx *ctx, const conker_grid *g, const void *spec, con
         CK_OK((launch_len<T, +1>(ctx, PK_FFT_INV_X_MUL, xm, d.nx, AX_X, d, gxm, px)));
     }
     OpInplace<T> py{twy, d, AX_Y, (C *)tspec, nc, {}, nullptr, mask, xcount};
-    py.persist = persist_y;
+    py.persist = persist_y && xcount != nullptr;   // pays where many slabs are skipped
     CK_OK((launch_len<T, +1>(ctx, PK_FFT_INV_Y, col_mode_for<T>(ctx, d, AX_Y), d.ny, AX_Y, d,
                                  dim3(1, (unsigned)nb), py)));
     if (!maps_a) return CONKER_OK;   // x and y passes only

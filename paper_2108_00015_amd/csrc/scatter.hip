@@ -93,6 +93,12 @@ __global__ __launch_bounds__(256) void k_scatter(const float *__restrict__ pos,
 //                their brick's slots (ranks from LDS atomics);
 //   k_bin_accum  one workgroup per brick holding points: LDS tile sums, then
 //                the tile is added to the grid (the grid is accumulated into).
+//                Where the brick's point count times the largest |w| (from
+//                the count pass) stays below 2^22, the tile sums are 64-bit
+//                integers of w 2^40 (LDS integer adds run several times
+//                faster than float ones): exact for |w| >= 2^-17, rounded
+//                once when added to the grid, and independent of the order;
+//                other bricks add floats.
 // The sums are the same as the direct kernel's, in another order (exact for
 // unit weights, which give integer counts).
 // ---------------------------------------------------------------------------
@@ -122,10 +128,13 @@ __device__ __forceinline__ bool locate(const float *pos, const float *w, int64_t
 __global__ __launch_bounds__(BT) void k_bin_count(const float *__restrict__ pos, const float *__restrict__ w,
                                                   int64_t n, int64_t chunk, GridGeom g, BrickGeom bg, int nb,
                                                   unsigned *__restrict__ hist_out, unsigned *__restrict__ totals,
-                                                  double *wsum, unsigned long long *n_out) {
+                                                  double *wsum, unsigned long long *n_out,
+                                                  unsigned *__restrict__ wmax_bits) {
     __shared__ unsigned hist[MAX_BRICKS];
     __shared__ double sw[BT / 64];
     __shared__ unsigned long long so[BT / 64];
+    __shared__ float sm[BT / 64];
+    float my_max = 0.f;
     for (int b = threadIdx.x; b < nb; b += BT) hist[b] = 0u;
     __syncthreads();
     double my_w = 0.0;
@@ -147,6 +156,7 @@ __global__ __launch_bounds__(BT) void k_bin_count(const float *__restrict__ pos,
             if (ok[k]) {
                 atomicAdd(&hist[brick[k]], 1u);
                 my_w += (double)wt[k];
+                my_max = fmaxf(my_max, fabsf(wt[k]));
             }
     }
     __syncthreads();
@@ -161,21 +171,26 @@ __global__ __launch_bounds__(BT) void k_bin_count(const float *__restrict__ pos,
     for (int o = 32; o >= 1; o >>= 1) {
         my_w += __shfl_xor(my_w, o);
         my_out += __shfl_xor(my_out, o);
+        my_max = fmaxf(my_max, __shfl_xor(my_max, o));
     }
     if ((threadIdx.x & 63) == 0) {
         sw[threadIdx.x >> 6] = my_w;
         so[threadIdx.x >> 6] = my_out;
+        sm[threadIdx.x >> 6] = my_max;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         double a = 0.0;
         unsigned long long b = 0;
+        float m = 0.f;
         for (int i = 0; i < BT / 64; ++i) {
             a += sw[i];
             b += so[i];
+            m = fmaxf(m, sm[i]);
         }
         if (wsum) unsafeAtomicAdd(wsum, a);
         if (n_out && b) atomicAdd(n_out, b);
+        atomicMax(wmax_bits, __float_as_uint(m));   // |w| >= 0: float order = bit order
     }
 }
 
@@ -239,12 +254,16 @@ __global__ __launch_bounds__(BT) void k_bin_place(const float *__restrict__ pos,
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_bin_accum(const uint2 *__restrict__ items, const unsigned *__restrict__ start,
-                                                   GridGeom g, BrickGeom bg, T *__restrict__ grid) {
-    __shared__ T tile[BCELLS];
+                                                   GridGeom g, BrickGeom bg, T *__restrict__ grid,
+                                                   const unsigned *__restrict__ wmax_bits) {
+    __shared__ unsigned long long acc[BCELLS];   // fixed-point sums, or the T sums in its first bytes
+    T *const tile = reinterpret_cast<T *>(acc);
     const int b = blockIdx.x;
     const unsigned i0 = start[b], i1 = start[b + 1];
     if (i0 == i1) return;   // uniform: no point in this brick
-    for (int e = threadIdx.x; e < BCELLS; e += 256) tile[e] = (T)0;
+    // every cell sum of the brick stays below (i1 - i0) max|w| < 2^22: w 2^40 fits 64 bits
+    const bool fixed = (float)(i1 - i0) * __uint_as_float(*wmax_bits) < 4194304.0f;   // uniform
+    for (int e = threadIdx.x; e < BCELLS; e += 256) acc[e] = 0ull;   // zero bits: 0 in every view
     __syncthreads();
     for (unsigned i = i0 + threadIdx.x; i < i1; i += 4 * 256) {
         uint2 it[4];
@@ -252,7 +271,11 @@ __global__ __launch_bounds__(256) void k_bin_accum(const uint2 *__restrict__ ite
         for (int k = 0; k < 4; ++k) it[k] = i + k * 256 < i1 ? items[i + k * 256] : uint2{0u, 0u};
 #pragma unroll
         for (int k = 0; k < 4; ++k)
-            if (i + k * 256 < i1) atomicAdd(&tile[it[k].x], (T)__uint_as_float(it[k].y));
+            if (i + k * 256 < i1) {
+                const float wv = __uint_as_float(it[k].y);
+                if (fixed) atomicAdd(&acc[it[k].x], (unsigned long long)(long long)(wv * 1099511627776.0f));
+                else atomicAdd(&tile[it[k].x], (T)wv);
+            }
     }
     __syncthreads();
     // the brick's rows of BZ cells, 4 values a thread-step; every value read before any is written
@@ -272,7 +295,11 @@ __global__ __launch_bounds__(256) void k_bin_accum(const uint2 *__restrict__ ite
     for (int k = 0; k < PER; ++k) {
         const int e = (threadIdx.x + k * 256) * V;
 #pragma unroll
-        for (int j = 0; j < V; ++j) grid[lin[k] + j] = v[k][j] + tile[e + j];
+        for (int j = 0; j < V; ++j) {
+            const T s = fixed ? (T)((double)(long long)acc[e + j] * 9.094947017729282379e-13)   // 2^-40
+                              : tile[e + j];
+            grid[lin[k] + j] = v[k][j] + s;
+        }
     }
 }
 
@@ -313,7 +340,8 @@ extern "C" int conker_grid_assign(conker_ctx *c, const conker_grid *g, const flo
         g->dims[2] % BZ == 0 && nb64 <= MAX_BRICKS) {
         const int nb = (int)nb64;
         const auto up = [](size_t b) { return (b + 255) / 256 * 256; };
-        const size_t tot_b = up(nb * sizeof(unsigned)), start_b = up((nb + 1) * sizeof(unsigned));
+        // totals[nb] (zeroed with the totals) holds the largest |w| as float bits
+        const size_t tot_b = up((nb + 1) * sizeof(unsigned)), start_b = up((nb + 1) * sizeof(unsigned));
         const size_t hist_b = up((size_t)BG * nb * sizeof(unsigned)), items_b = up((size_t)n * sizeof(uint2));
         CK_OK(ws_reserve(c, c->bins, 3 * tot_b + start_b + hist_b + items_b));
         char *base = (char *)c->bins.p;
@@ -323,10 +351,11 @@ extern "C" int conker_grid_assign(conker_ctx *c, const conker_grid *g, const flo
         unsigned *hist = (unsigned *)(base + 3 * tot_b + start_b);
         uint2 *items = (uint2 *)(base + 3 * tot_b + start_b + hist_b);
         const int64_t chunk = (n + BG - 1) / BG;
-        hipLaunchKernelGGL(k_zero_u32, dim3(64), dim3(256), 0, c->stream, totals, nb);
+        unsigned *wmax_bits = totals + nb;
+        hipLaunchKernelGGL(k_zero_u32, dim3(64), dim3(256), 0, c->stream, totals, nb + 1);
         CK_LAUNCH(c);
         hipLaunchKernelGGL(k_bin_count, dim3(BG), dim3(BT), 0, c->stream, pos, w, n, chunk, gg, bg, nb, hist, totals,
-                           wsum, no);
+                           wsum, no, wmax_bits);
         CK_LAUNCH(c);
         hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(BT), 0, c->stream, totals, nb, start, cursor);
         CK_LAUNCH(c);
@@ -335,10 +364,10 @@ extern "C" int conker_grid_assign(conker_ctx *c, const conker_grid *g, const flo
         CK_LAUNCH(c);
         if (dt == CONKER_F32)
             hipLaunchKernelGGL(k_bin_accum<float>, dim3(nb), dim3(256), 0, c->stream, items, start, gg, bg,
-                               (float *)grid);
+                               (float *)grid, (const unsigned *)wmax_bits);
         else
             hipLaunchKernelGGL(k_bin_accum<double>, dim3(nb), dim3(256), 0, c->stream, items, start, gg, bg,
-                               (double *)grid);
+                               (double *)grid, (const unsigned *)wmax_bits);
         CK_LAUNCH(c);
         return CONKER_OK;
     }

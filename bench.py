@@ -36,7 +36,8 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_bytes(kind, n_launch_units, nc, ns, kel, n_data, n_rand, weighted, esize, batch, fx=1.0, fl=1.0):
+def kernel_bytes(kind, n_launch_units, nc, ns, kel, n_data, n_rand, weighted, esize, batch, fx=1.0, fl=1.0,
+                 pruned_fwd=False):
     """Algorithmic HBM bytes of all launches of one kind in one step.
 
     esize = bytes of one real value (4 or 8); complex = 2 * esize.  When the maps
@@ -45,13 +46,22 @@ def kernel_bytes(kind, n_launch_units, nc, ns, kel, n_data, n_rand, weighted, es
     the x pass writes fx of its output, the y pass reads fx and writes fl, the
     z pass reads fl.  With the axes permuted (axis_order), x, y and z are the
     axes of the permuted grid: fx is the fraction of its first-axis slabs and fl
-    that of lines along its last axis.
+    that of lines along its last axis.  With pruned_fwd (auto-correlations in
+    one call: the fields are zero off their own support) the forward passes are
+    pruned the same way: the z pass reads and writes carrying lines only, the y
+    pass reads them and writes the slabs holding them, the x pass reads those
+    slabs and writes every cell.
     """
     c = 2 * esize
+    gz, gy_in, gy_out, gx_in = (fl, fl, fx, fx) if pruned_fwd else (1.0, 1.0, 1.0, 1.0)
     if kind == "fft_fwd_z":       # two real fields in, one complex field out
-        return 2 * nc * esize + nc * c
-    if kind in ("fft_fwd_y", "fft_fwd_x"):
-        return 2 * nc * c
+        return gz * (2 * nc * esize + nc * c)
+    if kind == "fft_fwd_y":
+        return (gy_in + gy_out) * nc * c
+    if kind == "fft_fwd_x":
+        return (gx_in + 1.0) * nc * c
+    if kind == "pack_scale":      # both fields read once for their sums of squares
+        return 2 * nc * esize
     if kind == "fft_inv_x_mul":   # spectrum read once per batch, kernel octant + output per radius
         n_batches = math.ceil(ns / batch)
         return n_batches * nc * c + ns * (kel * esize + fx * nc * c)
@@ -399,10 +409,13 @@ def main():
     fx, fl, fb = support_fractions(w, data, rand, order)
     if args.field_at_a_time:   # conker_convolve_shells: every slab and line, full maps
         fx = fl = 1.0
+    pruned_fwd = args.mode != "pair2" and not args.field_at_a_time
     stages = {}
+    over_peak = []
     for kind, (launches, tot) in mixed["prof"].items():
         per_step = tot / args.steps
-        b = kernel_bytes(kind, launches, nc, ns, kel, len(data), len(rand), data.w is not None, 4, batch, fx, fl)
+        b = kernel_bytes(kind, launches, nc, ns, kel, len(data), len(rand), data.w is not None, 4, batch, fx, fl,
+                         pruned_fwd)
         if kind == "support" and "axis_order" in mixed["prof"]:
             # built from the axis-order projections: line mask, slab counts and list written
             b = (launches / args.steps) * (nc ** (2.0 / 3.0)) * 5
@@ -411,8 +424,13 @@ def main():
         ent = dict(launches_per_step=launches / args.steps, ms_per_step=per_step,
                    avg_launch_ms=tot / launches)
         if b is not None:
-            ent["gbs"] = b / (per_step * 1e-3) / 1e9
-            ent["bytes_per_launch"] = b / (launches / args.steps)
+            gbs = b / (per_step * 1e-3) / 1e9
+            if gbs > HBM_PEAK_GBS:   # the byte model overstates this kernel's traffic: no figure
+                over_peak.append(kind)
+                log("  stage %s: %.0f GB/s from the byte model exceeds the HBM peak; not reported" % (kind, gbs))
+            else:
+                ent["gbs"] = gbs
+                ent["bytes_per_launch"] = b / (launches / args.steps)
         stages[kind] = ent
     # matrix-core use of the separate summation (orders n >= 3)
     if "contract_mm" in stages and args.n >= 3:
@@ -473,6 +491,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "stages_mixed": stages,
+        "stages_over_peak": over_peak,
     }
     if fp64:
         st64 = {}

@@ -9,10 +9,10 @@
  *   summation    (Sec. 2.5, Eq. ksin_delta)         conker_contract_npt, conker_ratio
  *   both at once, maps never returned               conker_convolve_contract
  * and the paper's other forms: equidistant sums (Eq. ksinDiag,
- * conker_convolve_diag / conker_contract_diag), cross-correlations (Sec. 2.7,
- * *_cross), continuous delta fields (Sec. 2.6, conker_delta_field), n = 2 in
+ * conker_convolve_diag / conker_contract_diag), cross-correlations (Sec. 2.8,
+ * *_cross), continuous delta fields (Sec. 2.7, conker_delta_field), n = 2 in
  * Fourier space (conker_pair_spectral), regions combined (Eq. ksi3combined,
- * conker_ratio_combined), maps and their distributions (Sec. 4,
+ * conker_ratio_combined), maps and their distributions (Sec. 4.2,
  * conker_map_ratio, conker_value_histogram), the survey front end (Sec. 2.2,
  * conker_sky_to_cartesian, conker_analytic_randoms) and batches of catalogs
  * replayed as one HIP graph (conker_batch_*), whose launch shapes can be
@@ -152,8 +152,12 @@ int conker_make_shell_kernels(conker_ctx *ctx, const conker_grid *grid,
  *   maps_a[m](x) = sum over delta in S_m of field_a((x + delta) mod dims),
  * i.e. the circular 3D convolution field *** K_m done with FFTs.  The two
  * fields (typically N and R_raw) share every transform: they travel as the
- * real and imaginary parts of one complex field, which the real, even kernel
- * spectrum keeps apart.
+ * real and imaginary parts of one complex field, a + i s b, which the real,
+ * even kernel spectrum keeps apart.  s is a power of two chosen on the device
+ * from the two fields' sums of squares (s b about a quarter of a in root mean
+ * square), so that the rounding of the larger field does not swamp the
+ * smaller one; it is undone exactly (maps_b are returned unscaled).  Every
+ * call taking two fields does the same.
  *   d_field_a, d_field_b   dtype [nx][ny][nz]; d_field_b may be NULL.
  *   d_kspec                from conker_make_shell_kernels (same grid, dtype).
  *   d_maps_a, d_maps_b     dtype [n_radii][nx][ny][nz]; d_maps_b must be NULL
@@ -163,7 +167,7 @@ int conker_convolve_shells(conker_ctx *ctx, const conker_grid *grid, conker_dtyp
                            const void *d_kspec, int n_radii,
                            void *d_maps_a, void *d_maps_b);
 
-/* ---- summation (Sec. 2.5, Eqs. ksin_delta, ksi2_delta, ksi3, ksinDiag) ----
+/* ---- summation (Sec. 2.5, Eqs. ksin_delta, ksi2_delta, ksi3; Sec. 2.6) -----
  * Number of radius tuples of order n: multisets a_1 <= ... <= a_{n-1} of
  * n_radii shell indices, C(n_radii + n - 2, n - 1).  Returns -1 if n < 2. */
 int64_t conker_num_tuples(int n_radii, int n);
@@ -204,7 +208,7 @@ int conker_convolve_contract(conker_ctx *ctx, const conker_grid *grid, conker_dt
                              const void *d_field_a, const void *d_field_b, const void *d_kspec,
                              int n_radii, int n, conker_mmprec prec, double *d_W_a, double *d_W_b);
 
-/* ---- equidistant configurations (Sec. 2.5, Eq. ksinDiag) -------------------
+/* ---- equidistant configurations (Sec. 2.6, Eq. ksinDiag) -------------------
  * The diagonal entries a_1 = ... = a_{n-1} = m of Eq. ksin_delta, for every
  * order n = 2 .. n_max at once:
  *   out[(n - 2) * n_radii + m] = sum over all cells x of field(x) * C_m(x)^(n-1)
@@ -228,7 +232,7 @@ int conker_convolve_diag(conker_ctx *ctx, const conker_grid *grid, conker_dtype 
                          const void *d_field_a, const void *d_field_b, const void *d_kspec,
                          int n_radii, int n_max, double *d_out_a, double *d_out_b);
 
-/* ---- cross-correlation of two tracers (Sec. 2.7) ----------------------------
+/* ---- cross-correlation of two tracers (Sec. 2.8) ----------------------------
  * Vertex 0 weighs with one field (the "centre" field Delta_0), the shells with
  * the maps of another (Delta_1).  From stored maps this is conker_contract_npt
  * called with d_field = Delta_0 and d_maps = the maps of Delta_1.  Without
@@ -259,7 +263,7 @@ int conker_ratio_cross(conker_ctx *ctx, const double *d_W_cross, const double *d
                        const double *d_alpha0, const double *d_alpha1, int n, int64_t count,
                        double *d_xi);
 
-/* ---- n = 2 in Fourier space (Sec. 2.5, Eq. ksi2_delta; Sec. 2.7) ------------
+/* ---- n = 2 in Fourier space (Sec. 2.5, Eq. ksi2_delta; Sec. 2.8) ------------
  * conker_pair_spectral: for every radius m, from the forward spectra alone
  * (Parseval, K_m real and even):
  *   W_aa[m] = sum_x a(x) (K_m *** a)(x),  W_bb[m] likewise for b,
@@ -272,7 +276,7 @@ int conker_pair_spectral(conker_ctx *ctx, const conker_grid *grid, conker_dtype 
                          const void *d_field_a, const void *d_field_b, const void *d_kspec,
                          int n_radii, double *d_W_aa, double *d_W_bb, double *d_W_ab);
 
-/* ---- continuous tracers (Sec. 2.6, Eqs. densitycont, ksin_cont) -------------
+/* ---- continuous tracers (Sec. 2.7, Eqs. densitycont, ksin_cont) -------------
  * conker_delta_field: delta = (D - alpha R) / (alpha R) on cells where
  * alpha R != 0, and 0 on cells without random coverage.  d_alpha: device
  * float64 scalar, or NULL for 1.  d_delta may alias d_D.  The estimator of a
@@ -281,7 +285,7 @@ int conker_pair_spectral(conker_ctx *ctx, const conker_grid *grid, conker_dtype 
 int conker_delta_field(conker_ctx *ctx, const conker_grid *grid, conker_dtype dtype, const void *d_D,
                        const void *d_R, const double *d_alpha, void *d_delta);
 
-/* ---- regions, maps and distributions (Sec. 3.3, Eq. ksi3combined; Sec. 4) ---
+/* ---- regions, maps and distributions (Sec. 3.4, Eq. ksi3combined; Sec. 4.2) ---
  * conker_ratio_combined: regions (or mocks) measured separately, combined by
  * adding numerators and denominators:
  *   num[t] = sum_j W_delta[j][t],  den[t] = sum_j alpha_j^n W_rand[j][t],
@@ -387,7 +391,12 @@ typedef struct {
  * conker_batch_capture: records the whole batch into one HIP graph (the
  * context stream must not be the default stream); nothing is allocated or
  * zeroed with memset nodes inside the capture.
- * conker_batch_launch: replays the captured graph on the context stream. */
+ * conker_batch_launch: replays the captured graph on the context stream.
+ *   The graph holds the addresses of the context's workspace buffers: any
+ *   later call on the context that has to grow one of them (a larger grid,
+ *   more radii, a larger catalog) frees it and drops the captured graph, and
+ *   conker_batch_launch then fails with CONKER_EINVAL ("no captured batch")
+ *   until the batch is captured again. */
 int conker_batch_plan(conker_ctx *ctx, const conker_job *jobs, int n_jobs);
 int conker_batch_run(conker_ctx *ctx);
 int conker_batch_capture(conker_ctx *ctx);

@@ -178,7 +178,7 @@ def direct_shell_sum(F: np.ndarray, r: float, cells: np.ndarray) -> np.ndarray:
 
 
 # ----------------------------------------------------------------------------
-# summation (Sec. 2.5, Eqs. ksin_delta, ksi2_delta, ksi3; Eq. ksinDiag)
+# summation (Sec. 2.5, Eqs. ksin_delta, ksi2_delta, ksi3; Sec. 2.6, Eq. ksinDiag)
 # ----------------------------------------------------------------------------
 
 def radius_tuples(n_radii: int, n: int) -> List[Tuple[int, ...]]:
@@ -256,7 +256,7 @@ def diagonal(F: np.ndarray, map_1: np.ndarray, n: int) -> float:
 
 
 # ----------------------------------------------------------------------------
-# continuous tracers (Sec. 2.6, Eqs. densitycont, ksin_cont, ksi2_cont)
+# continuous tracers (Sec. 2.7, Eqs. densitycont, ksin_cont, ksi2_cont)
 # ----------------------------------------------------------------------------
 
 def delta_field(D: np.ndarray, R: np.ndarray) -> np.ndarray:
@@ -281,7 +281,7 @@ def npcf_continuous(D: np.ndarray, R: np.ndarray, radii_cells: Sequence[float], 
 
 
 # ----------------------------------------------------------------------------
-# cross-correlation of two tracers (Sec. 2.7)
+# cross-correlation of two tracers (Sec. 2.8)
 # ----------------------------------------------------------------------------
 
 def estimator_cross(W_cross: np.ndarray, W_rand_raw: np.ndarray, alpha0: float, alpha1: float,
@@ -310,7 +310,7 @@ def npcf_cross(data0_pos, data1_pos, rand_pos, dims, origin, cell, radii, n,
 
 
 # ----------------------------------------------------------------------------
-# regions, maps and their distributions (Sec. 3.3, Eq. ksi3combined; Sec. 4)
+# regions, maps and their distributions (Sec. 3.4, Eq. ksi3combined; Sec. 4.2)
 # ----------------------------------------------------------------------------
 
 def combine_regions(W_deltas: Sequence[np.ndarray], W_rands_raw: Sequence[np.ndarray],
@@ -324,7 +324,7 @@ def combine_regions(W_deltas: Sequence[np.ndarray], W_rands_raw: Sequence[np.nda
 
 
 def map_ratio(N: np.ndarray, map_N: np.ndarray, W_rand_raw_2: float, alpha: float) -> np.ndarray:
-    """Per-cell W_0 W_1 / <B_0 B_1> for one radius (the maps of Sec. 4): N(x) C^N(x)
+    """Per-cell W_0 W_1 / <B_0 B_1> for one radius (the maps of Sec. 4.2): N(x) C^N(x)
     over the cell average of B_0 B_1 = alpha^2 R_raw C^R, i.e. alpha^2 W_R2 / N_c.
     Its cell average is the 2pcf of that radius."""
     return N * map_N / (alpha * alpha * W_rand_raw_2 / N.size)

@@ -575,7 +575,7 @@ def npcf_pair2(ctx: Context, grid: Grid, data_pos: torch.Tensor, rand_pos: torch
 
 def npcf_continuous(ctx: Context, grid: Grid, D: torch.Tensor, R: torch.Tensor, kspec: torch.Tensor, n: int,
                     precision: str = "f64", alpha: Optional[torch.Tensor] = None, fused: Optional[bool] = None) -> dict:
-    """Continuous tracers (Sec. 2.6): delta = (D - R) / R, then xi_n = sum_x delta prod_i (delta *** K_{a_i})
+    """Continuous tracers (Sec. 2.7): delta = (D - R) / R, then xi_n = sum_x delta prod_i (delta *** K_{a_i})
     (Eq. ksin_cont), with no further normalisation.  Returns xi (= W) and delta."""
     delta = ctx.delta_field(grid, D, R, alpha)
     if fused is None:
@@ -594,7 +594,7 @@ def npcf_cross(ctx: Context, grid: Grid, data0_pos: torch.Tensor, data1_pos: tor
                precision: str = "f64", dtype=torch.float64, fused: Optional[bool] = None,
                allow_outside: bool = False) -> dict:
     """Cross-correlation of tracer 0 (vertex 0) with tracer 1 (the shells), both background-subtracted
-    against one random catalog (Sec. 2.7): xi = W_cross / (alpha0 alpha1^(n-1) W_rand_raw)."""
+    against one random catalog (Sec. 2.8): xi = W_cross / (alpha0 alpha1^(n-1) W_rand_raw)."""
     dev = data0_pos.device
     shape = tuple(int(d) for d in grid.dims)
     N0 = torch.zeros(shape, dtype=dtype, device=dev)

@@ -21,6 +21,21 @@ struct Buf {
     size_t bytes = 0;
 };
 
+// Power-of-two scale s = 2^k of the field packed into the imaginary part of
+// the forward transform (a + i s b, fft.hip), in both float widths, written
+// on the device by every packed forward transform and read by the passes and
+// reductions that undo it.  Lives at offset 0 of conker_ctx::scal; the
+// per-workgroup sums it is chosen from follow at SCAL_PART_OFF.
+struct PackScale {
+    double s, s_inv;
+    float sf, sf_inv;
+    int k;
+    int pad;
+};
+constexpr size_t SCAL_PART_OFF = 256;
+constexpr int SCAL_MAX_PART = 4096;   // workgroups of the sums (two doubles each)
+constexpr size_t SCAL_BYTES = SCAL_PART_OFF + (size_t)SCAL_MAX_PART * 2 * sizeof(double);
+
 }  // namespace conker
 
 struct conker_ctx {
@@ -42,6 +57,7 @@ struct conker_ctx {
     conker::Buf bins;       // binned mapping: per-brick counts and starts, per-workgroup histograms, placed points
     conker::Buf blocks;     // summation: list of the 64-cell blocks where the field is non-zero
     conker::Buf maps;       // convolve-contract without the fused kernel: maps of carrying lines
+    conker::Buf scal;       // allocated once by conker_create: PackScale and its partial sums
     int order_last = 0;             // axis order of the last map-free summation (1..6), -1: on the device
     const int *order_dev = nullptr; // with order_last -1: the chosen permutation index (0..5)
     std::map<uint64_t, conker::Buf> tables;  // item / tuple tables, keyed by (n_radii, n, prec)
@@ -92,6 +108,8 @@ enum ProfKind {
     PK_SURVEY,
     PK_ORDER,
     PK_BLOCKS,
+    PK_PACK_SCALE,
+    PK_PACK_SCALE_REDUCE,
     PK_COUNT
 };
 
@@ -166,17 +184,28 @@ struct Support {
     const int *xcount = nullptr;           // [nx] carrying lines per x-slab
     const int *list = nullptr;             // carrying lines x * ny + y, increasing
     const int *count = nullptr;            // device scalar: length of list
+    // sums of squares of the two fields the support was taken from, as
+    // sums_n per-workgroup partial pairs (sum a^2, sum b^2), added in a fixed
+    // order by the packed forward transform of those same fields
+    const double *sums = nullptr;
+    int sums_n = 0;
 };
 int support_lines(conker_ctx *c, const conker_grid *g, bool f64, const void *fa, const void *fb, Support *out);
 // The same outputs from a mask and per-slab counts computed elsewhere:
-// support_alloc reserves the buffers (mask [nx * ny], xcount [nx]) to fill,
-// support_list then builds the ordered list and its count.
-int support_alloc(conker_ctx *c, int nx, int ny, Support *out, unsigned char **mask, int **xcount);
+// support_alloc reserves the buffers (mask [nx * ny], xcount [nx]; room for
+// nx pairs of sums in *sums_slot when it is given) to fill, support_list then
+// builds the ordered list and its count.
+int support_alloc(conker_ctx *c, int nx, int ny, Support *out, unsigned char **mask, int **xcount,
+                  double **sums_slot = nullptr);
 int support_list(conker_ctx *c, int nx, int ny, const Support &s);
 
 // FFT passes (fft.hip) ------------------------------------------------------
 // Forward 3D FFT of the complex field packed from two real fields
-// (a + i b) into the spectrum buffer `spec` (natural order, unnormalised).
+// (a + i s b) into the spectrum buffer `spec` (natural order, unnormalised).
+// With b, s = 2^k is first chosen on the device from the sums of squares of
+// a and b (taken from sup->sums when given, else by a pass over both fields)
+// and written to the context's PackScale; without b, nothing is scaled and
+// the PackScale is left as it was.
 // With `sup`, the line support of a and b themselves (both zero on every other
 // line): inputs known to be zero are neither written between the passes nor
 // read.
@@ -214,6 +243,10 @@ int fft_inverse_batch(conker_ctx *ctx, const conker_grid *g, bool f64,
 int fft_inverse_z_diag(conker_ctx *ctx, const conker_grid *g, bool f64, const void *tspec, int nb,
                        const void *fa, const void *fb, int pmax, int blocks, void *part,
                        const Support *sup = nullptr);
+
+// The context's PackScale (device memory, valid on the context's stream after
+// the last packed forward transform).
+inline const PackScale *pack_scale_dev(const conker_ctx *c) { return (const PackScale *)c->scal.p; }
 
 // Device list of the 64-cell blocks (cells 64 k .. 64 k + 63) holding a cell
 // where F != 0, ascending (blocks.hip): *list = int[*count], both in device

@@ -31,6 +31,13 @@ int ws_reserve(conker_ctx *ctx, Buf &b, size_t bytes) {
         return fail(ctx, CONKER_ENOMEM, "workspace of %zu bytes needed, cap is %zu", next, ctx->ws_cap);
     if (b.p) {
         CK_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        // a captured batch replays kernels on this buffer's address: it is
+        // dropped with the buffer (conker_batch_launch then reports that no
+        // batch is captured)
+        if (ctx->graph_exec) {
+            CK_HIP(ctx, hipGraphExecDestroy(ctx->graph_exec));
+            ctx->graph_exec = nullptr;
+        }
         CK_HIP(ctx, hipFree(b.p));
         ctx->ws_bytes -= b.bytes;
         b.p = nullptr;
@@ -204,6 +211,23 @@ extern "C" int conker_create(conker_ctx **out, int device, void *stream, size_t 
     c->device = device;
     c->stream = (hipStream_t)stream;
     c->ws_cap = cap;
+    // the packed-pair scale and its partial sums: held for the context's life
+    // (never regrown, so graphs may record its address); s = 1 until the first
+    // packed forward transform
+    e = hipMalloc(&c->scal.p, SCAL_BYTES);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        delete c;
+        return fail(nullptr, CONKER_ENOMEM, "hipMalloc(%zu) failed: %s", SCAL_BYTES, hipGetErrorString(e));
+    }
+    c->scal.bytes = SCAL_BYTES;
+    const PackScale one{1.0, 1.0, 1.0f, 1.0f, 0, 0};
+    e = hipMemcpy(c->scal.p, &one, sizeof one, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(c->scal.p);
+        delete c;
+        return fail(nullptr, CONKER_EHIP, "hipMemcpy: %s", hipGetErrorString(e));
+    }
     *out = c;
     return CONKER_OK;
 }
@@ -235,6 +259,7 @@ extern "C" void conker_destroy(conker_ctx *c) {
     rel(c->bins);
     rel(c->blocks);
     rel(c->maps);
+    rel(c->scal);
     delete c;
 }
 
@@ -288,7 +313,7 @@ extern "C" const char *conker_profile_kind_name(int kind) {
         "scatter", "form_delta", "fft_fwd_z", "fft_fwd_y", "fft_fwd_x", "fft_inv_x_mul", "fft_inv_y",
         "fft_inv_z", "bank_z", "bank_y", "bank_x", "contract_dot", "contract_mm", "contract_reduce", "ratio",
         "fused_zinv_contract", "diag_zinv", "diag_maps", "diag_reduce", "support", "pair_spectral", "survey_front_end",
-        "axis_order", "cell_blocks"};
+        "axis_order", "cell_blocks", "pack_scale", "pack_scale_reduce"};
     return (kind >= 0 && kind < PK_COUNT) ? names[kind] : nullptr;
 }
 

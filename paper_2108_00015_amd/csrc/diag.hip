@@ -94,8 +94,11 @@ __global__ __launch_bounds__(DT) void k_diag_maps(const T *__restrict__ F, const
 }
 
 // part rows [ns][blocks][nf * P] -> out_f[(p - 1) * ns + m], p = 1 .. P.
+// With ps, field b was transformed times the pair's scale s: its sums of
+// power p carry s^p.
 __global__ __launch_bounds__(DT) void k_diag_reduce(const double *__restrict__ part, int blocks, int ns, int nf,
-                                                    int P, double *__restrict__ out_a, double *__restrict__ out_b) {
+                                                    int P, double *__restrict__ out_a, double *__restrict__ out_b,
+                                                    const PackScale *ps) {
     __shared__ double red[DT];
     const int m = blockIdx.x;
     const int W = nf * P;
@@ -111,7 +114,10 @@ __global__ __launch_bounds__(DT) void k_diag_reduce(const double *__restrict__ p
         if (threadIdx.x == 0) {
             const int f = j / P, p = j - f * P;
             double *o = f == 0 ? out_a : out_b;
-            if (o) o[(size_t)p * ns + m] = red[0];
+            double v = red[0];
+            if (f == 1 && ps)
+                for (int q = 0; q <= p; ++q) v *= ps->s_inv;   // a power of two: exact
+            if (o) o[(size_t)p * ns + m] = v;
         }
         __syncthreads();
     }
@@ -130,9 +136,10 @@ int launch_maps(conker_ctx *c, const T *F, const T *maps, size_t nc, int ns, int
     return CONKER_OK;
 }
 
-int reduce(conker_ctx *c, const double *part, int blocks, int ns, int nf, int P, double *oa, double *ob) {
+int reduce(conker_ctx *c, const double *part, int blocks, int ns, int nf, int P, double *oa, double *ob,
+           const PackScale *scale) {
     ProfScope ps(c, PK_DIAG_REDUCE);
-    hipLaunchKernelGGL(k_diag_reduce, dim3(ns), dim3(DT), 0, c->stream, part, blocks, ns, nf, P, oa, ob);
+    hipLaunchKernelGGL(k_diag_reduce, dim3(ns), dim3(DT), 0, c->stream, part, blocks, ns, nf, P, oa, ob, scale);
     CK_LAUNCH(c);
     return CONKER_OK;
 }
@@ -167,7 +174,7 @@ extern "C" int conker_contract_diag(conker_ctx *c, const conker_grid *g, conker_
         if (f64) CK_OK(launch_maps<double>(c, (const double *)field, (const double *)maps, nc, n_radii, P, G, chunk, part));
         else CK_OK(launch_maps<float>(c, (const float *)field, (const float *)maps, nc, n_radii, P, G, chunk, part));
     }
-    return reduce(c, part, G, n_radii, 1, P, out, nullptr);
+    return reduce(c, part, G, n_radii, 1, P, out, nullptr, nullptr);
 }
 
 // Maps from fa (fb), summed against the centre fields ca (cb).
@@ -206,7 +213,7 @@ static int convolve_diag(conker_ctx *c, const conker_grid *g, conker_dtype dt, c
         CK_OK(fft_inverse_z_diag(c, g, f64, c->tspec.p, nb, ca, cb, P, blocks,
                                  part + (size_t)m0 * blocks * 2 * P, &sup));
     }
-    return reduce(c, part, blocks, n_radii, 2, P, out_a, out_b);
+    return reduce(c, part, blocks, n_radii, 2, P, out_a, out_b, fb ? pack_scale_dev(c) : nullptr);
 }
 
 extern "C" int conker_convolve_diag(conker_ctx *c, const conker_grid *g, conker_dtype dt, const void *fa,

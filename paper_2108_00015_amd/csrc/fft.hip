@@ -15,6 +15,7 @@
 // engine packs two real fields into one complex field, multiplies by a kernel
 // spectrum, unpacks real maps, generates shell indicators on the fly, or
 // extracts the stored octant of a kernel spectrum.
+#include <algorithm>
 #include <cstdlib>
 #include <type_traits>
 #include <utility>
@@ -381,14 +382,133 @@ __device__ __forceinline__ unsigned off(const Tile &g, int i, int c) {
 __device__ __forceinline__ int fold(int k, int n) { return k <= n - k ? k : n - k; }
 
 // ---------------------------------------------------------------------------
+// Scale of the packed pair.  Two real fields share one complex transform as
+// a + i s b.  Float rounding in a complex transform is relative to the size
+// of the complex values, so the rounding of s b leaks into a's spectrum and
+// maps, and the reverse.  In the estimator a is N = D - alpha R, whose sums
+// cancel between cells, and b is the random field R, several times larger
+// per cell and one-signed.  s is therefore a power of two (exact to apply and
+// to undo) that brings the root mean square of s b to about a quarter of a's:
+// a's rounding then stays within a few per cent of that of a transformed
+// alone, and b's grows about fourfold on sums that do not cancel.  s is
+// chosen on the device (no host synchronisation, graph-safe) from the sums
+// of squares of both fields, added in a fixed order.  It is undone exactly:
+// stored maps of b are multiplied by 1/s, sums of order p over maps of b by
+// s^-p.
+// ---------------------------------------------------------------------------
+constexpr int PS_T = 256;
+
+template <typename T, int PV>
+__global__ __launch_bounds__(PS_T) void k_pack_sums(const T *__restrict__ a, const T *__restrict__ b, size_t n,
+                                                    double *__restrict__ part) {
+    __shared__ double red[PS_T / 64][2];
+    double sa = 0.0, sb = 0.0;
+    const size_t nv = n / PV, stride = (size_t)gridDim.x * PS_T;
+    for (size_t i = (size_t)blockIdx.x * PS_T + threadIdx.x; i < nv; i += stride) {
+        if constexpr (PV == 1) {
+            const double x = (double)a[i], y = (double)b[i];
+            sa += x * x;
+            sb += y * y;
+        } else {
+            using V = typename std::conditional<std::is_same<T, float>::value, float4, double2>::type;
+            const V x = reinterpret_cast<const V *>(a)[i];
+            const V y = reinterpret_cast<const V *>(b)[i];
+            if constexpr (std::is_same<T, float>::value) {
+                sa += (double)x.x * x.x + (double)x.y * x.y + (double)x.z * x.z + (double)x.w * x.w;
+                sb += (double)y.x * y.x + (double)y.y * y.y + (double)y.z * y.z + (double)y.w * y.w;
+            } else {
+                sa += x.x * x.x + x.y * x.y;
+                sb += y.x * y.x + y.y * y.y;
+            }
+        }
+    }
+    if (blockIdx.x == 0)   // the tail beyond whole vectors
+        for (size_t i = nv * PV + threadIdx.x; i < n; i += PS_T) {
+            const double x = (double)a[i], y = (double)b[i];
+            sa += x * x;
+            sb += y * y;
+        }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int o = 32; o >= 1; o >>= 1) {
+        sa += __shfl_xor(sa, o);
+        sb += __shfl_xor(sb, o);
+    }
+    if (lane == 0) {
+        red[wv][0] = sa;
+        red[wv][1] = sb;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        double v = 0.0;
+        for (int w = 0; w < PS_T / 64; ++w) v += red[w][threadIdx.x];
+        part[2 * blockIdx.x + threadIdx.x] = v;
+    }
+}
+
+// One workgroup: the G partial pairs (sum a^2, sum b^2) in a fixed order, then s.  Fields that are
+// zero or not finite leave s = 1.  |k| <= 60 keeps s b and its maps far from
+// the float range limits.
+constexpr int PSR_T = 1024;   // threads of the one workgroup that adds the partials
+
+__global__ __launch_bounds__(PSR_T) void k_pack_scale(const double *__restrict__ part, int G, PackScale *out) {
+    __shared__ double red[2][PSR_T];
+    double sa = 0.0, sb = 0.0;
+    for (int g = threadIdx.x; g < G; g += PSR_T) {
+        const double2 v = reinterpret_cast<const double2 *>(part)[g];
+        sa += v.x;
+        sb += v.y;
+    }
+    red[0][threadIdx.x] = sa;
+    red[1][threadIdx.x] = sb;
+    __syncthreads();
+    for (int h = PSR_T / 2; h >= 1; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + h];
+            red[1][threadIdx.x] += red[1][threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double ta = red[0][0], tb = red[1][0];
+        int k = 0;
+        if (ta > 0.0 && tb > 0.0 && isfinite(ta) && isfinite(tb)) {
+            // rms(s b) = rms(a) / 4:  k = log2(rms a / rms b) - 2
+            const double e = 0.5 * (log2(ta) - log2(tb)) - 2.0;
+            k = (int)rint(e);
+            k = k < -60 ? -60 : (k > 60 ? 60 : k);
+        }
+        PackScale ps;
+        ps.s = ldexp(1.0, k);
+        ps.s_inv = ldexp(1.0, -k);
+        ps.sf = (float)ps.s;
+        ps.sf_inv = (float)ps.s_inv;
+        ps.k = k;
+        ps.pad = 0;
+        *out = ps;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ T scale_of(const PackScale *ps) {
+    if constexpr (std::is_same<T, float>::value) return ps->sf;
+    else return ps->s;
+}
+template <typename T>
+__device__ __forceinline__ T scale_inv_of(const PackScale *ps) {
+    if constexpr (std::is_same<T, float>::value) return ps->sf_inv;
+    else return ps->s_inv;
+}
+
+// ---------------------------------------------------------------------------
 // operators
 // ---------------------------------------------------------------------------
 // With `mask` (line flags [nx * ny], both fields zero on lines without one):
 // z-line tiles without a flagged line do nothing, and only flagged lines are
-// written (the y pass then reads the others as zero).
+// written (the y pass then reads the others as zero).  With `ps`, b is
+// multiplied by the pair's scale s.
 template <typename T>
 struct OpPack {
-    static constexpr bool STAGED = false;   // z pass, forward: (a + i b) -> spec
+    static constexpr bool STAGED = false;   // z pass, forward: (a + i s b) -> spec
     using C = cplx<T>;
     const void *tw;
     Dims d;
@@ -398,12 +518,15 @@ struct OpPack {
     Tile g;
     const unsigned char *mask;
     int tcn;
+    const PackScale *ps;
+    T sb;
     template <int TC> __device__ void begin() {
         g = make_tile(AX_Z, d, blockIdx.x, TC);
         tcn = TC;
         a += g.base;
         if (b) b += g.base;
         out += g.base;
+        sb = ps ? scale_of<T>(ps) : (T)1;
     }
     __device__ bool active() const {   // the same for every thread: any line of the tile flagged
         if (!mask) return true;
@@ -415,7 +538,7 @@ struct OpPack {
     __device__ void set_iter(int) {}
     __device__ C load(int i, int c) const {
         const unsigned k = off(g, i, c);
-        return C{a[k], b ? b[k] : (T)0};
+        return C{a[k], b ? b[k] * sb : (T)0};
     }
     __device__ void store(int i, int c, C v) const {
         if (mask && !mask[(size_t)g.p0 + c]) return;
@@ -572,9 +695,12 @@ struct OpUnpack {
     int pair, ns;
     const unsigned char *mask;   // NULL, or line flags [nx * ny]: only lines with a flag are written
     int tcn;
+    const PackScale *ps;         // two packed fields: the maps of b are stored times 1/s
+    T sbi;
     template <int TC> __device__ void begin() {
         g = make_tile(AX_Z, d, blockIdx.x, TC);
         tcn = TC;
+        sbi = ps ? scale_inv_of<T>(ps) : (T)1;
         src = tspec + (size_t)blockIdx.y * nc + g.base;
         if (pair) {
             const int ra = 2 * (m0 + blockIdx.y);
@@ -599,7 +725,7 @@ struct OpUnpack {
         if (mask && !mask[(size_t)g.p0 + c]) return;
         const unsigned k = off(g, i, c);
         ma[k] = v.x;
-        if (mb) mb[k] = v.y;
+        if (mb) mb[k] = v.y * sbi;
     }
 };
 
@@ -1003,6 +1129,27 @@ int launch_len(conker_ctx *ctx, int kind, int mode, int L, int axis, const Dims 
     return launch_len_mode<T, TM_W, DIR>(ctx, L, axis, d, gy, op);
 }
 
+// Sums of squares of a and b, then the pair's scale into the context's PackScale.
+template <typename T>
+int pack_scale_t(conker_ctx *ctx, size_t n, const T *a, const T *b) {
+    constexpr int PV = 16 / (int)sizeof(T);
+    const bool vec = (((uintptr_t)a | (uintptr_t)b) & 15) == 0;
+    const size_t units = vec ? n / PV : n;
+    const int G = (int)std::max<size_t>(1, std::min<size_t>({(size_t)SCAL_MAX_PART, (size_t)4 * cu_count(ctx),
+                                                            (units + PS_T - 1) / PS_T}));
+    double *part = (double *)((char *)ctx->scal.p + SCAL_PART_OFF);
+    ProfScope ps(ctx, PK_PACK_SCALE);
+    if (vec)
+        hipLaunchKernelGGL((k_pack_sums<T, PV>), dim3(G), dim3(PS_T), 0, ctx->stream, a, b, n, part);
+    else
+        hipLaunchKernelGGL((k_pack_sums<T, 1>), dim3(G), dim3(PS_T), 0, ctx->stream, a, b, n, part);
+    CK_LAUNCH(ctx);
+    hipLaunchKernelGGL(k_pack_scale, dim3(1), dim3(PSR_T), 0, ctx->stream, (const double *)part, G,
+                       (PackScale *)ctx->scal.p);
+    CK_LAUNCH(ctx);
+    return CONKER_OK;
+}
+
 template <typename T>
 int forward_pair_t(conker_ctx *ctx, const conker_grid *g, const void *a, const void *b, void *spec,
                    const Support *sup) {
@@ -1018,7 +1165,18 @@ int forward_pair_t(conker_ctx *ctx, const conker_grid *g, const void *a, const v
     // reads them in carrying slabs only, the x pass reads carrying slabs
     const unsigned char *mask = sup ? sup->mask : nullptr;
     const int *xcount = sup ? sup->xcount : nullptr;
-    OpPack<T> pz{twz, d, (const T *)a, (const T *)b, (C *)spec, {}, mask, 0};
+    if (b) {
+        if (sup && sup->sums) {   // sums of squares taken with the support: only their reduction
+            ProfScope ps(ctx, PK_PACK_SCALE_REDUCE);
+            hipLaunchKernelGGL(k_pack_scale, dim3(1), dim3(PSR_T), 0, ctx->stream, sup->sums, sup->sums_n,
+                               (PackScale *)ctx->scal.p);
+            CK_LAUNCH(ctx);
+        } else {
+            CK_OK(pack_scale_t<T>(ctx, nc, (const T *)a, (const T *)b));
+        }
+    }
+    OpPack<T> pz{twz, d, (const T *)a, (const T *)b, (C *)spec, {}, mask, 0, b ? pack_scale_dev(ctx) : nullptr,
+                 (T)1};
     CK_OK((launch_len<T, -1>(ctx, PK_FFT_FWD_Z, TM_J, d.nz, AX_Z, d, dim3(1, 1), pz)));
     OpInplace<T, true> py{twy, d, AX_Y, (C *)spec, nc, {}, nullptr, nullptr, xcount, mask, nullptr};
     CK_OK((launch_len<T, -1>(ctx, PK_FFT_FWD_Y, col_mode_for<T>(ctx, d, AX_Y), d.ny, AX_Y, d, dim3(1, 1), py)));
@@ -1113,7 +1271,8 @@ int inverse_batch_t(conker_ctx *ctx, const conker_grid *g, const void *spec, con
     CK_OK((launch_len<T, +1>(ctx, PK_FFT_INV_Y, col_mode_for<T>(ctx, d, AX_Y), d.ny, AX_Y, d,
                                  dim3(1, (unsigned)nb), py)));
     if (!maps_a) return CONKER_OK;   // x and y passes only
-    OpUnpack<T> pz{twz, d, (const C *)tspec, (T *)maps_a, (T *)maps_b, nc, m0, {}, nullptr, pair, pair_ns, mask, 0};
+    OpUnpack<T> pz{twz, d, (const C *)tspec, (T *)maps_a, (T *)maps_b, nc, m0, {}, nullptr, pair, pair_ns, mask, 0,
+                   (maps_b && !pair) ? pack_scale_dev(ctx) : nullptr, (T)1};
     CK_OK((launch_len<T, +1>(ctx, PK_FFT_INV_Z, TM_J, d.nz, AX_Z, d, dim3(1, (unsigned)nb), pz)));
     return CONKER_OK;
 }

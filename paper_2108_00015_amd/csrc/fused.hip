@@ -254,8 +254,9 @@ __global__ __launch_bounds__(NT, 1) void k_zinv_contract(const float2 *__restric
 
 // Sums the workgroup partials in order and gathers the tuples:
 //   n = 3: W[(a, b)], a <= b, lexicographic;  n = 2: W[a].
+// Field b was transformed times the pair's scale s: its sums carry s^(n-1).
 __global__ void k_fused_finish(const double *__restrict__ partial, int G, int ns, int n, double *Wa,
-                               double *Wb) {
+                               double *Wb, const PackScale *ps) {
     const int cnt = n == 3 ? ns * (ns + 1) / 2 : ns;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= 2 * cnt) return;
@@ -273,6 +274,8 @@ __global__ void k_fused_finish(const double *__restrict__ partial, int G, int ns
     }
     double s = 0.0;
     for (int g = 0; g < G; ++g) s += partial[(size_t)g * PART + e];
+    if (f == 1)
+        for (int p = 1; p < n; ++p) s *= ps->s_inv;   // a power of two: exact
     W[k] = s;
 }
 
@@ -377,7 +380,7 @@ static int convolve_contract(conker_ctx *c, const conker_grid *g, conker_dtype d
     ProfScope ps(c, PK_CONTRACT_REDUCE);
     const int cnt = n == 3 ? ns * (ns + 1) / 2 : ns;
     hipLaunchKernelGGL(k_fused_finish, dim3((2 * cnt + 127) / 128), dim3(128), 0, c->stream,
-                       (const double *)c->partial.p, G, ns, n, Wa, Wb);
+                       (const double *)c->partial.p, G, ns, n, Wa, Wb, pack_scale_dev(c));
     CK_LAUNCH(c);
     return CONKER_OK;
 }

@@ -37,17 +37,35 @@ constexpr int OT = 256;   // threads per workgroup
 // Non-zero is a bit test of everything but the sign, as for the line masks.
 // Each lane reads 16 bytes (CPL cells) per step; the lanes' flags are packed
 // into 32-bit words (LPW lanes a word) with shuffles.
+// With `sums` (both fields given): also the sums of squares of each field
+// over the workgroup's lines, written as the pair sums[2 blockIdx.x + {0, 1}]
+// (the packed transform's scale is chosen from them).
+template <typename T>
+__device__ __forceinline__ double sq16(const uint4 &v) {   // sum of squares of the values in 16 bytes
+    if constexpr (sizeof(T) == 4) {
+        const float a = __uint_as_float(v.x), b = __uint_as_float(v.y), c = __uint_as_float(v.z),
+                    d = __uint_as_float(v.w);
+        return (double)a * a + (double)b * b + (double)c * c + (double)d * d;
+    } else {
+        const double a = __hiloint2double((int)v.y, (int)v.x), b = __hiloint2double((int)v.w, (int)v.z);
+        return a * a + b * b;
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(OT) void k_occ_bits(const T *__restrict__ fa, const T *__restrict__ fb, int L,
-                                                 unsigned *__restrict__ bits, unsigned char *__restrict__ pxy) {
+                                                 unsigned *__restrict__ bits, unsigned char *__restrict__ pxy,
+                                                 double *__restrict__ sums) {
     constexpr int CPL = 16 / (int)sizeof(T), LPW = 32 / CPL;
+    __shared__ double red[OT / 64][2];
     const int lane = threadIdx.x & 63;
     const size_t line = (size_t)blockIdx.x * (OT / 64) + (threadIdx.x >> 6);
-    if (line >= (size_t)L * L) return;   // uniform per wave
-    const uint4 *a = reinterpret_cast<const uint4 *>(fa + line * L);
-    const uint4 *b = fb ? reinterpret_cast<const uint4 *>(fb + line * L) : nullptr;
-    const int W = L / 32, units = L / CPL;
+    const bool valid = line < (size_t)L * L;   // uniform per wave
+    const uint4 *a = reinterpret_cast<const uint4 *>(fa + (valid ? line : 0) * L);
+    const uint4 *b = fb ? reinterpret_cast<const uint4 *>(fb + (valid ? line : 0) * L) : nullptr;
+    const int W = L / 32, units = valid ? L / CPL : 0;
     unsigned any = 0;
+    double sa = 0.0, sb = 0.0;
     for (int j = 0; j * 64 < units; ++j) {
         const int q = j * 64 + lane;
         unsigned fl = 0;
@@ -55,8 +73,10 @@ __global__ __launch_bounds__(OT) void k_occ_bits(const T *__restrict__ fa, const
             // sign bits cleared: -0.0 adds nothing to any sum and counts as zero
             constexpr unsigned MLO = CPL == 4 ? 0x7fffffffu : 0xffffffffu;
             uint4 v = a[q];
+            if (sums) sa += sq16<T>(v);
             if (b) {
                 const uint4 v2 = b[q];
+                if (sums) sb += sq16<T>(v2);
                 v = uint4{v.x | v2.x, v.y | v2.y, v.z | v2.z, v.w | v2.w};
             }
             v = uint4{v.x & MLO, v.y & 0x7fffffffu, v.z & MLO, v.w & 0x7fffffffu};
@@ -74,7 +94,23 @@ __global__ __launch_bounds__(OT) void k_occ_bits(const T *__restrict__ fa, const
         if (lane % LPW == 0 && wi < W) bits[line * W + wi] = word;
     }
     const bool carry = __ballot(any != 0u) != 0ull;
-    if (lane == 0) pxy[line] = carry ? 1 : 0;
+    if (lane == 0 && valid) pxy[line] = carry ? 1 : 0;
+    if (sums) {   // uniform
+        for (int o = 32; o >= 1; o >>= 1) {
+            sa += __shfl_xor(sa, o);
+            sb += __shfl_xor(sb, o);
+        }
+        if (lane == 0) {
+            red[threadIdx.x >> 6][0] = sa;
+            red[threadIdx.x >> 6][1] = sb;
+        }
+        __syncthreads();
+        if (threadIdx.x < 2) {
+            double v = 0.0;
+            for (int w = 0; w < OT / 64; ++w) v += red[w][threadIdx.x];
+            sums[2 * blockIdx.x + threadIdx.x] = v;
+        }
+    }
 }
 
 // Projections onto the (x, z) and (y, z) planes: workgroups 0 .. L-1 write
@@ -265,7 +301,9 @@ int order_fields(conker_ctx *c, const conker_grid *g, bool f64, int ns, const vo
     const auto up = [](size_t b) { return (b + 255) / 256 * 256; };
     const size_t pxy_b = up((size_t)L * L), plane_b = up(W * L * sizeof(unsigned));
     const size_t bits_b = up((size_t)L * L * W * sizeof(unsigned));
-    const size_t head = pxy_b + 2 * plane_b + 256 + bits_b;
+    const unsigned blocks = (unsigned)(((size_t)L * L + OT / 64 - 1) / (OT / 64));
+    const size_t sums_b = up((size_t)blocks * 2 * sizeof(double));
+    const size_t head = pxy_b + 2 * plane_b + 256 + bits_b + sums_b;
     const size_t field_b = up(nc * esz);
     CK_OK(ws_reserve(c, c->order, head + (size_t)n_copy * field_b));
     char *base = (char *)c->order.p;
@@ -274,17 +312,18 @@ int order_fields(conker_ctx *c, const conker_grid *g, bool f64, int ns, const vo
     unsigned *pyz = (unsigned *)(base + pxy_b + plane_b);
     int *perm = (int *)(base + pxy_b + 2 * plane_b);
     unsigned *bits = (unsigned *)(base + pxy_b + 2 * plane_b + 256);
+    double *sums = (double *)(base + pxy_b + 2 * plane_b + 256 + bits_b);
+    // projections of the centre fields' support (they carry the factor F of every term)
+    const void *sa = in[n_in >= 4 ? 2 : 0], *sb = in[n_in >= 4 ? 3 : 1];
+    if (!sb) sums = nullptr;   // one field: nothing is packed beside it
     {
         ProfScope ps(c, PK_ORDER);
-        // projections of the centre fields' support (they carry the factor F of every term)
-        const void *sa = in[n_in >= 4 ? 2 : 0], *sb = in[n_in >= 4 ? 3 : 1];
-        const unsigned blocks = (unsigned)(((size_t)L * L + OT / 64 - 1) / (OT / 64));
         if (f64)
             hipLaunchKernelGGL(k_occ_bits<double>, dim3(blocks), dim3(OT), 0, c->stream, (const double *)sa,
-                               (const double *)sb, L, bits, pxy);
+                               (const double *)sb, L, bits, pxy, sums);
         else
             hipLaunchKernelGGL(k_occ_bits<float>, dim3(blocks), dim3(OT), 0, c->stream, (const float *)sa,
-                               (const float *)sb, L, bits, pxy);
+                               (const float *)sb, L, bits, pxy, sums);
         CK_LAUNCH(c);
         hipLaunchKernelGGL(k_occ_planes, dim3(2 * L), dim3(OT), 0, c->stream, bits, L, pxz, pyz);
         CK_LAUNCH(c);
@@ -319,6 +358,8 @@ int order_fields(conker_ctx *c, const conker_grid *g, bool f64, int ns, const vo
             CK_LAUNCH(c);
         }
         CK_OK(support_list(c, L, L, *sup));
+        sup->sums = sums;   // of the (unpermuted) centre fields: permutations keep them
+        sup->sums_n = sums ? (int)blocks : 0;
         if (have_sup) *have_sup = true;
     }
     return CONKER_OK;

@@ -1,9 +1,9 @@
 // Regions, maps and distributions.
 //
 // * Several regions or mocks measured separately (for instance the two
-//   galactic caps, Sec. 3.3) are combined by adding numerators and
+//   galactic caps, Sec. 3.4) are combined by adding numerators and
 //   denominators (Eq. ksi3combined): xi = sum_j W_delta_j / sum_j alpha_j^n W_R_j.
-// * The maps keep the location information (Sec. 4): the per-cell map
+// * The maps keep the location information (Sec. 4.2): the per-cell map
 //   W_0 W_1 / <B_0 B_1> of one radius is N(x) C^N(x) over the cell average of
 //   alpha^2 R_raw C^R, i.e. alpha^2 W_R2 / N_c; its cell average is the 2pcf.
 // * Distributions of map values: equal-width bins of [lo, hi) plus one bin

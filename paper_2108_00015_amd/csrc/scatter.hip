@@ -95,12 +95,13 @@ __global__ __launch_bounds__(256) void k_scatter(const float *__restrict__ pos,
 //                their brick's slots (ranks from LDS atomics);
 //   k_bin_accum  one workgroup per brick holding points: LDS tile sums, then
 //                the tile is added to the grid (the grid is accumulated into).
-//                Where the brick's point count times the largest |w| (from
-//                the count pass) stays below 2^22, the tile sums are 64-bit
-//                integers of w 2^40 (LDS integer adds run several times
-//                faster than float ones): exact for |w| >= 2^-17, rounded
-//                once when added to the grid, and independent of the order;
-//                other bricks add floats.
+//                The tile sums are 64-bit integers of w 2^E (LDS integer
+//                adds run several times faster than float ones), E chosen
+//                per brick from its point count times the largest |w| (from
+//                the count pass) so that no sum can leave 62 bits; each w is
+//                rounded to nearest (unbiased), the sums are independent of
+//                the order and rounded once when added to the grid.  Bricks
+//                whose bound is not finite add floats.
 // The sums are the same as the direct kernel's, in another order (exact for
 // unit weights, which give integer counts).
 // ---------------------------------------------------------------------------
@@ -263,8 +264,19 @@ __global__ __launch_bounds__(256) void k_bin_accum(const uint2 *__restrict__ ite
     const int b = blockIdx.x;
     const unsigned i0 = start[b], i1 = start[b + 1];
     if (i0 == i1) return;   // uniform: no point in this brick
-    // every cell sum of the brick stays below (i1 - i0) max|w| < 2^22: w 2^40 fits 64 bits
-    const bool fixed = (float)(i1 - i0) * __uint_as_float(*wmax_bits) < 4194304.0f;   // uniform
+    // Fixed point w 2^E with 2^E chosen per brick so that every cell sum stays
+    // within (i1 - i0) max|w| 2^E <= 2^62 (int64): each w is rounded to the
+    // nearest multiple of 2^-E, exactly for |w| >= 2^(23 - E) (unit weights
+    // always; in a brick of 2^13 points every |w| >= 2^-26 max|w|), so the
+    // sums are unbiased and independent of the order.  Bricks whose bound is
+    // not finite add floats.  Uniform over the workgroup.
+    const float bound = (float)(i1 - i0) * __uint_as_float(*wmax_bits);
+    int eb = 0;
+    (void)frexpf(bound, &eb);                       // bound < 2^eb
+    const int E = bound > 0.f ? min(62 - eb, 126) : 0;   // eb <= 128: E >= -66
+    const bool fixed = isfinite(bound);
+    const float to_fixed = ldexpf(1.0f, E);
+    const double from_fixed = ldexp(1.0, -E);
     for (int e = threadIdx.x; e < BCELLS; e += 256) acc[e] = 0ull;   // zero bits: 0 in every view
     __syncthreads();
     for (unsigned i = i0 + threadIdx.x; i < i1; i += 4 * 256) {
@@ -275,7 +287,7 @@ __global__ __launch_bounds__(256) void k_bin_accum(const uint2 *__restrict__ ite
         for (int k = 0; k < 4; ++k)
             if (i + k * 256 < i1) {
                 const float wv = __uint_as_float(it[k].y);
-                if (fixed) atomicAdd(&acc[it[k].x], (unsigned long long)(long long)(wv * 1099511627776.0f));
+                if (fixed) atomicAdd(&acc[it[k].x], (unsigned long long)__float2ll_rn(wv * to_fixed));
                 else atomicAdd(&tile[it[k].x], (T)wv);
             }
     }
@@ -298,8 +310,7 @@ __global__ __launch_bounds__(256) void k_bin_accum(const uint2 *__restrict__ ite
         const int e = (threadIdx.x + k * 256) * V;
 #pragma unroll
         for (int j = 0; j < V; ++j) {
-            const T s = fixed ? (T)((double)(long long)acc[e + j] * 9.094947017729282379e-13)   // 2^-40
-                              : tile[e + j];
+            const T s = fixed ? (T)((double)(long long)acc[e + j] * from_fixed) : tile[e + j];
             grid[lin[k] + j] = v[k][j] + s;
         }
     }

@@ -1,6 +1,6 @@
 // Two further forms of the estimator:
 //
-// * Continuous tracers (Sec. 2.6, Eq. densitycont): the field is the relative
+// * Continuous tracers (Sec. 2.7, Eq. densitycont): the field is the relative
 //   over-density delta = (D - R) / R of two continuous maps on the grid; it is
 //   convolved and summed like N (Eq. ksin_cont) with no normalisation after.
 //
@@ -13,7 +13,7 @@
 //   The sum over all k is folded onto the stored octant: every octant point
 //   (kx <= nx/2, ky <= ny/2, kz <= nz/2) stands for its 1, 2, 4 or 8 sign
 //   mirrors, which share the value of K_m^ and hold -k for each of their k.
-//   Cross-correlations of the two fields (Sec. 2.7) come out of the same pass.
+//   Cross-correlations of the two fields (Sec. 2.8) come out of the same pass.
 #include <algorithm>
 
 #include "common.h"
@@ -136,8 +136,10 @@ __global__ __launch_bounds__(NT) void k_pair_spectral(const typename std::condit
 }
 
 // part rows [ns][blocks][3] -> W_aa[m], W_bb[m], W_ab[m] (any may be NULL), fixed order.
+// b was transformed times the pair's scale s: W_bb carries s^2, W_ab s.
 __global__ __launch_bounds__(NT) void k_spectral_reduce(const double *__restrict__ part, int blocks, int ns,
-                                                        double *Waa, double *Wbb, double *Wab) {
+                                                        double *Waa, double *Wbb, double *Wab,
+                                                        const PackScale *ps) {
     __shared__ double red[NT];
     const int m = blockIdx.x;
     for (int j = 0; j < 3; ++j) {
@@ -151,7 +153,10 @@ __global__ __launch_bounds__(NT) void k_spectral_reduce(const double *__restrict
         }
         if (threadIdx.x == 0) {
             double *o = j == 0 ? Waa : (j == 1 ? Wbb : Wab);
-            if (o) o[m] = red[0];
+            double v = red[0];
+            if (j == 1) v *= ps->s_inv * ps->s_inv;   // powers of two: exact
+            if (j == 2) v *= ps->s_inv;
+            if (o) o[m] = v;
         }
         __syncthreads();
     }
@@ -232,7 +237,7 @@ extern "C" int conker_pair_spectral(conker_ctx *c, const conker_grid *g, conker_
     }
     ProfScope ps(c, PK_DIAG_REDUCE);
     hipLaunchKernelGGL(k_spectral_reduce, dim3(n_radii), dim3(NT), 0, c->stream, (const double *)c->partial.p, blocks,
-                       n_radii, W_aa, fb ? W_bb : nullptr, fb ? W_ab : nullptr);
+                       n_radii, W_aa, fb ? W_bb : nullptr, fb ? W_ab : nullptr, pack_scale_dev(c));
     CK_LAUNCH(c);
     return CONKER_OK;
 }

@@ -26,21 +26,41 @@ constexpr int ST = 256;   // threads per workgroup (4 waves)
 
 // sm: the bits other than the sign of the four 32-bit words of 16 bytes
 // (float32: every word; float64: the high word of each value).
+// With `sums` (both fields given): also each field's sum of squares over the
+// slab, written as the pair sums[2 x + {0, 1}] (the packed transform's scale
+// is chosen from them).
+template <typename T>
+__device__ __forceinline__ double sq16(const uint4 &v) {   // sum of squares of the values in 16 bytes
+    if constexpr (sizeof(T) == 4) {
+        const float a = __uint_as_float(v.x), b = __uint_as_float(v.y), c = __uint_as_float(v.z),
+                    d = __uint_as_float(v.w);
+        return (double)a * a + (double)b * b + (double)c * c + (double)d * d;
+    } else {
+        const double a = __hiloint2double((int)v.y, (int)v.x), b = __hiloint2double((int)v.w, (int)v.z);
+        return a * a + b * b;
+    }
+}
+
+template <typename T>
 __global__ __launch_bounds__(ST) void k_line_mask(const uint4 *__restrict__ fa, const uint4 *__restrict__ fb,
                                                   int ny, int units, uint4 sm, unsigned char *__restrict__ mask,
-                                                  int *__restrict__ xcount) {
+                                                  int *__restrict__ xcount, double *__restrict__ sums) {
     __shared__ int cnt[ST / 64];
+    __shared__ double red[ST / 64][2];
     const int x = blockIdx.x, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     int c = 0;
+    double sa = 0.0, sb = 0.0;
     for (int y = w; y < ny; y += ST / 64) {
         const size_t base = ((size_t)x * ny + y) * units;
         unsigned any = 0;
         for (int u = lane; u < units; u += 64) {
             const uint4 a = fa[base + u];
             any |= (a.x & sm.x) | (a.y & sm.y) | (a.z & sm.z) | (a.w & sm.w);
+            if (sums) sa += sq16<T>(a);
             if (fb) {
                 const uint4 b = fb[base + u];
                 any |= (b.x & sm.x) | (b.y & sm.y) | (b.z & sm.z) | (b.w & sm.w);
+                if (sums) sb += sq16<T>(b);
             }
         }
         const bool on = __ballot(any != 0u) != 0ull;
@@ -50,11 +70,26 @@ __global__ __launch_bounds__(ST) void k_line_mask(const uint4 *__restrict__ fa, 
         }
     }
     if (lane == 0) cnt[w] = c;
+    if (sums) {   // uniform
+        for (int o = 32; o >= 1; o >>= 1) {
+            sa += __shfl_xor(sa, o);
+            sb += __shfl_xor(sb, o);
+        }
+        if (lane == 0) {
+            red[w][0] = sa;
+            red[w][1] = sb;
+        }
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         int s = 0;
         for (int i = 0; i < ST / 64; ++i) s += cnt[i];
         xcount[x] = s;
+    }
+    if (sums && threadIdx.x < 2) {
+        double v = 0.0;
+        for (int i = 0; i < ST / 64; ++i) v += red[i][threadIdx.x];
+        sums[2 * x + threadIdx.x] = v;
     }
 }
 
@@ -99,18 +134,21 @@ __global__ __launch_bounds__(ST) void k_line_list(const unsigned char *__restric
 
 namespace conker {
 
-int support_alloc(conker_ctx *c, int nx, int ny, Support *out, unsigned char **mask, int **xcount) {
+int support_alloc(conker_ctx *c, int nx, int ny, Support *out, unsigned char **mask, int **xcount,
+                  double **sums_slot) {
     *out = Support{};
     const size_t nl = (size_t)nx * ny;
     const size_t mask_b = (nl + 255) / 256 * 256;
     const size_t xc_b = ((size_t)nx * sizeof(int) + 255) / 256 * 256;
     const size_t list_b = (nl * sizeof(int) + 255) / 256 * 256;
-    CK_OK(ws_reserve(c, c->support, mask_b + xc_b + list_b + 256));
+    const size_t sums_b = ((size_t)nx * 2 * sizeof(double) + 255) / 256 * 256;
+    CK_OK(ws_reserve(c, c->support, mask_b + xc_b + list_b + 256 + sums_b));
     char *p = (char *)c->support.p;
     out->mask = *mask = (unsigned char *)p;
     out->xcount = *xcount = (int *)(p + mask_b);
     out->list = (int *)(p + mask_b + xc_b);
     out->count = (int *)(p + mask_b + xc_b + list_b);
+    if (sums_slot) *sums_slot = (double *)(p + mask_b + xc_b + list_b + 256);   // room for nx pairs
     return CONKER_OK;
 }
 
@@ -129,16 +167,24 @@ int support_lines(conker_ctx *c, const conker_grid *g, bool f64, const void *fa,
         return fail(c, CONKER_EINVAL, "fields must be 16-byte aligned");
     unsigned char *mask;
     int *xcount;
-    CK_OK(support_alloc(c, nx, ny, out, &mask, &xcount));
+    double *sums;
+    CK_OK(support_alloc(c, nx, ny, out, &mask, &xcount, &sums));
     const int units = (int)((size_t)nz * (f64 ? 8 : 4) / 16);   // 16-byte words per line
+    if (!fb) sums = nullptr;   // one field: nothing is packed beside it
     {
         ProfScope ps(c, PK_SUPPORT);
         const uint4 sm = f64 ? uint4{0xffffffffu, 0x7fffffffu, 0xffffffffu, 0x7fffffffu}
                              : uint4{0x7fffffffu, 0x7fffffffu, 0x7fffffffu, 0x7fffffffu};
-        hipLaunchKernelGGL(k_line_mask, dim3(nx), dim3(ST), 0, c->stream, (const uint4 *)fa, (const uint4 *)fb, ny,
-                           units, sm, mask, xcount);
+        if (f64)
+            hipLaunchKernelGGL(k_line_mask<double>, dim3(nx), dim3(ST), 0, c->stream, (const uint4 *)fa,
+                               (const uint4 *)fb, ny, units, sm, mask, xcount, sums);
+        else
+            hipLaunchKernelGGL(k_line_mask<float>, dim3(nx), dim3(ST), 0, c->stream, (const uint4 *)fa,
+                               (const uint4 *)fb, ny, units, sm, mask, xcount, sums);
         CK_LAUNCH(c);
     }
+    out->sums = sums;
+    out->sums_n = sums ? nx : 0;
     return support_list(c, nx, ny, *out);
 }
 

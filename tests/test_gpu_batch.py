@@ -256,3 +256,48 @@ def test_batch_axis_order_under_graph_capture():
     assert used1 == 1
     for k in range(len(cats)):
         assert _rel(first[k], given[k]) <= 1e-5, (k, _rel(first[k], given[k]))
+
+
+def test_batch_graph_dropped_when_workspace_grows():
+    """A captured batch records the context's workspace addresses.  An eager
+    call that makes the workspace grow (here a larger grid) frees those
+    buffers, so the captured batch is dropped with them: launching it then
+    reports an error instead of replaying on freed memory, and a new capture
+    runs again."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2108_00015_amd as ck
+    DEV = "cuda:0"
+    dims, cell = (32, 32, 512), 1.0
+    radii = [1.0, 2.0, 3.5]
+    d = synth.neyman_scott_box(3000, 30, 1.5, 0.0, 30.0, seed=520)
+    r = synth.uniform_box(30000, 0.0, 30.0, seed=720)
+    ctx = ck.Context(0, stream=torch.cuda.Stream())
+    grid = ck.Grid(dims, (0, 0, 0), cell)
+    ks, _ = ctx.make_shell_kernels(grid, radii, torch.float32)
+    jobs = [ck.make_job(grid, ks, 3, "split_bf16", torch.from_numpy(d).to(DEV), torch.from_numpy(r).to(DEV))]
+    torch.cuda.synchronize()
+    ctx.batch_plan(jobs)
+    first = _outs(jobs)
+    ctx.batch_capture()
+    ctx.batch_launch()
+    ctx.synchronize()
+    # an eager call on a grid four times larger grows the spectrum buffers
+    big = ck.Grid((64, 64, 512), (0, 0, 0), cell)
+    ksb, _ = ctx.make_shell_kernels(big, radii, torch.float32)
+    f = torch.zeros(big.dims, dtype=torch.float32, device=DEV)
+    f[10, 10, 10] = 1.0
+    ctx.convolve_contract(big, f, f.clone(), ksb, 3, "split_bf16")
+    ctx.synchronize()
+    with pytest.raises(ck.ConkerError) as e:
+        ctx.batch_launch()
+    assert "no captured batch" in str(e.value)
+    ctx.batch_capture()
+    for j in jobs:
+        j.W_delta.fill_(5.0)
+    torch.cuda.synchronize()
+    ctx.batch_launch()
+    ctx.synchronize()
+    for k, o in enumerate(_outs(jobs)):
+        assert _rel(o, first[k]) <= 1e-5
+    ctx.close()

@@ -1,4 +1,4 @@
-"""Cross-correlation (Sec. 2.7), continuous delta fields (Sec. 2.6) and the
+"""Cross-correlation (Sec. 2.8), continuous delta fields (Sec. 2.7) and the
 n = 2 Fourier-space form, through the C ABI against the FP64 oracle.
 
 Error measure: max |got - ref| / max |ref| over one output vector.  Bars:

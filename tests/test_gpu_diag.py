@@ -189,9 +189,6 @@ def test_convolve_diag_sparse_support(ck, ctx, dims, dt):
     rng = np.random.default_rng(42)
     nx, ny, nz = dims
     A, B = _fields(dims, dt, 43)
-    # non-negative (count-like) fields: sums without cancellation, so that the
-    # relative bar measures the arithmetic; the masking is exercised all the same
-    A = np.abs(A)
     x = np.arange(nx)[:, None]
     y = np.arange(ny)[None, :]
     keep = ((x - nx / 2) / (nx / 2)) ** 2 + ((y - ny / 2) / (ny / 2)) ** 2 <= 0.6

@@ -1,5 +1,5 @@
 """Regions combined (Eq. ksi3combined), per-cell W_0 W_1 / <B_0 B_1> maps and
-value histograms (Sec. 4) through the C ABI against the FP64 oracle.
+value histograms (Sec. 4.2) through the C ABI against the FP64 oracle.
 Bars: float64 <= 1e-12 (elementwise relative to the largest value); the
 histograms are integer counts and must match exactly.
 """

@@ -378,7 +378,7 @@ def test_distance_calibration_rms_matches_paper():
 
 
 # ---------------------------------------------------------------------------
-# continuous delta fields (Sec. 2.6) and cross-correlation (Sec. 2.7)
+# continuous delta fields (Sec. 2.7) and cross-correlation (Sec. 2.8)
 # ---------------------------------------------------------------------------
 
 def test_delta_field_closed_forms():

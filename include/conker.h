@@ -221,6 +221,21 @@ int conker_contract_diag(conker_ctx *ctx, const conker_grid *grid, conker_dtype 
                          const void *d_field, const void *d_maps, int n_radii, int n_max,
                          double *d_out);
 
+/* conker_contract_diag_noalloc: conker_contract_diag for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, kernels and results; it
+ * calls no hipMalloc, hipFree or allocating routine.  Its partial sums live in
+ * a fixed device array of 2^19 doubles (4 MiB) per GPU, held from the first
+ * conker_create on that GPU until the process ends: calls needing more
+ * (n_radii x workgroups x (n_max - 1), at most 64 radii on grids of 2^21
+ * cells and more) fail with CONKER_ERANGE.  Every call on one GPU shares that
+ * array, so calls that overlap on one GPU (other streams, other contexts)
+ * race; calls in one stream are ordered and safe.  Each call overwrites every
+ * partial it reads, so nothing needs clearing between calls. */
+int conker_contract_diag_noalloc(conker_ctx *ctx, const conker_grid *grid, conker_dtype dtype,
+                                 const void *d_field, const void *d_maps, int n_radii, int n_max,
+                                 double *d_out);
+
 /* conker_convolve_diag: the same sums for field_a (and field_b) straight from
  * the kernel bank, without storing any map: the last inverse FFT pass of each
  * radius feeds the sums instead of memory, so the device holds only the

@@ -43,6 +43,8 @@ SIGNATURES = {
                                             ct.c_void_p]),
     "conker_contract_diag": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_void_p,
                                         ct.c_int, ct.c_int, ct.c_void_p]),
+    "conker_contract_diag_noalloc": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_void_p,
+                                                ct.c_int, ct.c_int, ct.c_void_p]),
     "conker_convolve_diag": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_void_p,
                                         ct.c_void_p, ct.c_int, ct.c_int, ct.c_void_p, ct.c_void_p]),
     "conker_convolve_contract_cross": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_void_p,

@@ -354,6 +354,20 @@ class Context:
                                                   nr, int(n_max), _ptr(out)))
         return out
 
+    def contract_diag_noalloc(self, grid: Grid, field: torch.Tensor, maps: torch.Tensor, n_max: int,
+                              out: torch.Tensor) -> torch.Tensor:
+        """contract_diag into a caller-given out ([n_max - 1, n_radii] float64): the library
+        allocates nothing (conker_contract_diag_noalloc)."""
+        nr = int(maps.shape[0])
+        if maps.dtype != field.dtype or maps.numel() != nr * grid.n_cells or field.numel() != grid.n_cells:
+            raise ValueError("field / maps shape or dtype mismatch")
+        if out.dtype != torch.float64 or out.numel() != (n_max - 1) * nr:
+            raise ValueError("out must be float64 with (n_max - 1) * n_radii values")
+        g = grid.c()
+        self._check(self.lib.conker_contract_diag_noalloc(self.h, ct.byref(g), _DT[field.dtype], _ptr(field),
+                                                          _ptr(maps), nr, int(n_max), _ptr(out)))
+        return out
+
     def convolve_diag(self, grid: Grid, field_a: torch.Tensor, field_b: Optional[torch.Tensor],
                       kspec: torch.Tensor, n_max: int, centre_a: Optional[torch.Tensor] = None,
                       centre_b: Optional[torch.Tensor] = None):

@@ -154,6 +154,10 @@ int fail(conker_ctx *ctx, int code, const char *fmt, ...);
 // context's workspace cap.  Waits for the stream before releasing memory.
 int ws_reserve(conker_ctx *ctx, Buf &b, size_t bytes);
 
+// Looks up this device's copy of the allocation-free call's scratch array
+// (diag.hip); the device must be current.  Once per device.
+int noalloc_init(int device);
+
 // Number of compute units of the context's device (cached).
 int cu_count(conker_ctx *ctx);
 

@@ -207,6 +207,10 @@ extern "C" int conker_create(conker_ctx **out, int device, void *stream, size_t 
     if (device < 0 || device >= n) return fail(nullptr, CONKER_EINVAL, "device %d out of range", device);
     e = hipSetDevice(device);
     if (e != hipSuccess) return fail(nullptr, CONKER_EHIP, "hipSetDevice: %s", hipGetErrorString(e));
+    {
+        const int st = noalloc_init(device);   // device current: its copy of the scratch array
+        if (st != CONKER_OK) return st;
+    }
     conker_ctx *c = new conker_ctx();
     c->device = device;
     c->stream = (hipStream_t)stream;

@@ -7,12 +7,25 @@
 // Both write per-workgroup FP64 partial rows that one kernel reduces in a
 // fixed order, so results do not depend on scheduling.
 #include <algorithm>
+#include <mutex>
 
 #include "common.h"
 
 using namespace conker;
 
+// Partial rows of conker_contract_diag_noalloc: a file-scope device array (one
+// copy per GPU, held until the process ends) in place of the context's
+// workspace, so that the call allocates nothing.  Host code never passes this
+// name to a kernel: the address of each device's copy is looked up once per
+// device (noalloc_init) and that address is used.
+constexpr size_t NOALLOC_DOUBLES = (size_t)1 << 19;   // 4 MiB
+static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+
 namespace {
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_noalloc_mu;
+void *g_noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
 
 constexpr int DT = 256;   // threads of the map and reduce kernels
 
@@ -152,7 +165,37 @@ int check_common(conker_ctx *c, const conker_grid *g, conker_dtype dt, int ns, i
     return CONKER_OK;
 }
 
+// Workgroups of the map kernel and the cells each covers (a whole number of
+// vector steps).
+void diag_plan(size_t nc, bool f64, int *G_out, size_t *chunk_out) {
+    const size_t step = (size_t)DT * (f64 ? 2 : 4);
+    int G = (int)std::min<size_t>(2048, std::max<size_t>(1, nc / (4 * step)));
+    size_t chunk = (nc + G - 1) / G;
+    chunk = (chunk + step - 1) / step * step;
+    *G_out = (int)((nc + chunk - 1) / chunk);
+    *chunk_out = chunk;
+}
+
 }  // namespace
+
+namespace conker {
+
+// Address of this device's copy of `scratch`, looked up once per device with
+// that device current (conker_create).
+int noalloc_init(int device) {
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES) return CONKER_OK;   // the call then reports it
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (g_noalloc_ptr[device]) return CONKER_OK;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        return fail(nullptr, CONKER_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", device,
+                    hipGetErrorString(e));
+    g_noalloc_ptr[device] = ptr;
+    return CONKER_OK;
+}
+
+}  // namespace conker
 
 extern "C" int conker_contract_diag(conker_ctx *c, const conker_grid *g, conker_dtype dt, const void *field,
                                     const void *maps, int n_radii, int n_max, double *out) {
@@ -161,11 +204,9 @@ extern "C" int conker_contract_diag(conker_ctx *c, const conker_grid *g, conker_
     CK_HIP(c, hipSetDevice(c->device));
     const size_t nc = ncells(g);
     const bool f64 = dt == CONKER_F64;
-    const size_t step = (size_t)DT * (f64 ? 2 : 4);
-    int G = (int)std::min<size_t>(2048, std::max<size_t>(1, nc / (4 * step)));
-    size_t chunk = (nc + G - 1) / G;
-    chunk = (chunk + step - 1) / step * step;
-    G = (int)((nc + chunk - 1) / chunk);
+    int G;
+    size_t chunk;
+    diag_plan(nc, f64, &G, &chunk);
     const int P = n_max - 1;
     CK_OK(ws_reserve(c, c->partial, (size_t)n_radii * G * P * sizeof(double)));
     double *part = (double *)c->partial.p;
@@ -175,6 +216,38 @@ extern "C" int conker_contract_diag(conker_ctx *c, const conker_grid *g, conker_
         else CK_OK(launch_maps<float>(c, (const float *)field, (const float *)maps, nc, n_radii, P, G, chunk, part));
     }
     return reduce(c, part, G, n_radii, 1, P, out, nullptr, nullptr);
+}
+
+// The same sums with the partial rows in the file-scope `scratch` array: no
+// allocation, no memset, no event; the maps kernel overwrites every row the
+// reduction reads.  Calls that overlap on one GPU share the array and race.
+extern "C" int conker_contract_diag_noalloc(conker_ctx *c, const conker_grid *g, conker_dtype dt,
+                                            const void *field, const void *maps, int n_radii, int n_max,
+                                            double *out) {
+    CK_OK(check_common(c, g, dt, n_radii, n_max));
+    if (!field || !maps || !out) return fail(c, CONKER_EINVAL, "NULL pointer");
+    const size_t nc = ncells(g);
+    const bool f64 = dt == CONKER_F64;
+    int G;
+    size_t chunk;
+    diag_plan(nc, f64, &G, &chunk);
+    const int P = n_max - 1;
+    const size_t need = (size_t)n_radii * G * P;
+    if (need > NOALLOC_DOUBLES)
+        return fail(c, CONKER_ERANGE,
+                    "allocation-free call: %d radii x %d workgroups x %d powers = %zu partial sums, above its "
+                    "fixed %zu (n_radii <= %zu at n_max %d on this grid)",
+                    n_radii, G, P, need, NOALLOC_DOUBLES, NOALLOC_DOUBLES / ((size_t)G * P), n_max);
+    if (c->device < 0 || c->device >= NOALLOC_MAX_DEVICES || !g_noalloc_ptr[c->device])
+        return fail(c, CONKER_EHIP, "allocation-free scratch of device %d not set up", c->device);
+    double *part = (double *)g_noalloc_ptr[c->device];
+    CK_HIP(c, hipSetDevice(c->device));
+    if (f64) CK_OK(launch_maps<double>(c, (const double *)field, (const double *)maps, nc, n_radii, P, G, chunk, part));
+    else CK_OK(launch_maps<float>(c, (const float *)field, (const float *)maps, nc, n_radii, P, G, chunk, part));
+    hipLaunchKernelGGL(k_diag_reduce, dim3(n_radii), dim3(DT), 0, c->stream, part, G, n_radii, 1, P, out, nullptr,
+                       nullptr);
+    CK_LAUNCH(c);
+    return CONKER_OK;
 }
 
 // Maps from fa (fb), summed against the centre fields ca (cb).

@@ -504,9 +504,10 @@ __device__ __forceinline__ T scale_inv_of(const PackScale *ps) {
 // ---------------------------------------------------------------------------
 // With `mask` (line flags [nx * ny], both fields zero on lines without one):
 // z-line tiles without a flagged line do nothing, and only flagged lines are
-// written (the y pass then reads the others as zero).  With `ps`, b is
-// multiplied by the pair's scale s.
-template <typename T>
+// written (the y pass then reads the others as zero).  TWO: b is given and
+// multiplied by the pair's scale s (a separate instantiation, so that no
+// branch on b sits between the loads of a tile and they all issue together).
+template <typename T, bool TWO>
 struct OpPack {
     static constexpr bool STAGED = false;   // z pass, forward: (a + i s b) -> spec
     using C = cplx<T>;
@@ -524,9 +525,11 @@ struct OpPack {
         g = make_tile(AX_Z, d, blockIdx.x, TC);
         tcn = TC;
         a += g.base;
-        if (b) b += g.base;
+        if constexpr (TWO) {
+            b += g.base;
+            sb = scale_of<T>(ps);
+        }
         out += g.base;
-        sb = ps ? scale_of<T>(ps) : (T)1;
     }
     __device__ bool active() const {   // the same for every thread: any line of the tile flagged
         if (!mask) return true;
@@ -538,7 +541,8 @@ struct OpPack {
     __device__ void set_iter(int) {}
     __device__ C load(int i, int c) const {
         const unsigned k = off(g, i, c);
-        return C{a[k], b ? b[k] * sb : (T)0};
+        if constexpr (TWO) return C{a[k], b[k] * sb};
+        else return C{a[k], (T)0};
     }
     __device__ void store(int i, int c, C v) const {
         if (mask && !mask[(size_t)g.p0 + c]) return;
@@ -1175,9 +1179,13 @@ int forward_pair_t(conker_ctx *ctx, const conker_grid *g, const void *a, const v
             CK_OK(pack_scale_t<T>(ctx, nc, (const T *)a, (const T *)b));
         }
     }
-    OpPack<T> pz{twz, d, (const T *)a, (const T *)b, (C *)spec, {}, mask, 0, b ? pack_scale_dev(ctx) : nullptr,
-                 (T)1};
-    CK_OK((launch_len<T, -1>(ctx, PK_FFT_FWD_Z, TM_J, d.nz, AX_Z, d, dim3(1, 1), pz)));
+    if (b) {
+        OpPack<T, true> pz{twz, d, (const T *)a, (const T *)b, (C *)spec, {}, mask, 0, pack_scale_dev(ctx), (T)1};
+        CK_OK((launch_len<T, -1>(ctx, PK_FFT_FWD_Z, TM_J, d.nz, AX_Z, d, dim3(1, 1), pz)));
+    } else {
+        OpPack<T, false> pz{twz, d, (const T *)a, nullptr, (C *)spec, {}, mask, 0, nullptr, (T)1};
+        CK_OK((launch_len<T, -1>(ctx, PK_FFT_FWD_Z, TM_J, d.nz, AX_Z, d, dim3(1, 1), pz)));
+    }
     OpInplace<T, true> py{twy, d, AX_Y, (C *)spec, nc, {}, nullptr, nullptr, xcount, mask, nullptr};
     CK_OK((launch_len<T, -1>(ctx, PK_FFT_FWD_Y, col_mode_for<T>(ctx, d, AX_Y), d.ny, AX_Y, d, dim3(1, 1), py)));
     OpInplace<T, true> px{twx, d, AX_X, (C *)spec, nc, {}, nullptr, nullptr, nullptr, nullptr, xcount};

@@ -1,7 +1,9 @@
 """Batches of independent mocks through conker_batch_*: the eager planning pass,
 eager re-runs and HIP-graph replays agree with each other and with the FP64
-oracle (Eq. ksi3combined is then a sum over jobs).  Grids of 96, 128 and 192
-cells per side exercise the radix-3 FFT lengths beside the powers of two.
+oracle (Eq. ksi3combined is then a sum over jobs).  Grids of 96, 128, 192 and
+256 cells per side (every size class of the mock workload, radix-3 FFT lengths
+beside the powers of two) with 50k-400k clustered points and ten times as many
+randoms; one mock of each size class is checked against the oracle.
 """
 import sys
 
@@ -18,7 +20,8 @@ pytestmark = pytest.mark.gpu
 CELL = 5.0
 RADII = synth.MOCK_RADII          # 16 shells, 10 .. 85
 SAMPLE = (0, 7, 15)               # shells the oracle convolves
-MOCKS = ((96, 20_000), (128, 30_000), (192, 40_000), (96, 10_000))
+MOCKS = ((96, 50_000), (128, 120_000), (192, 250_000), (96, 80_000), (256, 400_000))
+CHECKED = (0, 1, 2, 4)            # one mock of each size class against the oracle
 
 
 def _say(*a):
@@ -37,11 +40,9 @@ def mocks():
     return [synth.mock_catalog(j, g, n, cell=CELL) for j, (g, n) in enumerate(MOCKS)]
 
 
-@pytest.fixture(scope="module")
-def oracle_first(mocks):
-    """FP64 oracle for mock 0 (96^3): alpha, and W_n over the tuples of SAMPLE."""
-    g = MOCKS[0][0]
-    d, r = mocks[0]
+def _oracle_mock(mock, g):
+    """FP64 oracle for one mock: alpha, and W_n over the tuples of SAMPLE (n = 2, 3)."""
+    d, r = mock
     dims = (g, g, g)
     D, wd, _ = oc.histogram(d.pos, d.w, (0.0, 0.0, 0.0), CELL, dims)
     R, wr, _ = oc.histogram(r.pos, r.w, (0.0, 0.0, 0.0), CELL, dims)
@@ -54,6 +55,12 @@ def oracle_first(mocks):
         tl = [tuple(SAMPLE[i] for i in t) for t in loc]
         ref[n] = (tl, oc.contract(N, mN, n, loc), oc.contract(R, mR, n, loc))
     return alpha, ref
+
+
+@pytest.fixture(scope="module")
+def oracle_classes(mocks):
+    """The oracle of one mock per size class: {job index: (alpha, ref)}."""
+    return {k: _oracle_mock(mocks[k], MOCKS[k][0]) for k in CHECKED}
 
 
 def _pick(W, n, tuples):
@@ -92,7 +99,7 @@ def _outs(jobs):
 @pytest.mark.parametrize("maps", ["stored", "workspace"])
 @pytest.mark.parametrize("path", ["fp64", "mixed"])
 @pytest.mark.parametrize("n", [3, 2])
-def test_batch_eager_graph_oracle(mocks, oracle_first, path, n, maps):
+def test_batch_eager_graph_oracle(mocks, oracle_classes, path, n, maps):
     import paper_2108_00015_amd as ck
     dtype = torch.float64 if path == "fp64" else torch.float32
     prec = "f64" if path == "fp64" else "split_bf16"
@@ -126,16 +133,18 @@ def test_batch_eager_graph_oracle(mocks, oracle_first, path, n, maps):
     for k in range(len(jobs)):
         for o in [again[k]] + [gr[k] for gr in graphs]:
             assert _rel(o, first[k]) <= tol_self, (k, _rel(o, first[k]))
-    # oracle on mock 0
-    alpha, ref = oracle_first
-    tl, rd, rr = ref[n]
-    j0 = jobs[0]
-    gd = _pick(graphs[-1][0][:len(j0.W_delta)], n, tl)
-    gr_ = _pick(graphs[-1][0][len(j0.W_delta):2 * len(j0.W_delta)], n, tl)
-    ed, er = _rel(gd, rd), _rel(gr_, rr)
-    _say("  oracle mock0: W_delta %.3e W_R %.3e" % (ed, er))
-    assert ed <= tol_ref and er <= tol_ref
-    assert abs(j0.alpha.item() - alpha) <= 1e-13 * alpha
+    # oracle on one mock per size class, from the last graph replay
+    for k in CHECKED:
+        alpha, ref = oracle_classes[k]
+        tl, rd, rr = ref[n]
+        jk = jobs[k]
+        nt = len(jk.W_delta)
+        gd = _pick(graphs[-1][k][:nt], n, tl)
+        gr_ = _pick(graphs[-1][k][nt:2 * nt], n, tl)
+        ed, er = _rel(gd, rd), _rel(gr_, rr)
+        _say("  oracle mock %d (%d^3): W_delta %.3e W_R %.3e" % (k, MOCKS[k][0], ed, er))
+        assert ed <= tol_ref and er <= tol_ref, k
+        assert abs(jk.alpha.item() - alpha) <= 1e-13 * alpha
     ctx.close()
 
 

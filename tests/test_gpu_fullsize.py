@@ -1,8 +1,8 @@
 """Parity at full size: the survey-cap workload (512^3 grid, 30 shells, 800k + 32M
 weighted tracers) in the configuration bench.py times, against the FP64 oracle
 on sampled outputs it can afford: the histograms and alpha in full, the maps of
-two shells at sampled cells (direct shell sums), and W_2 / W_3 for the tuples
-among the sampled shells.
+two shells at sampled cells (direct shell sums), and W_2, W_3 and W_4 for the
+tuples among the sampled shells.
 """
 import sys
 
@@ -39,7 +39,7 @@ def cap():
     mN = oc.convolve_shells(N, rc)
     mR = oc.convolve_shells(R, rc)
     ref = {}
-    for n in (2, 3):
+    for n in (2, 3, 4):
         tl = [tuple(SAMPLE[i] for i in t) for t in oc.radius_tuples(len(SAMPLE), n)]
         loc = [tuple(i for i in t) for t in oc.radius_tuples(len(SAMPLE), n)]
         ref[n] = (tl, oc.contract(N, mN, n, loc), oc.contract(R, mR, n, loc))
@@ -55,6 +55,12 @@ def _pick(W, ns, n, tuples):
 
 def _rel(got, ref):
     return float(np.abs(got - ref).max() / np.abs(ref).max())
+
+
+def _rel_each(got, ref):
+    """Tuple by tuple, for sums that are positive in every tuple (W_R)."""
+    assert np.all(ref > 0)
+    return float((np.abs(got - ref) / ref).max())
 
 
 @pytest.mark.parametrize("path", ["fp64", "mixed"])
@@ -81,10 +87,10 @@ def test_cap512_full_size_sampled(cap, path):
         tl, rd, rr = o["ref"][n]
         gd = _pick(out["W_delta"].cpu().numpy(), ns, n, tl)
         gr = _pick(out["W_rand_raw"].cpu().numpy(), ns, n, tl)
-        ed, er = _rel(gd, rd), _rel(gr, rr)
-        _say("  n=%d W_delta %.3e W_R %.3e" % (n, ed, er))
+        ed, er, ee = _rel(gd, rd), _rel(gr, rr), _rel_each(gr, rr)
+        _say("  n=%d W_delta %.3e W_R %.3e (per tuple %.3e)" % (n, ed, er, ee))
         tol = 1e-12 if path == "fp64" else 1e-5
-        assert ed <= tol and er <= tol
+        assert ed <= tol and er <= tol and ee <= tol
         assert abs(out["alpha"].item() - o["alpha"]) <= 1e-13 * o["alpha"]
         b = out["bufs"]
         assert b["nout"].cpu().numpy().tolist() == list(o["out"]) == [0, 0]
@@ -97,6 +103,33 @@ def test_cap512_full_size_sampled(cap, path):
             direct = oc.direct_shell_sum(o["N"], w.radii[m] / w.cell, cells)
             got = maps_N[m][cells[:, 0], cells[:, 1], cells[:, 2]].cpu().numpy()
             assert np.abs(got - direct).max() <= 1e-11 * max(1.0, np.abs(direct).max())
+    ctx.close()
+    del ks
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("prec", ["split_f16", "split_bf16"])
+def test_cap512_full_size_n4(cap, prec):
+    """Order 4 (4,960 tuples) on the survey cap: maps of the carrying lines in the
+    workspace, then the matrix-core summation with split operands; the tuples
+    among the two sampled shells against the oracle."""
+    ck, w, data, rand, o = cap
+    dev = "cuda:0"
+    grid = ck.Grid(w.dims, w.origin, w.cell)
+    ctx = ck.Context(0)
+    _say("full size n=4", prec)
+    ks, _ = ctx.make_shell_kernels(grid, w.radii, torch.float32)
+    dpos, rpos = torch.from_numpy(data.pos).to(dev), torch.from_numpy(rand.pos).to(dev)
+    dw, rw = torch.from_numpy(data.w).to(dev), torch.from_numpy(rand.w).to(dev)
+    ns = len(w.radii)
+    out = ck.npcf(ctx, grid, dpos, rpos, ks, 4, dw, rw, precision=prec, dtype=torch.float32)
+    assert out["W_delta"].numel() == 4960
+    tl, rd, rr = o["ref"][4]
+    gd = _pick(out["W_delta"].cpu().numpy(), ns, 4, tl)
+    gr = _pick(out["W_rand_raw"].cpu().numpy(), ns, 4, tl)
+    ed, er, ee = _rel(gd, rd), _rel(gr, rr), _rel_each(gr, rr)
+    _say("  n=4 W_delta %.3e W_R %.3e (per tuple %.3e)" % (ed, er, ee))
+    assert ed <= 1e-5 and er <= 1e-5 and ee <= 1e-5
     ctx.close()
     del ks
     torch.cuda.empty_cache()

@@ -53,6 +53,46 @@ def _gpu(a, dtype):
     return torch.from_numpy(np.ascontiguousarray(a)).to(DEV, dtype)
 
 
+@pytest.mark.parametrize("dims", [(512, 32, 64), (512, 64, 96)])
+@pytest.mark.parametrize("dt,tol", [("f64", 1e-12), ("f32", 3e-6)])
+def test_xmul_every_resident_form_512_lines(ck, ctx, dims, dt, tol):
+    """x lines of 512 cells (the survey-cap length of the first inverse pass):
+    every form of that pass against the oracle, with every row stored (maps)
+    and with only the x-slabs that carry field stored (the workspace summation
+    path, fields zero on 70 % of the x-slabs)."""
+    rng = np.random.default_rng(137)
+    A = rng.normal(size=dims)
+    B = rng.poisson(3.0, size=dims).astype(np.float64)
+    radii = [1.0, 3.0, 6.5, 11.0]
+    Af = A.astype(np.float32).astype(np.float64) if dt == "f32" else A
+    ref_a, ref_b = oc.convolve_shells(Af, radii), oc.convolve_shells(B, radii)
+    As, Bs = Af.copy(), B.copy()
+    As[:150] = 0.0
+    As[300:] = 0.0
+    Bs[:150] = 0.0
+    Bs[300:] = 0.0
+    ms_a, ms_b = oc.convolve_shells(As, radii), oc.convolve_shells(Bs, radii)
+    prec = "f64" if dt == "f64" else "split_bf16"
+    wref_a, wref_b = oc.contract(As, ms_a, 3), oc.contract(Bs, ms_b, 3)
+    grid = ck.Grid(dims, (0, 0, 0), 1.0)
+    ks, _ = ctx.make_shell_kernels(grid, radii, TDT[dt])
+    At, Bt = _gpu(A, TDT[dt]), _gpu(B, TDT[dt])
+    Ast, Bst = _gpu(As, TDT[dt]), _gpu(Bs, TDT[dt])
+    for xr in (0, 1, 2, 3):
+        _say("512-cell x lines", dims, dt, "x_resident", xr)
+        ctx.set_tune(x_resident=xr)
+        ma, mb = ctx.convolve_shells(grid, At, Bt, ks)
+        ma, mb = ma.cpu().numpy(), mb.cpu().numpy()
+        for m in range(len(radii)):
+            ea, eb = relerr(ma[m], ref_a[m]), relerr(mb[m], ref_b[m])
+            assert ea <= tol and eb <= tol, (xr, m, ea, eb)
+        Wa, Wb = ctx.convolve_contract(grid, Ast, Bst, ks, 3, prec)
+        wtol = 1e-12 if dt == "f64" else 1e-5
+        ea, eb = relerr(Wa.cpu().numpy(), wref_a), relerr(Wb.cpu().numpy(), wref_b)
+        _say("  sums: a %.2e b %.2e" % (ea, eb))
+        assert ea <= wtol and eb <= wtol, (xr, ea, eb)
+
+
 @pytest.mark.parametrize("dims", [(64, 96, 128), (96, 64, 32), (32, 1024, 64), (1024, 32, 32), (32, 32, 512)])
 @pytest.mark.parametrize("dt,tol", [("f64", 1e-12), ("f32", 3e-6)])
 def test_convolve_every_tile_setting(ck, ctx, dims, dt, tol):

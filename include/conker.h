@@ -433,8 +433,11 @@ int conker_batch_launch(conker_ctx *ctx);
  *                   Default: 2 where the pass stores only the slabs
  *                   carrying field, else 3.
  *   mm_kernel       matrix-core summation: 1 one output tile per wave,
- *                   2 operand sharing across a workgroup.  Default: 2 above
- *                   four 32 x 32 output tiles, else 1.
+ *                   2 operand sharing across a workgroup, 3 (n = 3 with
+ *                   split operands and at most 64 radii) every output tile
+ *                   in each wave from one load of the maps.  Default: 3
+ *                   where it applies, else 2 above four 32 x 32 output
+ *                   tiles, else 1.
  *   radius_batch    radii (or radius pairs) per inverse batch, 1..64.
  *                   Default: as many as half of the free device memory holds.
  *   axis_order      map-free summations (conker_convolve_contract*,

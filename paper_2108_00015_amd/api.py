@@ -417,7 +417,7 @@ class Context:
         """Launch setting for later calls: x_tile, y_tile (1 narrow, 2 wide),
         x_resident (1 streamed, 2 resident with two LDS exchange buffers where
         they fit, 3 resident with one), mm_kernel (1 per-wave tiles,
-        2 operand sharing), radius_batch, axis_order (1 as given, 2..6 the
+        2 operand sharing, 3 n = 3 every tile per wave), radius_batch, axis_order (1 as given, 2..6 the
         other permutations of a cubic grid, see conker.h); 0 or omitted = default."""
         bad = set(fields) - set(TUNE_FIELDS)
         if bad:

@@ -86,7 +86,7 @@ int run_all(conker_ctx *c) {
 
 bool tune_ok(const conker_tune &t) {
     auto in = [](int v, int lo, int hi) { return v >= lo && v <= hi; };
-    return in(t.x_tile, 0, 2) && in(t.y_tile, 0, 2) && in(t.x_resident, 0, 3) && in(t.mm_kernel, 0, 2) &&
+    return in(t.x_tile, 0, 2) && in(t.y_tile, 0, 2) && in(t.x_resident, 0, 3) && in(t.mm_kernel, 0, 3) &&
            in(t.radius_batch, 0, 64) && in(t.axis_order, 0, 6);
 }
 
@@ -135,7 +135,9 @@ int tune_job(conker_ctx *c, const conker_job &j, int reps, hipEvent_t e0, hipEve
     std::vector<Knob> knobs = {{&conker_tune::y_tile, {1, 2}},
                                {&conker_tune::x_tile, {1, 2}},
                                {&conker_tune::x_resident, {1, 2, 3}}};
-    if (!fused && j.n >= 3 && j.prec != CONKER_MM_F64) knobs.push_back({&conker_tune::mm_kernel, {1, 2}});
+    if (!fused && j.n >= 3 && j.prec != CONKER_MM_F64)
+        knobs.push_back({&conker_tune::mm_kernel,
+                         (j.n == 3 && j.prec != CONKER_MM_F32) ? std::vector<int>{1, 2, 3} : std::vector<int>{1, 2}});
     if (nomaps && j.grid.dims[0] == j.grid.dims[1] && j.grid.dims[1] == j.grid.dims[2])
         knobs.push_back({&conker_tune::axis_order, {1}});   // the given order against the chosen one
     if (!fused && slots >= 4) {
@@ -249,7 +251,7 @@ extern "C" int conker_set_tune(conker_ctx *c, const conker_tune *t) {
     v.ms = 0.f;
     if (!tune_ok(v))
         return fail(c, CONKER_EINVAL,
-                    "launch setting out of range (tiles, resident, kernel 0..2; radius batch 0..64; axis order 0..6)");
+                    "launch setting out of range (tiles 0..2, resident 0..3, kernel 0..3; radius batch 0..64; axis order 0..6)");
     c->user_tune = v;
     c->tune = v;
     return CONKER_OK;

@@ -1045,6 +1045,147 @@ int contract_dot(conker_ctx *c, const T *F, const T *maps, size_t nc, int ns, co
     return CONKER_OK;
 }
 
+// ---------------------------------------------------------------------------
+// n = 3 with at most 64 radii, split operands: every output tile of the
+// product from one load of each map value.  For a 32x32x16 matrix
+// instruction lane l holds A[row l % 32][8 cells] and B[8 cells][column l % 32]:
+// with row items F C_a and column items C_b these are the same map values, so
+// one wave loads C_r and C_{32 + r} (r = l % 32) and F for 16 cells and feeds
+// the tiles (0,0) = (F C_r, C_r), (0,1) = (F C_r, C_{32+r}), (1,1) =
+// (F C_{32+r}, C_{32+r}) (only the first for ns <= 32), the order in which
+// make_plan numbers them.  The loads of the next 16 cells are issued before
+// the current ones are used, so a wave keeps one step of loads in flight.
+// Cells: each wave takes 16 of every 64-cell block of its workgroup's share.
+// ---------------------------------------------------------------------------
+template <int RT, int PREC>
+__global__ __launch_bounds__(NT) void k_mm3(const float *__restrict__ F, const float *__restrict__ maps, size_t nc,
+                                            const int *__restrict__ list, const int *__restrict__ count, int ns,
+                                            double *__restrict__ partial, const unsigned *__restrict__ maxabs) {
+    constexpr bool F16 = PREC == CONKER_MM_SPLIT_F16;
+    constexpr int NTL = RT == 1 ? 1 : 3, TS = 32, CPI = 16, FLUSH = 8;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int r = lane & 31, h = lane >> 5;
+    const int m0 = r < ns ? r : -1;
+    const int m1 = (RT == 2 && 32 + r < ns) ? 32 + r : -1;
+    const float *p0 = maps + (size_t)(m0 < 0 ? 0 : m0) * nc;
+    const float *p1 = maps + (size_t)(m1 < 0 ? 0 : m1) * nc;
+    // split-f16 scale exponents: row items F C_m (with F), column items C_m
+    int eA0 = 0, eB0 = 0, eA1 = 0, eB1 = 0;
+    if constexpr (F16) {
+        eA0 = items_exp(maxabs, ns, m0 < 0 ? -2 : m0, -1, true);
+        eB0 = items_exp(maxabs, ns, m0 < 0 ? -2 : m0, -1, false);
+        eA1 = items_exp(maxabs, ns, m1 < 0 ? -2 : m1, -1, true);
+        eB1 = items_exp(maxabs, ns, m1 < 0 ? -2 : m1, -1, false);
+    }
+    floatx16 acc[NTL];
+    double accd[NTL][16];
+#pragma unroll
+    for (int s = 0; s < NTL; ++s) {
+        acc[s] = floatx16{0};
+#pragma unroll
+        for (int v = 0; v < 16; ++v) accd[s][v] = 0.0;
+    }
+    auto mma = [&](floatx16 &a, const float (&av)[8], const float (&bv)[8], int ea, int eb) {
+        if constexpr (F16) {
+            float sa[8], sb[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                sa[e] = ldexpf(av[e], ea);
+                sb[e] = ldexpf(bv[e], eb);
+            }
+            f16x8 ah, al, bh, bl;
+            split2h(sa, ah, al);
+            split2h(sb, bh, bl);
+            a = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, bh, a, 0, 0, 0);
+            a = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bl, a, 0, 0, 0);
+            a = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bh, a, 0, 0, 0);
+        } else {
+            bf16x8 ah, am, al, bh, bm, bl;
+            split3(av, ah, am, al);
+            split3(bv, bh, bm, bl);
+            a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, a, 0, 0, 0);
+            a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bm, a, 0, 0, 0);
+            a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, a, 0, 0, 0);
+            a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bh, a, 0, 0, 0);
+            a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bm, a, 0, 0, 0);
+            a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, a, 0, 0, 0);
+        }
+    };
+    // this wave's 8 cells of a block: x = first(k) + 16 w + 8 h; the last
+    // block of the grid may be partial (nc % 16 == 0, so a wave's 16 cells are
+    // either all in the grid or all beyond it)
+    // Lanes without a map (rows beyond ns) and cells beyond the grid read a
+    // valid address (cell 0) and are zeroed by a select: no branches.
+    const bool h0 = m0 >= 0, h1 = m1 >= 0;
+    float f[8], c0[8], c1[8];
+    const Blocks bk = my_blocks(list, count, nc);
+    const size_t off = (size_t)w * CPI + 8 * h;
+    auto load = [&](int k) {
+        const size_t xw = bk.first(k) + (size_t)w * CPI;   // the wave's 16 cells: all in or all out
+        const bool in = xw < nc;
+        const size_t x = in ? xw + 8 * h : 0;
+        ld<float, 8>(F + x, f);
+        ld<float, 8>(p0 + x, c0);
+        if constexpr (RT == 2) ld<float, 8>(p1 + x, c1);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            f[e] = in ? f[e] : 0.f;
+            c0[e] = h0 ? c0[e] : 0.f;
+            c1[e] = (RT == 2 && h1) ? c1[e] : 0.f;
+        }
+    };
+    (void)off;
+    if (bk.k0 < bk.k1) load(bk.k0);
+    int cnt = 0;
+    for (int k = bk.k0; k < bk.k1; ++k) {
+        float fc[8], c0c[8], c1c[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            fc[e] = f[e];
+            c0c[e] = c0[e];
+            c1c[e] = c1[e];
+        }
+        load(k + 1 < bk.k1 ? k + 1 : k);   // the next block (this one again at the end: no branch)
+        float a0[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) a0[e] = fc[e] * c0c[e];
+        mma(acc[0], a0, c0c, eA0, eB0);
+        if constexpr (RT == 2) {
+            float a1[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) a1[e] = fc[e] * c1c[e];
+            mma(acc[1], a0, c1c, eA0, eB1);
+            mma(acc[2], a1, c1c, eA1, eB1);
+        }
+        if (++cnt == FLUSH) {
+            cnt = 0;
+#pragma unroll
+            for (int s = 0; s < NTL; ++s) {
+#pragma unroll
+                for (int v = 0; v < 16; ++v) accd[s][v] += (double)acc[s][v];
+                acc[s] = floatx16{0};
+            }
+        }
+    }
+    __shared__ double lds[WAVES * 16 * 64];
+    const int G = gridDim.x;
+#pragma unroll
+    for (int s = 0; s < NTL; ++s) {
+        double a16[16];
+#pragma unroll
+        for (int v = 0; v < 16; ++v) a16[v] = accd[s][v] + (double)acc[s][v];
+        if constexpr (F16) {   // element (i, j = lane % 32): row exponent of lane i, column exponent ours
+            const int er = s == 2 ? eA1 : eA0, ec = s == 0 ? eB0 : eB1;
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int i = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                a16[v] = ldexp(a16[v], -(__shfl(er, i) + ec));
+            }
+        }
+        wave_combine_store<32>(a16, lds, partial + ((size_t)s * G + blockIdx.x) * (TS * TS));
+    }
+}
+
 template <int NBW>
 int launch_mm(conker_ctx *c, conker_mmprec prec, dim3 grid, const void *F, const void *maps, size_t nc,
               const int *list, const int *count, const Items *tab, int n_tiles, double *part, int ns,
@@ -1101,10 +1242,11 @@ extern "C" int conker_contract_npt(conker_ctx *c, const conker_grid *g, conker_d
     // tiles, where k_mm2 would leave most waves of a workgroup idle.
     static const int mm_env = [] {
         const char *e = std::getenv("CONKER_MM_KERNEL");
-        return e ? std::atoi(e) : 0;   // 0 auto, 1 per-wave tiles, 2 operand sharing
+        return e ? std::atoi(e) : 0;   // 0 auto, 1 per-wave tiles, 2 operand sharing, 3 n = 3 all tiles per wave
     }();
     const int mm_kernel = c->tune.mm_kernel ? c->tune.mm_kernel : mm_env;
-    const bool use_v2 = prec != CONKER_MM_F64 && (mm_kernel == 2 || (mm_kernel == 0 && pl.n_tiles > 4));
+    const bool use_v2 = prec != CONKER_MM_F64 && (mm_kernel == 2 || (mm_kernel == 0 && pl.n_tiles > 4)) &&
+                        !(mm_kernel == 3 && n == 3);
     unsigned *maxabs = nullptr;
     if (prec == CONKER_MM_SPLIT_F16) {   // largest |value| of every map and of F, after the workspace below
         CK_OK(ws_reserve(c, c->scales, 256 * sizeof(unsigned)));
@@ -1170,6 +1312,47 @@ extern "C" int conker_contract_npt(conker_ctx *c, const conker_grid *g, conker_d
         CK_LAUNCH(c);
         hipLaunchKernelGGL(k_tile_reduce2, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, c->stream, slices,
                            p2.n_tiles, te, full);
+        CK_LAUNCH(c);
+        hipLaunchKernelGGL(k_gather, dim3((unsigned)((pl.count + 255) / 256)), dim3(256), 0, c->stream,
+                           (const double *)full, (const int *)pl.where->p, pl.count, W);
+        CK_LAUNCH(c);
+        return CONKER_OK;
+    }
+    // n = 3, at most 64 radii, split operands: every tile from one load of the maps
+    const bool use_mm3 = n == 3 && ns <= 64 && (prec == CONKER_MM_SPLIT_BF16 || prec == CONKER_MM_SPLIT_F16) &&
+                         (mm_kernel == 3 || mm_kernel == 0);
+    if (use_mm3) {
+        const int RT = ns <= 32 ? 1 : 2;
+        if (pl.n_tiles != (RT == 1 ? 1 : 3)) return fail(c, CONKER_EINVAL, "unexpected tile plan");
+        const size_t G = std::max<size_t>(1, std::min<size_t>(nc / 1024, (size_t)8 * cu_count(c)));
+        const int te = TS * TS;
+        CK_OK(ws_reserve(c, c->partial, (size_t)pl.n_tiles * G * te * sizeof(double)));
+        CK_OK(ws_reserve(c, c->full, (size_t)pl.n_tiles * te * (RED_S + 1) * sizeof(double)));
+        double *part = (double *)c->partial.p;
+        {
+            ProfScope ps(c, PK_CONTRACT_MM);
+            auto go = [&](auto kern) {
+                hipLaunchKernelGGL(kern, dim3((unsigned)G), dim3(NT), 0, c->stream, (const float *)F,
+                                   (const float *)maps, nc, blist, bcount, ns, part, (const unsigned *)maxabs);
+            };
+            if (RT == 1) {
+                if (prec == CONKER_MM_SPLIT_F16) go(k_mm3<1, CONKER_MM_SPLIT_F16>);
+                else go(k_mm3<1, CONKER_MM_SPLIT_BF16>);
+            } else {
+                if (prec == CONKER_MM_SPLIT_F16) go(k_mm3<2, CONKER_MM_SPLIT_F16>);
+                else go(k_mm3<2, CONKER_MM_SPLIT_BF16>);
+            }
+            CK_LAUNCH(c);
+        }
+        ProfScope ps(c, PK_CONTRACT_REDUCE);
+        const size_t tot = (size_t)pl.n_tiles * te;
+        double *full = (double *)c->full.p;
+        double *slices = full + tot;
+        hipLaunchKernelGGL(k_tile_reduce1, dim3((unsigned)((tot * RED_S + 255) / 256)), dim3(256), 0, c->stream,
+                           part, pl.n_tiles, (int)G, te, slices);
+        CK_LAUNCH(c);
+        hipLaunchKernelGGL(k_tile_reduce2, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, c->stream, slices,
+                           pl.n_tiles, te, full);
         CK_LAUNCH(c);
         hipLaunchKernelGGL(k_gather, dim3((unsigned)((pl.count + 255) / 256)), dim3(256), 0, c->stream,
                            (const double *)full, (const int *)pl.where->p, pl.count, W);

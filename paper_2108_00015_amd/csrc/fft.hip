@@ -796,18 +796,23 @@ struct OpExtract {
 // coalesced reads, prefetched into registers while the previous radius is
 // transformed.
 // ---------------------------------------------------------------------------
-template <typename T, int L, int TC, int PER0>
+template <typename T, int L, int TC, int PER0, bool PAIR = false>
 struct OpResident {
     static constexpr bool STAGED = false;
     using C = cplx<T>;
     const C (*sreg)[8];   // registers: this thread's first-stage inputs [PER0][8]
-    const T *kt;          // LDS: kernel values [TC][L/2 + 1]
+    const T *kt;          // LDS: kernel values [TC][L/2 + 1]; with PAIR a second such block (radius b)
     C *out;               // global: output tile base
     unsigned si;
     const unsigned char *xf;   // LDS: x-slab carries field (row written), or NULL: every row
     __device__ C load_r(int q, int r, int i, int c) const {
         const C s = sreg[q][r];
-        const T k = kt[c * (L / 2 + 1) + (i <= L - i ? i : L - i)];
+        const int e = c * (L / 2 + 1) + (i <= L - i ? i : L - i);
+        const T k = kt[e];
+        if constexpr (PAIR) {   // s (K_a + i K_b)
+            const T kb = kt[TC * (L / 2 + 1) + e];
+            return C{s.x * k - s.y * kb, s.y * k + s.x * kb};
+        }
         return C{s.x * k, s.y * k};
     }
     __device__ bool keeps() const { return xf != nullptr; }
@@ -815,12 +820,12 @@ struct OpResident {
     __device__ void store(int i, int c, C v) const { out[(unsigned)i * si + (unsigned)c] = v; }   // rows with a flag
 };
 
-template <typename T, int L>
+template <typename T, int L, bool PAIR = false>
 constexpr bool resident_fits() {
     using SH = Shape<T, L, TM_R>;
     return Plan<L>::r[0] == 8 &&
            (size_t)SH::LDS * sizeof(cplx<T>) + (size_t)L * sizeof(cplx<T>) +
-                   (size_t)SH::TC * (L / 2 + 1) * sizeof(T) + (size_t)L <=
+                   (PAIR ? 2 : 1) * (size_t)SH::TC * (L / 2 + 1) * sizeof(T) + (size_t)L <=
                160 * 1024;
 }
 
@@ -836,19 +841,24 @@ constexpr bool pingpong_fits() {
                160 * 1024;
 }
 
-template <typename T, int L, bool PPW>
+// PAIR (one real field, radii paired): slot m is multiplied by K_{2j} + i K_{2j+1}
+// with j = m0 + m (K_{2j} alone when 2j + 1 = pair_ns), so one transform gives
+// the maps of two radii; the two kernel rows are staged side by side.
+template <typename T, int L, bool PPW, bool PAIR>
 __global__ __launch_bounds__((Shape<T, L, TM_R>::NT), (Shape<T, L, TM_R>::MINW)) void k_xmul_resident(
     const cplx<T> *__restrict__ spec, const T *__restrict__ kspec, cplx<T> *__restrict__ tspec,
-    const cplx<T> *__restrict__ twg, Dims d, size_t nc, size_t kel, int m0, int nb, const int *__restrict__ xcount) {
+    const cplx<T> *__restrict__ twg, Dims d, size_t nc, size_t kel, int m0, int nb, const int *__restrict__ xcount,
+    int pair_ns) {
     using C = cplx<T>;
     using SH = Shape<T, L, TM_R>;
     constexpr int TC = SH::TC, NT = SH::NT, NXH = L / 2 + 1;
-    constexpr int KPT = (TC * NXH + NT - 1) / NT;   // kernel values staged per thread
-    constexpr bool PP = PPW && pingpong_fits<T, L>();
+    constexpr int KR = PAIR ? 2 : 1;                     // kernel rows per slot
+    constexpr int KPT = (KR * TC * NXH + NT - 1) / NT;   // kernel values staged per thread
+    constexpr bool PP = PPW && !PAIR && pingpong_fits<T, L>();
     constexpr int PADR = PP ? 1 : SH::PAD, LDSN = L * (TC + PADR);
     __shared__ C lds[PP ? 2 * LDSN : LDSN];
     __shared__ C tw[L];
-    __shared__ T kt[TC * NXH];
+    __shared__ T kt[KR * TC * NXH];
     __shared__ unsigned char xf[L];   // x-slabs carrying field (when xcount is given)
     // Tiles (ky, kz-block) and (ny - ky, kz-block) read the same kernel values.
     // Workgroups are dispatched round-robin over the 8 XCDs; ids w and w + 8
@@ -886,13 +896,17 @@ __global__ __launch_bounds__((Shape<T, L, TM_R>::NT), (Shape<T, L, TM_R>::MINW))
     const int oy = fold(g.p0, d.ny);
     const int nzh = d.nz / 2 + 1;
     auto kload = [&](int m, T (&kv)[KPT]) {
-        const T *kb = kspec + (size_t)(m0 + m) * kel + (size_t)oy * nzh * NXH;
+        const int ra = PAIR ? 2 * (m0 + m) : m0 + m;
 #pragma unroll
         for (int q = 0; q < KPT; ++q) {
             const int e = threadIdx.x + q * NT;
-            if (e < TC * NXH) {
-                const int c = e / NXH, ox = e - (e / NXH) * NXH;
-                kv[q] = kb[(size_t)fold(g.p1 + c, d.nz) * NXH + ox];
+            if (e < KR * TC * NXH) {
+                const int h = e / (TC * NXH), el = e - h * (TC * NXH);   // h = 1: radius b of the pair
+                const int c = el / NXH, ox = el - (el / NXH) * NXH;
+                const int rr = ra + h;
+                kv[q] = (!PAIR || rr < pair_ns)
+                            ? kspec[(size_t)rr * kel + ((size_t)oy * nzh + fold(g.p1 + c, d.nz)) * NXH + ox]
+                            : (T)0;
             }
         }
     };
@@ -900,7 +914,7 @@ __global__ __launch_bounds__((Shape<T, L, TM_R>::NT), (Shape<T, L, TM_R>::MINW))
 #pragma unroll
         for (int q = 0; q < KPT; ++q) {
             const int e = threadIdx.x + q * NT;
-            if (e < TC * NXH) kt[e] = kv[q];
+            if (e < KR * TC * NXH) kt[e] = kv[q];
         }
     };
     T kv[KPT];
@@ -918,8 +932,8 @@ __global__ __launch_bounds__((Shape<T, L, TM_R>::NT), (Shape<T, L, TM_R>::MINW))
         __syncthreads();
         C *const la = lds, *const lb = lds + LDSN;
         for (int m = 0; m < nb; ++m) {
-            OpResident<T, L, TC, PER0> op{sreg, kt, tspec + (size_t)m * nc + g.base, (unsigned)g.si,
-                                          xcount ? xf : nullptr};
+            OpResident<T, L, TC, PER0, PAIR> op{sreg, kt, tspec + (size_t)m * nc + g.base, (unsigned)g.si,
+                                                xcount ? xf : nullptr};
             fft_stage<T, L, TM_R, +1, 0, false, false, PADR>(la, la, tw, op);
             __syncthreads();
             fft_stage<T, L, TM_R, +1, 1, false, false, PADR>(la, lb, tw, op);
@@ -935,8 +949,8 @@ __global__ __launch_bounds__((Shape<T, L, TM_R>::NT), (Shape<T, L, TM_R>::MINW))
             kstage(kv);
             __syncthreads();
             if (m + 1 < nb) kload(m + 1, kv);
-            OpResident<T, L, TC, PER0> op{sreg, kt, tspec + (size_t)m * nc + g.base, (unsigned)g.si,
-                                          xcount ? xf : nullptr};
+            OpResident<T, L, TC, PER0, PAIR> op{sreg, kt, tspec + (size_t)m * nc + g.base, (unsigned)g.si,
+                                                xcount ? xf : nullptr};
             fft_line_tile<T, L, TM_R, +1, false>(lds, tw, op);
             __syncthreads();
         }
@@ -1228,22 +1242,26 @@ int inverse_batch_t(conker_ctx *ctx, const conker_grid *g, const void *spec, con
     const bool one_buffer = ctx->tune.x_resident == 3 || (ctx->tune.x_resident == 0 && !xcount);
     static const bool persist_y = env_flag("CONKER_Y_PERSIST", 1) != 0;
     bool done = false;
-    if (resident && !pair) {
+    if (resident) {
         auto go = [&](auto Lc) -> int {
             constexpr int LL = decltype(Lc)::value;
-            if constexpr (resident_fits<T, LL>()) {
+            auto run = [&](auto kern) {
                 using SH = Shape<T, LL, TM_R>;
-                if (d.nz % SH::TC) return CONKER_OK;
                 ProfScope ps(ctx, PK_FFT_INV_X_MUL);
                 const unsigned nt = (unsigned)((long)d.ny * d.nz / SH::TC);
-                if (one_buffer)
-                    hipLaunchKernelGGL((k_xmul_resident<T, LL, false>), dim3(nt), dim3(SH::NT), 0, ctx->stream,
-                                       (const C *)spec, (const T *)kspec, (C *)tspec, (const C *)twx, d, nc, kel,
-                                       m0, nb, xcount);
-                else
-                    hipLaunchKernelGGL((k_xmul_resident<T, LL, true>), dim3(nt), dim3(SH::NT), 0, ctx->stream,
-                                       (const C *)spec, (const T *)kspec, (C *)tspec, (const C *)twx, d, nc, kel,
-                                       m0, nb, xcount);
+                hipLaunchKernelGGL(kern, dim3(nt), dim3(SH::NT), 0, ctx->stream, (const C *)spec, (const T *)kspec,
+                                   (C *)tspec, (const C *)twx, d, nc, kel, m0, nb, xcount, pair_ns);
+            };
+            if (d.nz % Shape<T, LL, TM_R>::TC) return CONKER_OK;
+            if (pair) {   // one exchange buffer (the second kernel row takes the room of the other)
+                if constexpr (resident_fits<T, LL, true>()) {
+                    run(k_xmul_resident<T, LL, false, true>);
+                    CK_LAUNCH(ctx);
+                    done = true;
+                }
+            } else if constexpr (resident_fits<T, LL>()) {
+                if (one_buffer) run(k_xmul_resident<T, LL, false, false>);
+                else run(k_xmul_resident<T, LL, true, false>);
                 CK_LAUNCH(ctx);
                 done = true;
             }

@@ -151,6 +151,35 @@ def test_summation_kernel_setting(ck, ctx, mm, prec, n):
     assert e <= 1e-5
 
 
+@pytest.mark.parametrize("ns", [7, 32, 33, 40, 64])
+@pytest.mark.parametrize("prec", ["split_bf16", "split_f16"])
+@pytest.mark.parametrize("mm", [0, 1, 3])
+def test_summation_n3_every_tile_per_wave(ck, ctx, ns, prec, mm):
+    """n = 3 from stored maps with every output tile in each wave (setting 3,
+    the default for the split forms up to 64 radii) against the oracle and the
+    per-wave tile kernel: one row tile (7, 32 radii) and two (33, 40, 64), on
+    a field zero on a third of the 64-cell blocks, with a partial last block
+    (1,680 cells) and maps of mixed magnitudes."""
+    dims = (5, 7, 48)
+    rng = np.random.default_rng(150 + ns)
+    F = rng.normal(size=dims)
+    Ff = F.reshape(-1)
+    for b in range(0, Ff.size, 64):
+        if rng.random() < 0.33:
+            Ff[b:b + 64] = 0.0
+    F = F.astype(np.float32).astype(np.float64)
+    maps = (rng.normal(size=(ns,) + dims) * np.exp(rng.normal(size=(ns, 1, 1, 1)) * 3.0))
+    maps = maps.astype(np.float32).astype(np.float64)
+    ref = oc.contract(F, maps, 3)
+    grid = ck.Grid(dims, (0, 0, 0), 1.0)
+    ctx.set_tune(mm_kernel=mm)
+    W = ctx.contract_npt(grid, _gpu(F, torch.float32), _gpu(maps, torch.float32), 3, prec)
+    e = relerr(W.cpu().numpy(), ref)
+    _say("n=3 summation", ns, prec, "kernel", mm, "%.3e" % e)
+    assert W.numel() == ns * (ns + 1) // 2
+    assert e <= 1e-5
+
+
 @pytest.mark.parametrize("yt", [1, 2])
 def test_fused_and_diag_with_line_masks(ck, ctx, yt):
     """Survey-shaped support (the y pass skips empty slabs, writes carrying lines)."""
@@ -182,7 +211,7 @@ def test_fused_and_diag_with_line_masks(ck, ctx, yt):
 
 
 def test_set_tune_rejects_out_of_range(ck, ctx):
-    for bad in (dict(x_tile=3), dict(y_tile=-1), dict(x_resident=5), dict(mm_kernel=3), dict(radius_batch=65)):
+    for bad in (dict(x_tile=3), dict(y_tile=-1), dict(x_resident=5), dict(mm_kernel=4), dict(radius_batch=65)):
         with pytest.raises(ck.ConkerError):
             ctx.set_tune(**bad)
     with pytest.raises(ValueError):
@@ -236,7 +265,7 @@ def test_batch_autotune_then_graph(ck, ctx):
     assert len(chosen) == len(jobs)
     for t in chosen:
         assert t["x_tile"] in (0, 1, 2) and t["y_tile"] in (0, 1, 2) and t["x_resident"] in (0, 1, 2, 3)
-        assert t["mm_kernel"] in (0, 1, 2) and 0 <= t["radius_batch"] <= 16
+        assert t["mm_kernel"] in (0, 1, 2, 3) and 0 <= t["radius_batch"] <= 16
         assert 0.0 < t["ms"] < 1e4
     strip = [{k: v for k, v in t.items() if k != "ms"} for t in chosen]
     assert strip[0] == strip[2] and chosen[0]["ms"] == chosen[2]["ms"]     # same shape, one tuning

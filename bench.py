@@ -263,11 +263,81 @@ def run_path(ck, torch, ctx, grid, w, dpos, dw, rpos, rw, n, dtype, prec, steps,
 MOCKS_NAME = "mocks64_periodic_grid96-256_r16"
 
 
+def mock_stage_bytes(kind, sizes, ns, npts, nb=8):
+    """Algorithmic HBM bytes of one kind of launch over a whole mock batch run as
+    size classes (float32 grids, every line carries field: periodic boxes)."""
+    tot = 0.0
+    for (g, _), n in zip(sizes, npts):
+        nc = g ** 3
+        kel = (g // 2 + 1) ** 3
+        if kind == "contract_mm":     # field and maps of both fields, every block
+            b = 2 * (ns + 1) * nc * 4
+        elif kind == "scatter":       # zeroing both grids, positions in, one grid RMW per point
+            b = 2 * nc * 4 + n * (12 + 8)
+        elif kind == "contract_reduce":
+            b = None
+        else:
+            b = kernel_bytes(kind, 1, nc, ns, kel, n, 0, False, 4, nb)
+        if b is None:
+            return None
+        tot += b
+    return tot
+
+
+def mocks_cpu_baseline(sizes, cats, radii, n, k=6):
+    """The FP64 oracle on one mock of each grid size (mapping, k shells,
+    summation over the tuples of those shells), extrapolated to every shell and
+    tuple and to the batch's count of mocks of that size."""
+    from oracle import conker as oc
+    ns = len(radii)
+    total, parts = 0.0, {}
+    t_all = time.perf_counter()
+    for g in sorted({g for g, _ in sizes}):
+        d, r = cats[next(i for i, (gg, _) in enumerate(sizes) if gg == g)]
+        dims = (g, g, g)
+        t0 = time.perf_counter()
+        D, wd, _ = oc.histogram(d.pos, d.w, (0.0, 0.0, 0.0), 5.0, dims)
+        R, wr, _ = oc.histogram(r.pos, r.w, (0.0, 0.0, 0.0), 5.0, dims)
+        N, _ = oc.density_deviation(D, R, wd, wr)
+        t1 = time.perf_counter()
+        rc = [s / 5.0 for s in radii[:k]]
+        mN, mR = oc.convolve_shells(N, rc), oc.convolve_shells(R, rc)
+        t2 = time.perf_counter()
+        oc.contract(N, mN, n)
+        oc.contract(R, mR, n)
+        t3 = time.perf_counter()
+        one = (t1 - t0) + (ns / k) * (t2 - t1) + (oc.num_tuples(ns, n) / oc.num_tuples(k, n)) * (t3 - t2)
+        count = sum(1 for gg, _ in sizes if gg == g)
+        parts["%d^3" % g] = round(one, 3)
+        total += count * one
+    return dict(value=2 * ns * len(sizes) / total, unit="shell-convs/s", cores=len(os.sched_getaffinity(0)),
+                kind="oracle",
+                sample=("one mock of each grid size: full mapping, convolution of both fields with %d of %d "
+                        "shells, summation (n=%d) over the %d tuples of those shells; extrapolated to %d shells, "
+                        "%d tuples and the batch's %d mocks" % (k, ns, n, oc.num_tuples(k, n), ns,
+                                                                 oc.num_tuples(ns, n), len(sizes))),
+                sample_seconds=round(time.perf_counter() - t_all, 2),
+                extrapolated_step_seconds=round(total, 2), mock_seconds=parts)
+
+
+def time_batch(ctx, stream, torch, steps):
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        e0.record(stream)
+        for _ in range(steps):
+            ctx.batch_launch()
+        e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
 def bench_mocks(args):
     """A batch of 64 independent periodic mocks (grids of 96..256 cells a side,
     50k..400k Neyman-Scott points + 10x uniform randoms each, 16 shells 10..85,
-    n = 3, mixed precision), planned once and replayed as one HIP graph.  One
-    step = the whole batch; value = shell convolutions per second (2 x 16 per mock)."""
+    n = 3, mixed precision), planned once and replayed as one HIP graph.  Mocks
+    on one grid size run as size classes: every stage one launch for a chunk
+    of mocks.  One step = the whole batch; value = shell convolutions per
+    second (2 x 16 per mock).  The float64 batch (job by job) is timed beside it."""
     import torch
     import paper_2108_00015_amd as ck
     import synth
@@ -277,55 +347,107 @@ def bench_mocks(args):
     npts = sum(len(d) + len(r) for d, r in cats)
     log("64 mocks: %d points in %.1f s" % (npts, time.perf_counter() - t))
     dev = torch.device("cuda:0")
-    stream = torch.cuda.Stream()
-    ctx = ck.Context(0, stream=stream)
     radii = synth.MOCK_RADII
     ns = len(radii)
-    gmax = max(g for g, _ in sizes) ** 3
-    dt = torch.float32
-    N = torch.empty(gmax, dtype=dt, device=dev)
-    R = torch.empty(gmax, dtype=dt, device=dev)
-    mN = torch.empty(ns * gmax, dtype=dt, device=dev)
-    mR = torch.empty(ns * gmax, dtype=dt, device=dev)
-    kspecs, jobs = {}, []
-    for (g, _), (d, r) in zip(sizes, cats):
-        grid = ck.Grid((g, g, g), (0.0, 0.0, 0.0), 5.0)
-        if g not in kspecs:
-            kspecs[g] = ctx.make_shell_kernels(grid, radii, dt)[0]
-        jobs.append(ck.make_job(grid, kspecs[g], args.n, args.prec, torch.from_numpy(d.pos).to(dev),
-                                torch.from_numpy(r.pos).to(dev), N=N, R=R, maps_N=mN, maps_R=mR, fused=False))
+    pos = [(torch.from_numpy(d.pos).to(dev), torch.from_numpy(r.pos).to(dev)) for d, r in cats]
+
+    def build(dt, prec, own):
+        stream = torch.cuda.Stream()
+        ctx = ck.Context(0, stream=stream)
+        gmax = max(g for g, _ in sizes) ** 3
+        shared = (torch.empty(gmax, dtype=dt, device=dev), torch.empty(gmax, dtype=dt, device=dev))
+        kspecs, jobs = {}, []
+        for (g, _), (dp, rp) in zip(sizes, pos):
+            grid = ck.Grid((g, g, g), (0.0, 0.0, 0.0), 5.0)
+            if g not in kspecs:
+                kspecs[g] = ctx.make_shell_kernels(grid, radii, dt)[0]
+            kw = {} if own else dict(N=shared[0], R=shared[1])
+            # no map buffers: the library keeps the maps it needs in its workspace
+            jobs.append(ck.make_job(grid, kspecs[g], args.n, prec, dp, rp, fused=True, **kw))
+        return ctx, stream, jobs
+
+    ctx, stream, jobs = build(torch.float32, args.prec, True)
     torch.cuda.synchronize()
     t = time.perf_counter()
     ctx.batch_plan(jobs)
-    log("plan (one eager pass, allocations): %.2f s" % (time.perf_counter() - t))
+    layout = ctx.batch_layout()
+    log("plan (one eager pass, allocations): %.2f s; chunks %s" % (time.perf_counter() - t, layout))
     tuned = None
     if not args.no_autotune:
         t = time.perf_counter()
         chosen = ctx.batch_autotune(reps=2)
         tuned = {}
-        for (g, _), c in zip(sizes, chosen):
-            tuned.setdefault("%d^3" % g, c)
+        for (g, _), c, ch in zip(sizes, chosen, layout):
+            if ch < 0:
+                tuned.setdefault("%d^3" % g, c)
         log("autotune: %.2f s, %s" % (time.perf_counter() - t, tuned))
     ctx.batch_capture()
     for _ in range(args.warmup):
         ctx.batch_launch()
     ctx.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    with torch.cuda.stream(stream):
-        e0.record(stream)
-        for _ in range(args.steps):
-            ctx.batch_launch()
-        e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / args.steps
+    ms = time_batch(ctx, stream, torch, args.steps)
     log("  %.2f ms per batch of 64 mocks" % ms)
     # per-kind launch times of one eager pass (outside the timed region)
     ctx.profile(True)
     ctx.batch_run()
     ctx.synchronize()
-    stages = {k: dict(launches=v[0], ms=round(v[1], 3)) for k, v in ctx.profile_read().items()}
+    prof = ctx.profile_read()
     ctx.profile(False)
+    chunks = {}
+    for (g, _), ch in zip(sizes, layout):
+        if ch >= 0:
+            chunks.setdefault(ch, [g, 0])[1] += 1
+    npj = [len(d) + len(r) for d, r in cats]
+    stages, over_peak = {}, []
+    for kind, (launches, tot) in prof.items():
+        ent = dict(launches=launches, ms=round(tot, 3), avg_launch_ms=tot / launches)
+        b = mock_stage_bytes(kind, sizes, ns, npj)
+        if b is not None:
+            gbs = b / (tot * 1e-3) / 1e9
+            if gbs > HBM_PEAK_GBS:
+                over_peak.append(kind)
+            else:
+                ent["gbs"] = round(gbs, 1)
+                ent["bytes_per_launch"] = b / launches
+        stages[kind] = ent
+    dom = max(stages.items(), key=lambda kv: kv[1]["ms"]) if stages else None
+    roof = None
+    if dom is not None and "gbs" in dom[1]:
+        ach = dom[1]["bytes_per_launch"] / (dom[1]["avg_launch_ms"] * 1e-3) / 1e9
+        roof = dict(bound="hbm", kernel=dom[0], achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(ach / HBM_PEAK_GBS, 4), traffic=None, traffic_unit="bytes/launch",
+                    bytes_per_launch=dom[1]["bytes_per_launch"], avg_launch_ms=dom[1]["avg_launch_ms"],
+                    note="launches of one kind differ in grid size; per-launch figures are batch averages")
+    xi32 = [j.xi.cpu().numpy() for j in jobs]
+    wd32 = [j.W_delta.cpu().numpy() for j in jobs]
+    ctx.close()
+    del jobs
+    torch.cuda.empty_cache()
+
+    ms64, rel = None, None
+    if not args.no_fp64:
+        log("float64 batch (job by job, shared grids, one HIP graph)")
+        ctx64, stream64, jobs64 = build(torch.float64, "f64", False)
+        ctx64.batch_plan(jobs64)
+        ctx64.batch_capture()
+        ctx64.batch_launch()
+        ctx64.synchronize()
+        ms64 = time_batch(ctx64, stream64, torch, max(1, min(args.steps, 3)))
+        log("  %.2f ms per float64 batch" % ms64)
+        wd64 = [j.W_delta.cpu().numpy() for j in jobs64]
+        rel = max(float(np.abs(a - b).max() / np.abs(b).max()) for a, b in zip(wd32, wd64))
+        ctx64.close()
+        del jobs64
+        torch.cuda.empty_cache()
+
+    cpu = None
+    if not args.no_cpu:
+        log("cpu baseline (oracle, one mock per grid size, bounded sample)")
+        cpu = mocks_cpu_baseline(sizes, cats, radii, args.n)
+        log("  %.3f shell-convs/s on %d cores" % (cpu["value"], cpu["cores"]))
+
     total_cells = sum(g ** 3 for g, _ in sizes)
+    n_alone = sum(1 for ch in layout if ch < 0)
     line = {
         "metric": "shell-convs/s over a batch of 64 mocks (graph replay)",
         "value": round(2 * ns * len(sizes) / (ms / 1e3), 3),
@@ -335,9 +457,15 @@ def bench_mocks(args):
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": MOCKS_NAME, "n_mocks": len(sizes), "grids": sorted({g for g, _ in sizes}),
                    "total_cells": total_cells, "points": npts, "n_radii": ns, "n": args.n,
-                   "summation": args.prec, "fft": "f32", "execution": "one HIP graph per batch",
-                   "launch_settings": tuned if tuned is not None else "defaults"},
-        "roofline": None, "cpu_baseline": None, "stages_eager": stages,
+                   "summation": args.prec, "fft": "f32",
+                   "execution": "size classes (%d chunks: %s), %d mocks alone; one HIP graph per batch" % (
+                       len(chunks), ", ".join("%d x %d^3" % (m, g) for g, m in chunks.values()), n_alone),
+                   "launch_settings": tuned if tuned else "defaults"},
+        "fp64_ms_per_step": round(ms64, 3) if ms64 else None,
+        "fp64_over_mixed": round(ms64 / ms, 3) if ms64 else None,
+        "mixed_vs_fp64_rel_W_delta": rel,
+        "roofline": roof, "cpu_baseline": cpu, "stages_eager": stages, "stages_over_peak": over_peak,
+        "launches_per_batch": int(sum(v["launches"] for v in stages.values())),
     }
     print(json.dumps(line), flush=True)
 

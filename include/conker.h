@@ -417,6 +417,34 @@ int conker_batch_run(conker_ctx *ctx);
 int conker_batch_capture(conker_ctx *ctx);
 int conker_batch_launch(conker_ctx *ctx);
 
+/* Size classes.  Mock batches hold many catalogs on a few grid sizes; run one
+ * by one, a small grid leaves most of the device idle in every stage.  So
+ * conker_batch_plan groups the jobs that share the grid (dimensions, origin,
+ * cell), the kernel bank pointer and n_radii (at most 64), with dtype float32,
+ * n = 3, split summation (CONKER_MM_SPLIT_BF16 or _F16), both catalogs below
+ * 2^22 points, 16-byte aligned grids, a grid whose cell count is a multiple
+ * of 64 and whose x length has a resident first inverse pass, and buffers
+ * (grids, maps, outputs) that no other job of the group touches.  Such a group
+ * runs in chunks: every stage of the path (zeroing and mapping, N = D -
+ * alpha R, the packed forward transform, the inverse transforms in radius
+ * batches of 8, the order-3 summation from stored maps, the ratio) is one
+ * launch for all jobs of a chunk, the job taken from the launch grid.  The
+ * results are those of the job-by-job path up to the order of float
+ * additions (mapping atomics, partial sums).  Jobs with NULL maps keep their
+ * maps in a workspace of the chunk; a chunk's workspace is bounded by 16 GiB
+ * (a class of large grids runs in several chunks) and is held by the context
+ * until it is destroyed.  A group whose chunks would hold one job each, every
+ * other job, and every job when the workspace cannot be allocated run job by
+ * job.  Chunks run first, then the other jobs in order; conker_batch_autotune
+ * tunes only the latter (a job of a chunk reports the context setting and
+ * its chunk's time divided by its number of jobs).
+ * conker_batch_classes: on != 0 (the default) enables the grouping for later
+ *   conker_batch_plan calls on the context; 0 runs every job alone.
+ * conker_batch_layout: for each planned job, the index of the chunk it runs
+ *   in, or -1 when it runs alone (h_chunk: n_jobs ints, host memory). */
+int conker_batch_classes(conker_ctx *ctx, int on);
+int conker_batch_layout(const conker_ctx *ctx, int *h_chunk);
+
 /* ---- launch shapes and their tuning ---------------------------------------
  * Not part of the method: how the convolution and summation stages are cut
  * into workgroups.  Every choice computes the same sums (the same arithmetic

@@ -77,6 +77,8 @@ SIGNATURES = {
     "conker_batch_run": (ct.c_int, [ct.c_void_p]),
     "conker_batch_capture": (ct.c_int, [ct.c_void_p]),
     "conker_batch_launch": (ct.c_int, [ct.c_void_p]),
+    "conker_batch_classes": (ct.c_int, [ct.c_void_p, ct.c_int]),
+    "conker_batch_layout": (ct.c_int, [ct.c_void_p, ct.c_void_p]),
     "conker_set_tune": (ct.c_int, [ct.c_void_p, ct.c_void_p]),
     "conker_get_tune": (ct.c_int, [ct.c_void_p, ct.c_void_p]),
     "conker_batch_autotune": (ct.c_int, [ct.c_void_p, ct.c_int, ct.c_void_p]),

@@ -405,6 +405,18 @@ class Context:
     def batch_launch(self):
         self._check(self.lib.conker_batch_launch(self.h))
 
+    def batch_classes(self, on: bool = True):
+        """Whether later batch_plan calls run size classes of jobs stage by stage
+        (the default) or every job alone."""
+        self._check(self.lib.conker_batch_classes(self.h, 1 if on else 0))
+
+    def batch_layout(self) -> list:
+        """For each planned job, the chunk of a size class it runs in, or -1 (alone)."""
+        jobs = getattr(self, "_jobs", [])
+        arr = (ct.c_int * max(1, len(jobs)))()
+        self._check(self.lib.conker_batch_layout(self.h, ct.cast(arr, ct.c_void_p)))
+        return [int(arr[k]) for k in range(len(jobs))]
+
     def batch_autotune(self, reps: int = 3) -> list:
         """Times launch settings per job shape (after batch_plan) and keeps the
         fastest for later batch_run / batch_capture; returns one dict per job."""
@@ -506,7 +518,10 @@ def make_job(grid: Grid, kspec: torch.Tensor, n: int, precision: str, data_pos: 
              maps_N: Optional[torch.Tensor] = None, maps_R: Optional[torch.Tensor] = None,
              fused: Optional[bool] = None) -> Job:
     """Builds a Job, allocating what is not given.  Grid and map tensors may be
-    shared between jobs of one batch (they run in order); outputs are per job."""
+    shared between jobs of one batch (they run in order); outputs are per job.
+    fused=True gives the job no map buffers: the library keeps the maps it needs
+    in its workspace (fused kernel, maps of carrying lines, or a size class's
+    workspace).  Jobs that share no buffer can run as one size class."""
     dev, dt = kspec.device, kspec.dtype
     shape = tuple(int(d) for d in grid.dims)
     nr = int(kspec.shape[0])

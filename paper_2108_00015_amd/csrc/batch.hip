@@ -65,6 +65,233 @@ int run_job(conker_ctx *c, const conker_job &j) {
     return CONKER_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Size classes.  Jobs on one grid (dimensions, origin and cell), with one
+// kernel bank and number of radii (at most 64), float32, order 3, split
+// summation, catalogs below the binned mapping's size, and buffers that no
+// other job of the class touches, run stage by stage: each stage is one
+// launch for a chunk of such jobs, the job in the grid's y (or z) index and
+// its buffers in a device table (ClassJob).  The stages are those of the
+// job-by-job path (direct mapping, packed forward transform, resident first
+// inverse pass, radii in batches of CLASS_NB, matrix-core summation from
+// stored maps).  A chunk's workspace (spectra, radius-batch spectra, the maps
+// of jobs that give none, scales, partial sums) is at most CLASS_WS bytes, so
+// a class of large grids runs in several chunks; a class whose chunks would
+// hold one job each, and every other job, runs job by job.
+// ---------------------------------------------------------------------------
+constexpr size_t CLASS_WS = (size_t)16 << 30;
+constexpr int CLASS_NB = 8;
+
+size_t up256(size_t b) { return (b + 255) / 256 * 256; }
+
+struct ChunkLayout {
+    size_t spec, tspec, maps, scales, part, c3, bytes;
+};
+
+ChunkLayout chunk_layout(conker_ctx *c, const conker_job &j0, int M, int nb, bool maps) {
+    const size_t nc = ncells(&j0.grid);
+    const int ns = j0.n_radii;
+    ChunkLayout L;
+    L.spec = 0;
+    L.tspec = L.spec + up256((size_t)M * nc * 8);
+    L.maps = L.tspec + up256((size_t)M * nb * nc * 8);
+    L.scales = L.maps + (maps ? up256((size_t)M * 2 * ns * nc * 4) : 0);
+    L.part = L.scales + up256((size_t)M * sizeof(PackScale));
+    L.c3 = L.part + up256(((size_t)4 * cu_count(c) + M) * 2 * sizeof(double));
+    L.bytes = L.c3 + up256(contract3_jobs_bytes(c, &j0.grid, M, ns));
+    return L;
+}
+
+bool class_ok(const conker_job &j) {
+    const int64_t big = scatter_bin_min_points();
+    const size_t nc = ncells(&j.grid);
+    const bool aligned = (((uintptr_t)j.d_N | (uintptr_t)j.d_R) & 15) == 0;
+    return j.dtype == CONKER_F32 && j.n == 3 && (j.prec == CONKER_MM_SPLIT_BF16 || j.prec == CONKER_MM_SPLIT_F16) &&
+           j.n_radii <= 64 && j.n_data < big && j.n_rand < big && nc % 64 == 0 && aligned && fft_jobs_ok(&j.grid);
+}
+
+// Device byte ranges a job writes or owns (grids, maps, outputs).
+void job_ranges(const conker_job &j, std::vector<std::pair<uintptr_t, uintptr_t>> &out) {
+    const size_t nc = ncells(&j.grid), ns = j.n_radii;
+    const size_t cnt = (size_t)conker_num_tuples(j.n_radii, j.n);
+    auto add = [&](const void *p, size_t b) {
+        if (p && b) out.push_back({(uintptr_t)p, (uintptr_t)p + b});
+    };
+    add(j.d_N, nc * 4);
+    add(j.d_R, nc * 4);
+    add(j.d_maps_N, ns * nc * 4);
+    add(j.d_maps_R, ns * nc * 4);
+    add(j.d_wsum, 2 * sizeof(double));
+    add(j.d_n_outside, 2 * sizeof(int64_t));
+    add(j.d_alpha, sizeof(double));
+    add(j.d_W_delta, cnt * 8);
+    add(j.d_W_rand, cnt * 8);
+    add(j.d_xi, cnt * 8);
+}
+
+bool overlaps(const std::vector<std::pair<uintptr_t, uintptr_t>> &a,
+              const std::vector<std::pair<uintptr_t, uintptr_t>> &b) {
+    for (const auto &x : a)
+        for (const auto &y : b)
+            if (x.first < y.second && y.first < x.second) return true;
+    return false;
+}
+
+// Splits the planned batch into chunks of size classes and jobs run alone,
+// reserves conker_ctx::cls and writes the chunks' tables.
+int plan_classes(conker_ctx *c) {
+    c->chunks.clear();
+    c->seq_jobs.clear();
+    const int nj = (int)c->jobs.size();
+    std::vector<int> seq;
+    std::vector<std::vector<int>> groups;
+    if (c->batch_classes) {
+        using Key = std::tuple<int, int, int, double, double, double, double, const void *, int, int>;
+        std::map<Key, size_t> where;
+        for (int k = 0; k < nj; ++k) {
+            const conker_job &j = c->jobs[k];
+            if (!class_ok(j)) {
+                seq.push_back(k);
+                continue;
+            }
+            const Key key{j.grid.dims[0], j.grid.dims[1], j.grid.dims[2], j.grid.origin[0], j.grid.origin[1],
+                          j.grid.origin[2], j.grid.cell, j.d_kspec, j.n_radii, (int)j.prec};
+            auto it = where.find(key);
+            if (it == where.end()) {
+                where[key] = groups.size();
+                groups.push_back({k});
+            } else {
+                groups[it->second].push_back(k);
+            }
+        }
+    } else {
+        for (int k = 0; k < nj; ++k) seq.push_back(k);
+    }
+    size_t tab_bytes = 0, ws_max = 0;
+    for (const auto &grp : groups) {
+        // members whose buffers no earlier member touches
+        std::vector<int> mem;
+        std::vector<std::pair<uintptr_t, uintptr_t>> held;
+        for (int k : grp) {
+            std::vector<std::pair<uintptr_t, uintptr_t>> r;
+            job_ranges(c->jobs[k], r);
+            if (overlaps(r, held)) {
+                seq.push_back(k);
+                continue;
+            }
+            held.insert(held.end(), r.begin(), r.end());
+            mem.push_back(k);
+        }
+        const conker_job &j0 = c->jobs[grp[0]];
+        const int nb = std::min(j0.n_radii, CLASS_NB);
+        // greedy chunks under the workspace bound
+        std::vector<ClassChunk> mine;
+        ClassChunk cur;
+        cur.nb = nb;
+        auto bytes_of = [&](const std::vector<int> &js) {
+            bool maps = false;
+            for (int k : js) maps = maps || c->jobs[k].d_maps_N == nullptr;
+            return chunk_layout(c, j0, (int)js.size(), nb, maps).bytes;
+        };
+        for (int k : mem) {
+            std::vector<int> t = cur.jobs;
+            t.push_back(k);
+            if (!cur.jobs.empty() && bytes_of(t) > CLASS_WS) {
+                mine.push_back(cur);
+                cur.jobs.clear();
+                t = {k};
+            }
+            cur.jobs = t;
+        }
+        if (!cur.jobs.empty()) mine.push_back(cur);
+        size_t most = 0;
+        for (const auto &ch : mine) most = std::max(most, ch.jobs.size());
+        if (most < 2 || bytes_of({mine[0].jobs[0]}) > CLASS_WS) {   // nothing shared: job by job
+            for (int k : mem) seq.push_back(k);
+            continue;
+        }
+        for (auto &ch : mine) {
+            ch.tab_off = tab_bytes;
+            tab_bytes += up256(ch.jobs.size() * sizeof(ClassJob));
+            ws_max = std::max(ws_max, bytes_of(ch.jobs));
+            c->chunks.push_back(ch);
+        }
+    }
+    if (!c->chunks.empty()) {
+        const int st = ws_reserve(c, c->cls, tab_bytes + ws_max);
+        if (st != CONKER_OK) {   // no room: every job runs alone
+            if (st != CONKER_ENOMEM) return st;
+            c->err.clear();
+            for (const auto &ch : c->chunks) seq.insert(seq.end(), ch.jobs.begin(), ch.jobs.end());
+            c->chunks.clear();
+        }
+    }
+    c->cls_ws_off = tab_bytes;
+    std::sort(seq.begin(), seq.end());
+    c->seq_jobs = seq;
+    for (const auto &ch : c->chunks) {
+        const conker_job &j0 = c->jobs[ch.jobs[0]];
+        const int M = (int)ch.jobs.size();
+        bool maps = false;
+        for (int k : ch.jobs) maps = maps || c->jobs[k].d_maps_N == nullptr;
+        const ChunkLayout L = chunk_layout(c, j0, M, ch.nb, maps);
+        const size_t nc = ncells(&j0.grid), ns = j0.n_radii;
+        char *ws = (char *)c->cls.p + c->cls_ws_off;
+        std::vector<ClassJob> tab(M);
+        for (int i = 0; i < M; ++i) {
+            const conker_job &j = c->jobs[ch.jobs[i]];
+            ClassJob &t = tab[i];
+            t.N = (float *)j.d_N;
+            t.R = (float *)j.d_R;
+            if (j.d_maps_N) {
+                t.mapsN = (float *)j.d_maps_N;
+                t.mapsR = (float *)j.d_maps_R;
+            } else {
+                t.mapsN = (float *)(ws + L.maps) + (size_t)i * 2 * ns * nc;
+                t.mapsR = t.mapsN + ns * nc;
+            }
+            t.dpos = j.d_data_pos;
+            t.dw = j.d_data_w;
+            t.rpos = j.d_rand_pos;
+            t.rw = j.d_rand_w;
+            t.nd = j.n_data;
+            t.nr = j.n_rand;
+            t.wsum = j.d_wsum;
+            t.nout = (long long *)j.d_n_outside;
+            t.alpha = j.d_alpha;
+            t.Wd = j.d_W_delta;
+            t.Wr = j.d_W_rand;
+            t.xi = j.d_xi;
+        }
+        CK_HIP(c, hipMemcpyAsync((char *)c->cls.p + ch.tab_off, tab.data(), M * sizeof(ClassJob),
+                                 hipMemcpyHostToDevice, c->stream));
+    }
+    CK_HIP(c, hipStreamSynchronize(c->stream));
+    return CONKER_OK;
+}
+
+int run_chunk(conker_ctx *c, const ClassChunk &ch) {
+    const conker_job &j0 = c->jobs[ch.jobs[0]];
+    const int M = (int)ch.jobs.size(), ns = j0.n_radii;
+    bool maps = false;
+    int64_t n_max = 0;
+    for (int k : ch.jobs) {
+        maps = maps || c->jobs[k].d_maps_N == nullptr;
+        n_max = std::max({n_max, c->jobs[k].n_data, c->jobs[k].n_rand});
+    }
+    const ChunkLayout L = chunk_layout(c, j0, M, ch.nb, maps);
+    const ClassJob *tab = (const ClassJob *)((const char *)c->cls.p + ch.tab_off);
+    char *ws = (char *)c->cls.p + c->cls_ws_off;
+    PackScale *scales = (PackScale *)(ws + L.scales);
+    CK_OK(map_jobs(c, &j0.grid, M, tab, n_max));
+    CK_OK(fft_forward_jobs(c, &j0.grid, M, tab, ws + L.spec, scales, (double *)(ws + L.part)));
+    for (int m0 = 0; m0 < ns; m0 += ch.nb)
+        CK_OK(fft_inverse_jobs(c, &j0.grid, M, tab, j0.d_kspec, m0, std::min(ch.nb, ns - m0), ws + L.spec,
+                               ws + L.tspec, scales));
+    CK_OK(contract3_jobs(c, &j0.grid, M, tab, ns, j0.prec, ws + L.c3));
+    return ratio_jobs(c, M, tab, 3, conker_num_tuples(ns, 3));
+}
+
 // Launch shapes of job k while it is enqueued; the context setting again after.
 struct TuneScope {
     conker_ctx *c;
@@ -77,7 +304,11 @@ const conker_tune &tune_of(const conker_ctx *c, size_t k) {
 }
 
 int run_all(conker_ctx *c) {
-    for (size_t k = 0; k < c->jobs.size(); ++k) {
+    for (const auto &ch : c->chunks) {
+        TuneScope ts(c, c->user_tune);
+        CK_OK(run_chunk(c, ch));
+    }
+    for (int k : c->seq_jobs) {
         TuneScope ts(c, tune_of(c, k));
         CK_OK(run_job(c, c->jobs[k]));
     }
@@ -191,6 +422,13 @@ extern "C" int conker_batch_plan(conker_ctx *c, const conker_job *jobs, int n_jo
     }
     c->jobs.assign(jobs, jobs + n_jobs);
     c->job_tune.clear();
+    c->chunks.clear();
+    c->seq_jobs.clear();
+    const int st = plan_classes(c);
+    if (st != CONKER_OK) {
+        c->jobs.clear();
+        return st;
+    }
     // one eager pass allocates every buffer and table the jobs use
     CK_OK(run_all(c));
     CK_HIP(c, hipStreamSynchronize(c->stream));
@@ -244,6 +482,20 @@ extern "C" int conker_batch_launch(conker_ctx *c) {
     return CONKER_OK;
 }
 
+extern "C" int conker_batch_classes(conker_ctx *c, int on) {
+    if (!c) return CONKER_EINVAL;
+    c->batch_classes = on != 0;
+    return CONKER_OK;
+}
+
+extern "C" int conker_batch_layout(const conker_ctx *c, int *h_chunk) {
+    if (!c || !h_chunk) return CONKER_EINVAL;
+    for (size_t k = 0; k < c->jobs.size(); ++k) h_chunk[k] = -1;
+    for (size_t q = 0; q < c->chunks.size(); ++q)
+        for (int k : c->chunks[q].jobs) h_chunk[k] = (int)q;
+    return CONKER_OK;
+}
+
 extern "C" int conker_set_tune(conker_ctx *c, const conker_tune *t) {
     if (!c) return CONKER_EINVAL;
     conker_tune v{};
@@ -280,8 +532,21 @@ extern "C" int conker_batch_autotune(conker_ctx *c, int reps, conker_tune *h_cho
                  : fail(c, CONKER_EHIP, "hipEventCreate failed");
     using Key = std::tuple<int, int, int, int, int, int, int, bool>;
     std::map<Key, conker_tune> seen;
-    std::vector<conker_tune> chosen(c->jobs.size());
-    for (size_t k = 0; k < c->jobs.size() && st == CONKER_OK; ++k) {
+    std::vector<conker_tune> chosen(c->jobs.size(), c->user_tune);
+    for (const auto &ch : c->chunks) {   // size classes keep the context setting: their time per job
+        if (st != CONKER_OK) break;
+        float ms = 3.0e38f;
+        for (int r = 0; r <= reps && st == CONKER_OK; ++r) {   // the first run untimed
+            st = hipEventRecord(e0, c->stream) == hipSuccess ? run_chunk(c, ch) : CONKER_EHIP;
+            if (st == CONKER_OK && (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+                st = fail(c, CONKER_EHIP, "event timing failed");
+            float v = 0.f;
+            if (st == CONKER_OK && r > 0 && hipEventElapsedTime(&v, e0, e1) == hipSuccess) ms = std::min(ms, v);
+        }
+        for (int k : ch.jobs) chosen[k].ms = ms / (float)ch.jobs.size();
+    }
+    for (size_t q = 0; q < c->seq_jobs.size() && st == CONKER_OK; ++q) {
+        const size_t k = (size_t)c->seq_jobs[q];
         const conker_job &j = c->jobs[k];
         const Key key{j.grid.dims[0], j.grid.dims[1], j.grid.dims[2], (int)j.dtype, (int)j.prec, j.n, j.n_radii,
                       j.d_maps_N == nullptr};

@@ -36,6 +36,15 @@ constexpr size_t SCAL_PART_OFF = 256;
 constexpr int SCAL_MAX_PART = 4096;   // workgroups of the sums (two doubles each)
 constexpr size_t SCAL_BYTES = SCAL_PART_OFF + (size_t)SCAL_MAX_PART * 2 * sizeof(double);
 
+// A chunk of one size class of a planned batch (batch.hip): the planned jobs
+// `jobs`, run stage by stage; their device table at conker_ctx::cls + tab_off,
+// radii transformed nb at a time.
+struct ClassChunk {
+    std::vector<int> jobs;
+    size_t tab_off = 0;
+    int nb = 0;
+};
+
 }  // namespace conker
 
 struct conker_ctx {
@@ -69,6 +78,11 @@ struct conker_ctx {
     conker_tune tune{};                // launch shapes of the calls now enqueued (0 = default)
     conker_tune user_tune{};           // set by conker_set_tune
     std::vector<conker_tune> job_tune; // per planned job (conker_batch_autotune), else empty
+    bool batch_classes = true;         // conker_batch_classes
+    std::vector<conker::ClassChunk> chunks;  // size classes of the planned batch
+    std::vector<int> seq_jobs;         // planned jobs run one at a time
+    conker::Buf cls;                   // size classes: job tables, then the workspace of one chunk
+    size_t cls_ws_off = 0;
     hipGraphExec_t graph_exec = nullptr;
     struct Rec {
         int kind;
@@ -247,6 +261,46 @@ int fft_inverse_batch(conker_ctx *ctx, const conker_grid *g, bool f64,
 int fft_inverse_z_diag(conker_ctx *ctx, const conker_grid *g, bool f64, const void *tspec, int nb,
                        const void *fa, const void *fb, int pmax, int blocks, void *part,
                        const Support *sup = nullptr);
+
+// ---------------------------------------------------------------------------
+// Size classes of a batch (batch.hip): jobs on one grid with one kernel bank,
+// order and arithmetic run every stage as one launch over all of them, the job
+// taken from blockIdx.y (or z).  ClassJob is one entry of the device table of
+// their buffers (float32 grids).
+// ---------------------------------------------------------------------------
+struct ClassJob {
+    float *N, *R, *mapsN, *mapsR;
+    const float *dpos, *dw, *rpos, *rw;
+    long long nd, nr;
+    double *wsum;              // [2]
+    long long *nout;           // [2]
+    double *alpha;             // [1]
+    double *Wd, *Wr, *xi;      // [tuples]
+};
+// Forward transforms of all M jobs: spec[j] (complex [nc], contiguous by job)
+// of N_j + i s_j R_j, s_j into scales[j]; part holds M * 4 * cu_count pairs.
+int fft_forward_jobs(conker_ctx *c, const conker_grid *g, int M, const ClassJob *tab, void *spec,
+                     PackScale *scales, double *part);
+// Inverse transforms of radii [m0, m0 + nb) of all M jobs: tspec[j][0 .. nb)
+// (contiguous), then the maps of job j into tab[j].mapsN / mapsR rows m0 ..
+// (maps of R multiplied by 1 / s_j).
+int fft_inverse_jobs(conker_ctx *c, const conker_grid *g, int M, const ClassJob *tab, const void *kspec, int m0,
+                     int nb, const void *spec, void *tspec, const PackScale *scales);
+// Whether the size-class transforms support grid g (float32): a resident
+// first inverse pass exists for its x length and fits its z length.
+bool fft_jobs_ok(const conker_grid *g);
+// Zeroes, maps and forms N = D - alpha R for all M jobs (direct mapping with
+// atomics; n_max: the largest catalog of the table).
+int map_jobs(conker_ctx *c, const conker_grid *g, int M, const ClassJob *tab, int64_t n_max);
+// Catalogs of at least this many points take the binned mapping path.
+int64_t scatter_bin_min_points();
+// xi of every job of the table (count tuples of order n).
+int ratio_jobs(conker_ctx *c, int M, const ClassJob *tab, int n, int64_t count);
+// W_delta and W_R of order 3 of all M jobs from their maps (split arithmetic,
+// n_radii <= 64), into tab[j].Wd / Wr.  ws: workspace of contract3_jobs_bytes.
+size_t contract3_jobs_bytes(conker_ctx *c, const conker_grid *g, int M, int ns);
+int contract3_jobs(conker_ctx *c, const conker_grid *g, int M, const ClassJob *tab, int ns, conker_mmprec prec,
+                   void *ws);
 
 // The context's PackScale (device memory, valid on the context's stream after
 // the last packed forward transform).

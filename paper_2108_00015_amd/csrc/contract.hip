@@ -19,7 +19,9 @@
 // Matrix-core instructions (gfx950, wave64):
 //   float64:  v_mfma_f64_16x16x4_f64    (16x16 tiles, 4 cells per instruction)
 //   float32:  v_mfma_f32_32x32x2_f32    (32x32 tiles, 2 cells per instruction)
-//   split:    v_mfma_f32_32x32x16_bf16  (32x32 tiles, 16 cells per instruction);
+//   split:    v_mfma_f32_32x32x16_bf16  (32x32 tiles, 16 cells per instruction;
+//             n = 3 with at most 16 radii: v_mfma_f32_16x16x32_bf16, one
+//             16x16 tile, 32 cells per instruction);
 //             each float32 operand is split into three bfloat16 terms
 //             x = h + m + l and the six products of order <= 2^-16 relative
 //             (hh, hm, mh, hl, mm, lh) are accumulated.
@@ -391,10 +393,20 @@ __device__ __forceinline__ void split2h(const float (&v)[8], f16x8 &hi, f16x8 &l
 // max |x| of every map row and of F over the summed blocks (the cells that
 // enter any sum), as float bits (non-negative floats order like their bit
 // patterns): grid (workgroups, ns + 1).
+// With tab (size classes): field z = blockIdx.z is N (z even) or R (z odd) of
+// job z / 2, its rows at out + z (ns + 1).
 __global__ __launch_bounds__(256) void k_absmax(const float *__restrict__ F, const float *__restrict__ maps,
                                                 size_t nc, int ns, const int *__restrict__ list,
-                                                const int *__restrict__ count, unsigned *__restrict__ out) {
+                                                const int *__restrict__ count, unsigned *__restrict__ out,
+                                                const ClassJob *__restrict__ tab) {
     __shared__ float red[4];
+    if (tab) {
+        const ClassJob &j = tab[blockIdx.z >> 1];
+        const bool r = blockIdx.z & 1;
+        F = r ? j.R : j.N;
+        maps = r ? j.mapsR : j.mapsN;
+        out += (size_t)blockIdx.z * (ns + 1);
+    }
     const int row = blockIdx.y;
     const float *src = row < ns ? maps + (size_t)row * nc : F;
     const Blocks bk = my_blocks(list, count, nc);
@@ -840,6 +852,17 @@ __global__ void k_gather(const double *__restrict__ full, const int *__restrict_
     if (t < count) W[t] = full[where[t]];
 }
 
+// Size classes: field z = blockIdx.y (N of job z / 2 for even z, R for odd)
+// gathers from its tiles, tile_elems doubles apart.
+__global__ void k_gather_jobs(const double *__restrict__ full, size_t tile_elems, const int *__restrict__ where,
+                              int64_t count, const ClassJob *__restrict__ tab) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= count) return;
+    const ClassJob &j = tab[blockIdx.y >> 1];
+    double *W = (blockIdx.y & 1) ? j.Wr : j.Wd;
+    W[t] = full[(size_t)blockIdx.y * tile_elems + where[t]];
+}
+
 // ---------------------------------------------------------------------------
 // host-side planning: items, needed tiles, tuple locations
 // ---------------------------------------------------------------------------
@@ -1057,12 +1080,24 @@ int contract_dot(conker_ctx *c, const T *F, const T *maps, size_t nc, int ns, co
 // the current ones are used, so a wave keeps one step of loads in flight.
 // Cells: each wave takes 16 of every 64-cell block of its workgroup's share.
 // ---------------------------------------------------------------------------
+// With tab (size classes): field z = blockIdx.y is N (z even) or R (z odd) of
+// job z / 2, its scales at maxabs + z (ns + 1) and its tiles after the
+// z NTL G partial tiles of the fields before it.
 template <int RT, int PREC>
 __global__ __launch_bounds__(NT) void k_mm3(const float *__restrict__ F, const float *__restrict__ maps, size_t nc,
                                             const int *__restrict__ list, const int *__restrict__ count, int ns,
-                                            double *__restrict__ partial, const unsigned *__restrict__ maxabs) {
+                                            double *__restrict__ partial, const unsigned *__restrict__ maxabs,
+                                            const ClassJob *__restrict__ tab) {
     constexpr bool F16 = PREC == CONKER_MM_SPLIT_F16;
     constexpr int NTL = RT == 1 ? 1 : 3, TS = 32, CPI = 16, FLUSH = 8;
+    if (tab) {
+        const ClassJob &jb = tab[blockIdx.y >> 1];
+        const bool fr = blockIdx.y & 1;
+        F = fr ? jb.R : jb.N;
+        maps = fr ? jb.mapsR : jb.mapsN;
+        if (maxabs) maxabs += (size_t)blockIdx.y * (ns + 1);
+        partial += (size_t)blockIdx.y * NTL * gridDim.x * (TS * TS);
+    }
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int r = lane & 31, h = lane >> 5;
     const int m0 = r < ns ? r : -1;
@@ -1186,6 +1221,124 @@ __global__ __launch_bounds__(NT) void k_mm3(const float *__restrict__ F, const f
     }
 }
 
+// n = 3 with at most 16 radii: one 16 x 16 tile (v_mfma_f32_16x16x32_bf16 /
+// _f16, 32 cells per instruction), so no lane carries a padding row as it
+// would in a 32 x 32 tile.  Lane: row and column r = lane % 16, cells
+// 8 (lane / 16) .. + 7 of its wave's 32; two waves per 64-cell block, two
+// blocks per step of the workgroup.  Output element (i, j) of the tile sits
+// in lane j + 16 (i / 4), register i % 4.  The tile is written into the
+// upper-left corner of a 32 x 32 partial tile (zeros elsewhere), the layout
+// the reduction and gather of the 32 x 32 plan read.
+template <int PREC>
+__global__ __launch_bounds__(NT) void k_mm3s(const float *__restrict__ F, const float *__restrict__ maps, size_t nc,
+                                             const int *__restrict__ list, const int *__restrict__ count, int ns,
+                                             double *__restrict__ partial, const unsigned *__restrict__ maxabs,
+                                             const ClassJob *__restrict__ tab) {
+    constexpr bool F16 = PREC == CONKER_MM_SPLIT_F16;
+    constexpr int FLUSH = 4;   // float32 sums over 128 cells per lane, then float64
+    typedef float floatx4 __attribute__((ext_vector_type(4)));
+    if (tab) {
+        const ClassJob &jb = tab[blockIdx.y >> 1];
+        const bool fr = blockIdx.y & 1;
+        F = fr ? jb.R : jb.N;
+        maps = fr ? jb.mapsR : jb.mapsN;
+        if (maxabs) maxabs += (size_t)blockIdx.y * (ns + 1);
+        partial += (size_t)blockIdx.y * gridDim.x * 1024;
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int r = lane & 15, h = lane >> 4;
+    const int m0 = r < ns ? r : -1;
+    const float *p0 = maps + (size_t)(m0 < 0 ? 0 : m0) * nc;
+    int eA = 0, eB = 0;
+    if constexpr (F16) {
+        eA = items_exp(maxabs, ns, m0 < 0 ? -2 : m0, -1, true);
+        eB = items_exp(maxabs, ns, m0 < 0 ? -2 : m0, -1, false);
+    }
+    floatx4 acc = floatx4{0};
+    double accd[4] = {0.0, 0.0, 0.0, 0.0};
+    const bool hm = m0 >= 0;
+    float f[8], c0[8];
+    const Blocks bk = my_blocks(list, count, nc);
+    const int half = w & 1, pairw = w >> 1;
+    // Blocks beyond the workgroup's share, cells beyond the grid (nc % 16 == 0:
+    // a lane's 8 cells are all in or all out) and lanes without a map read a
+    // valid address and are zeroed by a select.
+    auto load = [&](int k) {
+        const int kb = k + pairw;
+        const bool inb = kb < bk.k1;
+        const size_t xw = bk.first(inb ? kb : k) + (size_t)half * 32 + 8 * h;
+        const bool in = inb && xw < nc;
+        const size_t x = in ? xw : 0;
+        ld<float, 8>(F + x, f);
+        ld<float, 8>(p0 + x, c0);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            f[e] = in ? f[e] : 0.f;
+            c0[e] = hm ? c0[e] : 0.f;
+        }
+    };
+    if (bk.k0 < bk.k1) load(bk.k0);
+    int cnt = 0;
+    for (int k = bk.k0; k < bk.k1; k += 2) {
+        float a[8], b[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            a[e] = f[e] * c0[e];
+            b[e] = c0[e];
+        }
+        load(k + 2 < bk.k1 ? k + 2 : k);
+        if constexpr (F16) {
+            float sa[8], sb[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                sa[e] = ldexpf(a[e], eA);
+                sb[e] = ldexpf(b[e], eB);
+            }
+            f16x8 ah, al, bh, bl;
+            split2h(sa, ah, al);
+            split2h(sb, bh, bl);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh, acc, 0, 0, 0);
+        } else {
+            bf16x8 ah, am, al, bh, bm, bl;
+            split3(a, ah, am, al);
+            split3(b, bh, bm, bl);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bm, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc, 0, 0, 0);
+        }
+        if (++cnt == FLUSH) {
+            cnt = 0;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) accd[v] += (double)acc[v];
+            acc = floatx4{0};
+        }
+    }
+    __shared__ double lds[WAVES * 4 * 64];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        double t = accd[v] + (double)acc[v];
+        if constexpr (F16) t = ldexp(t, -(__shfl(eA, 4 * h + v) + eB));   // row 4 h + v, column r
+        lds[(w * 4 + v) * 64 + lane] = t;
+    }
+    __syncthreads();
+    double *out = partial + (size_t)blockIdx.x * 1024;
+    for (int e = threadIdx.x; e < 1024; e += NT) {
+        const int i = e >> 5, j = e & 31;
+        double s = 0.0;
+        if (i < 16 && j < 16) {
+            const int l = j + 16 * (i >> 2), v = i & 3;
+#pragma unroll
+            for (int q = 0; q < WAVES; ++q) s += lds[(q * 4 + v) * 64 + l];
+        }
+        out[e] = s;
+    }
+}
+
 template <int NBW>
 int launch_mm(conker_ctx *c, conker_mmprec prec, dim3 grid, const void *F, const void *maps, size_t nc,
               const int *list, const int *count, const Items *tab, int n_tiles, double *part, int ns,
@@ -1257,7 +1410,7 @@ extern "C" int conker_contract_npt(conker_ctx *c, const conker_grid *g, conker_d
         const size_t mchunk = 64 * 1024;
         const dim3 mg((unsigned)((nc + mchunk - 1) / mchunk), (unsigned)(ns + 1));
         hipLaunchKernelGGL(k_absmax, mg, dim3(256), 0, c->stream, (const float *)F, (const float *)maps, nc, ns,
-                           blist, bcount, maxabs);
+                           blist, bcount, maxabs, (const ClassJob *)nullptr);
         CK_LAUNCH(c);
     }
     if (use_v2) {
@@ -1322,8 +1475,8 @@ extern "C" int conker_contract_npt(conker_ctx *c, const conker_grid *g, conker_d
     const bool use_mm3 = n == 3 && ns <= 64 && (prec == CONKER_MM_SPLIT_BF16 || prec == CONKER_MM_SPLIT_F16) &&
                          (mm_kernel == 3 || mm_kernel == 0);
     if (use_mm3) {
-        const int RT = ns <= 32 ? 1 : 2;
-        if (pl.n_tiles != (RT == 1 ? 1 : 3)) return fail(c, CONKER_EINVAL, "unexpected tile plan");
+        const int RT = ns <= 16 ? 0 : (ns <= 32 ? 1 : 2);
+        if (pl.n_tiles != (RT <= 1 ? 1 : 3)) return fail(c, CONKER_EINVAL, "unexpected tile plan");
         const size_t G = std::max<size_t>(1, std::min<size_t>(nc / 1024, (size_t)8 * cu_count(c)));
         const int te = TS * TS;
         CK_OK(ws_reserve(c, c->partial, (size_t)pl.n_tiles * G * te * sizeof(double)));
@@ -1333,9 +1486,13 @@ extern "C" int conker_contract_npt(conker_ctx *c, const conker_grid *g, conker_d
             ProfScope ps(c, PK_CONTRACT_MM);
             auto go = [&](auto kern) {
                 hipLaunchKernelGGL(kern, dim3((unsigned)G), dim3(NT), 0, c->stream, (const float *)F,
-                                   (const float *)maps, nc, blist, bcount, ns, part, (const unsigned *)maxabs);
+                                   (const float *)maps, nc, blist, bcount, ns, part, (const unsigned *)maxabs,
+                                   (const ClassJob *)nullptr);
             };
-            if (RT == 1) {
+            if (RT == 0) {
+                if (prec == CONKER_MM_SPLIT_F16) go(k_mm3s<CONKER_MM_SPLIT_F16>);
+                else go(k_mm3s<CONKER_MM_SPLIT_BF16>);
+            } else if (RT == 1) {
                 if (prec == CONKER_MM_SPLIT_F16) go(k_mm3<1, CONKER_MM_SPLIT_F16>);
                 else go(k_mm3<1, CONKER_MM_SPLIT_BF16>);
             } else {
@@ -1390,3 +1547,100 @@ extern "C" int conker_contract_npt(conker_ctx *c, const conker_grid *g, conker_d
     CK_LAUNCH(c);
     return CONKER_OK;
 }
+
+// ---------------------------------------------------------------------------
+// Order 3 for every job of a size class (batch.hip): absmax (split-f16), one
+// summation launch over all 2M fields (every 64-cell block: size classes are
+// full boxes), one two-level reduction over all their tiles, one gather.
+// ---------------------------------------------------------------------------
+namespace {
+struct Jobs3Layout {
+    int G, ntl;
+    size_t maxabs_off, part_off, full_off, bytes;
+};
+Jobs3Layout jobs3_layout(conker_ctx *c, size_t nc, int M, int ns) {
+    Jobs3Layout L;
+    L.ntl = ns <= 32 ? 1 : 3;
+    L.G = (int)std::max<size_t>(1, std::min<size_t>(nc / 1024, (size_t)8 * cu_count(c) / (2 * (size_t)M)));
+    const auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t nf = 2 * (size_t)M, te = 1024;
+    L.maxabs_off = 0;
+    L.part_off = up(nf * (ns + 1) * sizeof(unsigned));
+    L.full_off = L.part_off + up(nf * L.ntl * (size_t)L.G * te * sizeof(double));
+    L.bytes = L.full_off + up(nf * L.ntl * te * (RED_S + 1) * sizeof(double));
+    return L;
+}
+}  // namespace
+
+namespace conker {
+
+size_t contract3_jobs_bytes(conker_ctx *c, const conker_grid *g, int M, int ns) {
+    return jobs3_layout(c, ncells(g), M, ns).bytes;
+}
+
+int contract3_jobs(conker_ctx *c, const conker_grid *g, int M, const ClassJob *tab, int ns, conker_mmprec prec,
+                   void *ws) {
+    if (ns < 1 || ns > 64) return fail(c, CONKER_EINVAL, "size class: n_radii=%d outside 1..64", ns);
+    if (prec != CONKER_MM_SPLIT_BF16 && prec != CONKER_MM_SPLIT_F16)
+        return fail(c, CONKER_EINVAL, "size class: split summation only");
+    const size_t nc = ncells(g);
+    if (nc % 64) return fail(c, CONKER_EUNSUPPORTED, "cell count must be a multiple of 64");
+    const Jobs3Layout L = jobs3_layout(c, nc, M, ns);
+    Plan pl;
+    CK_OK(make_plan(c, ns, 3, 32, pl));
+    if (pl.n_tiles != L.ntl) return fail(c, CONKER_EINVAL, "unexpected tile plan");
+    char *base = (char *)ws;
+    unsigned *maxabs = (unsigned *)(base + L.maxabs_off);
+    double *part = (double *)(base + L.part_off);
+    double *full = (double *)(base + L.full_off);
+    const unsigned nf = 2u * (unsigned)M;
+    if (prec == CONKER_MM_SPLIT_F16) {
+        ProfScope ps(c, PK_CONTRACT_DOT);
+        const int nz = (int)nf * (ns + 1);
+        hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)((nz + 127) / 128)), dim3(128), 0, c->stream, maxabs, nz);
+        CK_LAUNCH(c);
+        const size_t mchunk = 64 * 1024;
+        const dim3 mg((unsigned)((nc + mchunk - 1) / mchunk), (unsigned)(ns + 1), nf);
+        hipLaunchKernelGGL(k_absmax, mg, dim3(256), 0, c->stream, (const float *)nullptr, (const float *)nullptr, nc,
+                           ns, (const int *)nullptr, (const int *)nullptr, maxabs, tab);
+        CK_LAUNCH(c);
+    }
+    {
+        ProfScope ps(c, PK_CONTRACT_MM);
+        const dim3 grid((unsigned)L.G, nf);
+        auto go = [&](auto kern) {
+            hipLaunchKernelGGL(kern, grid, dim3(NT), 0, c->stream, (const float *)nullptr, (const float *)nullptr, nc,
+                               (const int *)nullptr, (const int *)nullptr, ns, part,
+                               prec == CONKER_MM_SPLIT_F16 ? (const unsigned *)maxabs : (const unsigned *)nullptr,
+                               tab);
+        };
+        if (ns <= 16) {
+            if (prec == CONKER_MM_SPLIT_F16) go(k_mm3s<CONKER_MM_SPLIT_F16>);
+            else go(k_mm3s<CONKER_MM_SPLIT_BF16>);
+        } else if (L.ntl == 1) {
+            if (prec == CONKER_MM_SPLIT_F16) go(k_mm3<1, CONKER_MM_SPLIT_F16>);
+            else go(k_mm3<1, CONKER_MM_SPLIT_BF16>);
+        } else {
+            if (prec == CONKER_MM_SPLIT_F16) go(k_mm3<2, CONKER_MM_SPLIT_F16>);
+            else go(k_mm3<2, CONKER_MM_SPLIT_BF16>);
+        }
+        CK_LAUNCH(c);
+    }
+    ProfScope ps(c, PK_CONTRACT_REDUCE);
+    const int te = 1024;
+    const int tiles = (int)nf * L.ntl;   // every field's tiles, one after the other
+    const size_t tot = (size_t)tiles * te;
+    double *slices = full + tot;
+    hipLaunchKernelGGL(k_tile_reduce1, dim3((unsigned)((tot * RED_S + 255) / 256)), dim3(256), 0, c->stream, part,
+                       tiles, L.G, te, slices);
+    CK_LAUNCH(c);
+    hipLaunchKernelGGL(k_tile_reduce2, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, c->stream, slices, tiles,
+                       te, full);
+    CK_LAUNCH(c);
+    hipLaunchKernelGGL(k_gather_jobs, dim3((unsigned)((pl.count + 255) / 256), nf), dim3(256), 0, c->stream,
+                       (const double *)full, (size_t)L.ntl * te, (const int *)pl.where->p, pl.count, tab);
+    CK_LAUNCH(c);
+    return CONKER_OK;
+}
+
+}  // namespace conker

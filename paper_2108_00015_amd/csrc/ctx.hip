@@ -254,6 +254,7 @@ extern "C" void conker_destroy(conker_ctx *c) {
     c->pool.clear();
     rel(c->spec);
     rel(c->tspec);
+    rel(c->cls);
     rel(c->partial);
     rel(c->full);
     rel(c->support);
@@ -362,6 +363,27 @@ __global__ void k_ratio(const double *Wd, const double *Wr, const double *alpha,
     for (int k = 0; k < n; ++k) an *= a;
     xi[i] = Wd[i] / (an * Wr[i]);
 }
+
+// Size classes: the ratio of every job of the table (job = blockIdx.y).
+__global__ void k_ratio_jobs(const ClassJob *__restrict__ tab, int n, int64_t count) {
+    const ClassJob &j = tab[blockIdx.y];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    double a = *j.alpha, an = 1.0;
+    for (int k = 0; k < n; ++k) an *= a;
+    j.xi[i] = j.Wd[i] / (an * j.Wr[i]);
+}
+
+namespace conker {
+int ratio_jobs(conker_ctx *c, int M, const ClassJob *tab, int n, int64_t count) {
+    if (count <= 0) return CONKER_OK;
+    ProfScope ps(c, PK_RATIO);
+    hipLaunchKernelGGL(k_ratio_jobs, dim3((unsigned)((count + 255) / 256), (unsigned)M), dim3(256), 0, c->stream,
+                       tab, n, count);
+    CK_LAUNCH(c);
+    return CONKER_OK;
+}
+}  // namespace conker
 
 extern "C" int conker_ratio(conker_ctx *c, const double *Wd, const double *Wr, const double *alpha,
                             int n, int64_t count, double *xi) {

@@ -399,8 +399,26 @@ __device__ __forceinline__ int fold(int k, int n) { return k <= n - k ? k : n - 
 constexpr int PS_T = 256;
 
 template <typename T, int PV>
+__device__ __forceinline__ void pack_sums_body(const T *__restrict__ a, const T *__restrict__ b, size_t n,
+                                               double *__restrict__ part);
+
+template <typename T, int PV>
 __global__ __launch_bounds__(PS_T) void k_pack_sums(const T *__restrict__ a, const T *__restrict__ b, size_t n,
                                                     double *__restrict__ part) {
+    pack_sums_body<T, PV>(a, b, n, part);
+}
+
+// The same for every job of a size class (job = blockIdx.y): partial pairs at
+// part + 2 (job * gridDim.x + workgroup).
+__global__ __launch_bounds__(PS_T) void k_pack_sums_jobs(const ClassJob *__restrict__ tab, size_t n,
+                                                         double *__restrict__ part) {
+    const ClassJob &j = tab[blockIdx.y];
+    pack_sums_body<float, 4>(j.N, j.R, n, part + 2 * (size_t)blockIdx.y * gridDim.x);
+}
+
+template <typename T, int PV>
+__device__ __forceinline__ void pack_sums_body(const T *__restrict__ a, const T *__restrict__ b, size_t n,
+                                               double *__restrict__ part) {
     __shared__ double red[PS_T / 64][2];
     double sa = 0.0, sb = 0.0;
     const size_t nv = n / PV, stride = (size_t)gridDim.x * PS_T;
@@ -451,6 +469,9 @@ __global__ __launch_bounds__(PS_T) void k_pack_sums(const T *__restrict__ a, con
 constexpr int PSR_T = 1024;   // threads of the one workgroup that adds the partials
 
 __global__ __launch_bounds__(PSR_T) void k_pack_scale(const double *__restrict__ part, int G, PackScale *out) {
+    // one workgroup per pair (size classes: one per job, partials G apart)
+    part += 2 * (size_t)blockIdx.x * G;
+    out += blockIdx.x;
     __shared__ double red[2][PSR_T];
     double sa = 0.0, sb = 0.0;
     for (int g = threadIdx.x; g < G; g += PSR_T) {
@@ -548,6 +569,37 @@ struct OpPack {
         if (mask && !mask[(size_t)g.p0 + c]) return;
         out[off(g, i, c)] = v;
     }
+};
+
+// z pass, forward, for every job of a size class (job = blockIdx.y): N_j + i s_j R_j -> spec[j].
+struct OpPackJobs {
+    static constexpr bool STAGED = false;
+    using C = float2;
+    const void *tw;
+    Dims d;
+    const ClassJob *tab;
+    C *spec;
+    size_t nc;
+    const PackScale *scales;
+    Tile g;
+    const float *a, *b;
+    C *out;
+    float sb;
+    template <int TC> __device__ void begin() {
+        g = make_tile(AX_Z, d, blockIdx.x, TC);
+        const ClassJob &j = tab[blockIdx.y];
+        a = j.N + g.base;
+        b = j.R + g.base;
+        out = spec + (size_t)blockIdx.y * nc + g.base;
+        sb = scales[blockIdx.y].sf;
+    }
+    __device__ int iters() const { return 1; }
+    __device__ void set_iter(int) {}
+    __device__ C load(int i, int c) const {
+        const unsigned k = off(g, i, c);
+        return C{a[k], b[k] * sb};
+    }
+    __device__ void store(int i, int c, C v) const { out[off(g, i, c)] = v; }
 };
 
 // With `xcount` and `mask` (y axis only): tiles of x-slabs without carrying
@@ -733,6 +785,42 @@ struct OpUnpack {
     }
 };
 
+// z pass, inverse, for every job of a size class: blockIdx.y = job * nb + slot;
+// tspec[job][slot] -> rows m0 + slot of the job's maps (R's times 1 / s_j).
+struct OpUnpackJobs {
+    static constexpr bool STAGED = false;
+    using C = float2;
+    const void *tw;
+    Dims d;
+    const float2 *tspec;
+    const ClassJob *tab;
+    const PackScale *scales;
+    size_t nc;
+    int m0, nb;
+    Tile g;
+    const C *src;
+    float *ma, *mb;
+    float sbi;
+    template <int TC> __device__ void begin() {
+        g = make_tile(AX_Z, d, blockIdx.x, TC);
+        const int job = blockIdx.y / nb, slot = blockIdx.y - job * nb;
+        const ClassJob &j = tab[job];
+        src = tspec + (size_t)blockIdx.y * nc + g.base;
+        const size_t o = (size_t)(m0 + slot) * nc + g.base;
+        ma = j.mapsN + o;
+        mb = j.mapsR + o;
+        sbi = scales[job].sf_inv;
+    }
+    __device__ int iters() const { return 1; }
+    __device__ void set_iter(int) {}
+    __device__ C load(int i, int c) const { return src[off(g, i, c)]; }
+    __device__ void store(int i, int c, C v) const {
+        const unsigned k = off(g, i, c);
+        ma[k] = v.x;
+        mb[k] = v.y * sbi;
+    }
+};
+
 // z pass, forward, of two shell indicators generated on the fly:
 // real part = [lo_a <= |delta|^2 < hi_a], imaginary part likewise for b,
 // with delta the minimum-image offset of the cell from cell (0, 0, 0).
@@ -853,6 +941,10 @@ __global__ __launch_bounds__((Shape<T, L, TM_R>::NT), (Shape<T, L, TM_R>::MINW))
     using SH = Shape<T, L, TM_R>;
     constexpr int TC = SH::TC, NT = SH::NT, NXH = L / 2 + 1;
     constexpr int KR = PAIR ? 2 : 1;                     // kernel rows per slot
+    // size classes: job blockIdx.y has its spectrum at spec + job nc and its
+    // nb slots at tspec + job nb nc (one job otherwise)
+    spec += (size_t)blockIdx.y * nc;
+    tspec += (size_t)blockIdx.y * nb * nc;
     constexpr int KPT = (KR * TC * NXH + NT - 1) / NT;   // kernel values staged per thread
     constexpr bool PP = PPW && !PAIR && pingpong_fits<T, L>();
     constexpr int PADR = PP ? 1 : SH::PAD, LDSN = L * (TC + PADR);
@@ -1350,6 +1442,38 @@ int zinv_diag_p(conker_ctx *ctx, const conker_grid *g, const void *tspec, int nb
     }
 }
 
+// Resident first inverse pass over M jobs of a size class (grid y = job).
+int xmul_resident_jobs(conker_ctx *ctx, const Dims &d, int M, const float2 *spec, const float *kspec,
+                       float2 *tspec, const void *twx, size_t nc, size_t kel, int m0, int nb, bool *done) {
+    *done = false;
+    auto go = [&](auto Lc) -> int {
+        constexpr int LL = decltype(Lc)::value;
+        if constexpr (resident_fits<float, LL>()) {
+            using SH = Shape<float, LL, TM_R>;
+            if (d.nz % SH::TC) return CONKER_OK;
+            ProfScope ps(ctx, PK_FFT_INV_X_MUL);
+            const dim3 grid((unsigned)((long)d.ny * d.nz / SH::TC), (unsigned)M);
+            hipLaunchKernelGGL((k_xmul_resident<float, LL, false, false>), grid, dim3(SH::NT), 0, ctx->stream,
+                               spec, kspec, tspec, (const float2 *)twx, d, nc, kel, m0, nb, (const int *)nullptr, 0);
+            CK_LAUNCH(ctx);
+            *done = true;
+        }
+        return CONKER_OK;
+    };
+    switch (d.nx) {
+        case 96: return go(std::integral_constant<int, 96>());
+        case 192: return go(std::integral_constant<int, 192>());
+        case 384: return go(std::integral_constant<int, 384>());
+        case 32: return go(std::integral_constant<int, 32>());
+        case 64: return go(std::integral_constant<int, 64>());
+        case 128: return go(std::integral_constant<int, 128>());
+        case 256: return go(std::integral_constant<int, 256>());
+        case 512: return go(std::integral_constant<int, 512>());
+        case 1024: return go(std::integral_constant<int, 1024>());
+        default: return CONKER_OK;
+    }
+}
+
 }  // namespace
 
 namespace conker {
@@ -1377,6 +1501,79 @@ int fft_inverse_batch(conker_ctx *ctx, const conker_grid *g, bool f64, const voi
                       const Support *sup, int pair_ns, bool sup_maps) {
     return f64 ? inverse_batch_t<double>(ctx, g, spec, kspec, m0, nb, tspec, maps_a, maps_b, sup, pair_ns, sup_maps)
                : inverse_batch_t<float>(ctx, g, spec, kspec, m0, nb, tspec, maps_a, maps_b, sup, pair_ns, sup_maps);
+}
+
+bool fft_jobs_ok(const conker_grid *g) {
+    const Dims d{g->dims[0], g->dims[1], g->dims[2]};
+    bool ok = false;
+    auto go = [&](auto Lc) {
+        constexpr int LL = decltype(Lc)::value;
+        if constexpr (resident_fits<float, LL>()) ok = d.nz % Shape<float, LL, TM_R>::TC == 0;
+    };
+    switch (d.nx) {
+        case 96: go(std::integral_constant<int, 96>()); break;
+        case 192: go(std::integral_constant<int, 192>()); break;
+        case 384: go(std::integral_constant<int, 384>()); break;
+        case 32: go(std::integral_constant<int, 32>()); break;
+        case 64: go(std::integral_constant<int, 64>()); break;
+        case 128: go(std::integral_constant<int, 128>()); break;
+        case 256: go(std::integral_constant<int, 256>()); break;
+        case 512: go(std::integral_constant<int, 512>()); break;
+        case 1024: go(std::integral_constant<int, 1024>()); break;
+        default: break;
+    }
+    return ok;
+}
+
+int fft_forward_jobs(conker_ctx *ctx, const conker_grid *g, int M, const ClassJob *tab, void *spec,
+                     PackScale *scales, double *part) {
+    Dims d{g->dims[0], g->dims[1], g->dims[2]};
+    const void *twz, *twy, *twx;
+    CK_OK(twiddles(ctx, d.nz, false, &twz));
+    CK_OK(twiddles(ctx, d.ny, false, &twy));
+    CK_OK(twiddles(ctx, d.nx, false, &twx));
+    const size_t nc = ncells(g);
+    {
+        ProfScope ps(ctx, PK_PACK_SCALE);
+        const int G = (int)std::max<size_t>(1, std::min<size_t>((size_t)4 * cu_count(ctx) / (size_t)M + 1,
+                                                                (nc / 4 + PS_T - 1) / PS_T));
+        hipLaunchKernelGGL(k_pack_sums_jobs, dim3((unsigned)G, (unsigned)M), dim3(PS_T), 0, ctx->stream, tab, nc,
+                           part);
+        CK_LAUNCH(ctx);
+        hipLaunchKernelGGL(k_pack_scale, dim3((unsigned)M), dim3(PSR_T), 0, ctx->stream, (const double *)part, G,
+                           scales);
+        CK_LAUNCH(ctx);
+    }
+    OpPackJobs pz{twz, d, tab, (float2 *)spec, nc, scales, {}, nullptr, nullptr, nullptr, 1.f};
+    CK_OK((launch_len<float, -1>(ctx, PK_FFT_FWD_Z, TM_J, d.nz, AX_Z, d, dim3(1, (unsigned)M), pz)));
+    OpInplace<float> py{twy, d, AX_Y, (float2 *)spec, nc, {}, nullptr, nullptr, nullptr};
+    CK_OK((launch_len<float, -1>(ctx, PK_FFT_FWD_Y, col_mode_for<float>(ctx, d, AX_Y), d.ny, AX_Y, d,
+                                 dim3(1, (unsigned)M), py)));
+    OpInplace<float> px{twx, d, AX_X, (float2 *)spec, nc, {}, nullptr, nullptr, nullptr};
+    CK_OK((launch_len<float, -1>(ctx, PK_FFT_FWD_X, col_mode_for<float>(ctx, d, AX_X), d.nx, AX_X, d,
+                                 dim3(1, (unsigned)M), px)));
+    return CONKER_OK;
+}
+
+int fft_inverse_jobs(conker_ctx *ctx, const conker_grid *g, int M, const ClassJob *tab, const void *kspec, int m0,
+                     int nb, const void *spec, void *tspec, const PackScale *scales) {
+    Dims d{g->dims[0], g->dims[1], g->dims[2]};
+    const void *twz, *twy, *twx;
+    CK_OK(twiddles(ctx, d.nz, false, &twz));
+    CK_OK(twiddles(ctx, d.ny, false, &twy));
+    CK_OK(twiddles(ctx, d.nx, false, &twx));
+    const size_t nc = ncells(g);
+    const size_t kel = (size_t)(d.nx / 2 + 1) * (d.ny / 2 + 1) * (d.nz / 2 + 1);
+    bool done = false;
+    CK_OK(xmul_resident_jobs(ctx, d, M, (const float2 *)spec, (const float *)kspec, (float2 *)tspec, twx, nc, kel,
+                             m0, nb, &done));
+    if (!done) return fail(ctx, CONKER_EUNSUPPORTED, "size class: no resident first inverse pass for this grid");
+    OpInplace<float> py{twy, d, AX_Y, (float2 *)tspec, nc, {}, nullptr, nullptr, nullptr};
+    CK_OK((launch_len<float, +1>(ctx, PK_FFT_INV_Y, col_mode_for<float>(ctx, d, AX_Y), d.ny, AX_Y, d,
+                                 dim3(1, (unsigned)(M * nb)), py)));
+    OpUnpackJobs pz{twz, d, (const float2 *)tspec, tab, scales, nc, m0, nb, {}, nullptr, nullptr, nullptr, 1.f};
+    CK_OK((launch_len<float, +1>(ctx, PK_FFT_INV_Z, TM_J, d.nz, AX_Z, d, dim3(1, (unsigned)(M * nb)), pz)));
+    return CONKER_OK;
 }
 
 int fft_shell_pair(conker_ctx *ctx, const conker_grid *g, double lo_a, double hi_a, double lo_b,

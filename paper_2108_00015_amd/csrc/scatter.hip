@@ -1,4 +1,5 @@
 // Mapping stage (Sec. 2.2): nearest-grid-point histograms and N = D - alpha R.
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <type_traits>
@@ -349,9 +350,122 @@ __global__ __launch_bounds__(256) void k_form_delta(T *__restrict__ D, const T *
     for (size_t i = done + t0; i < n; i += stride) D[i] = (T)((double)D[i] - alpha * (double)R[i]);
 }
 
+// Size classes (job table, float32 grids): blockIdx.y = 2 job + {0 data, 1
+// randoms}, each catalog into its own grid as k_scatter does.
+__global__ __launch_bounds__(256) void k_scatter_jobs(const conker::ClassJob *__restrict__ tab, GridGeom g) {
+    const conker::ClassJob &j = tab[blockIdx.y >> 1];
+    const bool r = blockIdx.y & 1;
+    const float *pos = r ? j.rpos : j.dpos;
+    const float *w = r ? j.rw : j.dw;
+    const int64_t n = r ? j.nr : j.nd;
+    float *grid = r ? j.R : j.N;
+    double *wsum = j.wsum + (r ? 1 : 0);
+    auto *n_out = reinterpret_cast<unsigned long long *>(j.nout + (r ? 1 : 0));
+    double my_w = 0.0;
+    unsigned long long my_out = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
+        const float x = pos[3 * p + 0], y = pos[3 * p + 1], z = pos[3 * p + 2];
+        const float wt = w ? w[p] : 1.0f;
+        bool ok = isfinite(x) && isfinite(y) && isfinite(z) && isfinite(wt);
+        const int cx = cell_of(x, g.ox, g.cell, g.nx, ok);
+        const int cy = cell_of(y, g.oy, g.cell, g.ny, ok);
+        const int cz = cell_of(z, g.oz, g.cell, g.nz, ok);
+        if (ok) {
+            atomic_add_grid<float>(grid + ((size_t)cx * g.ny + cy) * g.nz + cz, wt);
+            my_w += (double)wt;
+        } else {
+            ++my_out;
+        }
+    }
+    for (int o = 32; o >= 1; o >>= 1) {
+        my_w += __shfl_xor(my_w, o);
+        my_out += __shfl_xor(my_out, o);
+    }
+    __shared__ double sw[4];
+    __shared__ unsigned long long so[4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) {
+        sw[wv] = my_w;
+        so[wv] = my_out;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double tw = sw[0] + sw[1] + sw[2] + sw[3];
+        const unsigned long long to = so[0] + so[1] + so[2] + so[3];
+        if (tw != 0.0) unsafeAtomicAdd(wsum, tw);
+        if (to) atomicAdd(n_out, to);
+    }
+}
+
+// Size classes: zeroes both grids (16-byte stores), the weight sums and the
+// rejected counts of job blockIdx.y.
+__global__ __launch_bounds__(256) void k_zero_jobs(const conker::ClassJob *__restrict__ tab, size_t nc) {
+    const conker::ClassJob &j = tab[blockIdx.y];
+    const size_t t0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (size_t)gridDim.x * blockDim.x;
+    float4 *a = reinterpret_cast<float4 *>(j.N), *b = reinterpret_cast<float4 *>(j.R);
+    const float4 z{0.f, 0.f, 0.f, 0.f};
+    for (size_t i = t0; i < nc / 4; i += stride) {
+        a[i] = z;
+        b[i] = z;
+    }
+    if (t0 < 2) {
+        j.wsum[t0] = 0.0;
+        j.nout[t0] = 0;
+    }
+}
+
+// Size classes: N = D - alpha R of job blockIdx.y in place (as k_form_delta).
+__global__ __launch_bounds__(256) void k_form_delta_jobs(const conker::ClassJob *__restrict__ tab, size_t nc) {
+    const conker::ClassJob &j = tab[blockIdx.y];
+    const double alpha = j.wsum[0] / j.wsum[1];
+    const size_t t0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (size_t)gridDim.x * blockDim.x;
+    if (t0 == 0) *j.alpha = alpha;
+    float4 *D = reinterpret_cast<float4 *>(j.N);
+    const float4 *R = reinterpret_cast<const float4 *>(j.R);
+    for (size_t i = t0; i < nc / 4; i += stride) {
+        float4 d = D[i];
+        const float4 r = R[i];
+        d.x = (float)((double)d.x - alpha * (double)r.x);
+        d.y = (float)((double)d.y - alpha * (double)r.y);
+        d.z = (float)((double)d.z - alpha * (double)r.z);
+        d.w = (float)((double)d.w - alpha * (double)r.w);
+        D[i] = d;
+    }
+}
+
 }  // namespace
 
 using namespace conker;
+
+namespace conker {
+
+int64_t scatter_bin_min_points() { return BIN_MIN_POINTS; }
+
+int map_jobs(conker_ctx *c, const conker_grid *g, int M, const ClassJob *tab, int64_t n_max) {
+    const size_t nc = ncells(g);
+    if (nc % 4) return fail(c, CONKER_EINVAL, "size class: cell count must be a multiple of 4");
+    const GridGeom gg{g->origin[0], g->origin[1], g->origin[2], g->cell, g->dims[0], g->dims[1], g->dims[2]};
+    const size_t cap = (size_t)4 * cu_count(c);
+    const unsigned zb = (unsigned)std::max<size_t>(1, std::min<size_t>(cap / M + 1, (nc / 4 + 255) / 256));
+    {
+        ProfScope ps(c, PK_SCATTER);
+        hipLaunchKernelGGL(k_zero_jobs, dim3(zb, (unsigned)M), dim3(256), 0, c->stream, tab, nc);
+        CK_LAUNCH(c);
+        if (n_max > 0) {
+            const int64_t want = (n_max + 255) / 256;
+            const unsigned sb = (unsigned)std::min<int64_t>(want, std::max<int64_t>(64, 16384 / M));
+            hipLaunchKernelGGL(k_scatter_jobs, dim3(sb, 2u * (unsigned)M), dim3(256), 0, c->stream, tab, gg);
+            CK_LAUNCH(c);
+        }
+    }
+    ProfScope ps(c, PK_FORM_DELTA);
+    hipLaunchKernelGGL(k_form_delta_jobs, dim3(zb, (unsigned)M), dim3(256), 0, c->stream, tab, nc);
+    CK_LAUNCH(c);
+    return CONKER_OK;
+}
+
+}  // namespace conker
 
 extern "C" int conker_grid_assign(conker_ctx *c, const conker_grid *g, const float *pos,
                                   const float *w, int64_t n, conker_dtype dt, void *grid,

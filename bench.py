@@ -265,7 +265,8 @@ MOCKS_NAME = "mocks64_periodic_grid96-256_r16"
 
 def mock_stage_bytes(kind, sizes, ns, npts, nb=8):
     """Algorithmic HBM bytes of one kind of launch over a whole mock batch run as
-    size classes (float32 grids, every line carries field: periodic boxes)."""
+    size classes (float32 grids, every line carries field: periodic boxes; nb
+    radii transformed per batch)."""
     tot = 0.0
     for (g, _), n in zip(sizes, npts):
         nc = g ** 3
@@ -399,9 +400,10 @@ def bench_mocks(args):
             chunks.setdefault(ch, [g, 0])[1] += 1
     npj = [len(d) + len(r) for d, r in cats]
     stages, over_peak = {}, []
+    nb = ns if "fused_zinv_contract" in prof else 8   # the fused summation transforms every radius at once
     for kind, (launches, tot) in prof.items():
         ent = dict(launches=launches, ms=round(tot, 3), avg_launch_ms=tot / launches)
-        b = mock_stage_bytes(kind, sizes, ns, npj)
+        b = mock_stage_bytes(kind, sizes, ns, npj, nb)
         if b is not None:
             gbs = b / (tot * 1e-3) / 1e9
             if gbs > HBM_PEAK_GBS:

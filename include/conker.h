@@ -431,7 +431,11 @@ int conker_batch_launch(conker_ctx *ctx);
  * launch for all jobs of a chunk, the job taken from the launch grid.  The
  * results are those of the job-by-job path up to the order of float
  * additions (mapping atomics, partial sums).  Jobs with NULL maps keep their
- * maps in a workspace of the chunk; a chunk's workspace is bounded by 16 GiB
+ * maps in a workspace of the chunk, except where every job of the group has
+ * NULL maps, CONKER_MM_SPLIT_BF16, at most 16 radii and a z length of 32, 64,
+ * 96, 128, 192 or 256: there the last inverse pass and the summation run as
+ * one kernel that never stores the maps (all radii transformed at once).  A
+ * chunk's workspace is bounded by 16 GiB
  * (a class of large grids runs in several chunks) and is held by the context
  * until it is destroyed.  A group whose chunks would hold one job each, every
  * other job, and every job when the workspace cannot be allocated run job by

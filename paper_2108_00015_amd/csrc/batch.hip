@@ -85,20 +85,28 @@ constexpr int CLASS_NB = 8;
 size_t up256(size_t b) { return (b + 255) / 256 * 256; }
 
 struct ChunkLayout {
-    size_t spec, tspec, maps, scales, part, c3, bytes;
+    size_t spec, tspec, maps, scales, part, c3, full3, bytes;
 };
 
-ChunkLayout chunk_layout(conker_ctx *c, const conker_job &j0, int M, int nb, bool maps) {
+// fused: all n_radii spectra at once, no maps, partial tiles of the fused
+// summation; else nb spectra at once, maps of the jobs that give none.
+ChunkLayout chunk_layout(conker_ctx *c, const conker_job &j0, int M, int nb, bool maps, bool fused) {
     const size_t nc = ncells(&j0.grid);
     const int ns = j0.n_radii;
     ChunkLayout L;
     L.spec = 0;
     L.tspec = L.spec + up256((size_t)M * nc * 8);
-    L.maps = L.tspec + up256((size_t)M * nb * nc * 8);
-    L.scales = L.maps + (maps ? up256((size_t)M * 2 * ns * nc * 4) : 0);
+    L.maps = L.tspec + up256((size_t)M * (fused ? ns : nb) * nc * 8);
+    L.scales = L.maps + (maps && !fused ? up256((size_t)M * 2 * ns * nc * 4) : 0);
     L.part = L.scales + up256((size_t)M * sizeof(PackScale));
     L.c3 = L.part + up256(((size_t)4 * cu_count(c) + M) * 2 * sizeof(double));
-    L.bytes = L.c3 + up256(contract3_jobs_bytes(c, &j0.grid, M, ns));
+    if (fused) {
+        L.full3 = L.c3 + up256((size_t)2 * M * fft_mm3_jobs_blocks(c, M) * 1024 * sizeof(double));
+        L.bytes = L.full3 + up256((size_t)2 * M * 1024 * (64 + 1) * sizeof(double));
+    } else {
+        L.full3 = L.c3;
+        L.bytes = L.c3 + up256(contract3_jobs_bytes(c, &j0.grid, M, ns));
+    }
     return L;
 }
 
@@ -184,14 +192,18 @@ int plan_classes(conker_ctx *c) {
         }
         const conker_job &j0 = c->jobs[grp[0]];
         const int nb = std::min(j0.n_radii, CLASS_NB);
+        // maps wanted by no member, split bfloat16: the fused summation where the grid allows
+        bool fused = j0.prec == CONKER_MM_SPLIT_BF16 && fft_mm3_jobs_ok(&j0.grid, j0.n_radii);
+        for (int k : mem) fused = fused && c->jobs[k].d_maps_N == nullptr;
         // greedy chunks under the workspace bound
         std::vector<ClassChunk> mine;
         ClassChunk cur;
         cur.nb = nb;
+        cur.fused = fused;
         auto bytes_of = [&](const std::vector<int> &js) {
             bool maps = false;
             for (int k : js) maps = maps || c->jobs[k].d_maps_N == nullptr;
-            return chunk_layout(c, j0, (int)js.size(), nb, maps).bytes;
+            return chunk_layout(c, j0, (int)js.size(), nb, maps, fused).bytes;
         };
         for (int k : mem) {
             std::vector<int> t = cur.jobs;
@@ -206,7 +218,7 @@ int plan_classes(conker_ctx *c) {
         if (!cur.jobs.empty()) mine.push_back(cur);
         size_t most = 0;
         for (const auto &ch : mine) most = std::max(most, ch.jobs.size());
-        if (most < 2 || bytes_of({mine[0].jobs[0]}) > CLASS_WS) {   // nothing shared: job by job
+        if (mem.empty() || most < 2 || bytes_of({mine[0].jobs[0]}) > CLASS_WS) {   // nothing shared: job by job
             for (int k : mem) seq.push_back(k);
             continue;
         }
@@ -234,7 +246,7 @@ int plan_classes(conker_ctx *c) {
         const int M = (int)ch.jobs.size();
         bool maps = false;
         for (int k : ch.jobs) maps = maps || c->jobs[k].d_maps_N == nullptr;
-        const ChunkLayout L = chunk_layout(c, j0, M, ch.nb, maps);
+        const ChunkLayout L = chunk_layout(c, j0, M, ch.nb, maps, ch.fused);
         const size_t nc = ncells(&j0.grid), ns = j0.n_radii;
         char *ws = (char *)c->cls.p + c->cls_ws_off;
         std::vector<ClassJob> tab(M);
@@ -243,7 +255,9 @@ int plan_classes(conker_ctx *c) {
             ClassJob &t = tab[i];
             t.N = (float *)j.d_N;
             t.R = (float *)j.d_R;
-            if (j.d_maps_N) {
+            if (ch.fused) {
+                t.mapsN = t.mapsR = nullptr;
+            } else if (j.d_maps_N) {
                 t.mapsN = (float *)j.d_maps_N;
                 t.mapsR = (float *)j.d_maps_R;
             } else {
@@ -279,12 +293,19 @@ int run_chunk(conker_ctx *c, const ClassChunk &ch) {
         maps = maps || c->jobs[k].d_maps_N == nullptr;
         n_max = std::max({n_max, c->jobs[k].n_data, c->jobs[k].n_rand});
     }
-    const ChunkLayout L = chunk_layout(c, j0, M, ch.nb, maps);
+    const ChunkLayout L = chunk_layout(c, j0, M, ch.nb, maps, ch.fused);
     const ClassJob *tab = (const ClassJob *)((const char *)c->cls.p + ch.tab_off);
     char *ws = (char *)c->cls.p + c->cls_ws_off;
     PackScale *scales = (PackScale *)(ws + L.scales);
     CK_OK(map_jobs(c, &j0.grid, M, tab, n_max));
     CK_OK(fft_forward_jobs(c, &j0.grid, M, tab, ws + L.spec, scales, (double *)(ws + L.part)));
+    if (ch.fused) {
+        CK_OK(fft_inverse_mm3_jobs(c, &j0.grid, M, tab, j0.d_kspec, ns, ws + L.spec, ws + L.tspec, scales,
+                                   (double *)(ws + L.c3)));
+        CK_OK(reduce3_jobs(c, M, tab, ns, fft_mm3_jobs_blocks(c, M), (const double *)(ws + L.c3),
+                           (double *)(ws + L.full3)));
+        return ratio_jobs(c, M, tab, 3, conker_num_tuples(ns, 3));
+    }
     for (int m0 = 0; m0 < ns; m0 += ch.nb)
         CK_OK(fft_inverse_jobs(c, &j0.grid, M, tab, j0.d_kspec, m0, std::min(ch.nb, ns - m0), ws + L.spec,
                                ws + L.tspec, scales));

@@ -43,6 +43,7 @@ struct ClassChunk {
     std::vector<int> jobs;
     size_t tab_off = 0;
     int nb = 0;
+    bool fused = false;   // maps never stored: inverse z pass and summation in one kernel
 };
 
 }  // namespace conker
@@ -296,6 +297,19 @@ int map_jobs(conker_ctx *c, const conker_grid *g, int M, const ClassJob *tab, in
 int64_t scatter_bin_min_points();
 // xi of every job of the table (count tuples of order n).
 int ratio_jobs(conker_ctx *c, int M, const ClassJob *tab, int n, int64_t count);
+// Whether the fused inverse z pass + order-3 summation (k_zinv_mm3_jobs)
+// serves grid g with n_radii = ns (split bfloat16, maps never stored).
+bool fft_mm3_jobs_ok(const conker_grid *g, int ns);
+// Its workgroups per job (partial tiles: 2 M of them per workgroup column).
+int fft_mm3_jobs_blocks(conker_ctx *ctx, int M);
+// Inverse transforms of all ns radii of all M jobs (tspec: M ns spectra) and
+// the order-3 summation on the fly: partial[(2 job + field) G + workgroup]
+// 32 x 32 float64 tiles, G = fft_mm3_jobs_blocks.
+int fft_inverse_mm3_jobs(conker_ctx *ctx, const conker_grid *g, int M, const ClassJob *tab, const void *kspec, int ns,
+                         const void *spec, void *tspec, const PackScale *scales, double *partial);
+// The reduction and gather of W_delta and W_R of order 3 from such partials
+// (full: 2 M 1024 (RED_S + 1) doubles).
+int reduce3_jobs(conker_ctx *c, int M, const ClassJob *tab, int ns, int G, const double *partial, double *full);
 // W_delta and W_R of order 3 of all M jobs from their maps (split arithmetic,
 // n_radii <= 64), into tab[j].Wd / Wr.  ws: workspace of contract3_jobs_bytes.
 size_t contract3_jobs_bytes(conker_ctx *c, const conker_grid *g, int M, int ns);

@@ -31,6 +31,7 @@
 #include <type_traits>
 
 #include "common.h"
+#include "split3.h"
 
 using namespace conker;
 
@@ -343,19 +344,6 @@ __global__ __launch_bounds__(NT) void k_mm_f32(const float *__restrict__ F, cons
 #pragma unroll
         for (int v = 0; v < 16; ++v) a16[v] = accd[s][v] + (double)acc[s][v];
         wave_combine_store<32>(a16, lds, partial + ((size_t)tile * G + blockIdx.x) * (TS * TS));
-    }
-}
-
-__device__ __forceinline__ void split3(const float (&v)[8], bf16x8 &hi, bf16x8 &mi, bf16x8 &lo) {
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        const __bf16 h = (__bf16)v[e];
-        const float r1 = v[e] - (float)h;
-        const __bf16 m = (__bf16)r1;
-        const float r2 = r1 - (float)m;
-        hi[e] = h;
-        mi[e] = m;
-        lo[e] = (__bf16)r2;
     }
 }
 
@@ -1576,6 +1564,26 @@ namespace conker {
 
 size_t contract3_jobs_bytes(conker_ctx *c, const conker_grid *g, int M, int ns) {
     return jobs3_layout(c, ncells(g), M, ns).bytes;
+}
+
+int reduce3_jobs(conker_ctx *c, int M, const ClassJob *tab, int ns, int G, const double *part, double *full) {
+    Plan pl;
+    CK_OK(make_plan(c, ns, 3, 32, pl));
+    if (pl.n_tiles != 1) return fail(c, CONKER_EINVAL, "unexpected tile plan");
+    ProfScope ps(c, PK_CONTRACT_REDUCE);
+    const int te = 1024, tiles = 2 * M;
+    const size_t tot = (size_t)tiles * te;
+    double *slices = full + tot;
+    hipLaunchKernelGGL(k_tile_reduce1, dim3((unsigned)((tot * RED_S + 255) / 256)), dim3(256), 0, c->stream, part,
+                       tiles, G, te, slices);
+    CK_LAUNCH(c);
+    hipLaunchKernelGGL(k_tile_reduce2, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, c->stream, slices, tiles,
+                       te, full);
+    CK_LAUNCH(c);
+    hipLaunchKernelGGL(k_gather_jobs, dim3((unsigned)((pl.count + 255) / 256), (unsigned)tiles), dim3(256), 0,
+                       c->stream, (const double *)full, (size_t)te, (const int *)pl.where->p, pl.count, tab);
+    CK_LAUNCH(c);
+    return CONKER_OK;
 }
 
 int contract3_jobs(conker_ctx *c, const conker_grid *g, int M, const ClassJob *tab, int ns, conker_mmprec prec,

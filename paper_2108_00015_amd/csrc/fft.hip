@@ -22,6 +22,7 @@
 
 #include "common.h"
 #include "fft_math.h"
+#include "split3.h"
 
 using namespace conker;
 
@@ -118,6 +119,13 @@ template <class Op, class = void>
 struct has_load_r : std::false_type {};
 template <class Op>
 struct has_load_r<Op, std::void_t<decltype(std::declval<const Op &>().load_r(0, 0, 0, 0))>> : std::true_type {};
+
+// Ops with SYNC_LAST = true store the last stage's outputs into the tile's own
+// LDS: the stage then waits for every thread's reads before its stores.
+template <class Op, class = void>
+struct has_sync_last : std::false_type {};
+template <class Op>
+struct has_sync_last<Op, std::enable_if_t<Op::SYNC_LAST>> : std::true_type {};
 
 // TM_J tiles whose stages all give a line the same number of butterflies, a
 // divisor of 64 (512 = 8 8 8, 64 = 8 8): the threads of a line then lie in one
@@ -217,8 +225,10 @@ __device__ __forceinline__ void fft_stage(const cplx<T> *src, cplx<T> *dst, cons
     }
     // in-place LDS stages wait for every read before any write; the last stage
     // writes global memory from registers, and every caller puts a barrier
-    // between a tile's last stage and the next writes to the LDS tile
+    // between a tile's last stage and the next writes to the LDS tile (ops
+    // that store into that tile wait here)
     if constexpr (SYNC && !FIRST && !LAST) stage_sync<L, MODE>();
+    if constexpr (LAST && has_sync_last<Op>::value) __syncthreads();
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
         const int b = threadIdx.x + q * NT;
@@ -1152,6 +1162,150 @@ __global__ __launch_bounds__((Shape<T, L, TM_J>::NT), (Shape<T, L, TM_J>::MINW))
 }
 
 // ---------------------------------------------------------------------------
+// Size classes, n = 3, at most 16 radii: the inverse z pass and the summation
+// in one kernel, so that no map is written to memory (Eq. ksin_delta needs
+// only the sums).  A tile holds LPT = TC / 16 consecutive z-lines of one job
+// for 16 radius slots (tile column c = slot LPT + line).  Its transform
+// leaves C_m on the tile's cells in LDS (both packed fields; R's times
+// 1 / s_j), and the workgroup then sums F(x) C_a(x) C_b(x) over those cells
+// on the matrix cores, as k_mm3s does from stored maps: one 16 x 16 tile per
+// field, split bfloat16, 32 cells per instruction, lane (r, h) = (lane % 16,
+// lane / 16) holding cells 8 h .. 8 h + 7 of a 32-cell chunk for radius r.
+// Slots from n_radii on transform zeros.  Workgroups of job blockIdx.y take
+// tiles blockIdx.x, + gridDim.x, ...; each writes float64 partial tiles (the
+// 32 x 32 layout of the summation, zeros beyond 16 x 16) for N and R of its
+// job, which the summation's reduction adds in a fixed order.
+// ---------------------------------------------------------------------------
+template <int L>
+struct ZMM {
+    using SH = Shape<float, L, TM_J>;
+    static constexpr int RS = 16;                  // radius slots
+    static constexpr int TC = SH::TC;
+    static constexpr int LPT = TC / RS;            // grid lines per tile
+    static constexpr int CELLS = LPT * L;          // cells per tile
+    static constexpr int P = CELLS + 4;            // LDS row of one slot (floats), padded
+    static constexpr bool OK = TC >= RS && SH::NT == 256 && CELLS % 32 == 0;
+};
+
+template <int L>
+struct OpZinvMM {
+    static constexpr bool STAGED = false;
+    static constexpr bool SYNC_LAST = true;   // the maps take the transform tile's LDS
+    using C = float2;
+    static constexpr int LPT = ZMM<L>::LPT, P = ZMM<L>::P, RS = ZMM<L>::RS;
+    const float2 *src;   // slot 0 of the job's spectra, at the tile's first cell
+    size_t nc;
+    int ns;
+    float *maps;         // LDS [2][RS][P]
+    float sbi;
+    __device__ C load(int i, int c) const {
+        const int sl = c / LPT, l = c - sl * LPT;
+        if (sl >= ns) return C{0.f, 0.f};
+        return src[(size_t)sl * nc + (unsigned)(l * L + i)];
+    }
+    __device__ void store(int i, int c, C v) const {
+        const int sl = c / LPT, l = c - sl * LPT;
+        const int o = sl * P + l * L + i;
+        maps[o] = v.x;
+        maps[RS * P + o] = v.y * sbi;
+    }
+};
+
+template <int L>
+__global__ __launch_bounds__(256, 4) void k_zinv_mm3_jobs(const float2 *__restrict__ tspec,
+                                                         const ClassJob *__restrict__ tab,
+                                                         const PackScale *__restrict__ scales,
+                                                         const float2 *__restrict__ twg, Dims d, size_t nc, int ns,
+                                                         double *__restrict__ partial) {
+    using Z = ZMM<L>;
+    using SH = typename Z::SH;
+    constexpr int NT = 256, NWV = NT / 64, CELLS = Z::CELLS, P = Z::P, NCH = CELLS / 32;
+    constexpr int FPT = (2 * CELLS + NT - 1) / NT;   // field values staged per thread
+    static_assert(Z::OK, "tile shape");
+    static_assert(2 * 16 * P * sizeof(float) >= NWV * 8 * 64 * sizeof(double), "combine area");
+    // the maps of a tile (both fields, 16 slots) and its field values take the
+    // LDS of the transform tile once its last stage has read it
+    static_assert((2 * 16 * P + 2 * CELLS) * sizeof(float) <= SH::LDS * sizeof(float2), "maps in the tile's LDS");
+    __shared__ __align__(16) float2 lds[SH::LDS];
+    __shared__ float2 tw[L];
+    float *const maps = reinterpret_cast<float *>(lds);
+    float *const fl = maps + 2 * 16 * P;
+    const int job = blockIdx.y;
+    const ClassJob &jb = tab[job];
+    for (int t = threadIdx.x; t < L; t += NT) tw[t] = twg[t];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, r = lane & 15, h = lane >> 4;
+    const bool hm = r < ns;
+    floatx4_t acc0 = floatx4_t{0}, acc1 = floatx4_t{0};
+    double accd[2][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+    OpZinvMM<L> op;
+    op.nc = nc;
+    op.ns = ns;
+    op.maps = maps;
+    op.sbi = scales[job].sf_inv;
+    const float2 *jspec = tspec + (size_t)job * ns * nc;
+    const long ntiles = (long)d.nx * d.ny / Z::LPT;
+    for (long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const size_t cell0 = (size_t)tile * CELLS;   // the tile's lines are consecutive
+        float fv[FPT];
+#pragma unroll
+        for (int k = 0; k < FPT; ++k) {   // both fields on the tile's cells, loaded before the transform
+            const int idx = threadIdx.x + k * NT;
+            fv[k] = idx < CELLS ? jb.N[cell0 + idx] : (idx < 2 * CELLS ? jb.R[cell0 + idx - CELLS] : 0.f);
+        }
+        op.src = jspec + cell0;
+        __syncthreads();   // the previous tile is done with maps, fl and lds (twiddles in)
+        fft_line_tile<float, L, TM_J, +1, false>(lds, tw, op);
+#pragma unroll
+        for (int k = 0; k < FPT; ++k) {
+            const int idx = threadIdx.x + k * NT;
+            if (idx < 2 * CELLS) fl[idx] = fv[k];
+        }
+        __syncthreads();
+        for (int q = w; q < 2 * NCH; q += NWV) {   // (field, 32-cell chunk), the same for the whole wave
+            const int f = q >= NCH ? 1 : 0;
+            const int x0 = (q - f * NCH) * 32 + 8 * h;
+            const float *mp = maps + (f * 16 + r) * P + x0;
+            const float *fp = fl + f * CELLS + x0;
+            float a[8], b[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                b[e] = hm ? mp[e] : 0.f;
+                a[e] = fp[e] * b[e];
+            }
+            if (f == 0) mma16_split3(acc0, a, b);
+            else mma16_split3(acc1, a, b);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {   // float64 after every tile (at most 2 NCH / NWV chunks of 32 cells)
+            accd[0][v] += (double)acc0[v];
+            accd[1][v] += (double)acc1[v];
+        }
+        acc0 = floatx4_t{0};
+        acc1 = floatx4_t{0};
+    }
+    __syncthreads();
+    double *red = reinterpret_cast<double *>(maps);
+#pragma unroll
+    for (int f = 0; f < 2; ++f)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) red[((w * 2 + f) * 4 + v) * 64 + lane] = accd[f][v];
+    __syncthreads();
+    for (int f = 0; f < 2; ++f) {
+        double *out = partial + ((size_t)(job * 2 + f) * gridDim.x + blockIdx.x) * 1024;
+        for (int e = threadIdx.x; e < 1024; e += NT) {   // element (i, j): lane j + 16 (i / 4), register i % 4
+            const int i = e >> 5, j = e & 31;
+            double sum = 0.0;
+            if (i < 16 && j < 16) {
+                const int l = j + 16 * (i >> 2), v = i & 3;
+#pragma unroll
+                for (int q = 0; q < NWV; ++q) sum += red[((q * 2 + f) * 4 + v) * 64 + l];
+            }
+            out[e] = sum;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // launch helpers
 // ---------------------------------------------------------------------------
 template <typename T, int L>
@@ -1552,6 +1706,65 @@ int fft_forward_jobs(conker_ctx *ctx, const conker_grid *g, int M, const ClassJo
     OpInplace<float> px{twx, d, AX_X, (float2 *)spec, nc, {}, nullptr, nullptr, nullptr};
     CK_OK((launch_len<float, -1>(ctx, PK_FFT_FWD_X, col_mode_for<float>(ctx, d, AX_X), d.nx, AX_X, d,
                                  dim3(1, (unsigned)M), px)));
+    return CONKER_OK;
+}
+
+bool fft_mm3_jobs_ok(const conker_grid *g, int ns) {
+    if (ns < 1 || ns > 16) return false;
+    bool ok = false;
+    auto go = [&](auto Lc) {
+        constexpr int LL = decltype(Lc)::value;
+        if constexpr (ZMM<LL>::OK) ok = ((long)g->dims[0] * g->dims[1]) % ZMM<LL>::LPT == 0;
+    };
+    switch (g->dims[2]) {
+        case 32: go(std::integral_constant<int, 32>()); break;
+        case 64: go(std::integral_constant<int, 64>()); break;
+        case 96: go(std::integral_constant<int, 96>()); break;
+        case 128: go(std::integral_constant<int, 128>()); break;
+        case 192: go(std::integral_constant<int, 192>()); break;
+        case 256: go(std::integral_constant<int, 256>()); break;
+        default: break;
+    }
+    return ok && fft_jobs_ok(g);
+}
+
+int fft_mm3_jobs_blocks(conker_ctx *ctx, int M) { return std::max(1, 4 * cu_count(ctx) / M); }   // four workgroups per CU
+
+int fft_inverse_mm3_jobs(conker_ctx *ctx, const conker_grid *g, int M, const ClassJob *tab, const void *kspec, int ns,
+                         const void *spec, void *tspec, const PackScale *scales, double *partial) {
+    if (!fft_mm3_jobs_ok(g, ns)) return fail(ctx, CONKER_EUNSUPPORTED, "size class: no fused summation for this grid");
+    Dims d{g->dims[0], g->dims[1], g->dims[2]};
+    const void *twz, *twy, *twx;
+    CK_OK(twiddles(ctx, d.nz, false, &twz));
+    CK_OK(twiddles(ctx, d.ny, false, &twy));
+    CK_OK(twiddles(ctx, d.nx, false, &twx));
+    const size_t nc = ncells(g);
+    const size_t kel = (size_t)(d.nx / 2 + 1) * (d.ny / 2 + 1) * (d.nz / 2 + 1);
+    bool done = false;
+    CK_OK(xmul_resident_jobs(ctx, d, M, (const float2 *)spec, (const float *)kspec, (float2 *)tspec, twx, nc, kel, 0,
+                             ns, &done));
+    if (!done) return fail(ctx, CONKER_EUNSUPPORTED, "size class: no resident first inverse pass for this grid");
+    OpInplace<float> py{twy, d, AX_Y, (float2 *)tspec, nc, {}, nullptr, nullptr, nullptr};
+    CK_OK((launch_len<float, +1>(ctx, PK_FFT_INV_Y, col_mode_for<float>(ctx, d, AX_Y), d.ny, AX_Y, d,
+                                 dim3(1, (unsigned)(M * ns)), py)));
+    const int G = fft_mm3_jobs_blocks(ctx, M);
+    ProfScope ps(ctx, PK_FUSED_ZC);
+    auto go = [&](auto Lc) {
+        constexpr int LL = decltype(Lc)::value;
+        if constexpr (ZMM<LL>::OK)
+            hipLaunchKernelGGL(k_zinv_mm3_jobs<LL>, dim3((unsigned)G, (unsigned)M), dim3(256), 0, ctx->stream,
+                               (const float2 *)tspec, tab, scales, (const float2 *)twz, d, nc, ns, partial);
+    };
+    switch (d.nz) {
+        case 32: go(std::integral_constant<int, 32>()); break;
+        case 64: go(std::integral_constant<int, 64>()); break;
+        case 96: go(std::integral_constant<int, 96>()); break;
+        case 128: go(std::integral_constant<int, 128>()); break;
+        case 192: go(std::integral_constant<int, 192>()); break;
+        case 256: go(std::integral_constant<int, 256>()); break;
+        default: break;
+    }
+    CK_LAUNCH(ctx);
     return CONKER_OK;
 }
 

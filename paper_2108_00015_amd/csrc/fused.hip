@@ -20,6 +20,7 @@
 #include <cstdlib>
 
 #include "common.h"
+#include "split3.h"
 #include "fft_math.h"
 
 using namespace conker;
@@ -46,19 +47,6 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-__device__ __forceinline__ void split3(const float (&v)[8], bf16x8 &hi, bf16x8 &mi, bf16x8 &lo) {
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        const __bf16 h = (__bf16)v[e];
-        const float r1 = v[e] - (float)h;
-        const __bf16 m = (__bf16)r1;
-        const float r2 = r1 - (float)m;
-        hi[e] = h;
-        mi[e] = m;
-        lo[e] = (__bf16)r2;
-    }
 }
 
 // acc += A^T B over the 16 cells of one chunk: lane (row r, half h) holds the

@@ -421,11 +421,12 @@ int conker_batch_launch(conker_ctx *ctx);
  * by one, a small grid leaves most of the device idle in every stage.  So
  * conker_batch_plan groups the jobs that share the grid (dimensions, origin,
  * cell), the kernel bank pointer and n_radii (at most 64), with dtype float32,
- * n = 3, split summation (CONKER_MM_SPLIT_BF16 or _F16), both catalogs below
- * 2^22 points, 16-byte aligned grids, a grid whose cell count is a multiple
- * of 64 and whose x length has a resident first inverse pass, and buffers
- * (grids, maps, outputs) that no other job of the group touches.  Such a group
- * runs in chunks: every stage of the path (zeroing and mapping, N = D -
+ * n = 3, split summation (CONKER_MM_SPLIT_BF16 or _F16), 16-byte aligned
+ * grids, a grid whose cell count is a multiple of 64 and whose x length has a
+ * resident first inverse pass, and buffers (grids, maps, outputs) that no
+ * other job of the group touches.  Such a group runs in chunks: every stage
+ * of the path (mapping, binned by brick as for large catalogs where the grid
+ * splits into bricks of 16 x 16 x 32 cells, else zeroing and atomics, N = D -
  * alpha R, the packed forward transform, the inverse transforms in radius
  * batches of 8, the order-3 summation from stored maps, the ratio) is one
  * launch for all jobs of a chunk, the job taken from the launch grid.  The
@@ -439,9 +440,8 @@ int conker_batch_launch(conker_ctx *ctx);
  * (a class of large grids runs in several chunks) and is held by the context
  * until it is destroyed.  A group whose chunks would hold one job each, every
  * other job, and every job when the workspace cannot be allocated run job by
- * job.  Chunks run first, then the other jobs in order; conker_batch_autotune
- * tunes only the latter (a job of a chunk reports the context setting and
- * its chunk's time divided by its number of jobs).
+ * job.  Chunks run first, then the other jobs in order (see
+ * conker_batch_autotune for how chunks are tuned).
  * conker_batch_classes: on != 0 (the default) enables the grouping for later
  *   conker_batch_plan calls on the context; 0 runs every job alone.
  * conker_batch_layout: for each planned job, the index of the chunk it runs
@@ -483,6 +483,13 @@ int conker_batch_layout(const conker_ctx *ctx, int *h_chunk);
  *                   summation); 0 (default) chosen on the device from the
  *                   support.  Other than 1, the fields are copied into the
  *                   permuted layout in workspace.
+ *   radix           radix schedule of the float32 transform passes (not the
+ *                   resident first inverse pass): 1 radix 8 first (32 = 8 4,
+ *                   64 = 8 8, 128 = 8 4 4, 256 = 8 8 4, 512 = 8 8 8,
+ *                   1024 = 8 8 4 4, 96 = 8 4 3, 192 = 8 8 3, 384 = 8 8 2 3),
+ *                   2 radix 16 first where that saves a stage (64 = 16 4,
+ *                   128 = 16 8, 256 = 16 16, 1024 = 16 16 4; other lengths
+ *                   as 1).  Default: 1.
  *   ms              conker_batch_autotune only: the measured time of one run
  *                   of the job with this setting (milliseconds).
  * conker_set_tune: the setting used by every later call on the context
@@ -495,6 +502,7 @@ typedef struct {
     int32_t mm_kernel;
     int32_t radius_batch;
     int32_t axis_order;
+    int32_t radix;
     float ms;
 } conker_tune;
 
@@ -511,10 +519,16 @@ int conker_axis_order_used(conker_ctx *ctx, int *h_order);
  * fused or not) by timing the first job of that shape with HIP events: start
  * from the defaults and, one field at a time, keep the alternative that is
  * faster than the best so far (the minimum of `reps` timed runs, 1..16, after
- * one untimed run per candidate).  Later conker_batch_run /
- * conker_batch_capture use the chosen settings job by job; the jobs' outputs
- * are recomputed with them before returning.  h_chosen (or NULL) receives
- * n_jobs settings with their times.  Synchronous. */
+ * one untimed run per candidate).  The fields searched: the column tiles, the
+ * resident first pass, the summation kernel (n >= 3 from maps), the axis
+ * order (map-free, cubic grids), the radius batch, and the radix schedule
+ * (float32 grids with an axis of 64, 128, 256 or 1024).  Each chunk of a size
+ * class is tuned as a whole over the column tiles and the radix schedule (its
+ * jobs report the chunk's setting and the chunk's time divided by its number
+ * of jobs).  Later conker_batch_run / conker_batch_capture use the chosen
+ * settings; the jobs' outputs are recomputed with them before returning.
+ * h_chosen (or NULL) receives n_jobs settings with their times.
+ * Synchronous. */
 int conker_batch_autotune(conker_ctx *ctx, int reps, conker_tune *h_chosen);
 
 /* Blocks until all work queued on the context's stream has finished. */

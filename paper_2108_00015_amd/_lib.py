@@ -101,7 +101,7 @@ class ConkerCosmology(ct.Structure):
 class ConkerTune(ct.Structure):
     _fields_ = [("x_tile", ct.c_int32), ("y_tile", ct.c_int32), ("x_resident", ct.c_int32),
                 ("mm_kernel", ct.c_int32), ("radius_batch", ct.c_int32), ("axis_order", ct.c_int32),
-                ("ms", ct.c_float)]
+                ("radix", ct.c_int32), ("ms", ct.c_float)]
 
 
 class ConkerJob(ct.Structure):

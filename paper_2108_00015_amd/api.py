@@ -38,7 +38,7 @@ def _check_outside(nout: torch.Tensor, allow_outside: bool):
                           "(pass allow_outside=True to drop them)" % cnt)
 
 
-TUNE_FIELDS = ("x_tile", "y_tile", "x_resident", "mm_kernel", "radius_batch", "axis_order")
+TUNE_FIELDS = ("x_tile", "y_tile", "x_resident", "mm_kernel", "radius_batch", "axis_order", "radix")
 
 
 def _tune_dict(t) -> dict:
@@ -430,7 +430,8 @@ class Context:
         x_resident (1 streamed, 2 resident with two LDS exchange buffers where
         they fit, 3 resident with one), mm_kernel (1 per-wave tiles,
         2 operand sharing, 3 n = 3 every tile per wave), radius_batch, axis_order (1 as given, 2..6 the
-        other permutations of a cubic grid, see conker.h); 0 or omitted = default."""
+        other permutations of a cubic grid, see conker.h), radix (1 radix-8-first schedules, 2 radix 16
+        first where that saves a stage); 0 or omitted = default."""
         bad = set(fields) - set(TUNE_FIELDS)
         if bad:
             raise ValueError("unknown launch setting(s): %s" % sorted(bad))

@@ -34,6 +34,15 @@ int zero_bytes(conker_ctx *c, void *p, size_t bytes) {
     return CONKER_OK;
 }
 
+// Whether an axis of the grid has a second radix schedule (conker_tune::radix).
+bool has_alt_radix(const conker_grid &g) {
+    for (int a = 0; a < 3; ++a) {
+        const int L = g.dims[a];
+        if (L == 64 || L == 128 || L == 256 || L == 1024) return true;
+    }
+    return false;
+}
+
 bool fused_ok(const conker_job &j) {
     return j.dtype == CONKER_F32 && (j.prec == CONKER_MM_F32 || j.prec == CONKER_MM_SPLIT_BF16) &&
            (j.n == 2 || j.n == 3) && j.grid.dims[2] == 512 && j.n_radii >= 1 && j.n_radii <= 30;
@@ -68,13 +77,14 @@ int run_job(conker_ctx *c, const conker_job &j) {
 // ---------------------------------------------------------------------------
 // Size classes.  Jobs on one grid (dimensions, origin and cell), with one
 // kernel bank and number of radii (at most 64), float32, order 3, split
-// summation, catalogs below the binned mapping's size, and buffers that no
-// other job of the class touches, run stage by stage: each stage is one
-// launch for a chunk of such jobs, the job in the grid's y (or z) index and
-// its buffers in a device table (ClassJob).  The stages are those of the
-// job-by-job path (direct mapping, packed forward transform, resident first
-// inverse pass, radii in batches of CLASS_NB, matrix-core summation from
-// stored maps).  A chunk's workspace (spectra, radius-batch spectra, the maps
+// summation, and buffers that no other job of the class touches, run stage
+// by stage: each stage is one launch for a chunk of such jobs, the job in the
+// grid's y (or z) index and its buffers in a device table (ClassJob).  The
+// stages are those of the job-by-job path (mapping binned by brick where the
+// grid splits into bricks, packed forward transform, resident first inverse
+// pass, radii in batches of CLASS_NB, matrix-core summation from stored
+// maps, or the last inverse pass and the summation fused where no job wants
+// its maps).  A chunk's workspace (spectra, radius-batch spectra, the maps
 // of jobs that give none, scales, partial sums) is at most CLASS_WS bytes, so
 // a class of large grids runs in several chunks; a class whose chunks would
 // hold one job each, and every other job, runs job by job.
@@ -85,12 +95,19 @@ constexpr int CLASS_NB = 8;
 size_t up256(size_t b) { return (b + 255) / 256 * 256; }
 
 struct ChunkLayout {
-    size_t spec, tspec, maps, scales, part, c3, full3, bytes;
+    size_t spec, tspec, maps, scales, part, c3, full3, bins, bytes;
 };
+
+int64_t points_of(const conker_ctx *c, const std::vector<int> &js) {
+    int64_t n = 0;
+    for (int k : js) n += c->jobs[k].n_data + c->jobs[k].n_rand;
+    return n;
+}
 
 // fused: all n_radii spectra at once, no maps, partial tiles of the fused
 // summation; else nb spectra at once, maps of the jobs that give none.
-ChunkLayout chunk_layout(conker_ctx *c, const conker_job &j0, int M, int nb, bool maps, bool fused) {
+ChunkLayout chunk_layout(conker_ctx *c, const conker_job &j0, int M, int nb, bool maps, bool fused,
+                         int64_t n_total) {
     const size_t nc = ncells(&j0.grid);
     const int ns = j0.n_radii;
     ChunkLayout L;
@@ -107,15 +124,16 @@ ChunkLayout chunk_layout(conker_ctx *c, const conker_job &j0, int M, int nb, boo
         L.full3 = L.c3;
         L.bytes = L.c3 + up256(contract3_jobs_bytes(c, &j0.grid, M, ns));
     }
+    L.bins = L.bytes;   // binned mapping (none where the grid does not split into its bricks)
+    L.bytes += up256(map_jobs_bytes(&j0.grid, M, n_total));
     return L;
 }
 
 bool class_ok(const conker_job &j) {
-    const int64_t big = scatter_bin_min_points();
     const size_t nc = ncells(&j.grid);
     const bool aligned = (((uintptr_t)j.d_N | (uintptr_t)j.d_R) & 15) == 0;
     return j.dtype == CONKER_F32 && j.n == 3 && (j.prec == CONKER_MM_SPLIT_BF16 || j.prec == CONKER_MM_SPLIT_F16) &&
-           j.n_radii <= 64 && j.n_data < big && j.n_rand < big && nc % 64 == 0 && aligned && fft_jobs_ok(&j.grid);
+           j.n_radii <= 64 && nc % 64 == 0 && aligned && fft_jobs_ok(&j.grid);
 }
 
 // Device byte ranges a job writes or owns (grids, maps, outputs).
@@ -203,7 +221,7 @@ int plan_classes(conker_ctx *c) {
         auto bytes_of = [&](const std::vector<int> &js) {
             bool maps = false;
             for (int k : js) maps = maps || c->jobs[k].d_maps_N == nullptr;
-            return chunk_layout(c, j0, (int)js.size(), nb, maps, fused).bytes;
+            return chunk_layout(c, j0, (int)js.size(), nb, maps, fused, points_of(c, js)).bytes;
         };
         for (int k : mem) {
             std::vector<int> t = cur.jobs;
@@ -246,10 +264,11 @@ int plan_classes(conker_ctx *c) {
         const int M = (int)ch.jobs.size();
         bool maps = false;
         for (int k : ch.jobs) maps = maps || c->jobs[k].d_maps_N == nullptr;
-        const ChunkLayout L = chunk_layout(c, j0, M, ch.nb, maps, ch.fused);
+        const ChunkLayout L = chunk_layout(c, j0, M, ch.nb, maps, ch.fused, points_of(c, ch.jobs));
         const size_t nc = ncells(&j0.grid), ns = j0.n_radii;
         char *ws = (char *)c->cls.p + c->cls_ws_off;
         std::vector<ClassJob> tab(M);
+        int64_t ioff = 0;
         for (int i = 0; i < M; ++i) {
             const conker_job &j = c->jobs[ch.jobs[i]];
             ClassJob &t = tab[i];
@@ -270,6 +289,10 @@ int plan_classes(conker_ctx *c) {
             t.rw = j.d_rand_w;
             t.nd = j.n_data;
             t.nr = j.n_rand;
+            t.ioff_d = ioff;
+            ioff += j.n_data;
+            t.ioff_r = ioff;
+            ioff += j.n_rand;
             t.wsum = j.d_wsum;
             t.nout = (long long *)j.d_n_outside;
             t.alpha = j.d_alpha;
@@ -293,11 +316,12 @@ int run_chunk(conker_ctx *c, const ClassChunk &ch) {
         maps = maps || c->jobs[k].d_maps_N == nullptr;
         n_max = std::max({n_max, c->jobs[k].n_data, c->jobs[k].n_rand});
     }
-    const ChunkLayout L = chunk_layout(c, j0, M, ch.nb, maps, ch.fused);
+    const int64_t n_total = points_of(c, ch.jobs);
+    const ChunkLayout L = chunk_layout(c, j0, M, ch.nb, maps, ch.fused, n_total);
     const ClassJob *tab = (const ClassJob *)((const char *)c->cls.p + ch.tab_off);
     char *ws = (char *)c->cls.p + c->cls_ws_off;
     PackScale *scales = (PackScale *)(ws + L.scales);
-    CK_OK(map_jobs(c, &j0.grid, M, tab, n_max));
+    CK_OK(map_jobs(c, &j0.grid, M, tab, n_max, n_total, L.bytes > L.bins ? ws + L.bins : nullptr));
     CK_OK(fft_forward_jobs(c, &j0.grid, M, tab, ws + L.spec, scales, (double *)(ws + L.part)));
     if (ch.fused) {
         CK_OK(fft_inverse_mm3_jobs(c, &j0.grid, M, tab, j0.d_kspec, ns, ws + L.spec, ws + L.tspec, scales,
@@ -326,7 +350,7 @@ const conker_tune &tune_of(const conker_ctx *c, size_t k) {
 
 int run_all(conker_ctx *c) {
     for (const auto &ch : c->chunks) {
-        TuneScope ts(c, c->user_tune);
+        TuneScope ts(c, ch.tuned ? ch.tune : c->user_tune);
         CK_OK(run_chunk(c, ch));
     }
     for (int k : c->seq_jobs) {
@@ -339,7 +363,7 @@ int run_all(conker_ctx *c) {
 bool tune_ok(const conker_tune &t) {
     auto in = [](int v, int lo, int hi) { return v >= lo && v <= hi; };
     return in(t.x_tile, 0, 2) && in(t.y_tile, 0, 2) && in(t.x_resident, 0, 3) && in(t.mm_kernel, 0, 3) &&
-           in(t.radius_batch, 0, 64) && in(t.axis_order, 0, 6);
+           in(t.radius_batch, 0, 64) && in(t.axis_order, 0, 6) && in(t.radix, 0, 2);
 }
 
 // Shortest of `reps` timed runs of job j with setting t (after one untimed run
@@ -392,6 +416,7 @@ int tune_job(conker_ctx *c, const conker_job &j, int reps, hipEvent_t e0, hipEve
                          (j.n == 3 && j.prec != CONKER_MM_F32) ? std::vector<int>{1, 2, 3} : std::vector<int>{1, 2}});
     if (nomaps && j.grid.dims[0] == j.grid.dims[1] && j.grid.dims[1] == j.grid.dims[2])
         knobs.push_back({&conker_tune::axis_order, {1}});   // the given order against the chosen one
+    if (j.dtype == CONKER_F32 && has_alt_radix(j.grid)) knobs.push_back({&conker_tune::radix, {2}});
     if (!fused && slots >= 4) {
         std::vector<int> rb = {(slots + 1) / 2};
         if (slots >= 8) rb.push_back((slots + 3) / 4);
@@ -412,6 +437,67 @@ int tune_job(conker_ctx *c, const conker_job &j, int reps, hipEvent_t e0, hipEve
         }
     }
     if (!(best_ms < 1.0e38f)) return fail(c, CONKER_ENOMEM, "no launch setting of the job fits in memory");
+    best.ms = best_ms;
+    *out = best;
+    return CONKER_OK;
+}
+
+// Time of one run of a chunk with setting t (the minimum of reps after one
+// untimed run); infinity where it fails for lack of memory.
+int time_chunk(conker_ctx *c, const ClassChunk &ch, const conker_tune &t, int reps, hipEvent_t e0, hipEvent_t e1,
+               float *ms) {
+    TuneScope ts(c, t);
+    int st = run_chunk(c, ch);
+    if (st == CONKER_ENOMEM) {
+        (void)hipGetLastError();
+        CK_HIP(c, hipStreamSynchronize(c->stream));
+        c->err.clear();
+        *ms = 3.0e38f;
+        return CONKER_OK;
+    }
+    CK_OK(st);
+    float best = 3.0e38f;
+    for (int r = 0; r < reps; ++r) {
+        CK_HIP(c, hipEventRecord(e0, c->stream));
+        CK_OK(run_chunk(c, ch));
+        CK_HIP(c, hipEventRecord(e1, c->stream));
+        CK_HIP(c, hipEventSynchronize(e1));
+        float v = 0.f;
+        CK_HIP(c, hipEventElapsedTime(&v, e0, e1));
+        best = std::min(best, v);
+    }
+    *ms = best;
+    return CONKER_OK;
+}
+
+// A chunk's sweep, as tune_job's: the tiles of the column passes and the
+// radix schedule (the other fields do not apply to the class stages).
+int tune_chunk(conker_ctx *c, const ClassChunk &ch, int reps, hipEvent_t e0, hipEvent_t e1, conker_tune *out) {
+    const conker_job &j0 = c->jobs[ch.jobs[0]];
+    conker_tune best = c->user_tune;
+    float best_ms;
+    CK_OK(time_chunk(c, ch, best, reps, e0, e1, &best_ms));
+    struct Knob {
+        int32_t conker_tune::*field;
+        std::vector<int> alt;
+    };
+    std::vector<Knob> knobs = {{&conker_tune::y_tile, {1, 2}}, {&conker_tune::x_tile, {1, 2}}};
+    if (has_alt_radix(j0.grid)) knobs.push_back({&conker_tune::radix, {2}});
+    for (const auto &k : knobs) {
+        const int start = best.*(k.field);
+        for (int v : k.alt) {
+            if (v == start) continue;
+            conker_tune cand = best;
+            cand.*(k.field) = v;
+            float ms;
+            CK_OK(time_chunk(c, ch, cand, reps, e0, e1, &ms));
+            if (ms < 0.99f * best_ms) {
+                best = cand;
+                best_ms = ms;
+            }
+        }
+    }
+    if (!(best_ms < 1.0e38f)) return fail(c, CONKER_ENOMEM, "no launch setting of the chunk fits in memory");
     best.ms = best_ms;
     *out = best;
     return CONKER_OK;
@@ -524,7 +610,8 @@ extern "C" int conker_set_tune(conker_ctx *c, const conker_tune *t) {
     v.ms = 0.f;
     if (!tune_ok(v))
         return fail(c, CONKER_EINVAL,
-                    "launch setting out of range (tiles 0..2, resident 0..3, kernel 0..3; radius batch 0..64; axis order 0..6)");
+                    "launch setting out of range (tiles 0..2, resident 0..3, kernel 0..3; radius batch 0..64; axis order "
+                    "0..6; radix 0..2)");
     c->user_tune = v;
     c->tune = v;
     return CONKER_OK;
@@ -554,17 +641,18 @@ extern "C" int conker_batch_autotune(conker_ctx *c, int reps, conker_tune *h_cho
     using Key = std::tuple<int, int, int, int, int, int, int, bool>;
     std::map<Key, conker_tune> seen;
     std::vector<conker_tune> chosen(c->jobs.size(), c->user_tune);
-    for (const auto &ch : c->chunks) {   // size classes keep the context setting: their time per job
+    for (auto &ch : c->chunks) {   // a chunk's setting, reported for each of its jobs with the time per job
+        ch.tuned = false;
         if (st != CONKER_OK) break;
-        float ms = 3.0e38f;
-        for (int r = 0; r <= reps && st == CONKER_OK; ++r) {   // the first run untimed
-            st = hipEventRecord(e0, c->stream) == hipSuccess ? run_chunk(c, ch) : CONKER_EHIP;
-            if (st == CONKER_OK && (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
-                st = fail(c, CONKER_EHIP, "event timing failed");
-            float v = 0.f;
-            if (st == CONKER_OK && r > 0 && hipEventElapsedTime(&v, e0, e1) == hipSuccess) ms = std::min(ms, v);
+        conker_tune t;
+        st = tune_chunk(c, ch, reps, e0, e1, &t);
+        if (st != CONKER_OK) break;
+        ch.tune = t;
+        ch.tuned = true;
+        for (int k : ch.jobs) {
+            chosen[k] = t;
+            chosen[k].ms = t.ms / (float)ch.jobs.size();
         }
-        for (int k : ch.jobs) chosen[k].ms = ms / (float)ch.jobs.size();
     }
     for (size_t q = 0; q < c->seq_jobs.size() && st == CONKER_OK; ++q) {
         const size_t k = (size_t)c->seq_jobs[q];
@@ -585,6 +673,7 @@ extern "C" int conker_batch_autotune(conker_ctx *c, int reps, conker_tune *h_cho
     c->tune = c->user_tune;
     if (st != CONKER_OK) {
         c->job_tune.clear();
+        for (auto &ch : c->chunks) ch.tuned = false;
         return st;
     }
     c->job_tune = chosen;

@@ -44,6 +44,8 @@ struct ClassChunk {
     size_t tab_off = 0;
     int nb = 0;
     bool fused = false;   // maps never stored: inverse z pass and summation in one kernel
+    bool tuned = false;   // conker_batch_autotune chose `tune` for the chunk
+    conker_tune tune{};
 };
 
 }  // namespace conker
@@ -273,6 +275,7 @@ struct ClassJob {
     float *N, *R, *mapsN, *mapsR;
     const float *dpos, *dw, *rpos, *rw;
     long long nd, nr;
+    long long ioff_d, ioff_r;  // binned mapping: offsets of the catalogs' placed points
     double *wsum;              // [2]
     long long *nout;           // [2]
     double *alpha;             // [1]
@@ -290,11 +293,14 @@ int fft_inverse_jobs(conker_ctx *c, const conker_grid *g, int M, const ClassJob 
 // Whether the size-class transforms support grid g (float32): a resident
 // first inverse pass exists for its x length and fits its z length.
 bool fft_jobs_ok(const conker_grid *g);
-// Zeroes, maps and forms N = D - alpha R for all M jobs (direct mapping with
-// atomics; n_max: the largest catalog of the table).
-int map_jobs(conker_ctx *c, const conker_grid *g, int M, const ClassJob *tab, int64_t n_max);
-// Catalogs of at least this many points take the binned mapping path.
-int64_t scatter_bin_min_points();
+// Maps both catalogs of all M jobs and forms N = D - alpha R.  With a
+// workspace of map_jobs_bytes (non-zero where the grid splits into the
+// binned mapping's bricks; n_total: all points of the table) the points are
+// binned by brick and summed in LDS, each brick written whole; else the grids
+// are zeroed and the points added with atomics (n_max: the largest catalog).
+size_t map_jobs_bytes(const conker_grid *g, int M, int64_t n_total);
+int map_jobs(conker_ctx *c, const conker_grid *g, int M, const ClassJob *tab, int64_t n_max, int64_t n_total,
+             void *ws);
 // xi of every job of the table (count tuples of order n).
 int ratio_jobs(conker_ctx *c, int M, const ClassJob *tab, int n, int64_t count);
 // Whether the fused inverse z pass + order-3 summation (k_zinv_mm3_jobs)

@@ -45,10 +45,27 @@ template <> struct Plan<96>   { static constexpr int n = 3; static constexpr int
 template <> struct Plan<192>  { static constexpr int n = 3; static constexpr int r[4] = {8, 8, 3, 1}; };
 template <> struct Plan<384>  { static constexpr int n = 4; static constexpr int r[4] = {8, 8, 2, 3}; };
 
-template <int L, int S>
+// The other schedule of a length (a launch setting, chosen per grid shape by
+// the autotuner): radix 16 first, one stage fewer (64 = 16 4, 128 = 16 8,
+// 256 = 16 16, 1024 = 16 16 4).  Carried in a pass's tile-mode parameter as
+// MODE + 8 (TM_BASE strips it); lengths without one keep their schedule.
+template <int L>
+struct PlanAlt {
+    static constexpr bool has = false;
+};
+template <> struct PlanAlt<64>   { static constexpr bool has = true; static constexpr int n = 2; static constexpr int r[4] = {16, 4, 1, 1}; };
+template <> struct PlanAlt<128>  { static constexpr bool has = true; static constexpr int n = 2; static constexpr int r[4] = {16, 8, 1, 1}; };
+template <> struct PlanAlt<256>  { static constexpr bool has = true; static constexpr int n = 2; static constexpr int r[4] = {16, 16, 1, 1}; };
+template <> struct PlanAlt<1024> { static constexpr bool has = true; static constexpr int n = 3; static constexpr int r[4] = {16, 16, 4, 1}; };
+
+constexpr int TM_BASE = 7, TM_ALT = 8;
+template <int L, int MODE>
+using PlanM = std::conditional_t<(MODE & TM_ALT) != 0 && PlanAlt<L>::has, PlanAlt<L>, Plan<L>>;
+
+template <int L, int MODE, int S>
 constexpr int stage_ns() {   // product of radices before stage S
     int p = 1;
-    for (int s = 0; s < S; ++s) p *= Plan<L>::r[s];
+    for (int s = 0; s < S; ++s) p *= PlanM<L, MODE>::r[s];
     return p;
 }
 
@@ -64,25 +81,26 @@ enum TileMode { TM_J = 0, TM_C = 1, TM_W = 2, TM_R = 3 };
 
 template <typename T, int L, int MODE>
 struct Shape {
+    static constexpr int BM = MODE & TM_BASE;
     static constexpr bool f64 = std::is_same<T, double>::value;
     static constexpr int TC_C = f64 ? (L >= 1024 ? 4 : 8) : (L >= 1024 ? 8 : 16);
     static constexpr int TCJ0 = (f64 ? 2048 : 4096) / L;   // lines per z tile: a power of two
     static constexpr int TCJ = TCJ0 >= 256 ? 256 : TCJ0 >= 128 ? 128 : TCJ0 >= 64 ? 64 : TCJ0 >= 32 ? 32
                              : TCJ0 >= 16 ? 16 : TCJ0 >= 8 ? 8 : TCJ0 >= 4 ? 4 : TCJ0 >= 2 ? 2 : 1;
-    static constexpr int TC = MODE == TM_J ? TCJ : (MODE == TM_W ? 2 * TC_C : TC_C);
-    static constexpr int PAD = MODE == TM_J ? 0 : (f64 ? 0 : 2);
-    static constexpr int NB0 = (L / 8) * TC;   // first-stage butterflies per tile
+    static constexpr int TC = BM == TM_J ? TCJ : (BM == TM_W ? 2 * TC_C : TC_C);
+    static constexpr int PAD = BM == TM_J ? 0 : (f64 ? 0 : 2);
+    static constexpr int NB0 = (L / PlanM<L, MODE>::r[0]) * TC;   // first-stage butterflies per tile
     static constexpr int NT =
-        MODE == TM_J ? 256
-                     : (((MODE == TM_W || MODE == TM_R) && NB0 >= 1024) ? 1024 : (NB0 >= 512 ? 512 : 256));
-    static constexpr int LDS = MODE == TM_J ? TC * (L + (L >> 3)) : L * (TC + PAD);
+        BM == TM_J ? 256
+                   : (((BM == TM_W || BM == TM_R) && NB0 >= 1024) ? 1024 : (NB0 >= 512 ? 512 : 256));
+    static constexpr int LDS = BM == TM_J ? TC * (L + (L >> 3)) : L * (TC + PAD);
     // registers per thread must stay near 128 for four waves per SIMD
     static constexpr int MINW = NT >= 512 ? 4 : 2;
 };
 
 template <int MODE, int L, int TC, int PAD>
 __device__ __forceinline__ int lds_addr(int i, int c) {
-    if constexpr (MODE == TM_J) return c * (L + (L >> 3)) + i + (i >> 3);
+    if constexpr ((MODE & TM_BASE) == TM_J) return c * (L + (L >> 3)) + i + (i >> 3);
     else return i * (TC + PAD) + c;
 }
 
@@ -92,7 +110,7 @@ __device__ __forceinline__ int lds_addr(int i, int c) {
 template <int NT, int MODE, int LR, int TC>
 __device__ __forceinline__ void split_q(int q, int &j, int &c) {
     const int t = threadIdx.x;
-    if constexpr (MODE == TM_J) {
+    if constexpr ((MODE & TM_BASE) == TM_J) {
         if constexpr (NT % LR == 0) { j = t % LR; c = t / LR + q * (NT / LR); }
         else { const int b = t + q * NT; j = b % LR; c = b / LR; }
     } else {
@@ -131,12 +149,13 @@ struct has_sync_last<Op, std::enable_if_t<Op::SYNC_LAST>> : std::true_type {};
 // divisor of 64 (512 = 8 8 8, 64 = 8 8): the threads of a line then lie in one
 // wave in every stage, each line owns its LDS rows, and an ordering within the
 // wave replaces the workgroup barrier between stages.
-template <int L>
+template <int L, int MODE>
 constexpr bool lines_in_wave() {
-    const int lr = L / Plan<L>::r[0];
+    using PL = PlanM<L, MODE>;
+    const int lr = L / PL::r[0];
     if (64 % lr != 0) return false;
-    for (int s = 1; s < Plan<L>::n; ++s)
-        if (L / Plan<L>::r[s] != lr) return false;
+    for (int s = 1; s < PL::n; ++s)
+        if (L / PL::r[s] != lr) return false;
     return true;
 }
 
@@ -148,7 +167,7 @@ __device__ __forceinline__ void wave_order() {
 
 template <int L, int MODE>
 __device__ __forceinline__ void stage_sync() {
-    if constexpr (MODE == TM_J && lines_in_wave<L>()) wave_order();
+    if constexpr ((MODE & TM_BASE) == TM_J && lines_in_wave<L, MODE>()) wave_order();
     else __syncthreads();
 }
 
@@ -161,17 +180,17 @@ __device__ __forceinline__ void fft_stage(const cplx<T> *src, cplx<T> *dst, cons
     using C = cplx<T>;
     using SH = Shape<T, L, MODE>;
     constexpr int NT = SH::NT, TC = SH::TC, PAD = PADX >= 0 ? PADX : SH::PAD;
-    constexpr int R = Plan<L>::r[S];
-    constexpr int NSV = stage_ns<L, S>();
+    constexpr int R = PlanM<L, MODE>::r[S];
+    constexpr int NSV = stage_ns<L, MODE, S>();
     constexpr bool FIRST = (S == 0) && !STAGED;   // first stage reads global memory
-    constexpr bool LAST = (S == Plan<L>::n - 1);
+    constexpr bool LAST = (S == PlanM<L, MODE>::n - 1);
     constexpr int LR = L / R;
     constexpr int NB = LR * TC;
     constexpr int PER = (NB + NT - 1) / NT;
     constexpr int TWS = L / (NSV * R);
     static_assert((NSV & (NSV - 1)) == 0, "stages before the last have power-of-two spans");
     constexpr bool KEEP = LAST && has_keep<Op>::value;
-    static_assert(!KEEP || R <= 8, "keep flags are packed 8 per butterfly");
+    static_assert(!KEEP || R <= 16, "keep flags are packed 16 per butterfly");
     unsigned kbits[PER];
     if constexpr (KEEP) {
         if (op.keeps()) {
@@ -194,7 +213,7 @@ __device__ __forceinline__ void fft_stage(const cplx<T> *src, cplx<T> *dst, cons
             }
         } else {
 #pragma unroll
-            for (int q = 0; q < PER; ++q) kbits[q] = 0xffu;
+            for (int q = 0; q < PER; ++q) kbits[q] = 0xffffu;
         }
     }
     C v[PER][R];
@@ -258,7 +277,7 @@ __device__ __forceinline__ void fft_stage(const cplx<T> *src, cplx<T> *dst, cons
 // and the first stage reads LDS.  Used where the load does extra work.
 template <typename T, int L, int MODE, int DIR, bool STAGED, class Op>
 __device__ __forceinline__ void fft_line_tile(cplx<T> *lds, const cplx<T> *tw, Op &op) {
-    constexpr bool ST = STAGED && MODE != TM_J;   // staged loads are for column tiles
+    constexpr bool ST = STAGED && (MODE & TM_BASE) != TM_J;   // staged loads are for column tiles
     if constexpr (ST) {
         using SH = Shape<T, L, MODE>;
         constexpr int NT = SH::NT, TC = SH::TC, PAD = SH::PAD;
@@ -267,10 +286,11 @@ __device__ __forceinline__ void fft_line_tile(cplx<T> *lds, const cplx<T> *tw, O
         for (int i = threadIdx.x / TC; i < L; i += NT / TC) lds[lds_addr<MODE, L, TC, PAD>(i, c)] = op.load(i, c);
         __syncthreads();
     }
+    using PL = PlanM<L, MODE>;
     fft_stage<T, L, MODE, DIR, 0, ST>(lds, lds, tw, op);
-    if constexpr (Plan<L>::n > 1) fft_stage<T, L, MODE, DIR, 1, ST>(lds, lds, tw, op);
-    if constexpr (Plan<L>::n > 2) fft_stage<T, L, MODE, DIR, 2, ST>(lds, lds, tw, op);
-    if constexpr (Plan<L>::n > 3) fft_stage<T, L, MODE, DIR, 3, ST>(lds, lds, tw, op);
+    if constexpr (PL::n > 1) fft_stage<T, L, MODE, DIR, 1, ST>(lds, lds, tw, op);
+    if constexpr (PL::n > 2) fft_stage<T, L, MODE, DIR, 2, ST>(lds, lds, tw, op);
+    if constexpr (PL::n > 3) fft_stage<T, L, MODE, DIR, 3, ST>(lds, lds, tw, op);
 }
 
 // Ops with an active() member may skip a whole tile (same answer for every
@@ -1211,7 +1231,7 @@ struct OpZinvMM {
     }
 };
 
-template <int L>
+template <int L, int MODE>
 __global__ __launch_bounds__(256, 4) void k_zinv_mm3_jobs(const float2 *__restrict__ tspec,
                                                          const ClassJob *__restrict__ tab,
                                                          const PackScale *__restrict__ scales,
@@ -1254,7 +1274,7 @@ __global__ __launch_bounds__(256, 4) void k_zinv_mm3_jobs(const float2 *__restri
         }
         op.src = jspec + cell0;
         __syncthreads();   // the previous tile is done with maps, fl and lds (twiddles in)
-        fft_line_tile<float, L, TM_J, +1, false>(lds, tw, op);
+        fft_line_tile<float, L, MODE, +1, false>(lds, tw, op);
 #pragma unroll
         for (int k = 0; k < FPT; ++k) {
             const int idx = threadIdx.x + k * NT;
@@ -1350,11 +1370,24 @@ int col_mode_for(const conker_ctx *ctx, const Dims &d, int axis) {
     return (wide && d.nz >= tc_of<T>(L, TM_W)) ? (int)TM_W : (int)TM_C;
 }
 
+// Whether the float32 passes of length L take the other radix schedule: the
+// context's radix setting (1 the usual schedules, 2 the other one where a
+// length has it), else CONKER_RADIX16=1, else the usual ones.
+bool radix_alt(const conker_ctx *ctx, int L) {
+    static const int env = env_flag("CONKER_RADIX16", 0);
+    const int r = ctx->tune.radix;
+    const bool want = r ? r == 2 : env != 0;
+    return want && (L == 64 || L == 128 || L == 256 || L == 1024);
+}
+
 template <typename T, int MODE, int DIR, class Op>
 int launch_len_mode(conker_ctx *ctx, int L, int axis, const Dims &d, dim3 gy, Op op) {
     auto go = [&](auto Lc) -> int {
         constexpr int LL = decltype(Lc)::value;
-        using SH = Shape<T, LL, MODE>;
+        // the other schedule where the length has one (float only), else the usual one
+        constexpr int MM = ((MODE & TM_ALT) && PlanAlt<LL>::has && std::is_same<T, float>::value) ? MODE
+                                                                                                  : (MODE & TM_BASE);
+        using SH = Shape<T, LL, MM>;
         long tiles;
         if (axis == AX_Z) tiles = (long)d.nx * d.ny / SH::TC;
         else if (axis == AX_Y) tiles = (long)d.nx * d.nz / SH::TC;
@@ -1367,7 +1400,7 @@ int launch_len_mode(conker_ctx *ctx, int L, int axis, const Dims &d, dim3 gy, Op
                 grid = dim3((unsigned)std::min<long>(items, cu_count(ctx)), 1, 1);
             }
         }
-        hipLaunchKernelGGL((k_fft<T, LL, MODE, DIR, Op>), grid, dim3(SH::NT), 0, ctx->stream, op, items, (int)tiles);
+        hipLaunchKernelGGL((k_fft<T, LL, MM, DIR, Op>), grid, dim3(SH::NT), 0, ctx->stream, op, items, (int)tiles);
         CK_LAUNCH(ctx);
         return CONKER_OK;
     };
@@ -1388,6 +1421,11 @@ int launch_len_mode(conker_ctx *ctx, int L, int axis, const Dims &d, dim3 gy, Op
 template <typename T, int DIR, class Op>
 int launch_len(conker_ctx *ctx, int kind, int mode, int L, int axis, const Dims &d, dim3 gy, Op op) {
     ProfScope ps(ctx, kind);
+    if (std::is_same<T, float>::value && radix_alt(ctx, L)) {
+        if (mode == TM_J) return launch_len_mode<T, TM_J | TM_ALT, DIR>(ctx, L, axis, d, gy, op);
+        if (mode == TM_C) return launch_len_mode<T, TM_C | TM_ALT, DIR>(ctx, L, axis, d, gy, op);
+        return launch_len_mode<T, TM_W | TM_ALT, DIR>(ctx, L, axis, d, gy, op);
+    }
     if (mode == TM_J) return launch_len_mode<T, TM_J, DIR>(ctx, L, axis, d, gy, op);
     if (mode == TM_C) return launch_len_mode<T, TM_C, DIR>(ctx, L, axis, d, gy, op);
     return launch_len_mode<T, TM_W, DIR>(ctx, L, axis, d, gy, op);
@@ -1749,11 +1787,19 @@ int fft_inverse_mm3_jobs(conker_ctx *ctx, const conker_grid *g, int M, const Cla
                                  dim3(1, (unsigned)(M * ns)), py)));
     const int G = fft_mm3_jobs_blocks(ctx, M);
     ProfScope ps(ctx, PK_FUSED_ZC);
+    const bool alt = radix_alt(ctx, d.nz);
     auto go = [&](auto Lc) {
         constexpr int LL = decltype(Lc)::value;
-        if constexpr (ZMM<LL>::OK)
-            hipLaunchKernelGGL(k_zinv_mm3_jobs<LL>, dim3((unsigned)G, (unsigned)M), dim3(256), 0, ctx->stream,
-                               (const float2 *)tspec, tab, scales, (const float2 *)twz, d, nc, ns, partial);
+        if constexpr (ZMM<LL>::OK) {
+            if (alt && PlanAlt<LL>::has)
+                hipLaunchKernelGGL((k_zinv_mm3_jobs<LL, TM_J | TM_ALT>), dim3((unsigned)G, (unsigned)M), dim3(256), 0,
+                                   ctx->stream, (const float2 *)tspec, tab, scales, (const float2 *)twz, d, nc, ns,
+                                   partial);
+            else
+                hipLaunchKernelGGL((k_zinv_mm3_jobs<LL, TM_J>), dim3((unsigned)G, (unsigned)M), dim3(256), 0,
+                                   ctx->stream, (const float2 *)tspec, tab, scales, (const float2 *)twz, d, nc, ns,
+                                   partial);
+        }
     };
     switch (d.nz) {
         case 32: go(std::integral_constant<int, 32>()); break;

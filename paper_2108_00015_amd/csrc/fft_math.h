@@ -1,4 +1,4 @@
-// Complex helpers and in-register radix-2/4/8 DFT butterflies shared by the
+// Complex helpers and in-register radix-2/3/4/8/16 DFT butterflies shared by the
 // FFT passes and the fused inverse-z / summation kernel.
 #pragma once
 
@@ -52,6 +52,30 @@ __device__ __forceinline__ void dft(C *v) {
         v[2] = csub(a0, a2);
         v[1] = cadd(a1, a3);
         v[3] = csub(a1, a3);
+    } else if constexpr (R == 16) {
+        // even and odd halves as 8-point DFTs, odd ones turned by
+        // exp(DIR 2 pi i k / 16), k = 0..7 (cos and sin of multiples of pi/8)
+        using T = decltype(v[0].x);
+        C e[8], o[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            e[k] = v[2 * k];
+            o[k] = v[2 * k + 1];
+        }
+        dft<8, DIR>(e);
+        dft<8, DIR>(o);
+        const T c1 = (T)0.92387953251128675613, s1 = (T)0.38268343236508977173;   // cos, sin pi/8
+        const T h = (T)0.70710678118654752440;
+        const T d = (T)DIR;
+        const T cs[8] = {(T)1, c1, h, s1, (T)0, -s1, -h, -c1};
+        const T sn[8] = {(T)0, s1, h, c1, (T)1, c1, h, s1};
+#pragma unroll
+        for (int k = 1; k < 8; ++k) o[k] = cmul(o[k], C{cs[k], d * sn[k]});
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            v[k] = cadd(e[k], o[k]);
+            v[k + 8] = csub(e[k], o[k]);
+        }
     } else {
         static_assert(R == 8, "radix");
         using T = decltype(v[0].x);

@@ -129,11 +129,11 @@ __device__ __forceinline__ bool locate(const float *pos, const float *w, int64_t
     return ok;
 }
 
-__global__ __launch_bounds__(BT) void k_bin_count(const float *__restrict__ pos, const float *__restrict__ w,
-                                                  int64_t n, int64_t chunk, GridGeom g, BrickGeom bg, int nb,
-                                                  unsigned *__restrict__ hist_out, unsigned *__restrict__ totals,
-                                                  double *wsum, unsigned long long *n_out,
-                                                  unsigned *__restrict__ wmax_bits) {
+__device__ __forceinline__ void bin_count_body(const float *__restrict__ pos, const float *__restrict__ w,
+                                               int64_t n, int64_t chunk, GridGeom g, BrickGeom bg, int nb,
+                                               unsigned *__restrict__ hist_out, unsigned *__restrict__ totals,
+                                               double *wsum, unsigned long long *n_out,
+                                               unsigned *__restrict__ wmax_bits) {
     __shared__ unsigned hist[MAX_BRICKS];
     __shared__ double sw[BT / 64];
     __shared__ unsigned long long so[BT / 64];
@@ -198,9 +198,64 @@ __global__ __launch_bounds__(BT) void k_bin_count(const float *__restrict__ pos,
     }
 }
 
+__global__ __launch_bounds__(BT) void k_bin_count(const float *__restrict__ pos, const float *__restrict__ w,
+                                                  int64_t n, int64_t chunk, GridGeom g, BrickGeom bg, int nb,
+                                                  unsigned *__restrict__ hist_out, unsigned *__restrict__ totals,
+                                                  double *wsum, unsigned long long *n_out,
+                                                  unsigned *__restrict__ wmax_bits) {
+    bin_count_body(pos, w, n, chunk, g, bg, nb, hist_out, totals, wsum, n_out, wmax_bits);
+}
+
+// ---------------------------------------------------------------------------
+// The binned mapping for every catalog of a size class at once: field
+// z = blockIdx.y = 2 job + {0 data, 1 randoms} has its own counts, starts and
+// cursors at meta + z 3 SB (totals, with the largest |w| after them; starts;
+// cursors), its workgroup histograms at hist + z gridDim.x nb and its placed
+// points at items + the field's item offset.
+// ---------------------------------------------------------------------------
+struct JobField {
+    const float *pos, *w;
+    int64_t n, ioff;
+    float *grid;
+    double *wsum;
+    unsigned long long *n_out;
+};
+
+__device__ __forceinline__ JobField job_field(const conker::ClassJob *tab, int z) {
+    const conker::ClassJob &j = tab[z >> 1];
+    const bool r = z & 1;
+    return JobField{r ? j.rpos : j.dpos, r ? j.rw : j.dw, r ? j.nr : j.nd, r ? j.ioff_r : j.ioff_d, r ? j.R : j.N,
+                    j.wsum + (r ? 1 : 0), reinterpret_cast<unsigned long long *>(j.nout + (r ? 1 : 0))};
+}
+
+// wsum, rejected counts and the brick totals (with the largest |w|) of every field
+__global__ void k_bin_zero_jobs(const conker::ClassJob *__restrict__ tab, int M, unsigned *__restrict__ meta,
+                                int sb) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < 2 * M) {
+        const JobField f = job_field(tab, t);
+        *f.wsum = 0.0;
+        *f.n_out = 0ull;
+    }
+    for (int i = t; i < 2 * M * sb; i += gridDim.x * blockDim.x) {
+        const int z = i / sb, k = i - z * sb;
+        meta[(size_t)z * 3 * sb + k] = 0u;
+    }
+}
+
+__global__ __launch_bounds__(BT) void k_bin_count_jobs(const conker::ClassJob *__restrict__ tab, GridGeom g,
+                                                       BrickGeom bg, int nb, unsigned *__restrict__ hist,
+                                                       unsigned *__restrict__ meta, int sb) {
+    const JobField f = job_field(tab, blockIdx.y);
+    const int64_t chunk = (f.n + gridDim.x - 1) / gridDim.x;
+    unsigned *totals = meta + (size_t)blockIdx.y * 3 * sb;
+    bin_count_body(f.pos, f.w, f.n, chunk, g, bg, nb, hist + (size_t)blockIdx.y * gridDim.x * nb, totals, f.wsum,
+                   f.n_out, totals + nb);
+}
+
 // One workgroup: start[b] = sum of totals before b (start[nb] = all), cursor = start.
-__global__ __launch_bounds__(BT) void k_bin_scan(const unsigned *__restrict__ totals, int nb,
-                                                 unsigned *__restrict__ start, unsigned *__restrict__ cursor) {
+__device__ __forceinline__ void bin_scan_body(const unsigned *__restrict__ totals, int nb,
+                                              unsigned *__restrict__ start, unsigned *__restrict__ cursor) {
     __shared__ unsigned part[BT];
     const int t = threadIdx.x, per = (nb + BT - 1) / BT;
     const int b0 = t * per;
@@ -223,10 +278,20 @@ __global__ __launch_bounds__(BT) void k_bin_scan(const unsigned *__restrict__ to
     if (t == BT - 1) start[nb] = part[t];
 }
 
-__global__ __launch_bounds__(BT) void k_bin_place(const float *__restrict__ pos, const float *__restrict__ w,
-                                                  int64_t n, int64_t chunk, GridGeom g, BrickGeom bg, int nb,
-                                                  const unsigned *__restrict__ hist_in, unsigned *__restrict__ cursor,
-                                                  uint2 *__restrict__ items) {
+__global__ __launch_bounds__(BT) void k_bin_scan(const unsigned *__restrict__ totals, int nb,
+                                                 unsigned *__restrict__ start, unsigned *__restrict__ cursor) {
+    bin_scan_body(totals, nb, start, cursor);
+}
+
+__global__ __launch_bounds__(BT) void k_bin_scan_jobs(int nb, unsigned *__restrict__ meta, int sb) {
+    unsigned *m = meta + (size_t)blockIdx.x * 3 * sb;
+    bin_scan_body(m, nb, m + sb, m + 2 * sb);
+}
+
+__device__ __forceinline__ void bin_place_body(const float *__restrict__ pos, const float *__restrict__ w,
+                                               int64_t n, int64_t chunk, GridGeom g, BrickGeom bg, int nb,
+                                               const unsigned *__restrict__ hist_in, unsigned *__restrict__ cursor,
+                                               uint2 *__restrict__ items) {
     __shared__ unsigned base[MAX_BRICKS];
     __shared__ unsigned rank[MAX_BRICKS];
     const unsigned *mine = hist_in + (size_t)blockIdx.x * nb;
@@ -256,15 +321,33 @@ __global__ __launch_bounds__(BT) void k_bin_place(const float *__restrict__ pos,
     }
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_bin_accum(const uint2 *__restrict__ items, const unsigned *__restrict__ start,
-                                                   GridGeom g, BrickGeom bg, T *__restrict__ grid,
-                                                   const unsigned *__restrict__ wmax_bits) {
+__global__ __launch_bounds__(BT) void k_bin_place(const float *__restrict__ pos, const float *__restrict__ w,
+                                                  int64_t n, int64_t chunk, GridGeom g, BrickGeom bg, int nb,
+                                                  const unsigned *__restrict__ hist_in, unsigned *__restrict__ cursor,
+                                                  uint2 *__restrict__ items) {
+    bin_place_body(pos, w, n, chunk, g, bg, nb, hist_in, cursor, items);
+}
+
+__global__ __launch_bounds__(BT) void k_bin_place_jobs(const conker::ClassJob *__restrict__ tab, GridGeom g,
+                                                       BrickGeom bg, int nb, const unsigned *__restrict__ hist,
+                                                       unsigned *__restrict__ meta, int sb, uint2 *__restrict__ items) {
+    const JobField f = job_field(tab, blockIdx.y);
+    const int64_t chunk = (f.n + gridDim.x - 1) / gridDim.x;
+    bin_place_body(f.pos, f.w, f.n, chunk, g, bg, nb, hist + (size_t)blockIdx.y * gridDim.x * nb,
+                   meta + (size_t)blockIdx.y * 3 * sb + 2 * sb, items + f.ioff);
+}
+
+// OVER: the brick's cells are written with its sums (every brick, empty ones
+// with zeros), else its sums are added to the grid (bricks with points only).
+template <typename T, bool OVER>
+__device__ __forceinline__ void bin_accum_body(const uint2 *__restrict__ items, const unsigned *__restrict__ start,
+                                               GridGeom g, BrickGeom bg, T *__restrict__ grid,
+                                               const unsigned *__restrict__ wmax_bits) {
     __shared__ unsigned long long acc[BCELLS];   // fixed-point sums, or the T sums in its first bytes
     T *const tile = reinterpret_cast<T *>(acc);
     const int b = blockIdx.x;
     const unsigned i0 = start[b], i1 = start[b + 1];
-    if (i0 == i1) return;   // uniform: no point in this brick
+    if (!OVER && i0 == i1) return;   // uniform: no point in this brick
     // Fixed point w 2^E with 2^E chosen per brick so that every cell sum stays
     // within (i1 - i0) max|w| 2^E <= 2^62 (int64): each w is rounded to the
     // nearest multiple of 2^-E, exactly for |w| >= 2^(23 - E) (unit weights
@@ -304,7 +387,7 @@ __global__ __launch_bounds__(256) void k_bin_accum(const uint2 *__restrict__ ite
         const int lz = e % BZ, ly = (e / BZ) % BY, lx = e / (BZ * BY);
         lin[k] = ((size_t)(bx * BX + lx) * g.ny + (by * BY + ly)) * g.nz + (bz * BZ + lz);
 #pragma unroll
-        for (int j = 0; j < V; ++j) v[k][j] = grid[lin[k] + j];
+        for (int j = 0; j < V; ++j) v[k][j] = OVER ? (T)0 : grid[lin[k] + j];
     }
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
@@ -312,9 +395,25 @@ __global__ __launch_bounds__(256) void k_bin_accum(const uint2 *__restrict__ ite
 #pragma unroll
         for (int j = 0; j < V; ++j) {
             const T s = fixed ? (T)((double)(long long)acc[e + j] * from_fixed) : tile[e + j];
-            grid[lin[k] + j] = v[k][j] + s;
+            grid[lin[k] + j] = OVER ? s : v[k][j] + s;
         }
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_bin_accum(const uint2 *__restrict__ items, const unsigned *__restrict__ start,
+                                                   GridGeom g, BrickGeom bg, T *__restrict__ grid,
+                                                   const unsigned *__restrict__ wmax_bits) {
+    bin_accum_body<T, false>(items, start, g, bg, grid, wmax_bits);
+}
+
+// every brick (blockIdx.x) of field blockIdx.y, written whole
+__global__ __launch_bounds__(256) void k_bin_accum_jobs(const conker::ClassJob *__restrict__ tab, GridGeom g,
+                                                        BrickGeom bg, int nb, const unsigned *__restrict__ meta,
+                                                        int sb, const uint2 *__restrict__ items) {
+    const JobField f = job_field(tab, blockIdx.y);
+    const unsigned *m = meta + (size_t)blockIdx.y * 3 * sb;
+    bin_accum_body<float, true>(items + f.ioff, m + sb, g, bg, f.grid, m + nb);
 }
 
 __global__ void k_zero_u32(unsigned *__restrict__ p, int n) {
@@ -440,15 +539,62 @@ using namespace conker;
 
 namespace conker {
 
-int64_t scatter_bin_min_points() { return BIN_MIN_POINTS; }
+namespace {
+struct BinLayout {
+    int nb, sb, bg;
+    size_t meta, hist, items, bytes;
+};
+bool bin_layout(const conker_grid *g, int M, int64_t n_total, BinLayout *L) {
+    if (g->dims[0] % BX || g->dims[1] % BY || g->dims[2] % BZ) return false;
+    const int64_t nb = (int64_t)(g->dims[0] / BX) * (g->dims[1] / BY) * (g->dims[2] / BZ);
+    if (nb > MAX_BRICKS || n_total > ((int64_t)1 << 32)) return false;
+    const auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+    L->nb = (int)nb;
+    L->sb = (int)((nb + 1 + 3) / 4 * 4);
+    L->bg = std::max(8, 512 / (2 * M));   // workgroups per catalog in the count and place passes
+    L->meta = 0;
+    L->hist = up((size_t)2 * M * 3 * L->sb * sizeof(unsigned));
+    L->items = L->hist + up((size_t)2 * M * L->bg * nb * sizeof(unsigned));
+    L->bytes = L->items + up((size_t)n_total * sizeof(uint2));
+    return true;
+}
+}  // namespace
 
-int map_jobs(conker_ctx *c, const conker_grid *g, int M, const ClassJob *tab, int64_t n_max) {
+size_t map_jobs_bytes(const conker_grid *g, int M, int64_t n_total) {
+    BinLayout L;
+    return bin_layout(g, M, n_total, &L) ? L.bytes : 0;
+}
+
+int map_jobs(conker_ctx *c, const conker_grid *g, int M, const ClassJob *tab, int64_t n_max, int64_t n_total,
+             void *ws) {
     const size_t nc = ncells(g);
     if (nc % 4) return fail(c, CONKER_EINVAL, "size class: cell count must be a multiple of 4");
     const GridGeom gg{g->origin[0], g->origin[1], g->origin[2], g->cell, g->dims[0], g->dims[1], g->dims[2]};
     const size_t cap = (size_t)4 * cu_count(c);
     const unsigned zb = (unsigned)std::max<size_t>(1, std::min<size_t>(cap / M + 1, (nc / 4 + 255) / 256));
-    {
+    BinLayout L;
+    if (ws && bin_layout(g, M, n_total, &L)) {   // binned: every grid written whole by its bricks
+        ProfScope ps(c, PK_SCATTER);
+        const BrickGeom bg{g->dims[0] / BX, g->dims[1] / BY, g->dims[2] / BZ};
+        char *base = (char *)ws;
+        unsigned *meta = (unsigned *)(base + L.meta), *hist = (unsigned *)(base + L.hist);
+        uint2 *items = (uint2 *)(base + L.items);
+        const unsigned nf = 2u * (unsigned)M;
+        hipLaunchKernelGGL(k_bin_zero_jobs, dim3((unsigned)((nf * L.sb + 255) / 256)), dim3(256), 0, c->stream, tab, M,
+                           meta, L.sb);
+        CK_LAUNCH(c);
+        hipLaunchKernelGGL(k_bin_count_jobs, dim3((unsigned)L.bg, nf), dim3(BT), 0, c->stream, tab, gg, bg, L.nb, hist,
+                           meta, L.sb);
+        CK_LAUNCH(c);
+        hipLaunchKernelGGL(k_bin_scan_jobs, dim3(nf), dim3(BT), 0, c->stream, L.nb, meta, L.sb);
+        CK_LAUNCH(c);
+        hipLaunchKernelGGL(k_bin_place_jobs, dim3((unsigned)L.bg, nf), dim3(BT), 0, c->stream, tab, gg, bg, L.nb,
+                           (const unsigned *)hist, meta, L.sb, items);
+        CK_LAUNCH(c);
+        hipLaunchKernelGGL(k_bin_accum_jobs, dim3((unsigned)L.nb, nf), dim3(256), 0, c->stream, tab, gg, bg, L.nb,
+                           (const unsigned *)meta, L.sb, (const uint2 *)items);
+        CK_LAUNCH(c);
+    } else {
         ProfScope ps(c, PK_SCATTER);
         hipLaunchKernelGGL(k_zero_jobs, dim3(zb, (unsigned)M), dim3(256), 0, c->stream, tab, nc);
         CK_LAUNCH(c);

@@ -94,10 +94,13 @@ def _outs(jobs):
             for j in jobs]
 
 
-def _run_both(ck, jobs, replays=3):
-    """Outputs with classes: plan, eager re-run, graph replays; then job by job."""
+def _run_both(ck, jobs, replays=3, **tune):
+    """Outputs with classes (launch setting `tune`): plan, eager re-run, graph
+    replays; then job by job with the defaults."""
     s = torch.cuda.Stream()
     ctx = ck.Context(0, stream=s)
+    if tune:
+        ctx.set_tune(**tune)
     torch.cuda.synchronize()
     ctx.batch_plan(jobs)
     layout = ctx.batch_layout()
@@ -131,14 +134,17 @@ def _run_both(ck, jobs, replays=3):
     return layout, runs, ref
 
 
-@pytest.mark.parametrize("stored", [False, True])
+@pytest.mark.parametrize("stored,radix", [(False, 0), (True, 0), (False, 2), (True, 2)])
 @pytest.mark.parametrize("prec", ["split_bf16", "split_f16"])
-def test_classes_match_job_by_job_and_oracle(mocks, oracle_classes, prec, stored):
+def test_classes_match_job_by_job_and_oracle(mocks, oracle_classes, prec, stored, radix):
+    """bf16 without maps: the fused last pass and summation; otherwise maps in
+    the class workspace or the caller's buffers.  radix 2: the radix-16 schedule
+    on the 128-cell axes."""
     import paper_2108_00015_amd as ck
-    _say("classes", prec, "maps given" if stored else "maps in workspace")
+    _say("classes", prec, "maps given" if stored else "maps in workspace", "radix", radix)
     ctx = ck.Context(0)
     jobs = _jobs(ck, ctx, MOCKS, mocks, CELL, RADII, prec, stored)
-    layout, runs, ref = _run_both(ck, jobs)
+    layout, runs, ref = _run_both(ck, jobs, **({"radix": radix} if radix else {}))
     _say("  layout", layout)
     # one chunk per size class (the workspace bound holds these grids whole)
     assert layout[0] == layout[2] == layout[4] >= 0 and layout[1] == layout[3] >= 0 and layout[0] != layout[1]

@@ -1,5 +1,6 @@
 """Launch settings (column tiles of the x / y passes, the LDS-resident x pass,
-the summation kernel, the radius batch) and the batch autotuner.  Every setting
+the summation kernel, the radius batch, the radix schedule) and the batch
+autotuner.  Every setting
 computes the same sums in another order of tiles, so each is held to the same
 bar against the FP64 oracle as the defaults: float64 1e-12, float32 3e-6 per
 map and 1e-5 for the summations (relative to the largest value).
@@ -118,6 +119,37 @@ def test_convolve_every_tile_setting(ck, ctx, dims, dt, tol):
         assert relerr(mp.cpu().numpy(), ref_a) <= tol
 
 
+@pytest.mark.parametrize("dims", [(64, 128, 256), (256, 64, 128), (128, 256, 64), (32, 32, 1024), (1024, 32, 32),
+                                  (96, 128, 64)])
+def test_radix_schedules(ck, ctx, dims):
+    """Both radix schedules (radix 8 first; radix 16 first on lengths 64, 128,
+    256 and 1024) on every axis: the maps of both fields against the oracle
+    (float32, 3e-6 of the largest value), the map-free order-3 sums (1e-5)."""
+    rng = np.random.default_rng(139)
+    A = rng.normal(size=dims)
+    B = rng.poisson(3.0, size=dims).astype(np.float64)
+    radii = [r for r in (1.0, 2.5, 4.0, 7.0) if 2 * oc.shell_reach(r) + 1 <= min(dims)]
+    Af = A.astype(np.float32).astype(np.float64)
+    ref_a, ref_b = oc.convolve_shells(Af, radii), oc.convolve_shells(B, radii)
+    wref_a = oc.contract(Af, ref_a, 3)
+    wref_b = oc.contract(B, ref_b, 3)
+    grid = ck.Grid(dims, (0, 0, 0), 1.0)
+    ks, _ = ctx.make_shell_kernels(grid, radii, torch.float32)
+    At, Bt = _gpu(A, torch.float32), _gpu(B, torch.float32)
+    for radix in (1, 2):
+        for xt in (1, 2):
+            _say("radix", radix, dims, "x_tile", xt)
+            ctx.set_tune(radix=radix, x_tile=xt, y_tile=xt)
+            ma, mb = ctx.convolve_shells(grid, At, Bt, ks)
+            ma, mb = ma.cpu().numpy(), mb.cpu().numpy()
+            for m in range(len(radii)):
+                ea, eb = relerr(ma[m], ref_a[m]), relerr(mb[m], ref_b[m])
+                assert ea <= 3e-6 and eb <= 3e-6, (radix, xt, m, ea, eb)
+            Wa, Wb = ctx.convolve_contract(grid, At, Bt, ks, 3, "split_bf16")
+            ea, eb = relerr(Wa.cpu().numpy(), wref_a), relerr(Wb.cpu().numpy(), wref_b)
+            assert ea <= 1e-5 and eb <= 1e-5, (radix, xt, ea, eb)
+
+
 @pytest.mark.parametrize("rb", [1, 3])
 def test_radius_batch_setting(ck, ctx, rb):
     dims = (64, 64, 64)
@@ -211,7 +243,8 @@ def test_fused_and_diag_with_line_masks(ck, ctx, yt):
 
 
 def test_set_tune_rejects_out_of_range(ck, ctx):
-    for bad in (dict(x_tile=3), dict(y_tile=-1), dict(x_resident=5), dict(mm_kernel=4), dict(radius_batch=65)):
+    for bad in (dict(x_tile=3), dict(y_tile=-1), dict(x_resident=5), dict(mm_kernel=4), dict(radius_batch=65),
+                dict(radix=3)):
         with pytest.raises(ck.ConkerError):
             ctx.set_tune(**bad)
     with pytest.raises(ValueError):

@@ -1071,7 +1071,7 @@ int contract_dot(conker_ctx *c, const T *F, const T *maps, size_t nc, int ns, co
 // With tab (size classes): field z = blockIdx.y is N (z even) or R (z odd) of
 // job z / 2, its scales at maxabs + z (ns + 1) and its tiles after the
 // z NTL G partial tiles of the fields before it.
-template <int RT, int PREC>
+template <int RT, int PREC, bool NEST>
 __global__ __launch_bounds__(NT) void k_mm3(const float *__restrict__ F, const float *__restrict__ maps, size_t nc,
                                             const int *__restrict__ list, const int *__restrict__ count, int ns,
                                             double *__restrict__ partial, const unsigned *__restrict__ maxabs,
@@ -1159,8 +1159,7 @@ __global__ __launch_bounds__(NT) void k_mm3(const float *__restrict__ F, const f
     };
     (void)off;
     if (bk.k0 < bk.k1) load(bk.k0);
-    int cnt = 0;
-    for (int k = bk.k0; k < bk.k1; ++k) {
+    auto step = [&](int k) {
         float fc[8], c0c[8], c1c[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
@@ -1180,13 +1179,33 @@ __global__ __launch_bounds__(NT) void k_mm3(const float *__restrict__ F, const f
             mma(acc[1], a0, c1c, eA0, eB1);
             mma(acc[2], a1, c1c, eA1, eB1);
         }
-        if (++cnt == FLUSH) {
-            cnt = 0;
+    };
+    auto flush = [&]() {
 #pragma unroll
-            for (int s = 0; s < NTL; ++s) {
+        for (int s = 0; s < NTL; ++s) {
 #pragma unroll
-                for (int v = 0; v < 16; ++v) accd[s][v] += (double)acc[s][v];
-                acc[s] = floatx16{0};
+            for (int v = 0; v < 16; ++v) accd[s][v] += (double)acc[s][v];
+            acc[s] = floatx16{0};
+        }
+    };
+    if constexpr (NEST) {
+        // FLUSH blocks into the float32 accumulators, then float64: the inner
+        // loop keeps them in the matrix-core registers (with a flush counter in
+        // a single loop the compiler copies them out and back every block).
+        // One tile only: with three (NEST false) the nested form measured
+        // slower (127 -> 155 ms on 1024^3 x 40 radii), the flat one stays.
+        for (int k = bk.k0; k < bk.k1;) {
+            const int kend = k + FLUSH < bk.k1 ? k + FLUSH : bk.k1;
+            for (; k < kend; ++k) step(k);
+            flush();
+        }
+    } else {
+        int cnt = 0;
+        for (int k = bk.k0; k < bk.k1; ++k) {
+            step(k);
+            if (++cnt == FLUSH) {
+                cnt = 0;
+                flush();
             }
         }
     }
@@ -1481,11 +1500,11 @@ extern "C" int conker_contract_npt(conker_ctx *c, const conker_grid *g, conker_d
                 if (prec == CONKER_MM_SPLIT_F16) go(k_mm3s<CONKER_MM_SPLIT_F16>);
                 else go(k_mm3s<CONKER_MM_SPLIT_BF16>);
             } else if (RT == 1) {
-                if (prec == CONKER_MM_SPLIT_F16) go(k_mm3<1, CONKER_MM_SPLIT_F16>);
-                else go(k_mm3<1, CONKER_MM_SPLIT_BF16>);
+                if (prec == CONKER_MM_SPLIT_F16) go(k_mm3<1, CONKER_MM_SPLIT_F16, true>);
+                else go(k_mm3<1, CONKER_MM_SPLIT_BF16, true>);
             } else {
-                if (prec == CONKER_MM_SPLIT_F16) go(k_mm3<2, CONKER_MM_SPLIT_F16>);
-                else go(k_mm3<2, CONKER_MM_SPLIT_BF16>);
+                if (prec == CONKER_MM_SPLIT_F16) go(k_mm3<2, CONKER_MM_SPLIT_F16, false>);
+                else go(k_mm3<2, CONKER_MM_SPLIT_BF16, false>);
             }
             CK_LAUNCH(c);
         }
@@ -1626,11 +1645,11 @@ int contract3_jobs(conker_ctx *c, const conker_grid *g, int M, const ClassJob *t
             if (prec == CONKER_MM_SPLIT_F16) go(k_mm3s<CONKER_MM_SPLIT_F16>);
             else go(k_mm3s<CONKER_MM_SPLIT_BF16>);
         } else if (L.ntl == 1) {
-            if (prec == CONKER_MM_SPLIT_F16) go(k_mm3<1, CONKER_MM_SPLIT_F16>);
-            else go(k_mm3<1, CONKER_MM_SPLIT_BF16>);
+            if (prec == CONKER_MM_SPLIT_F16) go(k_mm3<1, CONKER_MM_SPLIT_F16, true>);
+            else go(k_mm3<1, CONKER_MM_SPLIT_BF16, true>);
         } else {
-            if (prec == CONKER_MM_SPLIT_F16) go(k_mm3<2, CONKER_MM_SPLIT_F16>);
-            else go(k_mm3<2, CONKER_MM_SPLIT_BF16>);
+            if (prec == CONKER_MM_SPLIT_F16) go(k_mm3<2, CONKER_MM_SPLIT_F16, false>);
+            else go(k_mm3<2, CONKER_MM_SPLIT_BF16, false>);
         }
         CK_LAUNCH(c);
     }

@@ -982,18 +982,24 @@ __global__ __launch_bounds__((Shape<T, L, TM_R>::NT), (Shape<T, L, TM_R>::MINW))
     __shared__ C tw[L];
     __shared__ T kt[KR * TC * NXH];
     __shared__ unsigned char xf[L];   // x-slabs carrying field (when xcount is given)
-    // Tiles (ky, kz-block) and (ny - ky, kz-block) read the same kernel values.
-    // Workgroups are dispatched round-robin over the 8 XCDs; ids w and w + 8
-    // (same XCD, consecutive) take the two tiles of one mirror pair, so the
-    // second read of each kernel block hits that XCD's L2.  Pair k = 0 holds
-    // the two self-mirrored rows ky = 0 and ky = ny/2.
+    // Tiles (ky, kz-block) and (ny - ky, kz-block) read the same kernel values,
+    // and where a tile's rows are narrower than 128 bytes (TC complex values)
+    // the ZG z-blocks of one 128-byte run share every cache line they read and
+    // write.  Workgroups are dispatched round-robin over the 8 XCDs; ids w,
+    // w + 8, ..., w + 8 (2 ZG - 1) (same XCD, consecutive) take such a group of
+    // 2 ZG tiles, so the other reads of each kernel block and line hit that
+    // XCD's L2 and its partial-line writes merge there.  Pair k = 0 holds the
+    // two self-mirrored rows ky = 0 and ky = ny/2.
     const int nzb = d.nz / TC;
+    constexpr int RUN = TC * (int)sizeof(C);
+    constexpr int ZG = RUN >= 128 ? 1 : 128 / RUN, GM = 2 * ZG;
     int tile = blockIdx.x;
-    if ((((d.ny / 2) * nzb) & 7) == 0) {
+    const int nzg = nzb / ZG;
+    if (nzb % ZG == 0 && (((d.ny / 2) * nzg) & 7) == 0) {
         const int xcd = blockIdx.x & 7, s8 = blockIdx.x >> 3;
-        const int p = (s8 >> 1) * 8 + xcd, member = s8 & 1;
-        const int k = p / nzb, zb = p - (p / nzb) * nzb;
-        const int ky = member == 0 ? k : (k == 0 ? d.ny / 2 : d.ny - k);
+        const int p = (s8 / GM) * 8 + xcd, member = s8 % GM;
+        const int k = p / nzg, zb = (p - k * nzg) * ZG + member % ZG;
+        const int ky = member / ZG == 0 ? k : (k == 0 ? d.ny / 2 : d.ny - k);
         tile = ky * nzb + zb;
     }
     const Tile g = make_tile(AX_X, d, tile, TC);

@@ -90,7 +90,8 @@ def kernel_bytes(kind, n_launch_units, nc, ns, kel, n_data, n_rand, weighted, es
 # sources the kernel is built from; the figure is used only while they match.
 TRAFFIC_SOURCES = ("paper_2108_00015_amd/csrc/fft.hip", "paper_2108_00015_amd/csrc/fft_math.h",
                    "paper_2108_00015_amd/csrc/common.h", "paper_2108_00015_amd/csrc/fused.hip",
-                   "paper_2108_00015_amd/csrc/order.hip", "paper_2108_00015_amd/csrc/support.hip")
+                   "paper_2108_00015_amd/csrc/order.hip", "paper_2108_00015_amd/csrc/support.hip",
+                   "paper_2108_00015_amd/csrc/split3.h", "paper_2108_00015_amd/csrc/batch.hip")
 
 
 def source_hashes(paths=TRAFFIC_SOURCES):
@@ -378,9 +379,8 @@ def bench_mocks(args):
         t = time.perf_counter()
         chosen = ctx.batch_autotune(reps=2)
         tuned = {}
-        for (g, _), c, ch in zip(sizes, chosen, layout):
-            if ch < 0:
-                tuned.setdefault("%d^3" % g, c)
+        for (g, _), c in zip(sizes, chosen):   # a chunk's jobs share its setting
+            tuned.setdefault("%d^3" % g, c)
         log("autotune: %.2f s, %s" % (time.perf_counter() - t, tuned))
     ctx.batch_capture()
     for _ in range(args.warmup):
@@ -416,8 +416,10 @@ def bench_mocks(args):
     roof = None
     if dom is not None and "gbs" in dom[1]:
         ach = dom[1]["bytes_per_launch"] / (dom[1]["avg_launch_ms"] * 1e-3) / 1e9
+        traffic = measured_traffic(dom[0], MOCKS_NAME, args.n)
         roof = dict(bound="hbm", kernel=dom[0], achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(ach / HBM_PEAK_GBS, 4), traffic=None, traffic_unit="bytes/launch",
+                    frac=round(ach / HBM_PEAK_GBS, 4),
+                    traffic=(int(round(traffic)) if traffic is not None else None), traffic_unit="bytes/launch",
                     bytes_per_launch=dom[1]["bytes_per_launch"], avg_launch_ms=dom[1]["avg_launch_ms"],
                     note="launches of one kind differ in grid size; per-launch figures are batch averages")
     xi32 = [j.xi.cpu().numpy() for j in jobs]

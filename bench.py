@@ -286,7 +286,7 @@ def mock_stage_bytes(kind, sizes, ns, npts, nb=8):
     return tot
 
 
-def mocks_cpu_baseline(sizes, cats, radii, n, k=6):
+def mocks_cpu_baseline(sizes, cats, radii, n, k=16):
     """The FP64 oracle on one mock of each grid size (mapping, k shells,
     summation over the tuples of those shells), extrapolated to every shell and
     tuple and to the batch's count of mocks of that size."""
@@ -589,7 +589,7 @@ def main():
     cpu = None
     if not args.no_cpu:
         log("cpu baseline (oracle, bounded sample)")
-        cpu = cpu_baseline(w, data, rand, args.n)
+        cpu = cpu_baseline(w, data, rand, args.n, sample_radii=4)
         log("  %.3f shell-convs/s on %d cores" % (cpu["value"], cpu["cores"]))
 
     s_mixed = mixed["ms"] / 1e3

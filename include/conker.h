@@ -421,7 +421,8 @@ int conker_batch_launch(conker_ctx *ctx);
  * by one, a small grid leaves most of the device idle in every stage.  So
  * conker_batch_plan groups the jobs that share the grid (dimensions, origin,
  * cell), the kernel bank pointer and n_radii (at most 64), with dtype float32,
- * n = 3, split summation (CONKER_MM_SPLIT_BF16 or _F16), 16-byte aligned
+ * n = 3, split or float32 summation (CONKER_MM_SPLIT_BF16, _SPLIT_F16 or
+ * _F32; float32 only where the fused form below applies), 16-byte aligned
  * grids, a grid whose cell count is a multiple of 64 and whose x length has a
  * resident first inverse pass, and buffers (grids, maps, outputs) that no
  * other job of the group touches.  Such a group runs in chunks: every stage
@@ -433,9 +434,10 @@ int conker_batch_launch(conker_ctx *ctx);
  * results are those of the job-by-job path up to the order of float
  * additions (mapping atomics, partial sums).  Jobs with NULL maps keep their
  * maps in a workspace of the chunk, except where every job of the group has
- * NULL maps, CONKER_MM_SPLIT_BF16, at most 16 radii and a z length of 32, 64,
- * 96, 128, 192 or 256: there the last inverse pass and the summation run as
- * one kernel that never stores the maps (all radii transformed at once).  A
+ * NULL maps, CONKER_MM_SPLIT_BF16 or CONKER_MM_F32, at most 16 radii and a z
+ * length of 32, 64, 96, 128, 192 or 256: there the last inverse pass and the
+ * summation run as one kernel that never stores the maps (all radii
+ * transformed at once; float32 products on v_mfma_f32_16x16x4f32).  A
  * chunk's workspace is bounded by 16 GiB
  * (a class of large grids runs in several chunks) and is held by the context
  * until it is destroyed.  A group whose chunks would hold one job each, every

@@ -132,7 +132,8 @@ ChunkLayout chunk_layout(conker_ctx *c, const conker_job &j0, int M, int nb, boo
 bool class_ok(const conker_job &j) {
     const size_t nc = ncells(&j.grid);
     const bool aligned = (((uintptr_t)j.d_N | (uintptr_t)j.d_R) & 15) == 0;
-    return j.dtype == CONKER_F32 && j.n == 3 && (j.prec == CONKER_MM_SPLIT_BF16 || j.prec == CONKER_MM_SPLIT_F16) &&
+    return j.dtype == CONKER_F32 && j.n == 3 &&
+           (j.prec == CONKER_MM_SPLIT_BF16 || j.prec == CONKER_MM_SPLIT_F16 || j.prec == CONKER_MM_F32) &&
            j.n_radii <= 64 && nc % 64 == 0 && aligned && fft_jobs_ok(&j.grid);
 }
 
@@ -210,9 +211,14 @@ int plan_classes(conker_ctx *c) {
         }
         const conker_job &j0 = c->jobs[grp[0]];
         const int nb = std::min(j0.n_radii, CLASS_NB);
-        // maps wanted by no member, split bfloat16: the fused summation where the grid allows
-        bool fused = j0.prec == CONKER_MM_SPLIT_BF16 && fft_mm3_jobs_ok(&j0.grid, j0.n_radii);
+        // maps wanted by no member, split bfloat16 or float32: the fused summation where the grid allows
+        bool fused = (j0.prec == CONKER_MM_SPLIT_BF16 || j0.prec == CONKER_MM_F32) &&
+                     fft_mm3_jobs_ok(&j0.grid, j0.n_radii);
         for (int k : mem) fused = fused && c->jobs[k].d_maps_N == nullptr;
+        if (j0.prec == CONKER_MM_F32 && !fused) {   // the stored-map class summation is split-only
+            for (int k : mem) seq.push_back(k);
+            continue;
+        }
         // greedy chunks under the workspace bound
         std::vector<ClassChunk> mine;
         ClassChunk cur;
@@ -325,7 +331,7 @@ int run_chunk(conker_ctx *c, const ClassChunk &ch) {
     CK_OK(fft_forward_jobs(c, &j0.grid, M, tab, ws + L.spec, scales, (double *)(ws + L.part)));
     if (ch.fused) {
         CK_OK(fft_inverse_mm3_jobs(c, &j0.grid, M, tab, j0.d_kspec, ns, ws + L.spec, ws + L.tspec, scales,
-                                   (double *)(ws + L.c3)));
+                                   (double *)(ws + L.c3), j0.prec));
         CK_OK(reduce3_jobs(c, M, tab, ns, fft_mm3_jobs_blocks(c, M), (const double *)(ws + L.c3),
                            (double *)(ws + L.full3)));
         return ratio_jobs(c, M, tab, 3, conker_num_tuples(ns, 3));

@@ -304,7 +304,7 @@ int map_jobs(conker_ctx *c, const conker_grid *g, int M, const ClassJob *tab, in
 // xi of every job of the table (count tuples of order n).
 int ratio_jobs(conker_ctx *c, int M, const ClassJob *tab, int n, int64_t count);
 // Whether the fused inverse z pass + order-3 summation (k_zinv_mm3_jobs)
-// serves grid g with n_radii = ns (split bfloat16, maps never stored).
+// serves grid g with n_radii = ns (split bfloat16 or float32, maps never stored).
 bool fft_mm3_jobs_ok(const conker_grid *g, int ns);
 // Its workgroups per job (partial tiles: 2 M of them per workgroup column).
 int fft_mm3_jobs_blocks(conker_ctx *ctx, int M);
@@ -312,7 +312,7 @@ int fft_mm3_jobs_blocks(conker_ctx *ctx, int M);
 // the order-3 summation on the fly: partial[(2 job + field) G + workgroup]
 // 32 x 32 float64 tiles, G = fft_mm3_jobs_blocks.
 int fft_inverse_mm3_jobs(conker_ctx *ctx, const conker_grid *g, int M, const ClassJob *tab, const void *kspec, int ns,
-                         const void *spec, void *tspec, const PackScale *scales, double *partial);
+                         const void *spec, void *tspec, const PackScale *scales, double *partial, conker_mmprec prec);
 // The reduction and gather of W_delta and W_R of order 3 from such partials
 // (full: 2 M 1024 (RED_S + 1) doubles).
 int reduce3_jobs(conker_ctx *c, int M, const ClassJob *tab, int ns, int G, const double *partial, double *full);

@@ -1195,8 +1195,10 @@ __global__ __launch_bounds__((Shape<T, L, TM_J>::NT), (Shape<T, L, TM_J>::MINW))
 // leaves C_m on the tile's cells in LDS (both packed fields; R's times
 // 1 / s_j), and the workgroup then sums F(x) C_a(x) C_b(x) over those cells
 // on the matrix cores, as k_mm3s does from stored maps: one 16 x 16 tile per
-// field, split bfloat16, 32 cells per instruction, lane (r, h) = (lane % 16,
-// lane / 16) holding cells 8 h .. 8 h + 7 of a 32-cell chunk for radius r.
+// field, lane (r, h) = (lane % 16, lane / 16) holding cells 8 h .. 8 h + 7 of
+// a 32-cell chunk for radius r; split bfloat16 (32 cells per instruction) or
+// float32 (v_mfma_f32_16x16x4f32, cell 8 h + e of each lane group in the
+// e-th instruction: no operand splitting on the vector units).
 // Slots from n_radii on transform zeros.  Workgroups of job blockIdx.y take
 // tiles blockIdx.x, + gridDim.x, ...; each writes float64 partial tiles (the
 // 32 x 32 layout of the summation, zeros beyond 16 x 16) for N and R of its
@@ -1237,7 +1239,7 @@ struct OpZinvMM {
     }
 };
 
-template <int L, int MODE>
+template <int L, int MODE, int PREC>
 __global__ __launch_bounds__(256, 4) void k_zinv_mm3_jobs(const float2 *__restrict__ tspec,
                                                          const ClassJob *__restrict__ tab,
                                                          const PackScale *__restrict__ scales,
@@ -1298,8 +1300,13 @@ __global__ __launch_bounds__(256, 4) void k_zinv_mm3_jobs(const float2 *__restri
                 b[e] = hm ? mp[e] : 0.f;
                 a[e] = fp[e] * b[e];
             }
-            if (f == 0) mma16_split3(acc0, a, b);
-            else mma16_split3(acc1, a, b);
+            floatx4_t &acc = f == 0 ? acc0 : acc1;
+            if constexpr (PREC == CONKER_MM_F32) {   // float32 products: four cells per instruction
+#pragma unroll
+                for (int e = 0; e < 8; ++e) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e], b[e], acc, 0, 0, 0);
+            } else {
+                mma16_split3(acc, a, b);
+            }
         }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {   // float64 after every tile (at most 2 NCH / NWV chunks of 32 cells)
@@ -1775,7 +1782,9 @@ bool fft_mm3_jobs_ok(const conker_grid *g, int ns) {
 int fft_mm3_jobs_blocks(conker_ctx *ctx, int M) { return std::max(1, 4 * cu_count(ctx) / M); }   // four workgroups per CU
 
 int fft_inverse_mm3_jobs(conker_ctx *ctx, const conker_grid *g, int M, const ClassJob *tab, const void *kspec, int ns,
-                         const void *spec, void *tspec, const PackScale *scales, double *partial) {
+                         const void *spec, void *tspec, const PackScale *scales, double *partial, conker_mmprec prec) {
+    if (prec != CONKER_MM_SPLIT_BF16 && prec != CONKER_MM_F32)
+        return fail(ctx, CONKER_EINVAL, "size class: fused summation in split bfloat16 or float32 only");
     if (!fft_mm3_jobs_ok(g, ns)) return fail(ctx, CONKER_EUNSUPPORTED, "size class: no fused summation for this grid");
     Dims d{g->dims[0], g->dims[1], g->dims[2]};
     const void *twz, *twy, *twx;
@@ -1797,14 +1806,18 @@ int fft_inverse_mm3_jobs(conker_ctx *ctx, const conker_grid *g, int M, const Cla
     auto go = [&](auto Lc) {
         constexpr int LL = decltype(Lc)::value;
         if constexpr (ZMM<LL>::OK) {
-            if (alt && PlanAlt<LL>::has)
-                hipLaunchKernelGGL((k_zinv_mm3_jobs<LL, TM_J | TM_ALT>), dim3((unsigned)G, (unsigned)M), dim3(256), 0,
-                                   ctx->stream, (const float2 *)tspec, tab, scales, (const float2 *)twz, d, nc, ns,
-                                   partial);
-            else
-                hipLaunchKernelGGL((k_zinv_mm3_jobs<LL, TM_J>), dim3((unsigned)G, (unsigned)M), dim3(256), 0,
-                                   ctx->stream, (const float2 *)tspec, tab, scales, (const float2 *)twz, d, nc, ns,
-                                   partial);
+            auto run = [&](auto kern) {
+                hipLaunchKernelGGL(kern, dim3((unsigned)G, (unsigned)M), dim3(256), 0, ctx->stream,
+                                   (const float2 *)tspec, tab, scales, (const float2 *)twz, d, nc, ns, partial);
+            };
+            const bool f32 = prec == CONKER_MM_F32;
+            if (alt && PlanAlt<LL>::has) {
+                if (f32) run(k_zinv_mm3_jobs<LL, TM_J | TM_ALT, CONKER_MM_F32>);
+                else run(k_zinv_mm3_jobs<LL, TM_J | TM_ALT, CONKER_MM_SPLIT_BF16>);
+            } else {
+                if (f32) run(k_zinv_mm3_jobs<LL, TM_J, CONKER_MM_F32>);
+                else run(k_zinv_mm3_jobs<LL, TM_J, CONKER_MM_SPLIT_BF16>);
+            }
         }
     };
     switch (d.nz) {

@@ -134,12 +134,12 @@ def _run_both(ck, jobs, replays=3, **tune):
     return layout, runs, ref
 
 
-@pytest.mark.parametrize("stored,radix", [(False, 0), (True, 0), (False, 2), (True, 2)])
-@pytest.mark.parametrize("prec", ["split_bf16", "split_f16"])
+@pytest.mark.parametrize("prec,stored,radix", [(p, s, r) for p in ("split_bf16", "split_f16") for s in (False, True)
+                                               for r in (0, 2)] + [("f32", False, 0), ("f32", False, 2)])
 def test_classes_match_job_by_job_and_oracle(mocks, oracle_classes, prec, stored, radix):
-    """bf16 without maps: the fused last pass and summation; otherwise maps in
-    the class workspace or the caller's buffers.  radix 2: the radix-16 schedule
-    on the 128-cell axes."""
+    """bf16 and f32 without maps: the fused last pass and summation (f32 on
+    v_mfma_f32_16x16x4f32); otherwise maps in the class workspace or the
+    caller's buffers.  radix 2: the radix-16 schedule on the 128-cell axes."""
     import paper_2108_00015_amd as ck
     _say("classes", prec, "maps given" if stored else "maps in workspace", "radix", radix)
     ctx = ck.Context(0)

@@ -136,18 +136,26 @@ def test_radix_schedules(ck, ctx, dims):
     grid = ck.Grid(dims, (0, 0, 0), 1.0)
     ks, _ = ctx.make_shell_kernels(grid, radii, torch.float32)
     At, Bt = _gpu(A, torch.float32), _gpu(B, torch.float32)
+    dref = [np.array([[np.sum(F * ref[m] ** (p - 1)) for m in range(len(radii))] for p in (2, 3)])
+            for F, ref in ((Af, ref_a), (B, ref_b))]
     for radix in (1, 2):
-        for xt in (1, 2):
-            _say("radix", radix, dims, "x_tile", xt)
-            ctx.set_tune(radix=radix, x_tile=xt, y_tile=xt)
+        for xt, xr in ((1, 0), (2, 0), (2, 1)):
+            _say("radix", radix, dims, "x_tile", xt, "x_resident", xr)
+            ctx.set_tune(radix=radix, x_tile=xt, y_tile=xt, x_resident=xr)
             ma, mb = ctx.convolve_shells(grid, At, Bt, ks)
             ma, mb = ma.cpu().numpy(), mb.cpu().numpy()
             for m in range(len(radii)):
                 ea, eb = relerr(ma[m], ref_a[m]), relerr(mb[m], ref_b[m])
-                assert ea <= 3e-6 and eb <= 3e-6, (radix, xt, m, ea, eb)
+                assert ea <= 3e-6 and eb <= 3e-6, (radix, xt, xr, m, ea, eb)
             Wa, Wb = ctx.convolve_contract(grid, At, Bt, ks, 3, "split_bf16")
             ea, eb = relerr(Wa.cpu().numpy(), wref_a), relerr(Wb.cpu().numpy(), wref_b)
-            assert ea <= 1e-5 and eb <= 1e-5, (radix, xt, ea, eb)
+            assert ea <= 1e-5 and eb <= 1e-5, (radix, xt, xr, ea, eb)
+            # equidistant sums streamed out of the last pass (n = 2, 3)
+            da, db = ctx.convolve_diag(grid, At, Bt, ks, 3)
+            for got, ref in ((da, dref[0]), (db, dref[1])):
+                for p in range(2):
+                    e = relerr(got.cpu().numpy()[p], ref[p])
+                    assert e <= 1e-5, (radix, xt, xr, p, e)
 
 
 @pytest.mark.parametrize("rb", [1, 3])

@@ -195,3 +195,54 @@ def test_classes_forty_shells_and_aliasing():
     _say("  per tuple W_delta", np.abs(_pick(got[:nt], len(WIDE_RADII), tl) - rd) / np.abs(rd).max())
     assert ed <= 1e-5 and er <= 1e-5
     ctx.close()
+
+
+def test_mock_batch_full_size_as_benched():
+    """The 64-mock batch exactly as bench.py times it (grids 96..256 cells,
+    50k..400k clustered points + 10x randoms, 16 shells, split-bf16, per-job
+    grids, no map buffers: size classes with the fused last pass and
+    summation, captured as one graph): one mock of each grid size against the
+    oracle on the tuples among three sampled shells, and alpha; the graph
+    replay against the eager planning pass for every mock."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2108_00015_amd as ck
+    sizes = synth.mock_sizes(64, 400)
+    cats = [synth.mock_catalog(j, g, n) for j, (g, n) in enumerate(sizes)]
+    dev = "cuda:0"
+    s = torch.cuda.Stream()
+    ctx = ck.Context(0, stream=s)
+    kspecs, jobs = {}, []
+    for (g, _), (d, r) in zip(sizes, cats):
+        grid = ck.Grid((g, g, g), (0.0, 0.0, 0.0), CELL)
+        if g not in kspecs:
+            kspecs[g] = ctx.make_shell_kernels(grid, RADII, torch.float32)[0]
+        jobs.append(ck.make_job(grid, kspecs[g], 3, "split_bf16", torch.from_numpy(d.pos).to(dev),
+                                torch.from_numpy(r.pos).to(dev), fused=True))
+    torch.cuda.synchronize()
+    ctx.batch_plan(jobs)
+    layout = ctx.batch_layout()
+    _say("full mock batch, chunks", sorted(set(layout)), "alone", layout.count(-1))
+    assert min(layout) >= 0   # every mock runs in a size class
+    first = _outs(jobs)
+    ctx.batch_capture()
+    for j in jobs:
+        j.W_delta.fill_(7.0)
+        j.W_rand.fill_(-3.0)
+    torch.cuda.synchronize()
+    ctx.batch_launch()
+    ctx.synchronize()
+    again = _outs(jobs)
+    nt = len(jobs[0].W_delta)
+    for k in range(len(jobs)):
+        assert _rel(again[k][:3 * nt], first[k][:3 * nt]) <= 1e-5, k
+    ns = len(RADII)
+    for g in sorted({g for g, _ in sizes}):
+        k = next(i for i, (gg, _) in enumerate(sizes) if gg == g)
+        alpha, tl, rd, rr = _oracle(cats[k], g, CELL, RADII, SAMPLE)
+        got = again[k]
+        ed, er = _rel(_pick(got[:nt], ns, tl), rd), _rel(_pick(got[nt:2 * nt], ns, tl), rr)
+        _say("  mock %d (%d^3): W_delta %.3e W_R %.3e" % (k, g, ed, er))
+        assert ed <= 1e-5 and er <= 1e-5
+        assert abs(got[3 * nt] - alpha) <= 1e-13 * alpha
+    ctx.close()

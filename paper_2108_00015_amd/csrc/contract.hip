@@ -1346,6 +1346,135 @@ __global__ __launch_bounds__(NT) void k_mm3s(const float *__restrict__ F, const 
     }
 }
 
+// n = 3, split bfloat16, 33..16 NG radii (NG = 3): NG groups of 16 radii, one 16 x 16
+// tile (v_mfma_f32_16x16x32_bf16) for every pair of groups gi <= gj, 32 cells
+// per instruction (the 32 x 32 tiles of k_mm3 carry up to 31 rows of padding
+// here and twice the instruction cycles per cell).  Lane (r, h) holds map
+// 16 g + r of every group at cells 8 h .. 8 h + 7 of its wave's 32; each map
+// is split once as a column operand and once (times F) as a row operand.  The
+// 16 x 16 tiles are written into the three 32 x 32 partial tiles of the
+// summation plan (rows a, columns b >= a: tile 0 = (a, b) < 32, tile 1 =
+// a < 32 <= b, tile 2 = 32 <= a, b), zeros elsewhere.
+template <int NG>
+__global__ __launch_bounds__(NT) void k_mm3g(const float *__restrict__ F, const float *__restrict__ maps, size_t nc,
+                                             const int *__restrict__ list, const int *__restrict__ count, int ns,
+                                             double *__restrict__ partial, const ClassJob *__restrict__ tab) {
+    constexpr int NTT = NG * (NG + 1) / 2, FLUSH = 4;
+    if (tab) {
+        const ClassJob &jb = tab[blockIdx.y >> 1];
+        const bool fr = blockIdx.y & 1;
+        F = fr ? jb.R : jb.N;
+        maps = fr ? jb.mapsR : jb.mapsN;
+        partial += (size_t)blockIdx.y * 3 * gridDim.x * 1024;
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int r = lane & 15, h = lane >> 4;
+    const float *pg[NG];
+    bool hg[NG];
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+        const int m = 16 * g + r;
+        hg[g] = m < ns;
+        pg[g] = maps + (size_t)(hg[g] ? m : 0) * nc;
+    }
+    floatx4_t acc[NTT];
+    double accd[NTT][4];
+#pragma unroll
+    for (int t = 0; t < NTT; ++t) {
+        acc[t] = floatx4_t{0};
+#pragma unroll
+        for (int v = 0; v < 4; ++v) accd[t][v] = 0.0;
+    }
+    float f[8], c[NG][8];
+    const Blocks bk = my_blocks(list, count, nc);
+    const int half = w & 1, pairw = w >> 1;
+    auto load = [&](int k) {   // as k_mm3s: two waves per block, two blocks per step
+        const int kb = k + pairw;
+        const bool inb = kb < bk.k1;
+        const size_t xw = bk.first(inb ? kb : k) + (size_t)half * 32 + 8 * h;
+        const bool in = inb && xw < nc;
+        const size_t x = in ? xw : 0;
+        ld<float, 8>(F + x, f);
+#pragma unroll
+        for (int g = 0; g < NG; ++g) ld<float, 8>(pg[g] + x, c[g]);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            f[e] = in ? f[e] : 0.f;
+#pragma unroll
+            for (int g = 0; g < NG; ++g) c[g][e] = hg[g] ? c[g][e] : 0.f;
+        }
+    };
+    if (bk.k0 < bk.k1) load(bk.k0);
+    for (int k = bk.k0; k < bk.k1;) {
+        const int kend = k + 2 * FLUSH < bk.k1 ? k + 2 * FLUSH : bk.k1;
+        for (; k < kend; k += 2) {
+            float fc[8], cc[NG][8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                fc[e] = f[e];
+#pragma unroll
+                for (int g = 0; g < NG; ++g) cc[g][e] = c[g][e];
+            }
+            load(k + 2 < bk.k1 ? k + 2 : k);
+            bf16x8_t bh[NG], bm[NG], bl[NG];
+#pragma unroll
+            for (int g = 0; g < NG; ++g) split3(cc[g], bh[g], bm[g], bl[g]);
+            int t = 0;
+#pragma unroll
+            for (int gi = 0; gi < NG; ++gi) {
+                float a[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) a[e] = fc[e] * cc[gi][e];
+                bf16x8_t ah, am, al;
+                split3(a, ah, am, al);
+#pragma unroll
+                for (int gj = gi; gj < NG; ++gj, ++t) {
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[gj], acc[t], 0, 0, 0);
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bm[gj], acc[t], 0, 0, 0);
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[gj], acc[t], 0, 0, 0);
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh[gj], acc[t], 0, 0, 0);
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm[gj], acc[t], 0, 0, 0);
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[gj], acc[t], 0, 0, 0);
+                }
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < NTT; ++t) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) accd[t][v] += (double)acc[t][v];
+            acc[t] = floatx4_t{0};
+        }
+    }
+    // the workgroup's three 32 x 32 partial tiles: zeros, then each 16 x 16
+    // tile summed over the waves (element (i, j) of a tile: lane j + 16 (i / 4),
+    // register i % 4) at rows 16 gi + i, columns 16 gj + j
+    __shared__ double red[WAVES * 4 * 64];
+    const int G = gridDim.x;
+    for (int e = threadIdx.x; e < 3 * 1024; e += NT) partial[((size_t)(e >> 10) * G + blockIdx.x) * 1024 + (e & 1023)] = 0.0;
+    int t = 0;
+#pragma unroll
+    for (int gi = 0; gi < NG; ++gi) {
+#pragma unroll
+        for (int gj = gi; gj < NG; ++gj, ++t) {
+            __syncthreads();   // the previous tile's reads of red (and the zeros) are done
+#pragma unroll
+            for (int v = 0; v < 4; ++v) red[(w * 4 + v) * 64 + lane] = accd[t][v];
+            __syncthreads();
+            const int tile = gi < 2 ? (gj < 2 ? 0 : 1) : 2;
+            double *out = partial + ((size_t)tile * G + blockIdx.x) * 1024;
+            const int r0 = (gi & 1) * 16, c0 = (gj & 1) * 16;
+            for (int e = threadIdx.x; e < 256; e += NT) {
+                const int i = e >> 4, j = e & 15;
+                const int l = j + 16 * (i >> 2), v = i & 3;
+                double sum = 0.0;
+#pragma unroll
+                for (int q = 0; q < WAVES; ++q) sum += red[(q * 4 + v) * 64 + l];
+                out[(r0 + i) * 32 + c0 + j] = sum;
+            }
+        }
+    }
+}
+
 template <int NBW>
 int launch_mm(conker_ctx *c, conker_mmprec prec, dim3 grid, const void *F, const void *maps, size_t nc,
               const int *list, const int *count, const Items *tab, int n_tiles, double *part, int ns,
@@ -1502,7 +1631,10 @@ extern "C" int conker_contract_npt(conker_ctx *c, const conker_grid *g, conker_d
             } else if (RT == 1) {
                 if (prec == CONKER_MM_SPLIT_F16) go(k_mm3<1, CONKER_MM_SPLIT_F16, true>);
                 else go(k_mm3<1, CONKER_MM_SPLIT_BF16, true>);
-            } else {
+            } else if (prec == CONKER_MM_SPLIT_BF16 && ns <= 48) {   // 16 x 16 tiles over three groups of radii
+                hipLaunchKernelGGL(k_mm3g<3>, dim3((unsigned)G), dim3(NT), 0, c->stream, (const float *)F,
+                                   (const float *)maps, nc, blist, bcount, ns, part, (const ClassJob *)nullptr);
+            } else {   // four groups would need more registers than two waves per SIMD allow
                 if (prec == CONKER_MM_SPLIT_F16) go(k_mm3<2, CONKER_MM_SPLIT_F16, false>);
                 else go(k_mm3<2, CONKER_MM_SPLIT_BF16, false>);
             }
@@ -1647,6 +1779,9 @@ int contract3_jobs(conker_ctx *c, const conker_grid *g, int M, const ClassJob *t
         } else if (L.ntl == 1) {
             if (prec == CONKER_MM_SPLIT_F16) go(k_mm3<1, CONKER_MM_SPLIT_F16, true>);
             else go(k_mm3<1, CONKER_MM_SPLIT_BF16, true>);
+        } else if (prec == CONKER_MM_SPLIT_BF16 && ns <= 48) {
+            hipLaunchKernelGGL(k_mm3g<3>, grid, dim3(NT), 0, c->stream, (const float *)nullptr, (const float *)nullptr,
+                               nc, (const int *)nullptr, (const int *)nullptr, ns, part, tab);
         } else {
             if (prec == CONKER_MM_SPLIT_F16) go(k_mm3<2, CONKER_MM_SPLIT_F16, false>);
             else go(k_mm3<2, CONKER_MM_SPLIT_BF16, false>);

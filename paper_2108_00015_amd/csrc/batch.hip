@@ -327,8 +327,10 @@ int run_chunk(conker_ctx *c, const ClassChunk &ch) {
     const ClassJob *tab = (const ClassJob *)((const char *)c->cls.p + ch.tab_off);
     char *ws = (char *)c->cls.p + c->cls_ws_off;
     PackScale *scales = (PackScale *)(ws + L.scales);
-    CK_OK(map_jobs(c, &j0.grid, M, tab, n_max, n_total, L.bytes > L.bins ? ws + L.bins : nullptr));
-    CK_OK(fft_forward_jobs(c, &j0.grid, M, tab, ws + L.spec, scales, (double *)(ws + L.part)));
+    int sums_G = 0;
+    CK_OK(map_jobs(c, &j0.grid, M, tab, n_max, n_total, L.bytes > L.bins ? ws + L.bins : nullptr,
+                   (double *)(ws + L.part), &sums_G));
+    CK_OK(fft_forward_jobs(c, &j0.grid, M, tab, ws + L.spec, scales, (const double *)(ws + L.part), sums_G));
     if (ch.fused) {
         CK_OK(fft_inverse_mm3_jobs(c, &j0.grid, M, tab, j0.d_kspec, ns, ws + L.spec, ws + L.tspec, scales,
                                    (double *)(ws + L.c3), j0.prec));

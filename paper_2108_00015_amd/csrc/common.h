@@ -282,9 +282,10 @@ struct ClassJob {
     double *Wd, *Wr, *xi;      // [tuples]
 };
 // Forward transforms of all M jobs: spec[j] (complex [nc], contiguous by job)
-// of N_j + i s_j R_j, s_j into scales[j]; part holds M * 4 * cu_count pairs.
-int fft_forward_jobs(conker_ctx *c, const conker_grid *g, int M, const ClassJob *tab, void *spec,
-                     PackScale *scales, double *part);
+// of N_j + i s_j R_j, s_j into scales[j] chosen from the sums of squares in
+// part (sums_G pairs per job, as map_jobs leaves them).
+int fft_forward_jobs(conker_ctx *ctx, const conker_grid *g, int M, const ClassJob *tab, void *spec,
+                     PackScale *scales, const double *part, int sums_G);
 // Inverse transforms of radii [m0, m0 + nb) of all M jobs: tspec[j][0 .. nb)
 // (contiguous), then the maps of job j into tab[j].mapsN / mapsR rows m0 ..
 // (maps of R multiplied by 1 / s_j).
@@ -298,9 +299,11 @@ bool fft_jobs_ok(const conker_grid *g);
 // binned mapping's bricks; n_total: all points of the table) the points are
 // binned by brick and summed in LDS, each brick written whole; else the grids
 // are zeroed and the points added with atomics (n_max: the largest catalog).
+// Both fields' sums of squares go to part (pairs per workgroup, *sums_G
+// workgroups per job, at most 4 cu_count / M + 1) for fft_forward_jobs.
 size_t map_jobs_bytes(const conker_grid *g, int M, int64_t n_total);
 int map_jobs(conker_ctx *c, const conker_grid *g, int M, const ClassJob *tab, int64_t n_max, int64_t n_total,
-             void *ws);
+             void *ws, double *part, int *sums_G);
 // xi of every job of the table (count tuples of order n).
 int ratio_jobs(conker_ctx *c, int M, const ClassJob *tab, int n, int64_t count);
 // Whether the fused inverse z pass + order-3 summation (k_zinv_mm3_jobs)

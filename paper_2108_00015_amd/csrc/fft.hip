@@ -438,14 +438,6 @@ __global__ __launch_bounds__(PS_T) void k_pack_sums(const T *__restrict__ a, con
     pack_sums_body<T, PV>(a, b, n, part);
 }
 
-// The same for every job of a size class (job = blockIdx.y): partial pairs at
-// part + 2 (job * gridDim.x + workgroup).
-__global__ __launch_bounds__(PS_T) void k_pack_sums_jobs(const ClassJob *__restrict__ tab, size_t n,
-                                                         double *__restrict__ part) {
-    const ClassJob &j = tab[blockIdx.y];
-    pack_sums_body<float, 4>(j.N, j.R, n, part + 2 * (size_t)blockIdx.y * gridDim.x);
-}
-
 template <typename T, int PV>
 __device__ __forceinline__ void pack_sums_body(const T *__restrict__ a, const T *__restrict__ b, size_t n,
                                                double *__restrict__ part) {
@@ -1731,7 +1723,7 @@ bool fft_jobs_ok(const conker_grid *g) {
 }
 
 int fft_forward_jobs(conker_ctx *ctx, const conker_grid *g, int M, const ClassJob *tab, void *spec,
-                     PackScale *scales, double *part) {
+                     PackScale *scales, const double *part, int sums_G) {
     Dims d{g->dims[0], g->dims[1], g->dims[2]};
     const void *twz, *twy, *twx;
     CK_OK(twiddles(ctx, d.nz, false, &twz));
@@ -1739,14 +1731,8 @@ int fft_forward_jobs(conker_ctx *ctx, const conker_grid *g, int M, const ClassJo
     CK_OK(twiddles(ctx, d.nx, false, &twx));
     const size_t nc = ncells(g);
     {
-        ProfScope ps(ctx, PK_PACK_SCALE);
-        const int G = (int)std::max<size_t>(1, std::min<size_t>((size_t)4 * cu_count(ctx) / (size_t)M + 1,
-                                                                (nc / 4 + PS_T - 1) / PS_T));
-        hipLaunchKernelGGL(k_pack_sums_jobs, dim3((unsigned)G, (unsigned)M), dim3(PS_T), 0, ctx->stream, tab, nc,
-                           part);
-        CK_LAUNCH(ctx);
-        hipLaunchKernelGGL(k_pack_scale, dim3((unsigned)M), dim3(PSR_T), 0, ctx->stream, (const double *)part, G,
-                           scales);
+        ProfScope ps(ctx, PK_PACK_SCALE_REDUCE);
+        hipLaunchKernelGGL(k_pack_scale, dim3((unsigned)M), dim3(PSR_T), 0, ctx->stream, part, sums_G, scales);
         CK_LAUNCH(ctx);
     }
     OpPackJobs pz{twz, d, tab, (float2 *)spec, nc, scales, {}, nullptr, nullptr, nullptr, 1.f};

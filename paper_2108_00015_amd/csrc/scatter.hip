@@ -514,14 +514,18 @@ __global__ __launch_bounds__(256) void k_zero_jobs(const conker::ClassJob *__res
     }
 }
 
-// Size classes: N = D - alpha R of job blockIdx.y in place (as k_form_delta).
-__global__ __launch_bounds__(256) void k_form_delta_jobs(const conker::ClassJob *__restrict__ tab, size_t nc) {
+// Size classes: N = D - alpha R of job blockIdx.y in place (as k_form_delta),
+// and the sums of squares of N and R that the packed transform's scale is
+// chosen from (the pair of workgroup x of job y at part + 2 (y gridDim.x + x)).
+__global__ __launch_bounds__(256) void k_form_delta_jobs(const conker::ClassJob *__restrict__ tab, size_t nc,
+                                                         double *__restrict__ part) {
     const conker::ClassJob &j = tab[blockIdx.y];
     const double alpha = j.wsum[0] / j.wsum[1];
     const size_t t0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (size_t)gridDim.x * blockDim.x;
     if (t0 == 0) *j.alpha = alpha;
     float4 *D = reinterpret_cast<float4 *>(j.N);
     const float4 *R = reinterpret_cast<const float4 *>(j.R);
+    double sa = 0.0, sb = 0.0;
     for (size_t i = t0; i < nc / 4; i += stride) {
         float4 d = D[i];
         const float4 r = R[i];
@@ -530,7 +534,23 @@ __global__ __launch_bounds__(256) void k_form_delta_jobs(const conker::ClassJob 
         d.z = (float)((double)d.z - alpha * (double)r.z);
         d.w = (float)((double)d.w - alpha * (double)r.w);
         D[i] = d;
+        sa += (double)d.x * d.x + (double)d.y * d.y + (double)d.z * d.z + (double)d.w * d.w;
+        sb += (double)r.x * r.x + (double)r.y * r.y + (double)r.z * r.z + (double)r.w * r.w;
     }
+    for (int o = 32; o >= 1; o >>= 1) {
+        sa += __shfl_xor(sa, o);
+        sb += __shfl_xor(sb, o);
+    }
+    __shared__ double red[4][2];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[wv][0] = sa;
+        red[wv][1] = sb;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2)
+        part[2 * ((size_t)blockIdx.y * gridDim.x + blockIdx.x) + threadIdx.x] =
+            red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
 }
 
 }  // namespace
@@ -566,7 +586,7 @@ size_t map_jobs_bytes(const conker_grid *g, int M, int64_t n_total) {
 }
 
 int map_jobs(conker_ctx *c, const conker_grid *g, int M, const ClassJob *tab, int64_t n_max, int64_t n_total,
-             void *ws) {
+             void *ws, double *part, int *sums_G) {
     const size_t nc = ncells(g);
     if (nc % 4) return fail(c, CONKER_EINVAL, "size class: cell count must be a multiple of 4");
     const GridGeom gg{g->origin[0], g->origin[1], g->origin[2], g->cell, g->dims[0], g->dims[1], g->dims[2]};
@@ -606,8 +626,9 @@ int map_jobs(conker_ctx *c, const conker_grid *g, int M, const ClassJob *tab, in
         }
     }
     ProfScope ps(c, PK_FORM_DELTA);
-    hipLaunchKernelGGL(k_form_delta_jobs, dim3(zb, (unsigned)M), dim3(256), 0, c->stream, tab, nc);
+    hipLaunchKernelGGL(k_form_delta_jobs, dim3(zb, (unsigned)M), dim3(256), 0, c->stream, tab, nc, part);
     CK_LAUNCH(c);
+    *sums_G = (int)zb;
     return CONKER_OK;
 }
 

@@ -647,24 +647,31 @@ __global__ __launch_bounds__(V2_NT) void k_mm2(const float *__restrict__ F, cons
     }
     // staging of 64 cells: (ns + 1) * 16 float4, at most V2_PRE per thread
     const int nst = (ns + 1) * 16;
-    float4 pre[V2_PRE];
+    // Three named registers rather than an array: an array that the loads
+    // and stores reach through these lambdas ends up in scratch memory,
+    // where each load is waited for on the spot instead of in flight while
+    // the previous 64 cells are summed.
+    static_assert(V2_PRE == 3, "staging registers");
+    float4 pre0, pre1, pre2;
+    auto load1 = [&](int k, size_t x) {
+        const int e = min((int)threadIdx.x + k * V2_NT, nst - 1);   // past the end: repeat the last entry
+        const int row = e >> 4, q = e & 15;
+        const float *src = row < ns ? maps + (size_t)row * nc + x + 4 * q : F + x + 4 * q;
+        return *reinterpret_cast<const float4 *>(src);
+    };
     auto fetch = [&](size_t x) {
-#pragma unroll
-        for (int k = 0; k < V2_PRE; ++k) {
-            const int e = threadIdx.x + k * V2_NT;
-            if (e < nst) {
-                const int row = e >> 4, q = e & 15;
-                const float *src = row < ns ? maps + (size_t)row * nc + x + 4 * q : F + x + 4 * q;
-                pre[k] = *reinterpret_cast<const float4 *>(src);
-            }
-        }
+        pre0 = load1(0, x);
+        pre1 = load1(1, x);
+        pre2 = load1(2, x);
+    };
+    auto put1 = [&](float *dst, int k, float4 v) {
+        const int e = threadIdx.x + k * V2_NT;
+        if (e < nst) reinterpret_cast<float4 *>(dst + (e >> 4) * V2_SROW)[e & 15] = v;
     };
     auto put = [&](float *dst) {
-#pragma unroll
-        for (int k = 0; k < V2_PRE; ++k) {
-            const int e = threadIdx.x + k * V2_NT;
-            if (e < nst) reinterpret_cast<float4 *>(dst + (e >> 4) * V2_SROW)[e & 15] = pre[k];
-        }
+        put1(dst, 0, pre0);
+        put1(dst, 1, pre1);
+        put1(dst, 2, pre2);
     };
     // rows P_a = F C_a of a staged buffer (after its maps and F are visible)
     auto products = [&](float *buf) {

@@ -578,7 +578,18 @@ def main():
     # dominant kernel: largest time per step
     dom = max(stages.items(), key=lambda kv: kv[1]["ms_per_step"]) if stages else None
     roof = None
-    if dom is not None and "gbs" in dom[1]:
+    if dom is not None and dom[0] == "contract_mm" and args.n >= 4:
+        # orders 4 and 5 are bound by the matrix cores: issued matrix flops
+        # (every split product counted) per launch against the dense peak of
+        # the operand type; the unsplit count is the algorithmic one
+        ent = dom[1]
+        issued = ent["mfma_issued_tflops"] * 1e12 * ent["avg_launch_ms"] * 1e-3
+        peak = MFMA_PEAK_TFLOPS[args.prec]
+        roof = dict(bound="mfma", kernel=dom[0], achieved=ent["mfma_issued_tflops"], peak=peak, unit="TFLOP/s",
+                    frac=round(ent["mfma_issued_tflops"] / peak, 4), traffic=None,
+                    flops_per_launch=issued, algorithmic_flops_per_launch=issued / TERM_PRODUCTS[args.prec],
+                    term_products=TERM_PRODUCTS[args.prec], avg_launch_ms=ent["avg_launch_ms"])
+    elif dom is not None and "gbs" in dom[1]:
         ach = dom[1]["bytes_per_launch"] / (dom[1]["avg_launch_ms"] * 1e-3) / 1e9
         traffic = measured_traffic(dom[0], w.name, args.n)
         roof = dict(bound="hbm", kernel=dom[0], achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",

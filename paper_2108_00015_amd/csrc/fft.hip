@@ -175,6 +175,58 @@ __device__ __forceinline__ void stage_sync() {
 // writes dst (LDS; global memory for the last stage).  SYNC: the stage places
 // its own barriers (src == dst, in place); otherwise the caller orders the
 // buffers.  PADX >= 0 overrides the tile's row padding.
+// Ops that know their keep bits in advance (the same rows for every call on a
+// tile) expose KBITS and kb: the bits of the last stage, one word per
+// butterfly of this thread, as last_keep_bits computes them.
+template <class Op, class = void>
+struct has_kbits : std::false_type {};
+template <class Op>
+struct has_kbits<Op, std::enable_if_t<Op::KBITS>> : std::true_type {};
+
+// Shape of the last stage of a line transform.
+template <typename T, int L, int MODE>
+struct LastStage {
+    using SH = Shape<T, L, MODE>;
+    static constexpr int S = PlanM<L, MODE>::n - 1;
+    static constexpr int R = PlanM<L, MODE>::r[S];
+    static constexpr int NSV = stage_ns<L, MODE, S>();
+    static constexpr int LR = L / R;
+    static constexpr int NB = LR * SH::TC;
+    static constexpr int PER = (NB + SH::NT - 1) / SH::NT;
+};
+
+// Keep bits of the last stage: bit r of word q is set iff row base + r NSV of
+// butterfly q of this thread is written (op.flag of that row is nonzero).
+template <typename T, int L, int MODE, class Op>
+__device__ __forceinline__ void last_keep_bits(const Op &op, unsigned (&kbits)[LastStage<T, L, MODE>::PER]) {
+    using LS = LastStage<T, L, MODE>;
+    constexpr int R = LS::R, NSV = LS::NSV, LR = LS::LR, NB = LS::NB, PER = LS::PER;
+    constexpr int NT = Shape<T, L, MODE>::NT, TC = Shape<T, L, MODE>::TC;
+    static_assert(R <= 16, "keep flags are packed 16 per butterfly");
+    if (op.keeps()) {
+        int fl[PER][R];
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int b = threadIdx.x + q * NT;
+            int j, c;
+            split_q<NT, MODE, LR, TC>(q, j, c);
+            const int k = j & (NSV - 1);
+            const int base = (NB % NT == 0 || b < NB) ? (j - k) * R + k : 0;
+#pragma unroll
+            for (int r = 0; r < R; ++r) fl[q][r] = op.flag(base + r * NSV);   // base + r NSV < L
+        }
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            kbits[q] = 0;
+#pragma unroll
+            for (int r = 0; r < R; ++r) kbits[q] |= fl[q][r] != 0 ? (1u << r) : 0u;
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) kbits[q] = 0xffffu;
+    }
+}
+
 template <typename T, int L, int MODE, int DIR, int S, bool STAGED, bool SYNC = true, int PADX = -1, class Op>
 __device__ __forceinline__ void fft_stage(const cplx<T> *src, cplx<T> *dst, const cplx<T> *tw, Op &op) {
     using C = cplx<T>;
@@ -193,27 +245,12 @@ __device__ __forceinline__ void fft_stage(const cplx<T> *src, cplx<T> *dst, cons
     static_assert(!KEEP || R <= 16, "keep flags are packed 16 per butterfly");
     unsigned kbits[PER];
     if constexpr (KEEP) {
-        if (op.keeps()) {
-            int fl[PER][R];
+        static_assert(!KEEP || PER == LastStage<T, L, MODE>::PER, "last stage shape");
+        if constexpr (has_kbits<Op>::value) {
 #pragma unroll
-            for (int q = 0; q < PER; ++q) {
-                const int b = threadIdx.x + q * NT;
-                int j, c;
-                split_q<NT, MODE, LR, TC>(q, j, c);
-                const int k = j & (NSV - 1);
-                const int base = (NB % NT == 0 || b < NB) ? (j - k) * R + k : 0;
-#pragma unroll
-                for (int r = 0; r < R; ++r) fl[q][r] = op.flag(base + r * NSV);   // base + r NSV < L
-            }
-#pragma unroll
-            for (int q = 0; q < PER; ++q) {
-                kbits[q] = 0;
-#pragma unroll
-                for (int r = 0; r < R; ++r) kbits[q] |= fl[q][r] != 0 ? (1u << r) : 0u;
-            }
+            for (int q = 0; q < PER; ++q) kbits[q] = op.kb[q];
         } else {
-#pragma unroll
-            for (int q = 0; q < PER; ++q) kbits[q] = 0xffffu;
+            last_keep_bits<T, L, MODE>(op, kbits);
         }
     }
     C v[PER][R];
@@ -909,12 +946,14 @@ struct OpExtract {
 template <typename T, int L, int TC, int PER0, bool PAIR = false>
 struct OpResident {
     static constexpr bool STAGED = false;
+    static constexpr bool KBITS = true;
     using C = cplx<T>;
     const C (*sreg)[8];   // registers: this thread's first-stage inputs [PER0][8]
     const T *kt;          // LDS: kernel values [TC][L/2 + 1]; with PAIR a second such block (radius b)
     C *out;               // global: output tile base
     unsigned si;
     const unsigned char *xf;   // LDS: x-slab carries field (row written), or NULL: every row
+    const unsigned *kb;        // registers: the last stage's keep bits, taken once per tile
     __device__ C load_r(int q, int r, int i, int c) const {
         const C s = sreg[q][r];
         const int e = c * (L / 2 + 1) + (i <= L - i ? i : L - i);
@@ -1037,6 +1076,14 @@ __global__ __launch_bounds__((Shape<T, L, TM_R>::NT), (Shape<T, L, TM_R>::MINW))
             if (e < KR * TC * NXH) kt[e] = kv[q];
         }
     };
+    // the last stage's keep bits: the same rows for every radius of the tile
+    __syncthreads();   // xf written
+    unsigned kmask[LastStage<T, L, TM_R>::PER];
+    {
+        const OpResident<T, L, TC, PER0, PAIR> op0{sreg, kt, tspec + g.base, (unsigned)g.si, xcount ? xf : nullptr,
+                                                   nullptr};
+        last_keep_bits<T, L, TM_R>(op0, kmask);
+    }
     T kv[KPT];
     kload(0, kv);
     if constexpr (PP) {
@@ -1053,7 +1100,7 @@ __global__ __launch_bounds__((Shape<T, L, TM_R>::NT), (Shape<T, L, TM_R>::MINW))
         C *const la = lds, *const lb = lds + LDSN;
         for (int m = 0; m < nb; ++m) {
             OpResident<T, L, TC, PER0, PAIR> op{sreg, kt, tspec + (size_t)m * nc + g.base, (unsigned)g.si,
-                                                xcount ? xf : nullptr};
+                                                xcount ? xf : nullptr, kmask};
             fft_stage<T, L, TM_R, +1, 0, false, false, PADR>(la, la, tw, op);
             __syncthreads();
             fft_stage<T, L, TM_R, +1, 1, false, false, PADR>(la, lb, tw, op);
@@ -1070,7 +1117,7 @@ __global__ __launch_bounds__((Shape<T, L, TM_R>::NT), (Shape<T, L, TM_R>::MINW))
             __syncthreads();
             if (m + 1 < nb) kload(m + 1, kv);
             OpResident<T, L, TC, PER0, PAIR> op{sreg, kt, tspec + (size_t)m * nc + g.base, (unsigned)g.si,
-                                                xcount ? xf : nullptr};
+                                                xcount ? xf : nullptr, kmask};
             fft_line_tile<T, L, TM_R, +1, false>(lds, tw, op);
             __syncthreads();
         }

@@ -597,7 +597,12 @@ __global__ __launch_bounds__(V2_NT) void k_mm2(const float *__restrict__ F, cons
     // build units of this thread: unit u -> (item, half); items of A first, then B
     // Each unit builds v = S[r0] * S[r1] over 8 cells from two staged rows
     // (P_a, a map or zeros; a map or ones), with no branches, and stores it at
-    // operand offset uoff (-1: no such unit).
+    // operand offset uoff = 2 item + half (-1: no such unit).  The 32 lanes of
+    // a half-wave take the same half of 32 consecutive items, so that their
+    // stores are contiguous.
+    // Operand layout (bf16 / fp16): planes, then halves, then rows: element
+    // (plane p, half h, row i) at (p * 2 + h) * rows + i, 16 bytes each, so the
+    // 32 lanes that load one half of a 32-row tile read 512 contiguous bytes.
     const int a_units = na * 2;   // operand offsets below this are rows of A, the rest of B
     int urow[V2_MAXU][2];
     int uoff[V2_MAXU];
@@ -605,7 +610,7 @@ __global__ __launch_bounds__(V2_NT) void k_mm2(const float *__restrict__ F, cons
 #pragma unroll
     for (int k = 0; k < V2_MAXU; ++k) {
         const int u = threadIdx.x + k * V2_NT;
-        const int item = u >> 1, half = u & 1;
+        const int item = ((u >> 6) << 5) | (u & 31), half = (u >> 5) & 1;
         int2 it;
         if (item < na) it = ritems[gr.rt0 * 32 + item];
         else if (item < na + nb) it = citems[gr.ct0 * 32 + (item - na)];
@@ -702,7 +707,7 @@ __global__ __launch_bounds__(V2_NT) void k_mm2(const float *__restrict__ F, cons
             // build the operands of 16 cells
 #pragma unroll
             for (int k = 0; k < V2_MAXU; ++k) {
-                const int half = (threadIdx.x + k * V2_NT) & 1;
+                const int half = ((threadIdx.x + k * V2_NT) >> 5) & 1;
                 const int cb = sub * 16 + half * 8;
                 float v[8];
                 {
@@ -718,21 +723,22 @@ __global__ __launch_bounds__(V2_NT) void k_mm2(const float *__restrict__ F, cons
                 unsigned char *dst = isA ? sA : sB;
                 const int ro = isA ? o : o - a_units;   // (row * 2 + half) within its operand
                 const int nrows = isA ? na : nb;
+                const int hr = (ro & 1) * nrows + (ro >> 1);   // (half, row) within a plane
                 if constexpr (SPLIT) {
                     bf16x8 hi, mi, lo;
                     split3(v, hi, mi, lo);
                     bf16x8 *d = reinterpret_cast<bf16x8 *>(dst);
-                    d[0 * nrows * 2 + ro] = hi;
-                    d[1 * nrows * 2 + ro] = mi;
-                    d[2 * nrows * 2 + ro] = lo;
+                    d[0 * nrows * 2 + hr] = hi;
+                    d[1 * nrows * 2 + hr] = mi;
+                    d[2 * nrows * 2 + hr] = lo;
                 } else if constexpr (F16) {
 #pragma unroll
                     for (int e = 0; e < 8; ++e) v[e] = ldexpf(v[e], uexp[k]);
                     f16x8 hi, lo;
                     split2h(v, hi, lo);
                     f16x8 *d = reinterpret_cast<f16x8 *>(dst);
-                    d[0 * nrows * 2 + ro] = hi;
-                    d[1 * nrows * 2 + ro] = lo;
+                    d[0 * nrows * 2 + hr] = hi;
+                    d[1 * nrows * 2 + hr] = lo;
                 } else {
                     float4 *d = reinterpret_cast<float4 *>(dst) + ro * 2;
                     d[0] = float4{v[0], v[1], v[2], v[3]};
@@ -747,10 +753,10 @@ __global__ __launch_bounds__(V2_NT) void k_mm2(const float *__restrict__ F, cons
                 if constexpr (SPLIT) {
                     const bf16x8 *A = reinterpret_cast<const bf16x8 *>(sA);
                     const bf16x8 *B = reinterpret_cast<const bf16x8 *>(sB);
-                    const bf16x8 ah = A[(0 * na + ta[k]) * 2 + h], am = A[(1 * na + ta[k]) * 2 + h],
-                                 al = A[(2 * na + ta[k]) * 2 + h];
-                    const bf16x8 bh = B[(0 * nb + tb[k]) * 2 + h], bm = B[(1 * nb + tb[k]) * 2 + h],
-                                 bl = B[(2 * nb + tb[k]) * 2 + h];
+                    const bf16x8 ah = A[(0 * 2 + h) * na + ta[k]], am = A[(1 * 2 + h) * na + ta[k]],
+                                 al = A[(2 * 2 + h) * na + ta[k]];
+                    const bf16x8 bh = B[(0 * 2 + h) * nb + tb[k]], bm = B[(1 * 2 + h) * nb + tb[k]],
+                                 bl = B[(2 * 2 + h) * nb + tb[k]];
                     acc[k] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc[k], 0, 0, 0);
                     acc[k] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bm, acc[k], 0, 0, 0);
                     acc[k] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc[k], 0, 0, 0);
@@ -760,8 +766,8 @@ __global__ __launch_bounds__(V2_NT) void k_mm2(const float *__restrict__ F, cons
                 } else if constexpr (F16) {
                     const f16x8 *A = reinterpret_cast<const f16x8 *>(sA);
                     const f16x8 *B = reinterpret_cast<const f16x8 *>(sB);
-                    const f16x8 ah = A[(0 * na + ta[k]) * 2 + h], al = A[(1 * na + ta[k]) * 2 + h];
-                    const f16x8 bh = B[(0 * nb + tb[k]) * 2 + h], bl = B[(1 * nb + tb[k]) * 2 + h];
+                    const f16x8 ah = A[(0 * 2 + h) * na + ta[k]], al = A[(1 * 2 + h) * na + ta[k]];
+                    const f16x8 bh = B[(0 * 2 + h) * nb + tb[k]], bl = B[(1 * 2 + h) * nb + tb[k]];
                     acc[k] = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, bh, acc[k], 0, 0, 0);
                     acc[k] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bl, acc[k], 0, 0, 0);
                     acc[k] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bh, acc[k], 0, 0, 0);

@@ -596,7 +596,7 @@ __global__ __launch_bounds__(V2_NT) void k_mm2(const float *__restrict__ F, cons
     const int r = lane & 31, h = lane >> 5;
     // build units of this thread: unit u -> (item, half); items of A first, then B
     // Each unit builds v = S[r0] * S[r1] over 8 cells from two staged rows
-    // (P_a, a map or zeros; a map or ones), with no branches, and stores it at
+    // (P_a, a map or zeros; a map or ones) and stores it at
     // operand offset uoff = 2 item + half (-1: no such unit).  The 32 lanes of
     // a half-wave take the same half of 32 consecutive items, so that their
     // stores are contiguous.
@@ -707,6 +707,10 @@ __global__ __launch_bounds__(V2_NT) void k_mm2(const float *__restrict__ F, cons
             // build the operands of 16 cells
 #pragma unroll
             for (int k = 0; k < V2_MAXU; ++k) {
+                // a wave's units of one k are 32 consecutive items (a multiple
+                // of 32 exist), so this skips whole waves
+                const int o = uoff[k];
+                if (o < 0) continue;
                 const int half = ((threadIdx.x + k * V2_NT) >> 5) & 1;
                 const int cb = sub * 16 + half * 8;
                 float v[8];
@@ -717,8 +721,6 @@ __global__ __launch_bounds__(V2_NT) void k_mm2(const float *__restrict__ F, cons
                     v[0] = a0.x * b0.x; v[1] = a0.y * b0.y; v[2] = a0.z * b0.z; v[3] = a0.w * b0.w;
                     v[4] = a1.x * b1.x; v[5] = a1.y * b1.y; v[6] = a1.z * b1.z; v[7] = a1.w * b1.w;
                 }
-                const int o = uoff[k];
-                if (o < 0) continue;
                 const bool isA = o < a_units;
                 unsigned char *dst = isA ? sA : sB;
                 const int ro = isA ? o : o - a_units;   // (row * 2 + half) within its operand

@@ -112,9 +112,14 @@ __global__ __launch_bounds__(NT, 1) void k_zinv_contract(const float2 *__restric
         for (int q = 0; q < 8; ++q) nxt[q] = src[lane + 64 * q];
     }
     __syncthreads();
-    float2 w3[7];   // this lane's third-stage twiddles, read once (strided LDS reads conflict)
+    // this lane's second- and third-stage twiddles, read once (strided LDS
+    // reads conflict: the second stage's lanes k and k + 2 share a bank)
+    float2 w2[7], w3[7];
 #pragma unroll
-    for (int q = 1; q < 8; ++q) w3[q - 1] = tw[q * lane];
+    for (int q = 1; q < 8; ++q) {
+        w2[q - 1] = tw[q * (lane & 7) * 8];
+        w3[q - 1] = tw[q * lane];
+    }
 
     for (int idx = blockIdx.x; idx < nact; idx += gridDim.x) {
         const size_t base = (size_t)line_of(idx) * NZ;
@@ -148,7 +153,7 @@ __global__ __launch_bounds__(NT, 1) void k_zinv_contract(const float2 *__restric
             {
                 const int k = lane & 7;                      // stage 2: Ns = 8
 #pragma unroll
-                for (int q = 1; q < 8; ++q) v[q] = cmul(v[q], tw[q * k * 8]);
+                for (int q = 1; q < 8; ++q) v[q] = cmul(v[q], w2[q - 1]);
                 dft<8, +1>(v);
                 wave_sync();
                 const int b2 = (lane - k) * 8 + k;

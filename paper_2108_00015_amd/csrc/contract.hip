@@ -707,8 +707,8 @@ __global__ __launch_bounds__(V2_NT) void k_mm2(const float *__restrict__ F, cons
             // build the operands of 16 cells
 #pragma unroll
             for (int k = 0; k < V2_MAXU; ++k) {
-                // a wave's units of one k are 32 consecutive items (a multiple
-                // of 32 exist), so this skips whole waves
+                // a wave's units of one k are 32 consecutive items and the
+                // item count is a multiple of 32, so this skips whole waves
                 const int o = uoff[k];
                 if (o < 0) continue;
                 const int half = ((threadIdx.x + k * V2_NT) >> 5) & 1;

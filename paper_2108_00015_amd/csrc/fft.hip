@@ -171,10 +171,6 @@ __device__ __forceinline__ void stage_sync() {
     else __syncthreads();
 }
 
-// Stage S reads src (LDS; global memory or registers for the first stage) and
-// writes dst (LDS; global memory for the last stage).  SYNC: the stage places
-// its own barriers (src == dst, in place); otherwise the caller orders the
-// buffers.  PADX >= 0 overrides the tile's row padding.
 // Ops that know their keep bits in advance (the same rows for every call on a
 // tile) expose KBITS and kb: the bits of the last stage, one word per
 // butterfly of this thread, as last_keep_bits computes them.
@@ -227,6 +223,10 @@ __device__ __forceinline__ void last_keep_bits(const Op &op, unsigned (&kbits)[L
     }
 }
 
+// Stage S reads src (LDS; global memory or registers for the first stage) and
+// writes dst (LDS; global memory for the last stage).  SYNC: the stage places
+// its own barriers (src == dst, in place); otherwise the caller orders the
+// buffers.  PADX >= 0 overrides the tile's row padding.
 template <typename T, int L, int MODE, int DIR, int S, bool STAGED, bool SYNC = true, int PADX = -1, class Op>
 __device__ __forceinline__ void fft_stage(const cplx<T> *src, cplx<T> *dst, const cplx<T> *tw, Op &op) {
     using C = cplx<T>;

@@ -113,7 +113,8 @@ __global__ __launch_bounds__(NT, 1) void k_zinv_contract(const float2 *__restric
     }
     __syncthreads();
     // this lane's second- and third-stage twiddles, read once (strided LDS
-    // reads conflict: the second stage's lanes k and k + 2 share a bank)
+    // reads conflict: the second stage's eight addresses for one q lie 64 q
+    // bytes apart)
     float2 w2[7], w3[7];
 #pragma unroll
     for (int q = 1; q < 8; ++q) {

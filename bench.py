@@ -150,6 +150,40 @@ def comb_tuples(ns, n):
     return math.comb(ns + n - 2, n - 1)
 
 
+def roofline_of(stages, n, prec, workload, time_key="ms_per_step", note=None):
+    """The roofline entry of the dominant kernel (largest time per step).
+
+    stages: {kind: {time_key, avg_launch_ms, and gbs + bytes_per_launch where
+    the byte model applies, mfma_issued_tflops for the separate summation}}.
+    Orders 4 and 5 are bound by the matrix cores when the separate summation
+    dominates: issued matrix flops (every split product counted) per launch
+    against the dense peak of the operand type, the unsplit count beside them.
+    Otherwise the kernel is priced on HBM by its algorithmic bytes per launch,
+    with the committed counter traffic when it matches the sources.
+    """
+    if not stages:
+        return None
+    kind, ent = max(stages.items(), key=lambda kv: kv[1][time_key])
+    if kind == "contract_mm" and n >= 4 and "mfma_issued_tflops" in ent:
+        issued = ent["mfma_issued_tflops"] * 1e12 * ent["avg_launch_ms"] * 1e-3
+        peak = MFMA_PEAK_TFLOPS[prec]
+        return dict(bound="mfma", kernel=kind, achieved=ent["mfma_issued_tflops"], peak=peak, unit="TFLOP/s",
+                    frac=round(ent["mfma_issued_tflops"] / peak, 4), traffic=None,
+                    flops_per_launch=issued, algorithmic_flops_per_launch=issued / TERM_PRODUCTS[prec],
+                    term_products=TERM_PRODUCTS[prec], avg_launch_ms=ent["avg_launch_ms"])
+    if "gbs" not in ent:
+        return None
+    ach = ent["bytes_per_launch"] / (ent["avg_launch_ms"] * 1e-3) / 1e9
+    traffic = measured_traffic(kind, workload, n)
+    roof = dict(bound="hbm", kernel=kind, achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(ach / HBM_PEAK_GBS, 4),
+                traffic=(int(round(traffic)) if traffic is not None else None), traffic_unit="bytes/launch",
+                bytes_per_launch=ent["bytes_per_launch"], avg_launch_ms=ent["avg_launch_ms"])
+    if note:
+        roof["note"] = note
+    return roof
+
+
 def stages_use_fused(prof):
     return "fused_zinv_contract" in prof
 
@@ -412,16 +446,8 @@ def bench_mocks(args):
                 ent["gbs"] = round(gbs, 1)
                 ent["bytes_per_launch"] = b / launches
         stages[kind] = ent
-    dom = max(stages.items(), key=lambda kv: kv[1]["ms"]) if stages else None
-    roof = None
-    if dom is not None and "gbs" in dom[1]:
-        ach = dom[1]["bytes_per_launch"] / (dom[1]["avg_launch_ms"] * 1e-3) / 1e9
-        traffic = measured_traffic(dom[0], MOCKS_NAME, args.n)
-        roof = dict(bound="hbm", kernel=dom[0], achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(ach / HBM_PEAK_GBS, 4),
-                    traffic=(int(round(traffic)) if traffic is not None else None), traffic_unit="bytes/launch",
-                    bytes_per_launch=dom[1]["bytes_per_launch"], avg_launch_ms=dom[1]["avg_launch_ms"],
-                    note="launches of one kind differ in grid size; per-launch figures are batch averages")
+    roof = roofline_of(stages, args.n, "split_bf16", MOCKS_NAME, time_key="ms",
+                       note="launches of one kind differ in grid size; per-launch figures are batch averages")
     xi32 = [j.xi.cpu().numpy() for j in jobs]
     wd32 = [j.W_delta.cpu().numpy() for j in jobs]
     ctx.close()
@@ -576,26 +602,7 @@ def main():
         ent["mfma_frac_of_peak"] = round(tflops / MFMA_PEAK_TFLOPS[args.prec], 4)
         ent["tuple_cells_per_s"] = round(comb_tuples(ns, args.n) * fb * nc / (per_launch_ms * 1e-3), 1)
     # dominant kernel: largest time per step
-    dom = max(stages.items(), key=lambda kv: kv[1]["ms_per_step"]) if stages else None
-    roof = None
-    if dom is not None and dom[0] == "contract_mm" and args.n >= 4:
-        # orders 4 and 5 are bound by the matrix cores: issued matrix flops
-        # (every split product counted) per launch against the dense peak of
-        # the operand type; the unsplit count is the algorithmic one
-        ent = dom[1]
-        issued = ent["mfma_issued_tflops"] * 1e12 * ent["avg_launch_ms"] * 1e-3
-        peak = MFMA_PEAK_TFLOPS[args.prec]
-        roof = dict(bound="mfma", kernel=dom[0], achieved=ent["mfma_issued_tflops"], peak=peak, unit="TFLOP/s",
-                    frac=round(ent["mfma_issued_tflops"] / peak, 4), traffic=None,
-                    flops_per_launch=issued, algorithmic_flops_per_launch=issued / TERM_PRODUCTS[args.prec],
-                    term_products=TERM_PRODUCTS[args.prec], avg_launch_ms=ent["avg_launch_ms"])
-    elif dom is not None and "gbs" in dom[1]:
-        ach = dom[1]["bytes_per_launch"] / (dom[1]["avg_launch_ms"] * 1e-3) / 1e9
-        traffic = measured_traffic(dom[0], w.name, args.n)
-        roof = dict(bound="hbm", kernel=dom[0], achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(ach / HBM_PEAK_GBS, 4),
-                    traffic=(int(round(traffic)) if traffic is not None else None), traffic_unit="bytes/launch",
-                    bytes_per_launch=dom[1]["bytes_per_launch"], avg_launch_ms=dom[1]["avg_launch_ms"])
+    roof = roofline_of(stages, args.n, args.prec, w.name)
 
     cpu = None
     if not args.no_cpu:

@@ -122,15 +122,17 @@ TERM_PRODUCTS = {"split_bf16": 6, "split_f16": 3, "f32": 1, "f64": 1}
 
 def summation_tiles(ns, n, ts=32):
     """32 x 32 output tiles the matrix-core summation issues for order n (row items
-    F C_a or F C_a C_b, column items C_b or C_c C_d, as in the library's plan)."""
+    F C_a or F C_a C_b, column items C_b or C_c C_d, as in the library's plan:
+    row pairs ordered by their larger radius, column pairs lexicographically)."""
     singles = [(a,) for a in range(ns)]
     pairs = [(a, b) for a in range(ns) for b in range(a, ns)]
+    rows_by_b = sorted(pairs, key=lambda p: (p[1], p[0]))
     if n == 3:
         left, right = singles, singles
     elif n == 4:
-        left, right = pairs, singles
+        left, right = rows_by_b, singles
     else:
-        left, right = pairs, pairs
+        left, right = rows_by_b, pairs
     li = {t: i for i, t in enumerate(left)}
     ri = {t: i for i, t in enumerate(right)}
     import itertools

@@ -549,25 +549,27 @@ __global__ __launch_bounds__(NT) void k_mm_split(const float *__restrict__ F, co
 
 // ---------------------------------------------------------------------------
 // float32 / split-bf16 matrix-core summation with operands built once per
-// chunk.  A workgroup owns a share of the summed 64-cell blocks and a group of up to 16 output
+// chunk.  A workgroup owns a share of the summed 64-cell blocks and a group of up to 24 output
 // tiles (a rectangle of row tiles x column tiles).  For every 64 cells it
 // stages the maps and F in LDS; for every 16 of those it builds each row item
 // (F C_a [C_b]) and column item (C_c [C_d]) of its rectangle once, as three
 // bf16 planes (or one float32 plane), in LDS; then each wave runs the matrix
-// instructions of its (at most two) tiles from LDS.  float32 accumulators are
+// instructions of its (at most three) tiles from LDS.  Each group stages the
+// maps and builds its items anew, so fewer, larger groups cost less: with
+// three tiles per wave the 19 tiles of 20 radii at n = 5 are one group.  float32 accumulators are
 // flushed into float64 registers every 128 cells.
 // ---------------------------------------------------------------------------
 struct Group {
     int rt0, nrt, ct0, nct, t0, nt;
 };
 
-constexpr int V2_NT = 512, V2_WAVES = V2_NT / 64, V2_MAXT = 2, V2_MAXU = 4;
+constexpr int V2_NT = 512, V2_WAVES = V2_NT / 64, V2_MAXU = 4;   // tiles per wave: MAXT, 2 or 3
 constexpr int V2_PRE = 3;                       // staged float4 per thread: (64 + 1) * 16 <= 3 * 512
 constexpr int V2_LDS_MAX = 150 * 1024;          // dynamic LDS of one k_mm2 workgroup
 constexpr int V2_SROW = 68;                     // staged row stride (floats): 64 cells + 4 of padding
 
 
-template <int PREC>
+template <int PREC, int MAXT>
 __global__ __launch_bounds__(V2_NT) void k_mm2(const float *__restrict__ F, const float *__restrict__ maps, size_t nc,
                                               int ns, const int *__restrict__ list, const int *__restrict__ count,
                                               const int2 *__restrict__ ritems,
@@ -625,20 +627,20 @@ __global__ __launch_bounds__(V2_NT) void k_mm2(const float *__restrict__ F, cons
         }
     }
     // tiles of this wave
-    int ta[V2_MAXT], tb[V2_MAXT];
-    bool tl[V2_MAXT];
+    int ta[MAXT], tb[MAXT];
+    bool tl[MAXT];
 #pragma unroll
-    for (int k = 0; k < V2_MAXT; ++k) {
+    for (int k = 0; k < MAXT; ++k) {
         const int lt = w + k * V2_WAVES;
         tl[k] = lt < gr.nt;
         const int2 t = tl[k] ? tiles[gr.t0 + lt] : int2{gr.rt0, gr.ct0};
         ta[k] = (t.x - gr.rt0) * 32 + r;
         tb[k] = (t.y - gr.ct0) * 32 + r;
     }
-    floatx16 acc[V2_MAXT];
-    double dacc[V2_MAXT][16];
+    floatx16 acc[MAXT];
+    double dacc[MAXT][16];
 #pragma unroll
-    for (int k = 0; k < V2_MAXT; ++k) {
+    for (int k = 0; k < MAXT; ++k) {
         acc[k] = floatx16{0};
 #pragma unroll
         for (int v = 0; v < 16; ++v) dacc[k][v] = 0.0;
@@ -750,7 +752,7 @@ __global__ __launch_bounds__(V2_NT) void k_mm2(const float *__restrict__ F, cons
             __syncthreads();
             // matrix instructions of this wave's tiles
 #pragma unroll
-            for (int k = 0; k < V2_MAXT; ++k) {
+            for (int k = 0; k < MAXT; ++k) {
                 if (!tl[k]) continue;
                 if constexpr (SPLIT) {
                     const bf16x8 *A = reinterpret_cast<const bf16x8 *>(sA);
@@ -792,7 +794,7 @@ __global__ __launch_bounds__(V2_NT) void k_mm2(const float *__restrict__ F, cons
         if (++since == 2) {
             since = 0;
 #pragma unroll
-            for (int k = 0; k < V2_MAXT; ++k) {
+            for (int k = 0; k < MAXT; ++k) {
 #pragma unroll
                 for (int v = 0; v < 16; ++v) dacc[k][v] += (double)acc[k][v];
                 acc[k] = floatx16{0};
@@ -801,7 +803,7 @@ __global__ __launch_bounds__(V2_NT) void k_mm2(const float *__restrict__ F, cons
     }
     // write this wave's tiles: lane l, reg v holds (i = 8 (v / 4) + 4 (l / 32) + v % 4, j = l % 32)
 #pragma unroll
-    for (int k = 0; k < V2_MAXT; ++k) {
+    for (int k = 0; k < MAXT; ++k) {
         if (!tl[k]) continue;
         const int tile = gr.t0 + w + k * V2_WAVES;
         double *out = partial + ((size_t)tile * G + blockIdx.x) * 1024;
@@ -890,26 +892,62 @@ void enumerate_tuples(int ns, int k, std::vector<std::vector<int>> &out) {
     }
 }
 
+// Row and column items of the order-n summation as one matrix product (Eq.
+// ksin_delta): rows F C_a (n = 3) or F C_a C_b (a <= b), columns C_b (n = 3,
+// 4) or C_c C_d (c <= d).  The tuple a <= b <= c <= d takes row (a, b) and
+// column (c, d), so rows are ordered by their larger radius b (then a) and
+// columns by their smaller radius c (then d): the needed entries then fill a
+// staircase of whole tiles (for 20 radii at n = 5, 19 tiles of 32 x 32 instead
+// of 28 in lexicographic order).  row_of / col_of: position of pair (x, y) at
+// x ns + y, or of single x at x.
+struct ItemLists {
+    std::vector<std::pair<int, int>> left, right;
+    std::vector<int> row_of, col_of;
+};
+
+void item_lists(int ns, int n, ItemLists &L) {
+    std::vector<std::vector<int>> pairs;   // lexicographic: by c, then d
+    enumerate_tuples(ns, 2, pairs);
+    auto singles = [&](std::vector<std::pair<int, int>> &v, std::vector<int> &at) {
+        at.assign(ns, -1);
+        for (int a = 0; a < ns; ++a) {
+            at[a] = (int)v.size();
+            v.push_back({a, -1});
+        }
+    };
+    auto pair_list = [&](std::vector<std::pair<int, int>> &v, std::vector<int> &at, bool by_second) {
+        std::vector<std::pair<int, int>> ps;
+        for (auto &p : pairs) ps.push_back({p[0], p[1]});
+        if (by_second)
+            std::stable_sort(ps.begin(), ps.end(), [](const std::pair<int, int> &x, const std::pair<int, int> &y) {
+                return x.second != y.second ? x.second < y.second : x.first < y.first;
+            });
+        at.assign((size_t)ns * ns, -1);
+        for (auto &p : ps) {
+            at[(size_t)p.first * ns + p.second] = (int)v.size();
+            v.push_back(p);
+        }
+    };
+    if (n == 3) singles(L.left, L.row_of);
+    else pair_list(L.left, L.row_of, true);
+    if (n == 5) pair_list(L.right, L.col_of, false);
+    else singles(L.right, L.col_of);
+}
+
+// row and column position of tuple u (a_1 <= ... <= a_{n-1})
+inline std::pair<int, int> tuple_rc(const ItemLists &L, int ns, int n, const std::vector<int> &u) {
+    if (n == 3) return {L.row_of[u[0]], L.col_of[u[1]]};
+    if (n == 4) return {L.row_of[(size_t)u[0] * ns + u[1]], L.col_of[u[2]]};
+    return {L.row_of[(size_t)u[0] * ns + u[1]], L.col_of[(size_t)u[2] * ns + u[3]]};
+}
+
 int make_plan(conker_ctx *c, int ns, int n, int TS, Plan &pl) {
     const uint64_t key = ((uint64_t)ns << 16) | ((uint64_t)n << 8) | (uint64_t)TS;
     Buf &bi = c->tables[key * 2];
     Buf &bw = c->tables[key * 2 + 1];
-    // left / right item lists
-    std::vector<std::pair<int, int>> left, right;
-    std::vector<std::vector<int>> pairs;
-    enumerate_tuples(ns, 2, pairs);
-    std::vector<int> pair_index(ns * ns, -1);
-    for (size_t p = 0; p < pairs.size(); ++p) pair_index[pairs[p][0] * ns + pairs[p][1]] = (int)p;
-    if (n == 3 || n == 4) {
-        for (int a = 0; a < ns; ++a) right.push_back({a, -1});
-    }
-    if (n == 3) {
-        for (int a = 0; a < ns; ++a) left.push_back({a, -1});
-    } else {
-        for (auto &p : pairs) left.push_back({p[0], p[1]});
-        if (n == 5)
-            for (auto &p : pairs) right.push_back({p[0], p[1]});
-    }
+    ItemLists IL;
+    item_lists(ns, n, IL);
+    const auto &left = IL.left, &right = IL.right;
     const int LT = ((int)left.size() + TS - 1) / TS, RT = ((int)right.size() + TS - 1) / TS;
     std::vector<std::vector<int>> tuples;
     enumerate_tuples(ns, n - 1, tuples);
@@ -918,11 +956,7 @@ int make_plan(conker_ctx *c, int ns, int n, int TS, Plan &pl) {
     std::vector<std::pair<int, int>> tiles;
     std::vector<std::pair<int, int>> rc(tuples.size());
     for (size_t t = 0; t < tuples.size(); ++t) {
-        const auto &u = tuples[t];
-        int li, ri;
-        if (n == 3) { li = u[0]; ri = u[1]; }
-        else if (n == 4) { li = pair_index[u[0] * ns + u[1]]; ri = u[2]; }
-        else { li = pair_index[u[0] * ns + u[1]]; ri = pair_index[u[2] * ns + u[3]]; }
+        const auto [li, ri] = tuple_rc(IL, ns, n, tuples[t]);
         rc[t] = {li, ri};
         int &id = tile_id[(li / TS) * RT + ri / TS];
         if (id < 0) {
@@ -961,41 +995,28 @@ int make_plan(conker_ctx *c, int ns, int n, int TS, Plan &pl) {
 
 // Plan of the operand-sharing kernel: item tables per row / column tile, the
 // needed tiles (same order as make_plan, so `where` from make_plan applies),
-// and groups of at most 16 tiles whose row and column rectangles fit LDS.
+// and groups of at most three tiles per wave whose row and column rectangles
+// fit LDS.
 struct Plan2 {
     int n_tiles = 0, n_groups = 0, max_lds = 0;
     Buf *ritems = nullptr, *citems = nullptr, *tiles = nullptr, *groups = nullptr;
 };
 
-int make_plan2(conker_ctx *c, int ns, int n, bool split, Plan2 &p2) {
+int make_plan2(conker_ctx *c, int ns, int n, bool split, int maxt, Plan2 &p2) {
     constexpr int TS = 32;
-    const uint64_t key = (((uint64_t)ns << 16) | ((uint64_t)n << 8) | 32u) * 16 + (split ? 8 : 9);
+    const uint64_t key = (((uint64_t)ns << 16) | ((uint64_t)n << 8) | 32u) * 16 + (split ? 8 : 9) + (maxt == 3 ? 2 : 0);
     Buf &bri = c->tables[key * 4 + 0], &bci = c->tables[key * 4 + 1];
     Buf &bti = c->tables[key * 4 + 2], &bgr = c->tables[key * 4 + 3];
-    std::vector<std::pair<int, int>> left, right;
-    std::vector<std::vector<int>> pairs;
-    enumerate_tuples(ns, 2, pairs);
-    std::vector<int> pair_index(ns * ns, -1);
-    for (size_t p = 0; p < pairs.size(); ++p) pair_index[pairs[p][0] * ns + pairs[p][1]] = (int)p;
-    if (n == 3 || n == 4)
-        for (int a = 0; a < ns; ++a) right.push_back({a, -1});
-    if (n == 3) {
-        for (int a = 0; a < ns; ++a) left.push_back({a, -1});
-    } else {
-        for (auto &p : pairs) left.push_back({p[0], p[1]});
-        if (n == 5)
-            for (auto &p : pairs) right.push_back({p[0], p[1]});
-    }
+    ItemLists IL;
+    item_lists(ns, n, IL);
+    const auto &left = IL.left, &right = IL.right;
     const int LT = ((int)left.size() + TS - 1) / TS, RT = ((int)right.size() + TS - 1) / TS;
     std::vector<std::vector<int>> tuples;
     enumerate_tuples(ns, n - 1, tuples);
     std::vector<int> tile_id(LT * RT, -1);
     std::vector<std::pair<int, int>> tiles;
     for (auto &u : tuples) {
-        int li, ri;
-        if (n == 3) { li = u[0]; ri = u[1]; }
-        else if (n == 4) { li = pair_index[u[0] * ns + u[1]]; ri = u[2]; }
-        else { li = pair_index[u[0] * ns + u[1]]; ri = pair_index[u[2] * ns + u[3]]; }
+        const auto [li, ri] = tuple_rc(IL, ns, n, u);
         int &id = tile_id[(li / TS) * RT + ri / TS];
         if (id < 0) {
             id = (int)tiles.size();
@@ -1011,7 +1032,7 @@ int make_plan2(conker_ctx *c, int ns, int n, bool split, Plan2 &p2) {
         Group g{tiles[i].first, 1, tiles[i].second, 1, i, 1};
         int rlo = tiles[i].first, rhi = rlo, clo = tiles[i].second, chi = clo;
         int j = i + 1;
-        while (j < (int)tiles.size() && j - i < V2_WAVES * V2_MAXT) {
+        while (j < (int)tiles.size() && j - i < V2_WAVES * maxt) {
             const int nrlo = std::min(rlo, tiles[j].first), nrhi = std::max(rhi, tiles[j].first);
             const int nclo = std::min(clo, tiles[j].second), nchi = std::max(chi, tiles[j].second);
             const int nrt = nrhi - nrlo + 1, nct = nchi - nclo + 1;
@@ -1565,9 +1586,21 @@ extern "C" int conker_contract_npt(conker_ctx *c, const conker_grid *g, conker_d
         CK_LAUNCH(c);
     }
     if (use_v2) {
-        // operand-sharing matrix-core kernel
+        // operand-sharing matrix-core kernel: three tiles per wave where that
+        // makes fewer groups (each group stages the maps and builds its items
+        // anew), else two (fewer registers)
+        const bool split = prec == CONKER_MM_SPLIT_BF16;
         Plan2 p2;
-        CK_OK(make_plan2(c, ns, n, prec == CONKER_MM_SPLIT_BF16, p2));
+        int maxt = 2;
+        CK_OK(make_plan2(c, ns, n, split, 2, p2));
+        {
+            Plan2 p3;
+            CK_OK(make_plan2(c, ns, n, split, 3, p3));
+            if (p3.n_groups < p2.n_groups) {
+                p2 = p3;
+                maxt = 3;
+            }
+        }
         if (nc % 64) return fail(c, CONKER_EUNSUPPORTED, "cell count must be a multiple of 64");
         const size_t G = std::max<size_t>(1, std::min<size_t>(nc / 512, 1024 / (size_t)p2.n_groups));
         const int te = 1024;
@@ -1580,31 +1613,25 @@ extern "C" int conker_contract_npt(conker_ctx *c, const conker_grid *g, conker_d
             dim3 grid((unsigned)G, (unsigned)p2.n_groups);
             static bool attr_set = false;
             if (!attr_set) {
-                CK_HIP(c, hipFuncSetAttribute((const void *)k_mm2<CONKER_MM_SPLIT_BF16>,
-                                              hipFuncAttributeMaxDynamicSharedMemorySize, V2_LDS_MAX));
-                CK_HIP(c, hipFuncSetAttribute((const void *)k_mm2<CONKER_MM_F32>,
-                                              hipFuncAttributeMaxDynamicSharedMemorySize, V2_LDS_MAX));
-                CK_HIP(c, hipFuncSetAttribute((const void *)k_mm2<CONKER_MM_SPLIT_F16>,
-                                              hipFuncAttributeMaxDynamicSharedMemorySize, V2_LDS_MAX));
+                const void *ks[] = {(const void *)k_mm2<CONKER_MM_SPLIT_BF16, 2>, (const void *)k_mm2<CONKER_MM_F32, 2>,
+                                    (const void *)k_mm2<CONKER_MM_SPLIT_F16, 2>, (const void *)k_mm2<CONKER_MM_SPLIT_BF16, 3>,
+                                    (const void *)k_mm2<CONKER_MM_F32, 3>, (const void *)k_mm2<CONKER_MM_SPLIT_F16, 3>};
+                for (const void *k : ks)
+                    CK_HIP(c, hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, V2_LDS_MAX));
                 attr_set = true;
             }
-            if (prec == CONKER_MM_SPLIT_BF16)
-                hipLaunchKernelGGL(k_mm2<CONKER_MM_SPLIT_BF16>, grid, dim3(V2_NT), p2.max_lds, c->stream,
-                                   (const float *)F, (const float *)maps, nc, ns, blist, bcount,
-                                   (const int2 *)p2.ritems->p, (const int2 *)p2.citems->p,
-                                   (const int2 *)p2.tiles->p, (const Group *)p2.groups->p, (int)G, part,
-                                   (const unsigned *)nullptr);
-            else if (prec == CONKER_MM_SPLIT_F16)
-                hipLaunchKernelGGL(k_mm2<CONKER_MM_SPLIT_F16>, grid, dim3(V2_NT), p2.max_lds, c->stream,
-                                   (const float *)F, (const float *)maps, nc, ns, blist, bcount,
-                                   (const int2 *)p2.ritems->p, (const int2 *)p2.citems->p,
-                                   (const int2 *)p2.tiles->p, (const Group *)p2.groups->p, (int)G, part,
-                                   (const unsigned *)maxabs);
-            else
-                hipLaunchKernelGGL(k_mm2<CONKER_MM_F32>, grid, dim3(V2_NT), p2.max_lds, c->stream, (const float *)F,
+            auto launch = [&](auto kern) {
+                hipLaunchKernelGGL(kern, grid, dim3(V2_NT), p2.max_lds, c->stream, (const float *)F,
                                    (const float *)maps, nc, ns, blist, bcount, (const int2 *)p2.ritems->p,
                                    (const int2 *)p2.citems->p, (const int2 *)p2.tiles->p,
-                                   (const Group *)p2.groups->p, (int)G, part, (const unsigned *)nullptr);
+                                   (const Group *)p2.groups->p, (int)G, part, (const unsigned *)maxabs);
+            };
+            if (prec == CONKER_MM_SPLIT_BF16)
+                maxt == 3 ? launch(k_mm2<CONKER_MM_SPLIT_BF16, 3>) : launch(k_mm2<CONKER_MM_SPLIT_BF16, 2>);
+            else if (prec == CONKER_MM_SPLIT_F16)
+                maxt == 3 ? launch(k_mm2<CONKER_MM_SPLIT_F16, 3>) : launch(k_mm2<CONKER_MM_SPLIT_F16, 2>);
+            else
+                maxt == 3 ? launch(k_mm2<CONKER_MM_F32, 3>) : launch(k_mm2<CONKER_MM_F32, 2>);
             CK_LAUNCH(c);
         }
         ProfScope ps(c, PK_CONTRACT_REDUCE);

@@ -12,21 +12,22 @@ import bench
 def _tiles_by_bounds(ns, n, ts=32):
     """Tiles of the order-n summation counted a second way: a tile (I, J) is
     issued iff some tuple a1 <= ... <= a_{n-1} has its row item in row block I
-    and its column item in column block J.  Row items are sorted (a) or (a, b)
-    lexicographically, column items likewise, so a tile is needed iff the
-    smallest last radius of its row block is at most the largest first radius
-    of its column block (then the pair of those two items, completed in
-    between, is such a tuple)."""
+    and its column item in column block J, i.e. iff the smallest last radius of
+    its row block is at most the largest first radius of its column block (then
+    the pair of those two items, completed in between, is such a tuple).  Row
+    pairs in the library's order (by their larger radius), column pairs
+    lexicographic."""
     singles = [(a,) for a in range(ns)]
     pairs = [(a, b) for a in range(ns) for b in range(a, ns)]
-    left, right = {3: (singles, singles), 4: (pairs, singles), 5: (pairs, pairs)}[n]
+    rows = sorted(pairs, key=lambda p: (p[1], p[0]))
+    left, right = {3: (singles, singles), 4: (rows, singles), 5: (rows, pairs)}[n]
     lb = [left[i:i + ts] for i in range(0, len(left), ts)]
     rb = [right[j:j + ts] for j in range(0, len(right), ts)]
     count = 0
-    for rows in lb:
-        lo = min(t[-1] for t in rows)
-        for cols in rb:
-            if lo <= max(t[0] for t in cols):
+    for rblk in lb:
+        lo = min(t[-1] for t in rblk)
+        for cblk in rb:
+            if lo <= max(t[0] for t in cblk):
                 count += 1
     return count
 
@@ -41,6 +42,10 @@ def test_summation_tiles_known_counts():
     assert bench.summation_tiles(30, 3) == 1
     assert bench.summation_tiles(40, 3) == 3
     assert bench.summation_tiles(64, 3) == 3
+    # n = 5: rows ordered by their larger radius leave a staircase of tiles
+    # (lexicographic rows would need 28 and 120)
+    assert bench.summation_tiles(20, 5) == 19
+    assert bench.summation_tiles(30, 5) == 64
 
 
 @pytest.mark.parametrize("ns,n", [(5, 2), (10, 3), (30, 4), (20, 5), (1, 5)])

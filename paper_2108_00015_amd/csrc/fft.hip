@@ -179,6 +179,14 @@ struct has_kbits : std::false_type {};
 template <class Op>
 struct has_kbits<Op, std::enable_if_t<Op::KBITS>> : std::true_type {};
 
+// Ops that take the last stage's outputs with the butterfly and row indices
+// (q, r) of this thread, for values they fetched in advance, expose STORE_QR
+// and store_qr(q, r, i, c, v).
+template <class Op, class = void>
+struct has_store_qr : std::false_type {};
+template <class Op>
+struct has_store_qr<Op, std::enable_if_t<Op::STORE_QR>> : std::true_type {};
+
 // Shape of the last stage of a line transform.
 template <typename T, int L, int MODE>
 struct LastStage {
@@ -220,6 +228,27 @@ __device__ __forceinline__ void last_keep_bits(const Op &op, unsigned (&kbits)[L
     } else {
 #pragma unroll
         for (int q = 0; q < PER; ++q) kbits[q] = 0xffffu;
+    }
+}
+
+// The cells this thread's last stage writes: fn(q, r, i, c) for butterfly q
+// and output r (row i of column or line c), for the butterflies it owns.
+template <typename T, int L, int MODE, class Fn>
+__device__ __forceinline__ void last_stage_cells(Fn &&fn) {
+    using LS = LastStage<T, L, MODE>;
+    constexpr int R = LS::R, NSV = LS::NSV, LR = LS::LR, NB = LS::NB, PER = LS::PER;
+    constexpr int NT = Shape<T, L, MODE>::NT, TC = Shape<T, L, MODE>::TC;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int b = threadIdx.x + q * NT;
+        if (NB % NT == 0 || b < NB) {
+            int j, c;
+            split_q<NT, MODE, LR, TC>(q, j, c);
+            const int k = j & (NSV - 1);
+            const int base = (j - k) * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) fn(q, r, base + r * NSV, c);
+        }
     }
 }
 
@@ -298,6 +327,8 @@ __device__ __forceinline__ void fft_stage(const cplx<T> *src, cplx<T> *dst, cons
                 const int o = base + r * NSV;
                 if constexpr (KEEP) {
                     if (kbits[q] & (1u << r)) op.store(o, c, v[q][r]);
+                } else if constexpr (LAST && has_store_qr<Op>::value) {
+                    op.store_qr(q, r, o, c, v[q][r]);
                 } else if constexpr (LAST) {
                     op.store(o, c, v[q][r]);
                 } else {
@@ -1132,9 +1163,10 @@ __global__ __launch_bounds__((Shape<T, L, TM_R>::NT), (Shape<T, L, TM_R>::MINW))
 // writes one partial row per (radius, workgroup); rows are reduced in a fixed
 // order afterwards.
 // ---------------------------------------------------------------------------
-template <typename T, int P>
+template <typename T, int P, int PER, int R>
 struct OpDiag {
     static constexpr bool STAGED = false;
+    static constexpr bool STORE_QR = true;
     using C = cplx<T>;
     static constexpr unsigned NONE = 0xffffffffu;
     const C *src;
@@ -1142,16 +1174,28 @@ struct OpDiag {
     const T *fb;
     const unsigned *row;   // LDS: first cell of each line of the tile, NONE for no line
     double acc[2][P];
+    // F of both fields at this thread's last-stage cells, loaded when the tile
+    // starts so that the loads are in flight during its transform (0 where
+    // the tile has no line)
+    T va[PER][R], vb[PER][R];
     __device__ C load(int i, int c) const {
         const unsigned r = row[c];
         if (r == NONE) return C{(T)0, (T)0};
         return src[r + (unsigned)i];
     }
-    __device__ void store(int i, int c, C v) {
-        const unsigned r = row[c];
-        if (r == NONE) return;
-        const unsigned k = r + (unsigned)i;
-        const T a = fa[k];
+    template <int L, int MODE>
+    __device__ void prefetch() {
+        last_stage_cells<T, L, MODE>([&](int q, int r, int i, int c) {
+            const unsigned rw = row[c];
+            const bool ok = rw != NONE;
+            const unsigned k = ok ? rw + (unsigned)i : 0u;
+            va[q][r] = ok ? fa[k] : (T)0;
+            vb[q][r] = (ok && fb) ? fb[k] : (T)0;
+        });
+    }
+    // a cell outside every line adds F = 0: nothing
+    __device__ void store_qr(int q, int r, int, int, C v) {
+        const T a = va[q][r];
         T pw = v.x;
         acc[0][0] += (double)(a * pw);
 #pragma unroll
@@ -1160,7 +1204,7 @@ struct OpDiag {
             acc[0][p] += (double)(a * pw);
         }
         if (fb) {
-            const T b = fb[k];
+            const T b = vb[q][r];
             pw = v.y;
             acc[1][0] += (double)(b * pw);
 #pragma unroll
@@ -1185,7 +1229,8 @@ __global__ __launch_bounds__((Shape<T, L, TM_J>::NT), (Shape<T, L, TM_J>::MINW))
     __shared__ double red[NW][2 * P];
     __shared__ unsigned row[TC];
     for (int t = threadIdx.x; t < L; t += NT) tw[t] = twg[t];
-    OpDiag<T, P> op;
+    using LS = LastStage<T, L, TM_J>;
+    OpDiag<T, P, LS::PER, LS::R> op;
 #pragma unroll
     for (int p = 0; p < P; ++p) op.acc[0][p] = op.acc[1][p] = 0.0;
     op.row = row;
@@ -1200,10 +1245,11 @@ __global__ __launch_bounds__((Shape<T, L, TM_J>::NT), (Shape<T, L, TM_J>::MINW))
         __syncthreads();   // the previous tile is done with row (and the twiddles are in)
         for (int c = threadIdx.x; c < TC; c += NT) {
             const int k = tile * TC + c;
-            row[c] = list ? (k < nlist ? (unsigned)list[k] * (unsigned)d.nz : OpDiag<T, P>::NONE)
+            row[c] = list ? (k < nlist ? (unsigned)list[k] * (unsigned)d.nz : decltype(op)::NONE)
                           : (unsigned)k * (unsigned)d.nz;
         }
         __syncthreads();
+        op.template prefetch<L, TM_J>();
         fft_line_tile<T, L, TM_J, +1, false>(lds, tw, op);
     }
     __syncthreads();

@@ -974,6 +974,16 @@ struct OpExtract {
 // coalesced reads, prefetched into registers while the previous radius is
 // transformed.
 // ---------------------------------------------------------------------------
+// Row stride (values) of the staged kernel values of one tile column.  The
+// first stage's lanes read TC columns x 64/TC consecutive rows; a stride of
+// 64/TC modulo 32 banks puts those 64 reads on distinct banks (two rounds of
+// 32) instead of bank (column + row) mod 32.
+template <int L, int TC>
+constexpr int kt_stride() {
+    constexpr int nxh = L / 2 + 1, want = (64 / TC) % 32;
+    return nxh + (((want - nxh) % 32) + 32) % 32;
+}
+
 template <typename T, int L, int TC, int PER0, bool PAIR = false>
 struct OpResident {
     static constexpr bool STAGED = false;
@@ -987,10 +997,10 @@ struct OpResident {
     const unsigned *kb;        // registers: the last stage's keep bits, taken once per tile
     __device__ C load_r(int q, int r, int i, int c) const {
         const C s = sreg[q][r];
-        const int e = c * (L / 2 + 1) + (i <= L - i ? i : L - i);
+        const int e = c * kt_stride<L, TC>() + (i <= L - i ? i : L - i);
         const T k = kt[e];
         if constexpr (PAIR) {   // s (K_a + i K_b)
-            const T kb = kt[TC * (L / 2 + 1) + e];
+            const T kb = kt[TC * kt_stride<L, TC>() + e];
             return C{s.x * k - s.y * kb, s.y * k + s.x * kb};
         }
         return C{s.x * k, s.y * k};
@@ -1005,7 +1015,7 @@ constexpr bool resident_fits() {
     using SH = Shape<T, L, TM_R>;
     return Plan<L>::r[0] == 8 &&
            (size_t)SH::LDS * sizeof(cplx<T>) + (size_t)L * sizeof(cplx<T>) +
-                   (PAIR ? 2 : 1) * (size_t)SH::TC * (L / 2 + 1) * sizeof(T) + (size_t)L <=
+                   (PAIR ? 2 : 1) * (size_t)SH::TC * kt_stride<L, SH::TC>() * sizeof(T) + (size_t)L <=
                160 * 1024;
 }
 
@@ -1017,7 +1027,7 @@ constexpr bool pingpong_fits() {
     using SH = Shape<T, L, TM_R>;
     return Plan<L>::n == 3 &&
            2 * (size_t)L * (SH::TC + 1) * sizeof(cplx<T>) + (size_t)L * sizeof(cplx<T>) +
-                   (size_t)SH::TC * (L / 2 + 1) * sizeof(T) + (size_t)L <=
+                   (size_t)SH::TC * kt_stride<L, SH::TC>() * sizeof(T) + (size_t)L <=
                160 * 1024;
 }
 
@@ -1042,7 +1052,8 @@ __global__ __launch_bounds__((Shape<T, L, TM_R>::NT), (Shape<T, L, TM_R>::MINW))
     constexpr int PADR = PP ? 1 : SH::PAD, LDSN = L * (TC + PADR);
     __shared__ C lds[PP ? 2 * LDSN : LDSN];
     __shared__ C tw[L];
-    __shared__ T kt[KR * TC * NXH];
+    constexpr int KS = kt_stride<L, TC>();
+    __shared__ T kt[KR * TC * KS];   // [KR][TC][KS]: rows of NXH values, padded
     __shared__ unsigned char xf[L];   // x-slabs carrying field (when xcount is given)
     // Tiles (ky, kz-block) and (ny - ky, kz-block) read the same kernel values,
     // and where a tile's rows are narrower than 128 bytes (TC complex values)
@@ -1104,7 +1115,10 @@ __global__ __launch_bounds__((Shape<T, L, TM_R>::NT), (Shape<T, L, TM_R>::MINW))
 #pragma unroll
         for (int q = 0; q < KPT; ++q) {
             const int e = threadIdx.x + q * NT;
-            if (e < KR * TC * NXH) kt[e] = kv[q];
+            if (e < KR * TC * NXH) {
+                const int hc = e / NXH, ox = e - hc * NXH;   // (h, c) row, then ox
+                kt[hc * KS + ox] = kv[q];
+            }
         }
     };
     // the last stage's keep bits: the same rows for every radius of the tile
